@@ -1,0 +1,305 @@
+"""Pins of the FP64 oracle against the paper and the mathematics (CPU only).
+
+Each test checks the oracle against something other than itself: the plain
+damped Gauss-Newton step with an explicitly formed Jacobian (Section 3,
+Lemma B.1), closed forms (Theorem E.1, Appendix F), special cases (zero
+gradient at an exact rank-R tensor, mu -> infinity), printed values
+(Section 6 angle table, Section 4.3 densities) and brute-force loops.
+Planted-mistake tests show that plausible errors in the oracle fail a pin.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import cpgen
+from oracle import brute, cp
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+SHAPES = [
+    ((4, 3, 5), 1), ((5, 4, 3), 2), ((3, 5, 4), 3), ((4, 4, 4), 4),
+    ((3, 4, 3, 4), 2), ((4, 3, 3, 3), 3), ((3, 3, 3, 3, 3), 2),
+]
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def _problem(seed, dims, R, complex_=False, snr=20.0, c=0.4):
+    p = cpgen.small_problem(seed, dims, R, c=c, snr_db=snr, complex_=complex_)
+    return p, cp.as_tensor(p.y, dims)
+
+
+@pytest.mark.parametrize("complex_", [False, True])
+@pytest.mark.parametrize("variant", ["a", "b"])
+@pytest.mark.parametrize("mu", [1e-2, 1.0, 50.0])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_fast_step_equals_explicit_solve(shape, mu, variant, complex_):
+    dims, R = shape
+    p, Y = _problem(11 + len(dims) * 7 + R, dims, R, complex_)
+    st = cp.fast_step(Y, p.init, mu, variant=variant)
+    da, g, _ = brute.plain_step(p.y, p.init, mu)
+    assert _rel(cp.flat(st.dA), cp.flat(da)) < 1e-9
+    assert _rel(cp.flat(st.g), g) < 1e-12
+
+
+@pytest.mark.parametrize("complex_", [False, True])
+def test_printed_w_simplification_fails(complex_):
+    """Planted reading: w with the all-mode Hadamard Gamma (as printed in
+    Theorem 4.1) does not reproduce the explicit solve for R > 1."""
+    dims, R = (4, 5, 3), 3
+    p, Y = _problem(5, dims, R, complex_)
+    da, _, _ = brute.plain_step(p.y, p.init, 0.5)
+    bad = cp.fast_step(Y, p.init, 0.5, w_form="printed")
+    good = cp.fast_step(Y, p.init, 0.5)
+    assert _rel(cp.flat(good.dA), cp.flat(da)) < 1e-10
+    assert _rel(cp.flat(bad.dA), cp.flat(da)) > 1e-2
+
+
+def test_transposed_F_is_caught(monkeypatch):
+    """Planted mistake: reshaping f into F_n row-major instead of column-major."""
+    dims, R = (4, 3, 5), 3
+    p, Y = _problem(9, dims, R)
+    da, _, _ = brute.plain_step(p.y, p.init, 0.3)
+    orig = cp.unvec
+    monkeypatch.setattr(cp, "unvec", lambda x, r, c: orig(x, r, c).T)
+    bad = cp.fast_step(Y, p.init, 0.3)
+    assert _rel(cp.flat(bad.dA), cp.flat(da)) > 1e-3
+
+
+def test_wrong_K_index_is_caught(monkeypatch):
+    """Planted mistake: K built without the commutation matrix."""
+    dims, R = (4, 3, 5), 3
+    p, Y = _problem(10, dims, R)
+    da, _, _ = brute.plain_step(p.y, p.init, 0.3)
+    monkeypatch.setattr(cp, "commutation", lambda R: np.eye(R * R))
+    bad = cp.fast_step(Y, p.init, 0.3)
+    assert _rel(cp.flat(bad.dA), cp.flat(da)) > 1e-3
+
+
+@pytest.mark.parametrize("complex_", [False, True])
+def test_hessian_low_rank_adjustment(complex_):
+    """Theorem 4.2 (and Theorem 5.3): J^H J = G + Z K Z^H."""
+    dims, R = (3, 4, 5, 3), 3
+    p, _ = _problem(3, dims, R, complex_)
+    A = p.init
+    J = brute.jacobian(A)
+    H = J.conj().T @ J
+    C = cp.grams(A)
+    Gam = cp.gammas(C)
+    blocksG = [np.kron(Gam[n], np.eye(dims[n])) for n in range(len(A))]
+    blocksZ = [np.kron(np.eye(R), A[n]) for n in range(len(A))]
+    from scipy.linalg import block_diag
+    G = block_diag(*blocksG)
+    Z = block_diag(*blocksZ)
+    K = cp.kernel_K(C)
+    assert _rel(G + Z @ K @ Z.conj().T, H) < 1e-13
+
+
+@pytest.mark.parametrize("N", [3, 4, 5])
+def test_kernel_inverse_closed_form(N):
+    """Theorem E.1: the printed blocks of K^-1 invert K."""
+    rng = np.random.default_rng(N)
+    R = 3
+    A = [rng.standard_normal((5, R)) for _ in range(N)]
+    C = cp.grams(A)
+    K = cp.kernel_K(C)
+    Ki = cp.kernel_K_inverse(C)
+    assert np.abs(Ki @ K - np.eye(K.shape[0])).max() < 1e-10
+
+
+@pytest.mark.parametrize("complex_", [False, True])
+def test_euler_identity_of_jacobian(complex_):
+    """Y_hat is homogeneous of degree N in a: J a = N vec(Y_hat)."""
+    dims, R = (3, 4, 5), 2
+    p, _ = _problem(2, dims, R, complex_)
+    J = brute.jacobian(p.init)
+    a = brute.param_vec(p.init)
+    assert _rel(J @ a, len(dims) * brute.model_vec(p.init)) < 1e-13
+
+
+@pytest.mark.parametrize("complex_", [False, True])
+def test_matrix_free_products(complex_):
+    dims, R = (4, 3, 5, 3), 3
+    p, _ = _problem(4, dims, R, complex_)
+    rng = np.random.default_rng(0)
+    V = [rng.standard_normal(a.shape) + (1j * rng.standard_normal(a.shape) if complex_ else 0)
+         for a in p.init]
+    J = brute.jacobian(p.init)
+    v = cp.flat(V)
+    assert _rel(brute.jacobian_matvec(p.init, V), J @ v) < 1e-13
+    assert _rel(cp.flat(brute.hessian_matvec(p.init, V)), J.conj().T @ (J @ v)) < 1e-13
+
+
+@pytest.mark.parametrize("complex_", [False, True])
+def test_zero_gradient_at_exact_rank_R(complex_):
+    """Y = Y_hat(A) gives g = 0 and hence no update (Section 4.5, gradient)."""
+    dims, R = (6, 5, 4), 3
+    p, _ = _problem(6, dims, R, complex_)
+    Y = cp.full(p.init)
+    st = cp.fast_step(Y, p.init, 0.1)
+    scale = np.linalg.norm(cp.flat(st.M))
+    assert np.linalg.norm(cp.flat(st.g)) < 1e-13 * scale
+    assert np.linalg.norm(cp.flat(st.dA)) < 1e-11 * np.linalg.norm(cp.flat(p.init))
+
+
+def test_mu_to_infinity_is_steepest_descent():
+    """mu da -> g with an O(||H|| / mu) remainder as mu grows."""
+    dims, R = (5, 4, 3), 2
+    p, Y = _problem(7, dims, R)
+    errs = []
+    for mu in (1e4, 1e6, 1e8):
+        st = cp.fast_step(Y, p.init, mu)
+        errs.append(_rel(mu * cp.flat(st.dA), cp.flat(st.g)))
+    assert errs[0] > 50 * errs[1] and errs[1] > 50 * errs[2]
+    assert errs[2] < 1e-5
+
+
+@pytest.mark.parametrize("complex_", [False, True])
+def test_mttkrp_brute_force_loop(complex_):
+    """M_n[i_n, r] = sum over all entries y_i prod_{k != n} A_k[i_k, r] (conjugated factors for complex)."""
+    dims, R = (3, 4, 2, 3), 2
+    p, Y = _problem(8, dims, R, complex_)
+    A = p.init
+    for n in range(len(dims)):
+        M = np.zeros((dims[n], R), dtype=Y.dtype)
+        for idx in np.ndindex(*dims):
+            for r in range(R):
+                t = Y[idx]
+                for k in range(len(dims)):
+                    if k != n:
+                        t = t * (A[k][idx[k], r].conj() if complex_ else A[k][idx[k], r])
+                M[idx[n], r] += t
+        assert _rel(cp.mttkrp(Y, A, n, conj=complex_), M) < 1e-13
+
+
+def test_mttkrp_mode1_is_plain_gemm_and_cross_mode_invariant():
+    """Mode 1: the vec layout is Y_(1) column-major, so M_1 = reshape(y) @ KR.
+    All modes: sum(A_n * M_n) = <Y, Y_hat> computed from the full model."""
+    dims, R = (7, 5, 6, 4), 3
+    p, Y = _problem(12, dims, R)
+    A = p.init
+    KR = np.ones((1, R))
+    for a in A[1:]:
+        KR = (a[:, None, :] * KR[None, :, :]).reshape(-1, R)
+    M1 = p.y.reshape(dims[0], -1, order="F") @ KR
+    assert _rel(cp.mttkrp(Y, A, 0), M1) < 1e-14
+    inner = float(np.sum(Y * cp.full(A)))
+    for n in range(len(dims)):
+        assert abs(np.sum(A[n] * cp.mttkrp(Y, A, n)) - inner) < 1e-12 * abs(inner)
+
+
+def _congruence(A, B):
+    """Best column matching of factor sets A and B; product over modes of |cosines|."""
+    from itertools import permutations
+    R = A[0].shape[1]
+    best = 0.0
+    for perm in permutations(range(R)):
+        score = 1.0
+        for a, b in zip(A, B):
+            for r in range(R):
+                u, v = a[:, r], b[:, perm[r]]
+                score = min(score, abs(np.vdot(u, v)) / (np.linalg.norm(u) * np.linalg.norm(v)))
+        best = max(best, score)
+    return best
+
+
+@pytest.mark.parametrize("complex_", [False, True])
+def test_noiseless_recovery(complex_):
+    """Exact rank-R data from a perturbed truth: the fit reaches eps <= 1e-12
+    and recovers the components up to order and scale."""
+    dims, R = (8, 7, 6), 3
+    p = cpgen.small_problem(21, dims, R, c=0.6, snr_db=None, complex_=complex_)
+    Y = cp.as_tensor(p.y, dims)
+    rng = np.random.default_rng(1)
+    A0 = [a + 1e-2 * rng.standard_normal(a.shape) for a in p.truth]
+    res = cp.fit(Y, A0, mu0=-1, tol=0.0, max_iters=60)
+    assert res["eps"] <= 1e-12
+    assert _congruence(res["A"], p.truth) > 1 - 1e-10
+
+
+def test_fit_error_monotone_and_normalised():
+    p = cpgen.cfg1()
+    Y = cp.as_tensor(p.y, p.dims)
+    res = cp.fit(Y, p.init, mu0=p.mu0, tol=0.0, max_iters=20, trace=True)
+    errs = [h["err2"] for h in res["hist"]]
+    assert all(b <= a for a, b in zip(errs, errs[1:]))
+    norms = np.array([np.linalg.norm(a, axis=0) for a in res["A"]])
+    assert np.allclose(norms, norms[0][None, :], rtol=1e-12)
+
+
+def test_generator_gram_closed_form():
+    rng = np.random.default_rng(0)
+    for (I, R, c) in [(20, 3, 0.9), (50, 8, 0.95), (9, 9, 0.0)]:
+        A = cpgen.collinear_factor(rng, I, R, c)
+        target = (1 - c) * np.eye(R) + c * np.ones((R, R))
+        assert np.abs(A.T @ A / I - target).max() < 1e-12
+
+
+def test_generator_noise_level():
+    rng = np.random.default_rng(0)
+    y = rng.standard_normal(200000)
+    yn, sigma = cpgen.add_noise(rng, y, 20.0)
+    snr = 10 * np.log10(np.sum(y ** 2) / (sigma ** 2 * y.size))
+    assert abs(snr - 20.0) < 1e-12
+    assert abs(np.var(yn - y) / sigma ** 2 - 1) < 0.02
+
+
+def test_generator_section6_angles_and_magnitudes():
+    with open(os.path.join(GOLDEN, "section6_collinearity.json")) as fh:
+        gold = json.load(fh)
+    rng = np.random.default_rng(0)
+    for nu, t1, tq in zip(gold["nu"], gold["theta_1r_deg"], gold["theta_qr_deg"]):
+        A, _ = cpgen.nu_collinear_factors(rng, [12, 12, 12], 4, nu)
+        a = A[0] / np.linalg.norm(A[0], axis=0)
+        ang = np.degrees(np.arccos(np.clip(a.T @ a, -1, 1)))
+        assert round(ang[0, 1]) == t1 and round(ang[0, 3]) == t1
+        assert round(ang[1, 2]) == tq and round(ang[2, 3]) == tq
+    A, _ = cpgen.nu_collinear_factors(rng, [12, 12, 12], 3, 2.0)
+    a = A[0] / np.linalg.norm(A[0], axis=0)
+    ang = np.degrees(np.arccos(a.T @ a))
+    assert abs(ang[0, 1] - gold["nu2_theta_1r_deg_approx"]) < 1
+    assert abs(ang[1, 2] - gold["nu2_theta_qr_deg_approx"]) < 1
+    for nu, lam in gold["lambda_N3"].items():
+        _, l = cpgen.nu_collinear_factors(rng, [5, 5, 5], 3, float(nu))
+        assert abs(l[1] - lam) < 0.05
+
+
+def test_generator_appendix_f_eigenvalues():
+    """Appendix F: Y_(n) Y_(n)^T of the nu-collinear tensor has R-2 eigenvalues
+    (x-1)(y-1), and lambda_1 + lambda_R, lambda_1 lambda_R as printed."""
+    rng = np.random.default_rng(3)
+    for (N, R, nu, I) in [(3, 5, 0.5, 20), (4, 4, 0.3, 8), (3, 6, 1.0, 15)]:
+        A, _ = cpgen.nu_collinear_factors(rng, [I] * N, R, nu)
+        Y = cp.as_tensor(cpgen.cp_tensor(A), [I] * N)
+        ev = np.sort(np.linalg.eigvalsh(cp.unfold(Y, 0) @ cp.unfold(Y, 0).T))[::-1][:R]
+        x = 1 + nu ** 2
+        y = x ** (N - 1)
+        assert np.allclose(ev[1:R - 1], (x - 1) * (y - 1), rtol=1e-9)
+        assert abs(ev[0] + ev[-1] - (x * y + (R - 2) * (R + x + y) + 3)) < 1e-9 * ev[0]
+        assert abs(ev[0] * ev[-1] - (x - 1) * (y - 1)) < 1e-9 * ev[0]
+        # ||Y||^2 = trace(Sigma) = R^2 + (R-1)(xy - 1)  (the printed sigma^2 numerator
+        # reads R^2 + (R-1)xy - 1, which only agrees for R = 2)
+        assert abs(np.sum(Y ** 2) - (R ** 2 + (R - 1) * (x * y - 1))) < 1e-9 * np.sum(Y ** 2)
+
+
+def test_phi_densities_section43():
+    with open(os.path.join(GOLDEN, "section43_density.json")) as fh:
+        gold = json.load(fh)
+    dims, R = gold["dims"], gold["R"]
+    N = len(dims)
+    rng = np.random.default_rng(0)
+    A = [rng.standard_normal((I, R)) for I in dims]
+    C = cp.grams(A)
+    Gt = [cp.damped_inverse(g, 0.1) for g in cp.gammas(C)]
+    K = cp.kernel_K(C)
+    Psi = cp.psi(Gt, C)
+    Phi1 = np.eye(N * R * R) + Psi @ K
+    Phi2 = cp.kernel_K_inverse(C) + Psi
+    d1 = np.count_nonzero(np.abs(Phi1) > 1e-300) / Phi1.size
+    d2 = np.count_nonzero(np.abs(Phi2) > 1e-300) / Phi2.size
+    assert abs(d1 - ((N - 1) * R * R + 1) / (N * R * R)) < 1e-12
+    assert abs(d2 - (R * R + N - 1) / (N * R * R)) < 1e-12
