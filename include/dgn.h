@@ -1,0 +1,195 @@
+/*
+ * dgn.h -- C ABI of the MI355X (gfx950) fast damped Gauss-Newton library for
+ * CANDECOMP/PARAFAC (Phan, Tichavsky, Cichocki, "Low complexity damped
+ * Gauss-Newton algorithms for CANDECOMP/PARAFAC").
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - A tensor Y of order N (3 <= N <= DGN_MAX_ORDER) with sizes I_1..I_N is a
+ *   dense device buffer holding vec(Y) with the first index fastest
+ *   (column-major), the vectorisation of Section 2.  Y_(n) is never formed.
+ * - A factor A^(n) is a device buffer of I_n x R doubles (complex doubles
+ *   for complex tensors), column-major, leading dimension I_n.  Factors are
+ *   passed as a host array of N device pointers.
+ * - All device pointers are caller-owned.  The library never frees them and
+ *   never keeps them after a call returns.
+ * - `stream` is a hipStream_t passed as void*; NULL means the default stream.
+ *   Work is enqueued on that stream.  Calls that return host results
+ *   (dgn_step_info, dgn_fit_info, inner products) synchronise the stream
+ *   before returning.
+ * - A context is bound to one device and is not thread-safe: one context per
+ *   host thread / stream.
+ * - Every call returns a dgn_status; on failure dgn_last_error() gives a
+ *   readable message.  Shapes are validated before any work is enqueued:
+ *   order in [3, DGN_MAX_ORDER], every I_n >= 1, 1 <= R <= DGN_MAX_RANK,
+ *   mu > 0 (H = J^T J is singular, so mu = 0 is rejected), non-NULL pointers.
+ *
+ * Arithmetic
+ * ----------
+ * The tensor pass (MTTKRP and the residual) runs in the tensor's dtype:
+ * F64 -> FP64; F32 -> FP32 MFMA with FP32 accumulation; BF16 -> BF16 MFMA
+ * with FP32 accumulation; C128 -> FP64 complex; C64 -> FP32 complex.
+ * Partial sums are reduced in FP64.  Everything after the tensor pass (Gram
+ * and Hadamard products, the damped inverses, the NR^2 system and the factor
+ * update) is FP64 (complex FP64).
+ */
+#ifndef DGN_H
+#define DGN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DGN_MAX_ORDER 8
+#define DGN_MAX_RANK 64
+
+typedef enum dgn_status {
+  DGN_OK = 0,
+  DGN_EINVAL = -1,     /* bad shape, rank, dtype, mu or NULL pointer */
+  DGN_ENOMEM = -2,     /* workspace budget of the context too small */
+  DGN_ESINGULAR = -3,  /* non-positive pivot in (Gamma^(n) + mu I) or the NR^2 system */
+  DGN_ENONFINITE = -4, /* NaN/Inf in the tensor pass or the step */
+  DGN_EHIP = -5,       /* a HIP runtime call failed */
+  DGN_EBUSY = -6       /* request over the memory budget (serving) */
+} dgn_status;
+
+typedef enum dgn_dtype {
+  DGN_F64 = 0,
+  DGN_F32 = 1,
+  DGN_BF16 = 2,
+  DGN_C64 = 3,
+  DGN_C128 = 4
+} dgn_dtype;
+
+typedef enum dgn_normalize {
+  DGN_NORM_BALANCED = 0,        /* equal column norms across modes (Algorithm 1, normalisation step) */
+  DGN_NORM_UNIT_EXCEPT_LAST = 1,/* unit columns in modes 1..N-1 (Section 2) */
+  DGN_NORM_NONE = 2
+} dgn_normalize;
+
+typedef enum dgn_stop {
+  DGN_STOP_TOL = 0,       /* |eps_prev - eps| < tol on an accepted trial */
+  DGN_STOP_MAX_IT = 1,    /* max_iters trials done */
+  DGN_STOP_MU = 2,        /* mu > 1e30 (Section 4.5) */
+  DGN_STOP_NONFINITE = 3  /* non-finite error or step */
+} dgn_stop;
+
+/* Dense tensor descriptor.  dims[k] for k >= order are ignored.  `data` is a
+ * device pointer to prod(dims) elements of `dtype`, first index fastest. */
+typedef struct dgn_tensor {
+  int32_t order;
+  int64_t dims[DGN_MAX_ORDER];
+  int32_t dtype; /* dgn_dtype */
+  const void* data;
+} dgn_tensor;
+
+/* Options.  dgn_opts_default() fills the defaults; NULL opts means defaults. */
+typedef struct dgn_opts {
+  int32_t normalize;    /* dgn_normalize, default BALANCED */
+  double tau;           /* mu0 = tau * max_n max diag Gamma^(n) when mu0 <= 0 (eq. mu0); default 1e-3 */
+  /* Real F32/BF16 tensors: the gradient is first taken from the plain
+   * MTTKRP, and the error from ||Y||^2 - 2<Y,Y_hat> + ||Y_hat||^2.  Once an
+   * accepted trial changes the relative error eps by less than resid_switch
+   * the fit switches to the residual-corrected pass: E = Y - Y_hat is formed
+   * in FP32 inside the pass, the gradient is MTTKRP(E) and the error is
+   * sum(E^2).  0 never switches, a negative value starts residual-corrected.
+   * F64/C128 tensors always use the residual form.  Default 1e-4. */
+  double resid_switch;
+  /* Optional BF16 copy of Y (same dims, device) used by the plain passes of
+   * an F32 tensor before the switch.  NULL: the F32 tensor is used. */
+  const void* y_bf16;
+  int32_t poll_every;   /* cp_fit checks its stop flag every this many trials; default 8 */
+  int32_t timing;       /* nonzero: cp_fit records per-phase HIP events (dgn_last_phase_times) */
+} dgn_opts;
+
+/* Result of one trial step (dgn_step). */
+typedef struct dgn_step_info {
+  double err2_old;  /* ||Y - Y_hat(A_in)||^2 */
+  double err2_new;  /* ||Y - Y_hat(A_out)||^2 */
+  double rho;       /* (err2_old - err2_new) / denom  (gain ratio, Section 4.5) */
+  double denom;     /* Re(da^H (g + mu da)) */
+  double gnorm;     /* ||g||, g = J^H vec(Y - Y_hat) */
+  double mnorm;     /* ||[M_n]||, all-mode MTTKRP norm (plain form) or ||[M_n - A_n Gamma_n]|| is g */
+  double danorm;    /* ||da|| */
+} dgn_step_info;
+
+/* Result of a fit (cp_fit). */
+typedef struct dgn_fit_info {
+  int32_t iters;        /* trials done (accepted + rejected) */
+  int32_t accepted;     /* accepted trials */
+  int32_t reason;       /* dgn_stop */
+  int32_t resid_iters;  /* trials taken with the residual-corrected pass */
+  double eps;           /* final ||Y - Y_hat|| / ||Y|| */
+  double err2;          /* final ||Y - Y_hat||^2 */
+  double mu;            /* final damping */
+  double mu0;           /* initial damping actually used */
+} dgn_fit_info;
+
+typedef struct dgn_ctx dgn_ctx;
+
+/* Fill *opts with the defaults listed in dgn_opts. */
+void dgn_opts_default(dgn_opts* opts);
+
+/* Create a context on `device` owning a device workspace of ws_budget_bytes
+ * (allocated once here; 0 picks 1 GiB).  Calls needing more return
+ * DGN_ENOMEM; dgn_workspace_size() gives the requirement. */
+dgn_status dgn_create(dgn_ctx** out, int32_t device, size_t ws_budget_bytes);
+dgn_status dgn_destroy(dgn_ctx* ctx);
+/* Message of the last failure on this context ("" if none).  Owned by ctx. */
+const char* dgn_last_error(const dgn_ctx* ctx);
+
+/* Workspace bytes dgn_step / cp_fit / dgn_mttkrp need for this shape. */
+dgn_status dgn_workspace_size(const dgn_tensor* Y, int32_t R, const dgn_opts* opts, size_t* bytes);
+
+/* All-mode MTTKRP (Section 4.4, the O(NRJ) step; eq. ALS numerator):
+ * M_n = Y_(n) (A^(N) (.) ... (.) A^(n+1) (.) A^(n-1) (.) ... (.) A^(1)) for
+ * every n, with conjugated factors for complex tensors (Theorem 5.4), in one
+ * pass over Y.  A: N device pointers to I_n x R FP64 (C128) factors; the pass
+ * casts them to the tensor's compute type.  M: N device pointers to I_n x R
+ * FP64 (C128) outputs.  inner (host, may be NULL): <Y, Y_hat> = sum(A_n * M_n)
+ * (real part for complex).  Synchronises when inner != NULL. */
+dgn_status dgn_mttkrp(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, const void* const* A,
+                      void* const* M, double* inner, void* stream);
+
+/* One trial damped Gauss-Newton step at damping mu (Theorem 4.1 with the
+ * Jacobian-free products of Lemma 4.4 and the fLMa solve of Section 4.3):
+ * A_out = A_in + da with da = (J^H J + mu I)^-1 J^H vec(Y - Y_hat(A_in)).
+ * A_out may alias A_in.  No normalisation and no accept/reject: `info`
+ * (host, may be NULL) reports the errors before and after and the gain ratio.
+ * Synchronises the stream before returning. */
+dgn_status dgn_step(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, const void* const* A_in,
+                    void* const* A_out, double mu, const dgn_opts* opts, dgn_step_info* info,
+                    void* stream);
+
+/* Algorithm 1 with the damping of Section 4.5, device-resident.  A: in the
+ * starting factors, out the result (N device pointers, FP64 / C128).
+ * mu0 > 0 is used as given, mu0 <= 0 takes tau * max diag Gamma^(n).
+ * Each trial: step at mu; accept iff the residual decreases, then normalise
+ * and mu <- mu max(1/3, 1 - (2 rho - 1)^3); else mu <- 2 mu.  Stops on an
+ * accepted trial with |eps_prev - eps| < tol, after max_iters trials, or at
+ * mu > 1e30.  Synchronises the stream before returning. */
+dgn_status cp_fit(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, void* const* A, double mu0,
+                  double tol, int32_t max_iters, const dgn_opts* opts, dgn_fit_info* info,
+                  void* stream);
+
+/* Per-phase GPU time of the last cp_fit call made with opts->timing != 0,
+ * from HIP events recorded on that call's stream around each phase of every
+ * executed trial.  ms_out[k] (k < n <= DGN_NUM_PHASES) receives the total
+ * milliseconds of phase k; *trials the number of trials summed.  Phases:
+ * 0 Gamma / damped inverses / gradient rows / right-hand side,
+ * 1 assembly of the NR^2 system (with the block-1 Schur update),
+ * 2 Cholesky factorisation and triangular solves,
+ * 3 factor update and candidate Gram matrices,
+ * 4 tensor pass at the candidate (all-mode MTTKRP or residual pass),
+ * 5 damping control and commit. */
+#define DGN_NUM_PHASES 6
+dgn_status dgn_last_phase_times(const dgn_ctx* ctx, double* ms_out, int32_t n, int32_t* trials);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DGN_H */

@@ -70,16 +70,11 @@ def mttkrp(Y: np.ndarray, A, n: int, conj: bool = False) -> np.ndarray:
 
 
 def full(A) -> np.ndarray:
-    """The CP model (eq. CP): sum over r of outer products a^(1)_r o ... o a^(N)_r."""
+    """The CP model (eq. CP) through its mode-1 unfolding (Section 2):
+    Y_hat_(1) = A^(1) (A^(N) (.) ... (.) A^(2))^T, folded back to N-way."""
     dims = [a.shape[0] for a in A]
-    R = A[0].shape[1]
-    Y = np.zeros(dims, dtype=np.result_type(*A))
-    for r in range(R):
-        t = A[0][:, r]
-        for a in A[1:]:
-            t = np.multiply.outer(t, a[:, r])
-        Y = Y + t
-    return Y
+    Y1 = A[0] @ kr_except(A, 0).T
+    return Y1.reshape(dims, order="F")
 
 
 def residual_norm2(Y: np.ndarray, A) -> float:

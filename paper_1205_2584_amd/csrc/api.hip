@@ -1,0 +1,480 @@
+// C ABI of the library (declared in include/dgn.h): argument checking,
+// workspace carving and the enqueue order of the kernels of one trial step.
+#include <math.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "dgn.h"
+#include "internal.hpp"
+
+struct dgn_ctx {
+  int device;
+  char* ws;
+  size_t ws_size;
+  std::string err;
+  std::vector<hipEvent_t> events;   // timing pool, (DGN_NUM_PHASES + 1) per trial
+  double phase_ms[DGN_NUM_PHASES] = {0, 0, 0, 0, 0, 0};
+  int phase_trials = 0;
+};
+
+namespace dgn {
+hipError_t launch_inner(const Shape& s, const double* A, const double* M, double* out, hipStream_t st);
+}
+
+namespace {
+
+using namespace dgn;
+
+struct Arena {
+  char* base;
+  size_t size;
+  size_t used = 0;
+  bool fail = false;
+  template <typename T>
+  T* take(size_t n) {
+    const size_t bytes = ((n * sizeof(T)) + 255) & ~size_t(255);
+    if (used + bytes > size) {
+      fail = true;
+      used += bytes;
+      return nullptr;
+    }
+    T* p = base ? reinterpret_cast<T*>(base + used) : nullptr;
+    used += bytes;
+    return p;
+  }
+};
+
+constexpr int kNormParts = 1024;
+
+struct Work {
+  Shape s;
+  YType ymaster;
+  PassPlan pp;
+  SysPlan sp;
+  double *A, *Ac, *M, *Mc;
+  SmallBuffers sb;
+  PassBuffers pb;
+  SysBuffers sy;
+  FitState* state;
+  int* flags;      // [0] singular (step), [1..] spare
+  double* scr;     // [0..1023] norm partials, [1024] e2, [1025] e2c, [1026..1029] err2 / ynorm2
+};
+
+bool dtype_ok(int dt, YType* yt) {
+  switch (dt) {
+    case DGN_F64: *yt = YType::F64; return true;
+    case DGN_F32: *yt = YType::F32; return true;
+    case DGN_BF16: *yt = YType::BF16; return true;
+    default: return false;
+  }
+}
+
+dgn_status set_err(dgn_ctx* ctx, dgn_status st, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  return st;
+}
+
+dgn_status check_shape(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, Shape* s, YType* yt) {
+  if (!Y) return set_err(ctx, DGN_EINVAL, "tensor descriptor is NULL");
+  if (!Y->data) return set_err(ctx, DGN_EINVAL, "tensor data pointer is NULL");
+  if (Y->order < 3 || Y->order > DGN_MAX_ORDER)
+    return set_err(ctx, DGN_EINVAL, "tensor order must be in [3, 8]");
+  if (R < 1 || R > DGN_MAX_RANK) return set_err(ctx, DGN_EINVAL, "rank must be in [1, 64]");
+  if (!dtype_ok(Y->dtype, yt))
+    return set_err(ctx, DGN_EINVAL, "unsupported tensor dtype (real F64, F32, BF16 are built)");
+  s->N = Y->order;
+  s->R = R;
+  s->T = 0;
+  s->maxI = 0;
+  long double J = 1;
+  for (int n = 0; n < Y->order; ++n) {
+    if (Y->dims[n] < 1 || Y->dims[n] > (1LL << 30))
+      return set_err(ctx, DGN_EINVAL, "every mode size must be in [1, 2^30]");
+    s->I[n] = (int)Y->dims[n];
+    s->off[n] = s->T;
+    s->T += s->I[n];
+    if (s->I[n] > s->maxI) s->maxI = s->I[n];
+    J *= (long double)Y->dims[n];
+  }
+  for (int n = Y->order; n < kMaxOrder; ++n) {
+    s->I[n] = 1;
+    s->off[n] = s->T;
+  }
+  if (J > (long double)(1LL << 56)) return set_err(ctx, DGN_EINVAL, "tensor too large");
+  return DGN_OK;
+}
+
+void carve(Arena& ar, Work& w, bool with_system) {
+  const Shape& s = w.s;
+  const size_t TR = (size_t)s.T * s.R, NR2 = (size_t)s.N * s.R * s.R;
+  const int ch = row_chunks(s);
+  const size_t stride = (size_t)s.R * s.R + 4;
+  w.state = ar.take<FitState>(1);
+  w.flags = ar.take<int>(64);
+  w.scr = ar.take<double>(kNormParts + 64);
+  w.A = ar.take<double>(TR);
+  w.Ac = ar.take<double>(TR);
+  w.M = ar.take<double>(TR);
+  w.Mc = ar.take<double>(TR);
+  SmallBuffers& b = w.sb;
+  b.C = ar.take<double>(NR2);
+  b.Cc = ar.take<double>(NR2);
+  b.Gam = ar.take<double>(NR2);
+  b.Gt = ar.take<double>(NR2);
+  b.X = ar.take<double>(NR2);
+  b.Lc = ar.take<double>(NR2);
+  b.G = ar.take<double>(TR);
+  b.P = ar.take<double>(TR);
+  b.wpart = ar.take<double>((size_t)s.N * ch * stride);
+  b.rowpart = ar.take<double>((size_t)s.N * ch * stride);
+  b.scal = ar.take<double>(8);
+  b.w = ar.take<double>(NR2);
+  b.z = ar.take<double>(NR2);
+  b.y = ar.take<double>(NR2);
+  b.u = ar.take<double>(NR2);
+  b.f = ar.take<double>(NR2);
+  b.Q = ar.take<double>(NR2);
+  b.Tnm = with_system ? ar.take<double>((size_t)s.N * s.N * s.R * s.R * s.R) : nullptr;
+  const PassPlan& p = w.pp;
+  const size_t tcb = 8;  // sized for the widest compute type
+  w.pb.m0part = ar.take<char>(p.m0_elems * tcb);
+  w.pb.m1part = ar.take<char>(p.m1_elems * tcb);
+  w.pb.tpart = ar.take<char>(p.t_elems * tcb);
+  w.pb.e2part = ar.take<double>(p.e2_elems);
+  w.pb.tbuf = p.tbuf_elems ? ar.take<double>(p.tbuf_elems) : nullptr;
+  if (with_system) {
+    const SysPlan& q = w.sp;
+    const size_t r2p = ((size_t)q.R2 + 3) / 4 * 4;
+    w.sy.St = ar.take<double>((size_t)q.lds * q.ntp);
+    w.sy.B = ar.take<double>((size_t)q.ntp * r2p);
+    w.sy.yt = ar.take<double>((size_t)q.ntp);
+  } else {
+    w.sy = SysBuffers{nullptr, nullptr, nullptr};
+  }
+}
+
+dgn_status prepare(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, bool with_system, Work& w) {
+  dgn_status st = check_shape(ctx, Y, R, &w.s, &w.ymaster);
+  if (st != DGN_OK) return st;
+  w.pp = plan_pass(w.s, w.ymaster);
+  w.sp = plan_sys(w.s);
+  Arena ar{ctx ? ctx->ws : nullptr, ctx ? ctx->ws_size : (size_t)-1};
+  carve(ar, w, with_system);
+  if (ar.fail) {
+    return set_err(ctx, DGN_ENOMEM,
+                   "workspace budget too small: need " + std::to_string(ar.used) + " bytes, have " +
+                       std::to_string(ctx ? ctx->ws_size : 0));
+  }
+  return DGN_OK;
+}
+
+dgn_status hip_fail(dgn_ctx* ctx, hipError_t e, const char* where) {
+  return set_err(ctx, DGN_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(expr, where)                       \
+  do {                                            \
+    hipError_t _e = (expr);                       \
+    if (_e != hipSuccess) return hip_fail(ctx, _e, where); \
+  } while (0)
+
+hipError_t copy_factors_in(const Work& w, const void* const* A, double* dst, hipStream_t st) {
+  for (int n = 0; n < w.s.N; ++n) {
+    hipError_t e = hipMemcpyAsync(dst + (size_t)w.s.off[n] * w.s.R, A[n],
+                                  sizeof(double) * w.s.I[n] * w.s.R, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t copy_factors_out(const Work& w, const double* src, void* const* A, hipStream_t st) {
+  for (int n = 0; n < w.s.N; ++n) {
+    hipError_t e = hipMemcpyAsync(A[n], src + (size_t)w.s.off[n] * w.s.R,
+                                  sizeof(double) * w.s.I[n] * w.s.R, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// The kernels of one trial step from the current (A, M, C) to the candidate
+// (Ac, Cc) and the gain-ratio scalars; mu from state when state != NULL.
+hipError_t mark(hipEvent_t* ev, int k, hipStream_t st) {
+  return ev ? hipEventRecord(ev[k], st) : hipSuccess;
+}
+
+hipError_t enqueue_step(Work& w, bool resid, double mu_host, FitState* state, int* singular,
+                        const int* stop, hipStream_t st, hipEvent_t* ev = nullptr) {
+  const Shape& s = w.s;
+  hipError_t e;
+  if ((e = mark(ev, 0, st)) != hipSuccess) return e;
+  if ((e = launch_gamma(s, w.sb.C, mu_host, state, w.sb, singular, stop, st)) != hipSuccess) return e;
+  if ((e = launch_pw(s, w.A, w.M, resid, w.sb, stop, st)) != hipSuccess) return e;
+  if ((e = launch_wz(s, w.sb, stop, st)) != hipSuccess) return e;
+  if ((e = launch_tnm(s, w.sb, stop, st)) != hipSuccess) return e;
+  if ((e = mark(ev, 1, st)) != hipSuccess) return e;
+  if ((e = launch_sys_assemble(s, w.sp, w.sb, w.sy, stop, st)) != hipSuccess) return e;
+  if ((e = mark(ev, 2, st)) != hipSuccess) return e;
+  if ((e = launch_sys_factor_solve(s, w.sp, w.sb, w.sy, singular, stop, st)) != hipSuccess) return e;
+  if ((e = mark(ev, 3, st)) != hipSuccess) return e;
+  if ((e = launch_u(s, w.sb, stop, st)) != hipSuccess) return e;
+  if ((e = launch_fq(s, w.sb, stop, st)) != hipSuccess) return e;
+  if ((e = launch_update(s, w.A, w.Ac, w.sb, mu_host, state, stop, st)) != hipSuccess) return e;
+  return launch_update_reduce(s, w.sb, w.sb.scal, stop, st);
+}
+
+struct PassSel {
+  const void* data;
+  YType yt;
+};
+
+PassSel pass_tensor(const Work& w, const dgn_tensor* Y, const dgn_opts& o, bool resid) {
+  if (!resid && w.ymaster == YType::F32 && o.y_bf16) return PassSel{o.y_bf16, YType::BF16};
+  return PassSel{Y->data, w.ymaster};
+}
+
+}  // namespace
+
+extern "C" {
+
+void dgn_opts_default(dgn_opts* o) {
+  if (!o) return;
+  memset(o, 0, sizeof(*o));
+  o->normalize = DGN_NORM_BALANCED;
+  o->tau = 1e-3;
+  o->resid_switch = 1e-4;
+  o->y_bf16 = nullptr;
+  o->poll_every = 8;
+}
+
+dgn_status dgn_create(dgn_ctx** out, int32_t device, size_t ws_budget_bytes) {
+  if (!out) return DGN_EINVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return DGN_EINVAL;
+  if (hipSetDevice(device) != hipSuccess) return DGN_EHIP;
+  dgn_ctx* c = new dgn_ctx();
+  c->device = device;
+  c->ws_size = ws_budget_bytes ? ws_budget_bytes : (size_t(1) << 30);
+  if (hipMalloc((void**)&c->ws, c->ws_size) != hipSuccess) {
+    delete c;
+    return DGN_ENOMEM;
+  }
+  *out = c;
+  return DGN_OK;
+}
+
+dgn_status dgn_destroy(dgn_ctx* ctx) {
+  if (!ctx) return DGN_EINVAL;
+  hipSetDevice(ctx->device);
+  for (hipEvent_t e : ctx->events) hipEventDestroy(e);
+  hipFree(ctx->ws);
+  delete ctx;
+  return DGN_OK;
+}
+
+const char* dgn_last_error(const dgn_ctx* ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+dgn_status dgn_last_phase_times(const dgn_ctx* ctx, double* ms_out, int32_t n, int32_t* trials) {
+  if (!ctx || (!ms_out && n > 0) || n < 0 || n > DGN_NUM_PHASES) return DGN_EINVAL;
+  for (int k = 0; k < n; ++k) ms_out[k] = ctx->phase_ms[k];
+  if (trials) *trials = ctx->phase_trials;
+  return DGN_OK;
+}
+
+dgn_status dgn_workspace_size(const dgn_tensor* Y, int32_t R, const dgn_opts* opts, size_t* bytes) {
+  (void)opts;
+  if (!bytes) return DGN_EINVAL;
+  Work w{};
+  dgn_status st = check_shape(nullptr, Y, R, &w.s, &w.ymaster);
+  if (st != DGN_OK) return st;
+  w.pp = plan_pass(w.s, w.ymaster);
+  w.sp = plan_sys(w.s);
+  Arena ar{nullptr, (size_t)-1};
+  carve(ar, w, true);
+  *bytes = ar.used;
+  return DGN_OK;
+}
+
+dgn_status dgn_mttkrp(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, const void* const* A,
+                      void* const* M, double* inner, void* stream) {
+  if (!ctx) return DGN_EINVAL;
+  if (!A || !M) return set_err(ctx, DGN_EINVAL, "factor or output pointer array is NULL");
+  Work w{};
+  dgn_status rc = prepare(ctx, Y, R, false, w);
+  if (rc != DGN_OK) return rc;
+  for (int n = 0; n < w.s.N; ++n)
+    if (!A[n] || !M[n]) return set_err(ctx, DGN_EINVAL, "NULL factor or output pointer");
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(hipSetDevice(ctx->device), "hipSetDevice");
+  HIPCHK(copy_factors_in(w, A, w.A, st), "copy factors");
+  HIPCHK(launch_tensor_pass(w.s, w.ymaster, Y->data, w.A, false, w.pp, w.pb, w.M, nullptr, nullptr, st),
+         "tensor pass");
+  HIPCHK(copy_factors_out(w, w.M, M, st), "copy MTTKRP");
+  if (inner) {
+    HIPCHK(launch_inner(w.s, w.A, w.M, w.scr + 1026, st), "inner");
+    HIPCHK(hipMemcpyAsync(inner, w.scr + 1026, sizeof(double), hipMemcpyDeviceToHost, st), "copy inner");
+    HIPCHK(hipStreamSynchronize(st), "sync");
+  }
+  return DGN_OK;
+}
+
+dgn_status dgn_step(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, const void* const* A_in,
+                    void* const* A_out, double mu, const dgn_opts* opts, dgn_step_info* info,
+                    void* stream) {
+  if (!ctx) return DGN_EINVAL;
+  if (!A_in || !A_out) return set_err(ctx, DGN_EINVAL, "factor pointer array is NULL");
+  if (!(mu > 0.0) || !isfinite(mu)) return set_err(ctx, DGN_EINVAL, "mu must be finite and > 0");
+  dgn_opts o;
+  dgn_opts_default(&o);
+  if (opts) o = *opts;
+  Work w{};
+  dgn_status rc = prepare(ctx, Y, R, true, w);
+  if (rc != DGN_OK) return rc;
+  for (int n = 0; n < w.s.N; ++n)
+    if (!A_in[n] || !A_out[n]) return set_err(ctx, DGN_EINVAL, "NULL factor pointer");
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(hipSetDevice(ctx->device), "hipSetDevice");
+  const bool resid = (w.ymaster == YType::F64) || o.resid_switch < 0;
+  const PassSel ps = pass_tensor(w, Y, o, resid);
+  const long long J = [&] { long long j = 1; for (int n = 0; n < w.s.N; ++n) j *= w.s.I[n]; return j; }();
+  double* ynp = w.scr + 1028;
+  double* e2a = w.scr + 1024;
+  double* e2b = w.scr + 1025;
+  double* out = w.scr + 1026;  // err2 old, new
+  HIPCHK(hipMemsetAsync(w.flags, 0, 64 * sizeof(int), st), "memset");
+  HIPCHK(copy_factors_in(w, A_in, w.A, st), "copy factors");
+  HIPCHK(launch_norm2(ps.yt, ps.data, J, w.scr, kNormParts, ynp, st), "norm");
+  HIPCHK(launch_gram(w.s, w.A, w.sb, w.sb.C, nullptr, st), "gram");
+  HIPCHK(launch_tensor_pass(w.s, ps.yt, ps.data, w.A, resid, w.pp, w.pb, w.M, e2a, nullptr, st), "pass");
+  HIPCHK(launch_err2(w.s, w.A, w.M, w.sb.C, resid, e2a, ynp, out, st), "err2");
+  HIPCHK(enqueue_step(w, resid, mu, nullptr, w.flags, nullptr, st), "step");
+  HIPCHK(launch_tensor_pass(w.s, ps.yt, ps.data, w.Ac, resid, w.pp, w.pb, w.Mc, e2b, nullptr, st), "pass");
+  HIPCHK(launch_err2(w.s, w.Ac, w.Mc, w.sb.Cc, resid, e2b, ynp, out + 1, st), "err2");
+  HIPCHK(copy_factors_out(w, w.Ac, A_out, st), "copy out");
+  double host[2] = {0, 0}, sc[4] = {0, 0, 0, 0};
+  int flags[1] = {0};
+  HIPCHK(hipMemcpyAsync(host, out, sizeof host, hipMemcpyDeviceToHost, st), "copy");
+  HIPCHK(hipMemcpyAsync(sc, w.sb.scal, sizeof sc, hipMemcpyDeviceToHost, st), "copy");
+  HIPCHK(hipMemcpyAsync(flags, w.flags, sizeof flags, hipMemcpyDeviceToHost, st), "copy");
+  HIPCHK(hipStreamSynchronize(st), "sync");
+  if (info) {
+    info->err2_old = host[0];
+    info->err2_new = host[1];
+    info->denom = sc[0];
+    info->rho = (host[0] - host[1]) / sc[0];
+    info->danorm = sqrt(sc[1]);
+    info->gnorm = sqrt(sc[2]);
+    info->mnorm = sqrt(sc[3]);
+  }
+  if (flags[0]) return set_err(ctx, DGN_ESINGULAR, "non-positive pivot in (Gamma + mu I) or the NR^2 system");
+  if (!isfinite(host[1]) || !isfinite(sc[0])) return set_err(ctx, DGN_ENONFINITE, "non-finite step");
+  return DGN_OK;
+}
+
+dgn_status cp_fit(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, void* const* A, double mu0,
+                  double tol, int32_t max_iters, const dgn_opts* opts, dgn_fit_info* info,
+                  void* stream) {
+  if (!ctx) return DGN_EINVAL;
+  if (!A) return set_err(ctx, DGN_EINVAL, "factor pointer array is NULL");
+  if (max_iters < 0 || !(tol >= 0.0) || !isfinite(mu0))
+    return set_err(ctx, DGN_EINVAL, "need max_iters >= 0, tol >= 0 and a finite mu0");
+  dgn_opts o;
+  dgn_opts_default(&o);
+  if (opts) o = *opts;
+  if (o.poll_every < 1) o.poll_every = 1;
+  if (o.normalize < 0 || o.normalize > 2) return set_err(ctx, DGN_EINVAL, "bad normalize option");
+  Work w{};
+  dgn_status rc = prepare(ctx, Y, R, true, w);
+  if (rc != DGN_OK) return rc;
+  for (int n = 0; n < w.s.N; ++n)
+    if (!A[n]) return set_err(ctx, DGN_EINVAL, "NULL factor pointer");
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(hipSetDevice(ctx->device), "hipSetDevice");
+  bool resid = (w.ymaster == YType::F64) || o.resid_switch < 0;
+  const bool can_switch = !resid && o.resid_switch > 0;
+  PassSel ps = pass_tensor(w, Y, o, resid);
+  const long long J = [&] { long long j = 1; for (int n = 0; n < w.s.N; ++n) j *= w.s.I[n]; return j; }();
+  FitState hs;
+  memset(&hs, 0, sizeof hs);
+  hs.tol = tol;
+  hs.max_iters = max_iters;
+  hs.normalize = o.normalize;
+  hs.stop = 0;
+  FitState* ds = w.state;
+  double* e2 = w.scr + 1024;
+  double* e2c = w.scr + 1025;
+  HIPCHK(hipMemcpyAsync(ds, &hs, sizeof hs, hipMemcpyHostToDevice, st), "state");
+  HIPCHK(copy_factors_in(w, A, w.A, st), "copy factors");
+  HIPCHK(launch_norm2(w.ymaster, Y->data, J, w.scr, kNormParts, &ds->ynorm2, st), "norm");
+  HIPCHK(launch_norm2(ps.yt, ps.data, J, w.scr, kNormParts, &ds->ynorm2_pass, st), "norm");
+  HIPCHK(launch_gram(w.s, w.A, w.sb, w.sb.C, nullptr, st), "gram");
+  HIPCHK(launch_tensor_pass(w.s, ps.yt, ps.data, w.A, resid, w.pp, w.pb, w.M, e2, nullptr, st), "pass");
+  HIPCHK(launch_fit_init(w.s, w.A, w.M, w.sb.C, resid, e2, mu0, o.tau, ds, st), "init");
+  const int* stop = &ds->stop;
+  const int EV = DGN_NUM_PHASES + 1;
+  if (o.timing) {
+    const size_t need = (size_t)EV * max_iters;
+    while (ctx->events.size() < need) {
+      hipEvent_t e;
+      HIPCHK(hipEventCreate(&e), "hipEventCreate");
+      ctx->events.push_back(e);
+    }
+  }
+  ctx->phase_trials = 0;
+  for (int k = 0; k < DGN_NUM_PHASES; ++k) ctx->phase_ms[k] = 0.0;
+  int enq = 0;
+  for (int t = 0; t < max_iters; ++t) {
+    hipEvent_t* ev = o.timing ? &ctx->events[(size_t)EV * t] : nullptr;
+    HIPCHK(enqueue_step(w, resid, 0.0, ds, &ds->singular, stop, st, ev), "step");
+    HIPCHK(mark(ev, 4, st), "event");
+    HIPCHK(launch_tensor_pass(w.s, ps.yt, ps.data, w.Ac, resid, w.pp, w.pb, w.Mc, e2c, stop, st), "pass");
+    HIPCHK(mark(ev, 5, st), "event");
+    HIPCHK(launch_control(w.s, w.Ac, w.Mc, w.sb.Cc, resid, e2c, w.sb.scal, ds, t, st), "control");
+    HIPCHK(launch_commit(w.s, w.A, w.Ac, w.M, w.Mc, w.sb.C, w.sb.Cc, ds, t, st), "commit");
+    HIPCHK(mark(ev, 6, st), "event");
+    enq = t + 1;
+    if ((t + 1) % o.poll_every == 0 || t + 1 == max_iters) {
+      HIPCHK(hipMemcpyAsync(&hs, ds, sizeof hs, hipMemcpyDeviceToHost, st), "poll");
+      HIPCHK(hipStreamSynchronize(st), "sync");
+      if (hs.stop) break;
+      if (can_switch && !resid && hs.accepted > 0 && fabs(hs.eps_prev - hs.eps) < o.resid_switch) {
+        resid = true;
+        ps = pass_tensor(w, Y, o, resid);
+        HIPCHK(launch_tensor_pass(w.s, ps.yt, ps.data, w.A, true, w.pp, w.pb, w.M, e2, stop, st), "pass");
+        HIPCHK(launch_refresh(w.s, e2, ds, st), "refresh");
+      }
+    }
+  }
+  HIPCHK(copy_factors_out(w, w.A, A, st), "copy out");
+  HIPCHK(hipMemcpyAsync(&hs, ds, sizeof hs, hipMemcpyDeviceToHost, st), "state");
+  HIPCHK(hipStreamSynchronize(st), "sync");
+  if (o.timing) {
+    const int nt = hs.iters < enq ? hs.iters : enq;
+    for (int t = 0; t < nt; ++t) {
+      for (int k = 0; k < DGN_NUM_PHASES; ++k) {
+        float ms = 0.0f;
+        HIPCHK(hipEventElapsedTime(&ms, ctx->events[(size_t)EV * t + k], ctx->events[(size_t)EV * t + k + 1]),
+               "hipEventElapsedTime");
+        ctx->phase_ms[k] += ms;
+      }
+    }
+    ctx->phase_trials = nt;
+  }
+  if (info) {
+    info->iters = hs.iters;
+    info->accepted = hs.accepted;
+    info->reason = hs.reason;
+    info->resid_iters = hs.resid_iters;
+    info->eps = hs.eps;
+    info->err2 = hs.err2;
+    info->mu = hs.mu;
+    info->mu0 = hs.mu0;
+  }
+  if (hs.singular) return set_err(ctx, DGN_ESINGULAR, "non-positive pivot in (Gamma + mu I) or the NR^2 system");
+  if (hs.reason == DGN_STOP_NONFINITE) return set_err(ctx, DGN_ENONFINITE, "non-finite error or step");
+  return DGN_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,246 @@
+// Device-resident damping control of the fit (Algorithm 1, Section 4.5).
+//
+// One iteration is one trial step.  The residual of the candidate comes from
+// the tensor pass at the candidate factors: either directly (sum of E^2 in
+// the residual-corrected pass) or as ||Y||^2 - 2 <Y, Y_hat> + ||Y_hat||^2 with
+// <Y, Y_hat> = sum(A_1 * M_1) and ||Y_hat||^2 = sum_{r,s} prod_n C_n[r,s].
+// A trial is accepted iff the residual decreases; then mu <- mu max(1/3,
+// 1 - (2 rho - 1)^3), else mu <- 2 mu.  Accepted factors are normalised; the
+// stored MTTKRP (or gradient) columns and Gram matrices are rescaled with the
+// same column scales, which leave Y_hat unchanged.
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace dgn {
+
+namespace {
+
+// err2 of factors A with pass output M (mode 1 block) and Grams C.
+__device__ double err2_of(const Shape& s, const double* A, const double* M, const double* C,
+                          int resid, const double* e2, double ynorm2_pass, double* red) {
+  if (resid) return e2[0];
+  const int R = s.R, R2 = R * R, I0 = s.I[0];
+  double inner = 0.0;
+  for (int e = threadIdx.x; e < I0 * R; e += blockDim.x) inner += A[e] * M[e];
+  inner = block_sum(inner, red);
+  double yh = 0.0;
+  for (int e = threadIdx.x; e < R2; e += blockDim.x) {
+    double g = 1.0;
+    for (int k = 0; k < s.N; ++k) g *= C[(long long)k * R2 + e];
+    yh += g;
+  }
+  yh = block_sum(yh, red);
+  return ynorm2_pass - 2.0 * inner + yh;
+}
+
+__global__ __launch_bounds__(256) void k_fit_init(Shape s, const double* A, const double* M,
+                                                  const double* C, int resid, const double* e2,
+                                                  double mu0, double tau, FitState* st) {
+  __shared__ double red[16];
+  const double err2 = err2_of(s, A, M, C, resid, e2, st->ynorm2_pass, red);
+  if (threadIdx.x == 0) {
+    const int R = s.R, R2 = R * R;
+    double mu = mu0;
+    if (!(mu0 > 0.0)) {
+      double mx = 0.0;
+      for (int n = 0; n < s.N; ++n)
+        for (int r = 0; r < R; ++r) {
+          double g = 1.0;
+          for (int k = 0; k < s.N; ++k)
+            if (k != n) g *= C[(long long)k * R2 + r + r * R];
+          mx = g > mx ? g : mx;
+        }
+      mu = tau * mx;
+    }
+    st->mu = mu;
+    st->mu0 = mu;
+    st->err2 = err2;
+    st->eps = sqrt(err2 / st->ynorm2);
+    st->eps_prev = st->eps;
+    st->iters = 0;
+    st->accepted = 0;
+    st->stop = (isfinite(err2) && mu > 0.0) ? 0 : 1;
+    st->reason = st->stop ? 3 : 1;
+    st->commit_iter = -1;
+    st->singular = 0;
+    st->resid = resid;
+    st->resid_iters = 0;
+  }
+}
+
+// Residual of the current factors after a switch to the residual-corrected pass.
+__global__ __launch_bounds__(256) void k_refresh(Shape s, const double* e2, FitState* st) {
+  if (threadIdx.x == 0 && !st->stop) {
+    st->err2 = e2[0];
+    st->eps = sqrt(e2[0] / st->ynorm2);
+    st->resid = 1;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_err2(Shape s, const double* A, const double* M,
+                                              const double* C, int resid, const double* e2,
+                                              const double* ynorm2_pass, double* out) {
+  __shared__ double red[16];
+  const double v = err2_of(s, A, M, C, resid, e2, ynorm2_pass[0], red);
+  if (threadIdx.x == 0) out[0] = v;
+}
+
+__global__ __launch_bounds__(256) void k_inner(Shape s, const double* A, const double* M,
+                                               double* out) {
+  __shared__ double red[16];
+  double v = 0.0;
+  for (int e = threadIdx.x; e < s.I[0] * s.R; e += blockDim.x) v += A[e] * M[e];
+  v = block_sum(v, red);
+  if (threadIdx.x == 0) out[0] = v;
+}
+
+__global__ __launch_bounds__(256) void k_control(Shape s, const double* Ac, const double* Mc,
+                                                 const double* Cc, int resid, const double* e2,
+                                                 const double* scal, FitState* st, int trial) {
+  __shared__ double red[16];
+  if (st->stop) return;
+  const double err2c = err2_of(s, Ac, Mc, Cc, resid, e2, st->ynorm2_pass, red);
+  if (threadIdx.x != 0) return;
+  const int N = s.N, R = s.R, R2 = R * R;
+  const double denom = scal[0];
+  st->denom = denom;
+  st->danorm2 = scal[1];
+  st->gnorm2 = scal[2];
+  st->mnorm2 = scal[3];
+  st->err2_cand = err2c;
+  const double rho = (st->err2 - err2c) / denom;
+  st->rho = rho;
+  st->iters += 1;
+  if (resid) st->resid_iters += 1;
+  st->commit_iter = -1;
+  if (st->singular) {
+    st->stop = 1;
+    st->reason = 3;
+    return;
+  }
+  if (!isfinite(err2c) || !isfinite(denom)) {
+    st->stop = 1;
+    st->reason = 3;
+    return;
+  }
+  if (err2c < st->err2) {
+    st->accepted += 1;
+    st->eps_prev = st->eps;
+    st->err2 = err2c;
+    st->eps = sqrt(err2c / st->ynorm2);
+    const double t3 = 2.0 * rho - 1.0;
+    double f = 1.0 - t3 * t3 * t3;
+    if (f < 1.0 / 3.0) f = 1.0 / 3.0;
+    st->mu *= f;
+    st->commit_iter = trial;
+    // column scales of the normalisation (norms from the candidate Grams)
+    for (int r = 0; r < R; ++r) {
+      double lam = 1.0;
+      bool ok = true;
+      for (int n = 0; n < N; ++n) {
+        const double nr = sqrt(Cc[(long long)n * R2 + r + r * R]);
+        ok = ok && nr > 0.0;
+        lam *= nr;
+      }
+      for (int n = 0; n < N; ++n) {
+        const double nr = sqrt(Cc[(long long)n * R2 + r + r * R]);
+        double sc = 1.0;
+        if (ok) {
+          if (st->normalize == 0) {
+            sc = pow(lam, 1.0 / N) / nr;
+          } else if (st->normalize == 1) {
+            if (n < N - 1) {
+              sc = 1.0 / nr;
+            } else {
+              sc = 1.0;
+              for (int k = 0; k < N - 1; ++k) sc *= sqrt(Cc[(long long)k * R2 + r + r * R]);
+            }
+          }
+        }
+        st->scale[n * kMaxRank + r] = sc;
+      }
+    }
+    if (fabs(st->eps_prev - st->eps) < st->tol) {
+      st->stop = 1;
+      st->reason = 0;
+    }
+  } else {
+    st->mu *= 2.0;
+  }
+  if (!st->stop && st->mu > 1e30) {
+    st->stop = 1;
+    st->reason = 2;
+  }
+  if (!st->stop && st->iters >= st->max_iters) {
+    st->stop = 1;
+    st->reason = 1;
+  }
+}
+
+// Apply an accepted trial: A = Ac diag(s_n), M = Mc diag(prod_{k != n} s_k), C = s C s.
+__global__ __launch_bounds__(256) void k_commit(Shape s, double* A, const double* Ac, double* M,
+                                                const double* Mc, double* C, const double* Cc,
+                                                const FitState* st, int trial) {
+  if (st->commit_iter != trial) return;
+  const int n = blockIdx.x, c = blockIdx.y, R = s.R, R2 = R * R, In = s.I[n], N = s.N;
+  const double* sc = st->scale;
+  const long long base = (long long)s.off[n] * R;
+  for (int e = threadIdx.x; e < 64 * R; e += 256) {
+    const int ii = e & 63, r = e >> 6;
+    const int i = c * 64 + ii;
+    if (i >= In) continue;
+    const long long gi = base + i + (long long)r * In;
+    double other = 1.0;
+    for (int k = 0; k < N; ++k)
+      if (k != n) other *= sc[k * kMaxRank + r];
+    A[gi] = Ac[gi] * sc[n * kMaxRank + r];
+    M[gi] = Mc[gi] * other;
+  }
+  if (c == 0) {
+    for (int e = threadIdx.x; e < R2; e += 256) {
+      const int r = e % R, q = e / R;
+      C[(long long)n * R2 + e] = Cc[(long long)n * R2 + e] * sc[n * kMaxRank + r] * sc[n * kMaxRank + q];
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_fit_init(const Shape& s, const double* A, const double* M, const double* C,
+                           bool resid, const double* e2, double mu0, double tau, FitState* state,
+                           hipStream_t st) {
+  k_fit_init<<<1, 256, 0, st>>>(s, A, M, C, resid ? 1 : 0, e2, mu0, tau, state);
+  return hipGetLastError();
+}
+
+hipError_t launch_refresh(const Shape& s, const double* e2, FitState* state, hipStream_t st) {
+  k_refresh<<<1, 64, 0, st>>>(s, e2, state);
+  return hipGetLastError();
+}
+
+hipError_t launch_err2(const Shape& s, const double* A, const double* M, const double* C, bool resid,
+                       const double* e2, const double* ynorm2_pass, double* out, hipStream_t st) {
+  k_err2<<<1, 256, 0, st>>>(s, A, M, C, resid ? 1 : 0, e2, ynorm2_pass, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_inner(const Shape& s, const double* A, const double* M, double* out, hipStream_t st) {
+  k_inner<<<1, 256, 0, st>>>(s, A, M, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_control(const Shape& s, const double* Ac, const double* Mc, const double* Cc,
+                          bool resid, const double* e2, const double* scal, FitState* state,
+                          int trial, hipStream_t st) {
+  k_control<<<1, 256, 0, st>>>(s, Ac, Mc, Cc, resid ? 1 : 0, e2, scal, state, trial);
+  return hipGetLastError();
+}
+
+hipError_t launch_commit(const Shape& s, double* A, const double* Ac, double* M, const double* Mc,
+                         double* C, const double* Cc, const FitState* state, int trial,
+                         hipStream_t st) {
+  k_commit<<<dim3(s.N, row_chunks(s)), 256, 0, st>>>(s, A, Ac, M, Mc, C, Cc, state, trial);
+  return hipGetLastError();
+}
+
+}  // namespace dgn

@@ -1,0 +1,112 @@
+// Host-side launchers shared between the kernel files and the C ABI layer.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "common.hpp"
+
+namespace dgn {
+
+enum class YType { F64 = 0, F32 = 1, BF16 = 2 };
+
+// Launch plan of the one-pass tensor kernel (all-mode MTTKRP, optionally on
+// the residual E = Y - Y_hat formed on the fly).
+struct PassPlan {
+  int tiles_i, tiles_j;  // 64-row / 64-column tiles of the I_1 x I_2 slab
+  int n_qc, q_per;       // chunks of the trailing index q and slabs per chunk
+  long long Q;           // prod_{k>=2} I_k
+  size_t m0_elems, m1_elems, t_elems, e2_elems;  // partial-sum buffers (compute type)
+  size_t tbuf_elems;     // FP64 Q x R buffer (N >= 4 only)
+  int tc_bytes;          // 8 (FP64 pass) or 4 (FP32 accumulation)
+  int mfma;              // 1 when the MFMA kernel is used
+};
+
+PassPlan plan_pass(const Shape& s, YType yt);
+
+struct PassBuffers {
+  void* m0part;
+  void* m1part;
+  void* tpart;
+  double* e2part;
+  double* tbuf;
+};
+
+// M (stacked FP64, I_n x R per mode) = MTTKRP of Y (resid = false) or of
+// E = Y - Y_hat (resid = true) at the stacked FP64 factors A.  With resid,
+// e2out[0] receives sum(E^2).  Returns hipSuccess or the launch error.
+hipError_t launch_tensor_pass(const Shape& s, YType yt, const void* Y, const double* A, bool resid,
+                              const PassPlan& p, const PassBuffers& b, double* M, double* e2out,
+                              const int* stop, hipStream_t st);
+
+// sum(y^2) over n elements of Y in FP64.
+hipError_t launch_norm2(YType yt, const void* Y, long long n, double* part, int nparts, double* out,
+                        hipStream_t st);
+
+// ---- small FP64 kernels (R x R objects, factor rows) ------------------------
+struct SmallBuffers {
+  double *C, *Cc;        // Gram matrices (current / candidate), N R^2
+  double *Gam, *Gt, *X, *Lc;  // Gamma^(n), (Gamma^(n)+mu I)^-1, X X^T = Gt, L L^T = C; N R^2 each
+  double *G, *P;         // gradient blocks and G~ g blocks, stacked T x R
+  double *wpart;         // N x chunks x R^2
+  double *w, *z, *y, *u, *f, *Q;  // N R^2 each (y, z padded)
+  double *Tnm;           // N x N x R x R^2 (T_nm[i, a + d R])
+  double *rowpart;       // N x chunks x (R^2 + 4) partial Grams and scalars
+  double *scal;          // per-trial scalars: denom, ||da||^2, ||g||^2, ||M||^2
+};
+
+int row_chunks(const Shape& s);  // 64-row chunks per mode
+
+hipError_t launch_gram(const Shape& s, const double* A, const SmallBuffers& b, double* Cout,
+                       const int* stop, hipStream_t st);
+hipError_t launch_gamma(const Shape& s, const double* C, double mu_host, const FitState* state,
+                        const SmallBuffers& b, int* singular, const int* stop, hipStream_t st);
+hipError_t launch_pw(const Shape& s, const double* A, const double* M, bool resid,
+                     const SmallBuffers& b, const int* stop, hipStream_t st);
+hipError_t launch_wz(const Shape& s, const SmallBuffers& b, const int* stop, hipStream_t st);
+hipError_t launch_tnm(const Shape& s, const SmallBuffers& b, const int* stop, hipStream_t st);
+hipError_t launch_u(const Shape& s, const SmallBuffers& b, const int* stop, hipStream_t st);
+hipError_t launch_fq(const Shape& s, const SmallBuffers& b, const int* stop, hipStream_t st);
+// A_c = A + P - A Q_n; partial Grams of A_c and the gain-ratio denominator.
+hipError_t launch_update(const Shape& s, const double* A, double* Ac, const SmallBuffers& b,
+                         double mu_host, const FitState* state, const int* stop, hipStream_t st);
+hipError_t launch_update_reduce(const Shape& s, const SmallBuffers& b, double* scal_out,
+                                const int* stop, hipStream_t st);
+
+// ---- NR^2 system (trailing Schur complement, Cholesky, solves) --------------
+struct SysPlan {
+  int R2;       // R^2
+  int nt;       // (N-1) R^2, trailing size
+  int ntp;      // nt padded to a multiple of 64
+  int Tt;       // ntp / 64 tiles
+  int lds;      // leading dimension of the trailing matrix: ntp + 64 (RHS row tile)
+};
+SysPlan plan_sys(const Shape& s);
+
+struct SysBuffers {
+  double* St;   // lds x ntp, column-major; rows ntp.. hold the right-hand side row
+  double* B;    // ntp x R^2, the first block column of S below the identity block
+  double* yt;   // ntp
+};
+
+hipError_t launch_sys_assemble(const Shape& s, const SysPlan& p, const SmallBuffers& b,
+                               const SysBuffers& y, const int* stop, hipStream_t st);
+hipError_t launch_sys_factor_solve(const Shape& s, const SysPlan& p, const SmallBuffers& b,
+                                   const SysBuffers& y, int* singular, const int* stop,
+                                   hipStream_t st);
+
+// ---- fit control -------------------------------------------------------------
+hipError_t launch_fit_init(const Shape& s, const double* A, const double* M, const double* C,
+                           bool resid, const double* e2, double mu0, double tau, FitState* state,
+                           hipStream_t st);
+hipError_t launch_refresh(const Shape& s, const double* e2, FitState* state, hipStream_t st);
+hipError_t launch_err2(const Shape& s, const double* A, const double* M, const double* C, bool resid,
+                       const double* e2, const double* ynorm2_pass, double* out, hipStream_t st);
+hipError_t launch_control(const Shape& s, const double* Ac, const double* Mc, const double* Cc,
+                          bool resid, const double* e2, const double* scal, FitState* state,
+                          int trial, hipStream_t st);
+hipError_t launch_commit(const Shape& s, double* A, const double* Ac, double* M, const double* Mc,
+                         double* C, const double* Cc, const FitState* state, int trial,
+                         hipStream_t st);
+
+}  // namespace dgn

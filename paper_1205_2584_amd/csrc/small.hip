@@ -1,0 +1,507 @@
+// FP64 kernels on the R x R objects and the factor rows of the fast step.
+//
+// Notation (Theorem 4.1 and Lemma 4.4):  C_n = A_n^T A_n, Gamma_n and
+// Gamma_nm the Hadamard products of the C_k over k != n (k != n, m),
+// Gt_n = (Gamma_n + mu I)^-1, G_n = Y_(n) KR - A_n Gamma_n (gradient block),
+// P_n = G_n Gt_n (the block of G~_mu g), w_n = vec(A_n^T P_n).
+//
+// The NR^2 system is solved in the symmetric positive definite form
+//   S = I + W^T K W,   W = blkdiag(X_n (x) L_n),  X_n X_n^T = Gt_n,  L_n L_n^T = C_n,
+// so that Psi_mu = W W^T and f = K (I + Psi K)^-1 w = K (w - W S^-1 W^T K w).
+// These kernels build X_n, L_n, z = W^T K w, and after the solve
+// u = w - W y, f = K u, Q_n = F_n Gt_n and the update A_n + P_n - A_n Q_n.
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace dgn {
+
+namespace {
+
+constexpr int LD = kMaxRank + 1;
+
+__device__ __forceinline__ double gamma_except(const double* C, int N, int R2, int skip1, int skip2,
+                                               int e) {
+  double g = 1.0;
+  for (int k = 0; k < N; ++k)
+    if (k != skip1 && k != skip2) g *= C[(long long)k * R2 + e];
+  return g;
+}
+
+// Cholesky of the R x R matrix H (lower, in place) with 256 threads.
+// mode 0: a non-positive pivot sets *bad.  mode 1 (semidefinite): a pivot
+// below 64 u times the original diagonal zeroes the column.
+__device__ void chol_lds(double (*H)[LD], int R, int mode, int* bad, double* lk) {
+  const int t = threadIdx.x;
+  for (int k = 0; k < R; ++k) {
+    __syncthreads();
+    const double dkk = H[k][k];
+    double d;
+    bool zero = false;
+    if (mode == 0) {
+      if (!(dkk > 0.0)) {
+        if (t == 0) *bad = 1;
+        d = 1.0;
+      } else {
+        d = sqrt(dkk);
+      }
+    } else {
+      const double ref = lk[64 + k];
+      if (!(dkk > 64.0 * 2.220446049250313e-16 * ref)) zero = true;
+      d = zero ? 1.0 : sqrt(dkk);
+    }
+    for (int i = k + t; i < R; i += blockDim.x) lk[i] = zero ? 0.0 : ((i == k) ? d : H[i][k] / d);
+    __syncthreads();
+    const int m = R - k - 1;
+    for (int e = t; e < m * m; e += blockDim.x) {
+      const int i = k + 1 + e % m, j = k + 1 + e / m;
+      if (j <= i) H[i][j] -= lk[i] * lk[j];
+    }
+    for (int i = k + t; i < R; i += blockDim.x) H[i][k] = lk[i];
+  }
+  __syncthreads();
+  for (int e = t; e < R * R; e += blockDim.x) {
+    const int i = e % R, j = e / R;
+    if (j > i) H[i][j] = 0.0;
+  }
+  __syncthreads();
+}
+
+// Gram partials of 64-row chunks: part[(n * chunks + c) * stride + (r + s R)].
+__global__ __launch_bounds__(256) void k_gram_part(Shape s, const double* A, double* part,
+                                                   int chunks, int stride, const int* stop) {
+  if (stopped(stop)) return;
+  __shared__ double As[64][LD];
+  const int n = blockIdx.x, c = blockIdx.y, R = s.R, In = s.I[n];
+  const int r0 = c * 64;
+  double* out = part + ((long long)n * chunks + c) * stride;
+  const double* An = A + (long long)s.off[n] * R;
+  for (int e = threadIdx.x; e < 64 * R; e += 256) {
+    const int ii = e & 63, r = e >> 6;
+    As[ii][r] = (r0 + ii < In) ? An[r0 + ii + (long long)r * In] : 0.0;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < R * R; e += 256) {
+    const int r = e % R, q = e / R;
+    double acc = 0.0;
+    for (int i = 0; i < 64; ++i) acc += As[i][r] * As[i][q];
+    out[e] = acc;
+  }
+}
+
+// out[n * R2 + x] = sum_c part[(n * chunks + c) * stride + x], x < R2.
+__global__ void k_rows_reduce(const double* part, int chunks, int stride, int R2, double* out,
+                              const int* stop) {
+  if (stopped(stop)) return;
+  const int n = blockIdx.x;
+  for (int x = threadIdx.x; x < R2; x += blockDim.x) {
+    double acc = 0.0;
+    for (int c = 0; c < chunks; ++c) acc += part[((long long)n * chunks + c) * stride + x];
+    out[(long long)n * R2 + x] = acc;
+  }
+}
+
+// Per mode n: Gamma_n, Cholesky of Gamma_n + mu I, its inverse factor
+// X_n = L^-T, Gt_n = X_n X_n^T, and the (semidefinite-safe) Cholesky L_n of C_n.
+__global__ __launch_bounds__(256) void k_gamma(Shape s, const double* C, double mu_host,
+                                               const FitState* state, double* Gam, double* Gt,
+                                               double* X, double* Lc, int* bad, const int* stop) {
+  if (stopped(stop)) return;
+  __shared__ double H[64][LD];
+  __shared__ double Li[64][LD];
+  __shared__ double lk[128];
+  const int n = blockIdx.x, R = s.R, R2 = R * R, N = s.N, t = threadIdx.x;
+  const double mu = state ? state->mu : mu_host;
+  for (int e = t; e < R2; e += 256) {
+    const int r = e % R, q = e / R;
+    const double g = gamma_except(C, N, R2, n, -1, e);
+    Gam[(long long)n * R2 + e] = g;
+    H[r][q] = g + (r == q ? mu : 0.0);
+  }
+  chol_lds(H, R, 0, bad, lk);
+  // Li = L^-1 row by row (forward substitution on the identity)
+  for (int i = 0; i < R; ++i) {
+    for (int j = t; j <= i; j += 256) {
+      double v;
+      if (j == i) {
+        v = 1.0 / H[i][i];
+      } else {
+        double acc = 0.0;
+        for (int k = j; k < i; ++k) acc += H[i][k] * Li[k][j];
+        v = -acc / H[i][i];
+      }
+      Li[i][j] = v;
+    }
+    for (int j = i + 1 + t; j < R; j += 256) Li[i][j] = 0.0;
+    __syncthreads();
+  }
+  for (int e = t; e < R2; e += 256) {
+    const int r = e % R, q = e / R;
+    // X = Li^T (upper triangular), Gt = Li^T Li
+    X[(long long)n * R2 + e] = Li[q][r];
+    const int k0 = r > q ? r : q;
+    double acc = 0.0;
+    for (int k = k0; k < R; ++k) acc += Li[k][r] * Li[k][q];
+    Gt[(long long)n * R2 + e] = acc;
+  }
+  __syncthreads();
+  for (int e = t; e < R2; e += 256) {
+    const int r = e % R, q = e / R;
+    H[r][q] = C[(long long)n * R2 + e];
+  }
+  for (int r = t; r < R; r += 256) lk[64 + r] = C[(long long)n * R2 + r + r * R];
+  chol_lds(H, R, 1, bad, lk);
+  for (int e = t; e < R2; e += 256) {
+    const int r = e % R, q = e / R;
+    Lc[(long long)n * R2 + e] = H[r][q];
+  }
+}
+
+// Rows of mode n, chunk c: G = M - A Gamma (or M itself when it already is the
+// gradient), P = G Gt, partial w = A^T P, partial ||G||^2 and ||M||^2.
+__global__ __launch_bounds__(256) void k_pw(Shape s, const double* A, const double* M, int resid,
+                                            const double* Gam, const double* Gt, double* Gout,
+                                            double* Pout, double* part, int chunks, int stride,
+                                            const int* stop) {
+  if (stopped(stop)) return;
+  __shared__ double As[64][LD];
+  __shared__ double Gs[64][LD];
+  __shared__ double Ps[64][LD];
+  __shared__ double Gm[64][LD];
+  __shared__ double red[16];
+  const int n = blockIdx.x, c = blockIdx.y, R = s.R, R2 = R * R, In = s.I[n], t = threadIdx.x;
+  const int r0 = c * 64;
+  double* out = part + ((long long)n * chunks + c) * stride;
+  if (r0 >= In) {
+    for (int e = t; e < R2 + 4; e += 256) out[e] = 0.0;
+    return;
+  }
+  const long long base = (long long)s.off[n] * R;
+  for (int e = t; e < R2; e += 256) {
+    const int r = e % R, q = e / R;
+    Gm[r][q] = resid ? Gt[(long long)n * R2 + e] : Gam[(long long)n * R2 + e];
+  }
+  double m2 = 0.0;
+  for (int e = t; e < 64 * R; e += 256) {
+    const int ii = e & 63, r = e >> 6;
+    const bool ok = r0 + ii < In;
+    const long long gi = base + r0 + ii + (long long)r * In;
+    As[ii][r] = ok ? A[gi] : 0.0;
+    const double mv = ok ? M[gi] : 0.0;
+    Gs[ii][r] = mv;
+    m2 += mv * mv;
+  }
+  __syncthreads();
+  if (!resid) {
+    // G = M - A Gamma
+    for (int e = t; e < 64 * R; e += 256) {
+      const int ii = e & 63, r = e >> 6;
+      double acc = 0.0;
+      for (int k = 0; k < R; ++k) acc += As[ii][k] * Gm[k][r];
+      Ps[ii][r] = Gs[ii][r] - acc;
+    }
+    __syncthreads();
+    for (int e = t; e < 64 * R; e += 256) {
+      const int ii = e & 63, r = e >> 6;
+      Gs[ii][r] = Ps[ii][r];
+    }
+    __syncthreads();
+    for (int e = t; e < R2; e += 256) {
+      const int r = e % R, q = e / R;
+      Gm[r][q] = Gt[(long long)n * R2 + e];
+    }
+    __syncthreads();
+  }
+  double g2 = 0.0;
+  for (int e = t; e < 64 * R; e += 256) {
+    const int ii = e & 63, r = e >> 6;
+    double acc = 0.0;
+    for (int k = 0; k < R; ++k) acc += Gs[ii][k] * Gm[k][r];
+    Ps[ii][r] = acc;
+    if (r0 + ii < In) {
+      const long long gi = base + r0 + ii + (long long)r * In;
+      Gout[gi] = Gs[ii][r];
+      Pout[gi] = acc;
+      g2 += Gs[ii][r] * Gs[ii][r];
+    }
+  }
+  __syncthreads();
+  for (int e = t; e < R2; e += 256) {
+    const int a = e % R, b = e / R;
+    double acc = 0.0;
+    for (int i = 0; i < 64; ++i) acc += As[i][a] * Ps[i][b];
+    out[e] = acc;
+  }
+  g2 = block_sum(g2, red);
+  m2 = block_sum(m2, red);
+  if (t == 0) {
+    out[R2 + 0] = g2;
+    out[R2 + 1] = m2;
+    out[R2 + 2] = 0.0;
+    out[R2 + 3] = 0.0;
+  }
+}
+
+// Per mode n: w_n (reduced), V = sum_{m != n} Gamma_nm * W_m^T and z_n = vec(L_n^T V X_n).
+// Block 0 also reduces ||G||^2 and ||M||^2 into scal[2], scal[3].
+__global__ __launch_bounds__(256) void k_wz(Shape s, const double* C, const double* part,
+                                            int chunks, int stride, const double* X,
+                                            const double* Lc, double* w, double* z, double* scal,
+                                            const int* stop) {
+  if (stopped(stop)) return;
+  __shared__ double V[64][LD];
+  __shared__ double Ls[64][LD];
+  __shared__ double Tm[64][LD];
+  const int n = blockIdx.x, R = s.R, R2 = R * R, N = s.N, t = threadIdx.x;
+  for (int e = t; e < R2; e += 256) {
+    const int a = e % R, b = e / R;
+    double wn = 0.0;
+    for (int c = 0; c < chunks; ++c) wn += part[((long long)n * chunks + c) * stride + e];
+    w[(long long)n * R2 + e] = wn;
+    double v = 0.0;
+    const int et = b + a * R;  // transposed position
+    for (int m = 0; m < N; ++m) {
+      if (m == n) continue;
+      double wm = 0.0;
+      for (int c = 0; c < chunks; ++c) wm += part[((long long)m * chunks + c) * stride + et];
+      v += gamma_except(C, N, R2, n, m, e) * wm;
+    }
+    V[a][b] = v;
+    Ls[a][b] = Lc[(long long)n * R2 + e];
+  }
+  __syncthreads();
+  for (int e = t; e < R2; e += 256) {
+    const int a = e % R, b = e / R;
+    double acc = 0.0;
+    for (int k = 0; k < R; ++k) acc += Ls[k][a] * V[k][b];
+    Tm[a][b] = acc;
+  }
+  __syncthreads();
+  for (int e = t; e < R2; e += 256) {
+    const int a = e % R, b = e / R;
+    double acc = 0.0;
+    for (int k = 0; k < R; ++k) acc += Tm[a][k] * X[(long long)n * R2 + k + b * R];
+    z[(long long)n * R2 + e] = acc;
+  }
+  if (n == 0 && t < 2) {
+    double acc = 0.0;
+    for (int m = 0; m < N; ++m)
+      for (int c = 0; c < chunks; ++c) acc += part[((long long)m * chunks + c) * stride + R2 + t];
+    scal[2 + t] = acc;
+  }
+}
+
+// T_nm[(a + d R) * R + i] = sum_j Gamma_nm[i, j] L_n[j, a] X_m[j, d] for n != m.
+// Grid: (N * N pairs, R values of d).
+__global__ __launch_bounds__(256) void k_tnm(Shape s, const double* C, const double* X,
+                                             const double* Lc, double* Tnm, const int* stop) {
+  if (stopped(stop)) return;
+  __shared__ double Gs[64][LD];
+  __shared__ double Ls[64][LD];
+  __shared__ double xd[64];
+  const int pair = blockIdx.x, d = blockIdx.y, R = s.R, R2 = R * R, N = s.N, t = threadIdx.x;
+  const int n = pair / N, m = pair % N;
+  if (n == m) return;
+  for (int e = t; e < R2; e += 256) {
+    const int i = e % R, j = e / R;
+    Gs[i][j] = gamma_except(C, N, R2, n, m, e);
+    Ls[i][j] = Lc[(long long)n * R2 + e];
+  }
+  for (int j = t; j < R; j += 256) xd[j] = X[(long long)m * R2 + j + d * R];
+  __syncthreads();
+  double* out = Tnm + (long long)pair * R * R2;
+  for (int e = t; e < R2; e += 256) {
+    const int i = e % R, a = e / R;
+    double acc = 0.0;
+    for (int j = 0; j < R; ++j) acc += Gs[i][j] * Ls[j][a] * xd[j];
+    out[((long long)a + (long long)d * R) * R + i] = acc;
+  }
+}
+
+// u_n = w_n - vec(L_n Y_n X_n^T), Y_n = unvec(y_n).
+__global__ __launch_bounds__(256) void k_u(Shape s, const double* w, const double* y,
+                                           const double* X, const double* Lc, double* u,
+                                           const int* stop) {
+  if (stopped(stop)) return;
+  __shared__ double Ys[64][LD];
+  __shared__ double Tm[64][LD];
+  const int n = blockIdx.x, R = s.R, R2 = R * R, t = threadIdx.x;
+  for (int e = t; e < R2; e += 256) Ys[e % R][e / R] = y[(long long)n * R2 + e];
+  __syncthreads();
+  for (int e = t; e < R2; e += 256) {
+    const int a = e % R, b = e / R;
+    double acc = 0.0;
+    for (int k = 0; k < R; ++k) acc += Lc[(long long)n * R2 + a + k * R] * Ys[k][b];
+    Tm[a][b] = acc;
+  }
+  __syncthreads();
+  for (int e = t; e < R2; e += 256) {
+    const int a = e % R, b = e / R;
+    double acc = 0.0;
+    for (int k = 0; k < R; ++k) acc += Tm[a][k] * X[(long long)n * R2 + b + k * R];
+    u[(long long)n * R2 + e] = w[(long long)n * R2 + e] - acc;
+  }
+}
+
+// f_n = vec(sum_{m != n} Gamma_nm * U_m^T) (= (K u)_n), Q_n = F_n Gt_n.
+__global__ __launch_bounds__(256) void k_fq(Shape s, const double* C, const double* u,
+                                            const double* Gt, double* f, double* Q,
+                                            const int* stop) {
+  if (stopped(stop)) return;
+  __shared__ double Fs[64][LD];
+  const int n = blockIdx.x, R = s.R, R2 = R * R, N = s.N, t = threadIdx.x;
+  for (int e = t; e < R2; e += 256) {
+    const int a = e % R, b = e / R;
+    double v = 0.0;
+    for (int m = 0; m < N; ++m) {
+      if (m == n) continue;
+      v += gamma_except(C, N, R2, n, m, e) * u[(long long)m * R2 + b + a * R];
+    }
+    f[(long long)n * R2 + e] = v;
+    Fs[a][b] = v;
+  }
+  __syncthreads();
+  for (int e = t; e < R2; e += 256) {
+    const int a = e % R, b = e / R;
+    double acc = 0.0;
+    for (int k = 0; k < R; ++k) acc += Fs[a][k] * Gt[(long long)n * R2 + k + b * R];
+    Q[(long long)n * R2 + e] = acc;
+  }
+}
+
+// A_c = A + P - A Q_n on the rows of (mode n, chunk c).  Partials: Gram of A_c,
+// sum da (g + mu da) and sum da^2.
+__global__ __launch_bounds__(256) void k_update(Shape s, const double* A, const double* P,
+                                                const double* G, const double* Q, double mu_host,
+                                                const FitState* state, double* Ac, double* part,
+                                                int chunks, int stride, const int* stop) {
+  if (stopped(stop)) return;
+  __shared__ double As[64][LD];
+  __shared__ double Qs[64][LD];
+  __shared__ double Cs[64][LD];
+  __shared__ double red[16];
+  const int n = blockIdx.x, c = blockIdx.y, R = s.R, R2 = R * R, In = s.I[n], t = threadIdx.x;
+  const int r0 = c * 64;
+  double* out = part + ((long long)n * chunks + c) * stride;
+  if (r0 >= In) {
+    for (int e = t; e < R2 + 4; e += 256) out[e] = 0.0;
+    return;
+  }
+  const double mu = state ? state->mu : mu_host;
+  const long long base = (long long)s.off[n] * R;
+  for (int e = t; e < R2; e += 256) Qs[e % R][e / R] = Q[(long long)n * R2 + e];
+  for (int e = t; e < 64 * R; e += 256) {
+    const int ii = e & 63, r = e >> 6;
+    As[ii][r] = (r0 + ii < In) ? A[base + r0 + ii + (long long)r * In] : 0.0;
+  }
+  __syncthreads();
+  double den = 0.0, da2 = 0.0;
+  for (int e = t; e < 64 * R; e += 256) {
+    const int ii = e & 63, r = e >> 6;
+    double v = 0.0;
+    if (r0 + ii < In) {
+      const long long gi = base + r0 + ii + (long long)r * In;
+      double acc = 0.0;
+      for (int k = 0; k < R; ++k) acc += As[ii][k] * Qs[k][r];
+      const double da = P[gi] - acc;
+      v = As[ii][r] + da;
+      Ac[gi] = v;
+      den += da * (G[gi] + mu * da);
+      da2 += da * da;
+    }
+    Cs[ii][r] = v;
+  }
+  __syncthreads();
+  for (int e = t; e < R2; e += 256) {
+    const int r = e % R, q = e / R;
+    double acc = 0.0;
+    for (int i = 0; i < 64; ++i) acc += Cs[i][r] * Cs[i][q];
+    out[e] = acc;
+  }
+  den = block_sum(den, red);
+  da2 = block_sum(da2, red);
+  if (t == 0) {
+    out[R2 + 0] = den;
+    out[R2 + 1] = da2;
+    out[R2 + 2] = 0.0;
+    out[R2 + 3] = 0.0;
+  }
+}
+
+__global__ void k_scalars_reduce(const double* part, int N, int chunks, int stride, int R2,
+                                 double* scal, const int* stop) {
+  if (stopped(stop)) return;
+  if (threadIdx.x < 2) {
+    double acc = 0.0;
+    for (int m = 0; m < N; ++m)
+      for (int c = 0; c < chunks; ++c)
+        acc += part[((long long)m * chunks + c) * stride + R2 + threadIdx.x];
+    scal[threadIdx.x] = acc;
+  }
+}
+
+}  // namespace
+
+int row_chunks(const Shape& s) { return (s.maxI + 63) / 64; }
+
+static inline int part_stride(const Shape& s) { return s.R * s.R + 4; }
+
+hipError_t launch_gram(const Shape& s, const double* A, const SmallBuffers& b, double* Cout,
+                       const int* stop, hipStream_t st) {
+  const int ch = row_chunks(s), stride = part_stride(s);
+  k_gram_part<<<dim3(s.N, ch), 256, 0, st>>>(s, A, b.rowpart, ch, stride, stop);
+  k_rows_reduce<<<s.N, 256, 0, st>>>(b.rowpart, ch, stride, s.R * s.R, Cout, stop);
+  return hipGetLastError();
+}
+
+hipError_t launch_gamma(const Shape& s, const double* C, double mu_host, const FitState* state,
+                        const SmallBuffers& b, int* singular, const int* stop, hipStream_t st) {
+  k_gamma<<<s.N, 256, 0, st>>>(s, C, mu_host, state, b.Gam, b.Gt, b.X, b.Lc, singular, stop);
+  return hipGetLastError();
+}
+
+hipError_t launch_pw(const Shape& s, const double* A, const double* M, bool resid,
+                     const SmallBuffers& b, const int* stop, hipStream_t st) {
+  const int ch = row_chunks(s), stride = part_stride(s);
+  k_pw<<<dim3(s.N, ch), 256, 0, st>>>(s, A, M, resid ? 1 : 0, b.Gam, b.Gt, b.G, b.P, b.wpart, ch,
+                                       stride, stop);
+  return hipGetLastError();
+}
+
+hipError_t launch_wz(const Shape& s, const SmallBuffers& b, const int* stop, hipStream_t st) {
+  const int ch = row_chunks(s), stride = part_stride(s);
+  k_wz<<<s.N, 256, 0, st>>>(s, b.C, b.wpart, ch, stride, b.X, b.Lc, b.w, b.z, b.scal, stop);
+  return hipGetLastError();
+}
+
+hipError_t launch_tnm(const Shape& s, const SmallBuffers& b, const int* stop, hipStream_t st) {
+  k_tnm<<<dim3(s.N * s.N, s.R), 256, 0, st>>>(s, b.C, b.X, b.Lc, b.Tnm, stop);
+  return hipGetLastError();
+}
+
+hipError_t launch_u(const Shape& s, const SmallBuffers& b, const int* stop, hipStream_t st) {
+  k_u<<<s.N, 256, 0, st>>>(s, b.w, b.y, b.X, b.Lc, b.u, stop);
+  return hipGetLastError();
+}
+
+hipError_t launch_fq(const Shape& s, const SmallBuffers& b, const int* stop, hipStream_t st) {
+  k_fq<<<s.N, 256, 0, st>>>(s, b.C, b.u, b.Gt, b.f, b.Q, stop);
+  return hipGetLastError();
+}
+
+hipError_t launch_update(const Shape& s, const double* A, double* Ac, const SmallBuffers& b,
+                         double mu_host, const FitState* state, const int* stop, hipStream_t st) {
+  const int ch = row_chunks(s), stride = part_stride(s);
+  k_update<<<dim3(s.N, ch), 256, 0, st>>>(s, A, b.P, b.G, b.Q, mu_host, state, Ac, b.rowpart, ch,
+                                           stride, stop);
+  return hipGetLastError();
+}
+
+hipError_t launch_update_reduce(const Shape& s, const SmallBuffers& b, double* scal_out,
+                                const int* stop, hipStream_t st) {
+  const int ch = row_chunks(s), stride = part_stride(s);
+  k_rows_reduce<<<s.N, 256, 0, st>>>(b.rowpart, ch, stride, s.R * s.R, b.Cc, stop);
+  k_scalars_reduce<<<1, 64, 0, st>>>(b.rowpart, s.N, ch, stride, s.R * s.R, scal_out, stop);
+  return hipGetLastError();
+}
+
+}  // namespace dgn

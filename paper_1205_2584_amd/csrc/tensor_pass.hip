@@ -1,0 +1,319 @@
+// One pass over a dense tensor computing the MTTKRP of every mode
+// (Section 4.4: Y_(n) times the Khatri-Rao product of the other factors, the
+// O(NRJ) step of Algorithm 1), optionally on the residual E = Y - Y_hat formed
+// on the fly (residual-corrected gradient).
+//
+// Y (first index fastest) is viewed as I_1 x I_2 x Q with Q = prod_{k>=3} I_k
+// and c_q[r] = prod_{k>=3} A^(k)[i_k(q), r].  For every slab Y_q:
+//   Z_q = Y_q A^(2)      -> M_1 += Z_q diag(c_q)
+//   W_q = Y_q^T A^(1)    -> M_2 += W_q diag(c_q)
+//   t_q[r] = sum_i A^(1)[i,r] Z_q[i,r]  -> the trailing modes' MTTKRP from t.
+// Every element of Y is read once; the contraction costs 4 J R flops.
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace dgn {
+
+namespace {
+
+struct PassArgs {
+  const void* Y;
+  int I0, I1, N, R;
+  long long Q;
+  int It[kMaxOrder];   // I_3..I_N (trailing dims), It[k-2] for mode k
+  const double* A;     // stacked FP64 factors
+  int off[kMaxOrder];  // element offsets (row offset * R) of each mode's block
+  int tiles_i, tiles_j, q_per;
+  void* m0part;  // [n_qc][tiles_j][R][I0]
+  void* m1part;  // [n_qc][tiles_i][R][I1]
+  void* tpart;   // [tiles_i*tiles_j][R][Q]
+  double* e2part;
+};
+
+template <typename TY>
+__device__ __forceinline__ float load_cvt(const TY* p, long long i, float*) { return to_f32(p[i]); }
+__device__ __forceinline__ double load_cvt(const double* p, long long i, double*) { return p[i]; }
+
+// Generic FMA version: TC = double for FP64 tensors, float otherwise.
+template <typename TY, typename TC, bool RESID>
+__global__ __launch_bounds__(256) void k_pass_fma(PassArgs a, const int* stop) {
+  if (stopped(stop)) return;
+  __shared__ TC Ys[64][65];                 // Ys[jj][ii] = Y[i0+ii, j0+jj, q]
+  __shared__ TC A0s[64][kMaxRank + 1];      // A^(1) rows of the tile
+  __shared__ TC A1s[64][kMaxRank + 1];      // A^(2) rows of the tile
+  __shared__ TC A1c[RESID ? 64 : 1][kMaxRank + 1];  // A^(2) diag(c_q), residual only
+  __shared__ TC cq[kMaxRank];
+  __shared__ double red[16];
+
+  const int t = threadIdx.x, lane = t & 63, rg = t >> 6;
+  const int R = a.R, I0 = a.I0, I1 = a.I1;
+  const int tile = blockIdx.x;
+  const int ti = tile % a.tiles_i, tj = tile / a.tiles_i;
+  const int i0 = ti * 64, j0 = tj * 64;
+  const long long q0 = (long long)blockIdx.y * a.q_per;
+  long long q1 = q0 + a.q_per;
+  if (q1 > a.Q) q1 = a.Q;
+  const TY* Y = static_cast<const TY*>(a.Y);
+
+  for (int e = t; e < 64 * kMaxRank; e += 256) {
+    const int ii = e & 63, r = e >> 6;
+    const int gi = i0 + ii, gj = j0 + ii;
+    A0s[ii][r] = (r < R && gi < I0) ? (TC)a.A[a.off[0] + gi + (long long)r * I0] : (TC)0;
+    A1s[ii][r] = (r < R && gj < I1) ? (TC)a.A[a.off[1] + gj + (long long)r * I1] : (TC)0;
+  }
+
+  const int KR = (R + 3) / 4;
+  TC m0[16], m1[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) { m0[k] = 0; m1[k] = 0; }
+  double e2 = 0.0;
+
+  for (long long q = q0; q < q1; ++q) {
+    __syncthreads();
+    // stage the 64 x 64 slab tile (coalesced along the first index)
+    const long long base = (long long)I0 * I1 * q;
+#pragma unroll 4
+    for (int e = t; e < 64 * 64; e += 256) {
+      const int ii = e & 63, jj = e >> 6;
+      const int gi = i0 + ii, gj = j0 + jj;
+      TC v = 0;
+      if (gi < I0 && gj < I1) v = (TC)to_f64(Y[base + gi + (long long)I0 * gj]);
+      Ys[jj][ii] = v;
+    }
+    if (t < R) {
+      double c = 1.0;
+      long long qq = q;
+      for (int k = 2; k < a.N; ++k) {
+        const int Ik = a.It[k - 2];
+        const int ik = (int)(qq % Ik);
+        qq /= Ik;
+        c *= a.A[a.off[k] + ik + (long long)t * Ik];
+      }
+      cq[t] = (TC)c;
+    }
+    __syncthreads();
+    if (RESID) {
+      for (int e = t; e < 64 * kMaxRank; e += 256) {
+        const int jj = e & 63, r = e >> 6;
+        A1c[jj][r] = A1s[jj][r] * (r < R ? cq[r] : (TC)0);
+      }
+      __syncthreads();
+      for (int e = t; e < 64 * 64; e += 256) {
+        const int ii = e & 63, jj = e >> 6;
+        TC yh = 0;
+        for (int r = 0; r < R; ++r) yh += A0s[ii][r] * A1c[jj][r];
+        const TC ev = Ys[jj][ii] - yh;  // zero outside the tensor (both terms vanish)
+        e2 += (double)ev * (double)ev;
+        Ys[jj][ii] = ev;
+      }
+      __syncthreads();
+    }
+    TC zp[16], wp[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) { zp[k] = 0; wp[k] = 0; }
+    for (int jj = 0; jj < 64; ++jj) {
+      const TC yv = Ys[jj][lane];
+#pragma unroll
+      for (int k = 0; k < 16; ++k)
+        if (k < KR) zp[k] += yv * A1s[jj][rg + 4 * k];
+    }
+    for (int ii = 0; ii < 64; ++ii) {
+      const TC yv = Ys[lane][ii];
+#pragma unroll
+      for (int k = 0; k < 16; ++k)
+        if (k < KR) wp[k] += yv * A0s[ii][rg + 4 * k];
+    }
+    TC* tp = static_cast<TC*>(a.tpart) + (long long)tile * R * a.Q;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      if (k < KR) {
+        const int r = rg + 4 * k;
+        const TC c = (r < R) ? cq[r] : (TC)0;
+        m0[k] += c * zp[k];
+        m1[k] += c * wp[k];
+        const TC tv = wave_sum(A0s[lane][r] * zp[k]);
+        if (lane == 0 && r < R) tp[(long long)r * a.Q + q] = tv;
+      }
+    }
+  }
+  // partial MTTKRPs of modes 1 and 2 for this tile and q-chunk
+  TC* m0p = static_cast<TC*>(a.m0part) + ((long long)blockIdx.y * a.tiles_j + tj) * R * I0;
+  TC* m1p = static_cast<TC*>(a.m1part) + ((long long)blockIdx.y * a.tiles_i + ti) * R * I1;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int r = rg + 4 * k;
+    if (k < KR && r < R) {
+      if (i0 + lane < I0) m0p[(long long)r * I0 + i0 + lane] = m0[k];
+      if (j0 + lane < I1) m1p[(long long)r * I1 + j0 + lane] = m1[k];
+    }
+  }
+  if (RESID) {
+    const double s = block_sum(e2, red);
+    if (t == 0) a.e2part[(long long)blockIdx.y * gridDim.x + blockIdx.x] = s;
+  }
+}
+
+// out[x] = sum_s part[s * len + x], accumulated in FP64.
+template <typename TC>
+__global__ void k_reduce_slots(const TC* part, int nslots, long long len, double* out,
+                               const int* stop) {
+  if (stopped(stop)) return;
+  for (long long x = blockIdx.x * (long long)blockDim.x + threadIdx.x; x < len;
+       x += (long long)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int k = 0; k < nslots; ++k) s += (double)part[(long long)k * len + x];
+    out[x] = s;
+  }
+}
+
+// MTTKRP of the trailing modes k >= 3 from t[q, r] (Q x R, FP64):
+// M_k[i, r] = sum_{q : i_k(q) = i} t[q, r] prod_{l >= 3, l != k} A^(l)[i_l(q), r].
+__global__ void k_modes_from_t(PassArgs a, const double* tq, double* M, const int* stop) {
+  if (stopped(stop)) return;
+  const int R = a.R;
+  long long total = 0;
+  for (int k = 2; k < a.N; ++k) total += (long long)a.It[k - 2] * R;
+  for (long long x = blockIdx.x * (long long)blockDim.x + threadIdx.x; x < total;
+       x += (long long)gridDim.x * blockDim.x) {
+    long long rem = x;
+    int k = 2;
+    while (rem >= (long long)a.It[k - 2] * R) { rem -= (long long)a.It[k - 2] * R; ++k; }
+    const int Ik = a.It[k - 2];
+    const int i = (int)(rem % Ik), r = (int)(rem / Ik);
+    const long long nother = a.Q / Ik;
+    double s = 0.0;
+    for (long long o = 0; o < nother; ++o) {
+      long long oo = o, q = 0, stride = 1;
+      double c = 1.0;
+      for (int l = 2; l < a.N; ++l) {
+        const int Il = a.It[l - 2];
+        int il;
+        if (l == k) {
+          il = i;
+        } else {
+          il = (int)(oo % Il);
+          oo /= Il;
+          c *= a.A[a.off[l] + il + (long long)r * Il];
+        }
+        q += il * stride;
+        stride *= Il;
+      }
+      s += tq[(long long)r * a.Q + q] * c;
+    }
+    M[a.off[k] + i + (long long)r * Ik] = s;
+  }
+}
+
+__global__ void k_sum(const double* part, int n, double* out, const int* stop) {
+  if (stopped(stop)) return;
+  __shared__ double red[16];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) s += part[i];
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) out[0] = s;
+}
+
+template <typename TY>
+__global__ void k_norm2(const TY* y, long long n, double* part) {
+  __shared__ double red[16];
+  double s = 0.0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const double v = to_f64(y[i]);
+    s += v * v;
+  }
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+}  // namespace
+
+PassPlan plan_pass(const Shape& s, YType yt) {
+  PassPlan p{};
+  p.tiles_i = (s.I[0] + 63) / 64;
+  p.tiles_j = (s.I[1] + 63) / 64;
+  p.Q = 1;
+  for (int k = 2; k < s.N; ++k) p.Q *= s.I[k];
+  const long long tiles = (long long)p.tiles_i * p.tiles_j;
+  long long want = (2048 + tiles - 1) / tiles;
+  if (want > p.Q) want = p.Q;
+  if (want < 1) want = 1;
+  p.q_per = (int)((p.Q + want - 1) / want);
+  p.n_qc = (int)((p.Q + p.q_per - 1) / p.q_per);
+  p.tc_bytes = (yt == YType::F64) ? 8 : 4;
+  p.m0_elems = (size_t)p.n_qc * p.tiles_j * s.R * s.I[0];
+  p.m1_elems = (size_t)p.n_qc * p.tiles_i * s.R * s.I[1];
+  p.t_elems = (size_t)tiles * s.R * p.Q;
+  p.e2_elems = (size_t)tiles * p.n_qc;
+  p.tbuf_elems = (s.N >= 4) ? (size_t)p.Q * s.R : 0;
+  p.mfma = 0;
+  return p;
+}
+
+hipError_t launch_tensor_pass(const Shape& s, YType yt, const void* Y, const double* A, bool resid,
+                              const PassPlan& p, const PassBuffers& b, double* M, double* e2out,
+                              const int* stop, hipStream_t st) {
+  PassArgs a{};
+  a.Y = Y;
+  a.I0 = s.I[0];
+  a.I1 = s.I[1];
+  a.N = s.N;
+  a.R = s.R;
+  a.Q = p.Q;
+  for (int k = 2; k < s.N; ++k) a.It[k - 2] = s.I[k];
+  a.A = A;
+  for (int k = 0; k < s.N; ++k) a.off[k] = s.off[k] * s.R;
+  a.tiles_i = p.tiles_i;
+  a.tiles_j = p.tiles_j;
+  a.q_per = p.q_per;
+  a.m0part = b.m0part;
+  a.m1part = b.m1part;
+  a.tpart = b.tpart;
+  a.e2part = b.e2part;
+  dim3 grid(p.tiles_i * p.tiles_j, p.n_qc);
+  if (yt == YType::F64) {
+    if (resid) k_pass_fma<double, double, true><<<grid, 256, 0, st>>>(a, stop);
+    else k_pass_fma<double, double, false><<<grid, 256, 0, st>>>(a, stop);
+  } else if (yt == YType::F32) {
+    if (resid) k_pass_fma<float, float, true><<<grid, 256, 0, st>>>(a, stop);
+    else k_pass_fma<float, float, false><<<grid, 256, 0, st>>>(a, stop);
+  } else {
+    if (resid) k_pass_fma<__bf16, float, true><<<grid, 256, 0, st>>>(a, stop);
+    else k_pass_fma<__bf16, float, false><<<grid, 256, 0, st>>>(a, stop);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int red_grid = 256;
+  const int nslot0 = p.n_qc * p.tiles_j, nslot1 = p.n_qc * p.tiles_i;
+  const int ntile = p.tiles_i * p.tiles_j;
+  const long long len0 = (long long)s.R * s.I[0], len1 = (long long)s.R * s.I[1];
+  const long long lent = (long long)s.R * p.Q;
+  double* tdst = (s.N == 3) ? M + (long long)s.off[2] * s.R : b.tbuf;
+  if (p.tc_bytes == 8) {
+    k_reduce_slots<double><<<red_grid, 256, 0, st>>>((const double*)b.m0part, nslot0, len0,
+                                                       M + (long long)s.off[0] * s.R, stop);
+    k_reduce_slots<double><<<red_grid, 256, 0, st>>>((const double*)b.m1part, nslot1, len1,
+                                                       M + (long long)s.off[1] * s.R, stop);
+    k_reduce_slots<double><<<red_grid, 256, 0, st>>>((const double*)b.tpart, ntile, lent, tdst, stop);
+  } else {
+    k_reduce_slots<float><<<red_grid, 256, 0, st>>>((const float*)b.m0part, nslot0, len0,
+                                                      M + (long long)s.off[0] * s.R, stop);
+    k_reduce_slots<float><<<red_grid, 256, 0, st>>>((const float*)b.m1part, nslot1, len1,
+                                                      M + (long long)s.off[1] * s.R, stop);
+    k_reduce_slots<float><<<red_grid, 256, 0, st>>>((const float*)b.tpart, ntile, lent, tdst, stop);
+  }
+  if (s.N >= 4) k_modes_from_t<<<256, 256, 0, st>>>(a, b.tbuf, M, stop);
+  if (resid && e2out) k_sum<<<1, 256, 0, st>>>(b.e2part, (int)p.e2_elems, e2out, stop);
+  return hipGetLastError();
+}
+
+hipError_t launch_norm2(YType yt, const void* Y, long long n, double* part, int nparts, double* out,
+                        hipStream_t st) {
+  if (yt == YType::F64) k_norm2<double><<<nparts, 256, 0, st>>>((const double*)Y, n, part);
+  else if (yt == YType::F32) k_norm2<float><<<nparts, 256, 0, st>>>((const float*)Y, n, part);
+  else k_norm2<__bf16><<<nparts, 256, 0, st>>>((const __bf16*)Y, n, part);
+  k_sum<<<1, 256, 0, st>>>(part, nparts, out, nullptr);
+  return hipGetLastError();
+}
+
+}  // namespace dgn

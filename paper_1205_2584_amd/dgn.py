@@ -1,0 +1,221 @@
+"""ctypes binding of libdgn.so (C ABI in include/dgn.h), same names as the C calls.
+
+Argument marshalling only: device buffers are torch tensors on a ROCm device,
+the stream is torch's current stream.  Factors are float64 tensors of shape
+(R, I_n), contiguous -- i.e. column-major I_n x R, the layout the library
+expects.  Tensors are 1-D contiguous vec(Y) with the first index fastest.
+Every call raises DgnError on a non-zero status; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdgn.so")
+
+MAX_ORDER = 8
+F64, F32, BF16, C64, C128 = 0, 1, 2, 3, 4
+NORM_BALANCED, NORM_UNIT_EXCEPT_LAST, NORM_NONE = 0, 1, 2
+STOP_TOL, STOP_MAX_IT, STOP_MU, STOP_NONFINITE = 0, 1, 2, 3
+STATUS = {0: "DGN_OK", -1: "DGN_EINVAL", -2: "DGN_ENOMEM", -3: "DGN_ESINGULAR",
+          -4: "DGN_ENONFINITE", -5: "DGN_EHIP", -6: "DGN_EBUSY"}
+
+_DTYPE = {torch.float64: F64, torch.float32: F32, torch.bfloat16: BF16}
+
+
+class DgnError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class dgn_tensor(ctypes.Structure):
+    _fields_ = [("order", ctypes.c_int32), ("dims", ctypes.c_int64 * MAX_ORDER),
+                ("dtype", ctypes.c_int32), ("data", ctypes.c_void_p)]
+
+
+class dgn_opts(ctypes.Structure):
+    _fields_ = [("normalize", ctypes.c_int32), ("tau", ctypes.c_double),
+                ("resid_switch", ctypes.c_double), ("y_bf16", ctypes.c_void_p),
+                ("poll_every", ctypes.c_int32), ("timing", ctypes.c_int32)]
+
+
+class dgn_step_info(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in
+                ("err2_old", "err2_new", "rho", "denom", "gnorm", "mnorm", "danorm")]
+
+
+class dgn_fit_info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("accepted", ctypes.c_int32), ("reason", ctypes.c_int32),
+                ("resid_iters", ctypes.c_int32), ("eps", ctypes.c_double), ("err2", ctypes.c_double),
+                ("mu", ctypes.c_double), ("mu0", ctypes.c_double)]
+
+
+EXPORTS = ["dgn_opts_default", "dgn_create", "dgn_destroy", "dgn_last_error", "dgn_workspace_size",
+           "dgn_mttkrp", "dgn_step", "cp_fit", "dgn_last_phase_times"]
+NUM_PHASES = 6
+PHASES = ["pre", "assemble", "factor_solve", "update", "tensor_pass", "control"]
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libdgn.so (raises if it is missing: there is no CPU fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built; run __graft_entry__.build() first")
+    L = ctypes.CDLL(path)
+    vp, i32, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+    L.dgn_opts_default.argtypes = [ctypes.POINTER(dgn_opts)]
+    L.dgn_opts_default.restype = None
+    L.dgn_create.argtypes = [ctypes.POINTER(vp), i32, ctypes.c_size_t]
+    L.dgn_destroy.argtypes = [vp]
+    L.dgn_last_error.argtypes = [vp]
+    L.dgn_last_error.restype = ctypes.c_char_p
+    L.dgn_workspace_size.argtypes = [ctypes.POINTER(dgn_tensor), i32, ctypes.POINTER(dgn_opts),
+                                     ctypes.POINTER(ctypes.c_size_t)]
+    L.dgn_mttkrp.argtypes = [vp, ctypes.POINTER(dgn_tensor), i32, ctypes.POINTER(vp),
+                             ctypes.POINTER(vp), ctypes.POINTER(dbl), vp]
+    L.dgn_step.argtypes = [vp, ctypes.POINTER(dgn_tensor), i32, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                           dbl, ctypes.POINTER(dgn_opts), ctypes.POINTER(dgn_step_info), vp]
+    L.cp_fit.argtypes = [vp, ctypes.POINTER(dgn_tensor), i32, ctypes.POINTER(vp), dbl, dbl, i32,
+                         ctypes.POINTER(dgn_opts), ctypes.POINTER(dgn_fit_info), vp]
+    L.dgn_last_phase_times.argtypes = [vp, ctypes.POINTER(dbl), i32, ctypes.POINTER(i32)]
+    for name in ("dgn_create", "dgn_destroy", "dgn_workspace_size", "dgn_mttkrp", "dgn_step", "cp_fit",
+                 "dgn_last_phase_times"):
+        getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def tensor_desc(y: torch.Tensor, dims) -> dgn_tensor:
+    if y.dim() != 1 or not y.is_contiguous():
+        raise ValueError("Y must be a 1-D contiguous tensor holding vec(Y)")
+    if y.dtype not in _DTYPE:
+        raise ValueError(f"unsupported tensor dtype {y.dtype}")
+    d = dgn_tensor()
+    d.order = len(dims)
+    for k, v in enumerate(dims):
+        d.dims[k] = int(v)
+    d.dtype = _DTYPE[y.dtype]
+    d.data = y.data_ptr()
+    return d
+
+
+def opts(**kw) -> dgn_opts:
+    o = dgn_opts()
+    load().dgn_opts_default(ctypes.byref(o))
+    for k, v in kw.items():
+        if k == "y_bf16":
+            v = v.data_ptr() if isinstance(v, torch.Tensor) else v
+        setattr(o, k, v)
+    return o
+
+
+def _ptrs(ts):
+    arr = (ctypes.c_void_p * len(ts))()
+    for k, t in enumerate(ts):
+        if t.dtype != torch.float64 or not t.is_contiguous() or not t.is_cuda:
+            raise ValueError("factors must be contiguous float64 device tensors of shape (R, I_n)")
+        arr[k] = t.data_ptr()
+    return arr
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Context:
+    """A dgn_ctx: one device, one workspace arena (allocated once)."""
+
+    def __init__(self, device: int = 0, ws_bytes: int = 0):
+        self.L = load()
+        h = ctypes.c_void_p()
+        st = self.L.dgn_create(ctypes.byref(h), int(device), int(ws_bytes))
+        if st != 0:
+            raise DgnError(st, "dgn_create failed")
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if self.h:
+            self.L.dgn_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st):
+        if st != 0:
+            raise DgnError(st, self.L.dgn_last_error(self.h).decode())
+
+    def dgn_mttkrp(self, y, dims, R, factors):
+        M = [torch.empty_like(a) for a in factors]
+        inner = ctypes.c_double()
+        d = tensor_desc(y, dims)
+        self._check(self.L.dgn_mttkrp(self.h, ctypes.byref(d), int(R), _ptrs(factors), _ptrs(M),
+                                      ctypes.byref(inner), _stream()))
+        return M, inner.value
+
+    def dgn_step(self, y, dims, R, factors, mu, options: dgn_opts | None = None, out=None):
+        out = [torch.empty_like(a) for a in factors] if out is None else out
+        info = dgn_step_info()
+        d = tensor_desc(y, dims)
+        self._check(self.L.dgn_step(self.h, ctypes.byref(d), int(R), _ptrs(factors), _ptrs(out),
+                                    float(mu), ctypes.byref(options) if options else None,
+                                    ctypes.byref(info), _stream()))
+        return out, {k: getattr(info, k) for k, _ in dgn_step_info._fields_}
+
+    def cp_fit(self, y, dims, R, factors, mu0, tol, max_iters, options: dgn_opts | None = None):
+        """Fit in place: `factors` hold the start and receive the result."""
+        info = dgn_fit_info()
+        d = tensor_desc(y, dims)
+        self._check(self.L.cp_fit(self.h, ctypes.byref(d), int(R), _ptrs(factors), float(mu0),
+                                  float(tol), int(max_iters),
+                                  ctypes.byref(options) if options else None, ctypes.byref(info),
+                                  _stream()))
+        return {k: getattr(info, k) for k, _ in dgn_fit_info._fields_}
+
+    def dgn_last_phase_times(self):
+        """Per-phase total milliseconds of the last timed cp_fit and the trial count."""
+        ms = (ctypes.c_double * NUM_PHASES)()
+        n = ctypes.c_int32()
+        self._check(self.L.dgn_last_phase_times(self.h, ms, NUM_PHASES, ctypes.byref(n)))
+        return dict(zip(PHASES, list(ms))), n.value
+
+
+def workspace_size(dims, R, dtype=torch.float64) -> int:
+    d = dgn_tensor()
+    d.order = len(dims)
+    for k, v in enumerate(dims):
+        d.dims[k] = int(v)
+    d.dtype = _DTYPE[dtype]
+    d.data = 1
+    n = ctypes.c_size_t()
+    st = load().dgn_workspace_size(ctypes.byref(d), int(R), None, ctypes.byref(n))
+    if st != 0:
+        raise DgnError(st, "dgn_workspace_size failed")
+    return n.value
+
+
+# ---- host-side marshalling helpers (numpy <-> device layout) -------------------------
+
+def to_device_factors(A, device="cuda"):
+    """numpy (I_n, R) float64 factors -> contiguous (R, I_n) device tensors."""
+    import numpy as np
+    return [torch.from_numpy(np.ascontiguousarray(np.asarray(a, dtype=np.float64).T)).to(device)
+            for a in A]
+
+
+def to_host_factors(ts):
+    """(R, I_n) device tensors -> numpy (I_n, R) Fortran-ordered float64 arrays."""
+    import numpy as np
+    return [np.asfortranarray(t.detach().cpu().numpy().T) for t in ts]

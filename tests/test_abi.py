@@ -1,0 +1,79 @@
+"""The C ABI library (CPU-only checks: it loads, exports every declared call,
+and validates shapes without touching a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dgn.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1205_2584_amd import dgn
+    if not os.path.exists(dgn.LIB_PATH):
+        from paper_1205_2584_amd import build
+        build.build()
+    return dgn.load()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:[\w\s\*]+?)\b(\w+)\s*\(", text, flags=re.M)) - {"if"})
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ["dgn_create", "dgn_destroy", "dgn_last_error", "dgn_workspace_size", "dgn_mttkrp",
+              "dgn_step", "cp_fit", "dgn_opts_default"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for n in declared_functions():
+        assert hasattr(lib, n), n
+
+
+def test_binding_names_match_header():
+    from paper_1205_2584_amd import dgn
+    assert set(dgn.EXPORTS) == set(declared_functions())
+
+
+def test_opts_defaults(lib):
+    from paper_1205_2584_amd import dgn
+    o = dgn.dgn_opts()
+    lib.dgn_opts_default(ctypes.byref(o))
+    assert o.normalize == 0 and o.tau == 1e-3 and o.resid_switch == 1e-4 and o.poll_every == 8
+
+
+@pytest.mark.parametrize("dims,R,ok", [
+    ((20, 20, 20), 3, True), ((500, 500, 500), 30, True), ((3, 4, 5, 6, 7), 3, True),
+    ((4, 4), 2, False), ((4, 4, 4), 0, False), ((4, 4, 4), 65, False), ((4, 0, 4), 2, False),
+    ((2,) * 9, 2, False),
+])
+def test_workspace_size_validates(lib, dims, R, ok):
+    from paper_1205_2584_amd import dgn
+    d = dgn.dgn_tensor()
+    d.order = len(dims)
+    for k, v in enumerate(dims[:8]):
+        d.dims[k] = v
+    d.dtype = dgn.F32
+    d.data = 1
+    n = ctypes.c_size_t()
+    st = lib.dgn_workspace_size(ctypes.byref(d), R, None, ctypes.byref(n))
+    if ok:
+        assert st == 0 and n.value > 0
+    else:
+        assert st == -1
+
+
+def test_workspace_size_matches_system_size(lib):
+    """The dense trailing system dominates at 500^3, R = 30: ((N-1)R^2 padded)^2 doubles."""
+    from paper_1205_2584_amd import dgn
+    n = dgn.workspace_size((500, 500, 500), 30, dgn.torch.float32)
+    ntp = ((2 * 900 + 63) // 64) * 64
+    assert n > (ntp + 64) * ntp * 8
+    assert n < 512 << 20

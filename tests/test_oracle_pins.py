@@ -176,6 +176,13 @@ def test_mttkrp_brute_force_loop(complex_):
         assert _rel(cp.mttkrp(Y, A, n, conj=complex_), M) < 1e-13
 
 
+@pytest.mark.parametrize("complex_", [False, True])
+def test_full_model_equals_sum_of_outer_products(complex_):
+    dims, R = (4, 3, 5, 2), 3
+    p, _ = _problem(13, dims, R, complex_)
+    assert _rel(cp.full(p.init).reshape(-1, order="F"), brute.model_vec(p.init)) < 1e-14
+
+
 def test_mttkrp_mode1_is_plain_gemm_and_cross_mode_invariant():
     """Mode 1: the vec layout is Y_(1) column-major, so M_1 = reshape(y) @ KR.
     All modes: sum(A_n * M_n) = <Y, Y_hat> computed from the full model."""
