@@ -54,47 +54,175 @@ __device__ __forceinline__ void zero_acc(v4d acc[4]) {
   for (int b = 0; b < 4; ++b) acc[b] = v4d{0.0, 0.0, 0.0, 0.0};
 }
 
-// 64 x 64 Cholesky of the lower triangle of D (LDS) in place; bad pivots flag *bad.
-__device__ void chol64(double (*D)[TL], double* lk, int* bad) {
-  const int t = threadIdx.x;
-  for (int k = 0; k < 64; ++k) {
-    __syncthreads();
-    const double dkk = D[k][k];
-    double d = 1.0;
-    if (dkk > 0.0) d = sqrt(dkk);
-    else if (t == 0) *bad = 1;
-    if (t >= k && t < 64) lk[t] = (t == k) ? d : D[t][k] / d;
-    __syncthreads();
-    const int m = 63 - k;
-    for (int e = t; e < m * m; e += 256) {
-      const int i = k + 1 + e % m, j = k + 1 + e / m;
-      if (j <= i) D[i][j] -= lk[i] * lk[j];
+// Stage a 64 x 64 column-major global tile into LDS as T[col][row]
+// (coalesced; all 16 loads of a thread are issued before the LDS stores).
+__device__ __forceinline__ void stage(double (*T)[TL], const double* g, long long ld) {
+  double v[16];
+#pragma unroll
+  for (int s2 = 0; s2 < 16; ++s2) {
+    const int e = threadIdx.x + 256 * s2, r = e & 63, c = e >> 6;
+    v[s2] = g[r + (long long)c * ld];
+  }
+#pragma unroll
+  for (int s2 = 0; s2 < 16; ++s2) {
+    const int e = threadIdx.x + 256 * s2, r = e & 63, c = e >> 6;
+    T[c][r] = v[s2];
+  }
+}
+
+// Same, stored row-major: T[row][col].
+__device__ __forceinline__ void stage_rowmajor(double (*T)[TL], const double* g, long long ld) {
+  double v[16];
+#pragma unroll
+  for (int s2 = 0; s2 < 16; ++s2) {
+    const int e = threadIdx.x + 256 * s2, r = e & 63, c = e >> 6;
+    v[s2] = g[r + (long long)c * ld];
+  }
+#pragma unroll
+  for (int s2 = 0; s2 < 16; ++s2) {
+    const int e = threadIdx.x + 256 * s2, r = e & 63, c = e >> 6;
+    T[r][c] = v[s2];
+  }
+}
+
+// 1/sqrt(x) to FP64 accuracy: hardware estimate refined by two Newton steps.
+__device__ __forceinline__ double rsqrt_f64(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = y * (1.5 - 0.5 * x * y * y);
+  y = y * (1.5 - 0.5 * x * y * y);
+  return y;
+}
+
+// acc[blk] += A * B^T from LDS tiles stored [col][row]; wave w owns rows
+// 16w.. of A; the result element (v, blk) is (A B^T)[acc_row(v)][acc_col(blk)].
+__device__ __forceinline__ void mma_lds(const double (*A)[TL], const double (*B)[TL], v4d acc[4]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int ra = 16 * w + (lane & 15), kk = lane >> 4;
+#pragma unroll 4
+  for (int k = 0; k < 64; k += 4) {
+    const double a = A[k + kk][ra];
+#pragma unroll
+    for (int blk = 0; blk < 4; ++blk)
+      acc[blk] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, B[k + kk][16 * blk + (lane & 15)], acc[blk], 0, 0, 0);
+  }
+}
+
+// Broadcast lane `src` (wave-uniform) of v to the whole wave.
+__device__ __forceinline__ double lane_value(double v, int src) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), src);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// In-register Cholesky of the 16 x 16 block D[k0.., k0..] by one wave (lanes
+// 0..15 hold one row each); written back lower with zeros above.
+__device__ void chol16_wave(double (*D)[TL], int k0, int* bad) {
+  const int lane = threadIdx.x & 63;
+  const int row = lane & 15;
+  double r[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) r[j] = (j <= row) ? D[k0 + row][k0 + j] : 0.0;
+#pragma unroll
+  for (int c = 0; c < 16; ++c) {
+    const double piv = lane_value(r[c], c);
+    double inv = 1.0;
+    if (piv > 0.0) inv = rsqrt_f64(piv);
+    else if (lane == 0) *bad = 1;
+    const double d = piv > 0.0 ? piv * inv : 1.0;
+    const double l = (row > c) ? r[c] * inv : (row == c ? d : 0.0);
+    r[c] = l;
+#pragma unroll
+    for (int j = c + 1; j < 16; ++j) {
+      const double lj = lane_value(l, j);
+      if (row >= j) r[j] -= l * lj;
     }
-    if (t >= k && t < 64) D[t][k] = lk[t];
+  }
+  if (lane < 16) {
+#pragma unroll
+    for (int j = 0; j < 16; ++j) D[k0 + row][k0 + j] = (j <= row) ? r[j] : 0.0;
+  }
+}
+
+// Rows i (one per thread, i in [i_begin, 64)) of the 16-column block k0:
+// X[i][k0..k0+15] <- X[i][k0..] * L^-T with L = D[k0.., k0..] (lower, LDS).
+__device__ __forceinline__ void trsm16_rows(double (*X)[TL], const double (*L)[TL], int k0, int i) {
+  double x[16];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) x[c] = X[i][k0 + c];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) {
+    double v = x[c];
+#pragma unroll
+    for (int d = 0; d < c; ++d) v -= x[d] * L[k0 + c][k0 + d];
+    x[c] = v * (1.0 / L[k0 + c][k0 + c]);
+  }
+#pragma unroll
+  for (int c = 0; c < 16; ++c) X[i][k0 + c] = x[c];
+}
+
+// acc (one 16 x 16 block) += P[rows rb..][k0..k0+K) * Q[rows cb..][k0..)^T from
+// row-major LDS tiles; result element v is (row rb + lane/16 + 4v, col cb + lane%16).
+__device__ __forceinline__ v4d mma16_rowmajor(const double (*P)[TL], int rb, const double (*Q)[TL], int cb,
+                                              int k0, int K, v4d acc) {
+  const int lane = threadIdx.x & 63;
+  for (int k = 0; k < K; k += 4) {
+    const double a = P[rb + (lane & 15)][k0 + k + (lane >> 4)];
+    const double b = Q[cb + (lane & 15)][k0 + k + (lane >> 4)];
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+// Blocked 64 x 64 Cholesky of the lower triangle of D (row-major LDS) in place.
+__device__ void chol64(double (*D)[TL], int* bad) {
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+  for (int kb = 0; kb < 4; ++kb) {
+    const int k0 = 16 * kb;
+    __syncthreads();
+    if (w == 0) chol16_wave(D, k0, bad);
+    __syncthreads();
+    const int nrow = 48 - k0;
+    if (t < nrow) trsm16_rows(D, D, k0, k0 + 16 + t);
+    __syncthreads();
+    // trailing update of the lower 16 x 16 blocks (bi >= bj) right of k0 + 16
+    const int nb = 3 - kb;
+    int blk = 0;
+    for (int bi = 0; bi < nb; ++bi)
+      for (int bj = 0; bj <= bi; ++bj, ++blk) {
+        if ((blk & 3) != w) continue;
+        const int rb = k0 + 16 + 16 * bi, cb = k0 + 16 + 16 * bj;
+        v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+        acc = mma16_rowmajor(D, rb, D, cb, k0, 16, acc);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) D[rb + (lane >> 4) + 4 * v][cb + (lane & 15)] -= acc[v];
+      }
+  }
+  __syncthreads();
+  // zero the strict upper triangle
+  for (int e = t; e < 64 * 64; e += 256) {
+    const int r = e & 63, c = e >> 6;
+    if (c > r) D[r][c] = 0.0;
   }
   __syncthreads();
 }
 
-// X = Bt * L^-T for the 64 x 64 tile Bt (LDS, overwritten with X); L lower (LDS).
-// Four lanes share a row; each holds the columns congruent to its lane mod 4.
-__device__ void trsm64(double (*Bt)[TL], double (*L)[TL]) {
-  const int t = threadIdx.x, row = t >> 2, sub = t & 3;
-  double x[16];
+// X = Bt * L^-T (64 x 64, row-major LDS, overwritten), L lower (row-major LDS).
+__device__ void trsm64(double (*Bt)[TL], const double (*L)[TL]) {
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+  for (int kb = 0; kb < 4; ++kb) {
+    const int k0 = 16 * kb;
+    if (kb > 0) {
+      // Bt[:, k0..k0+16) -= X[:, 0..k0) L[k0..k0+16, 0..k0)^T ; wave w owns rows 16w..
+      v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+      acc = mma16_rowmajor(Bt, 16 * w, L, k0, 0, k0, acc);
 #pragma unroll
-  for (int c = 0; c < 64; ++c) {
-    double part = 0.0;
-#pragma unroll
-    for (int q = 0; q < 16; ++q)
-      if (4 * q + sub < c) part += x[q] * L[c][4 * q + sub];
-    part += __shfl_xor(part, 1, 64);
-    part += __shfl_xor(part, 2, 64);
-    const double v = (Bt[row][c] - part) / L[c][c];
-    if ((c & 3) == sub) x[c >> 2] = v;
+      for (int v = 0; v < 4; ++v) Bt[16 * w + (lane >> 4) + 4 * v][k0 + (lane & 15)] -= acc[v];
+    }
+    __syncthreads();
+    if (t < 64) trsm16_rows(Bt, L, k0, t);
+    __syncthreads();
   }
-  __syncthreads();
-#pragma unroll
-  for (int q = 0; q < 16; ++q) Bt[row][4 * q + sub] = x[q];
-  __syncthreads();
 }
 
 // Fill the lower tiles of St and all of B with identity / zeros (the
@@ -146,38 +274,72 @@ __global__ __launch_bounds__(256) void k_subblock(Shape s, SysPlan p, const doub
   (void)N;
   const int pair = n * N + m;
   const double* T = Tnm + (long long)pair * R * R2;
-  for (int e = threadIdx.x; e < R2; e += 256) {
-    const int i = e % R, a = e / R;
+  for (int a = (int)(threadIdx.x >> 6); a < R; a += 4)
+  for (int i = (int)(threadIdx.x & 63); i < R; i += 64) {
+    const int e = i + a * R;
     Td[i][a] = T[((long long)a + (long long)d * R) * R + i];
     Lm[i][a] = Lc[(long long)m * R2 + e];  // Lm[i][c] = L_m[i, c]
   }
   for (int i = threadIdx.x; i < R; i += 256) xb[i] = X[(long long)n * R2 + i + b * R];
   __syncthreads();
-  for (int e = threadIdx.x; e < R2; e += 256) {
-    const int a = e % R, c = e / R;
-    double acc = 0.0;
-    for (int i = 0; i < R; ++i) acc += Td[i][a] * xb[i] * Lm[i][c];
+  // fold x_b into T: Td[i][a] *= x_b[i]
+  for (int a = (int)(threadIdx.x >> 6); a < R; a += 4)
+    for (int i = (int)(threadIdx.x & 63); i < R; i += 64) Td[i][a] *= xb[i];
+  __syncthreads();
+  const int sh = R <= 16 ? 4 : (R <= 32 ? 5 : 6);
+  const int a = threadIdx.x & ((1 << sh) - 1), cg = threadIdx.x >> sh, cstep = 256 >> sh;
+  if (a < R) {
     const long long row = (long long)(n - 1) * R2 + a + b * R;  // trailing row index
-    if (m == 0) {
-      B[row + (long long)(c + d * R) * p.ntp] = acc;
-    } else {
-      const long long col = (long long)(m - 1) * R2 + c + d * R;
-      St[row + col * p.lds] = acc;
+    for (int c0 = cg; c0 < R; c0 += 4 * cstep) {
+      double acc[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int i = 0; i < R; ++i) {
+        const double ta = Td[i][a];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int c = c0 + u * cstep;
+          if (c < R) acc[u] += ta * Lm[i][c];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int c = c0 + u * cstep;
+        if (c >= R) continue;
+        if (m == 0) {
+          B[row + (long long)(c + d * R) * p.ntp] = acc[u];
+        } else {
+          const long long col = (long long)(m - 1) * R2 + c + d * R;
+          St[row + col * p.lds] = acc[u];
+        }
+      }
     }
   }
 }
 
-// Right-hand side row: St[ntp, q] = z_t[q] - (B z_1)[q].
-__global__ void k_rhs(SysPlan p, const double* B, const double* z, double* St, const int* stop) {
+// Right-hand side row: St[ntp, q] = z_t[q] - (B z_1)[q]; 64 rows per block,
+// the R^2 sum split over the block's sixteen waves.
+__global__ __launch_bounds__(1024) void k_rhs(SysPlan p, const double* B, const double* z, double* St,
+                                              const int* stop) {
   if (stopped(stop)) return;
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= p.ntp) return;
-  double v = 0.0;
+  __shared__ double part[16][65];
+  const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int q = blockIdx.x * 64 + lane;
+  double a0 = 0.0, a1 = 0.0;
   if (q < p.nt) {
-    v = z[p.R2 + q];
-    for (int k = 0; k < p.R2; ++k) v -= B[q + (long long)k * p.ntp] * z[k];
+    int k = g;
+    for (; k + 16 < p.R2; k += 32) {
+      a0 += B[q + (long long)k * p.ntp] * z[k];
+      a1 += B[q + (long long)(k + 16) * p.ntp] * z[k + 16];
+    }
+    if (k < p.R2) a0 += B[q + (long long)k * p.ntp] * z[k];
   }
-  St[p.ntp + (long long)q * p.lds] = v;
+  part[g][lane] = a0 + a1;
+  __syncthreads();
+  if (g == 0 && q < p.ntp) {
+    double acc = 0.0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc += part[i][lane];
+    St[p.ntp + (long long)q * p.lds] = (q < p.nt) ? z[p.R2 + q] - acc : 0.0;
+  }
 }
 
 __device__ __forceinline__ void tri_index(long long id, int& ti, int& tj) {
@@ -187,20 +349,40 @@ __device__ __forceinline__ void tri_index(long long id, int& ti, int& tj) {
   tj = (int)(id - (long long)ti * (ti + 1) / 2);
 }
 
-// St_tt -= B B^T on the lower tiles (K = R2p, a multiple of 4).
+// St_tt -= B B^T on the lower tiles; K = R^2 in chunks of 64 staged through LDS.
 __global__ __launch_bounds__(256) void k_syrk(SysPlan p, const double* B, int R2p, double* St,
                                               const int* stop) {
   if (stopped(stop)) return;
+  __shared__ double Ti[64][TL];
+  __shared__ double Tj[64][TL];
   int ti, tj;
   tri_index(blockIdx.x, ti, tj);
   v4d acc[4];
   zero_acc(acc);
-  mma_tile(B + ti * 64, p.ntp, B + tj * 64, p.ntp, R2p, acc);
+  for (int k0 = 0; k0 < R2p; k0 += 64) {
+    double vi[16], vj[16];
+#pragma unroll
+    for (int s2 = 0; s2 < 16; ++s2) {
+      const int e = threadIdx.x + 256 * s2, r = e & 63, c = e >> 6;
+      const bool ok = k0 + c < R2p;
+      vi[s2] = ok ? B[ti * 64 + r + (long long)(k0 + c) * p.ntp] : 0.0;
+      vj[s2] = ok ? B[tj * 64 + r + (long long)(k0 + c) * p.ntp] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s2 = 0; s2 < 16; ++s2) {
+      const int e = threadIdx.x + 256 * s2, r = e & 63, c = e >> 6;
+      Ti[c][r] = vi[s2];
+      Tj[c][r] = vj[s2];
+    }
+    __syncthreads();
+    mma_lds(Tj, Ti, acc);
+  }
   double* C = St + ti * 64 + (long long)tj * 64 * p.lds;
 #pragma unroll
   for (int blk = 0; blk < 4; ++blk)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) C[acc_row(v) + (long long)acc_col(blk) * p.lds] -= acc[blk][v];
+    for (int v = 0; v < 4; ++v) C[acc_col(blk) + (long long)acc_row(v) * p.lds] -= acc[blk][v];
 }
 
 // Phase ph of the tiled Cholesky.  Blocks [0, Tt - ph + 1): panel row tiles
@@ -211,9 +393,10 @@ __global__ __launch_bounds__(256) void k_syrk(SysPlan p, const double* B, int R2
 __global__ __launch_bounds__(256) void k_chol_phase(SysPlan p, int ph, double* St, int* bad,
                                                     const int* stop) {
   if (stopped(stop)) return;
-  __shared__ double D[64][TL];
-  __shared__ double Bt[64][TL];
-  __shared__ double lk[64];
+  __shared__ double D[64][TL];   // D[row][col]
+  __shared__ double Bt[64][TL];  // Bt[row][col]
+  __shared__ double La[64][TL];  // staged L(ph, ph-1), [col][row]
+  __shared__ double Lb[64][TL];  // staged L(i, ph-1),  [col][row]
   const int npanel = p.Tt - ph + 1;
   const long long lds = p.lds;
   const int t = threadIdx.x;
@@ -221,32 +404,31 @@ __global__ __launch_bounds__(256) void k_chol_phase(SysPlan p, int ph, double* S
     const int i = ph + blockIdx.x;
     double* Dg = St + ph * 64 + (long long)ph * 64 * lds;
     double* Bg = St + i * 64 + (long long)ph * 64 * lds;
-    for (int e = t; e < 64 * 64; e += 256) {
-      const int r = e & 63, c = e >> 6;
-      D[r][c] = Dg[r + c * lds];
-      if (i != ph) Bt[r][c] = Bg[r + c * lds];
+    stage_rowmajor(D, Dg, lds);
+    if (i != ph) stage_rowmajor(Bt, Bg, lds);
+    if (ph > 0) {
+      stage(La, St + ph * 64 + (long long)(ph - 1) * 64 * lds, lds);
+      if (i != ph) stage(Lb, St + i * 64 + (long long)(ph - 1) * 64 * lds, lds);
     }
     __syncthreads();
     if (ph > 0) {
-      const double* Lp = St + ph * 64 + (long long)(ph - 1) * 64 * lds;   // L(ph, ph-1)
       v4d acc[4];
       zero_acc(acc);
-      mma_tile(Lp, lds, Lp, lds, 64, acc);
+      mma_lds(La, La, acc);
 #pragma unroll
       for (int blk = 0; blk < 4; ++blk)
 #pragma unroll
         for (int v = 0; v < 4; ++v) D[acc_row(v)][acc_col(blk)] -= acc[blk][v];
       if (i != ph) {
-        const double* Li = St + i * 64 + (long long)(ph - 1) * 64 * lds;  // L(i, ph-1)
         zero_acc(acc);
-        mma_tile(Li, lds, Lp, lds, 64, acc);
+        mma_lds(La, Lb, acc);  // (La Lb^T)[ra][cb] = (Lb La^T)[cb][ra]
 #pragma unroll
         for (int blk = 0; blk < 4; ++blk)
 #pragma unroll
-          for (int v = 0; v < 4; ++v) Bt[acc_row(v)][acc_col(blk)] -= acc[blk][v];
+          for (int v = 0; v < 4; ++v) Bt[acc_col(blk)][acc_row(v)] -= acc[blk][v];
       }
     }
-    chol64(D, lk, bad);
+    chol64(D, bad);
     if (i == ph) {
       for (int e = t; e < 64 * 64; e += 256) {
         const int r = e & 63, c = e >> 6;
@@ -264,20 +446,20 @@ __global__ __launch_bounds__(256) void k_chol_phase(SysPlan p, int ph, double* S
   // trailing update with column ph - 1
   if (ph == 0) return;
   long long id = (long long)blockIdx.x - npanel;
-  // enumerate (i, j): j from ph+1 to Tt-1, i from j to Tt
   int j = ph + 1;
   while (id >= (long long)(p.Tt - j + 1)) { id -= (p.Tt - j + 1); ++j; }
   const int i = j + (int)id;
-  const double* Li = St + i * 64 + (long long)(ph - 1) * 64 * lds;
-  const double* Lj = St + j * 64 + (long long)(ph - 1) * 64 * lds;
+  stage(La, St + i * 64 + (long long)(ph - 1) * 64 * lds, lds);  // L(i, ph-1)
+  stage(Lb, St + j * 64 + (long long)(ph - 1) * 64 * lds, lds);  // L(j, ph-1)
+  __syncthreads();
   v4d acc[4];
   zero_acc(acc);
-  mma_tile(Li, lds, Lj, lds, 64, acc);
+  mma_lds(Lb, La, acc);  // (Lj Li^T)[rj][ci]
   double* C = St + i * 64 + (long long)j * 64 * lds;
 #pragma unroll
   for (int blk = 0; blk < 4; ++blk)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) C[acc_row(v) + (long long)acc_col(blk) * lds] -= acc[blk][v];
+    for (int v = 0; v < 4; ++v) C[acc_col(blk) + (long long)acc_row(v) * lds] -= acc[blk][v];
 }
 
 // Backward substitution, phase k (descending): every block solves
@@ -286,22 +468,24 @@ __global__ __launch_bounds__(256) void k_chol_phase(SysPlan p, int ph, double* S
 __global__ __launch_bounds__(256) void k_bsolve(SysPlan p, int k, double* St, double* yt,
                                                 const int* stop) {
   if (stopped(stop)) return;
-  __shared__ double L[64][TL];
+  __shared__ double L[64][TL];   // L[row][col] of the diagonal tile
+  __shared__ double Lt[64][TL];  // staged L(k, j), [col][row]
   __shared__ double ys[64];
+  __shared__ double part[4][64];
   const long long lds = p.lds;
   const int t = threadIdx.x, j = blockIdx.x;
   const double* Lg = St + k * 64 + (long long)k * 64 * lds;
-  for (int e = t; e < 64 * 64; e += 256) {
-    const int r = e & 63, c = e >> 6;
-    L[r][c] = Lg[r + c * lds];
-  }
+  stage_rowmajor(L, Lg, lds);
+  if (j != k) stage(Lt, St + k * 64 + (long long)j * 64 * lds, lds);
   __syncthreads();
   if (t < 64) {
-    // lane c holds u_k[c]; sweep c = 63..0
+    // lane c holds u_k[c]; sweep c = 63..0 (L_kk^T y = u)
     double val = St[p.ntp + (long long)(k * 64 + t) * lds];
+    const double rinv = 1.0 / L[t][t];
     double y = 0.0;
+#pragma unroll
     for (int c = 63; c >= 0; --c) {
-      const double yc = __shfl(val / L[c][c], c, 64);
+      const double yc = lane_value(val * rinv, c);
       if (t == c) y = yc;
       if (t < c) val -= L[c][t] * yc;
     }
@@ -313,11 +497,18 @@ __global__ __launch_bounds__(256) void k_bsolve(SysPlan p, int k, double* St, do
     return;
   }
   // u_j[c] -= sum_r L(k, j)[r][c] y_k[r]
-  const double* Lkj = St + k * 64 + (long long)j * 64 * lds;
+  const int c = t & 63, g = t >> 6;
+  double acc = 0.0;
+#pragma unroll
+  for (int s2 = 0; s2 < 16; ++s2) {
+    const int r = g + 4 * s2;
+    acc += Lt[c][r] * ys[r];
+  }
+  part[g][c] = acc;
+  __syncthreads();
   if (t < 64) {
-    double acc = 0.0;
-    for (int r = 0; r < 64; ++r) acc += Lkj[r + (long long)t * lds] * ys[r];
-    St[p.ntp + (long long)(j * 64 + t) * lds] -= acc;
+    const double v = part[0][t] + part[1][t] + part[2][t] + part[3][t];
+    St[p.ntp + (long long)(j * 64 + t) * lds] -= v;
   }
 }
 
@@ -359,7 +550,7 @@ hipError_t launch_sys_assemble(const Shape& s, const SysPlan& p, const SmallBuff
   k_fill<<<(unsigned)(ntri + extra), 256, 0, st>>>(p, y.St, y.B, R2p, stop);
   const int npairs = s.N * (s.N - 1) / 2;
   k_subblock<<<dim3(npairs * s.R, s.R), 256, 0, st>>>(s, p, b.Tnm, b.X, b.Lc, y.St, y.B, stop);
-  k_rhs<<<(p.ntp + 255) / 256, 256, 0, st>>>(p, y.B, b.z, y.St, stop);
+  k_rhs<<<p.ntp / 64, 1024, 0, st>>>(p, y.B, b.z, y.St, stop);
   k_syrk<<<(unsigned)((long long)p.Tt * (p.Tt + 1) / 2), 256, 0, st>>>(p, y.B, R2p, y.St, stop);
   return hipGetLastError();
 }

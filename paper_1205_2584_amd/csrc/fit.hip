@@ -98,82 +98,85 @@ __global__ __launch_bounds__(256) void k_control(Shape s, const double* Ac, cons
                                                  const double* Cc, int resid, const double* e2,
                                                  const double* scal, FitState* st, int trial) {
   __shared__ double red[16];
+  __shared__ int accept_s;
   if (st->stop) return;
   const double err2c = err2_of(s, Ac, Mc, Cc, resid, e2, st->ynorm2_pass, red);
-  if (threadIdx.x != 0) return;
   const int N = s.N, R = s.R, R2 = R * R;
-  const double denom = scal[0];
-  st->denom = denom;
-  st->danorm2 = scal[1];
-  st->gnorm2 = scal[2];
-  st->mnorm2 = scal[3];
-  st->err2_cand = err2c;
-  const double rho = (st->err2 - err2c) / denom;
-  st->rho = rho;
-  st->iters += 1;
-  if (resid) st->resid_iters += 1;
-  st->commit_iter = -1;
-  if (st->singular) {
-    st->stop = 1;
-    st->reason = 3;
-    return;
-  }
-  if (!isfinite(err2c) || !isfinite(denom)) {
-    st->stop = 1;
-    st->reason = 3;
-    return;
-  }
-  if (err2c < st->err2) {
-    st->accepted += 1;
-    st->eps_prev = st->eps;
-    st->err2 = err2c;
-    st->eps = sqrt(err2c / st->ynorm2);
-    const double t3 = 2.0 * rho - 1.0;
-    double f = 1.0 - t3 * t3 * t3;
-    if (f < 1.0 / 3.0) f = 1.0 / 3.0;
-    st->mu *= f;
-    st->commit_iter = trial;
-    // column scales of the normalisation (norms from the candidate Grams)
-    for (int r = 0; r < R; ++r) {
-      double lam = 1.0;
-      bool ok = true;
-      for (int n = 0; n < N; ++n) {
-        const double nr = sqrt(Cc[(long long)n * R2 + r + r * R]);
-        ok = ok && nr > 0.0;
-        lam *= nr;
+  if (threadIdx.x == 0) {
+    int accept = 0;
+    const double denom = scal[0];
+    st->denom = denom;
+    st->danorm2 = scal[1];
+    st->gnorm2 = scal[2];
+    st->mnorm2 = scal[3];
+    st->err2_cand = err2c;
+    const double rho = (st->err2 - err2c) / denom;
+    st->rho = rho;
+    st->iters += 1;
+    if (resid) st->resid_iters += 1;
+    st->commit_iter = -1;
+    if (st->singular || !isfinite(err2c) || !isfinite(denom)) {
+      st->stop = 1;
+      st->reason = 3;
+    } else {
+      if (err2c < st->err2) {
+        accept = 1;
+        st->accepted += 1;
+        st->eps_prev = st->eps;
+        st->err2 = err2c;
+        st->eps = sqrt(err2c / st->ynorm2);
+        const double t3 = 2.0 * rho - 1.0;
+        double f = 1.0 - t3 * t3 * t3;
+        if (f < 1.0 / 3.0) f = 1.0 / 3.0;
+        st->mu *= f;
+        st->commit_iter = trial;
+        if (fabs(st->eps_prev - st->eps) < st->tol) {
+          st->stop = 1;
+          st->reason = 0;
+        }
+      } else {
+        st->mu *= 2.0;
       }
-      for (int n = 0; n < N; ++n) {
-        const double nr = sqrt(Cc[(long long)n * R2 + r + r * R]);
-        double sc = 1.0;
-        if (ok) {
-          if (st->normalize == 0) {
-            sc = pow(lam, 1.0 / N) / nr;
-          } else if (st->normalize == 1) {
-            if (n < N - 1) {
-              sc = 1.0 / nr;
-            } else {
-              sc = 1.0;
-              for (int k = 0; k < N - 1; ++k) sc *= sqrt(Cc[(long long)k * R2 + r + r * R]);
-            }
+      if (!st->stop && st->mu > 1e30) {
+        st->stop = 1;
+        st->reason = 2;
+      }
+      if (!st->stop && st->iters >= st->max_iters) {
+        st->stop = 1;
+        st->reason = 1;
+      }
+    }
+    accept_s = accept;
+  }
+  __syncthreads();
+  // column scales of the normalisation (norms from the candidate Grams), one column per thread
+  const int r = threadIdx.x;
+  if (accept_s && r < R) {
+    double nr[kMaxOrder];
+    double lam = 1.0;
+    bool ok = true;
+    for (int n = 0; n < N; ++n) {
+      nr[n] = sqrt(Cc[(long long)n * R2 + r + r * R]);
+      ok = ok && nr[n] > 0.0;
+      lam *= nr[n];
+    }
+    const int mode = st->normalize;
+    for (int n = 0; n < N; ++n) {
+      double sc = 1.0;
+      if (ok) {
+        if (mode == 0) {
+          sc = pow(lam, 1.0 / N) / nr[n];
+        } else if (mode == 1) {
+          if (n < N - 1) {
+            sc = 1.0 / nr[n];
+          } else {
+            sc = 1.0;
+            for (int k = 0; k < N - 1; ++k) sc *= nr[k];
           }
         }
-        st->scale[n * kMaxRank + r] = sc;
       }
+      st->scale[n * kMaxRank + r] = sc;
     }
-    if (fabs(st->eps_prev - st->eps) < st->tol) {
-      st->stop = 1;
-      st->reason = 0;
-    }
-  } else {
-    st->mu *= 2.0;
-  }
-  if (!st->stop && st->mu > 1e30) {
-    st->stop = 1;
-    st->reason = 2;
-  }
-  if (!st->stop && st->iters >= st->max_iters) {
-    st->stop = 1;
-    st->reason = 1;
   }
 }
 
@@ -197,10 +200,11 @@ __global__ __launch_bounds__(256) void k_commit(Shape s, double* A, const double
     M[gi] = Mc[gi] * other;
   }
   if (c == 0) {
-    for (int e = threadIdx.x; e < R2; e += 256) {
-      const int r = e % R, q = e / R;
-      C[(long long)n * R2 + e] = Cc[(long long)n * R2 + e] * sc[n * kMaxRank + r] * sc[n * kMaxRank + q];
-    }
+    for (int q = (int)(threadIdx.x >> 6); q < R; q += 4)
+      for (int r = (int)(threadIdx.x & 63); r < R; r += 64) {
+        const int e = r + q * R;
+        C[(long long)n * R2 + e] = Cc[(long long)n * R2 + e] * sc[n * kMaxRank + r] * sc[n * kMaxRank + q];
+      }
   }
 }
 

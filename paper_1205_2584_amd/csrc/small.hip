@@ -19,6 +19,15 @@ namespace {
 
 constexpr int LD = kMaxRank + 1;
 
+// Loop over the R x R positions (r, q), R <= 64, without integer division:
+// thread t takes r = t mod 2^sh and q = t / 2^sh + s blockDim / 2^sh, with
+// 2^sh the smallest of 16, 32, 64 that covers R (declare RR_SHIFT first).
+__device__ __forceinline__ int rr_shift_of(int R) { return R <= 16 ? 4 : (R <= 32 ? 5 : 6); }
+#define RR_SHIFT const int rr_sh = rr_shift_of(R)
+#define FOR_RR(r, q)                                                              \
+  for (int q = (int)(threadIdx.x >> rr_sh); q < R; q += (int)(blockDim.x >> rr_sh)) \
+    for (int r = (int)(threadIdx.x & ((1 << rr_sh) - 1)); r < R; r += (1 << rr_sh))
+
 __device__ __forceinline__ double gamma_except(const double* C, int N, int R2, int skip1, int skip2,
                                                int e) {
   double g = 1.0;
@@ -51,16 +60,15 @@ __device__ void chol_lds(double (*H)[LD], int R, int mode, int* bad, double* lk)
     }
     for (int i = k + t; i < R; i += blockDim.x) lk[i] = zero ? 0.0 : ((i == k) ? d : H[i][k] / d);
     __syncthreads();
-    const int m = R - k - 1;
-    for (int e = t; e < m * m; e += blockDim.x) {
-      const int i = k + 1 + e % m, j = k + 1 + e / m;
-      if (j <= i) H[i][j] -= lk[i] * lk[j];
+    for (int j = k + 1 + (int)(t >> 6); j < R; j += (int)(blockDim.x >> 6)) {
+      const int i = t & 63;
+      if (i >= j && i < R) H[i][j] -= lk[i] * lk[j];
     }
     for (int i = k + t; i < R; i += blockDim.x) H[i][k] = lk[i];
   }
   __syncthreads();
-  for (int e = t; e < R * R; e += blockDim.x) {
-    const int i = e % R, j = e / R;
+  RR_SHIFT;
+  FOR_RR(i, j) {
     if (j > i) H[i][j] = 0.0;
   }
   __syncthreads();
@@ -72,6 +80,7 @@ __global__ __launch_bounds__(256) void k_gram_part(Shape s, const double* A, dou
   if (stopped(stop)) return;
   __shared__ double As[64][LD];
   const int n = blockIdx.x, c = blockIdx.y, R = s.R, In = s.I[n];
+  RR_SHIFT;
   const int r0 = c * 64;
   double* out = part + ((long long)n * chunks + c) * stride;
   const double* An = A + (long long)s.off[n] * R;
@@ -80,8 +89,8 @@ __global__ __launch_bounds__(256) void k_gram_part(Shape s, const double* A, dou
     As[ii][r] = (r0 + ii < In) ? An[r0 + ii + (long long)r * In] : 0.0;
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < R * R; e += 256) {
-    const int r = e % R, q = e / R;
+  FOR_RR(r, q) {
+    const int e = r + q * R;
     double acc = 0.0;
     for (int i = 0; i < 64; ++i) acc += As[i][r] * As[i][q];
     out[e] = acc;
@@ -110,32 +119,30 @@ __global__ __launch_bounds__(256) void k_gamma(Shape s, const double* C, double 
   __shared__ double Li[64][LD];
   __shared__ double lk[128];
   const int n = blockIdx.x, R = s.R, R2 = R * R, N = s.N, t = threadIdx.x;
+  RR_SHIFT;
   const double mu = state ? state->mu : mu_host;
-  for (int e = t; e < R2; e += 256) {
-    const int r = e % R, q = e / R;
+  FOR_RR(r, q) {
+    const int e = r + q * R;
     const double g = gamma_except(C, N, R2, n, -1, e);
     Gam[(long long)n * R2 + e] = g;
     H[r][q] = g + (r == q ? mu : 0.0);
   }
   chol_lds(H, R, 0, bad, lk);
-  // Li = L^-1 row by row (forward substitution on the identity)
-  for (int i = 0; i < R; ++i) {
-    for (int j = t; j <= i; j += 256) {
-      double v;
-      if (j == i) {
-        v = 1.0 / H[i][i];
-      } else {
+  // Li = L^-1, one column per thread (forward substitution on the identity)
+  for (int j = t; j < 64; j += 256) {
+    if (j < R) {
+      Li[j][j] = 1.0 / H[j][j];
+      for (int i = j + 1; i < R; ++i) {
         double acc = 0.0;
         for (int k = j; k < i; ++k) acc += H[i][k] * Li[k][j];
-        v = -acc / H[i][i];
+        Li[i][j] = -acc / H[i][i];
       }
-      Li[i][j] = v;
+      for (int i = 0; i < j; ++i) Li[i][j] = 0.0;
     }
-    for (int j = i + 1 + t; j < R; j += 256) Li[i][j] = 0.0;
-    __syncthreads();
   }
-  for (int e = t; e < R2; e += 256) {
-    const int r = e % R, q = e / R;
+  __syncthreads();
+  FOR_RR(r, q) {
+    const int e = r + q * R;
     // X = Li^T (upper triangular), Gt = Li^T Li
     X[(long long)n * R2 + e] = Li[q][r];
     const int k0 = r > q ? r : q;
@@ -144,14 +151,14 @@ __global__ __launch_bounds__(256) void k_gamma(Shape s, const double* C, double 
     Gt[(long long)n * R2 + e] = acc;
   }
   __syncthreads();
-  for (int e = t; e < R2; e += 256) {
-    const int r = e % R, q = e / R;
+  FOR_RR(r, q) {
+    const int e = r + q * R;
     H[r][q] = C[(long long)n * R2 + e];
   }
   for (int r = t; r < R; r += 256) lk[64 + r] = C[(long long)n * R2 + r + r * R];
   chol_lds(H, R, 1, bad, lk);
-  for (int e = t; e < R2; e += 256) {
-    const int r = e % R, q = e / R;
+  FOR_RR(r, q) {
+    const int e = r + q * R;
     Lc[(long long)n * R2 + e] = H[r][q];
   }
 }
@@ -169,6 +176,7 @@ __global__ __launch_bounds__(256) void k_pw(Shape s, const double* A, const doub
   __shared__ double Gm[64][LD];
   __shared__ double red[16];
   const int n = blockIdx.x, c = blockIdx.y, R = s.R, R2 = R * R, In = s.I[n], t = threadIdx.x;
+  RR_SHIFT;
   const int r0 = c * 64;
   double* out = part + ((long long)n * chunks + c) * stride;
   if (r0 >= In) {
@@ -176,8 +184,8 @@ __global__ __launch_bounds__(256) void k_pw(Shape s, const double* A, const doub
     return;
   }
   const long long base = (long long)s.off[n] * R;
-  for (int e = t; e < R2; e += 256) {
-    const int r = e % R, q = e / R;
+  FOR_RR(r, q) {
+    const int e = r + q * R;
     Gm[r][q] = resid ? Gt[(long long)n * R2 + e] : Gam[(long long)n * R2 + e];
   }
   double m2 = 0.0;
@@ -205,8 +213,8 @@ __global__ __launch_bounds__(256) void k_pw(Shape s, const double* A, const doub
       Gs[ii][r] = Ps[ii][r];
     }
     __syncthreads();
-    for (int e = t; e < R2; e += 256) {
-      const int r = e % R, q = e / R;
+    FOR_RR(r, q) {
+      const int e = r + q * R;
       Gm[r][q] = Gt[(long long)n * R2 + e];
     }
     __syncthreads();
@@ -225,8 +233,8 @@ __global__ __launch_bounds__(256) void k_pw(Shape s, const double* A, const doub
     }
   }
   __syncthreads();
-  for (int e = t; e < R2; e += 256) {
-    const int a = e % R, b = e / R;
+  FOR_RR(a, b) {
+    const int e = a + b * R;
     double acc = 0.0;
     for (int i = 0; i < 64; ++i) acc += As[i][a] * Ps[i][b];
     out[e] = acc;
@@ -241,52 +249,64 @@ __global__ __launch_bounds__(256) void k_pw(Shape s, const double* A, const doub
   }
 }
 
-// Per mode n: w_n (reduced), V = sum_{m != n} Gamma_nm * W_m^T and z_n = vec(L_n^T V X_n).
-// Block 0 also reduces ||G||^2 and ||M||^2 into scal[2], scal[3].
-__global__ __launch_bounds__(256) void k_wz(Shape s, const double* C, const double* part,
-                                            int chunks, int stride, const double* X,
-                                            const double* Lc, double* w, double* z, double* scal,
-                                            const int* stop) {
+// w_n = sum over row chunks of the partial A_n^T P_n; block 0 also reduces
+// ||G||^2 and ||M||^2 into scal[2], scal[3].
+__global__ __launch_bounds__(256) void k_wred(Shape s, const double* part, int chunks, int stride,
+                                              double* w, double* scal, const int* stop) {
   if (stopped(stop)) return;
-  __shared__ double V[64][LD];
-  __shared__ double Ls[64][LD];
-  __shared__ double Tm[64][LD];
   const int n = blockIdx.x, R = s.R, R2 = R * R, N = s.N, t = threadIdx.x;
   for (int e = t; e < R2; e += 256) {
-    const int a = e % R, b = e / R;
-    double wn = 0.0;
-    for (int c = 0; c < chunks; ++c) wn += part[((long long)n * chunks + c) * stride + e];
-    w[(long long)n * R2 + e] = wn;
-    double v = 0.0;
-    const int et = b + a * R;  // transposed position
-    for (int m = 0; m < N; ++m) {
-      if (m == n) continue;
-      double wm = 0.0;
-      for (int c = 0; c < chunks; ++c) wm += part[((long long)m * chunks + c) * stride + et];
-      v += gamma_except(C, N, R2, n, m, e) * wm;
+    const double* p0 = part + (long long)n * chunks * stride + e;
+    double a0 = 0.0, a1 = 0.0;
+    int c = 0;
+    for (; c + 1 < chunks; c += 2) {
+      a0 += p0[(long long)c * stride];
+      a1 += p0[(long long)(c + 1) * stride];
     }
-    V[a][b] = v;
-    Ls[a][b] = Lc[(long long)n * R2 + e];
-  }
-  __syncthreads();
-  for (int e = t; e < R2; e += 256) {
-    const int a = e % R, b = e / R;
-    double acc = 0.0;
-    for (int k = 0; k < R; ++k) acc += Ls[k][a] * V[k][b];
-    Tm[a][b] = acc;
-  }
-  __syncthreads();
-  for (int e = t; e < R2; e += 256) {
-    const int a = e % R, b = e / R;
-    double acc = 0.0;
-    for (int k = 0; k < R; ++k) acc += Tm[a][k] * X[(long long)n * R2 + k + b * R];
-    z[(long long)n * R2 + e] = acc;
+    if (c < chunks) a0 += p0[(long long)c * stride];
+    w[(long long)n * R2 + e] = a0 + a1;
   }
   if (n == 0 && t < 2) {
     double acc = 0.0;
     for (int m = 0; m < N; ++m)
       for (int c = 0; c < chunks; ++c) acc += part[((long long)m * chunks + c) * stride + R2 + t];
     scal[2 + t] = acc;
+  }
+}
+
+// Per mode n: V = sum_{m != n} Gamma_nm * W_m^T and z_n = vec(L_n^T V X_n) (= (W^T K w)_n).
+__global__ __launch_bounds__(256) void k_z(Shape s, const double* C, const double* w,
+                                           const double* X, const double* Lc, double* z,
+                                           const int* stop) {
+  if (stopped(stop)) return;
+  __shared__ double V[64][LD];
+  __shared__ double Ls[64][LD];
+  __shared__ double Xs[64][LD];
+  __shared__ double Tm[64][LD];
+  const int n = blockIdx.x, R = s.R, R2 = R * R, N = s.N;
+  RR_SHIFT;
+  FOR_RR(a, b) {
+    const int e = a + b * R;
+    double v = 0.0;
+    for (int m = 0; m < N; ++m) {
+      if (m == n) continue;
+      v += gamma_except(C, N, R2, n, m, e) * w[(long long)m * R2 + b + a * R];
+    }
+    V[a][b] = v;
+    Ls[a][b] = Lc[(long long)n * R2 + e];
+    Xs[a][b] = X[(long long)n * R2 + e];
+  }
+  __syncthreads();
+  FOR_RR(a, b) {
+    double acc = 0.0;
+    for (int k = 0; k < R; ++k) acc += Ls[k][a] * V[k][b];
+    Tm[a][b] = acc;
+  }
+  __syncthreads();
+  FOR_RR(a, b) {
+    double acc = 0.0;
+    for (int k = 0; k < R; ++k) acc += Tm[a][k] * Xs[k][b];
+    z[(long long)n * R2 + a + b * R] = acc;
   }
 }
 
@@ -299,18 +319,19 @@ __global__ __launch_bounds__(256) void k_tnm(Shape s, const double* C, const dou
   __shared__ double Ls[64][LD];
   __shared__ double xd[64];
   const int pair = blockIdx.x, d = blockIdx.y, R = s.R, R2 = R * R, N = s.N, t = threadIdx.x;
+  RR_SHIFT;
   const int n = pair / N, m = pair % N;
   if (n == m) return;
-  for (int e = t; e < R2; e += 256) {
-    const int i = e % R, j = e / R;
+  FOR_RR(i, j) {
+    const int e = i + j * R;
     Gs[i][j] = gamma_except(C, N, R2, n, m, e);
     Ls[i][j] = Lc[(long long)n * R2 + e];
   }
   for (int j = t; j < R; j += 256) xd[j] = X[(long long)m * R2 + j + d * R];
   __syncthreads();
   double* out = Tnm + (long long)pair * R * R2;
-  for (int e = t; e < R2; e += 256) {
-    const int i = e % R, a = e / R;
+  FOR_RR(i, a) {
+    const int e = i + a * R;
     double acc = 0.0;
     for (int j = 0; j < R; ++j) acc += Gs[i][j] * Ls[j][a] * xd[j];
     out[((long long)a + (long long)d * R) * R + i] = acc;
@@ -324,20 +345,27 @@ __global__ __launch_bounds__(256) void k_u(Shape s, const double* w, const doubl
   if (stopped(stop)) return;
   __shared__ double Ys[64][LD];
   __shared__ double Tm[64][LD];
-  const int n = blockIdx.x, R = s.R, R2 = R * R, t = threadIdx.x;
-  for (int e = t; e < R2; e += 256) Ys[e % R][e / R] = y[(long long)n * R2 + e];
+  __shared__ double Ls[64][LD];
+  __shared__ double Xs[64][LD];
+  const int n = blockIdx.x, R = s.R, R2 = R * R;
+  RR_SHIFT;
+  FOR_RR(r, q) {
+    const long long e = (long long)n * R2 + r + q * R;
+    Ys[r][q] = y[e];
+    Ls[r][q] = Lc[e];
+    Xs[r][q] = X[e];
+  }
   __syncthreads();
-  for (int e = t; e < R2; e += 256) {
-    const int a = e % R, b = e / R;
+  FOR_RR(a, b) {
     double acc = 0.0;
-    for (int k = 0; k < R; ++k) acc += Lc[(long long)n * R2 + a + k * R] * Ys[k][b];
+    for (int k = 0; k < R; ++k) acc += Ls[a][k] * Ys[k][b];
     Tm[a][b] = acc;
   }
   __syncthreads();
-  for (int e = t; e < R2; e += 256) {
-    const int a = e % R, b = e / R;
+  FOR_RR(a, b) {
+    const int e = a + b * R;
     double acc = 0.0;
-    for (int k = 0; k < R; ++k) acc += Tm[a][k] * X[(long long)n * R2 + b + k * R];
+    for (int k = 0; k < R; ++k) acc += Tm[a][k] * Xs[b][k];
     u[(long long)n * R2 + e] = w[(long long)n * R2 + e] - acc;
   }
 }
@@ -348,9 +376,12 @@ __global__ __launch_bounds__(256) void k_fq(Shape s, const double* C, const doub
                                             const int* stop) {
   if (stopped(stop)) return;
   __shared__ double Fs[64][LD];
-  const int n = blockIdx.x, R = s.R, R2 = R * R, N = s.N, t = threadIdx.x;
-  for (int e = t; e < R2; e += 256) {
-    const int a = e % R, b = e / R;
+  __shared__ double Gs[64][LD];
+  const int n = blockIdx.x, R = s.R, R2 = R * R, N = s.N;
+  RR_SHIFT;
+  FOR_RR(a, b) {
+    const int e = a + b * R;
+    Gs[a][b] = Gt[(long long)n * R2 + e];
     double v = 0.0;
     for (int m = 0; m < N; ++m) {
       if (m == n) continue;
@@ -360,10 +391,10 @@ __global__ __launch_bounds__(256) void k_fq(Shape s, const double* C, const doub
     Fs[a][b] = v;
   }
   __syncthreads();
-  for (int e = t; e < R2; e += 256) {
-    const int a = e % R, b = e / R;
+  FOR_RR(a, b) {
+    const int e = a + b * R;
     double acc = 0.0;
-    for (int k = 0; k < R; ++k) acc += Fs[a][k] * Gt[(long long)n * R2 + k + b * R];
+    for (int k = 0; k < R; ++k) acc += Fs[a][k] * Gs[k][b];
     Q[(long long)n * R2 + e] = acc;
   }
 }
@@ -380,6 +411,7 @@ __global__ __launch_bounds__(256) void k_update(Shape s, const double* A, const 
   __shared__ double Cs[64][LD];
   __shared__ double red[16];
   const int n = blockIdx.x, c = blockIdx.y, R = s.R, R2 = R * R, In = s.I[n], t = threadIdx.x;
+  RR_SHIFT;
   const int r0 = c * 64;
   double* out = part + ((long long)n * chunks + c) * stride;
   if (r0 >= In) {
@@ -388,7 +420,7 @@ __global__ __launch_bounds__(256) void k_update(Shape s, const double* A, const 
   }
   const double mu = state ? state->mu : mu_host;
   const long long base = (long long)s.off[n] * R;
-  for (int e = t; e < R2; e += 256) Qs[e % R][e / R] = Q[(long long)n * R2 + e];
+  FOR_RR(r, q) Qs[r][q] = Q[(long long)n * R2 + r + q * R];
   for (int e = t; e < 64 * R; e += 256) {
     const int ii = e & 63, r = e >> 6;
     As[ii][r] = (r0 + ii < In) ? A[base + r0 + ii + (long long)r * In] : 0.0;
@@ -411,8 +443,8 @@ __global__ __launch_bounds__(256) void k_update(Shape s, const double* A, const 
     Cs[ii][r] = v;
   }
   __syncthreads();
-  for (int e = t; e < R2; e += 256) {
-    const int r = e % R, q = e / R;
+  FOR_RR(r, q) {
+    const int e = r + q * R;
     double acc = 0.0;
     for (int i = 0; i < 64; ++i) acc += Cs[i][r] * Cs[i][q];
     out[e] = acc;
@@ -469,7 +501,8 @@ hipError_t launch_pw(const Shape& s, const double* A, const double* M, bool resi
 
 hipError_t launch_wz(const Shape& s, const SmallBuffers& b, const int* stop, hipStream_t st) {
   const int ch = row_chunks(s), stride = part_stride(s);
-  k_wz<<<s.N, 256, 0, st>>>(s, b.C, b.wpart, ch, stride, b.X, b.Lc, b.w, b.z, b.scal, stop);
+  k_wred<<<s.N, 256, 0, st>>>(s, b.wpart, ch, stride, b.w, b.scal, stop);
+  k_z<<<s.N, 256, 0, st>>>(s, b.C, b.w, b.X, b.Lc, b.z, stop);
   return hipGetLastError();
 }
 

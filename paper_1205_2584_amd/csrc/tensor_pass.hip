@@ -153,16 +153,359 @@ __global__ __launch_bounds__(256) void k_pass_fma(PassArgs a, const int* stop) {
   }
 }
 
-// out[x] = sum_s part[s * len + x], accumulated in FP64.
-template <typename TC>
-__global__ void k_reduce_slots(const TC* part, int nslots, long long len, double* out,
-                               const int* stop) {
+// ---------------------------------------------------------------------------
+// MFMA versions.  The slab tile (64 x 64, Ys[j][i] in LDS, i contiguous) feeds
+//   Z_q = Y_q A^(2):   v_mfma A-operand Y[i][j] (lane: i = 16w + l%16, k = j)
+//   W_q = Y_q^T A^(1): v_mfma A-operand Y^T[j][i] (lane: j = 16w + l%16, k = i)
+// The factor operands are loop constants held in registers.  The summation
+// index of W_q is permuted inside each 16-wide k block so that every lane
+// reads four (FP32) or eight (BF16) consecutive i with one LDS vector load;
+// the factor operand uses the same permutation.  Result layout of both
+// 16x16 instructions: D[4 (l/16) + v][l%16].
+// ---------------------------------------------------------------------------
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+constexpr int kQMax = 32;  // slabs per block of the MFMA kernels (t and c_q staged in LDS)
+
+__device__ __forceinline__ float fac(const PassArgs& a, int mode, int Im, int i, int r) {
+  return (i < Im && r < a.R) ? (float)a.A[a.off[mode] + i + (long long)r * Im] : 0.0f;
+}
+
+__device__ __forceinline__ float cq_of(const PassArgs& a, long long q, int r) {
+  if (r >= a.R) return 0.0f;
+  double c = 1.0;
+  long long qq = q;
+  for (int k = 2; k < a.N; ++k) {
+    const int Ik = a.It[k - 2];
+    const int ik = (int)(qq % Ik);
+    qq /= Ik;
+    c *= a.A[a.off[k] + ik + (long long)r * Ik];
+  }
+  return (float)c;
+}
+
+// Epilogue shared by the MFMA kernels: t from LDS, partial M_1 and M_2.
+template <int NB>
+__device__ __forceinline__ void pass_epilogue(const PassArgs& a, float (*tq_s)[64], long long q0,
+                                              long long q1, int tile, int ti, int tj, int i0, int j0,
+                                              const v4f* m0acc, const v4f* m1acc) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6, g = lane >> 4, c16 = lane & 15;
+  const int R = a.R, I0 = a.I0, I1 = a.I1;
+  __syncthreads();
+  float* tp = static_cast<float*>(a.tpart) + (long long)tile * R * a.Q;
+  const int nq = (int)(q1 - q0);
+  for (int e = t; e < nq * R; e += 256) {
+    const int ql = e % nq, r = e / nq;
+    tp[(long long)r * a.Q + q0 + ql] = tq_s[ql][r];
+  }
+  float* m0p = static_cast<float*>(a.m0part) + ((long long)blockIdx.y * a.tiles_j + tj) * R * I0;
+  float* m1p = static_cast<float*>(a.m1part) + ((long long)blockIdx.y * a.tiles_i + ti) * R * I1;
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    const int r = 16 * nb + c16;
+    if (r < R) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int ii = i0 + 16 * w + 4 * g + v, jj = j0 + 16 * w + 4 * g + v;
+        if (ii < I0) m0p[(long long)r * I0 + ii] = m0acc[nb][v];
+        if (jj < I1) m1p[(long long)r * I1 + jj] = m1acc[nb][v];
+      }
+    }
+  }
+}
+
+template <int NB, bool RESID>
+__global__ __launch_bounds__(256) void k_pass_f32(PassArgs a, const int* stop) {
   if (stopped(stop)) return;
-  for (long long x = blockIdx.x * (long long)blockDim.x + threadIdx.x; x < len;
-       x += (long long)gridDim.x * blockDim.x) {
-    double s = 0.0;
-    for (int k = 0; k < nslots; ++k) s += (double)part[(long long)k * len + x];
-    out[x] = s;
+  constexpr int LDY = 68;
+  __shared__ __attribute__((aligned(16))) float Ys[64][LDY];  // Ys[j][i]
+  __shared__ float cq_all[kQMax][64];
+  __shared__ float tq_s[kQMax][64];
+  __shared__ float A0s[RESID ? 64 : 1][65];
+  __shared__ float A1s[RESID ? 64 : 1][65];
+  __shared__ double red[16];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6, g = lane >> 4, c16 = lane & 15;
+  const int I0 = a.I0, I1 = a.I1;
+  const int tile = blockIdx.x, ti = tile % a.tiles_i, tj = tile / a.tiles_i;
+  const int i0 = ti * 64, j0 = tj * 64;
+  const long long q0 = (long long)blockIdx.y * a.q_per;
+  const long long q1 = (q0 + a.q_per < a.Q) ? q0 + a.q_per : a.Q;
+  const float* Y = static_cast<const float*>(a.Y);
+  const bool vec_ok = (I0 % 4) == 0;
+
+  float b1[16][NB], b0[16][NB], a0t[NB][4];
+#pragma unroll
+  for (int ks = 0; ks < 16; ++ks)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      b1[ks][nb] = fac(a, 1, I1, j0 + 4 * ks + g, 16 * nb + c16);
+      b0[ks][nb] = fac(a, 0, I0, i0 + 16 * (ks >> 2) + 4 * g + (ks & 3), 16 * nb + c16);
+    }
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) a0t[nb][v] = fac(a, 0, I0, i0 + 16 * w + 4 * g + v, 16 * nb + c16);
+  if (RESID) {
+    for (int e = t; e < 64 * 64; e += 256) {
+      const int ii = e & 63, r = e >> 6;
+      A0s[ii][r] = fac(a, 0, I0, i0 + ii, r);
+      A1s[ii][r] = fac(a, 1, I1, j0 + ii, r);
+    }
+  }
+  for (int e = t; e < kQMax * 64; e += 256) {
+    const int ql = e >> 6, r = e & 63;
+    tq_s[ql][r] = 0.0f;
+    cq_all[ql][r] = (q0 + ql < q1) ? cq_of(a, q0 + ql, r) : 0.0f;
+  }
+
+  v4f m0acc[NB], m1acc[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) { m0acc[nb] = v4f{0, 0, 0, 0}; m1acc[nb] = v4f{0, 0, 0, 0}; }
+  double e2 = 0.0;
+
+  v4f pf[4];
+  auto load = [&](long long q) {
+    const long long base = (long long)I0 * I1 * q;
+#pragma unroll
+    for (int s2 = 0; s2 < 4; ++s2) {
+      const int e = t + 256 * s2, jj = e >> 4, ii = (e & 15) * 4;
+      const int gi = i0 + ii, gj = j0 + jj;
+      v4f v = v4f{0, 0, 0, 0};
+      if (gj < I1) {
+        const float* src = Y + base + (long long)gj * I0 + gi;
+        if (vec_ok && gi + 3 < I0) {
+          v = *reinterpret_cast<const v4f*>(src);
+        } else {
+#pragma unroll
+          for (int k = 0; k < 4; ++k) v[k] = (gi + k < I0) ? src[k] : 0.0f;
+        }
+      }
+      pf[s2] = v;
+    }
+  };
+  if (q0 < q1) load(q0);
+  for (long long q = q0; q < q1; ++q) {
+    __syncthreads();
+#pragma unroll
+    for (int s2 = 0; s2 < 4; ++s2) {
+      const int e = t + 256 * s2, jj = e >> 4, ii = (e & 15) * 4;
+      *reinterpret_cast<v4f*>(&Ys[jj][ii]) = pf[s2];
+    }
+    const float* cq_s = cq_all[q - q0];
+    if (q + 1 < q1) load(q + 1);
+    __syncthreads();
+    if (RESID) {
+      constexpr int KS = NB * 4;  // R padded to 16, in steps of 4
+#pragma unroll
+      for (int jb = 0; jb < 4; ++jb) {
+        v4f acc = v4f{0, 0, 0, 0};
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+          const float av = A0s[16 * w + c16][4 * ks + g];
+          const float bv = cq_s[4 * ks + g] * A1s[16 * jb + c16][4 * ks + g];
+          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int ii = 16 * w + 4 * g + v, jj = 16 * jb + c16;
+          const float ev = Ys[jj][ii] - acc[v];
+          e2 += (double)ev * (double)ev;
+          Ys[jj][ii] = ev;
+        }
+      }
+      __syncthreads();
+    }
+    v4f zacc[NB], wacc[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) { zacc[nb] = v4f{0, 0, 0, 0}; wacc[nb] = v4f{0, 0, 0, 0}; }
+#pragma unroll
+    for (int ks = 0; ks < 16; ++ks) {
+      const float av = Ys[4 * ks + g][16 * w + c16];
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+        zacc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, b1[ks][nb], zacc[nb], 0, 0, 0);
+    }
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) {
+      const v4f y4 = *reinterpret_cast<const v4f*>(&Ys[16 * w + c16][16 * kb + 4 * g]);
+#pragma unroll
+      for (int s2 = 0; s2 < 4; ++s2)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+          wacc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(y4[s2], b0[4 * kb + s2][nb], wacc[nb], 0, 0, 0);
+    }
+    const int ql = (int)(q - q0);
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const float c = cq_s[16 * nb + c16];
+      m0acc[nb] += c * zacc[nb];
+      m1acc[nb] += c * wacc[nb];
+      float tv = a0t[nb][0] * zacc[nb][0] + a0t[nb][1] * zacc[nb][1] + a0t[nb][2] * zacc[nb][2] +
+                 a0t[nb][3] * zacc[nb][3];
+      tv += __shfl_xor(tv, 16, 64);
+      tv += __shfl_xor(tv, 32, 64);
+      if (g == 0) atomicAdd(&tq_s[ql][16 * nb + c16], tv);
+    }
+  }
+  pass_epilogue<NB>(a, tq_s, q0, q1, tile, ti, tj, i0, j0, m0acc, m1acc);
+  if (RESID) {
+    const double s2 = block_sum(e2, red);
+    if (t == 0) a.e2part[(long long)blockIdx.y * gridDim.x + blockIdx.x] = s2;
+  }
+}
+
+__device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
+  hi = (__bf16)x;
+  lo = (__bf16)(x - (float)hi);
+}
+
+// BF16 tensor: 16x16x32 BF16 MFMA with FP32 accumulation.  Factors enter as
+// hi + lo BF16 pairs (two instructions), so only the tensor's own rounding
+// remains at the BF16 level.
+template <int NB>
+__global__ __launch_bounds__(256) void k_pass_bf16(PassArgs a, const int* stop) {
+  if (stopped(stop)) return;
+  constexpr int LDY = 72;
+  __shared__ __attribute__((aligned(16))) __bf16 Ys[64][LDY];  // Ys[j][i]
+  __shared__ float cq_all[kQMax][64];
+  __shared__ float tq_s[kQMax][64];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6, g = lane >> 4, c16 = lane & 15;
+  const int I0 = a.I0, I1 = a.I1;
+  const int tile = blockIdx.x, ti = tile % a.tiles_i, tj = tile / a.tiles_i;
+  const int i0 = ti * 64, j0 = tj * 64;
+  const long long q0 = (long long)blockIdx.y * a.q_per;
+  const long long q1 = (q0 + a.q_per < a.Q) ? q0 + a.q_per : a.Q;
+  const __bf16* Y = static_cast<const __bf16*>(a.Y);
+  const bool vec_ok = (I0 % 4) == 0;
+
+  v8bf b1h[2][NB], b1l[2][NB], b0h[2][NB], b0l[2][NB];
+  float a0t[NB][4];
+#pragma unroll
+  for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int tt = 0; tt < 8; ++tt) {
+        __bf16 h, l;
+        split_bf16(fac(a, 1, I1, j0 + 32 * ks + 8 * g + tt, 16 * nb + c16), h, l);
+        b1h[ks][nb][tt] = h;
+        b1l[ks][nb][tt] = l;
+        split_bf16(fac(a, 0, I0, i0 + 32 * ks + 8 * g + tt, 16 * nb + c16), h, l);
+        b0h[ks][nb][tt] = h;
+        b0l[ks][nb][tt] = l;
+      }
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) a0t[nb][v] = fac(a, 0, I0, i0 + 16 * w + 4 * g + v, 16 * nb + c16);
+  for (int e = t; e < kQMax * 64; e += 256) {
+    const int ql = e >> 6, r = e & 63;
+    tq_s[ql][r] = 0.0f;
+    cq_all[ql][r] = (q0 + ql < q1) ? cq_of(a, q0 + ql, r) : 0.0f;
+  }
+
+  v4f m0acc[NB], m1acc[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) { m0acc[nb] = v4f{0, 0, 0, 0}; m1acc[nb] = v4f{0, 0, 0, 0}; }
+
+  typedef unsigned short us4 __attribute__((ext_vector_type(4)));
+  us4 pf[4];
+  auto load = [&](long long q) {
+    const long long base = (long long)I0 * I1 * q;
+    const unsigned short* Yu = reinterpret_cast<const unsigned short*>(Y);
+#pragma unroll
+    for (int s2 = 0; s2 < 4; ++s2) {
+      const int e = t + 256 * s2, jj = e >> 4, ii = (e & 15) * 4;
+      const int gi = i0 + ii, gj = j0 + jj;
+      us4 v = us4{0, 0, 0, 0};
+      if (gj < I1) {
+        const unsigned short* src = Yu + base + (long long)gj * I0 + gi;
+        if (vec_ok && gi + 3 < I0) {
+          v = *reinterpret_cast<const us4*>(src);
+        } else {
+#pragma unroll
+          for (int k = 0; k < 4; ++k) v[k] = (gi + k < I0) ? src[k] : (unsigned short)0;
+        }
+      }
+      pf[s2] = v;
+    }
+  };
+  if (q0 < q1) load(q0);
+  for (long long q = q0; q < q1; ++q) {
+    __syncthreads();
+#pragma unroll
+    for (int s2 = 0; s2 < 4; ++s2) {
+      const int e = t + 256 * s2, jj = e >> 4, ii = (e & 15) * 4;
+      *reinterpret_cast<us4*>(&Ys[jj][ii]) = pf[s2];
+    }
+    const float* cq_s = cq_all[q - q0];
+    if (q + 1 < q1) load(q + 1);
+    __syncthreads();
+    v4f zacc[NB], wacc[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) { zacc[nb] = v4f{0, 0, 0, 0}; wacc[nb] = v4f{0, 0, 0, 0}; }
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+      v8bf av;
+#pragma unroll
+      for (int tt = 0; tt < 8; ++tt) av[tt] = Ys[32 * ks + 8 * g + tt][16 * w + c16];
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        zacc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b1h[ks][nb], zacc[nb], 0, 0, 0);
+        zacc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b1l[ks][nb], zacc[nb], 0, 0, 0);
+      }
+      const v8bf yv = *reinterpret_cast<const v8bf*>(&Ys[16 * w + c16][32 * ks + 8 * g]);
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        wacc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(yv, b0h[ks][nb], wacc[nb], 0, 0, 0);
+        wacc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(yv, b0l[ks][nb], wacc[nb], 0, 0, 0);
+      }
+    }
+    const int ql = (int)(q - q0);
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const float c = cq_s[16 * nb + c16];
+      m0acc[nb] += c * zacc[nb];
+      m1acc[nb] += c * wacc[nb];
+      float tv = a0t[nb][0] * zacc[nb][0] + a0t[nb][1] * zacc[nb][1] + a0t[nb][2] * zacc[nb][2] +
+                 a0t[nb][3] * zacc[nb][3];
+      tv += __shfl_xor(tv, 16, 64);
+      tv += __shfl_xor(tv, 32, 64);
+      if (g == 0) atomicAdd(&tq_s[ql][16 * nb + c16], tv);
+    }
+  }
+  pass_epilogue<NB>(a, tq_s, q0, q1, tile, ti, tj, i0, j0, m0acc, m1acc);
+}
+
+// out[x] = sum_s part[s * len + x], accumulated in FP64.  A block covers 64
+// consecutive x; its 16 waves split the slots.
+template <typename TC>
+__global__ __launch_bounds__(1024) void k_reduce_slots(const TC* part, int nslots, long long len,
+                                                       double* out, const int* stop) {
+  if (stopped(stop)) return;
+  __shared__ double red[16][65];
+  const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const long long x = blockIdx.x * 64LL + lane;
+  double s = 0.0;
+  if (x < len) {
+    int k = g;
+    for (; k + 48 < nslots; k += 64) {
+      const double a0 = (double)part[(long long)k * len + x];
+      const double a1 = (double)part[(long long)(k + 16) * len + x];
+      const double a2 = (double)part[(long long)(k + 32) * len + x];
+      const double a3 = (double)part[(long long)(k + 48) * len + x];
+      s += (a0 + a1) + (a2 + a3);
+    }
+    for (; k < nslots; k += 16) s += (double)part[(long long)k * len + x];
+  }
+  red[g][lane] = s;
+  __syncthreads();
+  if (g == 0 && x < len) {
+    double v = 0.0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v += red[i][lane];
+    out[x] = v;
   }
 }
 
@@ -217,8 +560,14 @@ template <typename TY>
 __global__ void k_norm2(const TY* y, long long n, double* part) {
   __shared__ double red[16];
   double s = 0.0;
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
-       i += (long long)gridDim.x * blockDim.x) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  for (; i + 3 * stride < n; i += 4 * stride) {
+    const double a0 = to_f64(y[i]), a1 = to_f64(y[i + stride]);
+    const double a2 = to_f64(y[i + 2 * stride]), a3 = to_f64(y[i + 3 * stride]);
+    s += (a0 * a0 + a1 * a1) + (a2 * a2 + a3 * a3);
+  }
+  for (; i < n; i += stride) {
     const double v = to_f64(y[i]);
     s += v * v;
   }
@@ -240,13 +589,17 @@ PassPlan plan_pass(const Shape& s, YType yt) {
   if (want < 1) want = 1;
   p.q_per = (int)((p.Q + want - 1) / want);
   p.n_qc = (int)((p.Q + p.q_per - 1) / p.q_per);
+  p.mfma = (yt != YType::F64) ? 1 : 0;
+  if (p.mfma && p.q_per > kQMax) {
+    p.q_per = kQMax;
+    p.n_qc = (int)((p.Q + p.q_per - 1) / p.q_per);
+  }
   p.tc_bytes = (yt == YType::F64) ? 8 : 4;
   p.m0_elems = (size_t)p.n_qc * p.tiles_j * s.R * s.I[0];
   p.m1_elems = (size_t)p.n_qc * p.tiles_i * s.R * s.I[1];
   p.t_elems = (size_t)tiles * s.R * p.Q;
   p.e2_elems = (size_t)tiles * p.n_qc;
   p.tbuf_elems = (s.N >= 4) ? (size_t)p.Q * s.R : 0;
-  p.mfma = 0;
   return p;
 }
 
@@ -271,36 +624,47 @@ hipError_t launch_tensor_pass(const Shape& s, YType yt, const void* Y, const dou
   a.tpart = b.tpart;
   a.e2part = b.e2part;
   dim3 grid(p.tiles_i * p.tiles_j, p.n_qc);
+  const int NB = (s.R + 15) / 16;
   if (yt == YType::F64) {
     if (resid) k_pass_fma<double, double, true><<<grid, 256, 0, st>>>(a, stop);
     else k_pass_fma<double, double, false><<<grid, 256, 0, st>>>(a, stop);
   } else if (yt == YType::F32) {
-    if (resid) k_pass_fma<float, float, true><<<grid, 256, 0, st>>>(a, stop);
-    else k_pass_fma<float, float, false><<<grid, 256, 0, st>>>(a, stop);
+#define F32_CASE(nb)                                                        \
+  case nb:                                                                  \
+    if (resid) k_pass_f32<nb, true><<<grid, 256, 0, st>>>(a, stop);         \
+    else k_pass_f32<nb, false><<<grid, 256, 0, st>>>(a, stop);              \
+    break;
+    switch (NB) { F32_CASE(1) F32_CASE(2) F32_CASE(3) F32_CASE(4) default: return hipErrorInvalidValue; }
+#undef F32_CASE
   } else {
-    if (resid) k_pass_fma<__bf16, float, true><<<grid, 256, 0, st>>>(a, stop);
-    else k_pass_fma<__bf16, float, false><<<grid, 256, 0, st>>>(a, stop);
+    if (resid) return hipErrorInvalidValue;  // the residual pass reads the FP32 tensor
+    switch (NB) {
+      case 1: k_pass_bf16<1><<<grid, 256, 0, st>>>(a, stop); break;
+      case 2: k_pass_bf16<2><<<grid, 256, 0, st>>>(a, stop); break;
+      case 3: k_pass_bf16<3><<<grid, 256, 0, st>>>(a, stop); break;
+      case 4: k_pass_bf16<4><<<grid, 256, 0, st>>>(a, stop); break;
+      default: return hipErrorInvalidValue;
+    }
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int red_grid = 256;
   const int nslot0 = p.n_qc * p.tiles_j, nslot1 = p.n_qc * p.tiles_i;
   const int ntile = p.tiles_i * p.tiles_j;
   const long long len0 = (long long)s.R * s.I[0], len1 = (long long)s.R * s.I[1];
   const long long lent = (long long)s.R * p.Q;
   double* tdst = (s.N == 3) ? M + (long long)s.off[2] * s.R : b.tbuf;
   if (p.tc_bytes == 8) {
-    k_reduce_slots<double><<<red_grid, 256, 0, st>>>((const double*)b.m0part, nslot0, len0,
+    k_reduce_slots<double><<<(unsigned)((len0 + 63) / 64), 1024, 0, st>>>((const double*)b.m0part, nslot0, len0,
                                                        M + (long long)s.off[0] * s.R, stop);
-    k_reduce_slots<double><<<red_grid, 256, 0, st>>>((const double*)b.m1part, nslot1, len1,
+    k_reduce_slots<double><<<(unsigned)((len1 + 63) / 64), 1024, 0, st>>>((const double*)b.m1part, nslot1, len1,
                                                        M + (long long)s.off[1] * s.R, stop);
-    k_reduce_slots<double><<<red_grid, 256, 0, st>>>((const double*)b.tpart, ntile, lent, tdst, stop);
+    k_reduce_slots<double><<<(unsigned)((lent + 63) / 64), 1024, 0, st>>>((const double*)b.tpart, ntile, lent, tdst, stop);
   } else {
-    k_reduce_slots<float><<<red_grid, 256, 0, st>>>((const float*)b.m0part, nslot0, len0,
+    k_reduce_slots<float><<<(unsigned)((len0 + 63) / 64), 1024, 0, st>>>((const float*)b.m0part, nslot0, len0,
                                                       M + (long long)s.off[0] * s.R, stop);
-    k_reduce_slots<float><<<red_grid, 256, 0, st>>>((const float*)b.m1part, nslot1, len1,
+    k_reduce_slots<float><<<(unsigned)((len1 + 63) / 64), 1024, 0, st>>>((const float*)b.m1part, nslot1, len1,
                                                       M + (long long)s.off[1] * s.R, stop);
-    k_reduce_slots<float><<<red_grid, 256, 0, st>>>((const float*)b.tpart, ntile, lent, tdst, stop);
+    k_reduce_slots<float><<<(unsigned)((lent + 63) / 64), 1024, 0, st>>>((const float*)b.tpart, ntile, lent, tdst, stop);
   }
   if (s.N >= 4) k_modes_from_t<<<256, 256, 0, st>>>(a, b.tbuf, M, stop);
   if (resid && e2out) k_sum<<<1, 256, 0, st>>>(b.e2part, (int)p.e2_elems, e2out, stop);
