@@ -103,6 +103,9 @@ typedef struct dgn_opts {
   const void* y_bf16;
   int32_t poll_every;   /* cp_fit checks its stop flag every this many trials; default 8 */
   int32_t timing;       /* nonzero: cp_fit records per-phase HIP events (dgn_last_phase_times) */
+  int32_t graph;        /* cp_fit_batched: nonzero (default) replays poll_every trials from one
+                           captured hipGraph; zero launches them one by one */
+  int32_t reserved;
 } dgn_opts;
 
 /* Result of one trial step (dgn_step). */
@@ -174,6 +177,29 @@ dgn_status dgn_step(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, const void* co
 dgn_status cp_fit(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, void* const* A, double mu0,
                   double tol, int32_t max_iters, const dgn_opts* opts, dgn_fit_info* info,
                   void* stream);
+
+/* One small fit of a batch: a 3-way tensor (F32 or F64, every I_n <= 64),
+ * rank 1 <= R <= 8, the initial damping (> 0 used as given, <= 0 the tau
+ * rule) and three device pointers to FP64 column-major I_n x R factors
+ * (in: start, out: result).  The batch owns none of these buffers. */
+typedef struct dgn_batch_fit {
+  dgn_tensor Y;
+  int32_t R;
+  double mu0;
+  void* A[3];
+} dgn_batch_fit;
+
+/* B independent fits, each run exactly as cp_fit runs it (Algorithm 1 with
+ * the damping of Section 4.5, same stop rules, tol and max_iters shared),
+ * all advanced together: every trial of every unfinished fit is one block of
+ * one kernel launch; the launches are replayed from a captured hipGraph.
+ * Fits stop independently.  infos (host, B entries, may be NULL) receives
+ * each fit's result.  The tensor pass reads FP32 data and accumulates in
+ * FP64.  Returns DGN_EINVAL if a fit is outside the supported shapes (order
+ * 3, I_n <= 64, R <= 8).  Synchronises the stream before returning. */
+dgn_status cp_fit_batched(dgn_ctx* ctx, int32_t B, const dgn_batch_fit* fits, double tol,
+                          int32_t max_iters, const dgn_opts* opts, dgn_fit_info* infos,
+                          void* stream);
 
 /* Per-phase GPU time of the last cp_fit call made with opts->timing != 0,
  * from HIP events recorded on that call's stream around each phase of every

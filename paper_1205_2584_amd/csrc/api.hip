@@ -15,6 +15,7 @@ struct dgn_ctx {
   size_t ws_size;
   std::string err;
   std::vector<hipEvent_t> events;   // timing pool, (DGN_NUM_PHASES + 1) per trial
+  hipStream_t own = nullptr;        // private stream for graph capture (default priority)
   double phase_ms[DGN_NUM_PHASES] = {0, 0, 0, 0, 0, 0};
   int phase_trials = 0;
 };
@@ -246,6 +247,8 @@ void dgn_opts_default(dgn_opts* o) {
   o->resid_switch = 1e-4;
   o->y_bf16 = nullptr;
   o->poll_every = 8;
+  o->timing = 0;
+  o->graph = 1;
 }
 
 dgn_status dgn_create(dgn_ctx** out, int32_t device, size_t ws_budget_bytes) {
@@ -269,6 +272,7 @@ dgn_status dgn_destroy(dgn_ctx* ctx) {
   if (!ctx) return DGN_EINVAL;
   hipSetDevice(ctx->device);
   for (hipEvent_t e : ctx->events) hipEventDestroy(e);
+  if (ctx->own) hipStreamDestroy(ctx->own);
   hipFree(ctx->ws);
   delete ctx;
   return DGN_OK;
@@ -474,6 +478,126 @@ dgn_status cp_fit(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, void* const* A, 
   }
   if (hs.singular) return set_err(ctx, DGN_ESINGULAR, "non-positive pivot in (Gamma + mu I) or the NR^2 system");
   if (hs.reason == DGN_STOP_NONFINITE) return set_err(ctx, DGN_ENONFINITE, "non-finite error or step");
+  return DGN_OK;
+}
+
+
+dgn_status cp_fit_batched(dgn_ctx* ctx, int32_t B, const dgn_batch_fit* fits, double tol,
+                          int32_t max_iters, const dgn_opts* opts, dgn_fit_info* infos,
+                          void* stream) {
+  if (!ctx) return DGN_EINVAL;
+  if (B < 0 || (B > 0 && !fits)) return set_err(ctx, DGN_EINVAL, "bad batch size or NULL fits");
+  if (max_iters < 0 || !(tol >= 0.0)) return set_err(ctx, DGN_EINVAL, "need max_iters >= 0 and tol >= 0");
+  if (B == 0) return DGN_OK;
+  dgn_opts o;
+  dgn_opts_default(&o);
+  if (opts) o = *opts;
+  if (o.poll_every < 1) o.poll_every = 1;
+  // validate and size the workspace
+  size_t need = 0;
+  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+  std::vector<BFit> hf(B);
+  for (int b = 0; b < B; ++b) {
+    const dgn_batch_fit& f = fits[b];
+    if (!f.Y.data || (f.Y.dtype != DGN_F32 && f.Y.dtype != DGN_F64) ||
+        !batched_supported(f.Y.order, f.Y.dims, f.R) || !f.A[0] || !f.A[1] || !f.A[2] || !isfinite(f.mu0))
+      return set_err(ctx, DGN_EINVAL, "batch fit " + std::to_string(b) +
+                                          ": need order 3, F32/F64 data, I_n <= 64, 1 <= R <= 8, non-NULL factors");
+    int I[3] = {(int)f.Y.dims[0], (int)f.Y.dims[1], (int)f.Y.dims[2]};
+    need += al(batched_fit_doubles(I, f.R) * sizeof(double)) + al(sizeof(FitState));
+  }
+  need += al(sizeof(BFit) * (size_t)B) + al(sizeof(int) * 64);
+  if (need > ctx->ws_size)
+    return set_err(ctx, DGN_ENOMEM, "workspace budget too small for the batch: need " + std::to_string(need));
+  hipStream_t cs = (hipStream_t)stream;
+  HIPCHK(hipSetDevice(ctx->device), "hipSetDevice");
+  if (!ctx->own) HIPCHK(hipStreamCreateWithFlags(&ctx->own, hipStreamNonBlocking), "hipStreamCreate");
+  hipStream_t st = ctx->own;
+  char* base = ctx->ws;
+  size_t used = 0;
+  auto take = [&](size_t bytes) { char* p = base + used; used += al(bytes); return p; };
+  BFit* dfits = reinterpret_cast<BFit*>(take(sizeof(BFit) * (size_t)B));
+  int* nstopped = reinterpret_cast<int*>(take(sizeof(int) * 64));
+  std::vector<FitState*> states(B);
+  for (int b = 0; b < B; ++b) {
+    const dgn_batch_fit& f = fits[b];
+    BFit& h = hf[b];
+    h.Y = f.Y.data;
+    h.dtype = (f.Y.dtype == DGN_F64) ? 0 : 1;
+    for (int n = 0; n < 3; ++n) h.I[n] = (int)f.Y.dims[n];
+    h.R = f.R;
+    h.mu0 = f.mu0;
+    const size_t TR = (size_t)(h.I[0] + h.I[1] + h.I[2]) * f.R;
+    double* w = reinterpret_cast<double*>(take(batched_fit_doubles(h.I, f.R) * sizeof(double)));
+    h.A = w;
+    h.Ac = w + TR;
+    h.M = w + 2 * TR;
+    h.Mc = w + 3 * TR;
+    h.G = w + 4 * TR;
+    h.P = w + 5 * TR;
+    h.C = w + 6 * TR;
+    h.Cc = h.C + 3 * 64;
+    for (int n = 0; n < 3; ++n) h.Ain[n] = static_cast<double*>(f.A[n]);
+    h.st = reinterpret_cast<FitState*>(take(sizeof(FitState)));
+    states[b] = h.st;
+  }
+  BatchCfg cfg{tol, o.tau, o.resid_switch, max_iters, o.normalize, nstopped};
+  // order the private stream after the caller's work
+  hipEvent_t ev_in, ev_out;
+  HIPCHK(hipEventCreateWithFlags(&ev_in, hipEventDisableTiming), "event");
+  HIPCHK(hipEventCreateWithFlags(&ev_out, hipEventDisableTiming), "event");
+  HIPCHK(hipEventRecord(ev_in, cs), "event");
+  HIPCHK(hipStreamWaitEvent(st, ev_in, 0), "event");
+  HIPCHK(hipMemcpyAsync(dfits, hf.data(), sizeof(BFit) * (size_t)B, hipMemcpyHostToDevice, st), "copy fits");
+  HIPCHK(hipMemsetAsync(nstopped, 0, sizeof(int), st), "memset");
+  HIPCHK(launch_batched_init(dfits, B, cfg, st), "batched init");
+  const int per = o.poll_every < max_iters ? o.poll_every : (max_iters > 0 ? max_iters : 1);
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  if (o.graph && max_iters > 0) {
+    HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "capture");
+    for (int k = 0; k < per; ++k) launch_batched_trial(dfits, B, cfg, st);
+    HIPCHK(hipStreamEndCapture(st, &graph), "capture end");
+    HIPCHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "graph instantiate");
+  }
+  int done = 0, host_stopped = 0;
+  while (done < max_iters) {
+    if (exec) {
+      HIPCHK(hipGraphLaunch(exec, st), "graph launch");
+    } else {
+      for (int k = 0; k < per; ++k) HIPCHK(launch_batched_trial(dfits, B, cfg, st), "batched trial");
+    }
+    done += per;
+    HIPCHK(hipMemcpyAsync(&host_stopped, nstopped, sizeof(int), hipMemcpyDeviceToHost, st), "poll");
+    HIPCHK(hipStreamSynchronize(st), "sync");
+    if (host_stopped >= B) break;
+  }
+  if (exec) hipGraphExecDestroy(exec);
+  if (graph) hipGraphDestroy(graph);
+  HIPCHK(launch_batched_final(dfits, B, st), "batched final");
+  std::vector<FitState> hs(B);
+  for (int b = 0; b < B; ++b)
+    HIPCHK(hipMemcpyAsync(&hs[b], states[b], sizeof(FitState), hipMemcpyDeviceToHost, st), "state");
+  HIPCHK(hipEventRecord(ev_out, st), "event");
+  HIPCHK(hipStreamWaitEvent(cs, ev_out, 0), "event");
+  HIPCHK(hipStreamSynchronize(st), "sync");
+  hipEventDestroy(ev_in);
+  hipEventDestroy(ev_out);
+  int nonfinite = 0;
+  for (int b = 0; b < B; ++b) {
+    if (infos) {
+      infos[b].iters = hs[b].iters;
+      infos[b].accepted = hs[b].accepted;
+      infos[b].reason = hs[b].reason;
+      infos[b].resid_iters = hs[b].resid_iters;
+      infos[b].eps = hs[b].eps;
+      infos[b].err2 = hs[b].err2;
+      infos[b].mu = hs[b].mu;
+      infos[b].mu0 = hs[b].mu0;
+    }
+    nonfinite += hs[b].reason == DGN_STOP_NONFINITE;
+  }
+  if (nonfinite) return set_err(ctx, DGN_ENONFINITE, std::to_string(nonfinite) + " fit(s) stopped on a non-finite or singular step");
   return DGN_OK;
 }
 

@@ -1,0 +1,697 @@
+// Many small independent fits in one launch per trial.
+//
+// One 256-thread block owns one 3-way fit (R <= 8, every I_n <= 64) and runs
+// a whole trial of Algorithm 1 for it: Gamma / damped inverses, the
+// Jacobian-free products of Lemma 4.4, the NR^2 system in its SPD form
+// S = I + W^T K W (block 1 eliminated first, the trailing (N-1)R^2 system
+// factored in LDS with the right-hand side folded in as an extra row), the
+// factor update, the tensor pass at the candidate (all-mode MTTKRP, FP32 for
+// FP32 tensors, FP64 for FP64 ones; residual form after the switch), and the
+// damping control of Section 4.5.  The same formulas as the large-problem
+// kernels (small.hip, chol.hip, tensor_pass.hip, fit.hip); the trial kernel
+// takes no per-launch arguments, so a run of trials is captured once in a
+// hipGraph and replayed.
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace dgn {
+
+namespace {
+
+constexpr int BR = 8;          // max rank
+constexpr int BR2 = BR * BR;   // 64
+constexpr int BI = 64;         // max mode size
+constexpr int BNT = 2 * BR2;   // max trailing system size (128)
+constexpr int kPacked = (BNT + 1) * (BNT + 2) / 2;  // packed lower rows 0..BNT
+
+__device__ __forceinline__ int pidx(int i, int j) { return i * (i + 1) / 2 + j; }
+
+// Shared-memory layout (doubles).
+struct Smem {
+  double Cs[3][BR2], Gm[3][BR2], Gt[3][BR2], Xs[3][BR2], Ls[3][BR2], Qs[3][BR2];
+  double w[3 * BR2], z[3 * BR2], y[3 * BR2], v[3 * BR2];
+  double red[16];
+  double scal[8];
+  int flags[8];
+  union {
+    struct {
+      double Sp[kPacked];
+      double Bm[BNT][BR2];
+      double Tb[BR * BR * BR];
+      double lk[BNT + 2];
+    } sys;
+    struct {
+      double Ys[BI][BI + 1];  // Ys[j][i]
+      double A0s[BI][BR + 1], A1s[BI][BR + 1];
+      double cq[BR];
+    } pass;
+    struct {
+      double V[3][BR2], T1[3][BR2];
+    } rr;
+  } u;
+};
+
+__device__ __forceinline__ int mode_of_row(const BFit& f, int row, int* i) {
+  if (row < f.I[0]) { *i = row; return 0; }
+  if (row < f.I[0] + f.I[1]) { *i = row - f.I[0]; return 1; }
+  *i = row - f.I[0] - f.I[1];
+  return 2;
+}
+
+__device__ __forceinline__ long long aoff(const BFit& f, int n) {
+  long long o = 0;
+  for (int k = 0; k < n; ++k) o += (long long)f.I[k] * f.R;
+  return o;
+}
+
+// ---- tensor pass (one block, all modes) --------------------------------------
+// Mout = MTTKRP of Y (or of E = Y - Y_hat when resid) at factors Ain; returns
+// sum(E^2) (resid) or <Y, Y_hat> = sum(A_1 * M_1) (plain) to every thread.
+template <typename TY>
+__device__ double bpass(const BFit& f, const double* Ain, double* Mout, int resid, Smem& S) {
+  const int t = threadIdx.x, lane = t & 63, rg = t >> 6;
+  const int I0 = f.I[0], I1 = f.I[1], I2 = f.I[2], R = f.R;
+  const TY* Y = static_cast<const TY*>(f.Y);
+  const double* A0 = Ain;
+  const double* A1 = Ain + (long long)I0 * R;
+  const double* A2 = A1 + (long long)I1 * R;
+  double* M0 = Mout;
+  double* M1 = Mout + (long long)I0 * R;
+  double* M2 = M1 + (long long)I1 * R;
+  auto& P = S.u.pass;
+  __syncthreads();
+  for (int e = t; e < BI * BR; e += 256) {
+    const int ii = e & 63, r = e >> 6;
+    P.A0s[ii][r] = (ii < I0 && r < R) ? A0[ii + (long long)r * I0] : 0.0;
+    P.A1s[ii][r] = (ii < I1 && r < R) ? A1[ii + (long long)r * I1] : 0.0;
+  }
+  double m0[2] = {0.0, 0.0}, m1[2] = {0.0, 0.0};
+  double e2 = 0.0;
+  for (int q = 0; q < I2; ++q) {
+    __syncthreads();
+    const long long base = (long long)I0 * I1 * q;
+    for (int e = t; e < BI * BI; e += 256) {
+      const int ii = e & 63, jj = e >> 6;
+      P.Ys[jj][ii] = (ii < I0 && jj < I1) ? to_f64(Y[base + ii + (long long)I0 * jj]) : 0.0;
+    }
+    if (t < BR) P.cq[t] = (t < R) ? A2[q + (long long)t * I2] : 0.0;
+    __syncthreads();
+    if (resid) {
+      for (int e = t; e < BI * BI; e += 256) {
+        const int ii = e & 63, jj = e >> 6;
+        if (ii < I0 && jj < I1) {
+          double yh = 0.0;
+          for (int r = 0; r < R; ++r) yh += P.A0s[ii][r] * (P.A1s[jj][r] * P.cq[r]);
+          const double ev = P.Ys[jj][ii] - yh;
+          e2 += ev * ev;
+          P.Ys[jj][ii] = ev;
+        }
+      }
+      __syncthreads();
+    }
+    double zp[2] = {0.0, 0.0}, wp[2] = {0.0, 0.0};
+    for (int jj = 0; jj < I1; ++jj) {
+      const double yv = P.Ys[jj][lane];
+      zp[0] += yv * P.A1s[jj][rg];
+      zp[1] += yv * P.A1s[jj][rg + 4];
+    }
+    for (int ii = 0; ii < I0; ++ii) {
+      const double yv = P.Ys[lane][ii];
+      wp[0] += yv * P.A0s[ii][rg];
+      wp[1] += yv * P.A0s[ii][rg + 4];
+    }
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int r = rg + 4 * k;
+      const double c = P.cq[r];
+      m0[k] += c * zp[k];
+      m1[k] += c * wp[k];
+      const double tv = wave_sum(P.A0s[lane][r] * zp[k]);
+      if (lane == 0 && r < R) M2[q + (long long)r * I2] = tv;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int r = rg + 4 * k;
+    if (r < R) {
+      if (lane < I0) M0[lane + (long long)r * I0] = m0[k];
+      if (lane < I1) M1[lane + (long long)r * I1] = m1[k];
+    }
+  }
+  __syncthreads();
+  double out;
+  if (resid) {
+    out = block_sum(e2, S.red);
+  } else {
+    double inner = 0.0;
+    for (int e = t; e < I0 * R; e += 256) inner += A0[e] * M0[e];
+    out = block_sum(inner, S.red);
+  }
+  return out;
+}
+
+__device__ double pass_dispatch(const BFit& f, const double* Ain, double* Mout, int resid, Smem& S) {
+  if (f.dtype == 0) return bpass<double>(f, Ain, Mout, resid, S);
+  return bpass<float>(f, Ain, Mout, resid, S);
+}
+
+// sum_{r,s} prod_n C_n[r,s] (= ||Y_hat||^2) from LDS Grams.
+__device__ double yhat2(const BFit& f, const double (*Cs)[BR2], Smem& S) {
+  const int R = f.R;
+  double v = 0.0;
+  for (int e = threadIdx.x; e < BR2; e += 256) {
+    const int r = e & 7, q = e >> 3;
+    if (r < R && q < R) v += Cs[0][r + q * R] * Cs[1][r + q * R] * Cs[2][r + q * R];
+  }
+  return block_sum(v, S.red);
+}
+
+// Grams of the stacked factors Ain into Cdst (LDS) and Cglob.
+__device__ void grams(const BFit& f, const double* Ain, double (*Cdst)[BR2], double* Cglob) {
+  const int t = threadIdx.x, R = f.R;
+  __syncthreads();
+  if (t < 3 * BR2) {
+    const int n = t >> 6, e = t & 63, r = e & 7, q = e >> 3;
+    if (r < R && q < R) {
+      const int In = f.I[n];
+      const double* An = Ain + aoff(f, n);
+      double acc = 0.0;
+      for (int i = 0; i < In; ++i) acc += An[i + (long long)r * In] * An[i + (long long)q * In];
+      Cdst[n][r + q * R] = acc;
+      Cglob[n * BR2 + r + q * R] = acc;
+    }
+  }
+  __syncthreads();
+}
+
+__device__ double gamma_of(const double (*Cs)[BR2], int skip1, int skip2, int e) {
+  double g = 1.0;
+  for (int k = 0; k < 3; ++k)
+    if (k != skip1 && k != skip2) g *= Cs[k][e];
+  return g;
+}
+
+// Serial R x R work of one mode (R <= 8) by one thread: Gamma_n, Cholesky of
+// Gamma_n + mu I, X_n = L^-T, Gt_n = X_n X_n^T, semidefinite-safe L of C_n.
+__device__ void rr_mode(const BFit& f, int n, double mu, Smem& S) {
+  const int R = f.R;
+  double H[BR][BR], Li[BR][BR];
+  for (int r = 0; r < R; ++r)
+    for (int q = 0; q < R; ++q) {
+      const double g = gamma_of(S.Cs, n, -1, r + q * R);
+      S.Gm[n][r + q * R] = g;
+      H[r][q] = g + (r == q ? mu : 0.0);
+    }
+  for (int k = 0; k < R; ++k) {
+    double d = H[k][k];
+    for (int j = 0; j < k; ++j) d -= H[k][j] * H[k][j];
+    if (!(d > 0.0)) {
+      S.flags[0] = 1;
+      d = 1.0;
+    }
+    d = sqrt(d);
+    H[k][k] = d;
+    for (int i = k + 1; i < R; ++i) {
+      double s = H[i][k];
+      for (int j = 0; j < k; ++j) s -= H[i][j] * H[k][j];
+      H[i][k] = s / d;
+    }
+  }
+  for (int j = 0; j < R; ++j) {
+    for (int i = 0; i < R; ++i) Li[i][j] = 0.0;
+    Li[j][j] = 1.0 / H[j][j];
+    for (int i = j + 1; i < R; ++i) {
+      double acc = 0.0;
+      for (int k = j; k < i; ++k) acc += H[i][k] * Li[k][j];
+      Li[i][j] = -acc / H[i][i];
+    }
+  }
+  for (int r = 0; r < R; ++r)
+    for (int q = 0; q < R; ++q) {
+      S.Xs[n][r + q * R] = Li[q][r];
+      double acc = 0.0;
+      for (int k = (r > q ? r : q); k < R; ++k) acc += Li[k][r] * Li[k][q];
+      S.Gt[n][r + q * R] = acc;
+    }
+  // L L^T = C_n
+  for (int r = 0; r < R; ++r)
+    for (int q = 0; q < R; ++q) H[r][q] = S.Cs[n][r + q * R];
+  for (int k = 0; k < R; ++k) {
+    double d = H[k][k];
+    for (int j = 0; j < k; ++j) d -= H[k][j] * H[k][j];
+    const bool zero = !(d > 64.0 * 2.220446049250313e-16 * S.Cs[n][k + k * R]);
+    d = zero ? 0.0 : sqrt(d);
+    H[k][k] = d;
+    for (int i = k + 1; i < R; ++i) {
+      double s = H[i][k];
+      for (int j = 0; j < k; ++j) s -= H[i][j] * H[k][j];
+      H[i][k] = zero ? 0.0 : s / d;
+    }
+  }
+  for (int r = 0; r < R; ++r)
+    for (int q = 0; q < R; ++q) S.Ls[n][r + q * R] = (q <= r) ? H[r][q] : 0.0;
+}
+
+// Per-fit initial state: ||Y||^2, Grams, first tensor pass, err2, mu0.
+__global__ __launch_bounds__(256) void k_binit(BFit* fits, int nfits, BatchCfg cfg) {
+  __shared__ Smem S;
+  const int fi = blockIdx.x;
+  if (fi >= nfits) return;
+  const BFit f = fits[fi];
+  const int t = threadIdx.x, R = f.R;
+  FitState* st = f.st;
+  // stacked copy of the caller's factors
+  for (int n = 0; n < 3; ++n) {
+    const long long o = aoff(f, n);
+    for (int e = t; e < f.I[n] * R; e += 256) f.A[o + e] = f.Ain[n][e];
+  }
+  const long long J = (long long)f.I[0] * f.I[1] * f.I[2];
+  double yy = 0.0;
+  if (f.dtype == 0) {
+    const double* y = static_cast<const double*>(f.Y);
+    for (long long i = t; i < J; i += 256) yy += y[i] * y[i];
+  } else {
+    const float* y = static_cast<const float*>(f.Y);
+    for (long long i = t; i < J; i += 256) yy += (double)y[i] * (double)y[i];
+  }
+  yy = block_sum(yy, S.red);
+  grams(f, f.A, S.Cs, f.C);
+  const int resid = (f.dtype == 0) || cfg.resid_switch < 0.0;
+  const double pv = pass_dispatch(f, f.A, f.M, resid, S);
+  const double err2 = resid ? pv : yy - 2.0 * pv + yhat2(f, S.Cs, S);
+  if (t == 0) {
+    double mu = f.mu0;
+    if (!(mu > 0.0)) {
+      double mx = 0.0;
+      for (int n = 0; n < 3; ++n)
+        for (int r = 0; r < R; ++r) {
+          const double g = gamma_of(S.Cs, n, -1, r + r * R);
+          mx = g > mx ? g : mx;
+        }
+      mu = cfg.tau * mx;
+    }
+    st->mu = mu;
+    st->mu0 = mu;
+    st->ynorm2 = yy;
+    st->ynorm2_pass = yy;
+    st->err2 = err2;
+    st->eps = sqrt(err2 / yy);
+    st->eps_prev = st->eps;
+    st->iters = 0;
+    st->accepted = 0;
+    st->tol = cfg.tol;
+    st->max_iters = cfg.max_iters;
+    st->normalize = cfg.normalize;
+    st->stop = (isfinite(err2) && mu > 0.0 && cfg.max_iters > 0) ? 0 : 1;
+    st->reason = (isfinite(err2) && mu > 0.0) ? 1 : 3;
+    st->singular = 0;
+    st->resid = resid;
+    st->resid_iters = 0;
+    st->pad0 = 0;  // refresh pending
+    if (st->stop) atomicAdd(cfg.nstopped, 1);
+  }
+}
+
+// One trial for every unfinished fit.
+__global__ __launch_bounds__(256) void k_btrial(BFit* fits, int nfits, BatchCfg cfg) {
+  __shared__ Smem S;
+  const int fi = blockIdx.x;
+  if (fi >= nfits) return;
+  const BFit f = fits[fi];
+  FitState* st = f.st;
+  if (st->stop) return;
+  const int t = threadIdx.x, lane = t & 63, R = f.R, R2 = R * R, N = 3;
+  const int T = f.I[0] + f.I[1] + f.I[2];
+  const int nt = 2 * R2;
+  if (t < 8) S.flags[t] = 0;
+  // residual-corrected pass requested at the previous trial: refresh M and err2
+  int resid = st->resid;
+  if (st->pad0) {
+    const double e2 = pass_dispatch(f, f.A, f.M, 1, S);
+    if (t == 0) {
+      st->err2 = e2;
+      st->eps = sqrt(e2 / st->ynorm2);
+      st->pad0 = 0;
+    }
+  }
+  const double mu = st->mu;
+  __syncthreads();
+  // Grams of the current factors (kept in the workspace)
+  for (int e = t; e < 3 * BR2; e += 256) S.Cs[e >> 6][e & 63] = f.C[e];
+  __syncthreads();
+  // S1: R x R work per mode
+  if (t == 0 || t == 64 || t == 128) rr_mode(f, t >> 6, mu, S);
+  __syncthreads();
+  // S2: gradient rows G, P = G Gt
+  if (t < T) {
+    int i;
+    const int n = mode_of_row(f, t, &i);
+    const int In = f.I[n];
+    const long long o = aoff(f, n);
+    double g[BR], a[BR];
+    for (int r = 0; r < R; ++r) {
+      a[r] = f.A[o + i + (long long)r * In];
+      g[r] = f.M[o + i + (long long)r * In];
+    }
+    if (!resid)
+      for (int r = 0; r < R; ++r) {
+        double acc = 0.0;
+        for (int s2 = 0; s2 < R; ++s2) acc += a[s2] * S.Gm[n][s2 + r * R];
+        g[r] -= acc;
+      }
+    for (int r = 0; r < R; ++r) {
+      double acc = 0.0;
+      for (int s2 = 0; s2 < R; ++s2) acc += g[s2] * S.Gt[n][s2 + r * R];
+      f.G[o + i + (long long)r * In] = g[r];
+      f.P[o + i + (long long)r * In] = acc;
+    }
+  }
+  __syncthreads();
+  // w_n = vec(A_n^T P_n)
+  if (t < 3 * BR2) {
+    const int n = t >> 6, e = t & 63, a = e & 7, b = e >> 3;
+    if (a < R && b < R) {
+      const int In = f.I[n];
+      const long long o = aoff(f, n);
+      double acc = 0.0;
+      for (int i = 0; i < In; ++i) acc += f.A[o + i + (long long)a * In] * f.P[o + i + (long long)b * In];
+      S.w[n * R2 + a + b * R] = acc;
+    }
+  }
+  __syncthreads();
+  // S3: z_n = vec(L_n^T (sum_{m != n} Gamma_nm * W_m^T) X_n)
+  {
+    auto& rr = S.u.rr;
+    if (t < 3 * BR2) {
+      const int n = t >> 6, e = t & 63, a = e & 7, b = e >> 3;
+      if (a < R && b < R) {
+        double v = 0.0;
+        for (int m = 0; m < N; ++m)
+          if (m != n) v += gamma_of(S.Cs, n, m, a + b * R) * S.w[m * R2 + b + a * R];
+        rr.V[n][a + b * R] = v;
+      }
+    }
+    __syncthreads();
+    if (t < 3 * BR2) {
+      const int n = t >> 6, e = t & 63, a = e & 7, b = e >> 3;
+      if (a < R && b < R) {
+        double acc = 0.0;
+        for (int k = 0; k < R; ++k) acc += S.Ls[n][k + a * R] * rr.V[n][k + b * R];
+        rr.T1[n][a + b * R] = acc;
+      }
+    }
+    __syncthreads();
+    if (t < 3 * BR2) {
+      const int n = t >> 6, e = t & 63, a = e & 7, b = e >> 3;
+      if (a < R && b < R) {
+        double acc = 0.0;
+        for (int k = 0; k < R; ++k) acc += rr.T1[n][a + k * R] * S.Xs[n][k + b * R];
+        S.z[n * R2 + a + b * R] = acc;
+      }
+    }
+    __syncthreads();
+  }
+  // S4: trailing system (packed lower, rows 0..nt with the RHS as row nt) and B
+  auto& Y = S.u.sys;
+  for (int p = t; p < nt; p += 256)
+    for (int q = 0; q <= p; ++q) Y.Sp[pidx(p, q)] = (p == q) ? 1.0 : 0.0;
+  __syncthreads();
+  for (int pr = 0; pr < 3; ++pr) {
+    const int n = (pr == 0) ? 1 : 2, m = (pr == 2) ? 1 : 0;
+    // Tb[(a + d R) R + i] = sum_j Gamma_nm[i,j] L_n[j,a] X_m[j,d]
+    for (int e = t; e < R * R2; e += 256) {
+      const int i = e % R, ad = e / R, a = ad % R, d = ad / R;
+      double acc = 0.0;
+      for (int j = 0; j < R; ++j) acc += gamma_of(S.Cs, n, m, i + j * R) * S.Ls[n][j + a * R] * S.Xs[m][j + d * R];
+      Y.Tb[e] = acc;
+    }
+    __syncthreads();
+    for (int e = t; e < R2 * R2; e += 256) {
+      const int a = e % R, b = (e / R) % R, c = (e / R2) % R, d = e / (R2 * R);
+      double acc = 0.0;
+      for (int i = 0; i < R; ++i) acc += S.Xs[n][i + b * R] * S.Ls[m][i + c * R] * Y.Tb[(a + d * R) * R + i];
+      const int p = (n - 1) * R2 + a + b * R;
+      if (m == 0) Y.Bm[p][c + d * R] = acc;
+      else Y.Sp[pidx(p, (m - 1) * R2 + c + d * R)] = acc;
+    }
+    __syncthreads();
+  }
+  // Schur update with block 1 and the right-hand side row
+  for (int p = (t & 127); p < nt; p += 128)
+    for (int q = (t >> 7); q <= p; q += 2) {
+      double acc = 0.0;
+      for (int k = 0; k < R2; ++k) acc += Y.Bm[p][k] * Y.Bm[q][k];
+      Y.Sp[pidx(p, q)] -= acc;
+    }
+  for (int p = t; p < nt; p += 256) {
+    double acc = 0.0;
+    for (int k = 0; k < R2; ++k) acc += Y.Bm[p][k] * S.z[k];
+    Y.Sp[pidx(nt, p)] = S.z[R2 + p] - acc;
+  }
+  // S5: Cholesky of the trailing system; row nt becomes L^-1 z'
+  for (int k = 0; k < nt; ++k) {
+    __syncthreads();
+    const double dkk = Y.Sp[pidx(k, k)];
+    double d = 1.0;
+    if (dkk > 0.0) d = sqrt(dkk);
+    else if (t == 0) S.flags[0] = 1;
+    for (int i = k + 1 + t; i <= nt; i += 256) Y.lk[i] = Y.Sp[pidx(i, k)] / d;
+    __syncthreads();
+    if (t == 0) Y.Sp[pidx(k, k)] = d;
+    for (int i = k + 1 + t; i <= nt; i += 256) Y.Sp[pidx(i, k)] = Y.lk[i];
+    for (int i = k + 1 + (t & 127); i <= nt; i += 128)
+      for (int j = k + 1 + (t >> 7); j <= i && j < nt; j += 2) Y.Sp[pidx(i, j)] -= Y.lk[i] * Y.lk[j];
+  }
+  __syncthreads();
+  // backward substitution L^T y_t = v by wave 0 (rows lane and lane + 64)
+  if (t < 64) {
+    double v0 = (lane < nt) ? Y.Sp[pidx(nt, lane)] : 0.0;
+    double v1 = (lane + 64 < nt) ? Y.Sp[pidx(nt, lane + 64)] : 0.0;
+    for (int c = nt - 1; c >= 0; --c) {
+      const double own = (c < 64) ? v0 : v1;
+      const long long b = __double_as_longlong(own);
+      const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), c & 63);
+      const int hi = __builtin_amdgcn_readlane((int)(b >> 32), c & 63);
+      const double yc = __longlong_as_double(((long long)hi << 32) | (unsigned int)lo) / Y.Sp[pidx(c, c)];
+      if (lane == 0) S.y[R2 + c] = yc;
+      if (lane < c) v0 -= Y.Sp[pidx(c, lane)] * yc;
+      if (lane + 64 < c) v1 -= Y.Sp[pidx(c, lane + 64)] * yc;
+    }
+  }
+  __syncthreads();
+  // y_1 = z_1 - B^T y_t
+  if (t < R2) {
+    double acc = 0.0;
+    for (int p = 0; p < nt; ++p) acc += Y.Bm[p][t] * S.y[R2 + p];
+    S.y[t] = S.z[t] - acc;
+  }
+  __syncthreads();
+  // S6: u_n = w_n - vec(L_n Y_n X_n^T) (into v), f_n and Q_n = F_n Gt_n
+  {
+    auto& rr = S.u.rr;  // the system is no longer needed
+    if (t < 3 * BR2) {
+      const int n = t >> 6, e = t & 63, a = e & 7, b = e >> 3;
+      if (a < R && b < R) {
+        double acc = 0.0;
+        for (int k = 0; k < R; ++k) acc += S.Ls[n][a + k * R] * S.y[n * R2 + k + b * R];
+        rr.T1[n][a + b * R] = acc;
+      }
+    }
+    __syncthreads();
+    if (t < 3 * BR2) {
+      const int n = t >> 6, e = t & 63, a = e & 7, b = e >> 3;
+      if (a < R && b < R) {
+        double acc = 0.0;
+        for (int k = 0; k < R; ++k) acc += rr.T1[n][a + k * R] * S.Xs[n][b + k * R];
+        S.v[n * R2 + a + b * R] = S.w[n * R2 + a + b * R] - acc;
+      }
+    }
+    __syncthreads();
+    if (t < 3 * BR2) {
+      const int n = t >> 6, e = t & 63, a = e & 7, b = e >> 3;
+      if (a < R && b < R) {
+        double v = 0.0;
+        for (int m = 0; m < N; ++m)
+          if (m != n) v += gamma_of(S.Cs, n, m, a + b * R) * S.v[m * R2 + b + a * R];
+        rr.V[n][a + b * R] = v;
+      }
+    }
+    __syncthreads();
+    if (t < 3 * BR2) {
+      const int n = t >> 6, e = t & 63, a = e & 7, b = e >> 3;
+      if (a < R && b < R) {
+        double acc = 0.0;
+        for (int k = 0; k < R; ++k) acc += rr.V[n][a + k * R] * S.Gt[n][k + b * R];
+        S.Qs[n][a + b * R] = acc;
+      }
+    }
+    __syncthreads();
+  }
+  // S7: update rows A_c = A + P - A Q_n, gain-ratio denominator
+  double den = 0.0;
+  if (t < T) {
+    int i;
+    const int n = mode_of_row(f, t, &i);
+    const int In = f.I[n];
+    const long long o = aoff(f, n);
+    double a[BR];
+    for (int r = 0; r < R; ++r) a[r] = f.A[o + i + (long long)r * In];
+    for (int r = 0; r < R; ++r) {
+      double acc = 0.0;
+      for (int s2 = 0; s2 < R; ++s2) acc += a[s2] * S.Qs[n][s2 + r * R];
+      const long long gi = o + i + (long long)r * In;
+      const double da = f.P[gi] - acc;
+      f.Ac[gi] = a[r] + da;
+      den += da * (f.G[gi] + mu * da);
+    }
+  }
+  den = block_sum(den, S.red);
+  // candidate Grams into LDS rr scratch and the workspace
+  __shared__ double Cc[3][BR2];
+  grams(f, f.Ac, Cc, f.Cc);
+  // S8: tensor pass at the candidate
+  const double pv = pass_dispatch(f, f.Ac, f.Mc, resid, S);
+  double err2c;
+  if (resid) {
+    err2c = pv;
+  } else {
+    double yh = 0.0;
+    for (int e = t; e < BR2; e += 256) {
+      const int r = e & 7, q = e >> 3;
+      if (r < R && q < R) yh += Cc[0][r + q * R] * Cc[1][r + q * R] * Cc[2][r + q * R];
+    }
+    yh = block_sum(yh, S.red);
+    err2c = st->ynorm2_pass - 2.0 * pv + yh;
+  }
+  // S9: damping control, normalisation and commit
+  __shared__ int accept_s;
+  if (t == 0) {
+    int accept = 0;
+    const double rho = (st->err2 - err2c) / den;
+    st->denom = den;
+    st->rho = rho;
+    st->err2_cand = err2c;
+    st->iters += 1;
+    if (resid) st->resid_iters += 1;
+    if (S.flags[0]) st->singular = 1;
+    if (st->singular || !isfinite(err2c) || !isfinite(den)) {
+      st->stop = 1;
+      st->reason = 3;
+    } else {
+      if (err2c < st->err2) {
+        accept = 1;
+        st->accepted += 1;
+        st->eps_prev = st->eps;
+        st->err2 = err2c;
+        st->eps = sqrt(err2c / st->ynorm2);
+        const double t3 = 2.0 * rho - 1.0;
+        double fct = 1.0 - t3 * t3 * t3;
+        if (fct < 1.0 / 3.0) fct = 1.0 / 3.0;
+        st->mu *= fct;
+        if (fabs(st->eps_prev - st->eps) < st->tol) {
+          st->stop = 1;
+          st->reason = 0;
+        } else if (!resid && cfg.resid_switch > 0.0 && fabs(st->eps_prev - st->eps) < cfg.resid_switch) {
+          st->resid = 1;
+          st->pad0 = 1;
+        }
+      } else {
+        st->mu *= 2.0;
+      }
+      if (!st->stop && st->mu > 1e30) {
+        st->stop = 1;
+        st->reason = 2;
+      }
+      if (!st->stop && st->iters >= st->max_iters) {
+        st->stop = 1;
+        st->reason = 1;
+      }
+    }
+    if (st->stop) atomicAdd(cfg.nstopped, 1);
+    accept_s = accept;
+  }
+  __syncthreads();
+  if (!accept_s) return;
+  __shared__ double sc[3][BR];
+  if (t < R) {
+    double nr[3], lam = 1.0;
+    bool ok = true;
+    for (int n = 0; n < 3; ++n) {
+      nr[n] = sqrt(Cc[n][t + t * R]);
+      ok = ok && nr[n] > 0.0;
+      lam *= nr[n];
+    }
+    for (int n = 0; n < 3; ++n) {
+      double s2 = 1.0;
+      if (ok) {
+        if (st->normalize == 0) {
+          s2 = pow(lam, 1.0 / 3.0) / nr[n];
+        } else if (st->normalize == 1) {
+          s2 = (n < 2) ? 1.0 / nr[n] : nr[0] * nr[1];
+        }
+      }
+      sc[n][t] = s2;
+    }
+  }
+  __syncthreads();
+  if (t < T) {
+    int i;
+    const int n = mode_of_row(f, t, &i);
+    const int In = f.I[n];
+    const long long o = aoff(f, n);
+    for (int r = 0; r < R; ++r) {
+      double other = 1.0;
+      for (int k = 0; k < 3; ++k)
+        if (k != n) other *= sc[k][r];
+      const long long gi = o + i + (long long)r * In;
+      f.A[gi] = f.Ac[gi] * sc[n][r];
+      f.M[gi] = f.Mc[gi] * other;
+    }
+  }
+  if (t < 3 * BR2) {
+    const int n = t >> 6, e = t & 63, r = e & 7, q = e >> 3;
+    if (r < R && q < R) f.C[n * BR2 + r + q * R] = Cc[n][r + q * R] * sc[n][r] * sc[n][q];
+  }
+}
+
+// Copy the result factors back to the caller's buffers.
+__global__ __launch_bounds__(256) void k_bfinal(BFit* fits, int nfits) {
+  const int fi = blockIdx.x;
+  if (fi >= nfits) return;
+  const BFit f = fits[fi];
+  for (int n = 0; n < 3; ++n) {
+    const long long o = aoff(f, n);
+    for (int e = threadIdx.x; e < f.I[n] * f.R; e += 256) f.Ain[n][e] = f.A[o + e];
+  }
+}
+
+}  // namespace
+
+bool batched_supported(int order, const int64_t* dims, int R) {
+  if (order != 3 || R < 1 || R > BR) return false;
+  for (int n = 0; n < 3; ++n)
+    if (dims[n] < 1 || dims[n] > BI) return false;
+  return true;
+}
+
+size_t batched_fit_doubles(const int* I, int R) {
+  const size_t TR = (size_t)(I[0] + I[1] + I[2]) * R;
+  return 6 * TR + 2 * 3 * BR2;
+}
+
+hipError_t launch_batched_init(BFit* fits, int nfits, const BatchCfg& cfg, hipStream_t st) {
+  k_binit<<<nfits, 256, 0, st>>>(fits, nfits, cfg);
+  return hipGetLastError();
+}
+
+hipError_t launch_batched_trial(BFit* fits, int nfits, const BatchCfg& cfg, hipStream_t st) {
+  k_btrial<<<nfits, 256, 0, st>>>(fits, nfits, cfg);
+  return hipGetLastError();
+}
+
+hipError_t launch_batched_final(BFit* fits, int nfits, hipStream_t st) {
+  k_bfinal<<<nfits, 256, 0, st>>>(fits, nfits);
+  return hipGetLastError();
+}
+
+}  // namespace dgn

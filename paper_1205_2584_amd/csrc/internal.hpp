@@ -109,4 +109,28 @@ hipError_t launch_commit(const Shape& s, double* A, const double* Ac, double* M,
                          double* C, const double* Cc, const FitState* state, int trial,
                          hipStream_t st);
 
+// ---- batched small fits (one block per fit per trial) ---------------------------
+struct BFit {
+  const void* Y;
+  int dtype;  // 0 = FP64, 1 = FP32
+  int I[3];
+  int R;
+  double mu0;
+  double *A, *Ac, *M, *Mc, *G, *P, *C, *Cc;  // per-fit workspace
+  double* Ain[3];                             // caller's factors
+  FitState* st;
+};
+
+struct BatchCfg {
+  double tol, tau, resid_switch;
+  int max_iters, normalize;
+  int* nstopped;
+};
+
+bool batched_supported(int order, const int64_t* dims, int R);
+size_t batched_fit_doubles(const int* I, int R);
+hipError_t launch_batched_init(BFit* fits, int nfits, const BatchCfg& cfg, hipStream_t st);
+hipError_t launch_batched_trial(BFit* fits, int nfits, const BatchCfg& cfg, hipStream_t st);
+hipError_t launch_batched_final(BFit* fits, int nfits, hipStream_t st);
+
 }  // namespace dgn

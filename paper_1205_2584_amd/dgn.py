@@ -40,7 +40,8 @@ class dgn_tensor(ctypes.Structure):
 class dgn_opts(ctypes.Structure):
     _fields_ = [("normalize", ctypes.c_int32), ("tau", ctypes.c_double),
                 ("resid_switch", ctypes.c_double), ("y_bf16", ctypes.c_void_p),
-                ("poll_every", ctypes.c_int32), ("timing", ctypes.c_int32)]
+                ("poll_every", ctypes.c_int32), ("timing", ctypes.c_int32),
+                ("graph", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class dgn_step_info(ctypes.Structure):
@@ -54,8 +55,13 @@ class dgn_fit_info(ctypes.Structure):
                 ("mu", ctypes.c_double), ("mu0", ctypes.c_double)]
 
 
+class dgn_batch_fit(ctypes.Structure):
+    _fields_ = [("Y", dgn_tensor), ("R", ctypes.c_int32), ("mu0", ctypes.c_double),
+                ("A", ctypes.c_void_p * 3)]
+
+
 EXPORTS = ["dgn_opts_default", "dgn_create", "dgn_destroy", "dgn_last_error", "dgn_workspace_size",
-           "dgn_mttkrp", "dgn_step", "cp_fit", "dgn_last_phase_times"]
+           "dgn_mttkrp", "dgn_step", "cp_fit", "dgn_last_phase_times", "cp_fit_batched"]
 NUM_PHASES = 6
 PHASES = ["pre", "assemble", "factor_solve", "update", "tensor_pass", "control"]
 
@@ -86,8 +92,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.cp_fit.argtypes = [vp, ctypes.POINTER(dgn_tensor), i32, ctypes.POINTER(vp), dbl, dbl, i32,
                          ctypes.POINTER(dgn_opts), ctypes.POINTER(dgn_fit_info), vp]
     L.dgn_last_phase_times.argtypes = [vp, ctypes.POINTER(dbl), i32, ctypes.POINTER(i32)]
+    L.cp_fit_batched.argtypes = [vp, i32, ctypes.POINTER(dgn_batch_fit), dbl, i32,
+                                 ctypes.POINTER(dgn_opts), ctypes.POINTER(dgn_fit_info), vp]
     for name in ("dgn_create", "dgn_destroy", "dgn_workspace_size", "dgn_mttkrp", "dgn_step", "cp_fit",
-                 "dgn_last_phase_times"):
+                 "dgn_last_phase_times", "cp_fit_batched"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -183,6 +191,24 @@ class Context:
                                   ctypes.byref(options) if options else None, ctypes.byref(info),
                                   _stream()))
         return {k: getattr(info, k) for k, _ in dgn_fit_info._fields_}
+
+    def cp_fit_batched(self, problems, tol, max_iters, options: dgn_opts | None = None):
+        """problems: list of (y, dims, R, factors, mu0); factors are fitted in place.
+        Returns one info dict per problem."""
+        B = len(problems)
+        arr = (dgn_batch_fit * B)()
+        for b, (y, dims, R, factors, mu0) in enumerate(problems):
+            arr[b].Y = tensor_desc(y, dims)
+            arr[b].R = int(R)
+            arr[b].mu0 = float(mu0)
+            p = _ptrs(factors)
+            for n in range(3):
+                arr[b].A[n] = p[n]
+        infos = (dgn_fit_info * B)()
+        self._check(self.L.cp_fit_batched(self.h, B, arr, float(tol), int(max_iters),
+                                          ctypes.byref(options) if options else None, infos,
+                                          _stream()))
+        return [{k: getattr(infos[b], k) for k, _ in dgn_fit_info._fields_} for b in range(B)]
 
     def dgn_last_phase_times(self):
         """Per-phase total milliseconds of the last timed cp_fit and the trial count."""
