@@ -201,6 +201,49 @@ dgn_status cp_fit_batched(dgn_ctx* ctx, int32_t B, const dgn_batch_fit* fits, do
                           int32_t max_iters, const dgn_opts* opts, dgn_fit_info* infos,
                           void* stream);
 
+/* ---- Serving: a request loop over cp_fit ------------------------------------
+ * A server owns one device arena of budget_bytes.  Requests are admitted in
+ * arrival order when a slot is free and their workspace (dgn_workspace_size)
+ * fits in the free part of the arena; admitted requests run concurrently,
+ * each on its own stream, so their kernels overlap on the device.  The
+ * caller keeps ownership of each request's tensor and factors until its
+ * result has been polled.  Results do not depend on what else is running. */
+typedef struct dgn_server dgn_server;
+
+typedef struct dgn_request {
+  dgn_tensor Y;
+  int32_t R;
+  double mu0;          /* > 0 as given, <= 0 tau rule */
+  double tol;
+  int32_t max_iters;
+  void* A[DGN_MAX_ORDER]; /* device FP64 factors: in start, out result */
+  uint64_t tag;        /* caller's tag, returned with the result */
+} dgn_request;
+
+typedef struct dgn_result {
+  uint64_t id;
+  uint64_t tag;
+  int32_t status;      /* dgn_status of the fit */
+  dgn_fit_info info;
+  double t_submit, t_admit, t_done; /* seconds on the server's monotonic clock */
+} dgn_result;
+
+/* max_slots concurrent fits (1..64); opts as for cp_fit (may be NULL). */
+dgn_status dgn_server_create(dgn_server** out, int32_t device, size_t budget_bytes,
+                             int32_t max_slots, const dgn_opts* opts);
+/* Queue a request; never blocks.  DGN_EBUSY if its workspace can never fit
+ * the budget, DGN_EINVAL on a bad shape.  *id identifies the result. */
+dgn_status dgn_server_submit(dgn_server* srv, const dgn_request* req, uint64_t* id);
+/* Move up to max finished results into out; *n receives the count. */
+dgn_status dgn_server_poll(dgn_server* srv, dgn_result* out, int32_t max, int32_t* n);
+/* Block until nothing is queued or running. */
+dgn_status dgn_server_wait_idle(dgn_server* srv);
+/* Current arena bytes in use, running fits, queued requests (any may be NULL). */
+dgn_status dgn_server_stats(dgn_server* srv, size_t* in_use, int32_t* running, int32_t* queued);
+/* Seconds on the server clock (the clock of t_submit / t_admit / t_done). */
+double dgn_server_now(const dgn_server* srv);
+dgn_status dgn_server_destroy(dgn_server* srv);
+
 /* Per-phase GPU time of the last cp_fit call made with opts->timing != 0,
  * from HIP events recorded on that call's stream around each phase of every
  * executed trial.  ms_out[k] (k < n <= DGN_NUM_PHASES) receives the total

@@ -13,7 +13,7 @@ BUILD = os.path.join(HERE, "_build")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libdgn.so")
 
-SOURCES = ["tensor_pass.hip", "small.hip", "chol.hip", "fit.hip", "batched.hip", "api.hip"]
+SOURCES = ["tensor_pass.hip", "small.hip", "chol.hip", "fit.hip", "batched.hip", "api.hip", "serve.hip"]
 ARCH = os.environ.get("DGN_OFFLOAD_ARCH", "gfx950")
 FLAGS = [
     "-O3", f"--offload-arch={ARCH}", "-std=c++17", "-fPIC",
@@ -53,7 +53,7 @@ def build(verbose: bool = False) -> str:
     with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(compile_one, SOURCES))
     tmp = LIB + ".tmp"
-    _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs])
+    _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, "-lpthread"])
     os.replace(tmp, LIB)
     return LIB
 

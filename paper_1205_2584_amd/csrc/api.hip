@@ -13,6 +13,7 @@ struct dgn_ctx {
   int device;
   char* ws;
   size_t ws_size;
+  bool owns_ws = true;
   std::string err;
   std::vector<hipEvent_t> events;   // timing pool, (DGN_NUM_PHASES + 1) per trial
   hipStream_t own = nullptr;        // private stream for graph capture (default priority)
@@ -22,6 +23,16 @@ struct dgn_ctx {
 
 namespace dgn {
 hipError_t launch_inner(const Shape& s, const double* A, const double* M, double* out, hipStream_t st);
+
+// A context over a caller-provided device region (used by the server's slots).
+dgn_ctx* ctx_over(int device, char* ws, size_t size) {
+  dgn_ctx* c = new dgn_ctx();
+  c->device = device;
+  c->ws = ws;
+  c->ws_size = size;
+  c->owns_ws = false;
+  return c;
+}
 }
 
 namespace {
@@ -273,7 +284,7 @@ dgn_status dgn_destroy(dgn_ctx* ctx) {
   hipSetDevice(ctx->device);
   for (hipEvent_t e : ctx->events) hipEventDestroy(e);
   if (ctx->own) hipStreamDestroy(ctx->own);
-  hipFree(ctx->ws);
+  if (ctx->owns_ws) hipFree(ctx->ws);
   delete ctx;
   return DGN_OK;
 }

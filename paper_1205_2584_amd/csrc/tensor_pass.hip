@@ -166,7 +166,7 @@ __global__ __launch_bounds__(256) void k_pass_fma(PassArgs a, const int* stop) {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
-constexpr int kQMax = 32;  // slabs per block of the MFMA kernels (t and c_q staged in LDS)
+constexpr int kQMax = 16;  // slabs per block of the MFMA kernels (t and c_q staged in LDS)
 
 __device__ __forceinline__ float fac(const PassArgs& a, int mode, int Im, int i, int r) {
   return (i < Im && r < a.R) ? (float)a.A[a.off[mode] + i + (long long)r * Im] : 0.0f;
@@ -187,7 +187,7 @@ __device__ __forceinline__ float cq_of(const PassArgs& a, long long q, int r) {
 
 // Epilogue shared by the MFMA kernels: t from LDS, partial M_1 and M_2.
 template <int NB>
-__device__ __forceinline__ void pass_epilogue(const PassArgs& a, float (*tq_s)[64], long long q0,
+__device__ __forceinline__ void pass_epilogue(const PassArgs& a, float (*tq_s)[kQMax][64], long long q0,
                                               long long q1, int tile, int ti, int tj, int i0, int j0,
                                               const v4f* m0acc, const v4f* m1acc) {
   const int t = threadIdx.x, lane = t & 63, w = t >> 6, g = lane >> 4, c16 = lane & 15;
@@ -197,7 +197,7 @@ __device__ __forceinline__ void pass_epilogue(const PassArgs& a, float (*tq_s)[6
   const int nq = (int)(q1 - q0);
   for (int e = t; e < nq * R; e += 256) {
     const int ql = e % nq, r = e / nq;
-    tp[(long long)r * a.Q + q0 + ql] = tq_s[ql][r];
+    tp[(long long)r * a.Q + q0 + ql] = ((tq_s[0][ql][r] + tq_s[1][ql][r]) + tq_s[2][ql][r]) + tq_s[3][ql][r];
   }
   float* m0p = static_cast<float*>(a.m0part) + ((long long)blockIdx.y * a.tiles_j + tj) * R * I0;
   float* m1p = static_cast<float*>(a.m1part) + ((long long)blockIdx.y * a.tiles_i + ti) * R * I1;
@@ -221,7 +221,7 @@ __global__ __launch_bounds__(256) void k_pass_f32(PassArgs a, const int* stop) {
   constexpr int LDY = 68;
   __shared__ __attribute__((aligned(16))) float Ys[64][LDY];  // Ys[j][i]
   __shared__ float cq_all[kQMax][64];
-  __shared__ float tq_s[kQMax][64];
+  __shared__ float tq_s[4][kQMax][64];  // per-wave partial t, summed in wave order
   __shared__ float A0s[RESID ? 64 : 1][65];
   __shared__ float A1s[RESID ? 64 : 1][65];
   __shared__ double red[16];
@@ -255,7 +255,6 @@ __global__ __launch_bounds__(256) void k_pass_f32(PassArgs a, const int* stop) {
   }
   for (int e = t; e < kQMax * 64; e += 256) {
     const int ql = e >> 6, r = e & 63;
-    tq_s[ql][r] = 0.0f;
     cq_all[ql][r] = (q0 + ql < q1) ? cq_of(a, q0 + ql, r) : 0.0f;
   }
 
@@ -345,7 +344,7 @@ __global__ __launch_bounds__(256) void k_pass_f32(PassArgs a, const int* stop) {
                  a0t[nb][3] * zacc[nb][3];
       tv += __shfl_xor(tv, 16, 64);
       tv += __shfl_xor(tv, 32, 64);
-      if (g == 0) atomicAdd(&tq_s[ql][16 * nb + c16], tv);
+      if (g == 0) tq_s[w][ql][16 * nb + c16] = tv;
     }
   }
   pass_epilogue<NB>(a, tq_s, q0, q1, tile, ti, tj, i0, j0, m0acc, m1acc);
@@ -369,7 +368,7 @@ __global__ __launch_bounds__(256) void k_pass_bf16(PassArgs a, const int* stop) 
   constexpr int LDY = 72;
   __shared__ __attribute__((aligned(16))) __bf16 Ys[64][LDY];  // Ys[j][i]
   __shared__ float cq_all[kQMax][64];
-  __shared__ float tq_s[kQMax][64];
+  __shared__ float tq_s[4][kQMax][64];  // per-wave partial t, summed in wave order
   const int t = threadIdx.x, lane = t & 63, w = t >> 6, g = lane >> 4, c16 = lane & 15;
   const int I0 = a.I0, I1 = a.I1;
   const int tile = blockIdx.x, ti = tile % a.tiles_i, tj = tile / a.tiles_i;
@@ -401,7 +400,6 @@ __global__ __launch_bounds__(256) void k_pass_bf16(PassArgs a, const int* stop) 
     for (int v = 0; v < 4; ++v) a0t[nb][v] = fac(a, 0, I0, i0 + 16 * w + 4 * g + v, 16 * nb + c16);
   for (int e = t; e < kQMax * 64; e += 256) {
     const int ql = e >> 6, r = e & 63;
-    tq_s[ql][r] = 0.0f;
     cq_all[ql][r] = (q0 + ql < q1) ? cq_of(a, q0 + ql, r) : 0.0f;
   }
 
@@ -472,7 +470,7 @@ __global__ __launch_bounds__(256) void k_pass_bf16(PassArgs a, const int* stop) 
                  a0t[nb][3] * zacc[nb][3];
       tv += __shfl_xor(tv, 16, 64);
       tv += __shfl_xor(tv, 32, 64);
-      if (g == 0) atomicAdd(&tq_s[ql][16 * nb + c16], tv);
+      if (g == 0) tq_s[w][ql][16 * nb + c16] = tv;
     }
   }
   pass_epilogue<NB>(a, tq_s, q0, q1, tile, ti, tj, i0, j0, m0acc, m1acc);

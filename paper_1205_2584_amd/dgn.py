@@ -60,8 +60,22 @@ class dgn_batch_fit(ctypes.Structure):
                 ("A", ctypes.c_void_p * 3)]
 
 
+class dgn_request(ctypes.Structure):
+    _fields_ = [("Y", dgn_tensor), ("R", ctypes.c_int32), ("mu0", ctypes.c_double),
+                ("tol", ctypes.c_double), ("max_iters", ctypes.c_int32),
+                ("A", ctypes.c_void_p * MAX_ORDER), ("tag", ctypes.c_uint64)]
+
+
+class dgn_result(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_uint64), ("tag", ctypes.c_uint64), ("status", ctypes.c_int32),
+                ("info", dgn_fit_info), ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_done", ctypes.c_double)]
+
+
 EXPORTS = ["dgn_opts_default", "dgn_create", "dgn_destroy", "dgn_last_error", "dgn_workspace_size",
-           "dgn_mttkrp", "dgn_step", "cp_fit", "dgn_last_phase_times", "cp_fit_batched"]
+           "dgn_mttkrp", "dgn_step", "cp_fit", "dgn_last_phase_times", "cp_fit_batched",
+           "dgn_server_create", "dgn_server_submit", "dgn_server_poll", "dgn_server_wait_idle",
+           "dgn_server_stats", "dgn_server_now", "dgn_server_destroy"]
 NUM_PHASES = 6
 PHASES = ["pre", "assemble", "factor_solve", "update", "tensor_pass", "control"]
 
@@ -94,8 +108,17 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.dgn_last_phase_times.argtypes = [vp, ctypes.POINTER(dbl), i32, ctypes.POINTER(i32)]
     L.cp_fit_batched.argtypes = [vp, i32, ctypes.POINTER(dgn_batch_fit), dbl, i32,
                                  ctypes.POINTER(dgn_opts), ctypes.POINTER(dgn_fit_info), vp]
+    L.dgn_server_create.argtypes = [ctypes.POINTER(vp), i32, ctypes.c_size_t, i32, ctypes.POINTER(dgn_opts)]
+    L.dgn_server_submit.argtypes = [vp, ctypes.POINTER(dgn_request), ctypes.POINTER(ctypes.c_uint64)]
+    L.dgn_server_poll.argtypes = [vp, ctypes.POINTER(dgn_result), i32, ctypes.POINTER(i32)]
+    L.dgn_server_wait_idle.argtypes = [vp]
+    L.dgn_server_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    L.dgn_server_now.argtypes = [vp]
+    L.dgn_server_now.restype = dbl
+    L.dgn_server_destroy.argtypes = [vp]
     for name in ("dgn_create", "dgn_destroy", "dgn_workspace_size", "dgn_mttkrp", "dgn_step", "cp_fit",
-                 "dgn_last_phase_times", "cp_fit_batched"):
+                 "dgn_last_phase_times", "cp_fit_batched", "dgn_server_create", "dgn_server_submit",
+                 "dgn_server_poll", "dgn_server_wait_idle", "dgn_server_stats", "dgn_server_destroy"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -216,6 +239,71 @@ class Context:
         n = ctypes.c_int32()
         self._check(self.L.dgn_last_phase_times(self.h, ms, NUM_PHASES, ctypes.byref(n)))
         return dict(zip(PHASES, list(ms))), n.value
+
+
+class Server:
+    """dgn_server: FIFO admission by device-memory budget, concurrent slots."""
+
+    def __init__(self, device=0, budget_bytes=1 << 30, max_slots=4, options: dgn_opts | None = None):
+        self.L = load()
+        h = ctypes.c_void_p()
+        st = self.L.dgn_server_create(ctypes.byref(h), int(device), int(budget_bytes), int(max_slots),
+                                      ctypes.byref(options) if options else None)
+        if st != 0:
+            raise DgnError(st, "dgn_server_create failed")
+        self.h = h
+        self._keep = {}
+
+    def submit(self, y, dims, R, factors, mu0=-1.0, tol=1e-8, max_iters=200, tag=0):
+        r = dgn_request()
+        r.Y = tensor_desc(y, dims)
+        r.R, r.mu0, r.tol, r.max_iters, r.tag = int(R), float(mu0), float(tol), int(max_iters), int(tag)
+        p = _ptrs(factors)
+        for n in range(len(factors)):
+            r.A[n] = p[n]
+        rid = ctypes.c_uint64()
+        st = self.L.dgn_server_submit(self.h, ctypes.byref(r), ctypes.byref(rid))
+        if st != 0:
+            raise DgnError(st, "dgn_server_submit failed")
+        self._keep[rid.value] = (y, factors)  # the caller's buffers stay alive until polled
+        return rid.value
+
+    def poll(self, max_results=256):
+        out = (dgn_result * max_results)()
+        n = ctypes.c_int32()
+        st = self.L.dgn_server_poll(self.h, out, max_results, ctypes.byref(n))
+        if st != 0:
+            raise DgnError(st, "dgn_server_poll failed")
+        res = []
+        for k in range(n.value):
+            o = out[k]
+            self._keep.pop(o.id, None)
+            res.append(dict(id=o.id, tag=o.tag, status=o.status,
+                            info={f: getattr(o.info, f) for f, _ in dgn_fit_info._fields_},
+                            t_submit=o.t_submit, t_admit=o.t_admit, t_done=o.t_done))
+        return res
+
+    def wait_idle(self):
+        self.L.dgn_server_wait_idle(self.h)
+
+    def now(self):
+        return self.L.dgn_server_now(self.h)
+
+    def stats(self):
+        used, run, q = ctypes.c_size_t(), ctypes.c_int32(), ctypes.c_int32()
+        self.L.dgn_server_stats(self.h, ctypes.byref(used), ctypes.byref(run), ctypes.byref(q))
+        return used.value, run.value, q.value
+
+    def close(self):
+        if self.h:
+            self.L.dgn_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def workspace_size(dims, R, dtype=torch.float64) -> int:
