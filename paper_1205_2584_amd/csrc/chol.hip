@@ -390,8 +390,8 @@ __global__ __launch_bounds__(256) void k_syrk(SysPlan p, const double* B, int R2
 // update of column ph-1 to its tile and to the diagonal tile, factors the
 // diagonal tile and solves its tile.  Remaining blocks: trailing tiles
 // (i, j), ph < j <= i <= Tt, j < Tt, receive the update of column ph-1.
-__global__ __launch_bounds__(256) void k_chol_phase(SysPlan p, int ph, double* St, int* bad,
-                                                    const int* stop) {
+__global__ __launch_bounds__(256) void k_chol_phase(SysPlan p, int ph, double* St, double* Ld,
+                                                    int* bad, const int* stop) {
   if (stopped(stop)) return;
   __shared__ double D[64][TL];   // D[row][col]
   __shared__ double Bt[64][TL];  // Bt[row][col]
@@ -402,7 +402,7 @@ __global__ __launch_bounds__(256) void k_chol_phase(SysPlan p, int ph, double* S
   const int t = threadIdx.x;
   if ((int)blockIdx.x < npanel) {
     const int i = ph + blockIdx.x;
-    double* Dg = St + ph * 64 + (long long)ph * 64 * lds;
+    const double* Dg = St + ph * 64 + (long long)ph * 64 * lds;
     double* Bg = St + i * 64 + (long long)ph * 64 * lds;
     stage_rowmajor(D, Dg, lds);
     if (i != ph) stage_rowmajor(Bt, Bg, lds);
@@ -430,9 +430,12 @@ __global__ __launch_bounds__(256) void k_chol_phase(SysPlan p, int ph, double* S
     }
     chol64(D, bad);
     if (i == ph) {
+      // The factored tile goes to Ld, never back to St: the other panel workgroups of
+      // this launch stage the unfactored tile (ph, ph) from St and may start late.
+      double* Lg = Ld + (long long)ph * 64 * 64;
       for (int e = t; e < 64 * 64; e += 256) {
         const int r = e & 63, c = e >> 6;
-        Dg[r + c * lds] = (c <= r) ? D[r][c] : 0.0;
+        Lg[r + c * 64] = (c <= r) ? D[r][c] : 0.0;
       }
     } else {
       trsm64(Bt, D);
@@ -465,8 +468,8 @@ __global__ __launch_bounds__(256) void k_chol_phase(SysPlan p, int ph, double* S
 // Backward substitution, phase k (descending): every block solves
 // L_kk^T y_k = u_k (u in the RHS row); block k stores y_k, block j < k
 // updates u_j -= L_kj^T y_k.
-__global__ __launch_bounds__(256) void k_bsolve(SysPlan p, int k, double* St, double* yt,
-                                                const int* stop) {
+__global__ __launch_bounds__(256) void k_bsolve(SysPlan p, int k, double* St, const double* Ld,
+                                                double* yt, const int* stop) {
   if (stopped(stop)) return;
   __shared__ double L[64][TL];   // L[row][col] of the diagonal tile
   __shared__ double Lt[64][TL];  // staged L(k, j), [col][row]
@@ -474,8 +477,7 @@ __global__ __launch_bounds__(256) void k_bsolve(SysPlan p, int k, double* St, do
   __shared__ double part[4][64];
   const long long lds = p.lds;
   const int t = threadIdx.x, j = blockIdx.x;
-  const double* Lg = St + k * 64 + (long long)k * 64 * lds;
-  stage_rowmajor(L, Lg, lds);
+  stage_rowmajor(L, Ld + (long long)k * 64 * 64, 64);
   if (j != k) stage(Lt, St + k * 64 + (long long)j * 64 * lds, lds);
   __syncthreads();
   if (t < 64) {
@@ -564,9 +566,9 @@ hipError_t launch_sys_factor_solve(const Shape& s, const SysPlan& p, const Small
     long long nupd = 0;
     if (ph > 0)
       for (int j = ph + 1; j < p.Tt; ++j) nupd += p.Tt - j + 1;
-    k_chol_phase<<<(unsigned)(npanel + nupd), 256, 0, st>>>(p, ph, y.St, singular, stop);
+    k_chol_phase<<<(unsigned)(npanel + nupd), 256, 0, st>>>(p, ph, y.St, y.Ld, singular, stop);
   }
-  for (int k = p.Tt - 1; k >= 0; --k) k_bsolve<<<k + 1, 256, 0, st>>>(p, k, y.St, y.yt, stop);
+  for (int k = p.Tt - 1; k >= 0; --k) k_bsolve<<<k + 1, 256, 0, st>>>(p, k, y.St, y.Ld, y.yt, stop);
   k_y0<<<(p.R2 + 3) / 4, 256, 0, st>>>(p, y.B, b.z, y.yt, b.y, stop);
   return hipGetLastError();
 }

@@ -87,6 +87,9 @@ struct SysBuffers {
   double* St;   // lds x ntp, column-major; rows ntp.. hold the right-hand side row
   double* B;    // ntp x R^2, the first block column of S below the identity block
   double* yt;   // ntp
+  double* Ld;   // Tt tiles of 64 x 64 (column-major, leading dimension 64): the factored
+                // diagonal tiles L(k, k). They live apart from St so that, while phase k
+                // runs, every workgroup still reads the unfactored tile (k, k) from St.
 };
 
 hipError_t launch_sys_assemble(const Shape& s, const SysPlan& p, const SmallBuffers& b,
