@@ -96,7 +96,9 @@ typedef struct dgn_opts {
    * the fit switches to the residual-corrected pass: E = Y - Y_hat is formed
    * in FP32 inside the pass, the gradient is MTTKRP(E) and the error is
    * sum(E^2).  0 never switches, a negative value starts residual-corrected.
-   * F64/C128 tensors always use the residual form.  Default 1e-4. */
+   * F64/C128 tensors always use the residual form.  Default 1e-3: a BF16
+   * tensor carries about 2^-9 relative rounding per entry, so changes of eps
+   * below that level have to be judged from the exact residual. */
   double resid_switch;
   /* Optional BF16 copy of Y (same dims, device) used by the plain passes of
    * an F32 tensor before the switch.  NULL: the F32 tensor is used. */

@@ -256,7 +256,7 @@ void dgn_opts_default(dgn_opts* o) {
   memset(o, 0, sizeof(*o));
   o->normalize = DGN_NORM_BALANCED;
   o->tau = 1e-3;
-  o->resid_switch = 1e-4;
+  o->resid_switch = 1e-3;
   o->y_bf16 = nullptr;
   o->poll_every = 8;
   o->timing = 0;

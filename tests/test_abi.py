@@ -46,7 +46,7 @@ def test_opts_defaults(lib):
     from paper_1205_2584_amd import dgn
     o = dgn.dgn_opts()
     lib.dgn_opts_default(ctypes.byref(o))
-    assert o.normalize == 0 and o.tau == 1e-3 and o.resid_switch == 1e-4 and o.poll_every == 8
+    assert o.normalize == 0 and o.tau == 1e-3 and o.resid_switch == 1e-3 and o.poll_every == 8
 
 
 @pytest.mark.parametrize("dims,R,ok", [
