@@ -163,8 +163,9 @@ void carve(Arena& ar, Work& w, bool with_system) {
     w.sy.B = ar.take<double>((size_t)q.ntp * r2p);
     w.sy.yt = ar.take<double>((size_t)q.ntp);
     w.sy.Ld = ar.take<double>((size_t)q.Tt * 64 * 64);
+    w.sy.Li = ar.take<double>((size_t)q.Tt * 64 * 64);
   } else {
-    w.sy = SysBuffers{nullptr, nullptr, nullptr, nullptr};
+    w.sy = SysBuffers{nullptr, nullptr, nullptr, nullptr, nullptr};
   }
 }
 

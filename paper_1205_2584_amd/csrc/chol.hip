@@ -107,120 +107,176 @@ __device__ __forceinline__ void mma_lds(const double (*A)[TL], const double (*B)
   }
 }
 
-// Broadcast lane `src` (wave-uniform) of v to the whole wave.
-__device__ __forceinline__ double lane_value(double v, int src) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), src);
-  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+// ---- panel factorisation helpers ----------------------------------------------
+//
+// The panel of phase ph is the stacked 128 x 64 block [D; B] (D the diagonal
+// tile, B one tile below it) held row-major in LDS with row stride TR.  It is
+// factored in four 16-column steps: a 16 x 16 Cholesky of the diagonal block by
+// one wave, a row-parallel triangular solve for every row below it, and an MFMA
+// update of the columns to its right.
+
+constexpr int TR = 66;  // row stride of the panel: T[row][k] MFMA operand reads are bank-conflict free
+
+// Broadcast lane SRC of each 16-lane row of v to that whole row (DPP row_newbcast).
+template <int SRC>
+__device__ __forceinline__ double row_bcast(double v) {
+  return __builtin_amdgcn_update_dpp(0.0, v, 0x150 + SRC, 0xf, 0xf, true);
 }
 
-// In-register Cholesky of the 16 x 16 block D[k0.., k0..] by one wave (lanes
-// 0..15 hold one row each); written back lower with zeros above.
-__device__ void chol16_wave(double (*D)[TL], int k0, int* bad) {
+template <int J>
+__device__ __forceinline__ void chol_update(double (&r)[16], double l) {
+  if constexpr (J < 16) {
+    r[J] -= l * row_bcast<J>(l);
+    chol_update<J + 1>(r, l);
+  }
+}
+
+// Column C of the in-register 16 x 16 Cholesky: lane `row` holds row `row` in r.
+template <int C>
+__device__ __forceinline__ void chol_column(double (&r)[16], int row, bool& ok, double& myinv) {
+  if constexpr (C < 16) {
+    const double piv = row_bcast<C>(r[C]);
+    const bool pos = piv > 0.0;
+    ok = ok && pos;
+    const double inv = rsqrt_f64(pos ? piv : 1.0);
+    const double d = pos ? piv * inv : 1.0;
+    if (row == C) myinv = inv;
+    const double l = (row > C) ? r[C] * inv : (row == C ? d : 0.0);
+    r[C] = l;
+    chol_update<C + 1>(r, l);
+    chol_column<C + 1>(r, row, ok, myinv);
+  }
+}
+
+// Cholesky of the 16 x 16 block T[k0.., k0..] by one wave (each 16-lane row of
+// the wave computes the same rows).  L goes back into T (zeros above), a compact
+// copy into Lkk, and 1/L_cc into rinv[k0 + c].  A non-positive pivot sets *bad.
+__device__ void chol16(double (*T)[TR], int k0, int* bad, double (*Lkk)[16], double* rinv) {
   const int lane = threadIdx.x & 63;
   const int row = lane & 15;
   double r[16];
 #pragma unroll
-  for (int j = 0; j < 16; ++j) r[j] = (j <= row) ? D[k0 + row][k0 + j] : 0.0;
-#pragma unroll
-  for (int c = 0; c < 16; ++c) {
-    const double piv = lane_value(r[c], c);
-    double inv = 1.0;
-    if (piv > 0.0) inv = rsqrt_f64(piv);
-    else if (lane == 0) *bad = 1;
-    const double d = piv > 0.0 ? piv * inv : 1.0;
-    const double l = (row > c) ? r[c] * inv : (row == c ? d : 0.0);
-    r[c] = l;
-#pragma unroll
-    for (int j = c + 1; j < 16; ++j) {
-      const double lj = lane_value(l, j);
-      if (row >= j) r[j] -= l * lj;
-    }
-  }
+  for (int j = 0; j < 16; ++j) r[j] = T[k0 + row][k0 + j];
+  bool ok = true;
+  double myinv = 1.0;
+  chol_column<0>(r, row, ok, myinv);
   if (lane < 16) {
 #pragma unroll
-    for (int j = 0; j < 16; ++j) D[k0 + row][k0 + j] = (j <= row) ? r[j] : 0.0;
+    for (int j = 0; j < 16; ++j) {
+      const double v = (j <= row) ? r[j] : 0.0;
+      T[k0 + row][k0 + j] = v;
+      Lkk[row][j] = v;
+    }
+    rinv[k0 + row] = myinv;
   }
+  if (!ok && lane == 0) *bad = 1;
 }
 
-// Rows i (one per thread, i in [i_begin, 64)) of the 16-column block k0:
-// X[i][k0..k0+15] <- X[i][k0..] * L^-T with L = D[k0.., k0..] (lower, LDS).
-__device__ __forceinline__ void trsm16_rows(double (*X)[TL], const double (*L)[TL], int k0, int i) {
+// Row r of the 16-column block k0: T[r][k0..] <- T[r][k0..] L_kk^-T.
+__device__ __forceinline__ void trsm16_row(double (*T)[TR], int r, int k0, const double (*Lkk)[16],
+                                           const double* rinv) {
   double x[16];
 #pragma unroll
-  for (int c = 0; c < 16; ++c) x[c] = X[i][k0 + c];
+  for (int c = 0; c < 16; ++c) x[c] = T[r][k0 + c];
 #pragma unroll
   for (int c = 0; c < 16; ++c) {
     double v = x[c];
 #pragma unroll
-    for (int d = 0; d < c; ++d) v -= x[d] * L[k0 + c][k0 + d];
-    x[c] = v * (1.0 / L[k0 + c][k0 + c]);
+    for (int d = 0; d < c; ++d) v -= x[d] * Lkk[c][d];
+    x[c] = v * rinv[k0 + c];
   }
 #pragma unroll
-  for (int c = 0; c < 16; ++c) X[i][k0 + c] = x[c];
+  for (int c = 0; c < 16; ++c) T[r][k0 + c] = x[c];
 }
 
-// acc (one 16 x 16 block) += P[rows rb..][k0..k0+K) * Q[rows cb..][k0..)^T from
-// row-major LDS tiles; result element v is (row rb + lane/16 + 4v, col cb + lane%16).
-__device__ __forceinline__ v4d mma16_rowmajor(const double (*P)[TL], int rb, const double (*Q)[TL], int cb,
-                                              int k0, int K, v4d acc) {
-  const int lane = threadIdx.x & 63;
-  for (int k = 0; k < K; k += 4) {
-    const double a = P[rb + (lane & 15)][k0 + k + (lane >> 4)];
-    const double b = Q[cb + (lane & 15)][k0 + k + (lane >> 4)];
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
-  }
-  return acc;
-}
-
-// Blocked 64 x 64 Cholesky of the lower triangle of D (row-major LDS) in place.
-__device__ void chol64(double (*D)[TL], int* bad) {
-  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
-  for (int kb = 0; kb < 4; ++kb) {
-    const int k0 = 16 * kb;
-    __syncthreads();
-    if (w == 0) chol16_wave(D, k0, bad);
-    __syncthreads();
-    const int nrow = 48 - k0;
-    if (t < nrow) trsm16_rows(D, D, k0, k0 + 16 + t);
-    __syncthreads();
-    // trailing update of the lower 16 x 16 blocks (bi >= bj) right of k0 + 16
-    const int nb = 3 - kb;
-    int blk = 0;
-    for (int bi = 0; bi < nb; ++bi)
-      for (int bj = 0; bj <= bi; ++bj, ++blk) {
-        if ((blk & 3) != w) continue;
-        const int rb = k0 + 16 + 16 * bi, cb = k0 + 16 + 16 * bj;
-        v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
-        acc = mma16_rowmajor(D, rb, D, cb, k0, 16, acc);
+// Stage a 64 x 64 column-major global tile into LDS rows T[r][c] (row stride TR).
+__device__ __forceinline__ void stage_panel(double (*T)[TR], const double* g, long long ld) {
+  double v[16];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) D[rb + (lane >> 4) + 4 * v][cb + (lane & 15)] -= acc[v];
-      }
+  for (int s2 = 0; s2 < 16; ++s2) {
+    const int e = threadIdx.x + 256 * s2, r = e & 63, c = e >> 6;
+    v[s2] = g[r + (long long)c * ld];
   }
-  __syncthreads();
-  // zero the strict upper triangle
-  for (int e = t; e < 64 * 64; e += 256) {
-    const int r = e & 63, c = e >> 6;
-    if (c > r) D[r][c] = 0.0;
+#pragma unroll
+  for (int s2 = 0; s2 < 16; ++s2) {
+    const int e = threadIdx.x + 256 * s2, r = e & 63, c = e >> 6;
+    T[r][c] = v[s2];
   }
-  __syncthreads();
 }
 
-// X = Bt * L^-T (64 x 64, row-major LDS, overwritten), L lower (row-major LDS).
-__device__ void trsm64(double (*Bt)[TL], const double (*L)[TL]) {
-  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
-  for (int kb = 0; kb < 4; ++kb) {
-    const int k0 = 16 * kb;
-    if (kb > 0) {
-      // Bt[:, k0..k0+16) -= X[:, 0..k0) L[k0..k0+16, 0..k0)^T ; wave w owns rows 16w..
-      v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
-      acc = mma16_rowmajor(Bt, 16 * w, L, k0, 0, k0, acc);
+// 16 x 16 blocks of the update with column ph-1 inside a panel: 0..9 are the
+// lower blocks of D (row block bi, column block bj <= bi), 10..25 the blocks of B.
+__device__ __forceinline__ void panel_update_block(int b, int& bi, int& bj, bool& of_b) {
+  if (b < 10) {
+    bi = (b >= 1) + (b >= 3) + (b >= 6);
+    bj = b - bi * (bi + 1) / 2;
+    of_b = false;
+  } else {
+    bi = 4 + ((b - 10) >> 2);
+    bj = (b - 10) & 3;
+    of_b = true;
+  }
+}
+
+// Blocks of the in-panel update after column step kb: the lower blocks of D to
+// the right of it, then the blocks of B in those columns.
+__device__ __forceinline__ void panel_trail_block(int b, int kb, int& bi, int& bj) {
+  const int m = 3 - kb, ndb = m * (m + 1) / 2;
+  if (b < ndb) {
+    bi = (b >= 1) + (b >= 3);
+    bj = b - bi * (bi + 1) / 2;
+    bi += kb + 1;
+    bj += kb + 1;
+  } else {
+    bi = 4 + (b - ndb) / m;
+    bj = kb + 1 + (b - ndb) % m;
+  }
+}
+
+// X = L^-1 for the lower 64 x 64 factor in T rows 0..63, written to X (rows
+// 64..127 of the panel array, unused by the diagonal workgroup).  Diagonal
+// 16-blocks by forward substitution (wave w inverts block w, lane j a column),
+// then the blocks at distance d = 1..3 below the diagonal:
+//   X_ij = -X_ii sum_{k=j}^{i-1} L_ik X_kj.
+__device__ void invert_lower64(double (*T)[TR], double (*X)[TR], const double* rinv, double (*Z)[16][17]) {
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63, cl = lane & 15, kq = lane >> 4;
+  {
+    const int b0 = 16 * w, j = cl;
+    double x[16];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) Bt[16 * w + (lane >> 4) + 4 * v][k0 + (lane & 15)] -= acc[v];
+    for (int i = 0; i < 16; ++i) {
+      double v = (i == j) ? 1.0 : 0.0;
+#pragma unroll
+      for (int k = 0; k < i; ++k) v -= T[b0 + i][b0 + k] * x[k];
+      x[i] = v * rinv[b0 + i];
     }
-    __syncthreads();
-    if (t < 64) trsm16_rows(Bt, L, k0, t);
+    if (lane < 16) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) X[b0 + i][b0 + j] = x[i];
+    }
+  }
+  __syncthreads();
+  for (int d = 1; d < 4; ++d) {
+    const int j = w, i = w + d;
+    if (i < 4) {
+      v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+      for (int k = j; k < i; ++k)
+#pragma unroll
+        for (int s2 = 0; s2 < 16; s2 += 4)
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(T[16 * i + cl][16 * k + s2 + kq], X[16 * k + s2 + kq][16 * j + cl],
+                                                     acc, 0, 0, 0);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Z[w][kq + 4 * v][cl] = acc[v];
+      // Z is written and read by the same wave only
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      __builtin_amdgcn_wave_barrier();
+      acc = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s2 = 0; s2 < 16; s2 += 4)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(X[16 * i + cl][16 * i + s2 + kq], Z[w][s2 + kq][cl], acc, 0, 0, 0);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) X[16 * i + kq + 4 * v][16 * j + cl] = -acc[v];
+    }
     __syncthreads();
   }
 }
@@ -385,122 +441,166 @@ __global__ __launch_bounds__(256) void k_syrk(SysPlan p, const double* B, int R2
     for (int v = 0; v < 4; ++v) C[acc_col(blk) + (long long)acc_row(v) * p.lds] -= acc[blk][v];
 }
 
-// Phase ph of the tiled Cholesky.  Blocks [0, Tt - ph + 1): panel row tiles
-// i = ph + blk (the last one being the right-hand-side row); each applies the
-// update of column ph-1 to its tile and to the diagonal tile, factors the
-// diagonal tile and solves its tile.  Remaining blocks: trailing tiles
-// (i, j), ph < j <= i <= Tt, j < Tt, receive the update of column ph-1.
-__global__ __launch_bounds__(256) void k_chol_phase(SysPlan p, int ph, double* St, double* Ld,
-                                                    int* bad, const int* stop) {
+// Phase ph of the tiled Cholesky.  Blocks [0, Tt - ph + 1) are the panel row
+// tiles i = ph + blk (the last one is the right-hand-side row).  Each applies
+// the update of column ph-1 to the diagonal tile D and to its tile B, then
+// factors [D; B] in LDS.  Block 0 (i = ph, no B) writes L(ph, ph) to Ld and
+// L(ph, ph)^-1 (row-major) to Li.  Every diagonal-tile copy is read from St,
+// which this launch never writes.  The remaining blocks are the trailing tiles
+// (i, j), ph < j <= i <= Tt, j < Tt, which receive the update of column ph-1.
+// Their MFMA operands load straight from global memory into registers, so the
+// launch needs about 79 KB of LDS and two workgroups fit on a CU.
+__global__ __launch_bounds__(256, 2) void k_chol_phase(SysPlan p, int ph, double* St, double* Ld,
+                                                       double* Li, int* bad, const int* stop) {
   if (stopped(stop)) return;
-  __shared__ double D[64][TL];   // D[row][col]
-  __shared__ double Bt[64][TL];  // Bt[row][col]
-  __shared__ double La[64][TL];  // staged L(ph, ph-1), [col][row]
-  __shared__ double Lb[64][TL];  // staged L(i, ph-1),  [col][row]
+  __shared__ double T[128][TR];
+  __shared__ __align__(16) double Lkk[16][16];
+  __shared__ double rinv[64];
+  __shared__ double Z[4][16][17];
   const int npanel = p.Tt - ph + 1;
   const long long lds = p.lds;
-  const int t = threadIdx.x;
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+  const int cl = lane & 15, kq = lane >> 4;
   if ((int)blockIdx.x < npanel) {
     const int i = ph + blockIdx.x;
+    const bool hb = (i != ph);
     const double* Dg = St + ph * 64 + (long long)ph * 64 * lds;
     double* Bg = St + i * 64 + (long long)ph * 64 * lds;
-    stage_rowmajor(D, Dg, lds);
-    if (i != ph) stage_rowmajor(Bt, Bg, lds);
-    if (ph > 0) {
-      stage(La, St + ph * 64 + (long long)(ph - 1) * 64 * lds, lds);
-      if (i != ph) stage(Lb, St + i * 64 + (long long)(ph - 1) * 64 * lds, lds);
-    }
+    stage_panel(T, Dg, lds);
+    if (hb) stage_panel(T + 64, Bg, lds);
     __syncthreads();
     if (ph > 0) {
-      v4d acc[4];
-      zero_acc(acc);
-      mma_lds(La, La, acc);
+      const double* La = St + ph * 64 + (long long)(ph - 1) * 64 * lds;  // L(ph, ph-1)
+      const double* Lb = St + i * 64 + (long long)(ph - 1) * 64 * lds;   // L(i, ph-1)
+      const int nblk = 10 + (hb ? 16 : 0);
+      for (int b = w; b < nblk; b += 4) {
+        int bi, bj;
+        bool of_b;
+        panel_update_block(b, bi, bj, of_b);
+        const double* P = of_b ? Lb : La;
+        double av[16], bv[16];
 #pragma unroll
-      for (int blk = 0; blk < 4; ++blk)
+        for (int s2 = 0; s2 < 16; ++s2) {
+          av[s2] = P[((bi & 3) * 16 + cl) + (long long)(4 * s2 + kq) * lds];
+          bv[s2] = La[(16 * bj + cl) + (long long)(4 * s2 + kq) * lds];
+        }
+        v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int v = 0; v < 4; ++v) D[acc_row(v)][acc_col(blk)] -= acc[blk][v];
-      if (i != ph) {
-        zero_acc(acc);
-        mma_lds(La, Lb, acc);  // (La Lb^T)[ra][cb] = (Lb La^T)[cb][ra]
+        for (int s2 = 0; s2 < 16; ++s2) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s2], bv[s2], acc, 0, 0, 0);
 #pragma unroll
-        for (int blk = 0; blk < 4; ++blk)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) Bt[acc_col(blk)][acc_row(v)] -= acc[blk][v];
+        for (int v = 0; v < 4; ++v) T[16 * bi + kq + 4 * v][16 * bj + cl] -= acc[v];
       }
     }
-    chol64(D, bad);
-    if (i == ph) {
-      // The factored tile goes to Ld, never back to St: the other panel workgroups of
-      // this launch stage the unfactored tile (ph, ph) from St and may start late.
+    __syncthreads();
+    for (int kb = 0; kb < 4; ++kb) {
+      const int k0 = 16 * kb;
+      if (w == 0) chol16(T, k0, bad, Lkk, rinv);
+      __syncthreads();
+      const int nd = 48 - k0;
+      const int nr = nd + (hb ? 64 : 0);
+      if (t < nr) trsm16_row(T, t < nd ? k0 + 16 + t : 64 + (t - nd), k0, Lkk, rinv);
+      __syncthreads();
+      const int m = 3 - kb;
+      const int nblk = m * (m + 1) / 2 + (hb ? 4 * m : 0);
+      for (int b = w; b < nblk; b += 4) {
+        int bi, bj;
+        panel_trail_block(b, kb, bi, bj);
+        v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < 16; k += 4)
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(T[16 * bi + cl][k0 + k + kq], T[16 * bj + cl][k0 + k + kq], acc,
+                                                     0, 0, 0);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) T[16 * bi + kq + 4 * v][16 * bj + cl] -= acc[v];
+      }
+      __syncthreads();
+    }
+    if (!hb) {
+      invert_lower64(T, T + 64, rinv, Z);
       double* Lg = Ld + (long long)ph * 64 * 64;
+      double* Xg = Li + (long long)ph * 64 * 64;
       for (int e = t; e < 64 * 64; e += 256) {
         const int r = e & 63, c = e >> 6;
-        Lg[r + c * 64] = (c <= r) ? D[r][c] : 0.0;
+        Lg[r + c * 64] = (c <= r) ? T[r][c] : 0.0;
+        Xg[c + r * 64] = (c <= r) ? T[64 + r][c] : 0.0;
       }
     } else {
-      trsm64(Bt, D);
       for (int e = t; e < 64 * 64; e += 256) {
         const int r = e & 63, c = e >> 6;
-        Bg[r + c * lds] = Bt[r][c];
+        Bg[r + c * lds] = T[64 + r][c];
       }
     }
     return;
   }
-  // trailing update with column ph - 1
   if (ph == 0) return;
   long long id = (long long)blockIdx.x - npanel;
   int j = ph + 1;
-  while (id >= (long long)(p.Tt - j + 1)) { id -= (p.Tt - j + 1); ++j; }
+  while (id >= (long long)(p.Tt - j + 1)) {
+    id -= (p.Tt - j + 1);
+    ++j;
+  }
   const int i = j + (int)id;
-  stage(La, St + i * 64 + (long long)(ph - 1) * 64 * lds, lds);  // L(i, ph-1)
-  stage(Lb, St + j * 64 + (long long)(ph - 1) * 64 * lds, lds);  // L(j, ph-1)
-  __syncthreads();
+  // C(i, j) -= L(i, ph-1) L(j, ph-1)^T, computed in 16-column strips of C^T:
+  // wave w forms (L(j) L(i)^T)[16w.., :] = C[:, 16w..]^T.
+  const double* Ltj = St + j * 64 + (long long)(ph - 1) * 64 * lds;
+  const double* Lti = St + i * 64 + (long long)(ph - 1) * 64 * lds;
+  double* C = St + i * 64 + (long long)j * 64 * lds;
   v4d acc[4];
   zero_acc(acc);
-  mma_lds(Lb, La, acc);  // (Lj Li^T)[rj][ci]
-  double* C = St + i * 64 + (long long)j * 64 * lds;
+  for (int h = 0; h < 2; ++h) {  // two halves of k, operands loaded ahead of each half
+    double av[8], bv[4][8];
+#pragma unroll
+    for (int s2 = 0; s2 < 8; ++s2) {
+      const long long ko = (long long)(32 * h + 4 * s2 + kq) * lds;
+      av[s2] = Ltj[(16 * w + cl) + ko];
+#pragma unroll
+      for (int blk = 0; blk < 4; ++blk) bv[blk][s2] = Lti[(16 * blk + cl) + ko];
+    }
+#pragma unroll
+    for (int s2 = 0; s2 < 8; ++s2)
+#pragma unroll
+      for (int blk = 0; blk < 4; ++blk) acc[blk] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s2], bv[blk][s2], acc[blk], 0, 0, 0);
+  }
+  // acc[blk][v] = (L(j) L(i)^T)[16w + kq + 4v][16blk + cl] = C[16blk + cl][16w + kq + 4v]
 #pragma unroll
   for (int blk = 0; blk < 4; ++blk)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) C[acc_col(blk) + (long long)acc_row(v) * lds] -= acc[blk][v];
+    for (int v = 0; v < 4; ++v) C[(16 * blk + cl) + (long long)(16 * w + kq + 4 * v) * lds] -= acc[blk][v];
 }
 
-// Backward substitution, phase k (descending): every block solves
-// L_kk^T y_k = u_k (u in the RHS row); block k stores y_k, block j < k
-// updates u_j -= L_kj^T y_k.
-__global__ __launch_bounds__(256) void k_bsolve(SysPlan p, int k, double* St, const double* Ld,
-                                                double* yt, const int* stop) {
+// Backward substitution, phase k (descending).  Every block forms
+// y_k = L_kk^-T u_k from the inverse tile (u_k is the right-hand-side row of
+// tile column k); block k stores y_k and block j < k updates u_j -= L_kj^T y_k.
+__global__ __launch_bounds__(256) void k_bsolve(SysPlan p, int k, double* St, const double* Li, double* yt,
+                                                const int* stop) {
   if (stopped(stop)) return;
-  __shared__ double L[64][TL];   // L[row][col] of the diagonal tile
   __shared__ double Lt[64][TL];  // staged L(k, j), [col][row]
+  __shared__ double u[64];
   __shared__ double ys[64];
   __shared__ double part[4][64];
   const long long lds = p.lds;
-  const int t = threadIdx.x, j = blockIdx.x;
-  stage_rowmajor(L, Ld + (long long)k * 64 * 64, 64);
+  const int t = threadIdx.x, j = blockIdx.x, c = t & 63, g = t >> 6;
+  if (t < 64) u[t] = St[p.ntp + (long long)(k * 64 + t) * lds];
   if (j != k) stage(Lt, St + k * 64 + (long long)j * 64 * lds, lds);
   __syncthreads();
-  if (t < 64) {
-    // lane c holds u_k[c]; sweep c = 63..0 (L_kk^T y = u)
-    double val = St[p.ntp + (long long)(k * 64 + t) * lds];
-    const double rinv = 1.0 / L[t][t];
-    double y = 0.0;
+  // y_k[c] = sum_r X[r][c] u[r], X = L_kk^-1 stored row-major
+  const double* X = Li + (long long)k * 64 * 64;
+  double acc = 0.0;
 #pragma unroll
-    for (int c = 63; c >= 0; --c) {
-      const double yc = lane_value(val * rinv, c);
-      if (t == c) y = yc;
-      if (t < c) val -= L[c][t] * yc;
-    }
-    ys[t] = y;
+  for (int s2 = 0; s2 < 16; ++s2) {
+    const int r = g + 4 * s2;
+    acc += X[r * 64 + c] * u[r];
   }
+  part[g][c] = acc;
+  __syncthreads();
+  if (t < 64) ys[t] = part[0][t] + part[1][t] + part[2][t] + part[3][t];
   __syncthreads();
   if (j == k) {
     if (t < 64) yt[k * 64 + t] = ys[t];
     return;
   }
   // u_j[c] -= sum_r L(k, j)[r][c] y_k[r]
-  const int c = t & 63, g = t >> 6;
-  double acc = 0.0;
+  acc = 0.0;
 #pragma unroll
   for (int s2 = 0; s2 < 16; ++s2) {
     const int r = g + 4 * s2;
@@ -566,9 +666,9 @@ hipError_t launch_sys_factor_solve(const Shape& s, const SysPlan& p, const Small
     long long nupd = 0;
     if (ph > 0)
       for (int j = ph + 1; j < p.Tt; ++j) nupd += p.Tt - j + 1;
-    k_chol_phase<<<(unsigned)(npanel + nupd), 256, 0, st>>>(p, ph, y.St, y.Ld, singular, stop);
+    k_chol_phase<<<(unsigned)(npanel + nupd), 256, 0, st>>>(p, ph, y.St, y.Ld, y.Li, singular, stop);
   }
-  for (int k = p.Tt - 1; k >= 0; --k) k_bsolve<<<k + 1, 256, 0, st>>>(p, k, y.St, y.Ld, y.yt, stop);
+  for (int k = p.Tt - 1; k >= 0; --k) k_bsolve<<<k + 1, 256, 0, st>>>(p, k, y.St, y.Li, y.yt, stop);
   k_y0<<<(p.R2 + 3) / 4, 256, 0, st>>>(p, y.B, b.z, y.yt, b.y, stop);
   return hipGetLastError();
 }
