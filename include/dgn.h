@@ -21,17 +21,24 @@
  *   host thread / stream.
  * - Every call returns a dgn_status; on failure dgn_last_error() gives a
  *   readable message.  Shapes are validated before any work is enqueued:
- *   order in [3, DGN_MAX_ORDER], every I_n >= 1, 1 <= R <= DGN_MAX_RANK,
- *   mu > 0 (H = J^T J is singular, so mu = 0 is rejected), non-NULL pointers.
+ *   order in [3, DGN_MAX_ORDER], every I_n >= 1, 1 <= R <= DGN_MAX_RANK
+ *   (R <= DGN_MAX_RANK_COMPLEX for C64/C128 tensors), mu > 0 (H = J^T J is
+ *   singular, so mu = 0 is rejected), non-NULL pointers.
  *
  * Arithmetic
  * ----------
  * The tensor pass (MTTKRP and the residual) runs in the tensor's dtype:
  * F64 -> FP64; F32 -> FP32 MFMA with FP32 accumulation; BF16 -> BF16 MFMA
- * with FP32 accumulation; C128 -> FP64 complex; C64 -> FP32 complex.
- * Partial sums are reduced in FP64.  Everything after the tensor pass (Gram
- * and Hadamard products, the damped inverses, the NR^2 system and the factor
- * update) is FP64 (complex FP64).
+ * with FP32 accumulation; C128 and C64 -> FP64 complex (C64 entries are read
+ * as complex64 and widened).  Partial sums are reduced in FP64.  Everything
+ * after the tensor pass (Gram and Hadamard products, the damped inverses, the
+ * NR^2 system and the factor update) is FP64 (complex FP64).
+ *
+ * Complex tensors (Section 5): factors are complex128, stored as interleaved
+ * (re, im) pairs in the same column-major I_n x R layout.  The step always
+ * uses the residual form of the tensor pass, and the Hermitian positive
+ * definite NR^2 system is solved through its real symmetric embedding
+ * [[Re S, -Im S], [Im S, Re S]] by the same tiled Cholesky as the real case.
  */
 #ifndef DGN_H
 #define DGN_H
@@ -45,6 +52,7 @@ extern "C" {
 
 #define DGN_MAX_ORDER 8
 #define DGN_MAX_RANK 64
+#define DGN_MAX_RANK_COMPLEX 32
 
 typedef enum dgn_status {
   DGN_OK = 0,
@@ -154,8 +162,9 @@ dgn_status dgn_workspace_size(const dgn_tensor* Y, int32_t R, const dgn_opts* op
  * every n, with conjugated factors for complex tensors (Theorem 5.4), in one
  * pass over Y.  A: N device pointers to I_n x R FP64 (C128) factors; the pass
  * casts them to the tensor's compute type.  M: N device pointers to I_n x R
- * FP64 (C128) outputs.  inner (host, may be NULL): <Y, Y_hat> = sum(A_n * M_n)
- * (real part for complex).  Synchronises when inner != NULL. */
+ * FP64 (C128) outputs.  inner (host, may be NULL): <Y, Y_hat> = sum(A_1 * M_1);
+ * for complex tensors Re sum(conj(A_1) * M_1) = Re sum(y conj(y_hat)).
+ * Synchronises when inner != NULL. */
 dgn_status dgn_mttkrp(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, const void* const* A,
                       void* const* M, double* inner, void* stream);
 

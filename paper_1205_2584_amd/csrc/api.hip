@@ -63,6 +63,7 @@ constexpr int kNormParts = 1024;
 struct Work {
   Shape s;
   YType ymaster;
+  int cs = 1;      // doubles per element of the factor / R x R arrays: 1 real, 2 complex
   PassPlan pp;
   SysPlan sp;
   double *A, *Ac, *M, *Mc;
@@ -79,6 +80,8 @@ bool dtype_ok(int dt, YType* yt) {
     case DGN_F64: *yt = YType::F64; return true;
     case DGN_F32: *yt = YType::F32; return true;
     case DGN_BF16: *yt = YType::BF16; return true;
+    case DGN_C64: *yt = YType::C64; return true;
+    case DGN_C128: *yt = YType::C128; return true;
     default: return false;
   }
 }
@@ -95,7 +98,9 @@ dgn_status check_shape(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, Shape* s, Y
     return set_err(ctx, DGN_EINVAL, "tensor order must be in [3, 8]");
   if (R < 1 || R > DGN_MAX_RANK) return set_err(ctx, DGN_EINVAL, "rank must be in [1, 64]");
   if (!dtype_ok(Y->dtype, yt))
-    return set_err(ctx, DGN_EINVAL, "unsupported tensor dtype (real F64, F32, BF16 are built)");
+    return set_err(ctx, DGN_EINVAL, "unsupported tensor dtype");
+  if ((*yt == YType::C64 || *yt == YType::C128) && R > kMaxRankC)
+    return set_err(ctx, DGN_EINVAL, "complex tensors need rank <= 32");
   s->N = Y->order;
   s->R = R;
   s->T = 0;
@@ -118,11 +123,26 @@ dgn_status check_shape(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, Shape* s, Y
   return DGN_OK;
 }
 
+bool is_complex(YType t) { return t == YType::C64 || t == YType::C128; }
+
+// Pass and system plans for the tensor's type (complex: 32-tiles, embedded system).
+void plan(Work& w) {
+  w.cs = is_complex(w.ymaster) ? 2 : 1;
+  if (w.cs == 2) {
+    w.pp = plan_pass_c(w.s);
+    w.sp = plan_sys_c(w.s);
+  } else {
+    w.pp = plan_pass(w.s, w.ymaster);
+    w.sp = plan_sys(w.s);
+  }
+}
+
 void carve(Arena& ar, Work& w, bool with_system) {
   const Shape& s = w.s;
-  const size_t TR = (size_t)s.T * s.R, NR2 = (size_t)s.N * s.R * s.R;
+  const size_t cs = (size_t)w.cs;
+  const size_t TR = (size_t)s.T * s.R * cs, NR2 = (size_t)s.N * s.R * s.R * cs;
   const int ch = row_chunks(s);
-  const size_t stride = (size_t)s.R * s.R + 4;
+  const size_t stride = (size_t)s.R * s.R * cs + 4;
   w.state = ar.take<FitState>(1);
   w.flags = ar.take<int>(64);
   w.scr = ar.take<double>(kNormParts + 64);
@@ -148,7 +168,7 @@ void carve(Arena& ar, Work& w, bool with_system) {
   b.u = ar.take<double>(NR2);
   b.f = ar.take<double>(NR2);
   b.Q = ar.take<double>(NR2);
-  b.Tnm = with_system ? ar.take<double>((size_t)s.N * s.N * s.R * s.R * s.R) : nullptr;
+  b.Tnm = with_system ? ar.take<double>((size_t)s.N * s.N * s.R * s.R * s.R * cs) : nullptr;
   const PassPlan& p = w.pp;
   const size_t tcb = 8;  // sized for the widest compute type
   w.pb.m0part = ar.take<char>(p.m0_elems * tcb);
@@ -172,8 +192,7 @@ void carve(Arena& ar, Work& w, bool with_system) {
 dgn_status prepare(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, bool with_system, Work& w) {
   dgn_status st = check_shape(ctx, Y, R, &w.s, &w.ymaster);
   if (st != DGN_OK) return st;
-  w.pp = plan_pass(w.s, w.ymaster);
-  w.sp = plan_sys(w.s);
+  plan(w);
   Arena ar{ctx ? ctx->ws : nullptr, ctx ? ctx->ws_size : (size_t)-1};
   carve(ar, w, with_system);
   if (ar.fail) {
@@ -196,8 +215,8 @@ dgn_status hip_fail(dgn_ctx* ctx, hipError_t e, const char* where) {
 
 hipError_t copy_factors_in(const Work& w, const void* const* A, double* dst, hipStream_t st) {
   for (int n = 0; n < w.s.N; ++n) {
-    hipError_t e = hipMemcpyAsync(dst + (size_t)w.s.off[n] * w.s.R, A[n],
-                                  sizeof(double) * w.s.I[n] * w.s.R, hipMemcpyDeviceToDevice, st);
+    hipError_t e = hipMemcpyAsync(dst + (size_t)w.s.off[n] * w.s.R * w.cs, A[n],
+                                  sizeof(double) * w.cs * w.s.I[n] * w.s.R, hipMemcpyDeviceToDevice, st);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -205,8 +224,8 @@ hipError_t copy_factors_in(const Work& w, const void* const* A, double* dst, hip
 
 hipError_t copy_factors_out(const Work& w, const double* src, void* const* A, hipStream_t st) {
   for (int n = 0; n < w.s.N; ++n) {
-    hipError_t e = hipMemcpyAsync(A[n], src + (size_t)w.s.off[n] * w.s.R,
-                                  sizeof(double) * w.s.I[n] * w.s.R, hipMemcpyDeviceToDevice, st);
+    hipError_t e = hipMemcpyAsync(A[n], src + (size_t)w.s.off[n] * w.s.R * w.cs,
+                                  sizeof(double) * w.cs * w.s.I[n] * w.s.R, hipMemcpyDeviceToDevice, st);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -218,8 +237,27 @@ hipError_t mark(hipEvent_t* ev, int k, hipStream_t st) {
   return ev ? hipEventRecord(ev[k], st) : hipSuccess;
 }
 
+// Complex tensors (Section 5): complex small kernels around the real tiled
+// Cholesky of the embedded trailing system.
+hipError_t enqueue_step_c(Work& w, bool resid, double mu_host, FitState* state, int* singular,
+                          const int* stop, hipStream_t st, hipEvent_t* ev) {
+  const Shape& s = w.s;
+  hipError_t e;
+  if ((e = mark(ev, 0, st)) != hipSuccess) return e;
+  if ((e = launch_small_pre_c(s, w.A, w.M, resid, mu_host, state, w.sb, singular, stop, st)) != hipSuccess) return e;
+  if ((e = mark(ev, 1, st)) != hipSuccess) return e;
+  if ((e = launch_sys_fill(w.sp, w.sy, stop, st)) != hipSuccess) return e;
+  if ((e = launch_subblock_c(s, w.sp, w.sb, w.sy, stop, st)) != hipSuccess) return e;
+  if ((e = launch_sys_rhs_syrk(w.sp, w.sb.z, w.sy, stop, st)) != hipSuccess) return e;
+  if ((e = mark(ev, 2, st)) != hipSuccess) return e;
+  if ((e = launch_sys_factor_solve(s, w.sp, w.sb, w.sy, singular, stop, st)) != hipSuccess) return e;
+  if ((e = mark(ev, 3, st)) != hipSuccess) return e;
+  return launch_small_post_c(s, w.A, w.Ac, w.sb, mu_host, state, stop, st);
+}
+
 hipError_t enqueue_step(Work& w, bool resid, double mu_host, FitState* state, int* singular,
                         const int* stop, hipStream_t st, hipEvent_t* ev = nullptr) {
+  if (w.cs == 2) return enqueue_step_c(w, resid, mu_host, state, singular, stop, st, ev);
   const Shape& s = w.s;
   hipError_t e;
   if ((e = mark(ev, 0, st)) != hipSuccess) return e;
@@ -246,6 +284,25 @@ struct PassSel {
 PassSel pass_tensor(const Work& w, const dgn_tensor* Y, const dgn_opts& o, bool resid) {
   if (!resid && w.ymaster == YType::F32 && o.y_bf16) return PassSel{o.y_bf16, YType::BF16};
   return PassSel{Y->data, w.ymaster};
+}
+
+hipError_t run_pass(const Work& w, const PassSel& ps, const double* A, bool resid, double* M, double* e2,
+                    const int* stop, hipStream_t st) {
+  if (w.cs == 2)
+    return launch_tensor_pass_c(w.s, ps.yt == YType::C128, ps.data, A, resid, w.pp, w.pb, M, e2, stop, st);
+  return launch_tensor_pass(w.s, ps.yt, ps.data, A, resid, w.pp, w.pb, M, e2, stop, st);
+}
+
+// sum |y|^2; a complex tensor is summed as 2J real values.
+hipError_t run_norm2(const PassSel& ps, long long J, double* part, double* out, hipStream_t st) {
+  if (ps.yt == YType::C128) return launch_norm2(YType::F64, ps.data, 2 * J, part, kNormParts, out, st);
+  if (ps.yt == YType::C64) return launch_norm2(YType::F32, ps.data, 2 * J, part, kNormParts, out, st);
+  return launch_norm2(ps.yt, ps.data, J, part, kNormParts, out, st);
+}
+
+hipError_t run_gram(const Work& w, const double* A, double* Cout, const int* stop, hipStream_t st) {
+  if (w.cs == 2) return launch_gram_c(w.s, A, w.sb, Cout, stop, st);
+  return launch_gram(w.s, A, w.sb, Cout, stop, st);
 }
 
 }  // namespace
@@ -306,8 +363,7 @@ dgn_status dgn_workspace_size(const dgn_tensor* Y, int32_t R, const dgn_opts* op
   Work w{};
   dgn_status st = check_shape(nullptr, Y, R, &w.s, &w.ymaster);
   if (st != DGN_OK) return st;
-  w.pp = plan_pass(w.s, w.ymaster);
-  w.sp = plan_sys(w.s);
+  plan(w);
   Arena ar{nullptr, (size_t)-1};
   carve(ar, w, true);
   *bytes = ar.used;
@@ -326,11 +382,11 @@ dgn_status dgn_mttkrp(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, const void* 
   hipStream_t st = (hipStream_t)stream;
   HIPCHK(hipSetDevice(ctx->device), "hipSetDevice");
   HIPCHK(copy_factors_in(w, A, w.A, st), "copy factors");
-  HIPCHK(launch_tensor_pass(w.s, w.ymaster, Y->data, w.A, false, w.pp, w.pb, w.M, nullptr, nullptr, st),
-         "tensor pass");
+  HIPCHK(run_pass(w, PassSel{Y->data, w.ymaster}, w.A, false, w.M, nullptr, nullptr, st), "tensor pass");
   HIPCHK(copy_factors_out(w, w.M, M, st), "copy MTTKRP");
   if (inner) {
-    HIPCHK(launch_inner(w.s, w.A, w.M, w.scr + 1026, st), "inner");
+    if (w.cs == 2) HIPCHK(launch_inner_c(w.s, w.A, w.M, w.scr + 1026, st), "inner");
+    else HIPCHK(launch_inner(w.s, w.A, w.M, w.scr + 1026, st), "inner");
     HIPCHK(hipMemcpyAsync(inner, w.scr + 1026, sizeof(double), hipMemcpyDeviceToHost, st), "copy inner");
     HIPCHK(hipStreamSynchronize(st), "sync");
   }
@@ -353,7 +409,7 @@ dgn_status dgn_step(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, const void* co
     if (!A_in[n] || !A_out[n]) return set_err(ctx, DGN_EINVAL, "NULL factor pointer");
   hipStream_t st = (hipStream_t)stream;
   HIPCHK(hipSetDevice(ctx->device), "hipSetDevice");
-  const bool resid = (w.ymaster == YType::F64) || o.resid_switch < 0;
+  const bool resid = (w.ymaster == YType::F64) || w.cs == 2 || o.resid_switch < 0;
   const PassSel ps = pass_tensor(w, Y, o, resid);
   const long long J = [&] { long long j = 1; for (int n = 0; n < w.s.N; ++n) j *= w.s.I[n]; return j; }();
   double* ynp = w.scr + 1028;
@@ -362,12 +418,12 @@ dgn_status dgn_step(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, const void* co
   double* out = w.scr + 1026;  // err2 old, new
   HIPCHK(hipMemsetAsync(w.flags, 0, 64 * sizeof(int), st), "memset");
   HIPCHK(copy_factors_in(w, A_in, w.A, st), "copy factors");
-  HIPCHK(launch_norm2(ps.yt, ps.data, J, w.scr, kNormParts, ynp, st), "norm");
-  HIPCHK(launch_gram(w.s, w.A, w.sb, w.sb.C, nullptr, st), "gram");
-  HIPCHK(launch_tensor_pass(w.s, ps.yt, ps.data, w.A, resid, w.pp, w.pb, w.M, e2a, nullptr, st), "pass");
+  HIPCHK(run_norm2(ps, J, w.scr, ynp, st), "norm");
+  HIPCHK(run_gram(w, w.A, w.sb.C, nullptr, st), "gram");
+  HIPCHK(run_pass(w, ps, w.A, resid, w.M, e2a, nullptr, st), "pass");
   HIPCHK(launch_err2(w.s, w.A, w.M, w.sb.C, resid, e2a, ynp, out, st), "err2");
   HIPCHK(enqueue_step(w, resid, mu, nullptr, w.flags, nullptr, st), "step");
-  HIPCHK(launch_tensor_pass(w.s, ps.yt, ps.data, w.Ac, resid, w.pp, w.pb, w.Mc, e2b, nullptr, st), "pass");
+  HIPCHK(run_pass(w, ps, w.Ac, resid, w.Mc, e2b, nullptr, st), "pass");
   HIPCHK(launch_err2(w.s, w.Ac, w.Mc, w.sb.Cc, resid, e2b, ynp, out + 1, st), "err2");
   HIPCHK(copy_factors_out(w, w.Ac, A_out, st), "copy out");
   double host[2] = {0, 0}, sc[4] = {0, 0, 0, 0};
@@ -409,7 +465,7 @@ dgn_status cp_fit(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, void* const* A, 
     if (!A[n]) return set_err(ctx, DGN_EINVAL, "NULL factor pointer");
   hipStream_t st = (hipStream_t)stream;
   HIPCHK(hipSetDevice(ctx->device), "hipSetDevice");
-  bool resid = (w.ymaster == YType::F64) || o.resid_switch < 0;
+  bool resid = (w.ymaster == YType::F64) || w.cs == 2 || o.resid_switch < 0;
   const bool can_switch = !resid && o.resid_switch > 0;
   PassSel ps = pass_tensor(w, Y, o, resid);
   const long long J = [&] { long long j = 1; for (int n = 0; n < w.s.N; ++n) j *= w.s.I[n]; return j; }();
@@ -424,11 +480,11 @@ dgn_status cp_fit(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, void* const* A, 
   double* e2c = w.scr + 1025;
   HIPCHK(hipMemcpyAsync(ds, &hs, sizeof hs, hipMemcpyHostToDevice, st), "state");
   HIPCHK(copy_factors_in(w, A, w.A, st), "copy factors");
-  HIPCHK(launch_norm2(w.ymaster, Y->data, J, w.scr, kNormParts, &ds->ynorm2, st), "norm");
-  HIPCHK(launch_norm2(ps.yt, ps.data, J, w.scr, kNormParts, &ds->ynorm2_pass, st), "norm");
-  HIPCHK(launch_gram(w.s, w.A, w.sb, w.sb.C, nullptr, st), "gram");
-  HIPCHK(launch_tensor_pass(w.s, ps.yt, ps.data, w.A, resid, w.pp, w.pb, w.M, e2, nullptr, st), "pass");
-  HIPCHK(launch_fit_init(w.s, w.A, w.M, w.sb.C, resid, e2, mu0, o.tau, ds, st), "init");
+  HIPCHK(run_norm2(PassSel{Y->data, w.ymaster}, J, w.scr, &ds->ynorm2, st), "norm");
+  HIPCHK(run_norm2(ps, J, w.scr, &ds->ynorm2_pass, st), "norm");
+  HIPCHK(run_gram(w, w.A, w.sb.C, nullptr, st), "gram");
+  HIPCHK(run_pass(w, ps, w.A, resid, w.M, e2, nullptr, st), "pass");
+  HIPCHK(launch_fit_init(w.s, w.A, w.M, w.sb.C, resid, e2, mu0, o.tau, ds, st, w.cs), "init");
   const int* stop = &ds->stop;
   const int EV = DGN_NUM_PHASES + 1;
   if (o.timing) {
@@ -446,10 +502,10 @@ dgn_status cp_fit(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, void* const* A, 
     hipEvent_t* ev = o.timing ? &ctx->events[(size_t)EV * t] : nullptr;
     HIPCHK(enqueue_step(w, resid, 0.0, ds, &ds->singular, stop, st, ev), "step");
     HIPCHK(mark(ev, 4, st), "event");
-    HIPCHK(launch_tensor_pass(w.s, ps.yt, ps.data, w.Ac, resid, w.pp, w.pb, w.Mc, e2c, stop, st), "pass");
+    HIPCHK(run_pass(w, ps, w.Ac, resid, w.Mc, e2c, stop, st), "pass");
     HIPCHK(mark(ev, 5, st), "event");
-    HIPCHK(launch_control(w.s, w.Ac, w.Mc, w.sb.Cc, resid, e2c, w.sb.scal, ds, t, st), "control");
-    HIPCHK(launch_commit(w.s, w.A, w.Ac, w.M, w.Mc, w.sb.C, w.sb.Cc, ds, t, st), "commit");
+    HIPCHK(launch_control(w.s, w.Ac, w.Mc, w.sb.Cc, resid, e2c, w.sb.scal, ds, t, st, w.cs), "control");
+    HIPCHK(launch_commit(w.s, w.A, w.Ac, w.M, w.Mc, w.sb.C, w.sb.Cc, ds, t, st, w.cs), "commit");
     HIPCHK(mark(ev, 6, st), "event");
     enq = t + 1;
     if ((t + 1) % o.poll_every == 0 || t + 1 == max_iters) {
@@ -459,7 +515,7 @@ dgn_status cp_fit(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, void* const* A, 
       if (can_switch && !resid && hs.accepted > 0 && fabs(hs.eps_prev - hs.eps) < o.resid_switch) {
         resid = true;
         ps = pass_tensor(w, Y, o, resid);
-        HIPCHK(launch_tensor_pass(w.s, ps.yt, ps.data, w.A, true, w.pp, w.pb, w.M, e2, stop, st), "pass");
+        HIPCHK(run_pass(w, ps, w.A, true, w.M, e2, stop, st), "pass");
         HIPCHK(launch_refresh(w.s, e2, ds, st), "refresh");
       }
     }

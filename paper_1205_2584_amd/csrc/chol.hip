@@ -657,6 +657,33 @@ hipError_t launch_sys_assemble(const Shape& s, const SysPlan& p, const SmallBuff
   return hipGetLastError();
 }
 
+hipError_t launch_sys_fill(const SysPlan& p, const SysBuffers& y, const int* stop, hipStream_t st) {
+  const int R2p = r2pad(p.R2);
+  const long long ntri = (long long)p.Tt * (p.Tt + 1) / 2 + p.Tt;
+  const long long nbblocks = ((long long)p.ntp * R2p + 255) / 256;
+  long long extra = nbblocks < 1024 ? nbblocks : 1024;
+  k_fill<<<(unsigned)(ntri + extra), 256, 0, st>>>(p, y.St, y.B, R2p, stop);
+  return hipGetLastError();
+}
+
+hipError_t launch_sys_rhs_syrk(const SysPlan& p, const double* z, const SysBuffers& y, const int* stop,
+                               hipStream_t st) {
+  const int R2p = r2pad(p.R2);
+  k_rhs<<<p.ntp / 64, 1024, 0, st>>>(p, y.B, z, y.St, stop);
+  k_syrk<<<(unsigned)((long long)p.Tt * (p.Tt + 1) / 2), 256, 0, st>>>(p, y.B, R2p, y.St, stop);
+  return hipGetLastError();
+}
+
+SysPlan plan_sys_c(const Shape& s) {
+  SysPlan p{};
+  p.R2 = 2 * s.R * s.R;
+  p.nt = 2 * (s.N - 1) * s.R * s.R;
+  p.ntp = ((p.nt + 63) / 64) * 64;
+  p.Tt = p.ntp / 64;
+  p.lds = p.ntp + 64;
+  return p;
+}
+
 hipError_t launch_sys_factor_solve(const Shape& s, const SysPlan& p, const SmallBuffers& b,
                                    const SysBuffers& y, int* singular, const int* stop,
                                    hipStream_t st) {

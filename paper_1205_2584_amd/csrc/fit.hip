@@ -35,7 +35,7 @@ __device__ double err2_of(const Shape& s, const double* A, const double* M, cons
 
 __global__ __launch_bounds__(256) void k_fit_init(Shape s, const double* A, const double* M,
                                                   const double* C, int resid, const double* e2,
-                                                  double mu0, double tau, FitState* st) {
+                                                  double mu0, double tau, FitState* st, int cs) {
   __shared__ double red[16];
   const double err2 = err2_of(s, A, M, C, resid, e2, st->ynorm2_pass, red);
   if (threadIdx.x == 0) {
@@ -47,7 +47,7 @@ __global__ __launch_bounds__(256) void k_fit_init(Shape s, const double* A, cons
         for (int r = 0; r < R; ++r) {
           double g = 1.0;
           for (int k = 0; k < s.N; ++k)
-            if (k != n) g *= C[(long long)k * R2 + r + r * R];
+            if (k != n) g *= C[cs * ((long long)k * R2 + r + r * R)];
           mx = g > mx ? g : mx;
         }
       mu = tau * mx;
@@ -96,7 +96,7 @@ __global__ __launch_bounds__(256) void k_inner(Shape s, const double* A, const d
 
 __global__ __launch_bounds__(256) void k_control(Shape s, const double* Ac, const double* Mc,
                                                  const double* Cc, int resid, const double* e2,
-                                                 const double* scal, FitState* st, int trial) {
+                                                 const double* scal, FitState* st, int trial, int cs) {
   __shared__ double red[16];
   __shared__ int accept_s;
   if (st->stop) return;
@@ -156,7 +156,7 @@ __global__ __launch_bounds__(256) void k_control(Shape s, const double* Ac, cons
     double lam = 1.0;
     bool ok = true;
     for (int n = 0; n < N; ++n) {
-      nr[n] = sqrt(Cc[(long long)n * R2 + r + r * R]);
+      nr[n] = sqrt(Cc[cs * ((long long)n * R2 + r + r * R)]);
       ok = ok && nr[n] > 0.0;
       lam *= nr[n];
     }
@@ -181,9 +181,10 @@ __global__ __launch_bounds__(256) void k_control(Shape s, const double* Ac, cons
 }
 
 // Apply an accepted trial: A = Ac diag(s_n), M = Mc diag(prod_{k != n} s_k), C = s C s.
+// cs = 2 for interleaved complex arrays (the scales are real).
 __global__ __launch_bounds__(256) void k_commit(Shape s, double* A, const double* Ac, double* M,
                                                 const double* Mc, double* C, const double* Cc,
-                                                const FitState* st, int trial) {
+                                                const FitState* st, int trial, int cs) {
   if (st->commit_iter != trial) return;
   const int n = blockIdx.x, c = blockIdx.y, R = s.R, R2 = R * R, In = s.I[n], N = s.N;
   const double* sc = st->scale;
@@ -196,14 +197,17 @@ __global__ __launch_bounds__(256) void k_commit(Shape s, double* A, const double
     double other = 1.0;
     for (int k = 0; k < N; ++k)
       if (k != n) other *= sc[k * kMaxRank + r];
-    A[gi] = Ac[gi] * sc[n * kMaxRank + r];
-    M[gi] = Mc[gi] * other;
+    for (int h = 0; h < cs; ++h) {
+      A[cs * gi + h] = Ac[cs * gi + h] * sc[n * kMaxRank + r];
+      M[cs * gi + h] = Mc[cs * gi + h] * other;
+    }
   }
   if (c == 0) {
     for (int q = (int)(threadIdx.x >> 6); q < R; q += 4)
       for (int r = (int)(threadIdx.x & 63); r < R; r += 64) {
-        const int e = r + q * R;
-        C[(long long)n * R2 + e] = Cc[(long long)n * R2 + e] * sc[n * kMaxRank + r] * sc[n * kMaxRank + q];
+        const long long e = (long long)n * R2 + r + q * R;
+        for (int h = 0; h < cs; ++h)
+          C[cs * e + h] = Cc[cs * e + h] * sc[n * kMaxRank + r] * sc[n * kMaxRank + q];
       }
   }
 }
@@ -212,8 +216,8 @@ __global__ __launch_bounds__(256) void k_commit(Shape s, double* A, const double
 
 hipError_t launch_fit_init(const Shape& s, const double* A, const double* M, const double* C,
                            bool resid, const double* e2, double mu0, double tau, FitState* state,
-                           hipStream_t st) {
-  k_fit_init<<<1, 256, 0, st>>>(s, A, M, C, resid ? 1 : 0, e2, mu0, tau, state);
+                           hipStream_t st, int cs) {
+  k_fit_init<<<1, 256, 0, st>>>(s, A, M, C, resid ? 1 : 0, e2, mu0, tau, state, cs);
   return hipGetLastError();
 }
 
@@ -235,15 +239,15 @@ hipError_t launch_inner(const Shape& s, const double* A, const double* M, double
 
 hipError_t launch_control(const Shape& s, const double* Ac, const double* Mc, const double* Cc,
                           bool resid, const double* e2, const double* scal, FitState* state,
-                          int trial, hipStream_t st) {
-  k_control<<<1, 256, 0, st>>>(s, Ac, Mc, Cc, resid ? 1 : 0, e2, scal, state, trial);
+                          int trial, hipStream_t st, int cs) {
+  k_control<<<1, 256, 0, st>>>(s, Ac, Mc, Cc, resid ? 1 : 0, e2, scal, state, trial, cs);
   return hipGetLastError();
 }
 
 hipError_t launch_commit(const Shape& s, double* A, const double* Ac, double* M, const double* Mc,
                          double* C, const double* Cc, const FitState* state, int trial,
-                         hipStream_t st) {
-  k_commit<<<dim3(s.N, row_chunks(s)), 256, 0, st>>>(s, A, Ac, M, Mc, C, Cc, state, trial);
+                         hipStream_t st, int cs) {
+  k_commit<<<dim3(s.N, row_chunks(s)), 256, 0, st>>>(s, A, Ac, M, Mc, C, Cc, state, trial, cs);
   return hipGetLastError();
 }
 

@@ -8,7 +8,7 @@
 
 namespace dgn {
 
-enum class YType { F64 = 0, F32 = 1, BF16 = 2 };
+enum class YType { F64 = 0, F32 = 1, BF16 = 2, C64 = 3, C128 = 4 };
 
 // Launch plan of the one-pass tensor kernel (all-mode MTTKRP, optionally on
 // the residual E = Y - Y_hat formed on the fly).
@@ -99,19 +99,45 @@ hipError_t launch_sys_factor_solve(const Shape& s, const SysPlan& p, const Small
                                    const SysBuffers& y, int* singular, const int* stop,
                                    hipStream_t st);
 
+// The assemble phase in two parts so that the complex path can write its own
+// (embedded) sub-blocks in between: identity / zero fill, then RHS row and SYRK.
+hipError_t launch_sys_fill(const SysPlan& p, const SysBuffers& y, const int* stop, hipStream_t st);
+hipError_t launch_sys_rhs_syrk(const SysPlan& p, const double* z, const SysBuffers& y, const int* stop,
+                               hipStream_t st);
+
+// ---- complex path (Section 5): FP64 complex factors, interleaved (re, im) ------
+constexpr int kMaxRankC = 32;
+PassPlan plan_pass_c(const Shape& s);
+// The real embedding of the complex trailing system: R2 = 2 R^2, nt = 2 (N-1) R^2.
+SysPlan plan_sys_c(const Shape& s);
+hipError_t launch_tensor_pass_c(const Shape& s, bool y64, const void* Y, const double* A, bool resid,
+                                const PassPlan& p, const PassBuffers& b, double* M, double* e2out,
+                                const int* stop, hipStream_t st);
+hipError_t launch_inner_c(const Shape& s, const double* A, const double* M, double* out, hipStream_t st);
+hipError_t launch_gram_c(const Shape& s, const double* A, const SmallBuffers& b, double* Cout,
+                         const int* stop, hipStream_t st);
+hipError_t launch_small_pre_c(const Shape& s, const double* A, const double* M, bool resid, double mu_host,
+                              const FitState* state, const SmallBuffers& b, int* singular,
+                              const int* stop, hipStream_t st);
+hipError_t launch_subblock_c(const Shape& s, const SysPlan& p, const SmallBuffers& b, const SysBuffers& y,
+                             const int* stop, hipStream_t st);
+hipError_t launch_small_post_c(const Shape& s, const double* A, double* Ac, const SmallBuffers& b,
+                               double mu_host, const FitState* state, const int* stop, hipStream_t st);
+
 // ---- fit control -------------------------------------------------------------
+// cs: doubles per element of the factor, MTTKRP and Gram arrays (1 real, 2 complex).
 hipError_t launch_fit_init(const Shape& s, const double* A, const double* M, const double* C,
                            bool resid, const double* e2, double mu0, double tau, FitState* state,
-                           hipStream_t st);
+                           hipStream_t st, int cs = 1);
 hipError_t launch_refresh(const Shape& s, const double* e2, FitState* state, hipStream_t st);
 hipError_t launch_err2(const Shape& s, const double* A, const double* M, const double* C, bool resid,
                        const double* e2, const double* ynorm2_pass, double* out, hipStream_t st);
 hipError_t launch_control(const Shape& s, const double* Ac, const double* Mc, const double* Cc,
                           bool resid, const double* e2, const double* scal, FitState* state,
-                          int trial, hipStream_t st);
+                          int trial, hipStream_t st, int cs = 1);
 hipError_t launch_commit(const Shape& s, double* A, const double* Ac, double* M, const double* Mc,
                          double* C, const double* Cc, const FitState* state, int trial,
-                         hipStream_t st);
+                         hipStream_t st, int cs = 1);
 
 // ---- batched small fits (one block per fit per trial) ---------------------------
 struct BFit {

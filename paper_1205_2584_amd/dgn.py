@@ -23,7 +23,8 @@ STOP_TOL, STOP_MAX_IT, STOP_MU, STOP_NONFINITE = 0, 1, 2, 3
 STATUS = {0: "DGN_OK", -1: "DGN_EINVAL", -2: "DGN_ENOMEM", -3: "DGN_ESINGULAR",
           -4: "DGN_ENONFINITE", -5: "DGN_EHIP", -6: "DGN_EBUSY"}
 
-_DTYPE = {torch.float64: F64, torch.float32: F32, torch.bfloat16: BF16}
+_DTYPE = {torch.float64: F64, torch.float32: F32, torch.bfloat16: BF16,
+          torch.complex64: C64, torch.complex128: C128}
 
 
 class DgnError(RuntimeError):
@@ -151,8 +152,9 @@ def opts(**kw) -> dgn_opts:
 def _ptrs(ts):
     arr = (ctypes.c_void_p * len(ts))()
     for k, t in enumerate(ts):
-        if t.dtype != torch.float64 or not t.is_contiguous() or not t.is_cuda:
-            raise ValueError("factors must be contiguous float64 device tensors of shape (R, I_n)")
+        if t.dtype not in (torch.float64, torch.complex128) or not t.is_contiguous() or not t.is_cuda:
+            raise ValueError("factors must be contiguous float64 (complex128 for complex tensors) "
+                             "device tensors of shape (R, I_n)")
         arr[k] = t.data_ptr()
     return arr
 
@@ -323,13 +325,17 @@ def workspace_size(dims, R, dtype=torch.float64) -> int:
 # ---- host-side marshalling helpers (numpy <-> device layout) -------------------------
 
 def to_device_factors(A, device="cuda"):
-    """numpy (I_n, R) float64 factors -> contiguous (R, I_n) device tensors."""
+    """numpy (I_n, R) factors -> contiguous (R, I_n) device tensors: float64 for
+    real factors, complex128 (interleaved re, im) for complex ones."""
     import numpy as np
-    return [torch.from_numpy(np.ascontiguousarray(np.asarray(a, dtype=np.float64).T)).to(device)
-            for a in A]
+    out = []
+    for a in A:
+        dt = np.complex128 if np.iscomplexobj(a) else np.float64
+        out.append(torch.from_numpy(np.ascontiguousarray(np.asarray(a, dtype=dt).T)).to(device))
+    return out
 
 
 def to_host_factors(ts):
-    """(R, I_n) device tensors -> numpy (I_n, R) Fortran-ordered float64 arrays."""
+    """(R, I_n) device tensors -> numpy (I_n, R) Fortran-ordered arrays (float64 or complex128)."""
     import numpy as np
     return [np.asfortranarray(t.detach().cpu().numpy().T) for t in ts]

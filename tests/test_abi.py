@@ -77,3 +77,18 @@ def test_workspace_size_matches_system_size(lib):
     ntp = ((2 * 900 + 63) // 64) * 64
     assert n > (ntp + 64) * ntp * 8
     assert n < 512 << 20
+
+
+def test_workspace_size_complex(lib):
+    """Complex tensors: the embedded trailing system has twice the real size; R <= 32."""
+    from paper_1205_2584_amd import dgn
+    torch = dgn.torch
+    real = dgn.workspace_size((40, 30, 20), 8, torch.float64)
+    cplx = dgn.workspace_size((40, 30, 20), 8, torch.complex128)
+    nt = 2 * 2 * 64
+    ntp = ((nt + 63) // 64) * 64
+    assert cplx > real
+    assert cplx > (ntp + 64) * ntp * 8
+    assert dgn.workspace_size((40, 30, 20), 32, torch.complex64) > 0
+    with pytest.raises(dgn.DgnError):
+        dgn.workspace_size((40, 30, 20), 33, torch.complex64)
