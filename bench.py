@@ -143,25 +143,20 @@ def bench_batched(dgn, torch, count=1024, max_iters=200, tol=1e-8, seq_sample=8)
 
 
 def bench_serving(dgn, torch, n_req=256, rate=2000.0, pool=32, slots=4, seed=5):
-    """Poisson arrival trace (mean `rate` req/s) of real 3-/4-way fits drawn from a
-    seeded pool: N in {3,4}, I_n log-uniform in [16,64] (bounded so the pool is
-    generated in seconds), R ~ U{2..20}, correlation U[0,0.95], 20 dB; stop at
-    |delta eps| < 1e-8 or 200 trials.  Same trace through `slots` concurrent slots
-    and through one slot (FIFO one-at-a-time)."""
+    """Poisson arrival trace (mean `rate` req/s) of real fits drawn from a
+    seeded pool generated on the GPU: N in {3,4}, I_n log-uniform in [16,256],
+    R ~ U{2..20}, correlation U[0,0.95], 20 dB, 20 % complex64 requests, tensors
+    capped at 2^27 entries (larger draws are redrawn); stop at |delta eps| < 1e-8
+    or 200 trials.  The same trace runs through `slots` concurrent slots and
+    through one slot (FIFO one-at-a-time)."""
     import numpy as np
-    import cpgen
+    from cpgen import device as cdev
     rng = np.random.default_rng(seed)
-    probs = []
-    for k in range(pool):
-        N = int(rng.integers(3, 5))
-        dims = tuple(int(round(np.exp(rng.uniform(np.log(16), np.log(64))))) for _ in range(N))
-        R = int(rng.integers(2, 21))
-        p = cpgen.small_problem(seed * 1000 + k, dims, R, c=float(rng.uniform(0, 0.95)), snr_db=20.0)
-        probs.append(p)
-    ys = [torch.from_numpy(p.y.astype(np.float32)).cuda() for p in probs]
+    probs = cdev.make_pool(torch, seed * 1000, pool, max_elems=1 << 27)
+    ys = [p.y for p in probs]
     picks = rng.integers(0, pool, size=n_req)
     gaps = rng.exponential(1.0 / rate, size=n_req)
-    budget = 6 << 30
+    budget = 8 << 30
 
     def run(nslots):
         srv = dgn.Server(0, budget_bytes=budget, max_slots=nslots)
@@ -188,9 +183,12 @@ def bench_serving(dgn, torch, n_req=256, rate=2000.0, pool=32, slots=4, seed=5):
 
     multi = run(slots)
     single = run(1)
-    return {"requests": n_req, "offered_rate_per_s": rate, "slots": slots, "served": multi,
-            "fifo_one_slot": single, "speedup_vs_fifo": round(multi["fits_per_s"] / single["fits_per_s"], 2),
-            "trace": "Poisson arrivals; pool of 32 seeded real fits, N in {3,4}, I_n log-uniform [16,64], R in [2,20]"}
+    ncomplex = int(sum(probs[k].complex_ for k in picks))
+    return {"requests": n_req, "complex_requests": ncomplex, "offered_rate_per_s": rate, "slots": slots,
+            "served": multi, "fifo_one_slot": single,
+            "speedup_vs_fifo": round(multi["fits_per_s"] / single["fits_per_s"], 2),
+            "trace": "Poisson arrivals; pool of 32 seeded fits generated on the GPU, N in {3,4}, "
+                     "I_n log-uniform [16,256] (tensors <= 2^27 entries), R in [2,20], 20% complex64"}
 
 
 def rel(a, b):

@@ -18,10 +18,11 @@ def _dgn():
 def _requests():
     specs = [((24, 20, 18), 4, torch.float64), ((16, 30, 22, 12), 5, torch.float32),
              ((40, 33, 28), 10, torch.float32), ((17, 19, 16), 18, torch.float64),
-             ((50, 20, 12, 9), 3, torch.float32), ((64, 48, 40), 6, torch.float32)]
+             ((50, 20, 12, 9), 3, torch.float32), ((64, 48, 40), 6, torch.float32),
+             ((14, 12, 10), 5, torch.complex128), ((20, 18, 9, 6), 4, torch.complex64)]
     out = []
     for k, (dims, R, dt) in enumerate(specs):
-        p = cpgen.small_problem(300 + k, dims, R, c=0.5, snr_db=20.0)
+        p = cpgen.small_problem(300 + k, dims, R, c=0.5, snr_db=20.0, complex_=dt.is_complex)
         out.append((p, dt))
     return out
 
