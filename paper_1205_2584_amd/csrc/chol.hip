@@ -444,19 +444,39 @@ __global__ __launch_bounds__(256) void k_syrk(SysPlan p, const double* B, int R2
 // Phase ph of the tiled Cholesky.  Blocks [0, Tt - ph + 1) are the panel row
 // tiles i = ph + blk (the last one is the right-hand-side row).  Each applies
 // the update of column ph-1 to the diagonal tile D and to its tile B, then
-// factors [D; B] in LDS.  Block 0 (i = ph, no B) writes L(ph, ph) to Ld and
-// L(ph, ph)^-1 (row-major) to Li.  Every diagonal-tile copy is read from St,
+// factors [D; B] in LDS.  Block 0 (i = ph, no B) writes L(ph, ph) to Ld.  Every diagonal-tile copy is read from St,
 // which this launch never writes.  The remaining blocks are the trailing tiles
 // (i, j), ph < j <= i <= Tt, j < Tt, which receive the update of column ph-1.
 // Their MFMA operands load straight from global memory into registers, so the
 // launch needs about 79 KB of LDS and two workgroups fit on a CU.
+// Bounded wait until the workgroup-shared counter reaches `target`; on
+// exhaustion (never expected: the waves waited on make progress on their own)
+// the singular flag is raised and the wait ends.
+__device__ __forceinline__ void wait_at_least(int* ctr, int target, int* bad) {
+  int spins = 0;
+  while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < target) {
+    __builtin_amdgcn_s_sleep(1);
+    if (++spins > (1 << 22)) {
+      if ((threadIdx.x & 63) == 0) *bad = 1;
+      return;
+    }
+  }
+}
+
+// Barrier of waves 1..3 (wave 0 runs the diagonal chain meanwhile).
+__device__ __forceinline__ void barrier3(int* ctr, int& epoch, int* bad) {
+  ++epoch;
+  if ((threadIdx.x & 63) == 0) __hip_atomic_fetch_add(ctr, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+  wait_at_least(ctr, 3 * epoch, bad);
+}
+
 __global__ __launch_bounds__(256, 2) void k_chol_phase(SysPlan p, int ph, double* St, double* Ld,
                                                        double* Li, int* bad, const int* stop) {
   if (stopped(stop)) return;
   __shared__ double T[128][TR];
-  __shared__ __align__(16) double Lkk[16][16];
+  __shared__ __align__(16) double Lk[4][16][16];  // L_kk of each column step
   __shared__ double rinv[64];
-  __shared__ double Z[4][16][17];
+  __shared__ int step_done, b_count;
   const int npanel = p.Tt - ph + 1;
   const long long lds = p.lds;
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
@@ -466,63 +486,84 @@ __global__ __launch_bounds__(256, 2) void k_chol_phase(SysPlan p, int ph, double
     const bool hb = (i != ph);
     const double* Dg = St + ph * 64 + (long long)ph * 64 * lds;
     double* Bg = St + i * 64 + (long long)ph * 64 * lds;
+    if (t == 0) {
+      step_done = 0;
+      b_count = 0;
+    }
     stage_panel(T, Dg, lds);
     if (hb) stage_panel(T + 64, Bg, lds);
     __syncthreads();
-    if (ph > 0) {
-      const double* La = St + ph * 64 + (long long)(ph - 1) * 64 * lds;  // L(ph, ph-1)
-      const double* Lb = St + i * 64 + (long long)(ph - 1) * 64 * lds;   // L(i, ph-1)
-      const int nblk = 10 + (hb ? 16 : 0);
-      for (int b = w; b < nblk; b += 4) {
-        int bi, bj;
-        bool of_b;
-        panel_update_block(b, bi, bj, of_b);
-        const double* P = of_b ? Lb : La;
-        double av[16], bv[16];
+    const double* La = St + ph * 64 + (long long)(ph - 1) * 64 * lds;  // L(ph, ph-1)
+    const double* Lb = St + i * 64 + (long long)(ph - 1) * 64 * lds;   // L(i, ph-1)
+    // update block b (panel_update_block numbering) with column ph-1
+    auto update_block = [&](int b) {
+      int bi, bj;
+      bool of_b;
+      panel_update_block(b, bi, bj, of_b);
+      const double* P = of_b ? Lb : La;
+      double av[16], bv[16];
 #pragma unroll
-        for (int s2 = 0; s2 < 16; ++s2) {
-          av[s2] = P[((bi & 3) * 16 + cl) + (long long)(4 * s2 + kq) * lds];
-          bv[s2] = La[(16 * bj + cl) + (long long)(4 * s2 + kq) * lds];
+      for (int s2 = 0; s2 < 16; ++s2) {
+        av[s2] = P[((bi & 3) * 16 + cl) + (long long)(4 * s2 + kq) * lds];
+        bv[s2] = La[(16 * bj + cl) + (long long)(4 * s2 + kq) * lds];
+      }
+      v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s2 = 0; s2 < 16; ++s2) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s2], bv[s2], acc, 0, 0, 0);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) T[16 * bi + kq + 4 * v][16 * bj + cl] -= acc[v];
+    };
+    // in-panel update of the 16 x 16 block (bi, bj) with column step k0
+    auto trail_block = [&](int bi, int bj, int k0) {
+      v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int k = 0; k < 16; k += 4)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(T[16 * bi + cl][k0 + k + kq], T[16 * bj + cl][k0 + k + kq], acc,
+                                                   0, 0, 0);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) T[16 * bi + kq + 4 * v][16 * bj + cl] -= acc[v];
+    };
+    if (ph > 0)
+      for (int b = w; b < 10; b += 4) update_block(b);  // the lower blocks of D
+    __syncthreads();
+    if (w == 0) {
+      // Diagonal chain: factor D step by step.  After the rows of D below the
+      // diagonal block of step kb are solved, publish kb + 1.
+      for (int kb = 0; kb < 4; ++kb) {
+        const int k0 = 16 * kb;
+        chol16(T, k0, bad, Lk[kb], rinv);
+        if (lane < 48 - k0) trsm16_row(T, k0 + 16 + lane, k0, Lk[kb], rinv);
+        if (lane == 0) __hip_atomic_store(&step_done, kb + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+        const int m = 3 - kb, ndb = m * (m + 1) / 2;
+        for (int b = 0; b < ndb; ++b) {
+          int bi, bj;
+          panel_trail_block(b, kb, bi, bj);
+          trail_block(bi, bj, k0);
         }
-        v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int s2 = 0; s2 < 16; ++s2) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s2], bv[s2], acc, 0, 0, 0);
-#pragma unroll
-        for (int v = 0; v < 4; ++v) T[16 * bi + kq + 4 * v][16 * bj + cl] -= acc[v];
+      }
+    } else if (hb) {
+      // Waves 1..3: the rows of B.  Update with column ph-1, then follow the chain.
+      int epoch = 0;
+      if (ph > 0)
+        for (int b = w - 1; b < 16; b += 3) update_block(10 + b);
+      barrier3(&b_count, epoch, bad);
+      const int r0 = (w - 1) * 22, r1 = (w == 3) ? 64 : r0 + 22;  // rows of B solved by this wave
+      for (int kb = 0; kb < 4; ++kb) {
+        const int k0 = 16 * kb;
+        wait_at_least(&step_done, kb + 1, bad);
+        if (lane < r1 - r0) trsm16_row(T, 64 + r0 + lane, k0, Lk[kb], rinv);
+        barrier3(&b_count, epoch, bad);
+        const int m = 3 - kb;
+        for (int b = w - 1; b < 4 * m; b += 3) trail_block(4 + b / m, kb + 1 + b % m, k0);
+        barrier3(&b_count, epoch, bad);
       }
     }
     __syncthreads();
-    for (int kb = 0; kb < 4; ++kb) {
-      const int k0 = 16 * kb;
-      if (w == 0) chol16(T, k0, bad, Lkk, rinv);
-      __syncthreads();
-      const int nd = 48 - k0;
-      const int nr = nd + (hb ? 64 : 0);
-      if (t < nr) trsm16_row(T, t < nd ? k0 + 16 + t : 64 + (t - nd), k0, Lkk, rinv);
-      __syncthreads();
-      const int m = 3 - kb;
-      const int nblk = m * (m + 1) / 2 + (hb ? 4 * m : 0);
-      for (int b = w; b < nblk; b += 4) {
-        int bi, bj;
-        panel_trail_block(b, kb, bi, bj);
-        v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int k = 0; k < 16; k += 4)
-          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(T[16 * bi + cl][k0 + k + kq], T[16 * bj + cl][k0 + k + kq], acc,
-                                                     0, 0, 0);
-#pragma unroll
-        for (int v = 0; v < 4; ++v) T[16 * bi + kq + 4 * v][16 * bj + cl] -= acc[v];
-      }
-      __syncthreads();
-    }
     if (!hb) {
-      invert_lower64(T, T + 64, rinv, Z);
       double* Lg = Ld + (long long)ph * 64 * 64;
-      double* Xg = Li + (long long)ph * 64 * 64;
       for (int e = t; e < 64 * 64; e += 256) {
         const int r = e & 63, c = e >> 6;
         Lg[r + c * 64] = (c <= r) ? T[r][c] : 0.0;
-        Xg[c + r * 64] = (c <= r) ? T[64 + r][c] : 0.0;
       }
     } else {
       for (int e = t; e < 64 * 64; e += 256) {
@@ -566,6 +607,27 @@ __global__ __launch_bounds__(256, 2) void k_chol_phase(SysPlan p, int ph, double
   for (int blk = 0; blk < 4; ++blk)
 #pragma unroll
     for (int v = 0; v < 4; ++v) C[(16 * blk + cl) + (long long)(16 * w + kq + 4 * v) * lds] -= acc[blk][v];
+}
+
+// L_kk^-1 of every diagonal tile (row-major, into Li), one workgroup per tile,
+// after the factorisation: the inverses only serve the backward substitution.
+__global__ __launch_bounds__(256) void k_inv_diag(SysPlan p, const double* Ld, double* Li, const int* stop) {
+  if (stopped(stop)) return;
+  __shared__ double T[64][TR];
+  __shared__ double X[64][TR];
+  __shared__ double rinv[64];
+  __shared__ double Z[4][16][17];
+  const int k = blockIdx.x, t = threadIdx.x;
+  stage_panel(T, Ld + (long long)k * 64 * 64, 64);
+  __syncthreads();
+  if (t < 64) rinv[t] = 1.0 / T[t][t];
+  __syncthreads();
+  invert_lower64(T, X, rinv, Z);
+  double* Xg = Li + (long long)k * 64 * 64;
+  for (int e = t; e < 64 * 64; e += 256) {
+    const int r = e >> 6, c = e & 63;
+    Xg[c + r * 64] = (c <= r) ? X[r][c] : 0.0;
+  }
 }
 
 // Backward substitution, phase k (descending).  Every block forms
@@ -695,6 +757,7 @@ hipError_t launch_sys_factor_solve(const Shape& s, const SysPlan& p, const Small
       for (int j = ph + 1; j < p.Tt; ++j) nupd += p.Tt - j + 1;
     k_chol_phase<<<(unsigned)(npanel + nupd), 256, 0, st>>>(p, ph, y.St, y.Ld, y.Li, singular, stop);
   }
+  k_inv_diag<<<p.Tt, 256, 0, st>>>(p, y.Ld, y.Li, stop);
   for (int k = p.Tt - 1; k >= 0; --k) k_bsolve<<<k + 1, 256, 0, st>>>(p, k, y.St, y.Li, y.yt, stop);
   k_y0<<<(p.R2 + 3) / 4, 256, 0, st>>>(p, y.B, b.z, y.yt, b.y, stop);
   return hipGetLastError();
