@@ -476,7 +476,7 @@ __global__ __launch_bounds__(256, 2) void k_chol_phase(SysPlan p, int ph, double
   __shared__ double T[128][TR];
   __shared__ __align__(16) double Lk[4][16][16];  // L_kk of each column step
   __shared__ double rinv[64];
-  __shared__ int step_done, b_count;
+  __shared__ int step_done, b_count, d_done;
   const int npanel = p.Tt - ph + 1;
   const long long lds = p.lds;
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
@@ -489,30 +489,50 @@ __global__ __launch_bounds__(256, 2) void k_chol_phase(SysPlan p, int ph, double
     if (t == 0) {
       step_done = 0;
       b_count = 0;
+      d_done = 0;
     }
+    const double* La = St + ph * 64 + (long long)(ph - 1) * 64 * lds;  // L(ph, ph-1) (ph > 0)
+    const double* Lb = St + i * 64 + (long long)(ph - 1) * 64 * lds;   // L(i, ph-1)
+    // Update of column ph-1 by row blocks: wave w takes D row block dri (column
+    // blocks 0..dri) and then its B row blocks.  The column operand (all of
+    // L(ph, ph-1)) is read once per half of the summation range.
+    auto load_half = [&](int h, int bi, int ncol, const double* P, double (&av)[8], double (&bv)[4][8]) {
+#pragma unroll
+      for (int s2 = 0; s2 < 8; ++s2) {
+        const long long ko = (long long)(32 * h + 4 * s2 + kq) * lds;
+        av[s2] = P[((bi & 3) * 16 + cl) + ko];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) bv[q][s2] = (q < ncol) ? La[(16 * q + cl) + ko] : 0.0;
+      }
+    };
+    auto mfma_half = [&](const double (&av)[8], const double (&bv)[4][8], int ncol, v4d (&acc)[4]) {
+#pragma unroll
+      for (int s2 = 0; s2 < 8; ++s2)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (q < ncol) acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s2], bv[q][s2], acc[q], 0, 0, 0);
+    };
+    auto update_rows = [&](int bi, int ncol, const double* P, const double (&av0)[8], const double (&bv0)[4][8]) {
+      // av0 / bv0: the first half, already loaded
+      v4d acc[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q] = v4d{0.0, 0.0, 0.0, 0.0};
+      double av1[8], bv1[4][8];
+      load_half(1, bi, ncol, P, av1, bv1);
+      mfma_half(av0, bv0, ncol, acc);
+      mfma_half(av1, bv1, ncol, acc);
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (q < ncol)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) T[16 * bi + kq + 4 * v][16 * q + cl] -= acc[q][v];
+    };
+    const int dri = (w == 0) ? 0 : 4 - w;  // D row block of this wave: 0, 3, 2, 1
+    double av0[8], bv0[4][8];
+    if (ph > 0) load_half(0, dri, dri + 1, La, av0, bv0);  // in flight while the panel is staged
     stage_panel(T, Dg, lds);
     if (hb) stage_panel(T + 64, Bg, lds);
     __syncthreads();
-    const double* La = St + ph * 64 + (long long)(ph - 1) * 64 * lds;  // L(ph, ph-1)
-    const double* Lb = St + i * 64 + (long long)(ph - 1) * 64 * lds;   // L(i, ph-1)
-    // update block b (panel_update_block numbering) with column ph-1
-    auto update_block = [&](int b) {
-      int bi, bj;
-      bool of_b;
-      panel_update_block(b, bi, bj, of_b);
-      const double* P = of_b ? Lb : La;
-      double av[16], bv[16];
-#pragma unroll
-      for (int s2 = 0; s2 < 16; ++s2) {
-        av[s2] = P[((bi & 3) * 16 + cl) + (long long)(4 * s2 + kq) * lds];
-        bv[s2] = La[(16 * bj + cl) + (long long)(4 * s2 + kq) * lds];
-      }
-      v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int s2 = 0; s2 < 16; ++s2) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s2], bv[s2], acc, 0, 0, 0);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) T[16 * bi + kq + 4 * v][16 * bj + cl] -= acc[v];
-    };
     // in-panel update of the 16 x 16 block (bi, bj) with column step k0
     auto trail_block = [&](int bi, int bj, int k0) {
       v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
@@ -523,15 +543,17 @@ __global__ __launch_bounds__(256, 2) void k_chol_phase(SysPlan p, int ph, double
 #pragma unroll
       for (int v = 0; v < 4; ++v) T[16 * bi + kq + 4 * v][16 * bj + cl] -= acc[v];
     };
-    if (ph > 0)
-      for (int b = w; b < 10; b += 4) update_block(b);  // the lower blocks of D
-    __syncthreads();
+    if (ph > 0) update_rows(dri, dri + 1, La, av0, bv0);
+    if (lane == 0) __hip_atomic_fetch_add(&d_done, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
     if (w == 0) {
       // Diagonal chain: factor D step by step.  After the rows of D below the
       // diagonal block of step kb are solved, publish kb + 1.
       for (int kb = 0; kb < 4; ++kb) {
         const int k0 = 16 * kb;
         chol16(T, k0, bad, Lk[kb], rinv);
+        // D(0, 0) is this wave's own row block; the rest of D must be updated
+        // before the first solve and update below
+        if (kb == 0) wait_at_least(&d_done, 4, bad);
         if (lane < 48 - k0) trsm16_row(T, k0 + 16 + lane, k0, Lk[kb], rinv);
         if (lane == 0) __hip_atomic_store(&step_done, kb + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
         const int m = 3 - kb, ndb = m * (m + 1) / 2;
@@ -544,8 +566,14 @@ __global__ __launch_bounds__(256, 2) void k_chol_phase(SysPlan p, int ph, double
     } else if (hb) {
       // Waves 1..3: the rows of B.  Update with column ph-1, then follow the chain.
       int epoch = 0;
-      if (ph > 0)
-        for (int b = w - 1; b < 16; b += 3) update_block(10 + b);
+      if (ph > 0) {
+        load_half(0, 4 + (w - 1), 4, Lb, av0, bv0);
+        update_rows(4 + (w - 1), 4, Lb, av0, bv0);  // B row blocks 4, 5, 6 ...
+        if (w == 3) {                              // ... and 7
+          load_half(0, 7, 4, Lb, av0, bv0);
+          update_rows(7, 4, Lb, av0, bv0);
+        }
+      }
       barrier3(&b_count, epoch, bad);
       const int r0 = (w - 1) * 22, r1 = (w == 3) ? 64 : r0 + 22;  // rows of B solved by this wave
       for (int kb = 0; kb < 4; ++kb) {
