@@ -44,21 +44,25 @@ __device__ void chol_lds(double (*H)[LD], int R, int mode, int* bad, double* lk)
   for (int k = 0; k < R; ++k) {
     __syncthreads();
     const double dkk = H[k][k];
-    double d;
+    double d = 1.0, inv = 1.0;
     bool zero = false;
     if (mode == 0) {
       if (!(dkk > 0.0)) {
         if (t == 0) *bad = 1;
-        d = 1.0;
       } else {
         d = sqrt(dkk);
+        inv = 1.0 / d;
       }
     } else {
       const double ref = lk[64 + k];
-      if (!(dkk > 64.0 * 2.220446049250313e-16 * ref)) zero = true;
-      d = zero ? 1.0 : sqrt(dkk);
+      if (!(dkk > 64.0 * 2.220446049250313e-16 * ref)) {
+        zero = true;
+      } else {
+        d = sqrt(dkk);
+        inv = 1.0 / d;
+      }
     }
-    for (int i = k + t; i < R; i += blockDim.x) lk[i] = zero ? 0.0 : ((i == k) ? d : H[i][k] / d);
+    for (int i = k + t; i < R; i += blockDim.x) lk[i] = zero ? 0.0 : ((i == k) ? d : H[i][k] * inv);
     __syncthreads();
     for (int j = k + 1 + (int)(t >> 6); j < R; j += (int)(blockDim.x >> 6)) {
       const int i = t & 63;
@@ -120,6 +124,20 @@ __global__ __launch_bounds__(256) void k_gamma(Shape s, const double* C, double 
   __shared__ double lk[128];
   const int n = blockIdx.x, R = s.R, R2 = R * R, N = s.N, t = threadIdx.x;
   RR_SHIFT;
+  if (blockIdx.y == 1) {
+    // the (semidefinite-safe) Cholesky L_n of C_n, in parallel with the damped inverse
+    FOR_RR(r, q) {
+      const int e = r + q * R;
+      H[r][q] = C[(long long)n * R2 + e];
+    }
+    for (int r = t; r < R; r += 256) lk[64 + r] = C[(long long)n * R2 + r + r * R];
+    chol_lds(H, R, 1, bad, lk);
+    FOR_RR(r, q) {
+      const int e = r + q * R;
+      Lc[(long long)n * R2 + e] = H[r][q];
+    }
+    return;
+  }
   const double mu = state ? state->mu : mu_host;
   FOR_RR(r, q) {
     const int e = r + q * R;
@@ -129,13 +147,15 @@ __global__ __launch_bounds__(256) void k_gamma(Shape s, const double* C, double 
   }
   chol_lds(H, R, 0, bad, lk);
   // Li = L^-1, one column per thread (forward substitution on the identity)
+  if (t < R) lk[t] = 1.0 / H[t][t];
+  __syncthreads();
   for (int j = t; j < 64; j += 256) {
     if (j < R) {
-      Li[j][j] = 1.0 / H[j][j];
+      Li[j][j] = lk[j];
       for (int i = j + 1; i < R; ++i) {
         double acc = 0.0;
         for (int k = j; k < i; ++k) acc += H[i][k] * Li[k][j];
-        Li[i][j] = -acc / H[i][i];
+        Li[i][j] = -acc * lk[i];
       }
       for (int i = 0; i < j; ++i) Li[i][j] = 0.0;
     }
@@ -149,17 +169,6 @@ __global__ __launch_bounds__(256) void k_gamma(Shape s, const double* C, double 
     double acc = 0.0;
     for (int k = k0; k < R; ++k) acc += Li[k][r] * Li[k][q];
     Gt[(long long)n * R2 + e] = acc;
-  }
-  __syncthreads();
-  FOR_RR(r, q) {
-    const int e = r + q * R;
-    H[r][q] = C[(long long)n * R2 + e];
-  }
-  for (int r = t; r < R; r += 256) lk[64 + r] = C[(long long)n * R2 + r + r * R];
-  chol_lds(H, R, 1, bad, lk);
-  FOR_RR(r, q) {
-    const int e = r + q * R;
-    Lc[(long long)n * R2 + e] = H[r][q];
   }
 }
 
@@ -487,7 +496,7 @@ hipError_t launch_gram(const Shape& s, const double* A, const SmallBuffers& b, d
 
 hipError_t launch_gamma(const Shape& s, const double* C, double mu_host, const FitState* state,
                         const SmallBuffers& b, int* singular, const int* stop, hipStream_t st) {
-  k_gamma<<<s.N, 256, 0, st>>>(s, C, mu_host, state, b.Gam, b.Gt, b.X, b.Lc, singular, stop);
+  k_gamma<<<dim3(s.N, 2), 256, 0, st>>>(s, C, mu_host, state, b.Gam, b.Gt, b.X, b.Lc, singular, stop);
   return hipGetLastError();
 }
 
