@@ -406,17 +406,36 @@ __device__ __forceinline__ void tri_index(long long id, int& ti, int& tj) {
 }
 
 // St_tt -= B B^T on the lower tiles; K = R^2 in chunks of 64 staged through LDS.
+// acc[blk] += A * B^T from LDS tiles stored [k][row] with row stride 80 (the
+// [k][row] MFMA operand reads are then bank-conflict free); wave w owns rows
+// 16w.. of A.
+constexpr int TS = 80;
+__device__ __forceinline__ void mma_lds80(const double (*A)[TS], const double (*B)[TS], v4d acc[4]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int ra = 16 * w + (lane & 15), kk = lane >> 4;
+#pragma unroll 4
+  for (int k = 0; k < 64; k += 4) {
+    const double a = A[k + kk][ra];
+#pragma unroll
+    for (int blk = 0; blk < 4; ++blk)
+      acc[blk] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, B[k + kk][16 * blk + (lane & 15)], acc[blk], 0, 0, 0);
+  }
+}
+
+// S_tt -= B B^T on the lower tiles (ti >= tj).  The 64-wide chunks of the
+// summation range are double-buffered in registers: the next chunk is in
+// flight while the current one runs on MFMA.
 __global__ __launch_bounds__(256) void k_syrk(SysPlan p, const double* B, int R2p, double* St,
                                               const int* stop) {
   if (stopped(stop)) return;
-  __shared__ double Ti[64][TL];
-  __shared__ double Tj[64][TL];
+  __shared__ double Ti[64][TS];
+  __shared__ double Tj[64][TS];
   int ti, tj;
   tri_index(blockIdx.x, ti, tj);
   v4d acc[4];
   zero_acc(acc);
-  for (int k0 = 0; k0 < R2p; k0 += 64) {
-    double vi[16], vj[16];
+  double vi[16], vj[16];
+  auto load = [&](int k0) {
 #pragma unroll
     for (int s2 = 0; s2 < 16; ++s2) {
       const int e = threadIdx.x + 256 * s2, r = e & 63, c = e >> 6;
@@ -424,6 +443,9 @@ __global__ __launch_bounds__(256) void k_syrk(SysPlan p, const double* B, int R2
       vi[s2] = ok ? B[ti * 64 + r + (long long)(k0 + c) * p.ntp] : 0.0;
       vj[s2] = ok ? B[tj * 64 + r + (long long)(k0 + c) * p.ntp] : 0.0;
     }
+  };
+  load(0);
+  for (int k0 = 0; k0 < R2p; k0 += 64) {
     __syncthreads();
 #pragma unroll
     for (int s2 = 0; s2 < 16; ++s2) {
@@ -432,7 +454,8 @@ __global__ __launch_bounds__(256) void k_syrk(SysPlan p, const double* B, int R2
       Tj[c][r] = vj[s2];
     }
     __syncthreads();
-    mma_lds(Tj, Ti, acc);
+    if (k0 + 64 < R2p) load(k0 + 64);
+    mma_lds80(Tj, Ti, acc);
   }
   double* C = St + ti * 64 + (long long)tj * 64 * p.lds;
 #pragma unroll
