@@ -185,13 +185,10 @@ __device__ __forceinline__ float cq_of(const PassArgs& a, long long q, int r) {
   return (float)c;
 }
 
-// Epilogue shared by the MFMA kernels: t from LDS, partial M_1 and M_2.
-template <int NB>
-__device__ __forceinline__ void pass_epilogue(const PassArgs& a, float (*tq_s)[kQMax][64], long long q0,
-                                              long long q1, int tile, int ti, int tj, int i0, int j0,
-                                              const v4f* m0acc, const v4f* m1acc) {
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6, g = lane >> 4, c16 = lane & 15;
-  const int R = a.R, I0 = a.I0, I1 = a.I1;
+// t of the slabs [q0, q1) (at most kQMax, staged per wave in LDS) to the tile's partial.
+__device__ __forceinline__ void flush_t(const PassArgs& a, float (*tq_s)[kQMax][64], long long q0, long long q1,
+                                        int tile) {
+  const int t = threadIdx.x, R = a.R;
   __syncthreads();
   float* tp = static_cast<float*>(a.tpart) + (long long)tile * R * a.Q;
   const int nq = (int)(q1 - q0);
@@ -199,6 +196,14 @@ __device__ __forceinline__ void pass_epilogue(const PassArgs& a, float (*tq_s)[k
     const int ql = e % nq, r = e / nq;
     tp[(long long)r * a.Q + q0 + ql] = ((tq_s[0][ql][r] + tq_s[1][ql][r]) + tq_s[2][ql][r]) + tq_s[3][ql][r];
   }
+}
+
+// Partial M_1 and M_2 of the block's tile and q-chunk.
+template <int NB>
+__device__ __forceinline__ void write_m(const PassArgs& a, int ti, int tj, int i0, int j0, const v4f* m0acc,
+                                        const v4f* m1acc) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6, g = lane >> 4, c16 = lane & 15;
+  const int R = a.R, I0 = a.I0, I1 = a.I1;
   float* m0p = static_cast<float*>(a.m0part) + ((long long)blockIdx.y * a.tiles_j + tj) * R * I0;
   float* m1p = static_cast<float*>(a.m1part) + ((long long)blockIdx.y * a.tiles_i + ti) * R * I1;
 #pragma unroll
@@ -253,10 +258,6 @@ __global__ __launch_bounds__(256) void k_pass_f32(PassArgs a, const int* stop) {
       A1s[ii][r] = fac(a, 1, I1, j0 + ii, r);
     }
   }
-  for (int e = t; e < kQMax * 64; e += 256) {
-    const int ql = e >> 6, r = e & 63;
-    cq_all[ql][r] = (q0 + ql < q1) ? cq_of(a, q0 + ql, r) : 0.0f;
-  }
 
   v4f m0acc[NB], m1acc[NB];
 #pragma unroll
@@ -284,14 +285,22 @@ __global__ __launch_bounds__(256) void k_pass_f32(PassArgs a, const int* stop) {
     }
   };
   if (q0 < q1) load(q0);
-  for (long long q = q0; q < q1; ++q) {
+  for (long long sq0 = q0; sq0 < q1; sq0 += kQMax) {
+  // sub-chunk [sq0, sq1) of at most kQMax slabs: c_q staged here, t flushed after
+  const long long sq1 = (sq0 + kQMax < q1) ? sq0 + kQMax : q1;
+  __syncthreads();
+  for (int e = t; e < kQMax * 64; e += 256) {
+    const int ql = e >> 6, r = e & 63;
+    cq_all[ql][r] = (sq0 + ql < sq1) ? cq_of(a, sq0 + ql, r) : 0.0f;
+  }
+  for (long long q = sq0; q < sq1; ++q) {
     __syncthreads();
 #pragma unroll
     for (int s2 = 0; s2 < 4; ++s2) {
       const int e = t + 256 * s2, jj = e >> 4, ii = (e & 15) * 4;
       *reinterpret_cast<v4f*>(&Ys[jj][ii]) = pf[s2];
     }
-    const float* cq_s = cq_all[q - q0];
+    const float* cq_s = cq_all[q - sq0];
     if (q + 1 < q1) load(q + 1);
     __syncthreads();
     if (RESID) {
@@ -334,7 +343,7 @@ __global__ __launch_bounds__(256) void k_pass_f32(PassArgs a, const int* stop) {
         for (int nb = 0; nb < NB; ++nb)
           wacc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(y4[s2], b0[4 * kb + s2][nb], wacc[nb], 0, 0, 0);
     }
-    const int ql = (int)(q - q0);
+    const int ql = (int)(q - sq0);
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
       const float c = cq_s[16 * nb + c16];
@@ -347,7 +356,9 @@ __global__ __launch_bounds__(256) void k_pass_f32(PassArgs a, const int* stop) {
       if (g == 0) tq_s[w][ql][16 * nb + c16] = tv;
     }
   }
-  pass_epilogue<NB>(a, tq_s, q0, q1, tile, ti, tj, i0, j0, m0acc, m1acc);
+  flush_t(a, tq_s, sq0, sq1, tile);
+  }
+  write_m<NB>(a, ti, tj, i0, j0, m0acc, m1acc);
   if (RESID) {
     const double s2 = block_sum(e2, red);
     if (t == 0) a.e2part[(long long)blockIdx.y * gridDim.x + blockIdx.x] = s2;
@@ -398,10 +409,6 @@ __global__ __launch_bounds__(256) void k_pass_bf16(PassArgs a, const int* stop) 
   for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
     for (int v = 0; v < 4; ++v) a0t[nb][v] = fac(a, 0, I0, i0 + 16 * w + 4 * g + v, 16 * nb + c16);
-  for (int e = t; e < kQMax * 64; e += 256) {
-    const int ql = e >> 6, r = e & 63;
-    cq_all[ql][r] = (q0 + ql < q1) ? cq_of(a, q0 + ql, r) : 0.0f;
-  }
 
   v4f m0acc[NB], m1acc[NB];
 #pragma unroll
@@ -430,14 +437,22 @@ __global__ __launch_bounds__(256) void k_pass_bf16(PassArgs a, const int* stop) 
     }
   };
   if (q0 < q1) load(q0);
-  for (long long q = q0; q < q1; ++q) {
+  for (long long sq0 = q0; sq0 < q1; sq0 += kQMax) {
+  // sub-chunk [sq0, sq1) of at most kQMax slabs: c_q staged here, t flushed after
+  const long long sq1 = (sq0 + kQMax < q1) ? sq0 + kQMax : q1;
+  __syncthreads();
+  for (int e = t; e < kQMax * 64; e += 256) {
+    const int ql = e >> 6, r = e & 63;
+    cq_all[ql][r] = (sq0 + ql < sq1) ? cq_of(a, sq0 + ql, r) : 0.0f;
+  }
+  for (long long q = sq0; q < sq1; ++q) {
     __syncthreads();
 #pragma unroll
     for (int s2 = 0; s2 < 4; ++s2) {
       const int e = t + 256 * s2, jj = e >> 4, ii = (e & 15) * 4;
       *reinterpret_cast<us4*>(&Ys[jj][ii]) = pf[s2];
     }
-    const float* cq_s = cq_all[q - q0];
+    const float* cq_s = cq_all[q - sq0];
     if (q + 1 < q1) load(q + 1);
     __syncthreads();
     v4f zacc[NB], wacc[NB];
@@ -460,7 +475,7 @@ __global__ __launch_bounds__(256) void k_pass_bf16(PassArgs a, const int* stop) 
         wacc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(yv, b0l[ks][nb], wacc[nb], 0, 0, 0);
       }
     }
-    const int ql = (int)(q - q0);
+    const int ql = (int)(q - sq0);
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
       const float c = cq_s[16 * nb + c16];
@@ -473,7 +488,9 @@ __global__ __launch_bounds__(256) void k_pass_bf16(PassArgs a, const int* stop) 
       if (g == 0) tq_s[w][ql][16 * nb + c16] = tv;
     }
   }
-  pass_epilogue<NB>(a, tq_s, q0, q1, tile, ti, tj, i0, j0, m0acc, m1acc);
+  flush_t(a, tq_s, sq0, sq1, tile);
+  }
+  write_m<NB>(a, ti, tj, i0, j0, m0acc, m1acc);
 }
 
 // out[x] = sum_s part[s * len + x], accumulated in FP64.  A block covers 64
@@ -582,16 +599,15 @@ PassPlan plan_pass(const Shape& s, YType yt) {
   p.Q = 1;
   for (int k = 2; k < s.N; ++k) p.Q *= s.I[k];
   const long long tiles = (long long)p.tiles_i * p.tiles_j;
-  long long want = (2048 + tiles - 1) / tiles;
+  // MFMA passes: about one resident round (256 CUs x 2 blocks); a block walks
+  // its q-chunk in sub-chunks of kQMax slabs
+  const long long target = (yt != YType::F64) ? 512 : 2048;
+  long long want = (target + tiles - 1) / tiles;
   if (want > p.Q) want = p.Q;
   if (want < 1) want = 1;
   p.q_per = (int)((p.Q + want - 1) / want);
   p.n_qc = (int)((p.Q + p.q_per - 1) / p.q_per);
   p.mfma = (yt != YType::F64) ? 1 : 0;
-  if (p.mfma && p.q_per > kQMax) {
-    p.q_per = kQMax;
-    p.n_qc = (int)((p.Q + p.q_per - 1) / p.q_per);
-  }
   p.tc_bytes = (yt == YType::F64) ? 8 : 4;
   p.m0_elems = (size_t)p.n_qc * p.tiles_j * s.R * s.I[0];
   p.m1_elems = (size_t)p.n_qc * p.tiles_i * s.R * s.I[1];
