@@ -320,7 +320,6 @@ __global__ __launch_bounds__(256) void k_subblock(Shape s, SysPlan p, const doub
   if (stopped(stop)) return;
   __shared__ double Td[64][LD];  // Td[i][a] = T_nm[i, a + dR]
   __shared__ double Lm[64][LD];
-  __shared__ double xb[64];
   const int N = s.N, R = s.R, R2 = R * R;
   // decode the strictly lower pair (n, m), n > m
   int pr = blockIdx.x / R, b = blockIdx.x % R, d = blockIdx.y;
@@ -330,17 +329,29 @@ __global__ __launch_bounds__(256) void k_subblock(Shape s, SysPlan p, const doub
   (void)N;
   const int pair = n * N + m;
   const double* T = Tnm + (long long)pair * R * R2;
-  for (int a = (int)(threadIdx.x >> 6); a < R; a += 4)
-  for (int i = (int)(threadIdx.x & 63); i < R; i += 64) {
-    const int e = i + a * R;
-    Td[i][a] = T[((long long)a + (long long)d * R) * R + i];
-    Lm[i][a] = Lc[(long long)m * R2 + e];  // Lm[i][c] = L_m[i, c]
+  {
+    // all loads of the thread in flight at once; x_b folded into T on the way to LDS:
+    // Td[i][a] = x_b[i] T_nm[i, a + dR], Lm[i][c] = L_m[i, c]
+    const int i = threadIdx.x & 63, a0 = threadIdx.x >> 6;
+    const bool iok = i < R;
+    double tv[16], lv[16];
+#pragma unroll
+    for (int s2 = 0; s2 < 16; ++s2) {
+      const int a = a0 + 4 * s2;
+      const bool ok = iok && a < R;
+      tv[s2] = ok ? T[((long long)a + (long long)d * R) * R + i] : 0.0;
+      lv[s2] = ok ? Lc[(long long)m * R2 + i + a * R] : 0.0;
+    }
+    const double xbi = iok ? X[(long long)n * R2 + i + b * R] : 0.0;
+#pragma unroll
+    for (int s2 = 0; s2 < 16; ++s2) {
+      const int a = a0 + 4 * s2;
+      if (iok && a < R) {
+        Td[i][a] = tv[s2] * xbi;
+        Lm[i][a] = lv[s2];
+      }
+    }
   }
-  for (int i = threadIdx.x; i < R; i += 256) xb[i] = X[(long long)n * R2 + i + b * R];
-  __syncthreads();
-  // fold x_b into T: Td[i][a] *= x_b[i]
-  for (int a = (int)(threadIdx.x >> 6); a < R; a += 4)
-    for (int i = (int)(threadIdx.x & 63); i < R; i += 64) Td[i][a] *= xb[i];
   __syncthreads();
   const int sh = R <= 16 ? 4 : (R <= 32 ? 5 : 6);
   const int a = threadIdx.x & ((1 << sh) - 1), cg = threadIdx.x >> sh, cstep = 256 >> sh;

@@ -36,6 +36,27 @@ __device__ __forceinline__ double gamma_except(const double* C, int N, int R2, i
   return g;
 }
 
+// Stage rows r0..r0+63 of the column-major In x R block src into S[ii][r]
+// (zero outside), with every load of the thread issued before the LDS stores.
+// Returns nothing; optional square-sum of the staged values through *sq.
+__device__ __forceinline__ void stage_rows(double (*S)[LD], const double* src, int In, int r0, int R,
+                                           double* sq = nullptr) {
+  double v[16];
+#pragma unroll
+  for (int s2 = 0; s2 < 16; ++s2) {
+    const int e = threadIdx.x + 256 * s2, ii = e & 63, r = e >> 6;
+    v[s2] = (r < R && r0 + ii < In) ? src[r0 + ii + (long long)r * In] : 0.0;
+  }
+  double acc = 0.0;
+#pragma unroll
+  for (int s2 = 0; s2 < 16; ++s2) {
+    const int e = threadIdx.x + 256 * s2, ii = e & 63, r = e >> 6;
+    if (r < R) S[ii][r] = v[s2];
+    acc += v[s2] * v[s2];
+  }
+  if (sq) *sq += acc;
+}
+
 // Cholesky of the R x R matrix H (lower, in place) with 256 threads.
 // mode 0: a non-positive pivot sets *bad.  mode 1 (semidefinite): a pivot
 // below 64 u times the original diagonal zeroes the column.
@@ -88,10 +109,7 @@ __global__ __launch_bounds__(256) void k_gram_part(Shape s, const double* A, dou
   const int r0 = c * 64;
   double* out = part + ((long long)n * chunks + c) * stride;
   const double* An = A + (long long)s.off[n] * R;
-  for (int e = threadIdx.x; e < 64 * R; e += 256) {
-    const int ii = e & 63, r = e >> 6;
-    As[ii][r] = (r0 + ii < In) ? An[r0 + ii + (long long)r * In] : 0.0;
-  }
+  stage_rows(As, An, In, r0, R);
   __syncthreads();
   FOR_RR(r, q) {
     const int e = r + q * R;
@@ -198,15 +216,8 @@ __global__ __launch_bounds__(256) void k_pw(Shape s, const double* A, const doub
     Gm[r][q] = resid ? Gt[(long long)n * R2 + e] : Gam[(long long)n * R2 + e];
   }
   double m2 = 0.0;
-  for (int e = t; e < 64 * R; e += 256) {
-    const int ii = e & 63, r = e >> 6;
-    const bool ok = r0 + ii < In;
-    const long long gi = base + r0 + ii + (long long)r * In;
-    As[ii][r] = ok ? A[gi] : 0.0;
-    const double mv = ok ? M[gi] : 0.0;
-    Gs[ii][r] = mv;
-    m2 += mv * mv;
-  }
+  stage_rows(As, A + base, In, r0, R);
+  stage_rows(Gs, M + base, In, r0, R, &m2);
   __syncthreads();
   if (!resid) {
     // G = M - A Gamma
@@ -430,10 +441,7 @@ __global__ __launch_bounds__(256) void k_update(Shape s, const double* A, const 
   const double mu = state ? state->mu : mu_host;
   const long long base = (long long)s.off[n] * R;
   FOR_RR(r, q) Qs[r][q] = Q[(long long)n * R2 + r + q * R];
-  for (int e = t; e < 64 * R; e += 256) {
-    const int ii = e & 63, r = e >> 6;
-    As[ii][r] = (r0 + ii < In) ? A[base + r0 + ii + (long long)r * In] : 0.0;
-  }
+  stage_rows(As, A + base, In, r0, R);
   __syncthreads();
   double den = 0.0, da2 = 0.0;
   for (int e = t; e < 64 * R; e += 256) {
