@@ -123,34 +123,54 @@ __device__ __forceinline__ double row_bcast(double v) {
   return __builtin_amdgcn_update_dpp(0.0, v, 0x150 + SRC, 0xf, 0xf, true);
 }
 
+// 1/x to FP64 accuracy: hardware estimate y = (1 - e)/x refined by one cubic
+// step, y (1 + e + e^2) = (1 - e^3)/x.
+__device__ __forceinline__ double rcp_f64(double x) {
+  const double y = __builtin_amdgcn_rcp(x);
+  const double e = __builtin_fma(-x, y, 1.0);
+  return __builtin_fma(__builtin_fma(e, e, e), y, y);
+}
+
+// Column C of the in-register 16 x 16 factorisation in L D L^T form: lane `row`
+// holds row `row` in r.  With a = A[row][C] (unscaled) and d_C = A[C][C], the
+// rows below the pivot are updated by A[row][J] -= (a / d_C) A[J][C]; the
+// broadcasts of column C do not wait for the reciprocal of the pivot.  r[C]
+// keeps a (so lane C keeps d_C).
 template <int J>
-__device__ __forceinline__ void chol_update(double (&r)[16], double l) {
+__device__ __forceinline__ void ldl_update(double (&r)[16], double l, double a) {
   if constexpr (J < 16) {
-    r[J] -= l * row_bcast<J>(l);
-    chol_update<J + 1>(r, l);
+    r[J] -= l * row_bcast<J>(a);
+    ldl_update<J + 1>(r, l, a);
   }
 }
 
-// Column C of the in-register 16 x 16 Cholesky: lane `row` holds row `row` in r.
 template <int C>
-__device__ __forceinline__ void chol_column(double (&r)[16], int row, bool& ok, double& myinv) {
+__device__ __forceinline__ void ldl_column(double (&r)[16], int row, bool& ok) {
   if constexpr (C < 16) {
-    const double piv = row_bcast<C>(r[C]);
-    const bool pos = piv > 0.0;
-    ok = ok && pos;
-    const double inv = rsqrt_f64(pos ? piv : 1.0);
-    const double d = pos ? piv * inv : 1.0;
-    if (row == C) myinv = inv;
-    const double l = (row > C) ? r[C] * inv : (row == C ? d : 0.0);
-    r[C] = l;
-    chol_update<C + 1>(r, l);
-    chol_column<C + 1>(r, row, ok, myinv);
+    const double a = r[C];
+    const double am = (row > C) ? a : 0.0;
+    const double piv = row_bcast<C>(a);
+    ok = ok && (piv > 0.0);
+    ldl_update<C + 1>(r, am * rcp_f64(piv), a);
+    ldl_column<C + 1>(r, row, ok);
+  }
+}
+
+// Rescale the L D L^T result of one lane to the Cholesky factor:
+// L[row][c] = A^(c)[row][c] / sqrt(d_c).
+template <int C>
+__device__ __forceinline__ void ldl_scale(double (&r)[16], int row, double myd, double myrsq) {
+  if constexpr (C < 16) {
+    const double rs = row_bcast<C>(myrsq);
+    r[C] = (row > C) ? r[C] * rs : (row == C ? myd * myrsq : 0.0);
+    ldl_scale<C + 1>(r, row, myd, myrsq);
   }
 }
 
 // Cholesky of the 16 x 16 block T[k0.., k0..] by one wave (each 16-lane row of
-// the wave computes the same rows).  L goes back into T (zeros above), a compact
-// copy into Lkk, and 1/L_cc into rinv[k0 + c].  A non-positive pivot sets *bad.
+// the wave computes the same rows).  L goes back into T (zeros above), a
+// compact copy into Lkk, and 1/L_cc into rinv[k0 + c].  A non-positive pivot
+// sets *bad.
 __device__ void chol16(double (*T)[TR], int k0, int* bad, double (*Lkk)[16], double* rinv) {
   const int lane = threadIdx.x & 63;
   const int row = lane & 15;
@@ -158,16 +178,20 @@ __device__ void chol16(double (*T)[TR], int k0, int* bad, double (*Lkk)[16], dou
 #pragma unroll
   for (int j = 0; j < 16; ++j) r[j] = T[k0 + row][k0 + j];
   bool ok = true;
-  double myinv = 1.0;
-  chol_column<0>(r, row, ok, myinv);
+  ldl_column<0>(r, row, ok);
+  double myd = 0.0;
+#pragma unroll
+  for (int j = 0; j < 16; ++j)
+    if (row == j) myd = r[j];
+  const double myrsq = rsqrt_f64(myd > 0.0 ? myd : 1.0);
+  ldl_scale<0>(r, row, myd, myrsq);
   if (lane < 16) {
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
-      const double v = (j <= row) ? r[j] : 0.0;
-      T[k0 + row][k0 + j] = v;
-      Lkk[row][j] = v;
+      T[k0 + row][k0 + j] = r[j];
+      Lkk[row][j] = r[j];
     }
-    rinv[k0 + row] = myinv;
+    rinv[k0 + row] = myrsq;
   }
   if (!ok && lane == 0) *bad = 1;
 }
@@ -738,6 +762,102 @@ __global__ __launch_bounds__(256) void k_bsolve(SysPlan p, int k, double* St, co
   }
 }
 
+// Backward substitution for the tile pair (k, k-1), k >= 1 (descending).  Every
+// block forms y_k = L_kk^-T u_k, u'_{k-1} = u_{k-1} - L(k, k-1)^T y_k and
+// y_{k-1} = L_{k-1,k-1}^-T u'_{k-1} from the inverse tiles; blocks k and k-1
+// store them, block j < k-1 updates u_j -= L(k, j)^T y_k + L(k-1, j)^T y_{k-1}.
+// All loads of a thread are issued before the first product.
+__global__ __launch_bounds__(256) void k_bsolve2(SysPlan p, int k, double* St, const double* Li, double* yt,
+                                                 const int* stop) {
+  if (stopped(stop)) return;
+  __shared__ double Lt[3][64][TL];  // L(k, k-1), L(k, j), L(k-1, j), each [col][row]
+  __shared__ double u[2][64];
+  __shared__ double ys[2][64];
+  __shared__ double part[4][64];
+  const long long lds = p.lds;
+  const int t = threadIdx.x, j = blockIdx.x, c = t & 63, g = t >> 6;
+  const bool upd = j < k - 1;
+  const double* src[3] = {St + k * 64 + (long long)(k - 1) * 64 * lds, upd ? St + k * 64 + (long long)j * 64 * lds : nullptr,
+                          upd ? St + (k - 1) * 64 + (long long)j * 64 * lds : nullptr};
+  const double* Xk = Li + (long long)k * 64 * 64;          // L_kk^-1, row-major
+  const double* Xk1 = Li + (long long)(k - 1) * 64 * 64;
+  double v[3][16], xk[16], xk1[16], u0 = 0.0, u1 = 0.0;
+  if (t < 64) {
+    u0 = St[p.ntp + (long long)(k * 64 + t) * lds];
+    u1 = St[p.ntp + (long long)((k - 1) * 64 + t) * lds];
+  }
+#pragma unroll
+  for (int s2 = 0; s2 < 16; ++s2) {
+    const int r = g + 4 * s2;
+    xk[s2] = Xk[r * 64 + c];
+    xk1[s2] = Xk1[r * 64 + c];
+  }
+#pragma unroll
+  for (int m = 0; m < 3; ++m)
+#pragma unroll
+    for (int s2 = 0; s2 < 16; ++s2) {
+      const int e = t + 256 * s2, rr = e & 63, cc = e >> 6;
+      v[m][s2] = src[m] ? src[m][rr + (long long)cc * lds] : 0.0;
+    }
+  if (t < 64) {
+    u[0][t] = u0;
+    u[1][t] = u1;
+  }
+#pragma unroll
+  for (int m = 0; m < 3; ++m)
+    if (src[m])
+#pragma unroll
+      for (int s2 = 0; s2 < 16; ++s2) {
+        const int e = t + 256 * s2, rr = e & 63, cc = e >> 6;
+        Lt[m][cc][rr] = v[m][s2];
+      }
+  __syncthreads();
+  // y_k[c] = sum_r X_k[r][c] u_k[r]
+  double acc = 0.0;
+#pragma unroll
+  for (int s2 = 0; s2 < 16; ++s2) acc += xk[s2] * u[0][g + 4 * s2];
+  part[g][c] = acc;
+  __syncthreads();
+  if (t < 64) ys[0][t] = part[0][t] + part[1][t] + part[2][t] + part[3][t];
+  __syncthreads();
+  // u_{k-1}[c] -= sum_r L(k, k-1)[r][c] y_k[r]
+  acc = 0.0;
+#pragma unroll
+  for (int s2 = 0; s2 < 16; ++s2) {
+    const int r = g + 4 * s2;
+    acc += Lt[0][c][r] * ys[0][r];
+  }
+  part[g][c] = acc;
+  __syncthreads();
+  if (t < 64) u[1][t] -= part[0][t] + part[1][t] + part[2][t] + part[3][t];
+  __syncthreads();
+  // y_{k-1}[c] = sum_r X_{k-1}[r][c] u'_{k-1}[r]
+  acc = 0.0;
+#pragma unroll
+  for (int s2 = 0; s2 < 16; ++s2) acc += xk1[s2] * u[1][g + 4 * s2];
+  part[g][c] = acc;
+  __syncthreads();
+  if (t < 64) ys[1][t] = part[0][t] + part[1][t] + part[2][t] + part[3][t];
+  __syncthreads();
+  if (j >= k - 1) {
+    if (t < 64) yt[(long long)j * 64 + t] = ys[j == k ? 0 : 1][t];
+    return;
+  }
+  // u_j[c] -= sum_r L(k, j)[r][c] y_k[r] + L(k-1, j)[r][c] y_{k-1}[r]
+  acc = 0.0;
+#pragma unroll
+  for (int s2 = 0; s2 < 16; ++s2) {
+    const int r = g + 4 * s2;
+    acc += Lt[1][c][r] * ys[0][r] + Lt[2][c][r] * ys[1][r];
+  }
+  part[g][c] = acc;
+  __syncthreads();
+  if (t < 64) {
+    const double d = part[0][t] + part[1][t] + part[2][t] + part[3][t];
+    St[p.ntp + (long long)(j * 64 + t) * lds] -= d;
+  }
+}
+
 // y_1 = z_1 - B^T y_t (one wave per entry) and y[R^2 + q] = y_t[q].
 __global__ __launch_bounds__(256) void k_y0(SysPlan p, const double* B, const double* z,
                                             const double* yt, double* y, const int* stop) {
@@ -820,7 +940,9 @@ hipError_t launch_sys_factor_solve(const Shape& s, const SysPlan& p, const Small
     k_chol_phase<<<(unsigned)(npanel + nupd), 256, 0, st>>>(p, ph, y.St, y.Ld, y.Li, singular, stop);
   }
   k_inv_diag<<<p.Tt, 256, 0, st>>>(p, y.Ld, y.Li, stop);
-  for (int k = p.Tt - 1; k >= 0; --k) k_bsolve<<<k + 1, 256, 0, st>>>(p, k, y.St, y.Li, y.yt, stop);
+  int k = p.Tt - 1;
+  for (; k >= 1; k -= 2) k_bsolve2<<<k + 1, 256, 0, st>>>(p, k, y.St, y.Li, y.yt, stop);
+  if (k == 0) k_bsolve<<<1, 256, 0, st>>>(p, 0, y.St, y.Li, y.yt, stop);
   k_y0<<<(p.R2 + 3) / 4, 256, 0, st>>>(p, y.B, b.z, y.yt, b.y, stop);
   return hipGetLastError();
 }

@@ -28,11 +28,46 @@ __device__ __forceinline__ int rr_shift_of(int R) { return R <= 16 ? 4 : (R <= 3
   for (int q = (int)(threadIdx.x >> rr_sh); q < R; q += (int)(blockDim.x >> rr_sh)) \
     for (int r = (int)(threadIdx.x & ((1 << rr_sh) - 1)); r < R; r += (1 << rr_sh))
 
-__device__ __forceinline__ double gamma_except(const double* C, int N, int R2, int skip1, int skip2,
-                                               int e) {
+// FOR_RR for staging: the values of up to four q-steps of the thread are
+// produced first (their loads in flight together), then put stores them.
+// get(r, q) is also called for q = R - 1 in place of positions beyond R.
+template <typename Get, typename Put>
+__device__ __forceinline__ void for_rr_staged(int R, int sh, Get get, Put put) {
+  const int r = (int)(threadIdx.x & ((1 << sh) - 1)), qs = (int)(blockDim.x >> sh);
+  if (r >= R) return;
+  for (int qb = (int)(threadIdx.x >> sh); qb < R; qb += 4 * qs) {
+    decltype(get(0, 0)) v[4];
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+      const int q = qb + it * qs;
+      v[it] = get(r, q < R ? q : R - 1);
+    }
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+      const int q = qb + it * qs;
+      if (q < R) put(r, q, v[it]);
+    }
+  }
+}
+
+struct d2 {
+  double x, y;
+};
+struct d3 {
+  double x, y, z;
+};
+
+// C_k[e] for every k < N (1 beyond N), loaded together.
+__device__ __forceinline__ void load_c(const double* C, int N, int R2, int e, double (&cv)[kMaxOrder]) {
+#pragma unroll
+  for (int k = 0; k < kMaxOrder; ++k) cv[k] = (k < N) ? C[(long long)k * R2 + e] : 1.0;
+}
+
+// prod_{k != s1, s2} cv[k] (an entry of Gamma_n or Gamma_nm), multiplied in the order of k.
+__device__ __forceinline__ double prod_except(const double (&cv)[kMaxOrder], int s1, int s2) {
   double g = 1.0;
-  for (int k = 0; k < N; ++k)
-    if (k != skip1 && k != skip2) g *= C[(long long)k * R2 + e];
+#pragma unroll
+  for (int k = 0; k < kMaxOrder; ++k) g *= (k == s1 || k == s2) ? 1.0 : cv[k];
   return g;
 }
 
@@ -144,10 +179,9 @@ __global__ __launch_bounds__(256) void k_gamma(Shape s, const double* C, double 
   RR_SHIFT;
   if (blockIdx.y == 1) {
     // the (semidefinite-safe) Cholesky L_n of C_n, in parallel with the damped inverse
-    FOR_RR(r, q) {
-      const int e = r + q * R;
-      H[r][q] = C[(long long)n * R2 + e];
-    }
+    for_rr_staged(
+        R, rr_sh, [&](int r, int q) { return C[(long long)n * R2 + r + q * R]; },
+        [&](int r, int q, double v) { H[r][q] = v; });
     for (int r = t; r < R; r += 256) lk[64 + r] = C[(long long)n * R2 + r + r * R];
     chol_lds(H, R, 1, bad, lk);
     FOR_RR(r, q) {
@@ -157,12 +191,17 @@ __global__ __launch_bounds__(256) void k_gamma(Shape s, const double* C, double 
     return;
   }
   const double mu = state ? state->mu : mu_host;
-  FOR_RR(r, q) {
-    const int e = r + q * R;
-    const double g = gamma_except(C, N, R2, n, -1, e);
-    Gam[(long long)n * R2 + e] = g;
-    H[r][q] = g + (r == q ? mu : 0.0);
-  }
+  for_rr_staged(
+      R, rr_sh,
+      [&](int r, int q) {
+        double cv[kMaxOrder];
+        load_c(C, N, R2, r + q * R, cv);
+        return prod_except(cv, n, -1);
+      },
+      [&](int r, int q, double g) {
+        Gam[(long long)n * R2 + r + q * R] = g;
+        H[r][q] = g + (r == q ? mu : 0.0);
+      });
   chol_lds(H, R, 0, bad, lk);
   // Li = L^-1, one column per thread (forward substitution on the identity)
   if (t < R) lk[t] = 1.0 / H[t][t];
@@ -211,10 +250,9 @@ __global__ __launch_bounds__(256) void k_pw(Shape s, const double* A, const doub
     return;
   }
   const long long base = (long long)s.off[n] * R;
-  FOR_RR(r, q) {
-    const int e = r + q * R;
-    Gm[r][q] = resid ? Gt[(long long)n * R2 + e] : Gam[(long long)n * R2 + e];
-  }
+  const double* G0 = (resid ? Gt : Gam) + (long long)n * R2;
+  for_rr_staged(
+      R, rr_sh, [&](int r, int q) { return G0[r + q * R]; }, [&](int r, int q, double v) { Gm[r][q] = v; });
   double m2 = 0.0;
   stage_rows(As, A + base, In, r0, R);
   stage_rows(Gs, M + base, In, r0, R, &m2);
@@ -233,10 +271,9 @@ __global__ __launch_bounds__(256) void k_pw(Shape s, const double* A, const doub
       Gs[ii][r] = Ps[ii][r];
     }
     __syncthreads();
-    FOR_RR(r, q) {
-      const int e = r + q * R;
-      Gm[r][q] = Gt[(long long)n * R2 + e];
-    }
+    for_rr_staged(
+        R, rr_sh, [&](int r, int q) { return Gt[(long long)n * R2 + r + q * R]; },
+        [&](int r, int q, double v) { Gm[r][q] = v; });
     __syncthreads();
   }
   double g2 = 0.0;
@@ -305,17 +342,25 @@ __global__ __launch_bounds__(256) void k_z(Shape s, const double* C, const doubl
   __shared__ double Tm[64][LD];
   const int n = blockIdx.x, R = s.R, R2 = R * R, N = s.N;
   RR_SHIFT;
-  FOR_RR(a, b) {
-    const int e = a + b * R;
-    double v = 0.0;
-    for (int m = 0; m < N; ++m) {
-      if (m == n) continue;
-      v += gamma_except(C, N, R2, n, m, e) * w[(long long)m * R2 + b + a * R];
-    }
-    V[a][b] = v;
-    Ls[a][b] = Lc[(long long)n * R2 + e];
-    Xs[a][b] = X[(long long)n * R2 + e];
-  }
+  for_rr_staged(
+      R, rr_sh,
+      [&](int a, int b) {
+        const int e = a + b * R;
+        double cv[kMaxOrder], wv[kMaxOrder];
+        load_c(C, N, R2, e, cv);
+#pragma unroll
+        for (int m = 0; m < kMaxOrder; ++m) wv[m] = (m < N && m != n) ? w[(long long)m * R2 + b + a * R] : 0.0;
+        double v = 0.0;
+#pragma unroll
+        for (int m = 0; m < kMaxOrder; ++m)
+          if (m < N && m != n) v += prod_except(cv, n, m) * wv[m];
+        return d3{v, Lc[(long long)n * R2 + e], X[(long long)n * R2 + e]};
+      },
+      [&](int a, int b, d3 v) {
+        V[a][b] = v.x;
+        Ls[a][b] = v.y;
+        Xs[a][b] = v.z;
+      });
   __syncthreads();
   FOR_RR(a, b) {
     double acc = 0.0;
@@ -342,11 +387,18 @@ __global__ __launch_bounds__(256) void k_tnm(Shape s, const double* C, const dou
   RR_SHIFT;
   const int n = pair / N, m = pair % N;
   if (n == m) return;
-  FOR_RR(i, j) {
-    const int e = i + j * R;
-    Gs[i][j] = gamma_except(C, N, R2, n, m, e);
-    Ls[i][j] = Lc[(long long)n * R2 + e];
-  }
+  for_rr_staged(
+      R, rr_sh,
+      [&](int i, int j) {
+        const int e = i + j * R;
+        double cv[kMaxOrder];
+        load_c(C, N, R2, e, cv);
+        return d2{prod_except(cv, n, m), Lc[(long long)n * R2 + e]};
+      },
+      [&](int i, int j, d2 v) {
+        Gs[i][j] = v.x;
+        Ls[i][j] = v.y;
+      });
   for (int j = t; j < R; j += 256) xd[j] = X[(long long)m * R2 + j + d * R];
   __syncthreads();
   double* out = Tnm + (long long)pair * R * R2;
@@ -369,12 +421,17 @@ __global__ __launch_bounds__(256) void k_u(Shape s, const double* w, const doubl
   __shared__ double Xs[64][LD];
   const int n = blockIdx.x, R = s.R, R2 = R * R;
   RR_SHIFT;
-  FOR_RR(r, q) {
-    const long long e = (long long)n * R2 + r + q * R;
-    Ys[r][q] = y[e];
-    Ls[r][q] = Lc[e];
-    Xs[r][q] = X[e];
-  }
+  for_rr_staged(
+      R, rr_sh,
+      [&](int r, int q) {
+        const long long e = (long long)n * R2 + r + q * R;
+        return d3{y[e], Lc[e], X[e]};
+      },
+      [&](int r, int q, d3 v) {
+        Ys[r][q] = v.x;
+        Ls[r][q] = v.y;
+        Xs[r][q] = v.z;
+      });
   __syncthreads();
   FOR_RR(a, b) {
     double acc = 0.0;
@@ -399,17 +456,25 @@ __global__ __launch_bounds__(256) void k_fq(Shape s, const double* C, const doub
   __shared__ double Gs[64][LD];
   const int n = blockIdx.x, R = s.R, R2 = R * R, N = s.N;
   RR_SHIFT;
-  FOR_RR(a, b) {
-    const int e = a + b * R;
-    Gs[a][b] = Gt[(long long)n * R2 + e];
-    double v = 0.0;
-    for (int m = 0; m < N; ++m) {
-      if (m == n) continue;
-      v += gamma_except(C, N, R2, n, m, e) * u[(long long)m * R2 + b + a * R];
-    }
-    f[(long long)n * R2 + e] = v;
-    Fs[a][b] = v;
-  }
+  for_rr_staged(
+      R, rr_sh,
+      [&](int a, int b) {
+        const int e = a + b * R;
+        double cv[kMaxOrder], uv[kMaxOrder];
+        load_c(C, N, R2, e, cv);
+#pragma unroll
+        for (int m = 0; m < kMaxOrder; ++m) uv[m] = (m < N && m != n) ? u[(long long)m * R2 + b + a * R] : 0.0;
+        double v = 0.0;
+#pragma unroll
+        for (int m = 0; m < kMaxOrder; ++m)
+          if (m < N && m != n) v += prod_except(cv, n, m) * uv[m];
+        return d2{Gt[(long long)n * R2 + e], v};
+      },
+      [&](int a, int b, d2 v) {
+        Gs[a][b] = v.x;
+        f[(long long)n * R2 + a + b * R] = v.y;
+        Fs[a][b] = v.y;
+      });
   __syncthreads();
   FOR_RR(a, b) {
     const int e = a + b * R;
@@ -440,7 +505,9 @@ __global__ __launch_bounds__(256) void k_update(Shape s, const double* A, const 
   }
   const double mu = state ? state->mu : mu_host;
   const long long base = (long long)s.off[n] * R;
-  FOR_RR(r, q) Qs[r][q] = Q[(long long)n * R2 + r + q * R];
+  for_rr_staged(
+      R, rr_sh, [&](int r, int q) { return Q[(long long)n * R2 + r + q * R]; },
+      [&](int r, int q, double v) { Qs[r][q] = v; });
   stage_rows(As, A + base, In, r0, R);
   __syncthreads();
   double den = 0.0, da2 = 0.0;

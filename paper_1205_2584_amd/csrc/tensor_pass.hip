@@ -167,6 +167,12 @@ __global__ __launch_bounds__(256) void k_pass_fma(PassArgs a, const int* stop) {
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 constexpr int kQMax = 16;  // slabs per block of the MFMA kernels (t and c_q staged in LDS)
+// Slabs in flight ahead of the computed one (the ring of slab registers): the
+// FP32 slab takes about 2k MFMA cycles per wave, the BF16 slab a fraction of
+// that, and both must cover the HBM latency.  kQMax is a multiple of both.
+constexpr int kPrefetchF32 = 2;
+constexpr int kPrefetchBf16 = 4;
+static_assert(kQMax % kPrefetchF32 == 0 && kQMax % kPrefetchBf16 == 0, "sub-chunks align with the ring");
 
 __device__ __forceinline__ float fac(const PassArgs& a, int mode, int Im, int i, int r) {
   return (i < Im && r < a.R) ? (float)a.A[a.off[mode] + i + (long long)r * Im] : 0.0f;
@@ -264,8 +270,9 @@ __global__ __launch_bounds__(256) void k_pass_f32(PassArgs a, const int* stop) {
   for (int nb = 0; nb < NB; ++nb) { m0acc[nb] = v4f{0, 0, 0, 0}; m1acc[nb] = v4f{0, 0, 0, 0}; }
   double e2 = 0.0;
 
-  v4f pf[4];
-  auto load = [&](long long q) {
+  // slab loads run kPrefetchF32 slabs ahead of the slab being computed
+  v4f pf[kPrefetchF32][4];
+  auto load = [&](long long q, v4f (&dst)[4]) {
     const long long base = (long long)I0 * I1 * q;
 #pragma unroll
     for (int s2 = 0; s2 < 4; ++s2) {
@@ -281,27 +288,35 @@ __global__ __launch_bounds__(256) void k_pass_f32(PassArgs a, const int* stop) {
           for (int k = 0; k < 4; ++k) v[k] = (gi + k < I0) ? src[k] : 0.0f;
         }
       }
-      pf[s2] = v;
+      dst[s2] = v;
     }
   };
-  if (q0 < q1) load(q0);
-  for (long long sq0 = q0; sq0 < q1; sq0 += kQMax) {
-  // sub-chunk [sq0, sq1) of at most kQMax slabs: c_q staged here, t flushed after
-  const long long sq1 = (sq0 + kQMax < q1) ? sq0 + kQMax : q1;
-  __syncthreads();
-  for (int e = t; e < kQMax * 64; e += 256) {
-    const int ql = e >> 6, r = e & 63;
-    cq_all[ql][r] = (sq0 + ql < sq1) ? cq_of(a, sq0 + ql, r) : 0.0f;
+#pragma unroll
+  for (int d = 0; d < kPrefetchF32; ++d)
+    if (q0 + d < q1) load(q0 + d, pf[d]);
+  for (long long qb = q0; qb < q1; qb += kPrefetchF32) {
+  if ((qb - q0) % kQMax == 0) {
+    // new sub-chunk of at most kQMax slabs: t of the previous one flushed, c_q staged
+    if (qb > q0) flush_t(a, tq_s, qb - kQMax, qb, tile);
+    const long long sq1 = (qb + kQMax < q1) ? qb + kQMax : q1;
+    for (int e = t; e < kQMax * 64; e += 256) {
+      const int ql = e >> 6, r = e & 63;
+      cq_all[ql][r] = (qb + ql < sq1) ? cq_of(a, qb + ql, r) : 0.0f;
+    }
   }
-  for (long long q = sq0; q < sq1; ++q) {
+#pragma unroll
+  for (int d = 0; d < kPrefetchF32; ++d) {
+    const long long q = qb + d;
+    if (q >= q1) break;
+    const int ql = (int)((q - q0) % kQMax);
     __syncthreads();
 #pragma unroll
     for (int s2 = 0; s2 < 4; ++s2) {
       const int e = t + 256 * s2, jj = e >> 4, ii = (e & 15) * 4;
-      *reinterpret_cast<v4f*>(&Ys[jj][ii]) = pf[s2];
+      *reinterpret_cast<v4f*>(&Ys[jj][ii]) = pf[d][s2];
     }
-    const float* cq_s = cq_all[q - sq0];
-    if (q + 1 < q1) load(q + 1);
+    const float* cq_s = cq_all[ql];
+    if (q + kPrefetchF32 < q1) load(q + kPrefetchF32, pf[d]);
     __syncthreads();
     if (RESID) {
       constexpr int KS = NB * 4;  // R padded to 16, in steps of 4
@@ -343,7 +358,6 @@ __global__ __launch_bounds__(256) void k_pass_f32(PassArgs a, const int* stop) {
         for (int nb = 0; nb < NB; ++nb)
           wacc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(y4[s2], b0[4 * kb + s2][nb], wacc[nb], 0, 0, 0);
     }
-    const int ql = (int)(q - sq0);
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
       const float c = cq_s[16 * nb + c16];
@@ -356,8 +370,8 @@ __global__ __launch_bounds__(256) void k_pass_f32(PassArgs a, const int* stop) {
       if (g == 0) tq_s[w][ql][16 * nb + c16] = tv;
     }
   }
-  flush_t(a, tq_s, sq0, sq1, tile);
   }
+  if (q0 < q1) flush_t(a, tq_s, q0 + ((q1 - q0 - 1) / kQMax) * kQMax, q1, tile);
   write_m<NB>(a, ti, tj, i0, j0, m0acc, m1acc);
   if (RESID) {
     const double s2 = block_sum(e2, red);
@@ -415,8 +429,9 @@ __global__ __launch_bounds__(256) void k_pass_bf16(PassArgs a, const int* stop) 
   for (int nb = 0; nb < NB; ++nb) { m0acc[nb] = v4f{0, 0, 0, 0}; m1acc[nb] = v4f{0, 0, 0, 0}; }
 
   typedef unsigned short us4 __attribute__((ext_vector_type(4)));
-  us4 pf[4];
-  auto load = [&](long long q) {
+  // slab loads run kPrefetchBf16 slabs ahead of the slab being computed
+  us4 pf[kPrefetchBf16][4];
+  auto load = [&](long long q, us4 (&dst)[4]) {
     const long long base = (long long)I0 * I1 * q;
     const unsigned short* Yu = reinterpret_cast<const unsigned short*>(Y);
 #pragma unroll
@@ -433,27 +448,35 @@ __global__ __launch_bounds__(256) void k_pass_bf16(PassArgs a, const int* stop) 
           for (int k = 0; k < 4; ++k) v[k] = (gi + k < I0) ? src[k] : (unsigned short)0;
         }
       }
-      pf[s2] = v;
+      dst[s2] = v;
     }
   };
-  if (q0 < q1) load(q0);
-  for (long long sq0 = q0; sq0 < q1; sq0 += kQMax) {
-  // sub-chunk [sq0, sq1) of at most kQMax slabs: c_q staged here, t flushed after
-  const long long sq1 = (sq0 + kQMax < q1) ? sq0 + kQMax : q1;
-  __syncthreads();
-  for (int e = t; e < kQMax * 64; e += 256) {
-    const int ql = e >> 6, r = e & 63;
-    cq_all[ql][r] = (sq0 + ql < sq1) ? cq_of(a, sq0 + ql, r) : 0.0f;
+#pragma unroll
+  for (int d = 0; d < kPrefetchBf16; ++d)
+    if (q0 + d < q1) load(q0 + d, pf[d]);
+  for (long long qb = q0; qb < q1; qb += kPrefetchBf16) {
+  if ((qb - q0) % kQMax == 0) {
+    // new sub-chunk of at most kQMax slabs: t of the previous one flushed, c_q staged
+    if (qb > q0) flush_t(a, tq_s, qb - kQMax, qb, tile);
+    const long long sq1 = (qb + kQMax < q1) ? qb + kQMax : q1;
+    for (int e = t; e < kQMax * 64; e += 256) {
+      const int ql = e >> 6, r = e & 63;
+      cq_all[ql][r] = (qb + ql < sq1) ? cq_of(a, qb + ql, r) : 0.0f;
+    }
   }
-  for (long long q = sq0; q < sq1; ++q) {
+#pragma unroll
+  for (int d = 0; d < kPrefetchBf16; ++d) {
+    const long long q = qb + d;
+    if (q >= q1) break;
+    const int ql = (int)((q - q0) % kQMax);
     __syncthreads();
 #pragma unroll
     for (int s2 = 0; s2 < 4; ++s2) {
       const int e = t + 256 * s2, jj = e >> 4, ii = (e & 15) * 4;
-      *reinterpret_cast<us4*>(&Ys[jj][ii]) = pf[s2];
+      *reinterpret_cast<us4*>(&Ys[jj][ii]) = pf[d][s2];
     }
-    const float* cq_s = cq_all[q - sq0];
-    if (q + 1 < q1) load(q + 1);
+    const float* cq_s = cq_all[ql];
+    if (q + kPrefetchBf16 < q1) load(q + kPrefetchBf16, pf[d]);
     __syncthreads();
     v4f zacc[NB], wacc[NB];
 #pragma unroll
@@ -475,7 +498,6 @@ __global__ __launch_bounds__(256) void k_pass_bf16(PassArgs a, const int* stop) 
         wacc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(yv, b0l[ks][nb], wacc[nb], 0, 0, 0);
       }
     }
-    const int ql = (int)(q - sq0);
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
       const float c = cq_s[16 * nb + c16];
@@ -488,8 +510,8 @@ __global__ __launch_bounds__(256) void k_pass_bf16(PassArgs a, const int* stop) 
       if (g == 0) tq_s[w][ql][16 * nb + c16] = tv;
     }
   }
-  flush_t(a, tq_s, sq0, sq1, tile);
   }
+  if (q0 < q1) flush_t(a, tq_s, q0 + ((q1 - q0 - 1) / kQMax) * kQMax, q1, tile);
   write_m<NB>(a, ti, tj, i0, j0, m0acc, m1acc);
 }
 
