@@ -338,12 +338,15 @@ __global__ __launch_bounds__(256) void k_fill(SysPlan p, double* St, double* B, 
 }
 
 // R x R sub-block (b, d) of S_nm for n > m: rows n R^2 + a + b R, columns m R^2 + c + d R.
+// RM: the rank bound the LDS tiles are sized for (32 or 64), so that ranks up to
+// 32 keep several blocks per CU.
+template <int RM>
 __global__ __launch_bounds__(256) void k_subblock(Shape s, SysPlan p, const double* Tnm,
                                                   const double* X, const double* Lc, double* St,
                                                   double* B, const int* stop) {
   if (stopped(stop)) return;
-  __shared__ double Td[64][LD];  // Td[i][a] = T_nm[i, a + dR]
-  __shared__ double Lm[64][LD];
+  __shared__ double Td[RM][RM + 1];  // Td[i][a] = T_nm[i, a + dR]
+  __shared__ double Lm[RM][RM + 1];
   const int N = s.N, R = s.R, R2 = R * R;
   // decode the strictly lower pair (n, m), n > m
   int pr = blockIdx.x / R, b = blockIdx.x % R, d = blockIdx.y;
@@ -356,20 +359,21 @@ __global__ __launch_bounds__(256) void k_subblock(Shape s, SysPlan p, const doub
   {
     // all loads of the thread in flight at once; x_b folded into T on the way to LDS:
     // Td[i][a] = x_b[i] T_nm[i, a + dR], Lm[i][c] = L_m[i, c]
-    const int i = threadIdx.x & 63, a0 = threadIdx.x >> 6;
+    constexpr int NS = RM * RM / 256;  // entries per thread
+    const int i = threadIdx.x & (RM - 1), a0 = threadIdx.x / RM;
     const bool iok = i < R;
-    double tv[16], lv[16];
+    double tv[NS], lv[NS];
 #pragma unroll
-    for (int s2 = 0; s2 < 16; ++s2) {
-      const int a = a0 + 4 * s2;
+    for (int s2 = 0; s2 < NS; ++s2) {
+      const int a = a0 + (256 / RM) * s2;
       const bool ok = iok && a < R;
       tv[s2] = ok ? T[((long long)a + (long long)d * R) * R + i] : 0.0;
       lv[s2] = ok ? Lc[(long long)m * R2 + i + a * R] : 0.0;
     }
     const double xbi = iok ? X[(long long)n * R2 + i + b * R] : 0.0;
 #pragma unroll
-    for (int s2 = 0; s2 < 16; ++s2) {
-      const int a = a0 + 4 * s2;
+    for (int s2 = 0; s2 < NS; ++s2) {
+      const int a = a0 + (256 / RM) * s2;
       if (iok && a < R) {
         Td[i][a] = tv[s2] * xbi;
         Lm[i][a] = lv[s2];
@@ -895,7 +899,10 @@ hipError_t launch_sys_assemble(const Shape& s, const SysPlan& p, const SmallBuff
   long long extra = nbblocks < 1024 ? nbblocks : 1024;
   k_fill<<<(unsigned)(ntri + extra), 256, 0, st>>>(p, y.St, y.B, R2p, stop);
   const int npairs = s.N * (s.N - 1) / 2;
-  k_subblock<<<dim3(npairs * s.R, s.R), 256, 0, st>>>(s, p, b.Tnm, b.X, b.Lc, y.St, y.B, stop);
+  if (s.R <= 32)
+    k_subblock<32><<<dim3(npairs * s.R, s.R), 256, 0, st>>>(s, p, b.Tnm, b.X, b.Lc, y.St, y.B, stop);
+  else
+    k_subblock<64><<<dim3(npairs * s.R, s.R), 256, 0, st>>>(s, p, b.Tnm, b.X, b.Lc, y.St, y.B, stop);
   k_rhs<<<p.ntp / 64, 1024, 0, st>>>(p, y.B, b.z, y.St, stop);
   k_syrk<<<(unsigned)((long long)p.Tt * (p.Tt + 1) / 2), 256, 0, st>>>(p, y.B, R2p, y.St, stop);
   return hipGetLastError();

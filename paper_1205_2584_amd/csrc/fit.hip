@@ -20,8 +20,15 @@ __device__ double err2_of(const Shape& s, const double* A, const double* M, cons
                           int resid, const double* e2, double ynorm2_pass, double* red) {
   if (resid) return e2[0];
   const int R = s.R, R2 = R * R, I0 = s.I[0];
-  double inner = 0.0;
-  for (int e = threadIdx.x; e < I0 * R; e += blockDim.x) inner += A[e] * M[e];
+  // 16 independent loads per thread in flight: the operands are a few hundred KB
+  const int n = I0 * R, bd = blockDim.x;
+  double part[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  int e = threadIdx.x;
+  for (; e + 7 * bd < n; e += 8 * bd)
+#pragma unroll
+    for (int q = 0; q < 8; ++q) part[q] += A[e + q * bd] * M[e + q * bd];
+  for (; e < n; e += bd) part[0] += A[e] * M[e];
+  double inner = ((part[0] + part[1]) + (part[2] + part[3])) + ((part[4] + part[5]) + (part[6] + part[7]));
   inner = block_sum(inner, red);
   double yh = 0.0;
   for (int e = threadIdx.x; e < R2; e += blockDim.x) {
