@@ -230,7 +230,11 @@ template <int NB, bool RESID>
 __global__ __launch_bounds__(256) void k_pass_f32(PassArgs a, const int* stop) {
   if (stopped(stop)) return;
   constexpr int LDY = 68;
-  __shared__ __attribute__((aligned(16))) float Ys[64][LDY];  // Ys[j][i]
+  // Ys[slab parity][j][i]: the slab is written into one buffer while the other
+  // may still be read, so one barrier per slab suffices.  The residual form keeps
+  // one buffer (and a second barrier) to stay at two workgroups per CU.
+  constexpr int NBUF = RESID ? 1 : 2;
+  __shared__ __attribute__((aligned(16))) float Ysb[NBUF][64][LDY];
   __shared__ float cq_all[kQMax][64];
   __shared__ float tq_s[4][kQMax][64];  // per-wave partial t, summed in wave order
   __shared__ float A0s[RESID ? 64 : 1][65];
@@ -309,7 +313,8 @@ __global__ __launch_bounds__(256) void k_pass_f32(PassArgs a, const int* stop) {
     const long long q = qb + d;
     if (q >= q1) break;
     const int ql = (int)((q - q0) % kQMax);
-    __syncthreads();
+    float (*Ys)[LDY] = Ysb[(q - q0) & (NBUF - 1)];
+    if (NBUF == 1) __syncthreads();
 #pragma unroll
     for (int s2 = 0; s2 < 4; ++s2) {
       const int e = t + 256 * s2, jj = e >> 4, ii = (e & 15) * 4;
@@ -391,7 +396,8 @@ template <int NB>
 __global__ __launch_bounds__(256) void k_pass_bf16(PassArgs a, const int* stop) {
   if (stopped(stop)) return;
   constexpr int LDY = 72;
-  __shared__ __attribute__((aligned(16))) __bf16 Ys[64][LDY];  // Ys[j][i]
+  // Ys[slab parity][j][i]: one barrier per slab (see k_pass_f32)
+  __shared__ __attribute__((aligned(16))) __bf16 Ysb[2][64][LDY];
   __shared__ float cq_all[kQMax][64];
   __shared__ float tq_s[4][kQMax][64];  // per-wave partial t, summed in wave order
   const int t = threadIdx.x, lane = t & 63, w = t >> 6, g = lane >> 4, c16 = lane & 15;
@@ -469,7 +475,7 @@ __global__ __launch_bounds__(256) void k_pass_bf16(PassArgs a, const int* stop) 
     const long long q = qb + d;
     if (q >= q1) break;
     const int ql = (int)((q - q0) % kQMax);
-    __syncthreads();
+    __bf16 (*Ys)[LDY] = Ysb[(q - q0) & 1];
 #pragma unroll
     for (int s2 = 0; s2 < 4; ++s2) {
       const int e = t + 256 * s2, jj = e >> 4, ii = (e & 15) * 4;
