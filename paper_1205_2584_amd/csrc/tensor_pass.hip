@@ -295,6 +295,7 @@ __global__ __launch_bounds__(256) void k_pass_f32(PassArgs a, const int* stop) {
       dst[s2] = v;
     }
   };
+
 #pragma unroll
   for (int d = 0; d < kPrefetchF32; ++d)
     if (q0 + d < q1) load(q0 + d, pf[d]);
@@ -437,24 +438,38 @@ __global__ __launch_bounds__(256) void k_pass_bf16(PassArgs a, const int* stop) 
   typedef unsigned short us4 __attribute__((ext_vector_type(4)));
   // slab loads run kPrefetchBf16 slabs ahead of the slab being computed
   us4 pf[kPrefetchBf16][4];
+  // this thread's four 4-element pieces of a slab: offset within the slab and
+  // how many of the 4 elements lie inside the tensor (an out-of-range piece
+  // reads the slab's first element and is zeroed, so every load is unconditional)
+  long long poff[4];
+  int pn[4];
+#pragma unroll
+  for (int s2 = 0; s2 < 4; ++s2) {
+    const int e = t + 256 * s2, jj = e >> 4, ii = (e & 15) * 4;
+    const int gi = i0 + ii, gj = j0 + jj;
+    const int n = (gj < I1) ? (I0 - gi < 0 ? 0 : (I0 - gi > 4 ? 4 : I0 - gi)) : 0;
+    pn[s2] = n;
+    poff[s2] = n > 0 ? (long long)gj * I0 + gi : 0;
+  }
   auto load = [&](long long q, us4 (&dst)[4]) {
-    const long long base = (long long)I0 * I1 * q;
-    const unsigned short* Yu = reinterpret_cast<const unsigned short*>(Y);
+    const unsigned short* base = reinterpret_cast<const unsigned short*>(Y) + (long long)I0 * I1 * q;
+    if (vec_ok) {
 #pragma unroll
-    for (int s2 = 0; s2 < 4; ++s2) {
-      const int e = t + 256 * s2, jj = e >> 4, ii = (e & 15) * 4;
-      const int gi = i0 + ii, gj = j0 + jj;
-      us4 v = us4{0, 0, 0, 0};
-      if (gj < I1) {
-        const unsigned short* src = Yu + base + (long long)gj * I0 + gi;
-        if (vec_ok && gi + 3 < I0) {
-          v = *reinterpret_cast<const us4*>(src);
-        } else {
-#pragma unroll
-          for (int k = 0; k < 4; ++k) v[k] = (gi + k < I0) ? src[k] : (unsigned short)0;
-        }
+      for (int s2 = 0; s2 < 4; ++s2) {
+        const us4 v = *reinterpret_cast<const us4*>(base + poff[s2]);
+        dst[s2] = pn[s2] == 4 ? v : us4{0, 0, 0, 0};
       }
-      dst[s2] = v;
+    } else {
+#pragma unroll
+      for (int s2 = 0; s2 < 4; ++s2) {
+        us4 v;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const unsigned short x = base[poff[s2] + (k < pn[s2] ? k : 0)];
+          v[k] = k < pn[s2] ? x : (unsigned short)0;
+        }
+        dst[s2] = v;
+      }
     }
   };
 #pragma unroll
