@@ -120,7 +120,7 @@ __global__ __launch_bounds__(256) void k_pass_c(PassArgsC a, const int* stop) {
   __shared__ double red[16];
   const int t = threadIdx.x, l32 = t & 31, rg = t >> 5;
   const int R = a.R, I0 = a.I0, I1 = a.I1;
-  const int tile = blockIdx.x, ti = tile % a.tiles_i, tj = tile / a.tiles_i;
+  const int tile = blockIdx.x, tj = tile % a.tiles_j, ti = tile / a.tiles_j;
   const int i0 = ti * TC, j0 = tj * TC;
   const long long q0 = (long long)blockIdx.y * a.q_per;
   long long q1 = q0 + a.q_per;

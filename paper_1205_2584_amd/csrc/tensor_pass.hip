@@ -48,7 +48,7 @@ __global__ __launch_bounds__(256) void k_pass_fma(PassArgs a, const int* stop) {
   const int t = threadIdx.x, lane = t & 63, rg = t >> 6;
   const int R = a.R, I0 = a.I0, I1 = a.I1;
   const int tile = blockIdx.x;
-  const int ti = tile % a.tiles_i, tj = tile / a.tiles_i;
+  const int tj = tile % a.tiles_j, ti = tile / a.tiles_j;
   const int i0 = ti * 64, j0 = tj * 64;
   const long long q0 = (long long)blockIdx.y * a.q_per;
   long long q1 = q0 + a.q_per;
@@ -162,6 +162,10 @@ __global__ __launch_bounds__(256) void k_pass_fma(PassArgs a, const int* stop) {
 // reads four (FP32) or eight (BF16) consecutive i with one LDS vector load;
 // the factor operand uses the same permutation.  Result layout of both
 // 16x16 instructions: D[4 (l/16) + v][l%16].
+// Tiles are numbered with the j-tile fastest.  Workgroups are dealt to the
+// XCDs in turn, so a run of consecutive workgroups shares one i-tile row and
+// each XCD sees the i-neighbours of its tiles; their row segments share the
+// 128-byte lines at the tile edges, which then meet in one L2.
 // ---------------------------------------------------------------------------
 
 typedef float v4f __attribute__((ext_vector_type(4)));
@@ -242,7 +246,7 @@ __global__ __launch_bounds__(256) void k_pass_f32(PassArgs a, const int* stop) {
   __shared__ double red[16];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6, g = lane >> 4, c16 = lane & 15;
   const int I0 = a.I0, I1 = a.I1;
-  const int tile = blockIdx.x, ti = tile % a.tiles_i, tj = tile / a.tiles_i;
+  const int tile = blockIdx.x, tj = tile % a.tiles_j, ti = tile / a.tiles_j;
   const int i0 = ti * 64, j0 = tj * 64;
   const long long q0 = (long long)blockIdx.y * a.q_per;
   const long long q1 = (q0 + a.q_per < a.Q) ? q0 + a.q_per : a.Q;
@@ -403,7 +407,7 @@ __global__ __launch_bounds__(256) void k_pass_bf16(PassArgs a, const int* stop) 
   __shared__ float tq_s[4][kQMax][64];  // per-wave partial t, summed in wave order
   const int t = threadIdx.x, lane = t & 63, w = t >> 6, g = lane >> 4, c16 = lane & 15;
   const int I0 = a.I0, I1 = a.I1;
-  const int tile = blockIdx.x, ti = tile % a.tiles_i, tj = tile / a.tiles_i;
+  const int tile = blockIdx.x, tj = tile % a.tiles_j, ti = tile / a.tiles_j;
   const int i0 = ti * 64, j0 = tj * 64;
   const long long q0 = (long long)blockIdx.y * a.q_per;
   const long long q1 = (q0 + a.q_per < a.Q) ? q0 + a.q_per : a.Q;
