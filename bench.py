@@ -60,8 +60,8 @@ def syrk_flops(N, R):
 # for the kernel source whose SHA-256 prefix is given; once that source changes
 # the figure no longer describes the kernel and is reported as null.
 TRAFFIC = {
-    "factor_solve": ("paper_1205_2584_amd/csrc/chol.hip", "755ee66a2b98edf9", 465560964),
-    "tensor_pass_f32": ("paper_1205_2584_amd/csrc/tensor_pass.hip", "c7c872e7ba136dd3", 812813348),
+    "factor_solve": ("paper_1205_2584_amd/csrc/chol.hip", "cbddbf545a71d6be", 466292037),
+    "tensor_pass_f32": ("paper_1205_2584_amd/csrc/tensor_pass.hip", "94f2716394b141e1", 546599604),
 }
 
 
@@ -222,10 +222,12 @@ def oracle_check(dgn, torch, p, ref, mu):
 
 
 def precision_report(dgn, torch, p):
-    """The same fit run to convergence (|delta eps| < 1e-8 or 200 trials) from
-    the FP64, FP32 and BF16 tensors; the mixed paths switch to the residual form
-    of the error near convergence.  Reports each final eps and its difference
-    from the FP64 path's."""
+    """The same fit run for 200 trials with no early stop from the FP64, FP32
+    and BF16 tensors (the mixed paths switch to the residual form of the error
+    near convergence), so that each path reaches the accuracy it can resolve.
+    Reports each final eps and its difference from the FP64 path's.  (With a
+    stop test |delta eps| < 1e-8 the FP32 path's stopping point is set by the
+    noise of its FP32 residual, about 3e-10 ||Y||^2 in eps^2, and can come early.)"""
     y64 = torch.from_numpy(p.y).cuda()
     y32 = y64.float()
     ybf = y32.to(torch.bfloat16)
@@ -233,7 +235,7 @@ def precision_report(dgn, torch, p):
     res = {}
     for name, y, o in (("f64", y64, dgn.opts()), ("f32", y32, dgn.opts()), ("bf16", y32, dgn.opts(y_bf16=ybf))):
         A = dgn.to_device_factors(p.init)
-        fi = ctx.cp_fit(y, p.dims, p.R, A, -1.0, 1e-8, 200, o)
+        fi = ctx.cp_fit(y, p.dims, p.R, A, -1.0, 0.0, 200, o)
         res[name] = {"eps": fi["eps"], "iters": fi["iters"], "accepted": fi["accepted"],
                      "reason": fi["reason"], "resid_iters": fi["resid_iters"]}
     ctx.close()
