@@ -79,7 +79,7 @@ __device__ double bpass(const BFit& f, const double* Ain, double* Mout, int resi
   double* M1 = Mout + (long long)I0 * R;
   double* M2 = M1 + (long long)I1 * R;
   auto& P = S.u.pass;
-  __syncthreads();
+  sync_block();
   for (int e = t; e < BI * BR; e += 256) {
     const int ii = e & 63, r = e >> 6;
     P.A0s[ii][r] = (ii < I0 && r < R) ? A0[ii + (long long)r * I0] : 0.0;
@@ -88,14 +88,14 @@ __device__ double bpass(const BFit& f, const double* Ain, double* Mout, int resi
   double m0[2] = {0.0, 0.0}, m1[2] = {0.0, 0.0};
   double e2 = 0.0;
   for (int q = 0; q < I2; ++q) {
-    __syncthreads();
+    sync_block();
     const long long base = (long long)I0 * I1 * q;
     for (int e = t; e < BI * BI; e += 256) {
       const int ii = e & 63, jj = e >> 6;
       P.Ys[jj][ii] = (ii < I0 && jj < I1) ? to_f64(Y[base + ii + (long long)I0 * jj]) : 0.0;
     }
     if (t < BR) P.cq[t] = (t < R) ? A2[q + (long long)t * I2] : 0.0;
-    __syncthreads();
+    sync_block();
     if (resid) {
       for (int e = t; e < BI * BI; e += 256) {
         const int ii = e & 63, jj = e >> 6;
@@ -107,7 +107,7 @@ __device__ double bpass(const BFit& f, const double* Ain, double* Mout, int resi
           P.Ys[jj][ii] = ev;
         }
       }
-      __syncthreads();
+      sync_block();
     }
     double zp[2] = {0.0, 0.0}, wp[2] = {0.0, 0.0};
     for (int jj = 0; jj < I1; ++jj) {
@@ -138,7 +138,7 @@ __device__ double bpass(const BFit& f, const double* Ain, double* Mout, int resi
       if (lane < I1) M1[lane + (long long)r * I1] = m1[k];
     }
   }
-  __syncthreads();
+  sync_block();
   double out;
   if (resid) {
     out = block_sum(e2, S.red);
@@ -169,7 +169,7 @@ __device__ double yhat2(const BFit& f, const double (*Cs)[BR2], Smem& S) {
 // Grams of the stacked factors Ain into Cdst (LDS) and Cglob.
 __device__ void grams(const BFit& f, const double* Ain, double (*Cdst)[BR2], double* Cglob) {
   const int t = threadIdx.x, R = f.R;
-  __syncthreads();
+  sync_block();
   if (t < 3 * BR2) {
     const int n = t >> 6, e = t & 63, r = e & 7, q = e >> 3;
     if (r < R && q < R) {
@@ -181,7 +181,7 @@ __device__ void grams(const BFit& f, const double* Ain, double (*Cdst)[BR2], dou
       Cglob[n * BR2 + r + q * R] = acc;
     }
   }
-  __syncthreads();
+  sync_block();
 }
 
 __device__ double gamma_of(const double (*Cs)[BR2], int skip1, int skip2, int e) {
@@ -335,13 +335,13 @@ __global__ __launch_bounds__(256) void k_btrial(BFit* fits, int nfits, BatchCfg 
     }
   }
   const double mu = st->mu;
-  __syncthreads();
+  sync_block();
   // Grams of the current factors (kept in the workspace)
   for (int e = t; e < 3 * BR2; e += 256) S.Cs[e >> 6][e & 63] = f.C[e];
-  __syncthreads();
+  sync_block();
   // S1: R x R work per mode
   if (t == 0 || t == 64 || t == 128) rr_mode(f, t >> 6, mu, S);
-  __syncthreads();
+  sync_block();
   // S2: gradient rows G, P = G Gt
   if (t < T) {
     int i;
@@ -366,7 +366,7 @@ __global__ __launch_bounds__(256) void k_btrial(BFit* fits, int nfits, BatchCfg 
       f.P[o + i + (long long)r * In] = acc;
     }
   }
-  __syncthreads();
+  sync_block();
   // w_n = vec(A_n^T P_n)
   if (t < 3 * BR2) {
     const int n = t >> 6, e = t & 63, a = e & 7, b = e >> 3;
@@ -378,7 +378,7 @@ __global__ __launch_bounds__(256) void k_btrial(BFit* fits, int nfits, BatchCfg 
       S.w[n * R2 + a + b * R] = acc;
     }
   }
-  __syncthreads();
+  sync_block();
   // S3: z_n = vec(L_n^T (sum_{m != n} Gamma_nm * W_m^T) X_n)
   {
     auto& rr = S.u.rr;
@@ -391,7 +391,7 @@ __global__ __launch_bounds__(256) void k_btrial(BFit* fits, int nfits, BatchCfg 
         rr.V[n][a + b * R] = v;
       }
     }
-    __syncthreads();
+    sync_block();
     if (t < 3 * BR2) {
       const int n = t >> 6, e = t & 63, a = e & 7, b = e >> 3;
       if (a < R && b < R) {
@@ -400,7 +400,7 @@ __global__ __launch_bounds__(256) void k_btrial(BFit* fits, int nfits, BatchCfg 
         rr.T1[n][a + b * R] = acc;
       }
     }
-    __syncthreads();
+    sync_block();
     if (t < 3 * BR2) {
       const int n = t >> 6, e = t & 63, a = e & 7, b = e >> 3;
       if (a < R && b < R) {
@@ -409,13 +409,13 @@ __global__ __launch_bounds__(256) void k_btrial(BFit* fits, int nfits, BatchCfg 
         S.z[n * R2 + a + b * R] = acc;
       }
     }
-    __syncthreads();
+    sync_block();
   }
   // S4: trailing system (packed lower, rows 0..nt with the RHS as row nt) and B
   auto& Y = S.u.sys;
   for (int p = t; p < nt; p += 256)
     for (int q = 0; q <= p; ++q) Y.Sp[pidx(p, q)] = (p == q) ? 1.0 : 0.0;
-  __syncthreads();
+  sync_block();
   for (int pr = 0; pr < 3; ++pr) {
     const int n = (pr == 0) ? 1 : 2, m = (pr == 2) ? 1 : 0;
     // Tb[(a + d R) R + i] = sum_j Gamma_nm[i,j] L_n[j,a] X_m[j,d]
@@ -425,7 +425,7 @@ __global__ __launch_bounds__(256) void k_btrial(BFit* fits, int nfits, BatchCfg 
       for (int j = 0; j < R; ++j) acc += gamma_of(S.Cs, n, m, i + j * R) * S.Ls[n][j + a * R] * S.Xs[m][j + d * R];
       Y.Tb[e] = acc;
     }
-    __syncthreads();
+    sync_block();
     for (int e = t; e < R2 * R2; e += 256) {
       const int a = e % R, b = (e / R) % R, c = (e / R2) % R, d = e / (R2 * R);
       double acc = 0.0;
@@ -434,7 +434,7 @@ __global__ __launch_bounds__(256) void k_btrial(BFit* fits, int nfits, BatchCfg 
       if (m == 0) Y.Bm[p][c + d * R] = acc;
       else Y.Sp[pidx(p, (m - 1) * R2 + c + d * R)] = acc;
     }
-    __syncthreads();
+    sync_block();
   }
   // Schur update with block 1 and the right-hand side row
   for (int p = (t & 127); p < nt; p += 128)
@@ -450,19 +450,19 @@ __global__ __launch_bounds__(256) void k_btrial(BFit* fits, int nfits, BatchCfg 
   }
   // S5: Cholesky of the trailing system; row nt becomes L^-1 z'
   for (int k = 0; k < nt; ++k) {
-    __syncthreads();
+    sync_block();
     const double dkk = Y.Sp[pidx(k, k)];
     double d = 1.0;
     if (dkk > 0.0) d = sqrt(dkk);
     else if (t == 0) S.flags[0] = 1;
     for (int i = k + 1 + t; i <= nt; i += 256) Y.lk[i] = Y.Sp[pidx(i, k)] / d;
-    __syncthreads();
+    sync_block();
     if (t == 0) Y.Sp[pidx(k, k)] = d;
     for (int i = k + 1 + t; i <= nt; i += 256) Y.Sp[pidx(i, k)] = Y.lk[i];
     for (int i = k + 1 + (t & 127); i <= nt; i += 128)
       for (int j = k + 1 + (t >> 7); j <= i && j < nt; j += 2) Y.Sp[pidx(i, j)] -= Y.lk[i] * Y.lk[j];
   }
-  __syncthreads();
+  sync_block();
   // backward substitution L^T y_t = v by wave 0 (rows lane and lane + 64)
   if (t < 64) {
     double v0 = (lane < nt) ? Y.Sp[pidx(nt, lane)] : 0.0;
@@ -478,14 +478,14 @@ __global__ __launch_bounds__(256) void k_btrial(BFit* fits, int nfits, BatchCfg 
       if (lane + 64 < c) v1 -= Y.Sp[pidx(c, lane + 64)] * yc;
     }
   }
-  __syncthreads();
+  sync_block();
   // y_1 = z_1 - B^T y_t
   if (t < R2) {
     double acc = 0.0;
     for (int p = 0; p < nt; ++p) acc += Y.Bm[p][t] * S.y[R2 + p];
     S.y[t] = S.z[t] - acc;
   }
-  __syncthreads();
+  sync_block();
   // S6: u_n = w_n - vec(L_n Y_n X_n^T) (into v), f_n and Q_n = F_n Gt_n
   {
     auto& rr = S.u.rr;  // the system is no longer needed
@@ -497,7 +497,7 @@ __global__ __launch_bounds__(256) void k_btrial(BFit* fits, int nfits, BatchCfg 
         rr.T1[n][a + b * R] = acc;
       }
     }
-    __syncthreads();
+    sync_block();
     if (t < 3 * BR2) {
       const int n = t >> 6, e = t & 63, a = e & 7, b = e >> 3;
       if (a < R && b < R) {
@@ -506,7 +506,7 @@ __global__ __launch_bounds__(256) void k_btrial(BFit* fits, int nfits, BatchCfg 
         S.v[n * R2 + a + b * R] = S.w[n * R2 + a + b * R] - acc;
       }
     }
-    __syncthreads();
+    sync_block();
     if (t < 3 * BR2) {
       const int n = t >> 6, e = t & 63, a = e & 7, b = e >> 3;
       if (a < R && b < R) {
@@ -516,7 +516,7 @@ __global__ __launch_bounds__(256) void k_btrial(BFit* fits, int nfits, BatchCfg 
         rr.V[n][a + b * R] = v;
       }
     }
-    __syncthreads();
+    sync_block();
     if (t < 3 * BR2) {
       const int n = t >> 6, e = t & 63, a = e & 7, b = e >> 3;
       if (a < R && b < R) {
@@ -525,7 +525,7 @@ __global__ __launch_bounds__(256) void k_btrial(BFit* fits, int nfits, BatchCfg 
         S.Qs[n][a + b * R] = acc;
       }
     }
-    __syncthreads();
+    sync_block();
   }
   // S7: update rows A_c = A + P - A Q_n, gain-ratio denominator
   double den = 0.0;
@@ -610,7 +610,7 @@ __global__ __launch_bounds__(256) void k_btrial(BFit* fits, int nfits, BatchCfg 
     if (st->stop) atomicAdd(cfg.nstopped, 1);
     accept_s = accept;
   }
-  __syncthreads();
+  sync_block();
   if (!accept_s) return;
   __shared__ double sc[3][BR];
   if (t < R) {
@@ -633,7 +633,7 @@ __global__ __launch_bounds__(256) void k_btrial(BFit* fits, int nfits, BatchCfg 
       sc[n][t] = s2;
     }
   }
-  __syncthreads();
+  sync_block();
   if (t < T) {
     int i;
     const int n = mode_of_row(f, t, &i);

@@ -279,7 +279,7 @@ __device__ void invert_lower64(double (*T)[TR], double (*X)[TR], const double* r
       for (int i = 0; i < 16; ++i) X[b0 + i][b0 + j] = x[i];
     }
   }
-  __syncthreads();
+  sync_block();
   for (int d = 1; d < 4; ++d) {
     const int j = w, i = w + d;
     if (i < 4) {
@@ -301,7 +301,7 @@ __device__ void invert_lower64(double (*T)[TR], double (*X)[TR], const double* r
 #pragma unroll
       for (int v = 0; v < 4; ++v) X[16 * i + kq + 4 * v][16 * j + cl] = -acc[v];
     }
-    __syncthreads();
+    sync_block();
   }
 }
 
@@ -380,7 +380,7 @@ __global__ __launch_bounds__(256) void k_subblock(Shape s, SysPlan p, const doub
       }
     }
   }
-  __syncthreads();
+  sync_block();
   const int sh = R <= 16 ? 4 : (R <= 32 ? 5 : 6);
   const int a = threadIdx.x & ((1 << sh) - 1), cg = threadIdx.x >> sh, cstep = 256 >> sh;
   if (a < R) {
@@ -428,7 +428,7 @@ __global__ __launch_bounds__(1024) void k_rhs(SysPlan p, const double* B, const 
     if (k < p.R2) a0 += B[q + (long long)k * p.ntp] * z[k];
   }
   part[g][lane] = a0 + a1;
-  __syncthreads();
+  sync_block();
   if (g == 0 && q < p.ntp) {
     double acc = 0.0;
 #pragma unroll
@@ -485,14 +485,14 @@ __global__ __launch_bounds__(256) void k_syrk(SysPlan p, const double* B, int R2
   };
   load(0);
   for (int k0 = 0; k0 < R2p; k0 += 64) {
-    __syncthreads();
+    sync_block();
 #pragma unroll
     for (int s2 = 0; s2 < 16; ++s2) {
       const int e = threadIdx.x + 256 * s2, r = e & 63, c = e >> 6;
       Ti[c][r] = vi[s2];
       Tj[c][r] = vj[s2];
     }
-    __syncthreads();
+    sync_block();
     if (k0 + 64 < R2p) load(k0 + 64);
     mma_lds80(Tj, Ti, acc);
   }
@@ -594,7 +594,7 @@ __global__ __launch_bounds__(256, 2) void k_chol_phase(SysPlan p, int ph, double
     if (ph > 0) load_half(0, dri, dri + 1, La, av0, bv0);  // in flight while the panel is staged
     stage_panel(T, Dg, lds);
     if (hb) stage_panel(T + 64, Bg, lds);
-    __syncthreads();
+    sync_block();
     // in-panel update of the 16 x 16 block (bi, bj) with column step k0
     auto trail_block = [&](int bi, int bj, int k0) {
       v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
@@ -648,7 +648,7 @@ __global__ __launch_bounds__(256, 2) void k_chol_phase(SysPlan p, int ph, double
         barrier3(&b_count, epoch, bad);
       }
     }
-    __syncthreads();
+    sync_block();
     if (!hb) {
       double* Lg = Ld + (long long)ph * 64 * 64;
       for (int e = t; e < 64 * 64; e += 256) {
@@ -709,9 +709,9 @@ __global__ __launch_bounds__(256) void k_inv_diag(SysPlan p, const double* Ld, d
   __shared__ double Z[4][16][17];
   const int k = blockIdx.x, t = threadIdx.x;
   stage_panel(T, Ld + (long long)k * 64 * 64, 64);
-  __syncthreads();
+  sync_block();
   if (t < 64) rinv[t] = 1.0 / T[t][t];
-  __syncthreads();
+  sync_block();
   invert_lower64(T, X, rinv, Z);
   double* Xg = Li + (long long)k * 64 * 64;
   for (int e = t; e < 64 * 64; e += 256) {
@@ -734,7 +734,7 @@ __global__ __launch_bounds__(256) void k_bsolve(SysPlan p, int k, double* St, co
   const int t = threadIdx.x, j = blockIdx.x, c = t & 63, g = t >> 6;
   if (t < 64) u[t] = St[p.ntp + (long long)(k * 64 + t) * lds];
   if (j != k) stage(Lt, St + k * 64 + (long long)j * 64 * lds, lds);
-  __syncthreads();
+  sync_block();
   // y_k[c] = sum_r X[r][c] u[r], X = L_kk^-1 stored row-major
   const double* X = Li + (long long)k * 64 * 64;
   double acc = 0.0;
@@ -744,9 +744,9 @@ __global__ __launch_bounds__(256) void k_bsolve(SysPlan p, int k, double* St, co
     acc += X[r * 64 + c] * u[r];
   }
   part[g][c] = acc;
-  __syncthreads();
+  sync_block();
   if (t < 64) ys[t] = part[0][t] + part[1][t] + part[2][t] + part[3][t];
-  __syncthreads();
+  sync_block();
   if (j == k) {
     if (t < 64) yt[k * 64 + t] = ys[t];
     return;
@@ -759,7 +759,7 @@ __global__ __launch_bounds__(256) void k_bsolve(SysPlan p, int k, double* St, co
     acc += Lt[c][r] * ys[r];
   }
   part[g][c] = acc;
-  __syncthreads();
+  sync_block();
   if (t < 64) {
     const double v = part[0][t] + part[1][t] + part[2][t] + part[3][t];
     St[p.ntp + (long long)(j * 64 + t) * lds] -= v;
@@ -815,15 +815,15 @@ __global__ __launch_bounds__(256) void k_bsolve2(SysPlan p, int k, double* St, c
         const int e = t + 256 * s2, rr = e & 63, cc = e >> 6;
         Lt[m][cc][rr] = v[m][s2];
       }
-  __syncthreads();
+  sync_block();
   // y_k[c] = sum_r X_k[r][c] u_k[r]
   double acc = 0.0;
 #pragma unroll
   for (int s2 = 0; s2 < 16; ++s2) acc += xk[s2] * u[0][g + 4 * s2];
   part[g][c] = acc;
-  __syncthreads();
+  sync_block();
   if (t < 64) ys[0][t] = part[0][t] + part[1][t] + part[2][t] + part[3][t];
-  __syncthreads();
+  sync_block();
   // u_{k-1}[c] -= sum_r L(k, k-1)[r][c] y_k[r]
   acc = 0.0;
 #pragma unroll
@@ -832,17 +832,17 @@ __global__ __launch_bounds__(256) void k_bsolve2(SysPlan p, int k, double* St, c
     acc += Lt[0][c][r] * ys[0][r];
   }
   part[g][c] = acc;
-  __syncthreads();
+  sync_block();
   if (t < 64) u[1][t] -= part[0][t] + part[1][t] + part[2][t] + part[3][t];
-  __syncthreads();
+  sync_block();
   // y_{k-1}[c] = sum_r X_{k-1}[r][c] u'_{k-1}[r]
   acc = 0.0;
 #pragma unroll
   for (int s2 = 0; s2 < 16; ++s2) acc += xk1[s2] * u[1][g + 4 * s2];
   part[g][c] = acc;
-  __syncthreads();
+  sync_block();
   if (t < 64) ys[1][t] = part[0][t] + part[1][t] + part[2][t] + part[3][t];
-  __syncthreads();
+  sync_block();
   if (j >= k - 1) {
     if (t < 64) yt[(long long)j * 64 + t] = ys[j == k ? 0 : 1][t];
     return;
@@ -855,7 +855,7 @@ __global__ __launch_bounds__(256) void k_bsolve2(SysPlan p, int k, double* St, c
     acc += Lt[1][c][r] * ys[0][r] + Lt[2][c][r] * ys[1][r];
   }
   part[g][c] = acc;
-  __syncthreads();
+  sync_block();
   if (t < 64) {
     const double d = part[0][t] + part[1][t] + part[2][t] + part[3][t];
     St[p.ntp + (long long)(j * 64 + t) * lds] -= d;

@@ -46,18 +46,31 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
+// Workgroup barrier.  On gfx950 s_barrier does not wait for the wave's own
+// outstanding LDS operations, so a barrier that orders LDS accesses between
+// waves has to be preceded by s_waitcnt lgkmcnt(0).  __syncthreads() gets that
+// wait from its release fence, but hipcc (ROCm 7.2) has been seen to drop it on
+// some paths into a barrier (a loop back-edge, a branch around the last LDS
+// store), leaving a store or load in flight while other waves pass the barrier.
+// The explicit wait here is an ordinary s_waitcnt, which the compiler keeps:
+// immediate 0xC07F = lgkmcnt(0) with the vmcnt and expcnt fields at their maxima.
+__device__ __forceinline__ void sync_block() {
+  __builtin_amdgcn_s_waitcnt(0xC07F);
+  __syncthreads();
+}
+
 // Block-wide sum for blockDim.x a multiple of 64 and <= 1024; every thread gets the result.
 template <typename T>
 __device__ T block_sum(T v, T* scratch /* >= 16 entries of shared memory */) {
   v = wave_sum(v);
   const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
   const int nw = blockDim.x / kWave;
-  __syncthreads();
+  sync_block();
   if (l == 0) scratch[w] = v;
-  __syncthreads();
+  sync_block();
   T s = 0;
   for (int i = 0; i < nw; ++i) s += scratch[i];
-  __syncthreads();
+  sync_block();
   return s;
 }
 

@@ -141,7 +141,7 @@ __global__ __launch_bounds__(256) void k_pass_c(PassArgsC a, const int* stop) {
   }
   double e2 = 0.0;
   for (long long q = q0; q < q1; ++q) {
-    __syncthreads();
+    sync_block();
     const long long base = (long long)I0 * I1 * q;
     for (int e = t; e < TC * TC; e += 256) {
       const int ii = e % TC, jj = e / TC;
@@ -149,13 +149,13 @@ __global__ __launch_bounds__(256) void k_pass_c(PassArgsC a, const int* stop) {
       Ys[jj][ii] = (gi < I0 && gj < I1) ? load_c<TY>(Y, base + gi + (long long)I0 * gj) : czero();
     }
     if (t < R) cq[t] = cq_conj(a, q, t);
-    __syncthreads();
+    sync_block();
     if (RESID) {
       for (int e = t; e < TC * kMaxRankC; e += 256) {
         const int jj = e % TC, r = e / TC;
         A1c[jj][r] = r < R ? A1s[jj][r] * cq[r] : czero();
       }
-      __syncthreads();
+      sync_block();
       // E = Y - Y_hat, Y_hat = conj(sum_r conj(A1) conj(A2) conj(c_q))
       for (int e = t; e < TC * TC; e += 256) {
         const int ii = e % TC, jj = e / TC;
@@ -165,7 +165,7 @@ __global__ __launch_bounds__(256) void k_pass_c(PassArgsC a, const int* stop) {
         e2 += abs2(ev);
         Ys[jj][ii] = ev;
       }
-      __syncthreads();
+      sync_block();
     }
     cd zp[4], wp[4];
 #pragma unroll
@@ -297,7 +297,7 @@ __global__ __launch_bounds__(256) void k_gram_part_c(Shape s, const cd* A, doubl
     const int ii = e & 63, r = e >> 6;
     As[ii][r] = (r0 + ii < In) ? An[r0 + ii + (long long)r * In] : czero();
   }
-  __syncthreads();
+  sync_block();
   for (int e = threadIdx.x; e < R * R; e += 256) {
     const int r = e % R, q = e / R;
     cd acc = czero();
@@ -323,7 +323,7 @@ __global__ void k_rows_reduce_c(const double* part, int chunks, int stride, int 
 __device__ void chol_herm(cd (*H)[LC], int R, int mode, const double* ref, int* bad, cd* lk) {
   const int t = threadIdx.x;
   for (int k = 0; k < R; ++k) {
-    __syncthreads();
+    sync_block();
     const double dkk = H[k][k].x;
     bool zero = false;
     double inv = 1.0, d = 1.0;
@@ -343,19 +343,19 @@ __device__ void chol_herm(cd (*H)[LC], int R, int mode, const double* ref, int* 
     }
     for (int i = k + t; i < R; i += blockDim.x)
       lk[i] = zero ? czero() : ((i == k) ? cd{d, 0.0} : inv * H[i][k]);
-    __syncthreads();
+    sync_block();
     for (int e = t; e < R * R; e += blockDim.x) {
       const int i = e % R, j = e / R;
       if (j > k && i >= j) H[i][j] -= lk[i] * conjc(lk[j]);
     }
     for (int i = k + t; i < R; i += blockDim.x) H[i][k] = lk[i];
   }
-  __syncthreads();
+  sync_block();
   for (int e = t; e < R * R; e += blockDim.x) {
     const int i = e % R, j = e / R;
     if (j > i) H[i][j] = czero();
   }
-  __syncthreads();
+  sync_block();
 }
 
 // blockIdx.x = n; blockIdx.y = 0: Gamma_n, the Cholesky of Gamma_n + mu I, its
@@ -400,7 +400,7 @@ __global__ __launch_bounds__(256) void k_gamma_c(Shape s, const cd* C, double mu
     }
     for (int i = 0; i < j; ++i) Li[i][j] = czero();
   }
-  __syncthreads();
+  sync_block();
   for (int e = t; e < R2; e += 256) {
     const int r = e % R, q = e / R;
     X[(long long)n * R2 + e] = conjc(Li[q][r]);  // X = Li^H
@@ -445,7 +445,7 @@ __global__ __launch_bounds__(256) void k_pw_c(Shape s, const cd* A, const cd* M,
     Gs[ii][r] = mv;
     m2 += abs2(mv);
   }
-  __syncthreads();
+  sync_block();
   if (!resid) {
     for (int e = t; e < 64 * R; e += 256) {
       const int ii = e & 63, r = e >> 6;
@@ -453,7 +453,7 @@ __global__ __launch_bounds__(256) void k_pw_c(Shape s, const cd* A, const cd* M,
       for (int k = 0; k < R; ++k) acc += As[ii][k] * Gm[k][r];  // (A Gamma^T)[ii][r]
       Ps[ii][r] = Gs[ii][r] - acc;
     }
-    __syncthreads();
+    sync_block();
     for (int e = t; e < 64 * R; e += 256) {
       const int ii = e & 63, r = e >> 6;
       Gs[ii][r] = Ps[ii][r];
@@ -462,7 +462,7 @@ __global__ __launch_bounds__(256) void k_pw_c(Shape s, const cd* A, const cd* M,
       const int r = e % R, q = e / R;
       Gm[q][r] = conjc(Gt[(long long)n * R2 + q + r * R]);  // conj(Gt)[q][r]
     }
-    __syncthreads();
+    sync_block();
   }
   double g2 = 0.0;
   for (int e = t; e < 64 * R; e += 256) {
@@ -477,7 +477,7 @@ __global__ __launch_bounds__(256) void k_pw_c(Shape s, const cd* A, const cd* M,
       g2 += abs2(Gs[ii][r]);
     }
   }
-  __syncthreads();
+  sync_block();
   for (int e = t; e < R2; e += 256) {
     const int a = e % R, b = e / R;
     cd acc = czero();
@@ -542,7 +542,7 @@ __global__ __launch_bounds__(256) void k_z_c(Shape s, const cd* C, const cd* w, 
     }
     V[a][b] = v;
   }
-  __syncthreads();
+  sync_block();
   const cd* L = Lc + (long long)n * R2;
   const cd* Xn = X + (long long)n * R2;
   for (int e = t; e < R2; e += 256) {
@@ -551,7 +551,7 @@ __global__ __launch_bounds__(256) void k_z_c(Shape s, const cd* C, const cd* w, 
     for (int k = 0; k < R; ++k) acc += conjc(L[k + a * R]) * V[k][b];  // (L^H V)[a][b]
     Tm[a][b] = acc;
   }
-  __syncthreads();
+  sync_block();
   for (int e = t; e < R2; e += 256) {
     const int a = e % R, b = e / R;
     cd acc = czero();
@@ -579,7 +579,7 @@ __global__ __launch_bounds__(256) void k_tnm_c(Shape s, const cd* C, const cd* X
     Ls[i][j] = conjc(Lc[(long long)n * R2 + e]);
   }
   for (int i = t; i < R; i += 256) xd[i] = X[(long long)m * R2 + i + d * R];
-  __syncthreads();
+  sync_block();
   cd* out = Tnm + (long long)pair * R * R2;
   for (int e = t; e < R2; e += 256) {
     const int j = e % R, a = e / R;
@@ -613,7 +613,7 @@ __global__ __launch_bounds__(256) void k_subblock_c(Shape s, SysPlan p, const cd
     Td[j][a] = conjc(X[(long long)n * R2 + j + b * R]) * T[((long long)a + (long long)d * R) * R + j];
     Lm[j][a] = Lc[(long long)m * R2 + e];
   }
-  __syncthreads();
+  sync_block();
   for (int e = t; e < R2; e += 256) {
     const int a = e % R, c = e / R;
     cd acc = czero();
@@ -648,7 +648,7 @@ __global__ __launch_bounds__(256) void k_u_c(Shape s, const cd* w, const double*
     emb_index(n, e, R2, nt, &ir, &ii);
     Ys[e % R][e / R] = cd{y[ir], y[ii]};
   }
-  __syncthreads();
+  sync_block();
   const cd* L = Lc + (long long)n * R2;
   const cd* Xn = X + (long long)n * R2;
   for (int e = t; e < R2; e += 256) {
@@ -657,7 +657,7 @@ __global__ __launch_bounds__(256) void k_u_c(Shape s, const cd* w, const double*
     for (int k = 0; k < R; ++k) acc += L[a + k * R] * Ys[k][b];
     Tm[a][b] = acc;
   }
-  __syncthreads();
+  sync_block();
   for (int e = t; e < R2; e += 256) {
     const int a = e % R, b = e / R;
     cd acc = czero();
@@ -682,7 +682,7 @@ __global__ __launch_bounds__(256) void k_fq_c(Shape s, const cd* C, const cd* u,
     f[(long long)n * R2 + e] = v;
     Fs[a][b] = v;
   }
-  __syncthreads();
+  sync_block();
   const cd* G = Gt + (long long)n * R2;
   for (int e = t; e < R2; e += 256) {
     const int a = e % R, b = e / R;
@@ -717,7 +717,7 @@ __global__ __launch_bounds__(256) void k_update_c(Shape s, const cd* A, const cd
     const int ii = e & 63, r = e >> 6;
     As[ii][r] = (r0 + ii < In) ? A[base + r0 + ii + (long long)r * In] : czero();
   }
-  __syncthreads();
+  sync_block();
   double den = 0.0, da2 = 0.0;
   for (int e = t; e < 64 * R; e += 256) {
     const int ii = e & 63, r = e >> 6;
@@ -735,7 +735,7 @@ __global__ __launch_bounds__(256) void k_update_c(Shape s, const cd* A, const cd
     }
     Cs[ii][r] = v;
   }
-  __syncthreads();
+  sync_block();
   for (int e = t; e < R2; e += 256) {
     const int r = e % R, q = e / R;
     cd acc = czero();

@@ -155,7 +155,7 @@ __global__ __launch_bounds__(256) void k_control(Shape s, const double* Ac, cons
     }
     accept_s = accept;
   }
-  __syncthreads();
+  sync_block();
   // column scales of the normalisation (norms from the candidate Grams), one column per thread
   const int r = threadIdx.x;
   if (accept_s && r < R) {

@@ -98,7 +98,7 @@ __device__ __forceinline__ void stage_rows(double (*S)[LD], const double* src, i
 __device__ void chol_lds(double (*H)[LD], int R, int mode, int* bad, double* lk) {
   const int t = threadIdx.x;
   for (int k = 0; k < R; ++k) {
-    __syncthreads();
+    sync_block();
     const double dkk = H[k][k];
     double d = 1.0, inv = 1.0;
     bool zero = false;
@@ -119,19 +119,19 @@ __device__ void chol_lds(double (*H)[LD], int R, int mode, int* bad, double* lk)
       }
     }
     for (int i = k + t; i < R; i += blockDim.x) lk[i] = zero ? 0.0 : ((i == k) ? d : H[i][k] * inv);
-    __syncthreads();
+    sync_block();
     for (int j = k + 1 + (int)(t >> 6); j < R; j += (int)(blockDim.x >> 6)) {
       const int i = t & 63;
       if (i >= j && i < R) H[i][j] -= lk[i] * lk[j];
     }
     for (int i = k + t; i < R; i += blockDim.x) H[i][k] = lk[i];
   }
-  __syncthreads();
+  sync_block();
   RR_SHIFT;
   FOR_RR(i, j) {
     if (j > i) H[i][j] = 0.0;
   }
-  __syncthreads();
+  sync_block();
 }
 
 // Gram partials of 64-row chunks: part[(n * chunks + c) * stride + (r + s R)].
@@ -145,7 +145,7 @@ __global__ __launch_bounds__(256) void k_gram_part(Shape s, const double* A, dou
   double* out = part + ((long long)n * chunks + c) * stride;
   const double* An = A + (long long)s.off[n] * R;
   stage_rows(As, An, In, r0, R);
-  __syncthreads();
+  sync_block();
   FOR_RR(r, q) {
     const int e = r + q * R;
     double acc = 0.0;
@@ -205,7 +205,7 @@ __global__ __launch_bounds__(256) void k_gamma(Shape s, const double* C, double 
   chol_lds(H, R, 0, bad, lk);
   // Li = L^-1, one column per thread (forward substitution on the identity)
   if (t < R) lk[t] = 1.0 / H[t][t];
-  __syncthreads();
+  sync_block();
   for (int j = t; j < 64; j += 256) {
     if (j < R) {
       Li[j][j] = lk[j];
@@ -217,7 +217,7 @@ __global__ __launch_bounds__(256) void k_gamma(Shape s, const double* C, double 
       for (int i = 0; i < j; ++i) Li[i][j] = 0.0;
     }
   }
-  __syncthreads();
+  sync_block();
   FOR_RR(r, q) {
     const int e = r + q * R;
     // X = Li^T (upper triangular), Gt = Li^T Li
@@ -256,7 +256,7 @@ __global__ __launch_bounds__(256) void k_pw(Shape s, const double* A, const doub
   double m2 = 0.0;
   stage_rows(As, A + base, In, r0, R);
   stage_rows(Gs, M + base, In, r0, R, &m2);
-  __syncthreads();
+  sync_block();
   if (!resid) {
     // G = M - A Gamma
     for (int e = t; e < 64 * R; e += 256) {
@@ -265,16 +265,16 @@ __global__ __launch_bounds__(256) void k_pw(Shape s, const double* A, const doub
       for (int k = 0; k < R; ++k) acc += As[ii][k] * Gm[k][r];
       Ps[ii][r] = Gs[ii][r] - acc;
     }
-    __syncthreads();
+    sync_block();
     for (int e = t; e < 64 * R; e += 256) {
       const int ii = e & 63, r = e >> 6;
       Gs[ii][r] = Ps[ii][r];
     }
-    __syncthreads();
+    sync_block();
     for_rr_staged(
         R, rr_sh, [&](int r, int q) { return Gt[(long long)n * R2 + r + q * R]; },
         [&](int r, int q, double v) { Gm[r][q] = v; });
-    __syncthreads();
+    sync_block();
   }
   double g2 = 0.0;
   for (int e = t; e < 64 * R; e += 256) {
@@ -289,7 +289,7 @@ __global__ __launch_bounds__(256) void k_pw(Shape s, const double* A, const doub
       g2 += Gs[ii][r] * Gs[ii][r];
     }
   }
-  __syncthreads();
+  sync_block();
   FOR_RR(a, b) {
     const int e = a + b * R;
     double acc = 0.0;
@@ -361,13 +361,13 @@ __global__ __launch_bounds__(256) void k_z(Shape s, const double* C, const doubl
         Ls[a][b] = v.y;
         Xs[a][b] = v.z;
       });
-  __syncthreads();
+  sync_block();
   FOR_RR(a, b) {
     double acc = 0.0;
     for (int k = 0; k < R; ++k) acc += Ls[k][a] * V[k][b];
     Tm[a][b] = acc;
   }
-  __syncthreads();
+  sync_block();
   FOR_RR(a, b) {
     double acc = 0.0;
     for (int k = 0; k < R; ++k) acc += Tm[a][k] * Xs[k][b];
@@ -400,7 +400,7 @@ __global__ __launch_bounds__(256) void k_tnm(Shape s, const double* C, const dou
         Ls[i][j] = v.y;
       });
   for (int j = t; j < R; j += 256) xd[j] = X[(long long)m * R2 + j + d * R];
-  __syncthreads();
+  sync_block();
   double* out = Tnm + (long long)pair * R * R2;
   FOR_RR(i, a) {
     const int e = i + a * R;
@@ -432,13 +432,13 @@ __global__ __launch_bounds__(256) void k_u(Shape s, const double* w, const doubl
         Ls[r][q] = v.y;
         Xs[r][q] = v.z;
       });
-  __syncthreads();
+  sync_block();
   FOR_RR(a, b) {
     double acc = 0.0;
     for (int k = 0; k < R; ++k) acc += Ls[a][k] * Ys[k][b];
     Tm[a][b] = acc;
   }
-  __syncthreads();
+  sync_block();
   FOR_RR(a, b) {
     const int e = a + b * R;
     double acc = 0.0;
@@ -475,7 +475,7 @@ __global__ __launch_bounds__(256) void k_fq(Shape s, const double* C, const doub
         f[(long long)n * R2 + a + b * R] = v.y;
         Fs[a][b] = v.y;
       });
-  __syncthreads();
+  sync_block();
   FOR_RR(a, b) {
     const int e = a + b * R;
     double acc = 0.0;
@@ -509,7 +509,7 @@ __global__ __launch_bounds__(256) void k_update(Shape s, const double* A, const 
       R, rr_sh, [&](int r, int q) { return Q[(long long)n * R2 + r + q * R]; },
       [&](int r, int q, double v) { Qs[r][q] = v; });
   stage_rows(As, A + base, In, r0, R);
-  __syncthreads();
+  sync_block();
   double den = 0.0, da2 = 0.0;
   for (int e = t; e < 64 * R; e += 256) {
     const int ii = e & 63, r = e >> 6;
@@ -526,7 +526,7 @@ __global__ __launch_bounds__(256) void k_update(Shape s, const double* A, const 
     }
     Cs[ii][r] = v;
   }
-  __syncthreads();
+  sync_block();
   FOR_RR(r, q) {
     const int e = r + q * R;
     double acc = 0.0;

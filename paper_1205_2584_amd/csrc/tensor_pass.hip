@@ -69,7 +69,7 @@ __global__ __launch_bounds__(256) void k_pass_fma(PassArgs a, const int* stop) {
   double e2 = 0.0;
 
   for (long long q = q0; q < q1; ++q) {
-    __syncthreads();
+    sync_block();
     // stage the 64 x 64 slab tile (coalesced along the first index)
     const long long base = (long long)I0 * I1 * q;
 #pragma unroll 4
@@ -91,13 +91,13 @@ __global__ __launch_bounds__(256) void k_pass_fma(PassArgs a, const int* stop) {
       }
       cq[t] = (TC)c;
     }
-    __syncthreads();
+    sync_block();
     if (RESID) {
       for (int e = t; e < 64 * kMaxRank; e += 256) {
         const int jj = e & 63, r = e >> 6;
         A1c[jj][r] = A1s[jj][r] * (r < R ? cq[r] : (TC)0);
       }
-      __syncthreads();
+      sync_block();
       for (int e = t; e < 64 * 64; e += 256) {
         const int ii = e & 63, jj = e >> 6;
         TC yh = 0;
@@ -106,7 +106,7 @@ __global__ __launch_bounds__(256) void k_pass_fma(PassArgs a, const int* stop) {
         e2 += (double)ev * (double)ev;
         Ys[jj][ii] = ev;
       }
-      __syncthreads();
+      sync_block();
     }
     TC zp[16], wp[16];
 #pragma unroll
@@ -199,7 +199,7 @@ __device__ __forceinline__ float cq_of(const PassArgs& a, long long q, int r) {
 __device__ __forceinline__ void flush_t(const PassArgs& a, float (*tq_s)[kQMax][64], long long q0, long long q1,
                                         int tile) {
   const int t = threadIdx.x, R = a.R;
-  __syncthreads();
+  sync_block();
   float* tp = static_cast<float*>(a.tpart) + (long long)tile * R * a.Q;
   const int nq = (int)(q1 - q0);
   for (int e = t; e < nq * R; e += 256) {
@@ -319,7 +319,7 @@ __global__ __launch_bounds__(256) void k_pass_f32(PassArgs a, const int* stop) {
     if (q >= q1) break;
     const int ql = (int)((q - q0) % kQMax);
     float (*Ys)[LDY] = Ysb[(q - q0) & (NBUF - 1)];
-    if (NBUF == 1) __syncthreads();
+    if (NBUF == 1) sync_block();
 #pragma unroll
     for (int s2 = 0; s2 < 4; ++s2) {
       const int e = t + 256 * s2, jj = e >> 4, ii = (e & 15) * 4;
@@ -327,7 +327,7 @@ __global__ __launch_bounds__(256) void k_pass_f32(PassArgs a, const int* stop) {
     }
     const float* cq_s = cq_all[ql];
     if (q + kPrefetchF32 < q1) load(q + kPrefetchF32, pf[d]);
-    __syncthreads();
+    sync_block();
     if (RESID) {
       constexpr int KS = NB * 4;  // R padded to 16, in steps of 4
 #pragma unroll
@@ -347,7 +347,7 @@ __global__ __launch_bounds__(256) void k_pass_f32(PassArgs a, const int* stop) {
           Ys[jj][ii] = ev;
         }
       }
-      __syncthreads();
+      sync_block();
     }
     v4f zacc[NB], wacc[NB];
 #pragma unroll
@@ -502,7 +502,7 @@ __global__ __launch_bounds__(256) void k_pass_bf16(PassArgs a, const int* stop) 
     }
     const float* cq_s = cq_all[ql];
     if (q + kPrefetchBf16 < q1) load(q + kPrefetchBf16, pf[d]);
-    __syncthreads();
+    sync_block();
     v4f zacc[NB], wacc[NB];
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) { zacc[nb] = v4f{0, 0, 0, 0}; wacc[nb] = v4f{0, 0, 0, 0}; }
@@ -562,7 +562,7 @@ __global__ __launch_bounds__(1024) void k_reduce_slots(const TC* part, int nslot
     for (; k < nslots; k += 16) s += (double)part[(long long)k * len + x];
   }
   red[g][lane] = s;
-  __syncthreads();
+  sync_block();
   if (g == 0 && x < len) {
     double v = 0.0;
 #pragma unroll

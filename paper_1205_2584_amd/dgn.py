@@ -130,6 +130,11 @@ def tensor_desc(y: torch.Tensor, dims) -> dgn_tensor:
         raise ValueError("Y must be a 1-D contiguous tensor holding vec(Y)")
     if y.dtype not in _DTYPE:
         raise ValueError(f"unsupported tensor dtype {y.dtype}")
+    J = 1
+    for v in dims:
+        J *= int(v)
+    if y.numel() != J:
+        raise ValueError(f"Y holds {y.numel()} elements, the dims need {J}")
     d = dgn_tensor()
     d.order = len(dims)
     for k, v in enumerate(dims):
