@@ -57,8 +57,9 @@ def syrk_flops(N, R):
 
 # HBM bytes per unit of work, from rocprofv3 FETCH_SIZE and WRITE_SIZE runs
 # (scaled against a 1 GiB copy), for the 500^3 R=30 workload.  Each entry holds
-# for the kernel source whose SHA-256 prefix is given; once that source changes
-# the figure no longer describes the kernel and is reported as null.
+# for the kernel source and compiler flags whose SHA-256 prefix is given; once
+# either changes the figure no longer describes the kernel and is reported as
+# null.
 TRAFFIC = {
     "factor_solve": ("paper_1205_2584_amd/csrc/chol.hip", "7458094a7ff7a6c0", 466292116),
     "tensor_pass_f32": ("paper_1205_2584_amd/csrc/tensor_pass.hip", "2b3159505630214f", 546896413),
@@ -70,9 +71,19 @@ def traffic(key, workload_name):
     if workload_name != "500cube_r30":
         return None
     path, sha, nbytes = TRAFFIC[key]
+    return nbytes if kernel_sha(path) == sha else None
+
+
+def kernel_sha(path):
+    """SHA-256 prefix of a kernel source together with the library's compiler flags."""
+    import hashlib
+    from paper_1205_2584_amd import build
+    h = hashlib.sha256()
     with open(os.path.join(ROOT, path), "rb") as f:
-        cur = hashlib.sha256(f.read()).hexdigest()[:16]
-    return nbytes if cur == sha else None
+        h.update(f.read())
+    flags = [f for i, f in enumerate(build.FLAGS) if f != "-I" and not (i and build.FLAGS[i - 1] == "-I")]
+    h.update(" ".join(flags).encode())  # include paths differ between machines
+    return h.hexdigest()[:16]
 
 
 def cpu_baseline(p, gpu_check, seconds_cap=30.0):

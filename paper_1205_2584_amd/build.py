@@ -19,6 +19,10 @@ FLAGS = [
     "-O3", f"--offload-arch={ARCH}", "-std=c++17", "-fPIC",
     # packed FP32 instructions are disabled for every kernel of this library
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # MFMA accumulators in ordinary VGPRs: without this the compiler kept them
+    # in VGPRs across loop iterations and copied them to AGPRs and back around
+    # every unrolled group of MFMAs, draining the matrix pipeline each time
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-I", INCLUDE, "-I", CSRC,
 ]
 

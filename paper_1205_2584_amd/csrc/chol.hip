@@ -444,16 +444,19 @@ __device__ __forceinline__ void tri_index(long long id, int& ti, int& tj) {
   tj = (int)(id - (long long)ti * (ti + 1) / 2);
 }
 
-// St_tt -= B B^T on the lower tiles; K = R^2 in chunks of 64 staged through LDS.
+// St_tt -= B B^T on the lower tiles; K = R^2 in chunks of KC staged through LDS.
 // acc[blk] += A * B^T from LDS tiles stored [k][row] with row stride 80 (the
 // [k][row] MFMA operand reads are then bank-conflict free); wave w owns rows
 // 16w.. of A.
 constexpr int TS = 80;
+// Summation chunk of the SYRK: 48 rows of k, so that the two staged operand
+// tiles take 60 KB of LDS and two workgroups fit on a CU.
+constexpr int KC = 48;
 __device__ __forceinline__ void mma_lds80(const double (*A)[TS], const double (*B)[TS], v4d acc[4]) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int ra = 16 * w + (lane & 15), kk = lane >> 4;
 #pragma unroll 4
-  for (int k = 0; k < 64; k += 4) {
+  for (int k = 0; k < KC; k += 4) {
     const double a = A[k + kk][ra];
 #pragma unroll
     for (int blk = 0; blk < 4; ++blk)
@@ -461,22 +464,23 @@ __device__ __forceinline__ void mma_lds80(const double (*A)[TS], const double (*
   }
 }
 
-// S_tt -= B B^T on the lower tiles (ti >= tj).  The 64-wide chunks of the
+// S_tt -= B B^T on the lower tiles (ti >= tj).  The KC-wide chunks of the
 // summation range are double-buffered in registers: the next chunk is in
 // flight while the current one runs on MFMA.
 __global__ __launch_bounds__(256) void k_syrk(SysPlan p, const double* B, int R2p, double* St,
                                               const int* stop) {
   if (stopped(stop)) return;
-  __shared__ double Ti[64][TS];
-  __shared__ double Tj[64][TS];
+  __shared__ double Ti[KC][TS];
+  __shared__ double Tj[KC][TS];
   int ti, tj;
   tri_index(blockIdx.x, ti, tj);
   v4d acc[4];
   zero_acc(acc);
-  double vi[16], vj[16];
+  constexpr int NS = KC / 4;  // elements of a chunk per thread
+  double vi[NS], vj[NS];
   auto load = [&](int k0) {
 #pragma unroll
-    for (int s2 = 0; s2 < 16; ++s2) {
+    for (int s2 = 0; s2 < NS; ++s2) {
       const int e = threadIdx.x + 256 * s2, r = e & 63, c = e >> 6;
       const bool ok = k0 + c < R2p;
       vi[s2] = ok ? B[ti * 64 + r + (long long)(k0 + c) * p.ntp] : 0.0;
@@ -484,16 +488,16 @@ __global__ __launch_bounds__(256) void k_syrk(SysPlan p, const double* B, int R2
     }
   };
   load(0);
-  for (int k0 = 0; k0 < R2p; k0 += 64) {
+  for (int k0 = 0; k0 < R2p; k0 += KC) {
     sync_block();
 #pragma unroll
-    for (int s2 = 0; s2 < 16; ++s2) {
+    for (int s2 = 0; s2 < NS; ++s2) {
       const int e = threadIdx.x + 256 * s2, r = e & 63, c = e >> 6;
       Ti[c][r] = vi[s2];
       Tj[c][r] = vj[s2];
     }
     sync_block();
-    if (k0 + 64 < R2p) load(k0 + 64);
+    if (k0 + KC < R2p) load(k0 + KC);
     mma_lds80(Tj, Ti, acc);
   }
   double* C = St + ti * 64 + (long long)tj * 64 * p.lds;
@@ -869,9 +873,18 @@ __global__ __launch_bounds__(256) void k_y0(SysPlan p, const double* B, const do
   const int lane = threadIdx.x & 63;
   const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (k < p.R2) {
-    double acc = 0.0;
-    for (int q = lane; q < p.nt; q += 64) acc += B[q + (long long)k * p.ntp] * yt[q];
-    acc = wave_sum(acc);
+    // four independent partial sums, so that four loads per lane are in flight
+    const double* Bk = B + (long long)k * p.ntp;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int q = lane;
+    for (; q + 192 < p.nt; q += 256) {
+      a0 += Bk[q] * yt[q];
+      a1 += Bk[q + 64] * yt[q + 64];
+      a2 += Bk[q + 128] * yt[q + 128];
+      a3 += Bk[q + 192] * yt[q + 192];
+    }
+    for (; q < p.nt; q += 64) a0 += Bk[q] * yt[q];
+    const double acc = wave_sum((a0 + a1) + (a2 + a3));
     if (lane == 0) y[k] = z[k] - acc;
   }
   for (int q = blockIdx.x * 256 + threadIdx.x; q < p.nt; q += gridDim.x * 256) y[p.R2 + q] = yt[q];
