@@ -411,28 +411,27 @@ __global__ __launch_bounds__(256) void k_subblock(Shape s, SysPlan p, const doub
 }
 
 // Right-hand side row: St[ntp, q] = z_t[q] - (B z_1)[q]; 64 rows per block,
-// the R^2 sum split over the block's sixteen waves.
-__global__ __launch_bounds__(1024) void k_rhs(SysPlan p, const double* B, const double* z, double* St,
-                                              const int* stop) {
-  if (stopped(stop)) return;
-  __shared__ double part[16][65];
+// the R^2 sum split over the block's four waves (four partial sums each).
+__device__ __forceinline__ void rhs_block(const SysPlan& p, const double* B, const double* z, double* St,
+                                          int blk) {
+  __shared__ double part[4][65];
   const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
-  const int q = blockIdx.x * 64 + lane;
-  double a0 = 0.0, a1 = 0.0;
+  const int q = blk * 64 + lane;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
   if (q < p.nt) {
     int k = g;
-    for (; k + 16 < p.R2; k += 32) {
+    for (; k + 12 < p.R2; k += 16) {
       a0 += B[q + (long long)k * p.ntp] * z[k];
-      a1 += B[q + (long long)(k + 16) * p.ntp] * z[k + 16];
+      a1 += B[q + (long long)(k + 4) * p.ntp] * z[k + 4];
+      a2 += B[q + (long long)(k + 8) * p.ntp] * z[k + 8];
+      a3 += B[q + (long long)(k + 12) * p.ntp] * z[k + 12];
     }
-    if (k < p.R2) a0 += B[q + (long long)k * p.ntp] * z[k];
+    for (; k < p.R2; k += 4) a0 += B[q + (long long)k * p.ntp] * z[k];
   }
-  part[g][lane] = a0 + a1;
+  part[g][lane] = (a0 + a1) + (a2 + a3);
   sync_block();
   if (g == 0 && q < p.ntp) {
-    double acc = 0.0;
-#pragma unroll
-    for (int i = 0; i < 16; ++i) acc += part[i][lane];
+    const double acc = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
     St[p.ntp + (long long)q * p.lds] = (q < p.nt) ? z[p.R2 + q] - acc : 0.0;
   }
 }
@@ -466,14 +465,20 @@ __device__ __forceinline__ void mma_lds80(const double (*A)[TS], const double (*
 
 // S_tt -= B B^T on the lower tiles (ti >= tj).  The KC-wide chunks of the
 // summation range are double-buffered in registers: the next chunk is in
-// flight while the current one runs on MFMA.
-__global__ __launch_bounds__(256) void k_syrk(SysPlan p, const double* B, int R2p, double* St,
-                                              const int* stop) {
+// flight while the current one runs on MFMA.  The first ntp / 64 blocks form
+// the right-hand-side row instead, which no tile block touches.
+__global__ __launch_bounds__(256) void k_syrk(SysPlan p, const double* B, const double* z, int R2p,
+                                              double* St, const int* stop) {
   if (stopped(stop)) return;
+  const int nrhs = p.ntp / 64;
+  if ((int)blockIdx.x < nrhs) {  // the right-hand-side row, independent of the tiles below
+    rhs_block(p, B, z, St, blockIdx.x);
+    return;
+  }
   __shared__ double Ti[KC][TS];
   __shared__ double Tj[KC][TS];
   int ti, tj;
-  tri_index(blockIdx.x, ti, tj);
+  tri_index((long long)blockIdx.x - nrhs, ti, tj);
   v4d acc[4];
   zero_acc(acc);
   constexpr int NS = KC / 4;  // elements of a chunk per thread
@@ -916,8 +921,7 @@ hipError_t launch_sys_assemble(const Shape& s, const SysPlan& p, const SmallBuff
     k_subblock<32><<<dim3(npairs * s.R, s.R), 256, 0, st>>>(s, p, b.Tnm, b.X, b.Lc, y.St, y.B, stop);
   else
     k_subblock<64><<<dim3(npairs * s.R, s.R), 256, 0, st>>>(s, p, b.Tnm, b.X, b.Lc, y.St, y.B, stop);
-  k_rhs<<<p.ntp / 64, 1024, 0, st>>>(p, y.B, b.z, y.St, stop);
-  k_syrk<<<(unsigned)((long long)p.Tt * (p.Tt + 1) / 2), 256, 0, st>>>(p, y.B, R2p, y.St, stop);
+  k_syrk<<<(unsigned)(p.ntp / 64 + (long long)p.Tt * (p.Tt + 1) / 2), 256, 0, st>>>(p, y.B, b.z, R2p, y.St, stop);
   return hipGetLastError();
 }
 
@@ -933,8 +937,7 @@ hipError_t launch_sys_fill(const SysPlan& p, const SysBuffers& y, const int* sto
 hipError_t launch_sys_rhs_syrk(const SysPlan& p, const double* z, const SysBuffers& y, const int* stop,
                                hipStream_t st) {
   const int R2p = r2pad(p.R2);
-  k_rhs<<<p.ntp / 64, 1024, 0, st>>>(p, y.B, z, y.St, stop);
-  k_syrk<<<(unsigned)((long long)p.Tt * (p.Tt + 1) / 2), 256, 0, st>>>(p, y.B, R2p, y.St, stop);
+  k_syrk<<<(unsigned)(p.ntp / 64 + (long long)p.Tt * (p.Tt + 1) / 2), 256, 0, st>>>(p, y.B, z, R2p, y.St, stop);
   return hipGetLastError();
 }
 

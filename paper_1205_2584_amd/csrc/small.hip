@@ -154,11 +154,22 @@ __global__ __launch_bounds__(256) void k_gram_part(Shape s, const double* A, dou
   }
 }
 
-// out[n * R2 + x] = sum_c part[(n * chunks + c) * stride + x], x < R2.
-__global__ void k_rows_reduce(const double* part, int chunks, int stride, int R2, double* out,
-                              const int* stop) {
+// out[n * R2 + x] = sum_c part[(n * chunks + c) * stride + x], x < R2, for the
+// N blocks n < N.  With scal != nullptr, block N sums the two per-row scalars
+// at offsets R2, R2 + 1 of every partial over all modes into scal[0], scal[1].
+__global__ void k_rows_reduce(const double* part, int N, int chunks, int stride, int R2, double* out,
+                              double* scal, const int* stop) {
   if (stopped(stop)) return;
   const int n = blockIdx.x;
+  if (n == N) {
+    if (threadIdx.x < 2) {
+      double acc = 0.0;
+      for (int m = 0; m < N; ++m)
+        for (int c = 0; c < chunks; ++c) acc += part[((long long)m * chunks + c) * stride + R2 + threadIdx.x];
+      scal[threadIdx.x] = acc;
+    }
+    return;
+  }
   for (int x = threadIdx.x; x < R2; x += blockDim.x) {
     double acc = 0.0;
     for (int c = 0; c < chunks; ++c) acc += part[((long long)n * chunks + c) * stride + x];
@@ -543,18 +554,6 @@ __global__ __launch_bounds__(256) void k_update(Shape s, const double* A, const 
   }
 }
 
-__global__ void k_scalars_reduce(const double* part, int N, int chunks, int stride, int R2,
-                                 double* scal, const int* stop) {
-  if (stopped(stop)) return;
-  if (threadIdx.x < 2) {
-    double acc = 0.0;
-    for (int m = 0; m < N; ++m)
-      for (int c = 0; c < chunks; ++c)
-        acc += part[((long long)m * chunks + c) * stride + R2 + threadIdx.x];
-    scal[threadIdx.x] = acc;
-  }
-}
-
 }  // namespace
 
 int row_chunks(const Shape& s) { return (s.maxI + 63) / 64; }
@@ -565,7 +564,7 @@ hipError_t launch_gram(const Shape& s, const double* A, const SmallBuffers& b, d
                        const int* stop, hipStream_t st) {
   const int ch = row_chunks(s), stride = part_stride(s);
   k_gram_part<<<dim3(s.N, ch), 256, 0, st>>>(s, A, b.rowpart, ch, stride, stop);
-  k_rows_reduce<<<s.N, 256, 0, st>>>(b.rowpart, ch, stride, s.R * s.R, Cout, stop);
+  k_rows_reduce<<<s.N, 256, 0, st>>>(b.rowpart, s.N, ch, stride, s.R * s.R, Cout, nullptr, stop);
   return hipGetLastError();
 }
 
@@ -616,8 +615,7 @@ hipError_t launch_update(const Shape& s, const double* A, double* Ac, const Smal
 hipError_t launch_update_reduce(const Shape& s, const SmallBuffers& b, double* scal_out,
                                 const int* stop, hipStream_t st) {
   const int ch = row_chunks(s), stride = part_stride(s);
-  k_rows_reduce<<<s.N, 256, 0, st>>>(b.rowpart, ch, stride, s.R * s.R, b.Cc, stop);
-  k_scalars_reduce<<<1, 64, 0, st>>>(b.rowpart, s.N, ch, stride, s.R * s.R, scal_out, stop);
+  k_rows_reduce<<<s.N + 1, 256, 0, st>>>(b.rowpart, s.N, ch, stride, s.R * s.R, b.Cc, scal_out, stop);
   return hipGetLastError();
 }
 
