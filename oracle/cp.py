@@ -357,3 +357,38 @@ def fit(Y: np.ndarray, A0, mu0: float, tol: float, max_iters: int, normalize: st
             break
     return dict(A=A, iters=it, accepted=accepted, eps=eps, err2=err2, mu=mu, reason=reason,
                 hist=hist, mu0=mu0)
+
+
+# ----------------------------------------------------------------------------
+# ALS warm-up (eq. ALS, Section 2; run for a few sweeps after initialisation,
+# Section 4.5)
+# ----------------------------------------------------------------------------
+
+
+def als_sweep(Y: np.ndarray, A):
+    """One sweep of the ALS rule, modes n = 1..N in turn, each update using the
+    factors already updated in this sweep:
+
+        A^(n) <- Y_(n) (Khatri-Rao of A^(k), k != n) (Gamma^(n))^dagger,
+        Gamma^(n) = Hadamard_{k != n} A^(k)T A^(k).
+
+    Real tensors only.  When every factor has full column rank, each Gamma^(n)
+    is positive definite (Schur product theorem) and the pseudo-inverse is the
+    inverse; the solve goes through a library linear solver on the normal
+    equations A^(n) Gamma^(n) = M_n (Gamma^(n) is symmetric)."""
+    A = [np.array(a, dtype=np.float64, copy=True) for a in A]
+    for n in range(len(A)):
+        M = mttkrp(Y, A, n)
+        G = hadamard_except(grams(A), {n})
+        A[n] = np.linalg.solve(G, M.T).T
+    return A
+
+
+def als(Y: np.ndarray, A, sweeps: int):
+    """`sweeps` ALS sweeps from A; returns the factors and ||Y - Y_hat||^2 after
+    each sweep."""
+    errs = []
+    for _ in range(sweeps):
+        A = als_sweep(Y, A)
+        errs.append(residual_norm2(Y, A))
+    return A, errs

@@ -310,3 +310,94 @@ def test_phi_densities_section43():
     d2 = np.count_nonzero(np.abs(Phi2) > 1e-300) / Phi2.size
     assert abs(d1 - ((N - 1) * R * R + 1) / (N * R * R)) < 1e-12
     assert abs(d2 - (R * R + N - 1) / (N * R * R)) < 1e-12
+
+
+# ---- ALS warm-up (eq. ALS) -------------------------------------------------
+
+
+def _brute_als_sweep(Y, A):
+    """The ALS sweep as a plain least-squares problem per mode: the design
+    matrix is built entry by entry from the definition of the Khatri-Rao
+    product on the mode-n unfolding (first remaining index fastest), and each
+    row of A^(n) comes from numpy's least-squares routine on it, with no Gram or
+    Hadamard product involved."""
+    A = [a.copy() for a in A]
+    N = len(A)
+    dims = Y.shape
+    R = A[0].shape[1]
+    for n in range(N):
+        others = [k for k in range(N) if k != n]
+        cols = int(np.prod([dims[k] for k in others]))
+        Z = np.zeros((cols, R))
+        Yn = np.zeros((dims[n], cols))
+        for j, idx in enumerate(np.ndindex(*[dims[k] for k in reversed(others)])):
+            idx = idx[::-1]  # first remaining index fastest
+            for r in range(R):
+                Z[j, r] = np.prod([A[k][i, r] for k, i in zip(others, idx)])
+            full_idx = [0] * N
+            for k, i in zip(others, idx):
+                full_idx[k] = i
+            for i_n in range(dims[n]):
+                full_idx[n] = i_n
+                Yn[i_n, j] = Y[tuple(full_idx)]
+        A[n] = np.linalg.lstsq(Z, Yn.T, rcond=None)[0].T
+    return A
+
+
+@pytest.mark.parametrize("dims,R", [((4, 3, 5), 2), ((5, 4, 3), 3), ((3, 4, 3, 4), 2)])
+def test_als_sweep_matches_brute_force_least_squares(dims, R):
+    rng = np.random.default_rng(11 + R)
+    Y = rng.standard_normal(dims)
+    A0 = [rng.standard_normal((I, R)) for I in dims]
+    got = cp.als_sweep(Y, A0)
+    want = _brute_als_sweep(Y, A0)
+    for g, w in zip(got, want):
+        assert _rel(g, w) < 1e-10
+
+
+def test_als_sweep_fixed_point_at_exact_factors():
+    # an exact rank-R tensor built from A is reproduced exactly, so every mode's
+    # least-squares update returns the same factor
+    rng = np.random.default_rng(5)
+    for dims, R in SHAPES:
+        A = [rng.standard_normal((I, R)) for I in dims]
+        Y = cp.full(A)
+        A1 = cp.als_sweep(Y, A)
+        for a, b in zip(A1, A):
+            assert _rel(a, b) < 1e-9
+
+
+def test_als_last_mode_solves_its_normal_equations_and_error_decreases():
+    rng = np.random.default_rng(9)
+    dims, R = (6, 5, 7), 3
+    truth = [rng.standard_normal((I, R)) for I in dims]
+    Y = cp.full(truth) + 0.05 * rng.standard_normal(dims)
+    A = [rng.standard_normal((I, R)) for I in dims]
+    prev = cp.residual_norm2(Y, A)
+    for _ in range(4):
+        A = cp.als_sweep(Y, A)
+        # the gradient with respect to the last updated factor vanishes:
+        # Y_(N) KR - A^(N) KR^T KR = 0 with KR^T KR from the unfolding itself
+        N = len(A)
+        KR = cp.kr_except(A, N - 1)
+        resid = cp.unfold(Y, N - 1) @ KR - A[N - 1] @ (KR.T @ KR)
+        assert np.linalg.norm(resid) < 1e-10 * np.linalg.norm(cp.unfold(Y, N - 1) @ KR)
+        err = cp.residual_norm2(Y, A)
+        assert err <= prev * (1 + 1e-12)
+        prev = err
+
+
+def test_als_planted_all_mode_gamma_fails_the_pin():
+    # the Hadamard over all modes (Gamma of Theorem 4.1's simplified form) in
+    # place of Gamma^(n) breaks the least-squares update
+    rng = np.random.default_rng(12)
+    dims, R = (4, 3, 5), 2
+    Y = rng.standard_normal(dims)
+    A = [rng.standard_normal((I, R)) for I in dims]
+    B = [a.copy() for a in A]
+    for n in range(3):
+        M = cp.mttkrp(Y, B, n)
+        G = cp.hadamard_except(cp.grams(B), set())
+        B[n] = np.linalg.solve(G, M.T).T
+    want = _brute_als_sweep(Y, A)
+    assert max(_rel(b, w) for b, w in zip(B, want)) > 1e-3
