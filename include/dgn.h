@@ -189,6 +189,23 @@ dgn_status cp_fit(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, void* const* A, 
                   double tol, int32_t max_iters, const dgn_opts* opts, dgn_fit_info* info,
                   void* stream);
 
+/* ALS warm-up (eq. ALS, Section 2; the paper runs a few ALS iterations after
+ * initialising the factors, Section 4.5).  `sweeps` sweeps of
+ *   A^(n) <- Y_(n) (Khatri-Rao of A^(k), k != n) (Gamma^(n))^-1,  n = 1..N in turn,
+ * each update using the factors already updated in the sweep, with
+ * Gamma^(n) = Hadamard_{k != n} A^(k)T A^(k) inverted through its Cholesky
+ * factor (the pseudo-inverse of eq. ALS equals the inverse when every factor has
+ * full column rank).  Real tensors (F64, F32, BF16) only; a complex dtype gives
+ * DGN_EINVAL.  A: N device pointers to I_n x R FP64 column-major factors, in the
+ * start and out the result (caller-owned; no normalisation).  err2 (host, may be
+ * NULL) receives ||Y - Y_hat||^2 after the last sweep (from the residual for F64
+ * tensors, else from ||Y||^2 - 2 <Y, Y_hat> + ||Y_hat||^2); sweeps = 0 only
+ * evaluates it.  A Gamma^(n) that is not positive definite gives DGN_ESINGULAR
+ * (the factors are then not meaningful).  Each mode update runs one all-mode
+ * tensor pass.  Synchronises the stream before returning. */
+dgn_status cp_als(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, void* const* A, int32_t sweeps,
+                  const dgn_opts* opts, double* err2, void* stream);
+
 /* One small fit of a batch: a 3-way tensor (F32 or F64, every I_n <= 64),
  * rank 1 <= R <= 8, the initial damping (> 0 used as given, <= 0 the tau
  * rule) and three device pointers to FP64 column-major I_n x R factors

@@ -551,6 +551,63 @@ dgn_status cp_fit(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, void* const* A, 
 }
 
 
+dgn_status cp_als(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, void* const* A, int32_t sweeps,
+                  const dgn_opts* opts, double* err2_out, void* stream) {
+  if (!ctx) return DGN_EINVAL;
+  if (!A) return set_err(ctx, DGN_EINVAL, "factor pointer array is NULL");
+  if (sweeps < 0) return set_err(ctx, DGN_EINVAL, "sweeps must be >= 0");
+  if (Y && (Y->dtype == DGN_C64 || Y->dtype == DGN_C128))
+    return set_err(ctx, DGN_EINVAL, "ALS is built for real tensors only");
+  dgn_opts o;
+  dgn_opts_default(&o);
+  if (opts) o = *opts;
+  Work w{};
+  dgn_status rc = prepare(ctx, Y, R, false, w);
+  if (rc != DGN_OK) return rc;
+  for (int n = 0; n < w.s.N; ++n)
+    if (!A[n]) return set_err(ctx, DGN_EINVAL, "NULL factor pointer");
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(hipSetDevice(ctx->device), "hipSetDevice");
+  const Shape& s = w.s;
+  // the updates use the plain MTTKRP; the error after the last sweep is taken
+  // from the residual pass for FP64 tensors (cancellation-free), otherwise from
+  // ||Y||^2 - 2 <Y, Y_hat> + ||Y_hat||^2
+  const PassSel plain = pass_tensor(w, Y, o, false);
+  const bool resid_err = (w.ymaster == YType::F64);
+  const long long J = [&] { long long j = 1; for (int n = 0; n < s.N; ++n) j *= s.I[n]; return j; }();
+  double* ynp = w.scr + 1028;
+  double* e2 = w.scr + 1024;
+  double* out = w.scr + 1026;
+  HIPCHK(hipMemsetAsync(w.flags, 0, 64 * sizeof(int), st), "memset");
+  HIPCHK(copy_factors_in(w, A, w.A, st), "copy factors");
+  for (int it = 0; it < sweeps; ++it)
+    for (int n = 0; n < s.N; ++n) {
+      // Gamma^(n)^-1 from the current factors (every mode but n is final for this update)
+      HIPCHK(run_gram(w, w.A, w.sb.C, nullptr, st), "gram");
+      HIPCHK(launch_gamma(s, w.sb.C, 0.0, nullptr, w.sb, w.flags, nullptr, st), "gamma");
+      HIPCHK(run_pass(w, plain, w.A, false, w.M, nullptr, nullptr, st), "pass");
+      HIPCHK(launch_als_rows(s, n, w.M, w.sb, w.A, st), "als rows");
+    }
+  HIPCHK(run_gram(w, w.A, w.sb.C, nullptr, st), "gram");
+  if (resid_err) {
+    HIPCHK(run_pass(w, PassSel{Y->data, w.ymaster}, w.A, true, w.M, e2, nullptr, st), "pass");
+  } else {
+    HIPCHK(run_norm2(plain, J, w.scr, ynp, st), "norm");
+    HIPCHK(run_pass(w, plain, w.A, false, w.M, nullptr, nullptr, st), "pass");
+  }
+  HIPCHK(launch_err2(s, w.A, w.M, w.sb.C, resid_err, e2, ynp, out, st), "err2");
+  HIPCHK(copy_factors_out(w, w.A, A, st), "copy out");
+  double host = 0.0;
+  int flags[1] = {0};
+  HIPCHK(hipMemcpyAsync(&host, out, sizeof host, hipMemcpyDeviceToHost, st), "copy");
+  HIPCHK(hipMemcpyAsync(flags, w.flags, sizeof flags, hipMemcpyDeviceToHost, st), "copy");
+  HIPCHK(hipStreamSynchronize(st), "sync");
+  if (err2_out) *err2_out = host;
+  if (flags[0]) return set_err(ctx, DGN_ESINGULAR, "a Gamma^(n) of the ALS update is not positive definite");
+  if (!isfinite(host)) return set_err(ctx, DGN_ENONFINITE, "non-finite error after the ALS sweeps");
+  return DGN_OK;
+}
+
 dgn_status cp_fit_batched(dgn_ctx* ctx, int32_t B, const dgn_batch_fit* fits, double tol,
                           int32_t max_iters, const dgn_opts* opts, dgn_fit_info* infos,
                           void* stream) {

@@ -72,6 +72,10 @@ hipError_t launch_update(const Shape& s, const double* A, double* Ac, const Smal
                          double mu_host, const FitState* state, const int* stop, hipStream_t st);
 hipError_t launch_update_reduce(const Shape& s, const SmallBuffers& b, double* scal_out,
                                 const int* stop, hipStream_t st);
+// ALS update of mode n (eq. ALS): A_n = M_n Gt_n, with Gt_n = Gamma^(n)^-1 as
+// left in b.Gt by launch_gamma at mu = 0.
+hipError_t launch_als_rows(const Shape& s, int n, const double* M, const SmallBuffers& b, double* A,
+                           hipStream_t st);
 
 // ---- NR^2 system (trailing Schur complement, Cholesky, solves) --------------
 struct SysPlan {

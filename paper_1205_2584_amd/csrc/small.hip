@@ -554,6 +554,24 @@ __global__ __launch_bounds__(256) void k_update(Shape s, const double* A, const 
   }
 }
 
+// ALS update of mode n (eq. ALS): A_n = M_n Gt_n with Gt_n = Gamma^(n)^-1
+// (symmetric), one thread per entry of the column-major I_n x R block.
+__global__ __launch_bounds__(256) void k_als_rows(Shape s, int n, const double* M, const double* Gt, double* A) {
+  __shared__ double Gs[kMaxRank * kMaxRank];
+  const int R = s.R, R2 = R * R, In = s.I[n], t = threadIdx.x;
+  for (int e = t; e < R2; e += 256) Gs[e] = Gt[(long long)n * R2 + e];
+  sync_block();
+  const double* Mn = M + (long long)s.off[n] * R;
+  double* An = A + (long long)s.off[n] * R;
+  const long long total = (long long)In * R;
+  for (long long e = blockIdx.x * 256LL + t; e < total; e += (long long)gridDim.x * 256) {
+    const int i = (int)(e % In), r = (int)(e / In);
+    double acc = 0.0;
+    for (int k = 0; k < R; ++k) acc += Mn[i + (long long)k * In] * Gs[k + r * R];
+    An[e] = acc;
+  }
+}
+
 }  // namespace
 
 int row_chunks(const Shape& s) { return (s.maxI + 63) / 64; }
@@ -616,6 +634,15 @@ hipError_t launch_update_reduce(const Shape& s, const SmallBuffers& b, double* s
                                 const int* stop, hipStream_t st) {
   const int ch = row_chunks(s), stride = part_stride(s);
   k_rows_reduce<<<s.N + 1, 256, 0, st>>>(b.rowpart, s.N, ch, stride, s.R * s.R, b.Cc, scal_out, stop);
+  return hipGetLastError();
+}
+
+hipError_t launch_als_rows(const Shape& s, int n, const double* M, const SmallBuffers& b, double* A,
+                           hipStream_t st) {
+  const long long total = (long long)s.I[n] * s.R;
+  long long blocks = (total + 255) / 256;
+  if (blocks > 1024) blocks = 1024;
+  k_als_rows<<<(unsigned)blocks, 256, 0, st>>>(s, n, M, b.Gt, A);
   return hipGetLastError();
 }
 

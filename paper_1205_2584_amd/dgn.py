@@ -74,7 +74,7 @@ class dgn_result(ctypes.Structure):
 
 
 EXPORTS = ["dgn_opts_default", "dgn_create", "dgn_destroy", "dgn_last_error", "dgn_workspace_size",
-           "dgn_mttkrp", "dgn_step", "cp_fit", "dgn_last_phase_times", "cp_fit_batched",
+           "dgn_mttkrp", "dgn_step", "cp_fit", "cp_als", "dgn_last_phase_times", "cp_fit_batched",
            "dgn_server_create", "dgn_server_submit", "dgn_server_poll", "dgn_server_wait_idle",
            "dgn_server_stats", "dgn_server_now", "dgn_server_destroy"]
 NUM_PHASES = 6
@@ -106,6 +106,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                            dbl, ctypes.POINTER(dgn_opts), ctypes.POINTER(dgn_step_info), vp]
     L.cp_fit.argtypes = [vp, ctypes.POINTER(dgn_tensor), i32, ctypes.POINTER(vp), dbl, dbl, i32,
                          ctypes.POINTER(dgn_opts), ctypes.POINTER(dgn_fit_info), vp]
+    L.cp_als.argtypes = [vp, ctypes.POINTER(dgn_tensor), i32, ctypes.POINTER(vp), i32,
+                         ctypes.POINTER(dgn_opts), ctypes.POINTER(dbl), vp]
     L.dgn_last_phase_times.argtypes = [vp, ctypes.POINTER(dbl), i32, ctypes.POINTER(i32)]
     L.cp_fit_batched.argtypes = [vp, i32, ctypes.POINTER(dgn_batch_fit), dbl, i32,
                                  ctypes.POINTER(dgn_opts), ctypes.POINTER(dgn_fit_info), vp]
@@ -117,7 +119,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.dgn_server_now.argtypes = [vp]
     L.dgn_server_now.restype = dbl
     L.dgn_server_destroy.argtypes = [vp]
-    for name in ("dgn_create", "dgn_destroy", "dgn_workspace_size", "dgn_mttkrp", "dgn_step", "cp_fit",
+    for name in ("dgn_create", "dgn_destroy", "dgn_workspace_size", "dgn_mttkrp", "dgn_step", "cp_fit", "cp_als",
                  "dgn_last_phase_times", "cp_fit_batched", "dgn_server_create", "dgn_server_submit",
                  "dgn_server_poll", "dgn_server_wait_idle", "dgn_server_stats", "dgn_server_destroy"):
         getattr(L, name).restype = ctypes.c_int
@@ -221,6 +223,15 @@ class Context:
                                   ctypes.byref(options) if options else None, ctypes.byref(info),
                                   _stream()))
         return {k: getattr(info, k) for k, _ in dgn_fit_info._fields_}
+
+    def cp_als(self, y, dims, R, factors, sweeps, options: dgn_opts | None = None):
+        """ALS sweeps in place on `factors`; returns ||Y - Y_hat||^2 after the last one."""
+        err2 = ctypes.c_double()
+        d = tensor_desc(y, dims)
+        self._check(self.L.cp_als(self.h, ctypes.byref(d), int(R), _ptrs(factors), int(sweeps),
+                                  ctypes.byref(options) if options else None, ctypes.byref(err2),
+                                  _stream()))
+        return err2.value
 
     def cp_fit_batched(self, problems, tol, max_iters, options: dgn_opts | None = None):
         """problems: list of (y, dims, R, factors, mu0); factors are fitted in place.

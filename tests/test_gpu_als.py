@@ -1,0 +1,137 @@
+"""cp_als (ALS warm-up, eq. ALS of Section 2) against the FP64 oracle's sweeps.
+
+Small and medium shapes compare every factor entry after 1 and 3 sweeps; the
+500^3 R=30 FP32 workload checks properties that hold at any size: the last
+updated mode satisfies its normal equations M_N = A^(N) Gamma^(N) (M_N and
+Gamma^(N) formed in FP64 with torch from the returned factors), and the
+reported ||Y - Y_hat||^2 equals the FP64 residual.
+
+Tolerances: an FP64 tensor's update differs from the oracle's only by rounding,
+amplified by cond(Gamma^(n)) (the GPU applies Gamma^-1 through its Cholesky
+factor, the oracle solves the normal equations); 1e-9 relative leaves three
+orders of margin.  An FP32 tensor's MTTKRP carries about 2e-7 relative error,
+amplified by the same condition number: 1e-4.
+"""
+import numpy as np
+import pytest
+import torch
+
+import cpgen
+from oracle import cp
+
+pytestmark = pytest.mark.gpu
+
+
+def _dgn():
+    from paper_1205_2584_amd import dgn
+    return dgn
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+CASES = [
+    ((70, 45, 33), 5, torch.float64),
+    ((37, 80, 66), 16, torch.float64),
+    ((20, 18, 25, 9), 4, torch.float64),
+    ((9, 7, 6, 5, 4), 3, torch.float64),
+    ((130, 65, 40), 30, torch.float64),
+    ((70, 45, 33), 1, torch.float64),
+    ((50, 40, 30), 8, torch.float32),
+    ((33, 70, 20, 11), 6, torch.float32),
+]
+
+
+@pytest.mark.parametrize("dims,R,dtype", CASES)
+def test_als_matches_oracle(dims, R, dtype):
+    dgn = _dgn()
+    p = cpgen.small_problem(900 + R + len(dims), dims, R, c=0.5, snr_db=20.0)
+    Y = cp.as_tensor(p.y, dims)
+    tol = 1e-9 if dtype == torch.float64 else 1e-4
+    y = torch.from_numpy(p.y.astype(np.float64 if dtype == torch.float64 else np.float32)).cuda()
+    ctx = dgn.Context(0, dgn.workspace_size(dims, R, dtype) + (16 << 20))
+    try:
+        for sweeps in (1, 3):
+            want, errs = cp.als(Y, p.init, sweeps)
+            A = dgn.to_device_factors(p.init)
+            err2 = ctx.cp_als(y, dims, R, A, sweeps)
+            got = dgn.to_host_factors(A)
+            for n, (g, w) in enumerate(zip(got, want)):
+                assert _rel(g, w) < tol, (sweeps, n, _rel(g, w))
+            assert abs(err2 - errs[-1]) <= tol * max(errs[-1], 1e-12 * float(np.sum(Y * Y)))
+    finally:
+        ctx.close()
+
+
+def test_als_fixed_point_and_zero_sweeps():
+    dgn = _dgn()
+    dims, R = (40, 30, 20), 6
+    p = cpgen.small_problem(77, dims, R, c=0.3, snr_db=None)  # noiseless: Y = [[truth]]
+    truth = [np.array(a) for a in p.truth]
+    Y = cp.as_tensor(p.y, dims)
+    ctx = dgn.Context(0, dgn.workspace_size(dims, R, torch.float64) + (16 << 20))
+    try:
+        y = torch.from_numpy(p.y).cuda()
+        # sweeps = 0 evaluates the error of the given factors and leaves them alone
+        A = dgn.to_device_factors(p.init)
+        e0 = ctx.cp_als(y, dims, R, A, 0)
+        assert abs(e0 - cp.residual_norm2(Y, p.init)) <= 1e-9 * e0
+        for g, w in zip(dgn.to_host_factors(A), p.init):
+            assert np.array_equal(g, w)
+        # an exact rank-R tensor is a fixed point of the sweep
+        A = dgn.to_device_factors(truth)
+        e1 = ctx.cp_als(y, dims, R, A, 1)
+        for g, w in zip(dgn.to_host_factors(A), truth):
+            assert _rel(g, w) < 1e-9
+        assert e1 <= 1e-18 * float(np.sum(Y * Y))
+    finally:
+        ctx.close()
+
+
+def test_als_rejects_complex_and_reports_singular_gamma():
+    dgn = _dgn()
+    dims, R = (12, 10, 8), 3
+    ctx = dgn.Context(0, dgn.workspace_size(dims, R, torch.float64) + (16 << 20))
+    try:
+        rng = np.random.default_rng(3)
+        yc = torch.zeros(int(np.prod(dims)), dtype=torch.complex128, device="cuda")
+        A = [torch.zeros((R, I), dtype=torch.complex128, device="cuda") for I in dims]
+        with pytest.raises(dgn.DgnError) as e:
+            ctx.cp_als(yc, dims, R, A, 1)
+        assert e.value.status == -1
+        y = torch.from_numpy(rng.standard_normal(int(np.prod(dims)))).cuda()
+        init = [rng.standard_normal((I, R)) for I in dims]
+        init[2][:, 1] = 0.0  # a zero column makes Gamma^(1) and Gamma^(2) singular
+        A = dgn.to_device_factors(init)
+        with pytest.raises(dgn.DgnError) as e:
+            ctx.cp_als(y, dims, R, A, 1)
+        assert e.value.status == -3
+    finally:
+        ctx.close()
+
+
+def test_als_full_size_properties():
+    dgn = _dgn()
+    dims, R = (500, 500, 500), 30
+    J = 500 ** 3
+    g = torch.Generator(device="cuda")
+    g.manual_seed(31)
+    y = torch.randn(J, generator=g, device="cuda", dtype=torch.float32)
+    A = [torch.randn((R, I), generator=g, device="cuda", dtype=torch.float64) for I in dims]
+    ctx = dgn.Context(0, dgn.workspace_size(dims, R, torch.float32) + (64 << 20))
+    try:
+        e0 = ctx.cp_als(y, dims, R, A, 0)
+        e1 = ctx.cp_als(y, dims, R, A, 1)
+    finally:
+        ctx.close()
+    assert e1 < e0
+    A1, A2, A3 = (a.T for a in A)  # I_n x R views
+    kr = (A2[:, None, :] * A1[None, :, :]).reshape(500 * 500, R)  # first index fastest
+    Y3 = y.view(500, 500 * 500).double()  # mode-3 unfolding of the column-major tensor
+    M3 = Y3 @ kr
+    G3 = (A1.T @ A1) * (A2.T @ A2)
+    resid = M3 - A3 @ G3
+    assert float(resid.norm() / M3.norm()) < 1e-4
+    e_ref = float(((Y3 - A3 @ kr.T) ** 2).sum())
+    assert abs(e1 - e_ref) <= 1e-5 * e_ref
