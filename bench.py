@@ -202,6 +202,29 @@ def bench_serving(dgn, torch, n_req=256, rate=2000.0, pool=32, slots=4, seed=5):
                      "I_n log-uniform [16,256] (tensors <= 2^27 entries), R in [2,20], 20% complex64"}
 
 
+def bench_als(dgn, torch, ctx, y, dims, R, p, dev, sweeps=5):
+    """ALS warm-up sweeps (eq. ALS) on the workload's FP32 tensor: each mode
+    update runs one all-mode tensor pass, so a sweep is N passes plus N small
+    R x R inversions.  The per-sweep time is the difference of a 1-sweep and a
+    `sweeps`-sweep call (both also copy the factors and evaluate the error once)."""
+    def timed(k):
+        A = dgn.to_device_factors(p.init, dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e = ctx.cp_als(y, dims, R, A, k)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, e
+    A = dgn.to_device_factors(p.init, dev)
+    e0 = ctx.cp_als(y, dims, R, A, 0)
+    timed(1)
+    t1, _ = timed(1)
+    tk, ek = timed(sweeps)
+    per = (tk - t1) / (sweeps - 1)
+    ynorm2 = float(torch.sum(y.double() ** 2))
+    return {"sweeps": sweeps, "ms_per_sweep": round(per * 1e3, 4), "sweeps_per_s": round(1.0 / per, 2),
+            "passes_per_sweep": len(dims), "eps_start": (e0 / ynorm2) ** 0.5, "eps_after": (ek / ynorm2) ** 0.5}
+
+
 def rel(a, b):
     import numpy as np
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
@@ -279,6 +302,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
+    ap.add_argument("--no-als", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run a plain copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
@@ -371,6 +395,8 @@ def main():
                 "resid_iters": info["resid_iters"]},
         "gen_s": round(gen_s, 1),
     }
+    if not args.no_als:
+        line["als"] = bench_als(dgn, torch, ctx, y32, dims, R, p, dev)
     ctx.close()
     del y32, ybf
     torch.cuda.empty_cache()
