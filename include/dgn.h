@@ -115,7 +115,9 @@ typedef struct dgn_opts {
   int32_t timing;       /* nonzero: cp_fit records per-phase HIP events (dgn_last_phase_times) */
   int32_t graph;        /* cp_fit_batched: nonzero (default) replays poll_every trials from one
                            captured hipGraph; zero launches them one by one */
-  int32_t reserved;
+  int32_t als_sweeps;   /* cp_fit and the server: ALS sweeps (as cp_als) on the starting factors
+                           before the first trial; default 0.  cp_fit_batched rejects a nonzero
+                           value with DGN_EINVAL */
 } dgn_opts;
 
 /* Result of one trial step (dgn_step). */

@@ -305,6 +305,22 @@ hipError_t run_gram(const Work& w, const double* A, double* Cout, const int* sto
   return launch_gram(w.s, A, w.sb, Cout, stop, st);
 }
 
+// ALS sweeps (eq. ALS) on the workspace factors w.A: modes in turn, each from a
+// fresh Gram set, Gamma^(n)^-1 (k_gamma at mu = 0) and an all-mode tensor pass.
+// A Gamma^(n) that is not positive definite raises singular[0].
+hipError_t enqueue_als(Work& w, const PassSel& plain, int sweeps, int* singular, hipStream_t st) {
+  const Shape& s = w.s;
+  hipError_t e;
+  for (int it = 0; it < sweeps; ++it)
+    for (int n = 0; n < s.N; ++n) {
+      if ((e = run_gram(w, w.A, w.sb.C, nullptr, st)) != hipSuccess) return e;
+      if ((e = launch_gamma(s, w.sb.C, 0.0, nullptr, w.sb, singular, nullptr, st)) != hipSuccess) return e;
+      if ((e = run_pass(w, plain, w.A, false, w.M, nullptr, nullptr, st)) != hipSuccess) return e;
+      if ((e = launch_als_rows(s, n, w.M, w.sb, w.A, st)) != hipSuccess) return e;
+    }
+  return hipSuccess;
+}
+
 }  // namespace
 
 extern "C" {
@@ -458,6 +474,9 @@ dgn_status cp_fit(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, void* const* A, 
   if (opts) o = *opts;
   if (o.poll_every < 1) o.poll_every = 1;
   if (o.normalize < 0 || o.normalize > 2) return set_err(ctx, DGN_EINVAL, "bad normalize option");
+  if (o.als_sweeps < 0) return set_err(ctx, DGN_EINVAL, "als_sweeps must be >= 0");
+  if (o.als_sweeps > 0 && Y && (Y->dtype == DGN_C64 || Y->dtype == DGN_C128))
+    return set_err(ctx, DGN_EINVAL, "the ALS warm-up is built for real tensors only");
   Work w{};
   dgn_status rc = prepare(ctx, Y, R, true, w);
   if (rc != DGN_OK) return rc;
@@ -480,6 +499,10 @@ dgn_status cp_fit(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, void* const* A, 
   double* e2c = w.scr + 1025;
   HIPCHK(hipMemcpyAsync(ds, &hs, sizeof hs, hipMemcpyHostToDevice, st), "state");
   HIPCHK(copy_factors_in(w, A, w.A, st), "copy factors");
+  if (o.als_sweeps > 0) {  // warm-up on the starting factors (eq. ALS)
+    HIPCHK(hipMemsetAsync(w.flags, 0, 64 * sizeof(int), st), "memset");
+    HIPCHK(enqueue_als(w, pass_tensor(w, Y, o, false), o.als_sweeps, w.flags, st), "als");
+  }
   HIPCHK(run_norm2(PassSel{Y->data, w.ymaster}, J, w.scr, &ds->ynorm2, st), "norm");
   HIPCHK(run_norm2(ps, J, w.scr, &ds->ynorm2_pass, st), "norm");
   HIPCHK(run_gram(w, w.A, w.sb.C, nullptr, st), "gram");
@@ -522,7 +545,10 @@ dgn_status cp_fit(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, void* const* A, 
   }
   HIPCHK(copy_factors_out(w, w.A, A, st), "copy out");
   HIPCHK(hipMemcpyAsync(&hs, ds, sizeof hs, hipMemcpyDeviceToHost, st), "state");
+  int als_flag = 0;
+  if (o.als_sweeps > 0) HIPCHK(hipMemcpyAsync(&als_flag, w.flags, sizeof als_flag, hipMemcpyDeviceToHost, st), "copy");
   HIPCHK(hipStreamSynchronize(st), "sync");
+  if (als_flag) return set_err(ctx, DGN_ESINGULAR, "a Gamma^(n) of the ALS warm-up is not positive definite");
   if (o.timing) {
     const int nt = hs.iters < enq ? hs.iters : enq;
     for (int t = 0; t < nt; ++t) {
@@ -580,14 +606,7 @@ dgn_status cp_als(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, void* const* A, 
   double* out = w.scr + 1026;
   HIPCHK(hipMemsetAsync(w.flags, 0, 64 * sizeof(int), st), "memset");
   HIPCHK(copy_factors_in(w, A, w.A, st), "copy factors");
-  for (int it = 0; it < sweeps; ++it)
-    for (int n = 0; n < s.N; ++n) {
-      // Gamma^(n)^-1 from the current factors (every mode but n is final for this update)
-      HIPCHK(run_gram(w, w.A, w.sb.C, nullptr, st), "gram");
-      HIPCHK(launch_gamma(s, w.sb.C, 0.0, nullptr, w.sb, w.flags, nullptr, st), "gamma");
-      HIPCHK(run_pass(w, plain, w.A, false, w.M, nullptr, nullptr, st), "pass");
-      HIPCHK(launch_als_rows(s, n, w.M, w.sb, w.A, st), "als rows");
-    }
+  HIPCHK(enqueue_als(w, plain, sweeps, w.flags, st), "als");
   HIPCHK(run_gram(w, w.A, w.sb.C, nullptr, st), "gram");
   if (resid_err) {
     HIPCHK(run_pass(w, PassSel{Y->data, w.ymaster}, w.A, true, w.M, e2, nullptr, st), "pass");
@@ -613,6 +632,8 @@ dgn_status cp_fit_batched(dgn_ctx* ctx, int32_t B, const dgn_batch_fit* fits, do
                           void* stream) {
   if (!ctx) return DGN_EINVAL;
   if (B < 0 || (B > 0 && !fits)) return set_err(ctx, DGN_EINVAL, "bad batch size or NULL fits");
+  if (opts && opts->als_sweeps != 0)
+    return set_err(ctx, DGN_EINVAL, "cp_fit_batched has no ALS warm-up (als_sweeps must be 0)");
   if (max_iters < 0 || !(tol >= 0.0)) return set_err(ctx, DGN_EINVAL, "need max_iters >= 0 and tol >= 0");
   if (B == 0) return DGN_OK;
   dgn_opts o;

@@ -42,7 +42,7 @@ class dgn_opts(ctypes.Structure):
     _fields_ = [("normalize", ctypes.c_int32), ("tau", ctypes.c_double),
                 ("resid_switch", ctypes.c_double), ("y_bf16", ctypes.c_void_p),
                 ("poll_every", ctypes.c_int32), ("timing", ctypes.c_int32),
-                ("graph", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("graph", ctypes.c_int32), ("als_sweeps", ctypes.c_int32)]
 
 
 class dgn_step_info(ctypes.Structure):

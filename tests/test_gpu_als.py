@@ -135,3 +135,33 @@ def test_als_full_size_properties():
     assert float(resid.norm() / M3.norm()) < 1e-4
     e_ref = float(((Y3 - A3 @ kr.T) ** 2).sum())
     assert abs(e1 - e_ref) <= 1e-5 * e_ref
+
+
+def test_fit_with_als_warmup_equals_als_then_fit():
+    # cp_fit's warm-up runs the same sweeps as cp_als on the starting factors, so
+    # the two routes give bit-identical fits
+    dgn = _dgn()
+    dims, R = (40, 35, 30), 5
+    p = cpgen.small_problem(321, dims, R, c=0.6, snr_db=25.0)
+    y = torch.from_numpy(p.y).cuda()
+    ctx = dgn.Context(0, dgn.workspace_size(dims, R, torch.float64) + (16 << 20))
+    try:
+        A1 = dgn.to_device_factors(p.init)
+        ctx.cp_als(y, dims, R, A1, 2)
+        info1 = ctx.cp_fit(y, dims, R, A1, -1.0, 1e-10, 12)
+        A2 = dgn.to_device_factors(p.init)
+        info2 = ctx.cp_fit(y, dims, R, A2, -1.0, 1e-10, 12, dgn.opts(als_sweeps=2))
+        assert info1 == info2
+        for a, b in zip(dgn.to_host_factors(A1), dgn.to_host_factors(A2)):
+            assert np.array_equal(a, b)
+        # options that do not apply are rejected, not ignored
+        A3 = dgn.to_device_factors(p.init)
+        with pytest.raises(dgn.DgnError) as e:
+            ctx.cp_fit(y, dims, R, A3, -1.0, 1e-10, 2, dgn.opts(als_sweeps=-1))
+        assert e.value.status == -1
+        with pytest.raises(dgn.DgnError) as e:
+            ctx.cp_fit_batched([(y.float(), dims, R, dgn.to_device_factors(p.init), -1.0)], 1e-8, 5,
+                               dgn.opts(als_sweeps=1))
+        assert e.value.status == -1
+    finally:
+        ctx.close()
