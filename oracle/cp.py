@@ -372,14 +372,22 @@ def als_sweep(Y: np.ndarray, A):
         A^(n) <- Y_(n) (Khatri-Rao of A^(k), k != n) (Gamma^(n))^dagger,
         Gamma^(n) = Hadamard_{k != n} A^(k)T A^(k).
 
-    Real tensors only.  When every factor has full column rank, each Gamma^(n)
-    is positive definite (Schur product theorem) and the pseudo-inverse is the
-    inverse; the solve goes through a library linear solver on the normal
-    equations A^(n) Gamma^(n) = M_n (Gamma^(n) is symmetric)."""
-    A = [np.array(a, dtype=np.float64, copy=True) for a in A]
+    When every factor has full column rank, each Gamma^(n) is positive definite
+    (Schur product theorem) and the pseudo-inverse is the inverse; the solve
+    goes through a library linear solver on the normal equations.
+
+    Complex tensors (Section 5): the least-squares solution of
+    Y_(n) ~ A^(n) KR^T is A^(n) = Y_(n) conj(KR) (KR^T conj(KR))^-1, where
+    Y_(n) conj(KR) is the MTTKRP with conjugated factors (Theorem 5.4) and
+    KR^T conj(KR) = conj(Gamma^(n)) = Gamma^(n)T with Gamma^(n) the Hadamard
+    product of A^(k)H A^(k); for real tensors this is the rule above."""
+    cplx = any(np.iscomplexobj(a) for a in A) or np.iscomplexobj(Y)
+    dt = np.complex128 if cplx else np.float64
+    A = [np.array(a, dtype=dt, copy=True) for a in A]
     for n in range(len(A)):
-        M = mttkrp(Y, A, n)
+        M = mttkrp(Y, A, n, conj=cplx)
         G = hadamard_except(grams(A), {n})
+        # A^(n) G^T = M  <=>  G A^(n)T = M^T
         A[n] = np.linalg.solve(G, M.T).T
     return A
 

@@ -325,11 +325,12 @@ def _brute_als_sweep(Y, A):
     N = len(A)
     dims = Y.shape
     R = A[0].shape[1]
+    dt = np.result_type(Y, *A)
     for n in range(N):
         others = [k for k in range(N) if k != n]
         cols = int(np.prod([dims[k] for k in others]))
-        Z = np.zeros((cols, R))
-        Yn = np.zeros((dims[n], cols))
+        Z = np.zeros((cols, R), dtype=dt)
+        Yn = np.zeros((dims[n], cols), dtype=dt)
         for j, idx in enumerate(np.ndindex(*[dims[k] for k in reversed(others)])):
             idx = idx[::-1]  # first remaining index fastest
             for r in range(R):
@@ -344,11 +345,16 @@ def _brute_als_sweep(Y, A):
     return A
 
 
-@pytest.mark.parametrize("dims,R", [((4, 3, 5), 2), ((5, 4, 3), 3), ((3, 4, 3, 4), 2)])
-def test_als_sweep_matches_brute_force_least_squares(dims, R):
+@pytest.mark.parametrize("dims,R,cplx", [((4, 3, 5), 2, False), ((5, 4, 3), 3, False), ((3, 4, 3, 4), 2, False),
+                                          ((4, 3, 5), 2, True), ((3, 4, 3, 4), 3, True)])
+def test_als_sweep_matches_brute_force_least_squares(dims, R, cplx):
     rng = np.random.default_rng(11 + R)
-    Y = rng.standard_normal(dims)
-    A0 = [rng.standard_normal((I, R)) for I in dims]
+
+    def draw(shape):
+        x = rng.standard_normal(shape)
+        return x + 1j * rng.standard_normal(shape) if cplx else x
+    Y = draw(dims)
+    A0 = [draw((I, R)) for I in dims]
     got = cp.als_sweep(Y, A0)
     want = _brute_als_sweep(Y, A0)
     for g, w in zip(got, want):
