@@ -197,12 +197,14 @@ dgn_status cp_fit(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, void* const* A, 
  * each update using the factors already updated in the sweep, with
  * Gamma^(n) = Hadamard_{k != n} A^(k)T A^(k) inverted through its Cholesky
  * factor (the pseudo-inverse of eq. ALS equals the inverse when every factor has
- * full column rank).  Real tensors (F64, F32, BF16) only; a complex dtype gives
- * DGN_EINVAL.  A: N device pointers to I_n x R FP64 column-major factors, in the
- * start and out the result (caller-owned; no normalisation).  err2 (host, may be
- * NULL) receives ||Y - Y_hat||^2 after the last sweep (from the residual for F64
- * tensors, else from ||Y||^2 - 2 <Y, Y_hat> + ||Y_hat||^2); sweeps = 0 only
- * evaluates it.  A Gamma^(n) that is not positive definite gives DGN_ESINGULAR
+ * full column rank).  Complex tensors (Section 5) use the MTTKRP on conjugated
+ * factors and (Gamma^(n)T)^-1, with Gamma^(n) the Hadamard product of
+ * A^(k)H A^(k) (the least-squares solution).  A: N device pointers to I_n x R
+ * column-major factors, FP64 (C128 for complex tensors), in the start and out
+ * the result (caller-owned; no normalisation).  err2 (host, may be NULL)
+ * receives ||Y - Y_hat||^2 after the last sweep (from the residual for F64 and
+ * complex tensors, else from ||Y||^2 - 2 <Y, Y_hat> + ||Y_hat||^2); sweeps = 0
+ * only evaluates it.  A Gamma^(n) that is not positive definite gives DGN_ESINGULAR
  * (the factors are then not meaningful).  Each mode update runs one all-mode
  * tensor pass.  Synchronises the stream before returning. */
 dgn_status cp_als(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, void* const* A, int32_t sweeps,

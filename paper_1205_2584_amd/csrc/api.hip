@@ -306,7 +306,8 @@ hipError_t run_gram(const Work& w, const double* A, double* Cout, const int* sto
 }
 
 // ALS sweeps (eq. ALS) on the workspace factors w.A: modes in turn, each from a
-// fresh Gram set, Gamma^(n)^-1 (k_gamma at mu = 0) and an all-mode tensor pass.
+// fresh Gram set, Gamma^(n)^-1 (k_gamma / k_gamma_c at mu = 0) and an all-mode
+// tensor pass (with conjugated factors for complex tensors, Theorem 5.4).
 // A Gamma^(n) that is not positive definite raises singular[0].
 hipError_t enqueue_als(Work& w, const PassSel& plain, int sweeps, int* singular, hipStream_t st) {
   const Shape& s = w.s;
@@ -314,9 +315,12 @@ hipError_t enqueue_als(Work& w, const PassSel& plain, int sweeps, int* singular,
   for (int it = 0; it < sweeps; ++it)
     for (int n = 0; n < s.N; ++n) {
       if ((e = run_gram(w, w.A, w.sb.C, nullptr, st)) != hipSuccess) return e;
-      if ((e = launch_gamma(s, w.sb.C, 0.0, nullptr, w.sb, singular, nullptr, st)) != hipSuccess) return e;
+      e = (w.cs == 2) ? launch_gamma_c(s, w.sb.C, 0.0, nullptr, w.sb, singular, nullptr, st)
+                      : launch_gamma(s, w.sb.C, 0.0, nullptr, w.sb, singular, nullptr, st);
+      if (e != hipSuccess) return e;
       if ((e = run_pass(w, plain, w.A, false, w.M, nullptr, nullptr, st)) != hipSuccess) return e;
-      if ((e = launch_als_rows(s, n, w.M, w.sb, w.A, st)) != hipSuccess) return e;
+      e = (w.cs == 2) ? launch_als_rows_c(s, n, w.M, w.sb, w.A, st) : launch_als_rows(s, n, w.M, w.sb, w.A, st);
+      if (e != hipSuccess) return e;
     }
   return hipSuccess;
 }
@@ -475,8 +479,6 @@ dgn_status cp_fit(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, void* const* A, 
   if (o.poll_every < 1) o.poll_every = 1;
   if (o.normalize < 0 || o.normalize > 2) return set_err(ctx, DGN_EINVAL, "bad normalize option");
   if (o.als_sweeps < 0) return set_err(ctx, DGN_EINVAL, "als_sweeps must be >= 0");
-  if (o.als_sweeps > 0 && Y && (Y->dtype == DGN_C64 || Y->dtype == DGN_C128))
-    return set_err(ctx, DGN_EINVAL, "the ALS warm-up is built for real tensors only");
   Work w{};
   dgn_status rc = prepare(ctx, Y, R, true, w);
   if (rc != DGN_OK) return rc;
@@ -582,8 +584,6 @@ dgn_status cp_als(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, void* const* A, 
   if (!ctx) return DGN_EINVAL;
   if (!A) return set_err(ctx, DGN_EINVAL, "factor pointer array is NULL");
   if (sweeps < 0) return set_err(ctx, DGN_EINVAL, "sweeps must be >= 0");
-  if (Y && (Y->dtype == DGN_C64 || Y->dtype == DGN_C128))
-    return set_err(ctx, DGN_EINVAL, "ALS is built for real tensors only");
   dgn_opts o;
   dgn_opts_default(&o);
   if (opts) o = *opts;
@@ -596,10 +596,10 @@ dgn_status cp_als(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, void* const* A, 
   HIPCHK(hipSetDevice(ctx->device), "hipSetDevice");
   const Shape& s = w.s;
   // the updates use the plain MTTKRP; the error after the last sweep is taken
-  // from the residual pass for FP64 tensors (cancellation-free), otherwise from
-  // ||Y||^2 - 2 <Y, Y_hat> + ||Y_hat||^2
+  // from the residual pass for FP64 and complex tensors (cancellation-free, and
+  // the form the complex fit uses), otherwise from ||Y||^2 - 2 <Y, Y_hat> + ||Y_hat||^2
   const PassSel plain = pass_tensor(w, Y, o, false);
-  const bool resid_err = (w.ymaster == YType::F64);
+  const bool resid_err = (w.ymaster == YType::F64) || w.cs == 2;
   const long long J = [&] { long long j = 1; for (int n = 0; n < s.N; ++n) j *= s.I[n]; return j; }();
   double* ynp = w.scr + 1028;
   double* e2 = w.scr + 1024;

@@ -775,6 +775,25 @@ __global__ void k_inner_c(Shape s, const cd* A, const cd* M, double* out) {
   if (threadIdx.x == 0) out[0] = v;
 }
 
+// ALS update of mode n for complex tensors: A_n = M_n conj(Gt_n) = M_n (Gamma^(n)T)^-1
+// (Gt_n = Gamma^(n)^-1, Hermitian; M_n is the MTTKRP on conjugated factors),
+// one thread per entry of the column-major I_n x R block.
+__global__ __launch_bounds__(256) void k_als_rows_c(Shape s, int n, const cd* M, const cd* Gt, cd* A) {
+  __shared__ cd Gs[kMaxRankC * kMaxRankC];
+  const int R = s.R, R2 = R * R, In = s.I[n], t = threadIdx.x;
+  for (int e = t; e < R2; e += 256) Gs[e] = conjc(Gt[(long long)n * R2 + e]);
+  sync_block();
+  const cd* Mn = M + (long long)s.off[n] * R;
+  cd* An = A + (long long)s.off[n] * R;
+  const long long total = (long long)In * R;
+  for (long long e = blockIdx.x * 256LL + t; e < total; e += (long long)gridDim.x * 256) {
+    const int i = (int)(e % In), r = (int)(e / In);
+    cd acc = czero();
+    for (int k = 0; k < R; ++k) acc += Mn[i + (long long)k * In] * Gs[k + r * R];
+    An[e] = acc;
+  }
+}
+
 }  // namespace
 
 PassPlan plan_pass_c(const Shape& s) {
@@ -913,6 +932,24 @@ hipError_t launch_small_post_c(const Shape& s, const double* A, double* Ac, cons
                                              mu_host, state, reinterpret_cast<cd*>(Ac), b.rowpart, ch, stride, stop);
   k_rows_reduce_c<<<s.N, 256, 0, st>>>(b.rowpart, ch, stride, 2 * s.R * s.R, b.Cc, stop);
   k_scalars_reduce_c<<<1, 64, 0, st>>>(b.rowpart, s.N, ch, stride, s.R * s.R, b.scal, stop);
+  return hipGetLastError();
+}
+
+hipError_t launch_gamma_c(const Shape& s, const double* C, double mu_host, const FitState* state,
+                          const SmallBuffers& b, int* singular, const int* stop, hipStream_t st) {
+  k_gamma_c<<<dim3(s.N, 2), 256, 0, st>>>(s, reinterpret_cast<const cd*>(C), mu_host, state,
+                                           reinterpret_cast<cd*>(b.Gam), reinterpret_cast<cd*>(b.Gt),
+                                           reinterpret_cast<cd*>(b.X), reinterpret_cast<cd*>(b.Lc), singular, stop);
+  return hipGetLastError();
+}
+
+hipError_t launch_als_rows_c(const Shape& s, int n, const double* M, const SmallBuffers& b, double* A,
+                             hipStream_t st) {
+  const long long total = (long long)s.I[n] * s.R;
+  long long blocks = (total + 255) / 256;
+  if (blocks > 1024) blocks = 1024;
+  k_als_rows_c<<<(unsigned)blocks, 256, 0, st>>>(s, n, reinterpret_cast<const cd*>(M),
+                                                  reinterpret_cast<const cd*>(b.Gt), reinterpret_cast<cd*>(A));
   return hipGetLastError();
 }
 

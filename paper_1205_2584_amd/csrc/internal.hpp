@@ -127,6 +127,12 @@ hipError_t launch_subblock_c(const Shape& s, const SysPlan& p, const SmallBuffer
                              const int* stop, hipStream_t st);
 hipError_t launch_small_post_c(const Shape& s, const double* A, double* Ac, const SmallBuffers& b,
                                double mu_host, const FitState* state, const int* stop, hipStream_t st);
+// Gamma_n, the Cholesky of Gamma_n + mu I and Gt_n = (Gamma_n + mu I)^-1 for every mode (complex).
+hipError_t launch_gamma_c(const Shape& s, const double* C, double mu_host, const FitState* state,
+                          const SmallBuffers& b, int* singular, const int* stop, hipStream_t st);
+// Complex ALS update of mode n: A_n = M_n conj(Gt_n), Gt_n = Gamma^(n)^-1 from launch_gamma_c at mu = 0.
+hipError_t launch_als_rows_c(const Shape& s, int n, const double* M, const SmallBuffers& b, double* A,
+                             hipStream_t st);
 
 // ---- fit control -------------------------------------------------------------
 // cs: doubles per element of the factor, MTTKRP and Gram arrays (1 real, 2 complex).
