@@ -180,6 +180,22 @@ dgn_status dgn_step(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, const void* co
                     void* const* A_out, double mu, const dgn_opts* opts, dgn_step_info* info,
                     void* stream);
 
+/* The plain damped Gauss-Newton step of Section 3 with the Hessian formed
+ * explicitly: (J^T J + mu I) da = J^T vec(Y - Y_hat), J^T J of size RT x RT
+ * with the block form of Appendix B (diagonal blocks Gamma^(n) (x) I, off-diagonal
+ * entries A_n[i, c] A_m[j, r] Gamma^(n,m)[r, c]), factored by the same tiled FP64
+ * Cholesky as the fast step.  The paper's dGN baseline, for cost and memory
+ * comparisons with dgn_step (Section 6); same arguments, outputs and errors as
+ * dgn_step, real tensors only (a complex dtype gives DGN_EINVAL).  Its workspace,
+ * about (RT)^2 x 8 bytes, comes from dgn_workspace_size_explicit.  Synchronises
+ * the stream before returning. */
+dgn_status dgn_step_explicit(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, const void* const* A_in,
+                             void* const* A_out, double mu, const dgn_opts* opts, dgn_step_info* info,
+                             void* stream);
+
+/* Workspace bytes dgn_step_explicit needs for this shape (real tensors). */
+dgn_status dgn_workspace_size_explicit(const dgn_tensor* Y, int32_t R, size_t* bytes);
+
 /* Algorithm 1 with the damping of Section 4.5, device-resident.  A: in the
  * starting factors, out the result (N device pointers, FP64 / C128).
  * mu0 > 0 is used as given, mu0 <= 0 takes tau * max diag Gamma^(n).

@@ -70,6 +70,8 @@ struct Work {
   SmallBuffers sb;
   PassBuffers pb;
   SysBuffers sy;
+  SysPlan ep;      // explicit-Hessian system (dgn_step_explicit only)
+  SysBuffers ey;
   FitState* state;
   int* flags;      // [0] singular (step), [1..] spare
   double* scr;     // [0..1023] norm partials, [1024] e2, [1025] e2c, [1026..1029] err2 / ynorm2
@@ -195,6 +197,34 @@ dgn_status prepare(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, bool with_syste
   plan(w);
   Arena ar{ctx ? ctx->ws : nullptr, ctx ? ctx->ws_size : (size_t)-1};
   carve(ar, w, with_system);
+  if (ar.fail) {
+    return set_err(ctx, DGN_ENOMEM,
+                   "workspace budget too small: need " + std::to_string(ar.used) + " bytes, have " +
+                       std::to_string(ctx ? ctx->ws_size : 0));
+  }
+  return DGN_OK;
+}
+
+// Workspace of dgn_step_explicit: the small buffers, the tensor pass and the
+// RT x RT Hessian system (no fast-step system).
+void carve_explicit(Arena& ar, Work& w) {
+  carve(ar, w, false);
+  w.ep = plan_sys_explicit(w.s);
+  const SysPlan& q = w.ep;
+  w.ey.St = ar.take<double>((size_t)q.lds * q.ntp);
+  w.ey.B = nullptr;
+  w.ey.yt = ar.take<double>((size_t)q.ntp);
+  w.ey.Ld = ar.take<double>((size_t)q.Tt * 64 * 64);
+  w.ey.Li = ar.take<double>((size_t)q.Tt * 64 * 64);
+}
+
+dgn_status prepare_explicit(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, Work& w) {
+  dgn_status st = check_shape(ctx, Y, R, &w.s, &w.ymaster);
+  if (st != DGN_OK) return st;
+  if (is_complex(w.ymaster)) return set_err(ctx, DGN_EINVAL, "the explicit-Hessian step is built for real tensors only");
+  plan(w);
+  Arena ar{ctx ? ctx->ws : nullptr, ctx ? ctx->ws_size : (size_t)-1};
+  carve_explicit(ar, w);
   if (ar.fail) {
     return set_err(ctx, DGN_ENOMEM,
                    "workspace budget too small: need " + std::to_string(ar.used) + " bytes, have " +
@@ -390,6 +420,19 @@ dgn_status dgn_workspace_size(const dgn_tensor* Y, int32_t R, const dgn_opts* op
   return DGN_OK;
 }
 
+dgn_status dgn_workspace_size_explicit(const dgn_tensor* Y, int32_t R, size_t* bytes) {
+  if (!bytes) return DGN_EINVAL;
+  Work w{};
+  dgn_status st = check_shape(nullptr, Y, R, &w.s, &w.ymaster);
+  if (st != DGN_OK) return st;
+  if (is_complex(w.ymaster)) return DGN_EINVAL;
+  plan(w);
+  Arena ar{nullptr, (size_t)-1};
+  carve_explicit(ar, w);
+  *bytes = ar.used;
+  return DGN_OK;
+}
+
 dgn_status dgn_mttkrp(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, const void* const* A,
                       void* const* M, double* inner, void* stream) {
   if (!ctx) return DGN_EINVAL;
@@ -462,6 +505,68 @@ dgn_status dgn_step(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, const void* co
     info->mnorm = sqrt(sc[3]);
   }
   if (flags[0]) return set_err(ctx, DGN_ESINGULAR, "non-positive pivot in (Gamma + mu I) or the NR^2 system");
+  if (!isfinite(host[1]) || !isfinite(sc[0])) return set_err(ctx, DGN_ENONFINITE, "non-finite step");
+  return DGN_OK;
+}
+
+dgn_status dgn_step_explicit(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, const void* const* A_in,
+                             void* const* A_out, double mu, const dgn_opts* opts, dgn_step_info* info,
+                             void* stream) {
+  if (!ctx) return DGN_EINVAL;
+  if (!A_in || !A_out) return set_err(ctx, DGN_EINVAL, "factor pointer array is NULL");
+  if (!(mu > 0.0) || !isfinite(mu)) return set_err(ctx, DGN_EINVAL, "mu must be finite and > 0");
+  dgn_opts o;
+  dgn_opts_default(&o);
+  if (opts) o = *opts;
+  Work w{};
+  dgn_status rc = prepare_explicit(ctx, Y, R, w);
+  if (rc != DGN_OK) return rc;
+  for (int n = 0; n < w.s.N; ++n)
+    if (!A_in[n] || !A_out[n]) return set_err(ctx, DGN_EINVAL, "NULL factor pointer");
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(hipSetDevice(ctx->device), "hipSetDevice");
+  const Shape& s = w.s;
+  const bool resid = (w.ymaster == YType::F64) || o.resid_switch < 0;
+  const PassSel ps = pass_tensor(w, Y, o, resid);
+  const long long J = [&] { long long j = 1; for (int n = 0; n < s.N; ++n) j *= s.I[n]; return j; }();
+  double* ynp = w.scr + 1028;
+  double* e2a = w.scr + 1024;
+  double* e2b = w.scr + 1025;
+  double* out = w.scr + 1026;
+  HIPCHK(hipMemsetAsync(w.flags, 0, 64 * sizeof(int), st), "memset");
+  HIPCHK(copy_factors_in(w, A_in, w.A, st), "copy factors");
+  HIPCHK(run_norm2(ps, J, w.scr, ynp, st), "norm");
+  HIPCHK(run_gram(w, w.A, w.sb.C, nullptr, st), "gram");
+  HIPCHK(run_pass(w, ps, w.A, resid, w.M, e2a, nullptr, st), "pass");
+  HIPCHK(launch_err2(s, w.A, w.M, w.sb.C, resid, e2a, ynp, out, st), "err2");
+  // gradient blocks G (and ||G||^2, ||M||^2) through the fast step's own kernels
+  HIPCHK(launch_gamma(s, w.sb.C, mu, nullptr, w.sb, w.flags, nullptr, st), "gamma");
+  HIPCHK(launch_pw(s, w.A, w.M, resid, w.sb, nullptr, st), "pw");
+  HIPCHK(launch_wz(s, w.sb, nullptr, st), "wz");
+  // (J^T J + mu I) da = g, J^T J formed explicitly
+  HIPCHK(launch_explicit_system(s, w.ep, w.A, w.sb.C, w.sb.G, mu, w.ey.St, st), "hessian");
+  HIPCHK(launch_sys_factor_solve_core(w.ep, w.ey, w.flags, nullptr, st), "factor");
+  HIPCHK(launch_explicit_update(w.ep, w.A, w.ey.yt, w.sb.G, mu, w.Ac, w.sb.scal, st), "update");
+  HIPCHK(run_gram(w, w.Ac, w.sb.Cc, nullptr, st), "gram");
+  HIPCHK(run_pass(w, ps, w.Ac, resid, w.Mc, e2b, nullptr, st), "pass");
+  HIPCHK(launch_err2(s, w.Ac, w.Mc, w.sb.Cc, resid, e2b, ynp, out + 1, st), "err2");
+  HIPCHK(copy_factors_out(w, w.Ac, A_out, st), "copy out");
+  double host[2] = {0, 0}, sc[4] = {0, 0, 0, 0};
+  int flags[1] = {0};
+  HIPCHK(hipMemcpyAsync(host, out, sizeof host, hipMemcpyDeviceToHost, st), "copy");
+  HIPCHK(hipMemcpyAsync(sc, w.sb.scal, sizeof sc, hipMemcpyDeviceToHost, st), "copy");
+  HIPCHK(hipMemcpyAsync(flags, w.flags, sizeof flags, hipMemcpyDeviceToHost, st), "copy");
+  HIPCHK(hipStreamSynchronize(st), "sync");
+  if (info) {
+    info->err2_old = host[0];
+    info->err2_new = host[1];
+    info->denom = sc[0];
+    info->rho = (host[0] - host[1]) / sc[0];
+    info->danorm = sqrt(sc[1]);
+    info->gnorm = sqrt(sc[2]);
+    info->mnorm = sqrt(sc[3]);
+  }
+  if (flags[0]) return set_err(ctx, DGN_ESINGULAR, "non-positive pivot in J^T J + mu I");
   if (!isfinite(host[1]) || !isfinite(sc[0])) return set_err(ctx, DGN_ENONFINITE, "non-finite step");
   return DGN_OK;
 }

@@ -951,10 +951,8 @@ SysPlan plan_sys_c(const Shape& s) {
   return p;
 }
 
-hipError_t launch_sys_factor_solve(const Shape& s, const SysPlan& p, const SmallBuffers& b,
-                                   const SysBuffers& y, int* singular, const int* stop,
-                                   hipStream_t st) {
-  (void)s;
+hipError_t launch_sys_factor_solve_core(const SysPlan& p, const SysBuffers& y, int* singular, const int* stop,
+                                        hipStream_t st) {
   for (int ph = 0; ph < p.Tt; ++ph) {
     const int npanel = p.Tt - ph + 1;
     long long nupd = 0;
@@ -966,6 +964,15 @@ hipError_t launch_sys_factor_solve(const Shape& s, const SysPlan& p, const Small
   int k = p.Tt - 1;
   for (; k >= 1; k -= 2) k_bsolve2<<<k + 1, 256, 0, st>>>(p, k, y.St, y.Li, y.yt, stop);
   if (k == 0) k_bsolve<<<1, 256, 0, st>>>(p, 0, y.St, y.Li, y.yt, stop);
+  return hipGetLastError();
+}
+
+hipError_t launch_sys_factor_solve(const Shape& s, const SysPlan& p, const SmallBuffers& b,
+                                   const SysBuffers& y, int* singular, const int* stop,
+                                   hipStream_t st) {
+  (void)s;
+  hipError_t e = launch_sys_factor_solve_core(p, y, singular, stop, st);
+  if (e != hipSuccess) return e;
   k_y0<<<(p.R2 + 3) / 4, 256, 0, st>>>(p, y.B, b.z, y.yt, b.y, stop);
   return hipGetLastError();
 }

@@ -102,6 +102,21 @@ hipError_t launch_sys_assemble(const Shape& s, const SysPlan& p, const SmallBuff
 hipError_t launch_sys_factor_solve(const Shape& s, const SysPlan& p, const SmallBuffers& b,
                                    const SysBuffers& y, int* singular, const int* stop,
                                    hipStream_t st);
+// The tiled Cholesky of the lower tiles of y.St with the right-hand-side row
+// (forward substitution inside), the inverse diagonal tiles and the backward
+// substitution into y.yt; any system size with the SysPlan layout.
+hipError_t launch_sys_factor_solve_core(const SysPlan& p, const SysBuffers& y, int* singular, const int* stop,
+                                        hipStream_t st);
+
+// ---- explicit-Hessian dGN step (Section 3; the comparison baseline) -----------
+// System of the RT parameters: nt = R T, padded to 64.
+SysPlan plan_sys_explicit(const Shape& s);
+// H + mu I (lower tiles) and the gradient G (stacked T x R, as the right-hand-side row) into St.
+hipError_t launch_explicit_system(const Shape& s, const SysPlan& p, const double* A, const double* C,
+                                  const double* G, double mu, double* St, hipStream_t st);
+// Ac = A + da; scal[0] = da^T (G + mu da), scal[1] = ||da||^2.
+hipError_t launch_explicit_update(const SysPlan& p, const double* A, const double* da, const double* G,
+                                  double mu, double* Ac, double* scal, hipStream_t st);
 
 // The assemble phase in two parts so that the complex path can write its own
 // (embedded) sub-blocks in between: identity / zero fill, then RHS row and SYRK.

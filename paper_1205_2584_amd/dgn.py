@@ -74,7 +74,8 @@ class dgn_result(ctypes.Structure):
 
 
 EXPORTS = ["dgn_opts_default", "dgn_create", "dgn_destroy", "dgn_last_error", "dgn_workspace_size",
-           "dgn_mttkrp", "dgn_step", "cp_fit", "cp_als", "dgn_last_phase_times", "cp_fit_batched",
+           "dgn_mttkrp", "dgn_step", "dgn_step_explicit", "dgn_workspace_size_explicit", "cp_fit", "cp_als",
+           "dgn_last_phase_times", "cp_fit_batched",
            "dgn_server_create", "dgn_server_submit", "dgn_server_poll", "dgn_server_wait_idle",
            "dgn_server_stats", "dgn_server_now", "dgn_server_destroy"]
 NUM_PHASES = 6
@@ -106,6 +107,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                            dbl, ctypes.POINTER(dgn_opts), ctypes.POINTER(dgn_step_info), vp]
     L.cp_fit.argtypes = [vp, ctypes.POINTER(dgn_tensor), i32, ctypes.POINTER(vp), dbl, dbl, i32,
                          ctypes.POINTER(dgn_opts), ctypes.POINTER(dgn_fit_info), vp]
+    L.dgn_step_explicit.argtypes = [vp, ctypes.POINTER(dgn_tensor), i32, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                    dbl, ctypes.POINTER(dgn_opts), ctypes.POINTER(dgn_step_info), vp]
+    L.dgn_workspace_size_explicit.argtypes = [ctypes.POINTER(dgn_tensor), i32, ctypes.POINTER(ctypes.c_size_t)]
     L.cp_als.argtypes = [vp, ctypes.POINTER(dgn_tensor), i32, ctypes.POINTER(vp), i32,
                          ctypes.POINTER(dgn_opts), ctypes.POINTER(dbl), vp]
     L.dgn_last_phase_times.argtypes = [vp, ctypes.POINTER(dbl), i32, ctypes.POINTER(i32)]
@@ -120,6 +124,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.dgn_server_now.restype = dbl
     L.dgn_server_destroy.argtypes = [vp]
     for name in ("dgn_create", "dgn_destroy", "dgn_workspace_size", "dgn_mttkrp", "dgn_step", "cp_fit", "cp_als",
+                 "dgn_step_explicit", "dgn_workspace_size_explicit",
                  "dgn_last_phase_times", "cp_fit_batched", "dgn_server_create", "dgn_server_submit",
                  "dgn_server_poll", "dgn_server_wait_idle", "dgn_server_stats", "dgn_server_destroy"):
         getattr(L, name).restype = ctypes.c_int
@@ -212,6 +217,16 @@ class Context:
         self._check(self.L.dgn_step(self.h, ctypes.byref(d), int(R), _ptrs(factors), _ptrs(out),
                                     float(mu), ctypes.byref(options) if options else None,
                                     ctypes.byref(info), _stream()))
+        return out, {k: getattr(info, k) for k, _ in dgn_step_info._fields_}
+
+    def dgn_step_explicit(self, y, dims, R, factors, mu, options: dgn_opts | None = None, out=None):
+        """The plain dGN step with J^T J formed explicitly (same outputs as dgn_step)."""
+        out = [torch.empty_like(a) for a in factors] if out is None else out
+        info = dgn_step_info()
+        d = tensor_desc(y, dims)
+        self._check(self.L.dgn_step_explicit(self.h, ctypes.byref(d), int(R), _ptrs(factors), _ptrs(out),
+                                             float(mu), ctypes.byref(options) if options else None,
+                                             ctypes.byref(info), _stream()))
         return out, {k: getattr(info, k) for k, _ in dgn_step_info._fields_}
 
     def cp_fit(self, y, dims, R, factors, mu0, tol, max_iters, options: dgn_opts | None = None):
@@ -322,6 +337,20 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def workspace_size_explicit(dims, R, dtype=torch.float64) -> int:
+    d = dgn_tensor()
+    d.order = len(dims)
+    for k, v in enumerate(dims):
+        d.dims[k] = int(v)
+    d.dtype = _DTYPE[dtype]
+    d.data = 1
+    n = ctypes.c_size_t()
+    st = load().dgn_workspace_size_explicit(ctypes.byref(d), int(R), ctypes.byref(n))
+    if st != 0:
+        raise DgnError(st, "dgn_workspace_size_explicit failed")
+    return n.value
 
 
 def workspace_size(dims, R, dtype=torch.float64) -> int:
