@@ -225,6 +225,42 @@ def bench_als(dgn, torch, ctx, y, dims, R, p, dev, sweeps=5):
             "passes_per_sweep": len(dims), "eps_start": (e0 / ynorm2) ** 0.5, "eps_after": (ek / ynorm2) ** 0.5}
 
 
+def bench_dgn_vs_flm(dgn, torch, ranks=(5, 10, 20, 30, 40, 50, 60), reps=3, mu=10.0):
+    """Time per step and workspace of the fast step (dgn_step) against the plain
+    dGN step with J^T J formed explicitly (dgn_step_explicit) on 100 x 100 x 100
+    tensors with random entries, as in the paper's complexity study (Section 6),
+    for ranks up to this library's limit of 64.  Both steps include the two
+    tensor passes (before and after) of a trial."""
+    dims = (100, 100, 100)
+    J = 100 ** 3
+    out = []
+    g = torch.Generator(device="cuda")
+    for R in ranks:
+        g.manual_seed(1000 + R)
+        y = torch.randn(J, generator=g, device="cuda", dtype=torch.float64)
+        A = [torch.randn((R, 100), generator=g, device="cuda", dtype=torch.float64) for _ in dims]
+        ws_f = dgn.workspace_size(dims, R)
+        ws_e = dgn.workspace_size_explicit(dims, R)
+        ctx = dgn.Context(0, max(ws_f, ws_e) + (16 << 20))
+        row = {"R": R, "flm_workspace_MB": round(ws_f / 1e6, 1), "dgn_workspace_MB": round(ws_e / 1e6, 1)}
+        try:
+            for name, fn in (("flm", ctx.dgn_step), ("dgn", ctx.dgn_step_explicit)):
+                fn(y, dims, R, A, mu)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    fn(y, dims, R, A, mu)
+                torch.cuda.synchronize()
+                row[f"{name}_ms_per_step"] = round((time.perf_counter() - t0) / reps * 1e3, 3)
+        finally:
+            ctx.close()
+        row["dgn_over_flm_time"] = round(row["dgn_ms_per_step"] / row["flm_ms_per_step"], 2)
+        out.append(row)
+        del y, A
+        torch.cuda.empty_cache()
+    return {"tensor": "100x100x100 FP64, random entries", "mu": mu, "steps": out}
+
+
 def rel(a, b):
     import numpy as np
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
@@ -303,6 +339,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--no-als", action="store_true")
+    ap.add_argument("--no-dgn-sweep", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run a plain copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
@@ -402,6 +439,8 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_precision:
         line["precision"] = precision_report(dgn, torch, p)
+    if not args.no_dgn_sweep:
+        line["dgn_vs_flm"] = bench_dgn_vs_flm(dgn, torch)
     if not args.no_batched:
         line["batched"] = bench_batched(dgn, torch)
     if not args.no_serving:
