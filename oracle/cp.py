@@ -400,3 +400,32 @@ def als(Y: np.ndarray, A, sweeps: int):
         A = als_sweep(Y, A)
         errs.append(residual_norm2(Y, A))
     return A, errs
+
+
+# ----------------------------------------------------------------------------
+# SVD initialisation (Section 4.5): the leading R left singular vectors of
+# every unfolding
+# ----------------------------------------------------------------------------
+
+
+def canonical_signs(U: np.ndarray) -> np.ndarray:
+    """Flip each column so that its entry of largest magnitude (the first one
+    on ties) is positive: singular vectors are defined up to sign."""
+    U = np.array(U, copy=True)
+    for r in range(U.shape[1]):
+        k = int(np.argmax(np.abs(U[:, r])))
+        if U[k, r] < 0:
+            U[:, r] = -U[:, r]
+    return U
+
+
+def svd_init(Y: np.ndarray, R: int):
+    """A^(n) = the R leading left singular vectors of Y_(n) (columns ordered by
+    decreasing singular value, canonical signs), through a library SVD, and the
+    singular values."""
+    A, S = [], []
+    for n in range(Y.ndim):
+        U, s, _ = np.linalg.svd(unfold(Y, n), full_matrices=False)
+        A.append(canonical_signs(U[:, :R]))
+        S.append(s[:R])
+    return A, S

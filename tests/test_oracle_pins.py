@@ -407,3 +407,39 @@ def test_als_planted_all_mode_gamma_fails_the_pin():
         B[n] = np.linalg.solve(G, M.T).T
     want = _brute_als_sweep(Y, A)
     assert max(_rel(b, w) for b, w in zip(B, want)) > 1e-3
+
+
+# ---- SVD initialisation (Section 4.5) ----------------------------------------
+
+
+def test_svd_init_matches_eigenvectors_of_the_mode_gram():
+    # a different route: eigenvectors of Y_(n) Y_(n)^T built by an explicit
+    # loop over the mode-n fibres, from a symmetric eigensolver
+    rng = np.random.default_rng(21)
+    dims, R = (7, 6, 5), 3
+    Y = rng.standard_normal(dims)
+    A, S = cp.svd_init(Y, R)
+    for n in range(3):
+        G = np.zeros((dims[n], dims[n]))
+        others = [k for k in range(3) if k != n]
+        for idx in np.ndindex(*[dims[k] for k in others]):
+            sl = [slice(None)] * 3
+            for k, i in zip(others, idx):
+                sl[k] = i
+            f = Y[tuple(sl)]
+            G += np.outer(f, f)
+        w, V = np.linalg.eigh(G)
+        V = cp.canonical_signs(V[:, ::-1][:, :R])
+        assert np.allclose(S[n] ** 2, w[::-1][:R], rtol=1e-10)
+        assert np.linalg.norm(A[n] - V) < 1e-9
+        assert np.linalg.norm(A[n].T @ A[n] - np.eye(R)) < 1e-12
+
+
+def test_svd_init_spans_the_factors_of_an_exact_rank_r_tensor():
+    rng = np.random.default_rng(22)
+    dims, R = (8, 7, 9), 3
+    F = [rng.standard_normal((I, R)) for I in dims]
+    A, _ = cp.svd_init(cp.full(F), R)
+    for a, f in zip(A, F):
+        # the projector onto span(A^(n)) reproduces the true factor
+        assert np.linalg.norm(a @ (a.T @ f) - f) < 1e-10 * np.linalg.norm(f)
