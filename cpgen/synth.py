@@ -188,3 +188,9 @@ def cfg4(seed: int = 4, count: int = 1024, max_iters: int = 200, tol: float = 1e
         out.append(Problem(dims, R, y, truth, init, mu0=-1.0, max_iters=max_iters, tol=tol,
                            sigma=sigma, meta={"name": "cfg4", "index": b, "c": c, "snr_db": snr}))
     return out
+
+
+def svd_start_block(rng: np.random.Generator, dims, block: int) -> np.ndarray:
+    """Random start blocks of the SVD initialisation: N(0,1) entries, mode n's
+    I_n x block column-major block after those of the earlier modes."""
+    return np.concatenate([rng.standard_normal((block, int(I))).reshape(-1) for I in dims])

@@ -226,6 +226,37 @@ dgn_status cp_fit(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, void* const* A, 
 dgn_status cp_als(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, void* const* A, int32_t sweeps,
                   const dgn_opts* opts, double* err2, void* stream);
 
+/* Mode-n Gram matrix G = Y_(n) Y_(n)^T (I_n x I_n, FP64, column-major,
+ * leading dimension I_n, both triangles written), the matrix whose leading
+ * eigenvectors are the mode-n singular vectors used to initialise the factors
+ * (Section 4.5).  Real tensors (F64, F32, BF16; entries widened to FP64 and
+ * products summed in FP64); a complex dtype or n outside [0, order) gives
+ * DGN_EINVAL.  G: caller-owned device buffer.  Uses the context's workspace
+ * (about 64 MB at most for the partial tiles); enqueued on `stream` without a
+ * synchronisation. */
+dgn_status dgn_mode_gram(dgn_ctx* ctx, const dgn_tensor* Y, int32_t n, double* G, void* stream);
+
+/* SVD initialisation (Section 4.5, as the experiments of Section 6 start):
+ * A^(n) = the R leading left singular vectors of Y_(n), for every n, columns in
+ * decreasing order of singular value, each column signed so that its entry of
+ * largest magnitude (the first such on ties) is positive.  Computed as the
+ * leading eigenvectors of Y_(n) Y_(n)^T (dgn_mode_gram) by `iters` steps of
+ * subspace iteration with a block of `block` columns (R <= block <= min(min_n
+ * I_n, 80); block > R speeds convergence of the R-th vector to the rate
+ * ((lambda_{block+1} + s) / (lambda_R + s))^iters, s = 1e-7 trace) and a final
+ * Rayleigh-Ritz step.  omega: device, the random start blocks, sum_n I_n x
+ * block doubles, mode n's I_n x block column-major block after those of modes
+ * < n.  A: N device pointers to I_n x R FP64 outputs.  sv (device, may be
+ * NULL): N x R doubles, sv[n R + r] = r-th singular value of Y_(n).  Needs
+ * R <= every I_n and a real tensor (DGN_EINVAL otherwise).  DGN_ESINGULAR if
+ * the orthonormalisation breaks down (omega of deficient rank).  Workspace
+ * from dgn_workspace_size_svd.  Synchronises the stream before returning. */
+dgn_status cp_svd_init(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, int32_t block, const double* omega,
+                       int32_t iters, void* const* A, double* sv, void* stream);
+
+/* Workspace bytes cp_svd_init needs for this shape, rank and block. */
+dgn_status dgn_workspace_size_svd(const dgn_tensor* Y, int32_t R, int32_t block, size_t* bytes);
+
 /* One small fit of a batch: a 3-way tensor (F32 or F64, every I_n <= 64),
  * rank 1 <= R <= 8, the initial damping (> 0 used as given, <= 0 the tau
  * rule) and three device pointers to FP64 column-major I_n x R factors

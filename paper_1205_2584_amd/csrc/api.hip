@@ -732,6 +732,124 @@ dgn_status cp_als(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, void* const* A, 
   return DGN_OK;
 }
 
+// ---- mode-n singular vectors (SVD initialisation) ---------------------------
+
+namespace {
+
+constexpr int kMaxSvdBlock = 80;
+
+struct SvdWork {
+  SvdModes m;
+  double* part;
+  double* sigma;
+  int* bad;
+};
+
+// Validates the tensor for the SVD calls (real dtypes, no rank check beyond
+// 1 <= R) and fills s / yt.
+dgn_status check_svd_tensor(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, Shape* s, YType* yt) {
+  const int32_t rr = (R >= 1 && R <= DGN_MAX_RANK) ? R : 1;
+  dgn_status st = check_shape(ctx, Y, rr, s, yt);
+  if (st != DGN_OK) return st;
+  if (is_complex(*yt)) return set_err(ctx, DGN_EINVAL, "the mode Gram and the SVD initialisation take real tensors");
+  return DGN_OK;
+}
+
+void carve_svd(Arena& ar, const Shape& s, int R, int b, SvdWork& w) {
+  SvdModes& m = w.m;
+  m.N = s.N;
+  m.b = b;
+  m.bp = (b + 15) / 16 * 16;
+  m.R = R;
+  m.blk0[0] = 0;
+  for (int n = 0; n < s.N; ++n) {
+    m.I[n] = s.I[n];
+    m.Ip[n] = (s.I[n] + 63) / 64 * 64;
+    m.G[n] = ar.take<double>((size_t)m.Ip[n] * m.Ip[n]);
+    m.Q[n] = ar.take<double>((size_t)m.Ip[n] * m.bp);
+    m.Z[n] = ar.take<double>((size_t)m.Ip[n] * m.bp);
+    m.A[n] = nullptr;
+    m.blk0[n + 1] = m.blk0[n] + (m.Ip[n] / 64) * (m.bp / 16);
+  }
+  w.part = ar.take<double>(gram_part_doubles(s));
+  w.sigma = ar.take<double>(kMaxOrder);
+  w.bad = ar.take<int>(64);
+}
+
+dgn_status check_svd_args(dgn_ctx* ctx, const Shape& s, int32_t R, int32_t block, int32_t iters) {
+  int mn = s.I[0];
+  for (int n = 1; n < s.N; ++n) mn = s.I[n] < mn ? s.I[n] : mn;
+  if (R < 1 || R > DGN_MAX_RANK) return set_err(ctx, DGN_EINVAL, "rank must be in [1, 64]");
+  if (R > mn) return set_err(ctx, DGN_EINVAL, "the SVD initialisation needs R <= every I_n");
+  if (block < R || block > mn || block > kMaxSvdBlock)
+    return set_err(ctx, DGN_EINVAL, "block must satisfy R <= block <= min(min_n I_n, 80)");
+  if (iters < 0) return set_err(ctx, DGN_EINVAL, "iters must be >= 0");
+  return DGN_OK;
+}
+
+}  // namespace
+
+dgn_status dgn_workspace_size_svd(const dgn_tensor* Y, int32_t R, int32_t block, size_t* bytes) {
+  if (!bytes) return DGN_EINVAL;
+  Shape s{};
+  YType yt;
+  dgn_status st = check_svd_tensor(nullptr, Y, R, &s, &yt);
+  if (st != DGN_OK) return st;
+  if ((st = check_svd_args(nullptr, s, R, block, 0)) != DGN_OK) return st;
+  Arena ar{nullptr, (size_t)-1};
+  SvdWork w{};
+  carve_svd(ar, s, R, block, w);
+  *bytes = ar.used;
+  return DGN_OK;
+}
+
+dgn_status dgn_mode_gram(dgn_ctx* ctx, const dgn_tensor* Y, int32_t n, double* G, void* stream) {
+  if (!ctx) return DGN_EINVAL;
+  Shape s{};
+  YType yt;
+  dgn_status st = check_svd_tensor(ctx, Y, 1, &s, &yt);
+  if (st != DGN_OK) return st;
+  if (n < 0 || n >= s.N) return set_err(ctx, DGN_EINVAL, "mode index out of range");
+  if (!G) return set_err(ctx, DGN_EINVAL, "output pointer is NULL");
+  Arena ar{ctx->ws, ctx->ws_size};
+  double* part = ar.take<double>(gram_part_doubles(s));
+  if (ar.fail)
+    return set_err(ctx, DGN_ENOMEM, "workspace budget too small: need " + std::to_string(ar.used) + " bytes");
+  hipStream_t hs = (hipStream_t)stream;
+  HIPCHK(hipSetDevice(ctx->device), "hipSetDevice");
+  HIPCHK(launch_mode_gram(s, n, Y->data, yt, part, G, s.I[n], s.I[n], hs), "mode gram");
+  return DGN_OK;
+}
+
+dgn_status cp_svd_init(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, int32_t block, const double* omega,
+                       int32_t iters, void* const* A, double* sv, void* stream) {
+  if (!ctx) return DGN_EINVAL;
+  Shape s{};
+  YType yt;
+  dgn_status st = check_svd_tensor(ctx, Y, R, &s, &yt);
+  if (st != DGN_OK) return st;
+  if ((st = check_svd_args(ctx, s, R, block, iters)) != DGN_OK) return st;
+  if (!omega) return set_err(ctx, DGN_EINVAL, "start block pointer is NULL");
+  if (!A) return set_err(ctx, DGN_EINVAL, "factor pointer array is NULL");
+  for (int n = 0; n < s.N; ++n)
+    if (!A[n]) return set_err(ctx, DGN_EINVAL, "NULL factor pointer");
+  Arena ar{ctx->ws, ctx->ws_size};
+  SvdWork w{};
+  carve_svd(ar, s, R, block, w);
+  if (ar.fail)
+    return set_err(ctx, DGN_ENOMEM, "workspace budget too small: need " + std::to_string(ar.used) + " bytes");
+  for (int n = 0; n < s.N; ++n) w.m.A[n] = (double*)A[n];
+  hipStream_t hs = (hipStream_t)stream;
+  HIPCHK(hipSetDevice(ctx->device), "hipSetDevice");
+  HIPCHK(hipMemsetAsync(w.bad, 0, sizeof(int), hs), "memset");
+  HIPCHK(launch_svd_init(s, Y->data, yt, w.m, omega, iters, w.part, w.sigma, sv, w.bad, hs), "svd init");
+  int bad = 0;
+  HIPCHK(hipMemcpyAsync(&bad, w.bad, sizeof bad, hipMemcpyDeviceToHost, hs), "copy");
+  HIPCHK(hipStreamSynchronize(hs), "sync");
+  if (bad) return set_err(ctx, DGN_ESINGULAR, "the orthonormalisation of the subspace iteration broke down");
+  return DGN_OK;
+}
+
 dgn_status cp_fit_batched(dgn_ctx* ctx, int32_t B, const dgn_batch_fit* fits, double tol,
                           int32_t max_iters, const dgn_opts* opts, dgn_fit_info* infos,
                           void* stream) {

@@ -188,4 +188,37 @@ hipError_t launch_batched_init(BFit* fits, int nfits, const BatchCfg& cfg, hipSt
 hipError_t launch_batched_trial(BFit* fits, int nfits, const BatchCfg& cfg, hipStream_t st);
 hipError_t launch_batched_final(BFit* fits, int nfits, hipStream_t st);
 
+// ---- mode-n singular vectors (SVD initialisation) ---------------------------
+// Y viewed for mode n as (P, I, Q): element (p, i, q) at p + P (i + I q).
+struct GramPlan {
+  long long P, Q;
+  int I, ntile;            // mode size, lower 64 x 64 tiles of G_n
+  long long nchunk, cps;   // summation chunks of 32, chunks per split
+  int S;                   // splits of the summation (partial tiles per tile)
+};
+GramPlan plan_gram(const Shape& s, int n);
+size_t gram_part_doubles(const Shape& s);  // partial-tile buffer for any mode
+
+// Per-mode buffers of the subspace iteration: G_n (Ip x Ip), Q_n and Z_n
+// (Ip x bp, column-major, leading dimension Ip; Ip = I_n rounded up to 64,
+// bp = b rounded up to 16) and the output factor A_n (I_n x R).
+struct SvdModes {
+  int N, b, bp, R;
+  int I[kMaxOrder], Ip[kMaxOrder];
+  double* G[kMaxOrder];
+  double* Q[kMaxOrder];
+  double* Z[kMaxOrder];
+  double* A[kMaxOrder];
+  int blk0[kMaxOrder + 1];  // first block of each mode in the Z = G Q launch
+};
+
+// G (leading dimension ld) = Y_(n) Y_(n)^T on rows/columns < lim (rows and
+// columns in [I_n, lim) get zeros); part holds gram_part_doubles(s) doubles.
+hipError_t launch_mode_gram(const Shape& s, int n, const void* Y, YType yt, double* part, double* G, long long ld,
+                            int lim, hipStream_t st);
+// The whole SVD initialisation; sigma: N doubles, sv: N x R or NULL, *bad
+// raised on a Cholesky breakdown of the orthonormalisation.
+hipError_t launch_svd_init(const Shape& s, const void* Y, YType yt, SvdModes m, const double* omega, int iters,
+                           double* part, double* sigma, double* sv, int* bad, hipStream_t st);
+
 }  // namespace dgn

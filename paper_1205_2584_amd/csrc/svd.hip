@@ -1,0 +1,585 @@
+// Mode-n singular vectors of a dense real tensor: the SVD initialisation of
+// the factors (Section 4.5; the comparisons of Section 6 start from it).
+//
+// A^(n) is the R leading left singular vectors of the unfolding Y_(n), that
+// is the leading eigenvectors of the mode-n Gram matrix G_n = Y_(n) Y_(n)^T.
+//  1. G_n in FP64 on the matrix cores: 64 x 64 lower tiles, the summation over
+//     the other modes split across workgroups (the splits of one tile set stay
+//     on one XCD so its L2 serves the shared row blocks), the partial tiles
+//     summed in a fixed order, so the result is deterministic.
+//  2. Subspace iteration on G_n + sigma_n I, which has the eigenvectors of G_n;
+//     sigma_n = 1e-7 trace(G_n) bounds the condition number of every iterate
+//     by about 1e7, also for a G_n of low rank.  Each iteration is
+//     Z = (G_n + sigma_n I) Q followed by Q = orth(Z), from the caller's random
+//     start block.  orth is the shifted Cholesky QR of Fukaya, Kannan,
+//     Nakatsukasa, Yamamoto and Yanagisawa (SIAM J. Sci. Comput. 2020), a
+//     Cholesky QR of Z^T Z + s I with s = 11 (m b + b (b + 1)) u ||Z||_F^2,
+//     followed by two plain Cholesky QR passes.
+//  3. Rayleigh-Ritz: H = Q^T (G_n + sigma_n I) Q, its eigenpairs by cyclic
+//     two-sided Jacobi rotations (round-robin ordering, b/2 disjoint rotations
+//     at a time), A^(n) = Q V for the R largest Ritz values in decreasing order,
+//     each column flipped so that its largest-magnitude entry (the first one on
+//     ties) is positive.  Singular values are sqrt(theta_r - sigma_n).
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace dgn {
+
+namespace {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+constexpr int GK = 32;  // summation chunk of a Gram tile
+constexpr int GS = 80;  // LDS row stride of the [k][row] operand tiles
+
+__device__ __forceinline__ void tri_index(long long id, int& ti, int& tj) {
+  ti = (int)((sqrt(8.0 * id + 1.0) - 1.0) / 2.0);
+  while ((long long)(ti + 1) * (ti + 2) / 2 <= id) ++ti;
+  while ((long long)ti * (ti + 1) / 2 > id) --ti;
+  tj = (int)(id - (long long)ti * (ti + 1) / 2);
+}
+
+// Barrier that also orders global-memory writes of the workgroup before the
+// reads after it (vmcnt(0) and lgkmcnt(0), then the barrier).
+__device__ __forceinline__ void sync_block_mem() {
+  __builtin_amdgcn_s_waitcnt(0x0070);
+  __threadfence_block();
+  __syncthreads();
+}
+
+// acc[blk] += A(rows 16w..16w+15)^T-chunk products: acc[blk][v] gains
+// sum_k A[k][16w + lane/16 + 4v] * B[k][16 blk + lane%16] over the GK rows of k.
+__device__ __forceinline__ void mma_chunk(const double (*A)[GS], const double (*B)[GS], v4d acc[4]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int ra = 16 * w + (lane & 15), kk = lane >> 4;
+#pragma unroll
+  for (int k = 0; k < GK; k += 4) {
+    const double a = A[k + kk][ra];
+#pragma unroll
+    for (int blk = 0; blk < 4; ++blk)
+      acc[blk] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, B[k + kk][16 * blk + (lane & 15)], acc[blk], 0, 0, 0);
+  }
+}
+
+// Partial Gram tiles.  Logical block L = tile + ntile * split; the hardware
+// block b runs L = (b % 8) * (gridDim.x / 8) + b / 8, so the consecutive
+// logical blocks that share a split (and its row blocks of Y) sit on one XCD.
+// part[(split * ntile + tile) * 4096 + c + 64 r] = sum over the split's chunks
+// of Y(., 64 ti + r, .) Y(., 64 tj + c, .).
+template <typename T>
+__global__ __launch_bounds__(256) void k_mode_gram(const T* __restrict__ Y, GramPlan g, double* __restrict__ part) {
+  const long long per_xcd = gridDim.x / 8;
+  const long long L = (long long)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  if (L >= (long long)g.ntile * g.S) return;
+  const int tile = (int)(L % g.ntile);
+  const long long split = L / g.ntile;
+  int ti, tj;
+  tri_index(tile, ti, tj);
+  __shared__ double Ti[GK][GS];
+  __shared__ double Tj[GK][GS];
+  const long long c_begin = split * g.cps;
+  const long long c_end = c_begin + g.cps < g.nchunk ? c_begin + g.cps : g.nchunk;
+  const long long cpq = (g.P + GK - 1) / GK;  // chunks per q when P > 1
+  constexpr int NS = GK * 64 / 256;
+  double vi[NS], vj[NS];
+  const bool rows_contig = g.P == 1;
+  auto load = [&](long long c) {
+    if (rows_contig) {  // mode 1: the rows of a chunk are contiguous
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const int e = threadIdx.x + 256 * s, r = e & 63, kc = e >> 6;
+        const long long q = c * GK + kc;
+        const int i = ti * 64 + r, j = tj * 64 + r;
+        vi[s] = (q < g.Q && i < g.I) ? to_f64(Y[i + (long long)g.I * q]) : 0.0;
+        vj[s] = (q < g.Q && j < g.I) ? to_f64(Y[j + (long long)g.I * q]) : 0.0;
+      }
+    } else {  // the chunk runs along p, contiguous for each row
+      const long long q = c / cpq;
+      const long long p0 = (c - q * cpq) * GK;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const int e = threadIdx.x + 256 * s, kc = e & (GK - 1), r = e / GK;
+        const long long p = p0 + kc;
+        const int i = ti * 64 + r, j = tj * 64 + r;
+        vi[s] = (p < g.P && i < g.I) ? to_f64(Y[p + g.P * (i + (long long)g.I * q)]) : 0.0;
+        vj[s] = (p < g.P && j < g.I) ? to_f64(Y[p + g.P * (j + (long long)g.I * q)]) : 0.0;
+      }
+    }
+  };
+  v4d acc[4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) acc[b] = v4d{0.0, 0.0, 0.0, 0.0};
+  if (c_begin < c_end) load(c_begin);
+  for (long long c = c_begin; c < c_end; ++c) {
+    sync_block();
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const int e = threadIdx.x + 256 * s;
+      const int r = rows_contig ? (e & 63) : e / GK;
+      const int kc = rows_contig ? (e >> 6) : (e & (GK - 1));
+      Ti[kc][r] = vi[s];
+      Tj[kc][r] = vj[s];
+    }
+    sync_block();
+    if (c + 1 < c_end) load(c + 1);
+    mma_chunk(Ti, Tj, acc);
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double* out = part + (split * g.ntile + tile) * 4096;
+#pragma unroll
+  for (int blk = 0; blk < 4; ++blk)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = 16 * w + (lane >> 4) + 4 * v, c = 16 * blk + (lane & 15);
+      out[c + 64 * r] = acc[blk][v];
+    }
+}
+
+// G[gr + ld gc] = G[gc + ld gr] = sum over splits (in order) of the partial
+// tiles, for gr >= gc, gr < lim.  One block per lower tile.
+__global__ __launch_bounds__(256) void k_gram_reduce(const double* __restrict__ part, int S, int ntile,
+                                                     double* __restrict__ G, long long ld, int lim) {
+  const int tile = blockIdx.x;
+  int ti, tj;
+  tri_index(tile, ti, tj);
+  for (int s = 0; s < 16; ++s) {
+    const int e = threadIdx.x + 256 * s, r = e >> 6, c = e & 63;
+    double v = 0.0;
+    for (int sp = 0; sp < S; ++sp) v += part[((long long)sp * ntile + tile) * 4096 + e];
+    const int gr = ti * 64 + r, gc = tj * 64 + c;
+    if (gr >= gc && gr < lim) {
+      G[gr + ld * gc] = v;
+      G[gc + ld * gr] = v;
+    }
+  }
+}
+
+// sigma[n] = 1e-7 * trace(G_n); one block per mode.
+__global__ __launch_bounds__(256) void k_svd_shift(SvdModes m, double* sigma) {
+  __shared__ double red[16];
+  const int n = blockIdx.x;
+  double t = 0.0;
+  for (int i = threadIdx.x; i < m.I[n]; i += 256) t += m.G[n][i + (long long)m.Ip[n] * i];
+  t = block_sum(t, red);
+  if (threadIdx.x == 0) sigma[n] = 1e-7 * t;
+}
+
+// Z_n = Omega_n (I_n x b, column-major, modes stacked) padded to Ip x bp with
+// zeros; Q_n = 0 (its padding stays zero for good).
+__global__ __launch_bounds__(256) void k_svd_load(SvdModes m, const double* __restrict__ omega) {
+  const int n = blockIdx.y;
+  const int I = m.I[n], Ip = m.Ip[n];
+  long long off = 0;
+  for (int k = 0; k < n; ++k) off += (long long)m.I[k] * m.b;
+  const long long total = (long long)Ip * m.bp;
+  for (long long e = blockIdx.x * 256LL + threadIdx.x; e < total; e += (long long)gridDim.x * 256) {
+    const int i = (int)(e % Ip), c = (int)(e / Ip);
+    m.Z[n][e] = (i < I && c < m.b) ? omega[off + i + (long long)I * c] : 0.0;
+    m.Q[n][e] = 0.0;
+  }
+}
+
+// Z_n = (G_n + sigma_n I) Q_n for every mode: blocks of 64 rows x 16 columns,
+// wave w owns rows 16w..16w+15; operands read from L2 (G_n, Q_n stay resident).
+__global__ __launch_bounds__(256) void k_gq(SvdModes m, const double* __restrict__ sigma) {
+  int n = 0;
+  while (n + 1 < m.N && (int)blockIdx.x >= m.blk0[n + 1]) ++n;
+  const int Ip = m.Ip[n], rt_count = Ip / 64;
+  const int local = blockIdx.x - m.blk0[n];
+  const int rt = local % rt_count, cb = local / rt_count;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const double* G = m.G[n];
+  const double* Q = m.Q[n];
+  const int row_a = rt * 64 + 16 * w + (lane & 15);
+  const int col = cb * 16 + (lane & 15);
+  const double* ap = G + row_a + (long long)(lane >> 4) * Ip;
+  const double* bp = Q + (lane >> 4) + (long long)col * Ip;
+  v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 8
+  for (int k = 0; k < Ip; k += 4)
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ap[(long long)k * Ip], bp[k], acc, 0, 0, 0);
+  const double sg = sigma[n];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const long long idx = (rt * 64 + 16 * w + (lane >> 4) + 4 * v) + (long long)col * Ip;
+    m.Z[n][idx] = acc[v] + sg * Q[idx];
+  }
+}
+
+// W[0..b)[0..b) (lower blocks of 16) = X^T Y over the first I rows of the
+// Ip x bp column-major X, Y, staged through LDS in chunks of 32 rows.
+// Waves take 16 x 16 blocks (bi, bj) round robin; `lower` limits them to bi >= bj.
+template <int BP>
+__device__ void gram_small(const double* X, const double* Y, int I, int Ip, bool lower, double (*W)[BP + 1],
+                           double (*Xc)[BP + 1], double (*Yc)[BP + 1]) {
+  constexpr int NB = BP / 16;
+  constexpr int NPAIR = NB * NB;
+  constexpr int NW = 8;
+  constexpr int MAXP = (NPAIR + NW - 1) / NW;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  v4d acc[MAXP];
+#pragma unroll
+  for (int p = 0; p < MAXP; ++p) acc[p] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int r0 = 0; r0 < I; r0 += 32) {
+    sync_block();
+    for (int e = threadIdx.x; e < 32 * BP; e += 512) {
+      const int kc = e & 31, c = e >> 5;
+      const long long idx = (r0 + kc) + (long long)c * Ip;  // r0 + kc < Ip (Ip is a multiple of 64)
+      Xc[kc][c] = X[idx];
+      if (Y != X) Yc[kc][c] = Y[idx];
+    }
+    sync_block();
+    const double (*Yv)[BP + 1] = (Y != X) ? Yc : Xc;
+#pragma unroll
+    for (int p = 0; p < MAXP; ++p) {
+      const int pr = w + NW * p;
+      if (pr >= NPAIR) break;
+      const int bi = pr / NB, bj = pr % NB;
+      if (lower && bi < bj) continue;
+#pragma unroll
+      for (int k = 0; k < 32; k += 4) {
+        const double a = Xc[k + (lane >> 4)][16 * bi + (lane & 15)];
+        const double bb = Yv[k + (lane >> 4)][16 * bj + (lane & 15)];
+        acc[p] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc[p], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < MAXP; ++p) {
+    const int pr = w + NW * p;
+    if (pr >= NPAIR) break;
+    const int bi = pr / NB, bj = pr % NB;
+    if (lower && bi < bj) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) W[16 * bi + (lane >> 4) + 4 * v][16 * bj + (lane & 15)] = acc[p][v];
+  }
+  sync_block();
+}
+
+// One workgroup (512 threads) per mode: Q_n = orth(Z_n) over the first b
+// columns by shifted Cholesky QR and two Cholesky QR passes.  Each pass forms
+// W = X^T X, factors W (+ s I in the first pass) = L L^T in LDS and replaces
+// every row x of X by the solution of L y^T = x^T.  A non-positive pivot sets
+// *bad and leaves Q_n as it is.
+template <int BP>
+__global__ __launch_bounds__(512) void k_orth(SvdModes m, int* bad) {
+  __shared__ double W[BP][BP + 1];
+  __shared__ double Xc[32][BP + 1];
+  __shared__ double Dinv[BP];
+  __shared__ int fail;
+  const int n = blockIdx.x;
+  const int I = m.I[n], Ip = m.Ip[n], b = m.b;
+  const double* Z = m.Z[n];
+  double* Q = m.Q[n];
+  if (threadIdx.x == 0) fail = 0;
+  for (int pass = 0; pass < 3; ++pass) {
+    const double* src = pass == 0 ? Z : Q;
+    gram_small<BP>(src, src, I, Ip, true, W, Xc, Xc);
+    if (pass == 0) {
+      double tr = 0.0;
+      for (int j = 0; j < b; ++j) tr += W[j][j];
+      sync_block();
+      const double s = 11.0 * ((double)I * b + (double)b * (b + 1)) * 0x1p-53 * tr;
+      if ((int)threadIdx.x < b) W[threadIdx.x][threadIdx.x] += s;
+      sync_block();
+    }
+    // unscaled right-looking Cholesky of the lower triangle: after step j,
+    // W[i][k] (k > j) holds the Schur complement, column j the unscaled column.
+    for (int j = 0; j < b; ++j) {
+      const double d = W[j][j];
+      if (!(d > 0.0) || !isfinite(d)) {
+        if (threadIdx.x == 0) fail = 1;
+        break;
+      }
+      const int mm = b - j - 1;
+      const double dinv = 1.0 / d;
+      for (int e = threadIdx.x; e < mm * mm; e += 512) {
+        const int i = j + 1 + e / mm, k = j + 1 + e % mm;
+        if (k <= i) W[i][k] -= W[i][j] * W[k][j] * dinv;
+      }
+      sync_block();
+    }
+    sync_block();
+    if (fail) break;
+    if ((int)threadIdx.x < b) Dinv[threadIdx.x] = 1.0 / sqrt(W[threadIdx.x][threadIdx.x]);
+    sync_block();
+    // L[c][k] = W[c][k] / sqrt(W[k][k]) for k < c
+    for (int e = threadIdx.x; e < b * b; e += 512) {
+      const int c = e / b, k = e % b;
+      if (k < c) W[c][k] *= Dinv[k];
+    }
+    sync_block();
+    for (int i = threadIdx.x; i < I; i += 512) {
+      // keeps the loads of L inside the loop (hoisted, they would take BP^2 / 2 registers)
+      __asm__ volatile("" ::: "memory");
+      double x[BP];
+#pragma unroll
+      for (int c = 0; c < BP; ++c) x[c] = c < b ? src[i + (long long)c * Ip] : 0.0;
+#pragma unroll
+      for (int c = 0; c < BP; ++c) {
+        if (c < b) {
+          double a = x[c];
+#pragma unroll
+          for (int k = 0; k < c; ++k) a -= W[c][k] * x[k];
+          x[c] = a * Dinv[c];
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < BP; ++c)
+        if (c < b) Q[i + (long long)c * Ip] = x[c];
+    }
+    sync_block_mem();
+  }
+  if (threadIdx.x == 0 && fail) atomicOr(bad, 1);
+}
+
+// One workgroup (512 threads) per mode: Rayleigh-Ritz on span(Q_n) with
+// Z_n = (G_n + sigma_n I) Q_n, Jacobi eigensolver, Ritz vectors of the R
+// largest Ritz values into A_n (I_n x R, leading dimension I_n) and the
+// singular values into sv[n R + r] (when sv != NULL).
+template <int BP>
+__global__ __launch_bounds__(512) void k_rayleigh_ritz(SvdModes m, const double* __restrict__ sigma, double* sv) {
+  __shared__ double H[BP][BP + 1];
+  __shared__ double V[BP][BP + 1];
+  __shared__ double Qc[32][BP + 1];
+  __shared__ double Zc[32][BP + 1];
+  __shared__ double rc[BP / 2], rs[BP / 2];
+  __shared__ int rp[BP / 2], rq[BP / 2];
+  __shared__ int rotated;
+  __shared__ int perm[BP];
+  __shared__ double lam[BP];
+  const int n = blockIdx.x;
+  const int I = m.I[n], Ip = m.Ip[n], b = m.b, R = m.R;
+  const double* Q = m.Q[n];
+  gram_small<BP>(Q, m.Z[n], I, Ip, false, H, Qc, Zc);
+  const double sg = sigma[n];
+  // symmetrise, remove the shift, V = identity
+  for (int e = threadIdx.x; e < b * b; e += 512) {
+    const int i = e / b, j = e % b;
+    if (i < j) {
+      const double h = 0.5 * (H[i][j] + H[j][i]);
+      H[i][j] = h;
+      H[j][i] = h;
+    } else if (i == j) {
+      H[i][i] -= sg;
+    }
+  }
+  sync_block();
+  for (int e = threadIdx.x; e < b * b; e += 512) V[e / b][e % b] = (e / b == e % b) ? 1.0 : 0.0;
+  sync_block();
+  const int bj = b + (b & 1), np = bj / 2;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    if (threadIdx.x == 0) rotated = 0;
+    sync_block();
+    for (int step = 0; step < bj - 1; ++step) {
+      if ((int)threadIdx.x < np) {
+        const int k = threadIdx.x;
+        // round-robin pairing: position 0 fixed, positions 1..bj-1 rotate
+        auto at = [&](int pos) { return pos == 0 ? 0 : 1 + (pos - 1 + step) % (bj - 1); };
+        int p = at(k), q = at(bj - 1 - k);
+        if (p > q) { const int t = p; p = q; q = t; }
+        double c = 1.0, s = 0.0;
+        bool act = false;
+        if (q < b) {
+          const double hpq = H[p][q], hpp = H[p][p], hqq = H[q][q];
+          if (fabs(hpq) > 1e-300 && fabs(hpq) > 1e-15 * sqrt(fabs(hpp * hqq))) {
+            const double th = (hqq - hpp) / (2.0 * hpq);
+            const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
+            c = 1.0 / sqrt(1.0 + t * t);
+            s = t * c;
+            act = true;
+          }
+        }
+        rc[k] = c;
+        rs[k] = s;
+        rp[k] = act ? p : -1;
+        rq[k] = q;
+        if (act) rotated = 1;
+      }
+      sync_block();
+      // rows p, q of H <- J^T H
+      for (int e = threadIdx.x; e < np * b; e += 512) {
+        const int k = e / b, j = e % b;
+        const int p = rp[k];
+        if (p < 0) continue;
+        const int q = rq[k];
+        const double c = rc[k], s = rs[k];
+        const double hp = H[p][j], hq = H[q][j];
+        H[p][j] = c * hp - s * hq;
+        H[q][j] = s * hp + c * hq;
+      }
+      sync_block();
+      // columns p, q of H <- H J and of V <- V J
+      for (int e = threadIdx.x; e < np * b; e += 512) {
+        const int k = e / b, i = e % b;
+        const int p = rp[k];
+        if (p < 0) continue;
+        const int q = rq[k];
+        const double c = rc[k], s = rs[k];
+        const double hp = H[i][p], hq = H[i][q];
+        H[i][p] = c * hp - s * hq;
+        H[i][q] = s * hp + c * hq;
+        const double vp = V[i][p], vq = V[i][q];
+        V[i][p] = c * vp - s * vq;
+        V[i][q] = s * vp + c * vq;
+      }
+      sync_block();
+    }
+    if (!rotated) break;
+    sync_block();
+  }
+  // order: decreasing Ritz value, lower index first on ties
+  if ((int)threadIdx.x < b) {
+    const int j = threadIdx.x;
+    const double lj = H[j][j];
+    int rank = 0;
+    for (int k = 0; k < b; ++k) {
+      const double lk = H[k][k];
+      rank += (lk > lj) || (lk == lj && k < j);
+    }
+    perm[rank] = j;
+    lam[rank] = lj;
+  }
+  sync_block();
+  double* A = m.A[n];
+  for (int i = threadIdx.x; i < I; i += 512) {
+    __asm__ volatile("" ::: "memory");
+    double q[BP];
+#pragma unroll
+    for (int k = 0; k < BP; ++k) q[k] = k < b ? Q[i + (long long)k * Ip] : 0.0;
+    for (int r = 0; r < R; ++r) {
+      const int j = perm[r];
+      double u = 0.0;
+#pragma unroll
+      for (int k = 0; k < BP; ++k)
+        if (k < b) u += q[k] * V[k][j];
+      A[i + (long long)I * r] = u;
+    }
+  }
+  sync_block_mem();
+  // sign of each column: largest |entry| positive (first index on ties)
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int r = w; r < R; r += 8) {
+    double best = -1.0, bval = 0.0;
+    int bi = 0x7fffffff;
+    for (int i = lane; i < I; i += 64) {
+      const double v = A[i + (long long)I * r];
+      if (fabs(v) > best) {
+        best = fabs(v);
+        bval = v;
+        bi = i;
+      }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ob = __shfl_xor(best, o, 64), ov = __shfl_xor(bval, o, 64);
+      const int oi = __shfl_xor(bi, o, 64);
+      if (ob > best || (ob == best && oi < bi)) {
+        best = ob;
+        bval = ov;
+        bi = oi;
+      }
+    }
+    if (bval < 0.0)
+      for (int i = lane; i < I; i += 64) A[i + (long long)I * r] = -A[i + (long long)I * r];
+  }
+  if (sv && (int)threadIdx.x < R) {
+    const double l = lam[threadIdx.x];
+    sv[n * R + threadIdx.x] = l > 0.0 ? sqrt(l) : 0.0;
+  }
+}
+
+template <int BP>
+hipError_t launch_orth_rr(const SvdModes& m, bool rr, const double* sigma, double* sv, int* bad, hipStream_t st) {
+  if (rr)
+    hipLaunchKernelGGL(k_rayleigh_ritz<BP>, dim3(m.N), dim3(512), 0, st, m, sigma, sv);
+  else
+    hipLaunchKernelGGL(k_orth<BP>, dim3(m.N), dim3(512), 0, st, m, bad);
+  return hipGetLastError();
+}
+
+hipError_t orth_or_rr(const SvdModes& m, bool rr, const double* sigma, double* sv, int* bad, hipStream_t st) {
+  switch (m.bp) {
+    case 16: return launch_orth_rr<16>(m, rr, sigma, sv, bad, st);
+    case 32: return launch_orth_rr<32>(m, rr, sigma, sv, bad, st);
+    case 48: return launch_orth_rr<48>(m, rr, sigma, sv, bad, st);
+    case 64: return launch_orth_rr<64>(m, rr, sigma, sv, bad, st);
+    case 80: return launch_orth_rr<80>(m, rr, sigma, sv, bad, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+GramPlan plan_gram(const Shape& s, int n) {
+  GramPlan g{};
+  g.P = 1;
+  g.Q = 1;
+  for (int k = 0; k < n; ++k) g.P *= s.I[k];
+  for (int k = n + 1; k < s.N; ++k) g.Q *= s.I[k];
+  g.I = s.I[n];
+  const int nt = (g.I + 63) / 64;
+  g.ntile = nt * (nt + 1) / 2;
+  g.nchunk = g.P == 1 ? (g.Q + GK - 1) / GK : g.Q * ((g.P + GK - 1) / GK);
+  long long S = (2048 + g.ntile - 1) / g.ntile;
+  if (S > g.nchunk) S = g.nchunk;
+  if (S < 1) S = 1;
+  g.cps = (g.nchunk + S - 1) / S;
+  g.S = (int)((g.nchunk + g.cps - 1) / g.cps);
+  return g;
+}
+
+size_t gram_part_doubles(const Shape& s) {
+  size_t mx = 0;
+  for (int n = 0; n < s.N; ++n) {
+    const GramPlan g = plan_gram(s, n);
+    const size_t d = (size_t)g.S * g.ntile * 4096;
+    if (d > mx) mx = d;
+  }
+  return mx;
+}
+
+hipError_t launch_mode_gram(const Shape& s, int n, const void* Y, YType yt, double* part, double* G, long long ld,
+                            int lim, hipStream_t st) {
+  const GramPlan g = plan_gram(s, n);
+  const long long blocks = (long long)g.ntile * g.S;
+  const unsigned grid = (unsigned)((blocks + 7) / 8 * 8);
+  switch (yt) {
+    case YType::F64:
+      hipLaunchKernelGGL(k_mode_gram<double>, dim3(grid), dim3(256), 0, st, (const double*)Y, g, part);
+      break;
+    case YType::F32:
+      hipLaunchKernelGGL(k_mode_gram<float>, dim3(grid), dim3(256), 0, st, (const float*)Y, g, part);
+      break;
+    case YType::BF16:
+      hipLaunchKernelGGL(k_mode_gram<__bf16>, dim3(grid), dim3(256), 0, st, (const __bf16*)Y, g, part);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_gram_reduce, dim3(g.ntile), dim3(256), 0, st, part, g.S, g.ntile, G, ld, lim);
+  return hipGetLastError();
+}
+
+hipError_t launch_svd_init(const Shape& s, const void* Y, YType yt, SvdModes m, const double* omega, int iters,
+                           double* part, double* sigma, double* sv, int* bad, hipStream_t st) {
+  hipError_t e;
+  for (int n = 0; n < s.N; ++n)
+    if ((e = launch_mode_gram(s, n, Y, yt, part, m.G[n], m.Ip[n], m.Ip[n], st)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_svd_shift, dim3(m.N), dim3(256), 0, st, m, sigma);
+  hipLaunchKernelGGL(k_svd_load, dim3(64, m.N), dim3(256), 0, st, m, omega);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = orth_or_rr(m, false, sigma, sv, bad, st)) != hipSuccess) return e;
+  for (int it = 0; it < iters; ++it) {
+    hipLaunchKernelGGL(k_gq, dim3(m.blk0[m.N]), dim3(256), 0, st, m, sigma);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = orth_or_rr(m, false, sigma, sv, bad, st)) != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_gq, dim3(m.blk0[m.N]), dim3(256), 0, st, m, sigma);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  return orth_or_rr(m, true, sigma, sv, bad, st);
+}
+
+}  // namespace dgn

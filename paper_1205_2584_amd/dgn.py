@@ -75,7 +75,7 @@ class dgn_result(ctypes.Structure):
 
 EXPORTS = ["dgn_opts_default", "dgn_create", "dgn_destroy", "dgn_last_error", "dgn_workspace_size",
            "dgn_mttkrp", "dgn_step", "dgn_step_explicit", "dgn_workspace_size_explicit", "cp_fit", "cp_als",
-           "dgn_last_phase_times", "cp_fit_batched",
+           "dgn_mode_gram", "cp_svd_init", "dgn_workspace_size_svd", "dgn_last_phase_times", "cp_fit_batched",
            "dgn_server_create", "dgn_server_submit", "dgn_server_poll", "dgn_server_wait_idle",
            "dgn_server_stats", "dgn_server_now", "dgn_server_destroy"]
 NUM_PHASES = 6
@@ -112,6 +112,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.dgn_workspace_size_explicit.argtypes = [ctypes.POINTER(dgn_tensor), i32, ctypes.POINTER(ctypes.c_size_t)]
     L.cp_als.argtypes = [vp, ctypes.POINTER(dgn_tensor), i32, ctypes.POINTER(vp), i32,
                          ctypes.POINTER(dgn_opts), ctypes.POINTER(dbl), vp]
+    L.dgn_mode_gram.argtypes = [vp, ctypes.POINTER(dgn_tensor), i32, vp, vp]
+    L.cp_svd_init.argtypes = [vp, ctypes.POINTER(dgn_tensor), i32, i32, vp, i32, ctypes.POINTER(vp), vp, vp]
+    L.dgn_workspace_size_svd.argtypes = [ctypes.POINTER(dgn_tensor), i32, i32, ctypes.POINTER(ctypes.c_size_t)]
     L.dgn_last_phase_times.argtypes = [vp, ctypes.POINTER(dbl), i32, ctypes.POINTER(i32)]
     L.cp_fit_batched.argtypes = [vp, i32, ctypes.POINTER(dgn_batch_fit), dbl, i32,
                                  ctypes.POINTER(dgn_opts), ctypes.POINTER(dgn_fit_info), vp]
@@ -125,6 +128,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.dgn_server_destroy.argtypes = [vp]
     for name in ("dgn_create", "dgn_destroy", "dgn_workspace_size", "dgn_mttkrp", "dgn_step", "cp_fit", "cp_als",
                  "dgn_step_explicit", "dgn_workspace_size_explicit",
+                 "dgn_mode_gram", "cp_svd_init", "dgn_workspace_size_svd",
                  "dgn_last_phase_times", "cp_fit_batched", "dgn_server_create", "dgn_server_submit",
                  "dgn_server_poll", "dgn_server_wait_idle", "dgn_server_stats", "dgn_server_destroy"):
         getattr(L, name).restype = ctypes.c_int
@@ -248,6 +252,31 @@ class Context:
                                   _stream()))
         return err2.value
 
+    def mode_gram(self, y, dims, n):
+        """Y_(n) Y_(n)^T as an (I_n, I_n) float64 device tensor (enqueued, not synchronised)."""
+        d = tensor_desc(y, dims)
+        G = None
+        if 0 <= int(n) < len(dims):
+            G = torch.empty((int(dims[n]), int(dims[n])), dtype=torch.float64, device=y.device)
+        self._check(self.L.dgn_mode_gram(self.h, ctypes.byref(d), int(n),
+                                         ctypes.c_void_p(G.data_ptr() if G is not None else 0), _stream()))
+        return G
+
+    def cp_svd_init(self, y, dims, R, block, omega, iters):
+        """Leading R left singular vectors of every unfolding; returns (factors, sv):
+        factors[n] of shape (R, I_n) (column-major I_n x R), sv of shape (N, R).
+        omega: float64 device tensor of sum_n I_n * block random start entries."""
+        d = tensor_desc(y, dims)
+        need = sum(int(I) for I in dims) * int(block)
+        if omega.dtype != torch.float64 or not omega.is_cuda or not omega.is_contiguous() or omega.numel() != need:
+            raise ValueError(f"omega must be a contiguous float64 device tensor of {need} entries")
+        A = [torch.empty((int(R), int(I)), dtype=torch.float64, device=y.device) for I in dims]
+        sv = torch.empty((len(dims), int(R)), dtype=torch.float64, device=y.device)
+        self._check(self.L.cp_svd_init(self.h, ctypes.byref(d), int(R), int(block),
+                                       ctypes.c_void_p(omega.data_ptr()), int(iters), _ptrs(A),
+                                       ctypes.c_void_p(sv.data_ptr()), _stream()))
+        return A, sv
+
     def cp_fit_batched(self, problems, tol, max_iters, options: dgn_opts | None = None):
         """problems: list of (y, dims, R, factors, mu0); factors are fitted in place.
         Returns one info dict per problem."""
@@ -337,6 +366,20 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def workspace_size_svd(dims, R, block, dtype=torch.float64) -> int:
+    d = dgn_tensor()
+    d.order = len(dims)
+    for k, v in enumerate(dims):
+        d.dims[k] = int(v)
+    d.dtype = _DTYPE[dtype]
+    d.data = 1
+    n = ctypes.c_size_t()
+    st = load().dgn_workspace_size_svd(ctypes.byref(d), int(R), int(block), ctypes.byref(n))
+    if st != 0:
+        raise DgnError(st, "dgn_workspace_size_svd failed")
+    return n.value
 
 
 def workspace_size_explicit(dims, R, dtype=torch.float64) -> int:
