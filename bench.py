@@ -225,6 +225,74 @@ def bench_als(dgn, torch, ctx, y, dims, R, p, dev, sweeps=5):
             "passes_per_sweep": len(dims), "eps_start": (e0 / ynorm2) ** 0.5, "eps_after": (ek / ynorm2) ** 0.5}
 
 
+def bench_svd_init(dgn, torch, y, dims, R, dev, block=48, iters=30, reps=3, sample=(200, 200, 200)):
+    """SVD initialisation (Section 4.5) of the workload's FP32 tensor: cp_svd_init
+    end to end, and its dominant kernel, the three FP64 mode Grams Y_(n) Y_(n)^T on
+    the matrix cores, against the FP64 MFMA peak.  Algorithmic flops of a Gram:
+    I_n (I_n + 1) K_n (the lower triangle, 2 flops per product, K_n = J / I_n).
+    The oracle (a library SVD of every unfolding) is timed on the CPU on a
+    `sample`-sized FP64 tensor, with the GPU timed on the same sample."""
+    import numpy as np
+    from cpgen import synth
+    J = 1
+    for I in dims:
+        J *= I
+    rng = np.random.default_rng(8)
+    omega = torch.from_numpy(synth.svd_start_block(rng, dims, block)).to(dev)
+    ctx = dgn.Context(0, dgn.workspace_size_svd(dims, R, block, y.dtype))
+    try:
+        ctx.cp_svd_init(y, dims, R, block, omega, iters)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            A, sv = ctx.cp_svd_init(y, dims, R, block, omega, iters)
+        torch.cuda.synchronize()
+        init_ms = (time.perf_counter() - t0) / reps * 1e3
+        # the three mode Grams alone, HIP events on the stream they run on
+        for n in range(len(dims)):
+            ctx.mode_gram(y, dims, n)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            for n in range(len(dims)):
+                ctx.mode_gram(y, dims, n)
+        e1.record()
+        torch.cuda.synchronize()
+        gram_ms = e0.elapsed_time(e1) / reps
+    finally:
+        ctx.close()
+    flops = sum(I * (I + 1) * (J // I) for I in dims)
+    tf = flops / (gram_ms * 1e-3) / 1e12
+    # the same init on the bounded sample, GPU and oracle
+    from oracle import cp
+    ys = synth.cp_tensor([rng.standard_normal((I, R)) for I in sample], 10.0 ** (-np.arange(R) / R))
+    ys, _ = synth.add_noise(rng, ys, 25.0)
+    yd = torch.from_numpy(ys).to(dev)
+    oms = torch.from_numpy(synth.svd_start_block(rng, sample, block)).to(dev)
+    c2 = dgn.Context(0, dgn.workspace_size_svd(sample, R, block))
+    try:
+        c2.cp_svd_init(yd, sample, R, block, oms, iters)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        c2.cp_svd_init(yd, sample, R, block, oms, iters)
+        torch.cuda.synchronize()
+        gpu_sample_ms = (time.perf_counter() - t0) * 1e3
+    finally:
+        c2.close()
+    Ys = cp.as_tensor(ys, sample)
+    t0 = time.perf_counter()
+    cp.svd_init(Ys, R)
+    cpu_sample_ms = (time.perf_counter() - t0) * 1e3
+    return {"block": block, "iters": iters, "ms_per_init": round(init_ms, 3),
+            "mode_gram_ms": round(gram_ms, 3),
+            "roofline_mode_gram": {"bound": "mfma", "achieved": round(tf, 2), "peak": PEAK_FP64_TFLOPS,
+                                   "unit": "TFLOP/s", "frac": round(tf / PEAK_FP64_TFLOPS, 4), "traffic": None,
+                                   "algorithmic_flops": flops},
+            "sample": "x".join(map(str, sample)) + " FP64",
+            "sample_gpu_ms": round(gpu_sample_ms, 3), "sample_oracle_ms": round(cpu_sample_ms, 1),
+            "oracle_threads": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count()))}
+
+
 def bench_dgn_vs_flm(dgn, torch, ranks=(5, 10, 20, 30, 40, 50, 60), reps=3, mu=10.0):
     """Time per step and workspace of the fast step (dgn_step) against the plain
     dGN step with J^T J formed explicitly (dgn_step_explicit) on 100 x 100 x 100
@@ -340,6 +408,7 @@ def main():
     ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--no-als", action="store_true")
     ap.add_argument("--no-dgn-sweep", action="store_true")
+    ap.add_argument("--no-svd", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run a plain copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
@@ -434,6 +503,8 @@ def main():
     }
     if not args.no_als:
         line["als"] = bench_als(dgn, torch, ctx, y32, dims, R, p, dev)
+    if not args.no_svd:
+        line["svd_init"] = bench_svd_init(dgn, torch, y32, dims, R, dev)
     ctx.close()
     del y32, ybf
     torch.cuda.empty_cache()

@@ -192,7 +192,7 @@ hipError_t launch_batched_final(BFit* fits, int nfits, hipStream_t st);
 // Y viewed for mode n as (P, I, Q): element (p, i, q) at p + P (i + I q).
 struct GramPlan {
   long long P, Q;
-  int I, ntile;            // mode size, lower 64 x 64 tiles of G_n
+  int I, ntile;            // mode size, lower 128 x 128 tiles of G_n
   long long nchunk, cps;   // summation chunks of 32, chunks per split
   int S;                   // splits of the summation (partial tiles per tile)
 };

@@ -3,7 +3,7 @@
 //
 // A^(n) is the R leading left singular vectors of the unfolding Y_(n), that
 // is the leading eigenvectors of the mode-n Gram matrix G_n = Y_(n) Y_(n)^T.
-//  1. G_n in FP64 on the matrix cores: 64 x 64 lower tiles, the summation over
+//  1. G_n in FP64 on the matrix cores: 128 x 128 lower tiles, the summation over
 //     the other modes split across workgroups (the splits of one tile set stay
 //     on one XCD so its L2 serves the shared row blocks), the partial tiles
 //     summed in a fixed order, so the result is deterministic.
@@ -29,8 +29,11 @@ namespace {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-constexpr int GK = 32;  // summation chunk of a Gram tile
-constexpr int GS = 80;  // LDS row stride of the [k][row] operand tiles
+constexpr int GT = 128;   // Gram tile edge
+constexpr int GK = 32;    // summation chunk of a Gram tile
+constexpr int GSK = 144;  // stride of the [k][row] LDS layout (rows contiguous)
+constexpr int GSR = 36;   // stride of the [row][k] LDS layout (k contiguous)
+constexpr int GOP = GK * GSK;  // doubles per staged operand (= GT * GSR)
 
 __device__ __forceinline__ void tri_index(long long id, int& ti, int& tj) {
   ti = (int)((sqrt(8.0 * id + 1.0) - 1.0) / 2.0);
@@ -47,111 +50,141 @@ __device__ __forceinline__ void sync_block_mem() {
   __syncthreads();
 }
 
-// acc[blk] += A(rows 16w..16w+15)^T-chunk products: acc[blk][v] gains
-// sum_k A[k][16w + lane/16 + 4v] * B[k][16 blk + lane%16] over the GK rows of k.
-__device__ __forceinline__ void mma_chunk(const double (*A)[GS], const double (*B)[GS], v4d acc[4]) {
+// One chunk of GK summation indices on a 128 x 128 tile: wave w owns the
+// 64 x 64 quadrant (rows 64 (w / 2), columns 64 (w % 2)) as 4 x 4 blocks of
+// v_mfma_f64_16x16x4f64 (lane l: A[l % 16][l / 16], B[l / 16][l % 16], result
+// rows l / 16 + 4v, column l % 16).  KR: operands stored [k][row] (stride GSK),
+// else [row][k] (stride GSR).  Both strides keep the 64 lanes of an operand read
+// on distinct bank pairs within its two LDS cycles.
+template <bool KR>
+__device__ __forceinline__ void mma_chunk128(const double* Ti, const double* Tj, v4d acc[4][4]) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int ra = 16 * w + (lane & 15), kk = lane >> 4;
-#pragma unroll
+  const int rw = 64 * (w >> 1), cw = 64 * (w & 1);
+#pragma unroll 2
   for (int k = 0; k < GK; k += 4) {
-    const double a = A[k + kk][ra];
+    const int kk = k + (lane >> 4);
+    double a[4], b[4];
 #pragma unroll
-    for (int blk = 0; blk < 4; ++blk)
-      acc[blk] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, B[k + kk][16 * blk + (lane & 15)], acc[blk], 0, 0, 0);
+    for (int q = 0; q < 4; ++q) {
+      const int row = rw + 16 * q + (lane & 15), col = cw + 16 * q + (lane & 15);
+      a[q] = KR ? Ti[kk * GSK + row] : Ti[row * GSR + kk];
+      b[q] = KR ? Tj[kk * GSK + col] : Tj[col * GSR + kk];
+    }
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb)
+        acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rb], b[cb], acc[rb][cb], 0, 0, 0);
   }
 }
 
 // Partial Gram tiles.  Logical block L = tile + ntile * split; the hardware
 // block b runs L = (b % 8) * (gridDim.x / 8) + b / 8, so the consecutive
 // logical blocks that share a split (and its row blocks of Y) sit on one XCD.
-// part[(split * ntile + tile) * 4096 + c + 64 r] = sum over the split's chunks
-// of Y(., 64 ti + r, .) Y(., 64 tj + c, .).
-template <typename T>
-__global__ __launch_bounds__(256) void k_mode_gram(const T* __restrict__ Y, GramPlan g, double* __restrict__ part) {
-  const long long per_xcd = gridDim.x / 8;
-  const long long L = (long long)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
-  if (L >= (long long)g.ntile * g.S) return;
-  const int tile = (int)(L % g.ntile);
-  const long long split = L / g.ntile;
+// part[(split * ntile + tile) * GT^2 + c + GT r] = sum over the split's chunks
+// of Y(., GT ti + r, .) Y(., GT tj + c, .).  Diagonal tiles stage one operand.
+template <typename T, bool KR>
+__device__ __forceinline__ void gram_tile(const T* __restrict__ Y, const GramPlan& g, double* __restrict__ part,
+                                          int tile, long long split, double* lds) {
   int ti, tj;
   tri_index(tile, ti, tj);
-  __shared__ double Ti[GK][GS];
-  __shared__ double Tj[GK][GS];
+  const bool diag = ti == tj;
+  double* Ti = lds;
+  double* Tj = diag ? lds : lds + GOP;
   const long long c_begin = split * g.cps;
   const long long c_end = c_begin + g.cps < g.nchunk ? c_begin + g.cps : g.nchunk;
   const long long cpq = (g.P + GK - 1) / GK;  // chunks per q when P > 1
-  constexpr int NS = GK * 64 / 256;
-  double vi[NS], vj[NS];
-  const bool rows_contig = g.P == 1;
+  constexpr int NS = GK * GT / 256;
+  T vi[NS], vj[NS];  // widened to FP64 when staged
+  // element s of a thread: KR: row r0, k index k0 + 2s; else: k index kc0,
+  // row r0 + 8s (256 threads cover 2 k rows x 128 rows, or 32 k x 8 rows)
+  const int r0 = KR ? (threadIdx.x & (GT - 1)) : (threadIdx.x >> 5);
+  const int k0 = KR ? (threadIdx.x >> 7) : (threadIdx.x & (GK - 1));
   auto load = [&](long long c) {
-    if (rows_contig) {  // mode 1: the rows of a chunk are contiguous
+    if (KR) {  // P == 1: the rows of a chunk are contiguous
+      const long long q0 = c * GK + k0;
+      const int i = ti * GT + r0, j = tj * GT + r0;
+      const T* yi = Y + i + (long long)g.I * q0;
+      const T* yj = Y + j + (long long)g.I * q0;
+      const long long step = 2LL * g.I;
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
-        const int e = threadIdx.x + 256 * s, r = e & 63, kc = e >> 6;
-        const long long q = c * GK + kc;
-        const int i = ti * 64 + r, j = tj * 64 + r;
-        vi[s] = (q < g.Q && i < g.I) ? to_f64(Y[i + (long long)g.I * q]) : 0.0;
-        vj[s] = (q < g.Q && j < g.I) ? to_f64(Y[j + (long long)g.I * q]) : 0.0;
+        const bool okq = q0 + 2 * s < g.Q;
+        vi[s] = (okq && i < g.I) ? yi[s * step] : T(0);
+        if (!diag) vj[s] = (okq && j < g.I) ? yj[s * step] : T(0);
       }
     } else {  // the chunk runs along p, contiguous for each row
       const long long q = c / cpq;
       const long long p0 = (c - q * cpq) * GK;
+      const bool okp = p0 + k0 < g.P;
+      const int i = ti * GT + r0, j = tj * GT + r0;
+      const T* yi = Y + (p0 + k0 + g.P * ((long long)g.I * q + i));
+      const T* yj = Y + (p0 + k0 + g.P * ((long long)g.I * q + j));
+      const long long step = 8LL * g.P;
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
-        const int e = threadIdx.x + 256 * s, kc = e & (GK - 1), r = e / GK;
-        const long long p = p0 + kc;
-        const int i = ti * 64 + r, j = tj * 64 + r;
-        vi[s] = (p < g.P && i < g.I) ? to_f64(Y[p + g.P * (i + (long long)g.I * q)]) : 0.0;
-        vj[s] = (p < g.P && j < g.I) ? to_f64(Y[p + g.P * (j + (long long)g.I * q)]) : 0.0;
+        vi[s] = (okp && i + 8 * s < g.I) ? yi[s * step] : T(0);
+        if (!diag) vj[s] = (okp && j + 8 * s < g.I) ? yj[s * step] : T(0);
       }
     }
   };
-  v4d acc[4];
+  v4d acc[4][4];
 #pragma unroll
-  for (int b = 0; b < 4; ++b) acc[b] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
   if (c_begin < c_end) load(c_begin);
   for (long long c = c_begin; c < c_end; ++c) {
     sync_block();
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-      const int e = threadIdx.x + 256 * s;
-      const int r = rows_contig ? (e & 63) : e / GK;
-      const int kc = rows_contig ? (e >> 6) : (e & (GK - 1));
-      Ti[kc][r] = vi[s];
-      Tj[kc][r] = vj[s];
+      const int idx = KR ? (k0 + 2 * s) * GSK + r0 : (r0 + 8 * s) * GSR + k0;
+      Ti[idx] = to_f64(vi[s]);
+      if (!diag) Tj[idx] = to_f64(vj[s]);
     }
     sync_block();
     if (c + 1 < c_end) load(c + 1);
-    mma_chunk(Ti, Tj, acc);
+    mma_chunk128<KR>(Ti, Tj, acc);
   }
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  double* out = part + (split * g.ntile + tile) * 4096;
+  const int rw = 64 * (w >> 1), cw = 64 * (w & 1);
+  double* out = part + (split * g.ntile + tile) * (GT * GT);
 #pragma unroll
-  for (int blk = 0; blk < 4; ++blk)
+  for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int r = 16 * w + (lane >> 4) + 4 * v, c = 16 * blk + (lane & 15);
-      out[c + 64 * r] = acc[blk][v];
-    }
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = rw + 16 * rb + (lane >> 4) + 4 * v, c = cw + 16 * cb + (lane & 15);
+        out[c + GT * r] = acc[rb][cb][v];
+      }
+}
+
+template <typename T, bool KR>
+__global__ __launch_bounds__(256, 2) void k_mode_gram(const T* __restrict__ Y, GramPlan g, double* __restrict__ part) {
+  __shared__ double lds[2 * GOP];
+  const long long per_xcd = gridDim.x / 8;
+  const long long L = (long long)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  if (L >= (long long)g.ntile * g.S) return;
+  gram_tile<T, KR>(Y, g, part, (int)(L % g.ntile), L / g.ntile, lds);
 }
 
 // G[gr + ld gc] = G[gc + ld gr] = sum over splits (in order) of the partial
-// tiles, for gr >= gc, gr < lim.  One block per lower tile.
+// tiles, for gr >= gc, gr < lim.  GT^2 / 256 blocks per lower tile, one
+// element per thread.
 __global__ __launch_bounds__(256) void k_gram_reduce(const double* __restrict__ part, int S, int ntile,
                                                      double* __restrict__ G, long long ld, int lim) {
-  const int tile = blockIdx.x;
+  constexpr int per_tile = GT * GT / 256;
+  const int tile = blockIdx.x / per_tile;
+  const int e = (blockIdx.x % per_tile) * 256 + threadIdx.x;
   int ti, tj;
   tri_index(tile, ti, tj);
-  for (int s = 0; s < 16; ++s) {
-    const int e = threadIdx.x + 256 * s, r = e >> 6, c = e & 63;
-    double v = 0.0;
-    for (int sp = 0; sp < S; ++sp) v += part[((long long)sp * ntile + tile) * 4096 + e];
-    const int gr = ti * 64 + r, gc = tj * 64 + c;
-    if (gr >= gc && gr < lim) {
-      G[gr + ld * gc] = v;
-      G[gc + ld * gr] = v;
-    }
-  }
+  const int gr = ti * GT + e / GT, gc = tj * GT + e % GT;
+  if (gr < gc || gr >= lim) return;
+  double v = 0.0;
+  for (int sp = 0; sp < S; ++sp) v += part[((long long)sp * ntile + tile) * (GT * GT) + e];
+  G[gr + ld * gc] = v;
+  G[gc + ld * gr] = v;
 }
 
 // sigma[n] = 1e-7 * trace(G_n); one block per mode.
@@ -518,10 +551,11 @@ GramPlan plan_gram(const Shape& s, int n) {
   for (int k = 0; k < n; ++k) g.P *= s.I[k];
   for (int k = n + 1; k < s.N; ++k) g.Q *= s.I[k];
   g.I = s.I[n];
-  const int nt = (g.I + 63) / 64;
+  const int nt = (g.I + GT - 1) / GT;
   g.ntile = nt * (nt + 1) / 2;
   g.nchunk = g.P == 1 ? (g.Q + GK - 1) / GK : g.Q * ((g.P + GK - 1) / GK);
-  long long S = (2048 + g.ntile - 1) / g.ntile;
+  // at most 512 workgroups, one round at two per CU, when the summation allows
+  long long S = 512 / g.ntile;
   if (S > g.nchunk) S = g.nchunk;
   if (S < 1) S = 1;
   g.cps = (g.nchunk + S - 1) / S;
@@ -533,7 +567,7 @@ size_t gram_part_doubles(const Shape& s) {
   size_t mx = 0;
   for (int n = 0; n < s.N; ++n) {
     const GramPlan g = plan_gram(s, n);
-    const size_t d = (size_t)g.S * g.ntile * 4096;
+    const size_t d = (size_t)g.S * g.ntile * GT * GT;
     if (d > mx) mx = d;
   }
   return mx;
@@ -544,22 +578,27 @@ hipError_t launch_mode_gram(const Shape& s, int n, const void* Y, YType yt, doub
   const GramPlan g = plan_gram(s, n);
   const long long blocks = (long long)g.ntile * g.S;
   const unsigned grid = (unsigned)((blocks + 7) / 8 * 8);
+  const bool kr = g.P == 1;  // mode 1: rows of a chunk contiguous in memory
   switch (yt) {
     case YType::F64:
-      hipLaunchKernelGGL(k_mode_gram<double>, dim3(grid), dim3(256), 0, st, (const double*)Y, g, part);
+      if (kr) hipLaunchKernelGGL((k_mode_gram<double, true>), dim3(grid), dim3(256), 0, st, (const double*)Y, g, part);
+      else hipLaunchKernelGGL((k_mode_gram<double, false>), dim3(grid), dim3(256), 0, st, (const double*)Y, g, part);
       break;
     case YType::F32:
-      hipLaunchKernelGGL(k_mode_gram<float>, dim3(grid), dim3(256), 0, st, (const float*)Y, g, part);
+      if (kr) hipLaunchKernelGGL((k_mode_gram<float, true>), dim3(grid), dim3(256), 0, st, (const float*)Y, g, part);
+      else hipLaunchKernelGGL((k_mode_gram<float, false>), dim3(grid), dim3(256), 0, st, (const float*)Y, g, part);
       break;
     case YType::BF16:
-      hipLaunchKernelGGL(k_mode_gram<__bf16>, dim3(grid), dim3(256), 0, st, (const __bf16*)Y, g, part);
+      if (kr) hipLaunchKernelGGL((k_mode_gram<__bf16, true>), dim3(grid), dim3(256), 0, st, (const __bf16*)Y, g, part);
+      else hipLaunchKernelGGL((k_mode_gram<__bf16, false>), dim3(grid), dim3(256), 0, st, (const __bf16*)Y, g, part);
       break;
     default:
       return hipErrorInvalidValue;
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_gram_reduce, dim3(g.ntile), dim3(256), 0, st, part, g.S, g.ntile, G, ld, lim);
+  hipLaunchKernelGGL(k_gram_reduce, dim3(g.ntile * (GT * GT / 256)), dim3(256), 0, st, part, g.S, g.ntile, G, ld,
+                     lim);
   return hipGetLastError();
 }
 
