@@ -240,29 +240,45 @@ __global__ __launch_bounds__(256) void k_gq(SvdModes m, const double* __restrict
 }
 
 // W[0..b)[0..b) (lower blocks of 16) = X^T Y over the first I rows of the
-// Ip x bp column-major X, Y, staged through LDS in chunks of 32 rows.
-// Waves take 16 x 16 blocks (bi, bj) round robin; `lower` limits them to bi >= bj.
-template <int BP>
+// Ip x bp column-major X, Y, staged through LDS in chunks of CH rows (the next
+// chunk in flight in registers while the current one runs on MFMA).  Waves
+// take 16 x 16 blocks (bi, bj) round robin; `lower` limits them to bi >= bj.
+template <int BP, int CH>
 __device__ void gram_small(const double* X, const double* Y, int I, int Ip, bool lower, double (*W)[BP + 1],
                            double (*Xc)[BP + 1], double (*Yc)[BP + 1]) {
   constexpr int NB = BP / 16;
   constexpr int NPAIR = NB * NB;
   constexpr int NW = 8;
   constexpr int MAXP = (NPAIR + NW - 1) / NW;
+  constexpr int NE = CH * BP / 512;  // staged elements per thread
+  static_assert(CH * BP % 512 == 0 && 64 % CH == 0, "chunk shape");
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const bool two = Y != X;
+  // element s of a thread: row kc of the chunk, column c0 + (512 / CH) s
+  const int kc = threadIdx.x % CH, c0 = threadIdx.x / CH;
+  double px[NE], py[NE];
+  auto load = [&](int r0) {  // r0 + CH <= Ip: r0 < I <= Ip, both multiples of CH | 64 | Ip
+#pragma unroll
+    for (int s = 0; s < NE; ++s) {
+      const long long idx = (r0 + kc) + (long long)(c0 + (512 / CH) * s) * Ip;
+      px[s] = X[idx];
+      if (two) py[s] = Y[idx];
+    }
+  };
   v4d acc[MAXP];
 #pragma unroll
   for (int p = 0; p < MAXP; ++p) acc[p] = v4d{0.0, 0.0, 0.0, 0.0};
-  for (int r0 = 0; r0 < I; r0 += 32) {
+  if (I > 0) load(0);
+  for (int r0 = 0; r0 < I; r0 += CH) {
     sync_block();
-    for (int e = threadIdx.x; e < 32 * BP; e += 512) {
-      const int kc = e & 31, c = e >> 5;
-      const long long idx = (r0 + kc) + (long long)c * Ip;  // r0 + kc < Ip (Ip is a multiple of 64)
-      Xc[kc][c] = X[idx];
-      if (Y != X) Yc[kc][c] = Y[idx];
+#pragma unroll
+    for (int s = 0; s < NE; ++s) {
+      Xc[kc][c0 + (512 / CH) * s] = px[s];
+      if (two) Yc[kc][c0 + (512 / CH) * s] = py[s];
     }
     sync_block();
-    const double (*Yv)[BP + 1] = (Y != X) ? Yc : Xc;
+    if (r0 + CH < I) load(r0 + CH);
+    const double (*Yv)[BP + 1] = two ? Yc : Xc;
 #pragma unroll
     for (int p = 0; p < MAXP; ++p) {
       const int pr = w + NW * p;
@@ -270,7 +286,7 @@ __device__ void gram_small(const double* X, const double* Y, int I, int Ip, bool
       const int bi = pr / NB, bj = pr % NB;
       if (lower && bi < bj) continue;
 #pragma unroll
-      for (int k = 0; k < 32; k += 4) {
+      for (int k = 0; k < CH; k += 4) {
         const double a = Xc[k + (lane >> 4)][16 * bi + (lane & 15)];
         const double bb = Yv[k + (lane >> 4)][16 * bj + (lane & 15)];
         acc[p] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc[p], 0, 0, 0);
@@ -297,7 +313,7 @@ __device__ void gram_small(const double* X, const double* Y, int I, int Ip, bool
 template <int BP>
 __global__ __launch_bounds__(512) void k_orth(SvdModes m, int* bad) {
   __shared__ double W[BP][BP + 1];
-  __shared__ double Xc[32][BP + 1];
+  __shared__ double Xc[64][BP + 1];
   __shared__ double Dinv[BP];
   __shared__ int fail;
   const int n = blockIdx.x;
@@ -307,7 +323,7 @@ __global__ __launch_bounds__(512) void k_orth(SvdModes m, int* bad) {
   if (threadIdx.x == 0) fail = 0;
   for (int pass = 0; pass < 3; ++pass) {
     const double* src = pass == 0 ? Z : Q;
-    gram_small<BP>(src, src, I, Ip, true, W, Xc, Xc);
+    gram_small<BP, 64>(src, src, I, Ip, true, W, Xc, Xc);
     if (pass == 0) {
       double tr = 0.0;
       for (int j = 0; j < b; ++j) tr += W[j][j];
@@ -324,42 +340,37 @@ __global__ __launch_bounds__(512) void k_orth(SvdModes m, int* bad) {
         if (threadIdx.x == 0) fail = 1;
         break;
       }
-      const int mm = b - j - 1;
       const double dinv = 1.0 / d;
-      for (int e = threadIdx.x; e < mm * mm; e += 512) {
-        const int i = j + 1 + e / mm, k = j + 1 + e % mm;
-        if (k <= i) W[i][k] -= W[i][j] * W[k][j] * dinv;
-      }
+      for (int i = j + 1 + (int)(threadIdx.x >> 4); i < b; i += 32)
+        for (int k = j + 1 + (int)(threadIdx.x & 15); k <= i; k += 16) W[i][k] -= W[i][j] * W[k][j] * dinv;
       sync_block();
     }
     sync_block();
     if (fail) break;
-    if ((int)threadIdx.x < b) Dinv[threadIdx.x] = 1.0 / sqrt(W[threadIdx.x][threadIdx.x]);
+    // Dinv = 1 / diag(L), zero on the padding columns [b, BP), whose rows of W
+    // are zero (zero columns of X): the substitution below then leaves them zero
+    if ((int)threadIdx.x < BP) Dinv[threadIdx.x] = (int)threadIdx.x < b ? 1.0 / sqrt(W[threadIdx.x][threadIdx.x]) : 0.0;
     sync_block();
     // L[c][k] = W[c][k] / sqrt(W[k][k]) for k < c
-    for (int e = threadIdx.x; e < b * b; e += 512) {
-      const int c = e / b, k = e % b;
-      if (k < c) W[c][k] *= Dinv[k];
-    }
+    for (int c = 1 + (int)(threadIdx.x >> 4); c < b; c += 32)
+      for (int k = threadIdx.x & 15; k < c; k += 16) W[c][k] *= Dinv[k];
     sync_block();
     for (int i = threadIdx.x; i < I; i += 512) {
       // keeps the loads of L inside the loop (hoisted, they would take BP^2 / 2 registers)
       __asm__ volatile("" ::: "memory");
+      // all BP columns, unguarded: padding columns are zero in and out
       double x[BP];
 #pragma unroll
-      for (int c = 0; c < BP; ++c) x[c] = c < b ? src[i + (long long)c * Ip] : 0.0;
+      for (int c = 0; c < BP; ++c) x[c] = src[i + (long long)c * Ip];
 #pragma unroll
       for (int c = 0; c < BP; ++c) {
-        if (c < b) {
-          double a = x[c];
+        double a = x[c];
 #pragma unroll
-          for (int k = 0; k < c; ++k) a -= W[c][k] * x[k];
-          x[c] = a * Dinv[c];
-        }
+        for (int k = 0; k < c; ++k) a -= W[c][k] * x[k];
+        x[c] = a * Dinv[c];
       }
 #pragma unroll
-      for (int c = 0; c < BP; ++c)
-        if (c < b) Q[i + (long long)c * Ip] = x[c];
+      for (int c = 0; c < BP; ++c) Q[i + (long long)c * Ip] = x[c];
     }
     sync_block_mem();
   }
@@ -384,7 +395,7 @@ __global__ __launch_bounds__(512) void k_rayleigh_ritz(SvdModes m, const double*
   const int n = blockIdx.x;
   const int I = m.I[n], Ip = m.Ip[n], b = m.b, R = m.R;
   const double* Q = m.Q[n];
-  gram_small<BP>(Q, m.Z[n], I, Ip, false, H, Qc, Zc);
+  gram_small<BP, 32>(Q, m.Z[n], I, Ip, false, H, Qc, Zc);
   const double sg = sigma[n];
   // symmetrise, remove the shift, V = identity
   for (int e = threadIdx.x; e < b * b; e += 512) {
@@ -398,7 +409,8 @@ __global__ __launch_bounds__(512) void k_rayleigh_ritz(SvdModes m, const double*
     }
   }
   sync_block();
-  for (int e = threadIdx.x; e < b * b; e += 512) V[e / b][e % b] = (e / b == e % b) ? 1.0 : 0.0;
+  // V = identity on [0, b), zero elsewhere (the padding rows stay zero)
+  for (int e = threadIdx.x; e < BP * BP; e += 512) V[e / BP][e % BP] = (e / BP == e % BP && e / BP < b) ? 1.0 : 0.0;
   sync_block();
   const int bj = b + (b & 1), np = bj / 2;
   for (int sweep = 0; sweep < 60; ++sweep) {
@@ -477,15 +489,14 @@ __global__ __launch_bounds__(512) void k_rayleigh_ritz(SvdModes m, const double*
   double* A = m.A[n];
   for (int i = threadIdx.x; i < I; i += 512) {
     __asm__ volatile("" ::: "memory");
-    double q[BP];
+    double q[BP];  // padding columns of Q are zero, as are the padding rows of V
 #pragma unroll
-    for (int k = 0; k < BP; ++k) q[k] = k < b ? Q[i + (long long)k * Ip] : 0.0;
+    for (int k = 0; k < BP; ++k) q[k] = Q[i + (long long)k * Ip];
     for (int r = 0; r < R; ++r) {
       const int j = perm[r];
       double u = 0.0;
 #pragma unroll
-      for (int k = 0; k < BP; ++k)
-        if (k < b) u += q[k] * V[k][j];
+      for (int k = 0; k < BP; ++k) u += q[k] * V[k][j];
       A[i + (long long)I * r] = u;
     }
   }
