@@ -118,7 +118,20 @@ typedef struct dgn_opts {
   int32_t als_sweeps;   /* cp_fit and the server: ALS sweeps (as cp_als) on the starting factors
                            before the first trial; default 0.  cp_fit_batched rejects a nonzero
                            value with DGN_EINVAL */
+  /* dgn_step and cp_fit, real tensors with N <= 4 and R <= 32: DGN_SOLVER_AUTO
+   * first solves the NR^2 system by conjugate gradients on its structured SPD
+   * form (Section 4.3: Kronecker and permuted-diagonal products, the matrix is
+   * never formed) and runs the direct tiled Cholesky only when CG has not
+   * reached ||r|| <= cg_tol ||z|| within cg_max_iters iterations; inside cp_fit
+   * the first such failure switches CG off for the rest of the fit.  The step
+   * then differs from the direct one by the CG tolerance (amplified by the
+   * condition number of the system).  Default DGN_SOLVER_DIRECT. */
+  int32_t solver;
+  int32_t cg_max_iters; /* default 200 */
+  double cg_tol;        /* default 1e-10 */
 } dgn_opts;
+
+typedef enum dgn_solver { DGN_SOLVER_DIRECT = 0, DGN_SOLVER_AUTO = 1 } dgn_solver;
 
 /* Result of one trial step (dgn_step). */
 typedef struct dgn_step_info {
@@ -129,6 +142,7 @@ typedef struct dgn_step_info {
   double gnorm;     /* ||g||, g = J^H vec(Y - Y_hat) */
   double mnorm;     /* ||[M_n]||, all-mode MTTKRP norm (plain form) or ||[M_n - A_n Gamma_n]|| is g */
   double danorm;    /* ||da|| */
+  int32_t cg_iters; /* DGN_SOLVER_AUTO: CG iterations of a converged CG solve, -1 when the direct solve ran */
 } dgn_step_info;
 
 /* Result of a fit (cp_fit). */
@@ -141,6 +155,8 @@ typedef struct dgn_fit_info {
   double err2;          /* final ||Y - Y_hat||^2 */
   double mu;            /* final damping */
   double mu0;           /* initial damping actually used */
+  int32_t cg_trials;    /* DGN_SOLVER_AUTO: trials whose NR^2 system CG solved (else 0) */
+  int32_t cg_iters;     /* their CG iterations, summed */
 } dgn_fit_info;
 
 typedef struct dgn_ctx dgn_ctx;

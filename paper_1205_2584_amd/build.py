@@ -14,7 +14,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libdgn.so")
 
 SOURCES = ["tensor_pass.hip", "small.hip", "chol.hip", "fit.hip", "complex.hip", "batched.hip", "api.hip", "serve.hip",
-           "explicit.hip", "svd.hip"]
+           "explicit.hip", "svd.hip", "cg.hip"]
 ARCH = os.environ.get("DGN_OFFLOAD_ARCH", "gfx950")
 FLAGS = [
     "-O3", f"--offload-arch={ARCH}", "-std=c++17", "-fPIC",

@@ -73,7 +73,11 @@ struct Work {
   SysPlan ep;      // explicit-Hessian system (dgn_step_explicit only)
   SysBuffers ey;
   FitState* state;
-  int* flags;      // [0] singular (step), [1..] spare
+  int* flags;      // [0] singular (step), [8..12] CG solve counters (launch_cg), others spare
+  int solver = 0;  // dgn_solver
+  int cg_max = 0;
+  double cg_tol = 0.0;
+  bool cg_sticky = false;
   double* scr;     // [0..1023] norm partials, [1024] e2, [1025] e2c, [1026..1029] err2 / ynorm2
 };
 
@@ -296,9 +300,16 @@ hipError_t enqueue_step(Work& w, bool resid, double mu_host, FitState* state, in
   if ((e = launch_wz(s, w.sb, stop, st)) != hipSuccess) return e;
   if ((e = launch_tnm(s, w.sb, stop, st)) != hipSuccess) return e;
   if ((e = mark(ev, 1, st)) != hipSuccess) return e;
-  if ((e = launch_sys_assemble(s, w.sp, w.sb, w.sy, stop, st)) != hipSuccess) return e;
+  // DGN_SOLVER_AUTO: CG first; the direct assembly and solve then skip
+  // themselves (flags[8] set) when CG converged or the fit has stopped
+  const int* solve_stop = stop;
+  if (w.solver == DGN_SOLVER_AUTO && cg_supported(s)) {
+    if ((e = launch_cg(s, w.sb, w.cg_tol, w.cg_max, w.cg_sticky, w.flags + 8, stop, st)) != hipSuccess) return e;
+    solve_stop = w.flags + 8;
+  }
+  if ((e = launch_sys_assemble(s, w.sp, w.sb, w.sy, solve_stop, st)) != hipSuccess) return e;
   if ((e = mark(ev, 2, st)) != hipSuccess) return e;
-  if ((e = launch_sys_factor_solve(s, w.sp, w.sb, w.sy, singular, stop, st)) != hipSuccess) return e;
+  if ((e = launch_sys_factor_solve(s, w.sp, w.sb, w.sy, singular, solve_stop, st)) != hipSuccess) return e;
   if ((e = mark(ev, 3, st)) != hipSuccess) return e;
   if ((e = launch_u(s, w.sb, stop, st)) != hipSuccess) return e;
   if ((e = launch_fq(s, w.sb, stop, st)) != hipSuccess) return e;
@@ -369,6 +380,9 @@ void dgn_opts_default(dgn_opts* o) {
   o->poll_every = 8;
   o->timing = 0;
   o->graph = 1;
+  o->solver = DGN_SOLVER_DIRECT;
+  o->cg_max_iters = 200;
+  o->cg_tol = 1e-10;
 }
 
 dgn_status dgn_create(dgn_ctx** out, int32_t device, size_t ws_budget_bytes) {
@@ -465,11 +479,18 @@ dgn_status dgn_step(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, const void* co
   dgn_opts o;
   dgn_opts_default(&o);
   if (opts) o = *opts;
+  if (o.solver != DGN_SOLVER_DIRECT && o.solver != DGN_SOLVER_AUTO) return set_err(ctx, DGN_EINVAL, "bad solver option");
+  if (o.solver == DGN_SOLVER_AUTO && (o.cg_max_iters < 0 || !(o.cg_tol > 0.0)))
+    return set_err(ctx, DGN_EINVAL, "need cg_max_iters >= 0 and cg_tol > 0");
   Work w{};
   dgn_status rc = prepare(ctx, Y, R, true, w);
   if (rc != DGN_OK) return rc;
   for (int n = 0; n < w.s.N; ++n)
     if (!A_in[n] || !A_out[n]) return set_err(ctx, DGN_EINVAL, "NULL factor pointer");
+  w.solver = o.solver;
+  w.cg_max = o.cg_max_iters;
+  w.cg_tol = o.cg_tol;
+  w.cg_sticky = false;
   hipStream_t st = (hipStream_t)stream;
   HIPCHK(hipSetDevice(ctx->device), "hipSetDevice");
   const bool resid = (w.ymaster == YType::F64) || w.cs == 2 || o.resid_switch < 0;
@@ -490,12 +511,14 @@ dgn_status dgn_step(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, const void* co
   HIPCHK(launch_err2(w.s, w.Ac, w.Mc, w.sb.Cc, resid, e2b, ynp, out + 1, st), "err2");
   HIPCHK(copy_factors_out(w, w.Ac, A_out, st), "copy out");
   double host[2] = {0, 0}, sc[4] = {0, 0, 0, 0};
-  int flags[1] = {0};
+  int flags[16] = {0};
   HIPCHK(hipMemcpyAsync(host, out, sizeof host, hipMemcpyDeviceToHost, st), "copy");
   HIPCHK(hipMemcpyAsync(sc, w.sb.scal, sizeof sc, hipMemcpyDeviceToHost, st), "copy");
   HIPCHK(hipMemcpyAsync(flags, w.flags, sizeof flags, hipMemcpyDeviceToHost, st), "copy");
   HIPCHK(hipStreamSynchronize(st), "sync");
+  const bool cg_ran = w.solver == DGN_SOLVER_AUTO && w.cs == 1 && cg_supported(w.s);
   if (info) {
+    info->cg_iters = (cg_ran && flags[8]) ? flags[10] : -1;
     info->err2_old = host[0];
     info->err2_new = host[1];
     info->denom = sc[0];
@@ -565,6 +588,7 @@ dgn_status dgn_step_explicit(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, const
     info->danorm = sqrt(sc[1]);
     info->gnorm = sqrt(sc[2]);
     info->mnorm = sqrt(sc[3]);
+    info->cg_iters = -1;
   }
   if (flags[0]) return set_err(ctx, DGN_ESINGULAR, "non-positive pivot in J^T J + mu I");
   if (!isfinite(host[1]) || !isfinite(sc[0])) return set_err(ctx, DGN_ENONFINITE, "non-finite step");
@@ -584,13 +608,21 @@ dgn_status cp_fit(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, void* const* A, 
   if (o.poll_every < 1) o.poll_every = 1;
   if (o.normalize < 0 || o.normalize > 2) return set_err(ctx, DGN_EINVAL, "bad normalize option");
   if (o.als_sweeps < 0) return set_err(ctx, DGN_EINVAL, "als_sweeps must be >= 0");
+  if (o.solver != DGN_SOLVER_DIRECT && o.solver != DGN_SOLVER_AUTO) return set_err(ctx, DGN_EINVAL, "bad solver option");
+  if (o.solver == DGN_SOLVER_AUTO && (o.cg_max_iters < 0 || !(o.cg_tol > 0.0)))
+    return set_err(ctx, DGN_EINVAL, "need cg_max_iters >= 0 and cg_tol > 0");
   Work w{};
   dgn_status rc = prepare(ctx, Y, R, true, w);
   if (rc != DGN_OK) return rc;
   for (int n = 0; n < w.s.N; ++n)
     if (!A[n]) return set_err(ctx, DGN_EINVAL, "NULL factor pointer");
+  w.solver = o.solver;
+  w.cg_max = o.cg_max_iters;
+  w.cg_tol = o.cg_tol;
+  w.cg_sticky = true;
   hipStream_t st = (hipStream_t)stream;
   HIPCHK(hipSetDevice(ctx->device), "hipSetDevice");
+  HIPCHK(hipMemsetAsync(w.flags, 0, 64 * sizeof(int), st), "memset");
   bool resid = (w.ymaster == YType::F64) || w.cs == 2 || o.resid_switch < 0;
   const bool can_switch = !resid && o.resid_switch > 0;
   PassSel ps = pass_tensor(w, Y, o, resid);
@@ -652,9 +684,10 @@ dgn_status cp_fit(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, void* const* A, 
   }
   HIPCHK(copy_factors_out(w, w.A, A, st), "copy out");
   HIPCHK(hipMemcpyAsync(&hs, ds, sizeof hs, hipMemcpyDeviceToHost, st), "state");
-  int als_flag = 0;
-  if (o.als_sweeps > 0) HIPCHK(hipMemcpyAsync(&als_flag, w.flags, sizeof als_flag, hipMemcpyDeviceToHost, st), "copy");
+  int fl[16] = {0};
+  HIPCHK(hipMemcpyAsync(fl, w.flags, sizeof fl, hipMemcpyDeviceToHost, st), "copy");
   HIPCHK(hipStreamSynchronize(st), "sync");
+  const int als_flag = o.als_sweeps > 0 ? fl[0] : 0;
   if (als_flag) return set_err(ctx, DGN_ESINGULAR, "a Gamma^(n) of the ALS warm-up is not positive definite");
   if (o.timing) {
     const int nt = hs.iters < enq ? hs.iters : enq;
@@ -677,6 +710,8 @@ dgn_status cp_fit(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, void* const* A, 
     info->err2 = hs.err2;
     info->mu = hs.mu;
     info->mu0 = hs.mu0;
+    info->cg_trials = fl[11];
+    info->cg_iters = fl[12];
   }
   if (hs.singular) return set_err(ctx, DGN_ESINGULAR, "non-positive pivot in (Gamma + mu I) or the NR^2 system");
   if (hs.reason == DGN_STOP_NONFINITE) return set_err(ctx, DGN_ENONFINITE, "non-finite error or step");
@@ -964,6 +999,8 @@ dgn_status cp_fit_batched(dgn_ctx* ctx, int32_t B, const dgn_batch_fit* fits, do
       infos[b].err2 = hs[b].err2;
       infos[b].mu = hs[b].mu;
       infos[b].mu0 = hs[b].mu0;
+      infos[b].cg_trials = 0;
+      infos[b].cg_iters = 0;
     }
     nonfinite += hs[b].reason == DGN_STOP_NONFINITE;
   }

@@ -1,0 +1,203 @@
+// Iterative solve of the NR^2 system of the fast step: conjugate gradients on
+// the SPD form S y = z, S = I + W^T K W (W = blkdiag(X_n (x) L_n),
+// X_n X_n^T = (Gamma_n + mu I)^-1, L_n L_n^T = C_n), with S never formed.
+// The product uses the Kronecker structure of W and the permuted-diagonal
+// blocks K_nm = P_R diag(vec Gamma_nm) of K (Section 4.3):
+//   U_m = L_m Y_m X_m^T,   V_n = sum_{m != n} Gamma_nm .* U_m,
+//   (S y)_n = Y_n + L_n^T V_n^T X_n,          Y_n = unvec(y_n) (R x R),
+// which costs O(N R^3 + N^2 R^2) flops against O(N^2 R^4) for the formed
+// matrix.  Section 4.3 suggests an iterative solver on the structured system;
+// S is symmetric positive definite, so CG applies.
+//
+// One workgroup of 1024 threads holds every operand in LDS (N <= 4, R <= 32,
+// padded to 32 with zeros); the four R x R products per mode run on FP64 MFMA.
+// Thread t owns entry (t % 32, t / 32) of every mode's R x R block of the CG
+// vectors, so the Hadamard step and the vector updates need no exchange.
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace dgn {
+
+namespace {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+constexpr int CN = 4;       // modes held
+constexpr int CR = 32;      // padded rank
+constexpr int CS = CR + 1;  // LDS row stride
+
+// out(m, r, c) = sum_k fa(m, r, k) fb(m, k, c) over k < 32 for the 32 x 32
+// products of modes m < N; wave w takes the 16 x 16 output blocks w, w + 16, ...
+// (v_mfma_f64_16x16x4f64: lane l holds A[l % 16][l / 16], B[l / 16][l % 16],
+// result rows l / 16 + 4v, column l % 16).
+template <class FA, class FB, class FO>
+__device__ __forceinline__ void gemm32(int N, FA fa, FB fb, FO fo) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int bidx = w; bidx < 4 * N; bidx += 16) {
+    const int m = bidx >> 2, r0 = 16 * ((bidx >> 1) & 1), c0 = 16 * (bidx & 1);
+    v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < CR; k += 4) {
+      const int kk = k + (lane >> 4);
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(fa(m, r0 + (lane & 15), kk), fb(m, kk, c0 + (lane & 15)), acc, 0,
+                                                 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) fo(m, r0 + (lane >> 4) + 4 * v, c0 + (lane & 15), acc[v]);
+  }
+}
+
+// cgf: [0] 1 when the direct solve is to be skipped (converged, or the fit has
+// stopped), [1] sticky "CG off" (set on a failure when `sticky`), [2] this
+// solve's iterations, [3] solves that converged, [4] their iterations summed.
+__global__ __launch_bounds__(1024) void k_cg(Shape s, const double* __restrict__ C, const double* __restrict__ X,
+                                             const double* __restrict__ Lc, const double* __restrict__ z,
+                                             double* __restrict__ y, double tol, int maxit, int sticky, int* cgf,
+                                             const int* stop) {
+  __shared__ double Ls[CN][CR][CS];
+  __shared__ double Xs[CN][CR][CS];
+  __shared__ double Ps[CN][CR][CS];
+  __shared__ double Ts[CN][CR][CS];
+  __shared__ double red[16];
+  if (stopped(stop)) {
+    if (threadIdx.x == 0) cgf[0] = 1;
+    return;
+  }
+  if (cgf[1]) {
+    if (threadIdx.x == 0) cgf[0] = 0;
+    return;
+  }
+  const int N = s.N, R = s.R, R2 = R * R, t = threadIdx.x;
+  for (int e = t; e < CN * CR * CR; e += 1024) {
+    const int n = e / (CR * CR), rem = e % (CR * CR), i = rem % CR, j = rem / CR;
+    const bool in = n < N && i < R && j < R;
+    Ls[n][i][j] = in ? Lc[(long long)n * R2 + i + j * R] : 0.0;
+    Xs[n][i][j] = in ? X[(long long)n * R2 + i + j * R] : 0.0;
+  }
+  const int gi = t % CR, gj = t / CR;
+  const bool gin = gi < R && gj < R;
+  // Gamma_nm at (gi, gj): the Hadamard product of C_k over k not in {n, m}
+  double cv[CN];
+#pragma unroll
+  for (int k = 0; k < CN; ++k) cv[k] = (k < N && gin) ? C[(long long)k * R2 + gi + gj * R] : 0.0;
+  double g[CN][CN];
+#pragma unroll
+  for (int n = 0; n < CN; ++n)
+#pragma unroll
+    for (int m = 0; m < CN; ++m) {
+      // zero for the modes n, m >= N that only pad the arrays, so that their
+      // entries of the CG vectors stay zero
+      double p = (gin && n < N && m < N) ? 1.0 : 0.0;
+#pragma unroll
+      for (int k = 0; k < CN; ++k)
+        if (k < N && k != n && k != m) p *= cv[k];
+      g[n][m] = p;
+    }
+  double xv[CN], rv[CN], pv[CN];
+  double zz = 0.0;
+#pragma unroll
+  for (int n = 0; n < CN; ++n) {
+    const double zv = (n < N && gin) ? z[(long long)n * R2 + gi + gj * R] : 0.0;
+    xv[n] = 0.0;
+    rv[n] = zv;
+    pv[n] = zv;
+    zz += zv * zv;
+  }
+  double rr = block_sum(zz, red);
+  const double goal = tol * tol * rr;  // stop at ||r|| <= tol ||z||
+  bool conv = rr <= goal;
+  int it = 0;
+  while (!conv && it < maxit && isfinite(rr)) {
+#pragma unroll
+    for (int n = 0; n < CN; ++n) Ps[n][gi][gj] = pv[n];
+    sync_block();
+    // T_m = L_m P_m
+    gemm32(
+        N, [&](int m, int r, int k) { return Ls[m][r][k]; }, [&](int m, int k, int c) { return Ps[m][k][c]; },
+        [&](int m, int r, int c, double v) { Ts[m][r][c] = v; });
+    sync_block();
+    // U_m = T_m X_m^T (into Ps)
+    gemm32(
+        N, [&](int m, int r, int k) { return Ts[m][r][k]; }, [&](int m, int k, int c) { return Xs[m][c][k]; },
+        [&](int m, int r, int c, double v) { Ps[m][r][c] = v; });
+    sync_block();
+    // V_n = sum_{m != n} Gamma_nm .* U_m (into Ts), entry (gi, gj) of every mode
+    {
+      double u[CN];
+#pragma unroll
+      for (int m = 0; m < CN; ++m) u[m] = Ps[m][gi][gj];
+#pragma unroll
+      for (int n = 0; n < CN; ++n) {
+        double v = 0.0;
+#pragma unroll
+        for (int m = 0; m < CN; ++m)
+          if (m != n) v += g[n][m] * u[m];
+        Ts[n][gi][gj] = v;
+      }
+    }
+    sync_block();
+    // W_n = V_n^T X_n (into Ps)
+    gemm32(
+        N, [&](int m, int r, int k) { return Ts[m][k][r]; }, [&](int m, int k, int c) { return Xs[m][k][c]; },
+        [&](int m, int r, int c, double v) { Ps[m][r][c] = v; });
+    sync_block();
+    // O_n = L_n^T W_n (into Ts); (S p)_n = P_n + O_n
+    gemm32(
+        N, [&](int m, int r, int k) { return Ls[m][k][r]; }, [&](int m, int k, int c) { return Ps[m][k][c]; },
+        [&](int m, int r, int c, double v) { Ts[m][r][c] = v; });
+    sync_block();
+    double ap[CN];
+    double pap = 0.0;
+#pragma unroll
+    for (int n = 0; n < CN; ++n) {
+      ap[n] = n < N ? pv[n] + Ts[n][gi][gj] : 0.0;
+      pap += pv[n] * ap[n];
+    }
+    pap = block_sum(pap, red);
+    if (!(pap > 0.0)) break;  // not positive definite in finite precision: leave it to the direct solve
+    const double alpha = rr / pap;
+    double rn = 0.0;
+#pragma unroll
+    for (int n = 0; n < CN; ++n) {
+      xv[n] += alpha * pv[n];
+      rv[n] -= alpha * ap[n];
+      rn += rv[n] * rv[n];
+    }
+    rn = block_sum(rn, red);
+    ++it;
+    conv = rn <= goal;
+    const double beta = rn / rr;
+    rr = rn;
+#pragma unroll
+    for (int n = 0; n < CN; ++n) pv[n] = rv[n] + beta * pv[n];
+  }
+  if (conv) {
+#pragma unroll
+    for (int n = 0; n < CN; ++n)
+      if (n < N && gin) y[(long long)n * R2 + gi + gj * R] = xv[n];
+  }
+  if (t == 0) {
+    cgf[0] = conv ? 1 : 0;
+    cgf[2] = it;
+    if (conv) {
+      cgf[3] += 1;
+      cgf[4] += it;
+    } else if (sticky) {
+      cgf[1] = 1;
+    }
+  }
+}
+
+}  // namespace
+
+bool cg_supported(const Shape& s) { return s.N <= CN && s.R <= CR; }
+
+hipError_t launch_cg(const Shape& s, const SmallBuffers& b, double tol, int maxit, bool sticky, int* cgf,
+                     const int* stop, hipStream_t st) {
+  if (!cg_supported(s)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_cg, dim3(1), dim3(1024), 0, st, s, b.C, b.X, b.Lc, b.z, b.y, tol, maxit, sticky ? 1 : 0, cgf,
+                     stop);
+  return hipGetLastError();
+}
+
+}  // namespace dgn

@@ -42,18 +42,20 @@ class dgn_opts(ctypes.Structure):
     _fields_ = [("normalize", ctypes.c_int32), ("tau", ctypes.c_double),
                 ("resid_switch", ctypes.c_double), ("y_bf16", ctypes.c_void_p),
                 ("poll_every", ctypes.c_int32), ("timing", ctypes.c_int32),
-                ("graph", ctypes.c_int32), ("als_sweeps", ctypes.c_int32)]
+                ("graph", ctypes.c_int32), ("als_sweeps", ctypes.c_int32),
+                ("solver", ctypes.c_int32), ("cg_max_iters", ctypes.c_int32), ("cg_tol", ctypes.c_double)]
 
 
 class dgn_step_info(ctypes.Structure):
     _fields_ = [(n, ctypes.c_double) for n in
-                ("err2_old", "err2_new", "rho", "denom", "gnorm", "mnorm", "danorm")]
+                ("err2_old", "err2_new", "rho", "denom", "gnorm", "mnorm", "danorm")] + [("cg_iters", ctypes.c_int32)]
 
 
 class dgn_fit_info(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("accepted", ctypes.c_int32), ("reason", ctypes.c_int32),
                 ("resid_iters", ctypes.c_int32), ("eps", ctypes.c_double), ("err2", ctypes.c_double),
-                ("mu", ctypes.c_double), ("mu0", ctypes.c_double)]
+                ("mu", ctypes.c_double), ("mu0", ctypes.c_double),
+                ("cg_trials", ctypes.c_int32), ("cg_iters", ctypes.c_int32)]
 
 
 class dgn_batch_fit(ctypes.Structure):
