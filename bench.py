@@ -409,6 +409,7 @@ def main():
     ap.add_argument("--no-als", action="store_true")
     ap.add_argument("--no-dgn-sweep", action="store_true")
     ap.add_argument("--no-svd", action="store_true")
+    ap.add_argument("--no-cg", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run a plain copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
@@ -457,6 +458,22 @@ def main():
     dtb, infob = run(args.steps, obf)
     phb, ntb = ctx.dgn_last_phase_times()
     perb = {k: v / max(ntb, 1) for k, v in phb.items()}
+    # the same fit with the iterative NR^2 solve (CG on the structured SPD
+    # system, the direct Cholesky where CG does not converge), reported beside it
+    cg_leg = None
+    if not args.no_cg:
+        ocg = dgn.opts(timing=1, solver=1)
+        run(args.warmup, ocg)
+        dtc, infoc = run(args.steps, ocg)
+        phc, ntc = ctx.dgn_last_phase_times()
+        perc = {k: v / max(ntc, 1) for k, v in phc.items()}
+        cg_leg = {"iters_per_s": round(infoc["iters"] / dtc, 3), "ms_per_step": round(dtc / max(infoc["iters"], 1) * 1e3, 4),
+                  "cg_trials": infoc["cg_trials"], "trials": infoc["iters"],
+                  "cg_iters_per_solve": round(infoc["cg_iters"] / max(infoc["cg_trials"], 1), 1),
+                  "solve_ms": round(perc["assemble"] + perc["factor_solve"], 4),
+                  "direct_solve_ms": round(per["assemble"] + per["factor_solve"], 4),
+                  "eps": infoc["eps"], "eps_direct": info["eps"],
+                  "phase_ms": {k: round(v, 4) for k, v in perc.items()}}
 
     pass_ms = per["tensor_pass"]
     pass_gbs = J * 4 / (pass_ms * 1e-3) / 1e9
@@ -501,6 +518,8 @@ def main():
                 "resid_iters": info["resid_iters"]},
         "gen_s": round(gen_s, 1),
     }
+    if cg_leg is not None:
+        line["cg_auto"] = cg_leg
     if not args.no_als:
         line["als"] = bench_als(dgn, torch, ctx, y32, dims, R, p, dev)
     if not args.no_svd:

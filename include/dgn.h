@@ -123,11 +123,11 @@ typedef struct dgn_opts {
    * form (Section 4.3: Kronecker and permuted-diagonal products, the matrix is
    * never formed) and runs the direct tiled Cholesky only when CG has not
    * reached ||r|| <= cg_tol ||z|| within cg_max_iters iterations; inside cp_fit
-   * the first such failure switches CG off for the rest of the fit.  The step
+   * the first such failure leaves CG out for the rest of the fit.  The step
    * then differs from the direct one by the CG tolerance (amplified by the
    * condition number of the system).  Default DGN_SOLVER_DIRECT. */
   int32_t solver;
-  int32_t cg_max_iters; /* default 200 */
+  int32_t cg_max_iters; /* default 100 */
   double cg_tol;        /* default 1e-10 */
 } dgn_opts;
 

@@ -77,7 +77,6 @@ struct Work {
   int solver = 0;  // dgn_solver
   int cg_max = 0;
   double cg_tol = 0.0;
-  bool cg_sticky = false;
   double* scr;     // [0..1023] norm partials, [1024] e2, [1025] e2c, [1026..1029] err2 / ynorm2
 };
 
@@ -304,7 +303,7 @@ hipError_t enqueue_step(Work& w, bool resid, double mu_host, FitState* state, in
   // themselves (flags[8] set) when CG converged or the fit has stopped
   const int* solve_stop = stop;
   if (w.solver == DGN_SOLVER_AUTO && cg_supported(s)) {
-    if ((e = launch_cg(s, w.sb, w.cg_tol, w.cg_max, w.cg_sticky, w.flags + 8, stop, st)) != hipSuccess) return e;
+    if ((e = launch_cg(s, w.sb, w.cg_tol, w.cg_max, state, mu_host, w.flags + 8, stop, st)) != hipSuccess) return e;
     solve_stop = w.flags + 8;
   }
   if ((e = launch_sys_assemble(s, w.sp, w.sb, w.sy, solve_stop, st)) != hipSuccess) return e;
@@ -381,7 +380,7 @@ void dgn_opts_default(dgn_opts* o) {
   o->timing = 0;
   o->graph = 1;
   o->solver = DGN_SOLVER_DIRECT;
-  o->cg_max_iters = 200;
+  o->cg_max_iters = 100;
   o->cg_tol = 1e-10;
 }
 
@@ -490,7 +489,6 @@ dgn_status dgn_step(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, const void* co
   w.solver = o.solver;
   w.cg_max = o.cg_max_iters;
   w.cg_tol = o.cg_tol;
-  w.cg_sticky = false;
   hipStream_t st = (hipStream_t)stream;
   HIPCHK(hipSetDevice(ctx->device), "hipSetDevice");
   const bool resid = (w.ymaster == YType::F64) || w.cs == 2 || o.resid_switch < 0;
@@ -619,7 +617,6 @@ dgn_status cp_fit(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, void* const* A, 
   w.solver = o.solver;
   w.cg_max = o.cg_max_iters;
   w.cg_tol = o.cg_tol;
-  w.cg_sticky = true;
   hipStream_t st = (hipStream_t)stream;
   HIPCHK(hipSetDevice(ctx->device), "hipSetDevice");
   HIPCHK(hipMemsetAsync(w.flags, 0, 64 * sizeof(int), st), "memset");

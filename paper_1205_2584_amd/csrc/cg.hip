@@ -47,23 +47,41 @@ __device__ __forceinline__ void gemm32(int N, FA fa, FB fb, FO fo) {
   }
 }
 
+// Sum over the workgroup with a single barrier: the callers alternate two
+// scratch arrays, and every reuse of one is separated from its previous reads
+// by the barriers of the product phases.
+__device__ __forceinline__ double block_sum1(double v, double* scratch) {
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) scratch[threadIdx.x >> 6] = v;
+  sync_block();
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) s += scratch[i];
+  return s;
+}
+
 // cgf: [0] 1 when the direct solve is to be skipped (converged, or the fit has
-// stopped), [1] sticky "CG off" (set on a failure when `sticky`), [2] this
-// solve's iterations, [3] solves that converged, [4] their iterations summed.
+// stopped), [2] this solve's iterations, [3] solves that converged, [4] their
+// iterations summed.  Inside a fit (state != NULL) the first failed solve
+// records its damping in the state and CG is not tried again in that fit, so a
+// fit loses at most one capped attempt.
 __global__ __launch_bounds__(1024) void k_cg(Shape s, const double* __restrict__ C, const double* __restrict__ X,
                                              const double* __restrict__ Lc, const double* __restrict__ z,
-                                             double* __restrict__ y, double tol, int maxit, int sticky, int* cgf,
-                                             const int* stop) {
+                                             double* __restrict__ y, double tol, int maxit, FitState* state,
+                                             double mu_host, int* cgf, const int* stop) {
   __shared__ double Ls[CN][CR][CS];
   __shared__ double Xs[CN][CR][CS];
   __shared__ double Ps[CN][CR][CS];
   __shared__ double Ts[CN][CR][CS];
   __shared__ double red[16];
+  __shared__ double red_a[16];
+  __shared__ double red_b[16];
   if (stopped(stop)) {
     if (threadIdx.x == 0) cgf[0] = 1;
     return;
   }
-  if (cgf[1]) {
+  const double mu = state ? state->mu : mu_host;
+  if (state && state->cg_mu_fail > 0.0) {
     if (threadIdx.x == 0) cgf[0] = 0;
     return;
   }
@@ -153,7 +171,7 @@ __global__ __launch_bounds__(1024) void k_cg(Shape s, const double* __restrict__
       ap[n] = n < N ? pv[n] + Ts[n][gi][gj] : 0.0;
       pap += pv[n] * ap[n];
     }
-    pap = block_sum(pap, red);
+    pap = block_sum1(pap, red_a);
     if (!(pap > 0.0)) break;  // not positive definite in finite precision: leave it to the direct solve
     const double alpha = rr / pap;
     double rn = 0.0;
@@ -163,7 +181,7 @@ __global__ __launch_bounds__(1024) void k_cg(Shape s, const double* __restrict__
       rv[n] -= alpha * ap[n];
       rn += rv[n] * rv[n];
     }
-    rn = block_sum(rn, red);
+    rn = block_sum1(rn, red_b);
     ++it;
     conv = rn <= goal;
     const double beta = rn / rr;
@@ -182,8 +200,8 @@ __global__ __launch_bounds__(1024) void k_cg(Shape s, const double* __restrict__
     if (conv) {
       cgf[3] += 1;
       cgf[4] += it;
-    } else if (sticky) {
-      cgf[1] = 1;
+    } else if (state) {
+      state->cg_mu_fail = mu;
     }
   }
 }
@@ -192,10 +210,10 @@ __global__ __launch_bounds__(1024) void k_cg(Shape s, const double* __restrict__
 
 bool cg_supported(const Shape& s) { return s.N <= CN && s.R <= CR; }
 
-hipError_t launch_cg(const Shape& s, const SmallBuffers& b, double tol, int maxit, bool sticky, int* cgf,
-                     const int* stop, hipStream_t st) {
+hipError_t launch_cg(const Shape& s, const SmallBuffers& b, double tol, int maxit, FitState* state, double mu_host,
+                     int* cgf, const int* stop, hipStream_t st) {
   if (!cg_supported(s)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_cg, dim3(1), dim3(1024), 0, st, s, b.C, b.X, b.Lc, b.z, b.y, tol, maxit, sticky ? 1 : 0, cgf,
+  hipLaunchKernelGGL(k_cg, dim3(1), dim3(1024), 0, st, s, b.C, b.X, b.Lc, b.z, b.y, tol, maxit, state, mu_host, cgf,
                      stop);
   return hipGetLastError();
 }

@@ -30,6 +30,7 @@ struct FitState {
   int iters, accepted, stop, reason;
   int max_iters, commit_iter, singular, normalize;
   int resid, resid_iters, pad0, pad1;
+  double cg_mu_fail;   // damping of the trial whose CG solve did not converge (0: none yet)
   double scale[kMaxOrder * kMaxRank];  // column scales of the last normalisation
 };
 

@@ -191,9 +191,10 @@ hipError_t launch_batched_final(BFit* fits, int nfits, hipStream_t st);
 // ---- iterative NR^2 solve (conjugate gradients on the structured SPD form) ----
 bool cg_supported(const Shape& s);  // N <= 4, R <= 32
 // y = S^-1 z by CG from b.C, b.X, b.Lc, b.z into b.y; cgf[0] = 1 when the
-// direct solve can be skipped (see the kernel for the other counters).
-hipError_t launch_cg(const Shape& s, const SmallBuffers& b, double tol, int maxit, bool sticky, int* cgf,
-                     const int* stop, hipStream_t st);
+// direct solve can be skipped (see the kernel for the other counters); mu from
+// state when state != NULL, which also carries the retry rule of a fit.
+hipError_t launch_cg(const Shape& s, const SmallBuffers& b, double tol, int maxit, FitState* state, double mu_host,
+                     int* cgf, const int* stop, hipStream_t st);
 
 // ---- mode-n singular vectors (SVD initialisation) ---------------------------
 // Y viewed for mode n as (P, I, Q): element (p, i, q) at p + P (i + I q).

@@ -154,7 +154,7 @@ def test_cg_fit_matches_direct_fit():
         assert info_c["iters"] == info_d["iters"] == 30
         # same trajectory within the solver tolerance: the final errors agree
         assert abs(info_c["eps"] - info_d["eps"]) <= 1e-6 * info_d["eps"]
-        # a CG that never converges switches itself off: bit-identical to the direct fit
+        # a CG that never converges leaves every trial to the direct solve: bit-identical to the direct fit
         Ao = dgn.to_device_factors(p.init)
         info_o = ctx.cp_fit(y, dims, R, Ao, -1.0, 0.0, 30, dgn.opts(solver=1, cg_max_iters=1))
         assert info_o["cg_trials"] == 0
