@@ -196,6 +196,20 @@ dgn_status dgn_step(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, const void* co
                     void* const* A_out, double mu, const dgn_opts* opts, dgn_step_info* info,
                     void* stream);
 
+/* The damped system with any right-hand side: X = (J^T J + mu I)^-1 V, the
+ * inverse of H_mu applied in the block form of Section 4.1 (the memory-saving
+ * representation: the R x R inverses (Gamma^(n) + mu I)^-1 and the NR^2
+ * system, never the RT x RT inverse), with J the Jacobian of the CP model at the
+ * factors A (Lemma B.1) -- dgn_step is this call with V = the gradient.  order,
+ * dims: the mode sizes; A: N device pointers to I_n x R FP64 factors; V, X: N
+ * device pointers to I_n x R FP64 column-major blocks (the parameter vector in
+ * blocks, as the factors are; X may not alias V).  Real factors only; mu > 0;
+ * opts->solver selects the direct or the iterative NR^2 solve as for dgn_step.
+ * Workspace as dgn_workspace_size for an F64 tensor of these sizes.
+ * Synchronises the stream before returning. */
+dgn_status dgn_hessian_solve(dgn_ctx* ctx, int32_t order, const int64_t* dims, int32_t R, const void* const* A,
+                             const void* const* V, void* const* X, double mu, const dgn_opts* opts, void* stream);
+
 /* The plain damped Gauss-Newton step of Section 3 with the Hessian formed
  * explicitly: (J^T J + mu I) da = J^T vec(Y - Y_hat), J^T J of size RT x RT
  * with the block form of Appendix B (diagonal blocks Gamma^(n) (x) I, off-diagonal

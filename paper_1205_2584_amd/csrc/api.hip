@@ -74,6 +74,7 @@ struct Work {
   SysBuffers ey;
   FitState* state;
   int* flags;      // [0] singular (step), [8..12] CG solve counters (launch_cg), others spare
+  double* da_out = nullptr;  // when set, the step's update also writes da (stacked like A)
   int solver = 0;  // dgn_solver
   int cg_max = 0;
   double cg_tol = 0.0;
@@ -312,7 +313,7 @@ hipError_t enqueue_step(Work& w, bool resid, double mu_host, FitState* state, in
   if ((e = mark(ev, 3, st)) != hipSuccess) return e;
   if ((e = launch_u(s, w.sb, stop, st)) != hipSuccess) return e;
   if ((e = launch_fq(s, w.sb, stop, st)) != hipSuccess) return e;
-  if ((e = launch_update(s, w.A, w.Ac, w.sb, mu_host, state, stop, st)) != hipSuccess) return e;
+  if ((e = launch_update(s, w.A, w.Ac, w.sb, mu_host, state, stop, st, w.da_out)) != hipSuccess) return e;
   return launch_update_reduce(s, w.sb, w.sb.scal, stop, st);
 }
 
@@ -527,6 +528,51 @@ dgn_status dgn_step(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, const void* co
   }
   if (flags[0]) return set_err(ctx, DGN_ESINGULAR, "non-positive pivot in (Gamma + mu I) or the NR^2 system");
   if (!isfinite(host[1]) || !isfinite(sc[0])) return set_err(ctx, DGN_ENONFINITE, "non-finite step");
+  return DGN_OK;
+}
+
+dgn_status dgn_hessian_solve(dgn_ctx* ctx, int32_t order, const int64_t* dims, int32_t R, const void* const* A,
+                             const void* const* V, void* const* X, double mu, const dgn_opts* opts, void* stream) {
+  if (!ctx) return DGN_EINVAL;
+  if (!dims || !A || !V || !X) return set_err(ctx, DGN_EINVAL, "NULL dims or pointer array");
+  if (!(mu > 0.0) || !isfinite(mu)) return set_err(ctx, DGN_EINVAL, "mu must be finite and > 0");
+  dgn_opts o;
+  dgn_opts_default(&o);
+  if (opts) o = *opts;
+  if (o.solver != DGN_SOLVER_DIRECT && o.solver != DGN_SOLVER_AUTO) return set_err(ctx, DGN_EINVAL, "bad solver option");
+  if (o.solver == DGN_SOLVER_AUTO && (o.cg_max_iters < 0 || !(o.cg_tol > 0.0)))
+    return set_err(ctx, DGN_EINVAL, "need cg_max_iters >= 0 and cg_tol > 0");
+  if (order < 3 || order > DGN_MAX_ORDER) return set_err(ctx, DGN_EINVAL, "order must be in [3, 8]");
+  // the system depends on the factors only: plan it as for an FP64 tensor of
+  // these sizes, whose data is never read
+  dgn_tensor t{};
+  t.order = order;
+  for (int n = 0; n < order; ++n) t.dims[n] = dims[n];
+  t.dtype = DGN_F64;
+  t.data = &t;
+  Work w{};
+  dgn_status rc = prepare(ctx, &t, R, true, w);
+  if (rc != DGN_OK) return rc;
+  for (int n = 0; n < w.s.N; ++n)
+    if (!A[n] || !V[n] || !X[n]) return set_err(ctx, DGN_EINVAL, "NULL factor or block pointer");
+  w.solver = o.solver;
+  w.cg_max = o.cg_max_iters;
+  w.cg_tol = o.cg_tol;
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(hipSetDevice(ctx->device), "hipSetDevice");
+  HIPCHK(hipMemsetAsync(w.flags, 0, 64 * sizeof(int), st), "memset");
+  HIPCHK(copy_factors_in(w, A, w.A, st), "copy factors");
+  HIPCHK(copy_factors_in(w, V, w.M, st), "copy right-hand side");
+  HIPCHK(run_gram(w, w.A, w.sb.C, nullptr, st), "gram");
+  // the step with M taken as the gradient (its residual form) solves
+  // (J^T J + mu I) da = vec(V); the update hands da out into Mc
+  w.da_out = w.Mc;
+  HIPCHK(enqueue_step(w, true, mu, nullptr, w.flags, nullptr, st), "solve");
+  HIPCHK(copy_factors_out(w, w.Mc, X, st), "copy out");
+  int flags[1] = {0};
+  HIPCHK(hipMemcpyAsync(flags, w.flags, sizeof flags, hipMemcpyDeviceToHost, st), "copy");
+  HIPCHK(hipStreamSynchronize(st), "sync");
+  if (flags[0]) return set_err(ctx, DGN_ESINGULAR, "non-positive pivot in (Gamma + mu I) or the NR^2 system");
   return DGN_OK;
 }
 

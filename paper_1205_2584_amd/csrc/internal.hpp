@@ -68,8 +68,10 @@ hipError_t launch_tnm(const Shape& s, const SmallBuffers& b, const int* stop, hi
 hipError_t launch_u(const Shape& s, const SmallBuffers& b, const int* stop, hipStream_t st);
 hipError_t launch_fq(const Shape& s, const SmallBuffers& b, const int* stop, hipStream_t st);
 // A_c = A + P - A Q_n; partial Grams of A_c and the gain-ratio denominator.
+// Ac = A + da; da itself also into da_out when it is not NULL.
 hipError_t launch_update(const Shape& s, const double* A, double* Ac, const SmallBuffers& b,
-                         double mu_host, const FitState* state, const int* stop, hipStream_t st);
+                         double mu_host, const FitState* state, const int* stop, hipStream_t st,
+                         double* da_out = nullptr);
 hipError_t launch_update_reduce(const Shape& s, const SmallBuffers& b, double* scal_out,
                                 const int* stop, hipStream_t st);
 // ALS update of mode n (eq. ALS): A_n = M_n Gt_n, with Gt_n = Gamma^(n)^-1 as

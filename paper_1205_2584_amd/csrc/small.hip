@@ -500,7 +500,7 @@ __global__ __launch_bounds__(256) void k_fq(Shape s, const double* C, const doub
 __global__ __launch_bounds__(256) void k_update(Shape s, const double* A, const double* P,
                                                 const double* G, const double* Q, double mu_host,
                                                 const FitState* state, double* Ac, double* part,
-                                                int chunks, int stride, const int* stop) {
+                                                int chunks, int stride, double* da_out, const int* stop) {
   if (stopped(stop)) return;
   __shared__ double As[64][LD];
   __shared__ double Qs[64][LD];
@@ -532,6 +532,7 @@ __global__ __launch_bounds__(256) void k_update(Shape s, const double* A, const 
       const double da = P[gi] - acc;
       v = As[ii][r] + da;
       Ac[gi] = v;
+      if (da_out) da_out[gi] = da;
       den += da * (G[gi] + mu * da);
       da2 += da * da;
     }
@@ -623,10 +624,11 @@ hipError_t launch_fq(const Shape& s, const SmallBuffers& b, const int* stop, hip
 }
 
 hipError_t launch_update(const Shape& s, const double* A, double* Ac, const SmallBuffers& b,
-                         double mu_host, const FitState* state, const int* stop, hipStream_t st) {
+                         double mu_host, const FitState* state, const int* stop, hipStream_t st,
+                         double* da_out) {
   const int ch = row_chunks(s), stride = part_stride(s);
   k_update<<<dim3(s.N, ch), 256, 0, st>>>(s, A, b.P, b.G, b.Q, mu_host, state, Ac, b.rowpart, ch,
-                                           stride, stop);
+                                           stride, da_out, stop);
   return hipGetLastError();
 }
 

@@ -77,7 +77,7 @@ class dgn_result(ctypes.Structure):
 
 EXPORTS = ["dgn_opts_default", "dgn_create", "dgn_destroy", "dgn_last_error", "dgn_workspace_size",
            "dgn_mttkrp", "dgn_step", "dgn_step_explicit", "dgn_workspace_size_explicit", "cp_fit", "cp_als",
-           "dgn_mode_gram", "cp_svd_init", "dgn_workspace_size_svd", "dgn_last_phase_times", "cp_fit_batched",
+           "dgn_mode_gram", "cp_svd_init", "dgn_workspace_size_svd", "dgn_hessian_solve", "dgn_last_phase_times", "cp_fit_batched",
            "dgn_server_create", "dgn_server_submit", "dgn_server_poll", "dgn_server_wait_idle",
            "dgn_server_stats", "dgn_server_now", "dgn_server_destroy"]
 NUM_PHASES = 6
@@ -115,6 +115,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.cp_als.argtypes = [vp, ctypes.POINTER(dgn_tensor), i32, ctypes.POINTER(vp), i32,
                          ctypes.POINTER(dgn_opts), ctypes.POINTER(dbl), vp]
     L.dgn_mode_gram.argtypes = [vp, ctypes.POINTER(dgn_tensor), i32, vp, vp]
+    L.dgn_hessian_solve.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int64), i32, ctypes.POINTER(vp),
+                                    ctypes.POINTER(vp), ctypes.POINTER(vp), dbl, ctypes.POINTER(dgn_opts), vp]
     L.cp_svd_init.argtypes = [vp, ctypes.POINTER(dgn_tensor), i32, i32, vp, i32, ctypes.POINTER(vp), vp, vp]
     L.dgn_workspace_size_svd.argtypes = [ctypes.POINTER(dgn_tensor), i32, i32, ctypes.POINTER(ctypes.c_size_t)]
     L.dgn_last_phase_times.argtypes = [vp, ctypes.POINTER(dbl), i32, ctypes.POINTER(i32)]
@@ -130,7 +132,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.dgn_server_destroy.argtypes = [vp]
     for name in ("dgn_create", "dgn_destroy", "dgn_workspace_size", "dgn_mttkrp", "dgn_step", "cp_fit", "cp_als",
                  "dgn_step_explicit", "dgn_workspace_size_explicit",
-                 "dgn_mode_gram", "cp_svd_init", "dgn_workspace_size_svd",
+                 "dgn_mode_gram", "cp_svd_init", "dgn_workspace_size_svd", "dgn_hessian_solve",
                  "dgn_last_phase_times", "cp_fit_batched", "dgn_server_create", "dgn_server_submit",
                  "dgn_server_poll", "dgn_server_wait_idle", "dgn_server_stats", "dgn_server_destroy"):
         getattr(L, name).restype = ctypes.c_int
@@ -253,6 +255,15 @@ class Context:
                                   ctypes.byref(options) if options else None, ctypes.byref(err2),
                                   _stream()))
         return err2.value
+
+    def hessian_solve(self, dims, R, factors, V, mu, options: dgn_opts | None = None):
+        """X = (J^T J + mu I)^-1 vec(V) at the factors; V and the result are (R, I_n)
+        float64 device tensors (column-major I_n x R blocks)."""
+        X = [torch.empty_like(v) for v in V]
+        d = (ctypes.c_int64 * len(dims))(*[int(v) for v in dims])
+        self._check(self.L.dgn_hessian_solve(self.h, len(dims), d, int(R), _ptrs(factors), _ptrs(V), _ptrs(X),
+                                             float(mu), ctypes.byref(options) if options else None, _stream()))
+        return X
 
     def mode_gram(self, y, dims, n):
         """Y_(n) Y_(n)^T as an (I_n, I_n) float64 device tensor (enqueued, not synchronised)."""
