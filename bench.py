@@ -410,6 +410,7 @@ def main():
     ap.add_argument("--no-dgn-sweep", action="store_true")
     ap.add_argument("--no-svd", action="store_true")
     ap.add_argument("--no-cg", action="store_true")
+    ap.add_argument("--no-hsolve", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run a plain copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
@@ -520,6 +521,21 @@ def main():
     }
     if cg_leg is not None:
         line["cg_auto"] = cg_leg
+    if not args.no_hsolve:
+        # (J^T J + mu I)^-1 V for a random V at the starting factors: the step
+        # without its tensor passes (block-form inverse, direct NR^2 solve)
+        rng = np.random.default_rng(12)
+        A0 = dgn.to_device_factors(p.init, dev)
+        V = dgn.to_device_factors([rng.standard_normal((I, R)) for I in dims], dev)
+        mu_h = float(info["mu0"])
+        ctx.hessian_solve(dims, R, A0, V, mu_h)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            ctx.hessian_solve(dims, R, A0, V, mu_h)
+        torch.cuda.synchronize()
+        line["hessian_solve"] = {"ms_per_solve": round((time.perf_counter() - t0) / 5 * 1e3, 4), "mu": mu_h,
+                                 "note": "(J^T J + mu I)^-1 V, V random, J at the starting factors of the workload"}
     if not args.no_als:
         line["als"] = bench_als(dgn, torch, ctx, y32, dims, R, p, dev)
     if not args.no_svd:
