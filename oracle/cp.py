@@ -409,12 +409,16 @@ def als(Y: np.ndarray, A, sweeps: int):
 
 
 def canonical_signs(U: np.ndarray) -> np.ndarray:
-    """Flip each column so that its entry of largest magnitude (the first one
-    on ties) is positive: singular vectors are defined up to sign."""
+    """Scale each column by the unit factor that makes its entry of largest
+    magnitude (the first one on ties) real and positive: singular vectors are
+    defined up to sign (complex: up to a unit complex factor, Section 5)."""
     U = np.array(U, copy=True)
     for r in range(U.shape[1]):
         k = int(np.argmax(np.abs(U[:, r])))
-        if U[k, r] < 0:
+        if np.iscomplexobj(U):
+            if U[k, r] != 0:
+                U[:, r] = U[:, r] * (np.conj(U[k, r]) / abs(U[k, r]))
+        elif U[k, r] < 0:
             U[:, r] = -U[:, r]
     return U
 

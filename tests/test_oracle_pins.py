@@ -443,3 +443,29 @@ def test_svd_init_spans_the_factors_of_an_exact_rank_r_tensor():
     for a, f in zip(A, F):
         # the projector onto span(A^(n)) reproduces the true factor
         assert np.linalg.norm(a @ (a.T @ f) - f) < 1e-10 * np.linalg.norm(f)
+
+
+def test_svd_init_complex_matches_hermitian_gram_eigenvectors():
+    # complex tensors (Section 5): the left singular vectors of Y_(n) are the
+    # eigenvectors of the Hermitian Y_(n) Y_(n)^H, built here by a fibre loop
+    rng = np.random.default_rng(23)
+    dims, R = (6, 5, 7), 3
+    Y = rng.standard_normal(dims) + 1j * rng.standard_normal(dims)
+    A, S = cp.svd_init(Y, R)
+    for n in range(3):
+        G = np.zeros((dims[n], dims[n]), dtype=complex)
+        others = [k for k in range(3) if k != n]
+        for idx in np.ndindex(*[dims[k] for k in others]):
+            sl = [slice(None)] * 3
+            for k, i in zip(others, idx):
+                sl[k] = i
+            f = Y[tuple(sl)]
+            G += np.outer(f, np.conj(f))
+        w, V = np.linalg.eigh(G)
+        V = cp.canonical_signs(V[:, ::-1][:, :R])
+        assert np.allclose(S[n] ** 2, w[::-1][:R], rtol=1e-10)
+        assert np.linalg.norm(A[n] - V) < 1e-9
+        assert np.linalg.norm(A[n].conj().T @ A[n] - np.eye(R)) < 1e-12
+        for r in range(R):  # the canonical phase: largest entry real and positive
+            k = int(np.argmax(np.abs(A[n][:, r])))
+            assert abs(A[n][k, r].imag) < 1e-15 and A[n][k, r].real > 0
