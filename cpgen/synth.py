@@ -194,3 +194,9 @@ def svd_start_block(rng: np.random.Generator, dims, block: int) -> np.ndarray:
     """Random start blocks of the SVD initialisation: N(0,1) entries, mode n's
     I_n x block column-major block after those of the earlier modes."""
     return np.concatenate([rng.standard_normal((block, int(I))).reshape(-1) for I in dims])
+
+
+def svd_start_block_complex(rng: np.random.Generator, dims, block: int) -> np.ndarray:
+    """Complex start blocks: real and imaginary parts N(0,1), same layout."""
+    re = svd_start_block(rng, dims, block)
+    return re + 1j * svd_start_block(rng, dims, block)

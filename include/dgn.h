@@ -259,11 +259,12 @@ dgn_status cp_als(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, void* const* A, 
 /* Mode-n Gram matrix G = Y_(n) Y_(n)^T (I_n x I_n, FP64, column-major,
  * leading dimension I_n, both triangles written), the matrix whose leading
  * eigenvectors are the mode-n singular vectors used to initialise the factors
- * (Section 4.5).  Real tensors (F64, F32, BF16; entries widened to FP64 and
- * products summed in FP64); a complex dtype or n outside [0, order) gives
- * DGN_EINVAL.  G: caller-owned device buffer.  Uses the context's workspace
- * (about 64 MB at most for the partial tiles); enqueued on `stream` without a
- * synchronisation. */
+ * (Section 4.5).  Entries are widened to FP64 and products summed in FP64.
+ * Complex tensors (C64, C128; Section 5): the Hermitian G = Y_(n) Y_(n)^H as
+ * interleaved complex128.  n outside [0, order) gives DGN_EINVAL.  G:
+ * caller-owned device buffer.  Uses the context's workspace (about 64 MB at
+ * most for the partial tiles, plus (2 I_n)^2 doubles for complex tensors);
+ * enqueued on `stream` without a synchronisation. */
 dgn_status dgn_mode_gram(dgn_ctx* ctx, const dgn_tensor* Y, int32_t n, double* G, void* stream);
 
 /* SVD initialisation (Section 4.5, as the experiments of Section 6 start):
@@ -278,7 +279,11 @@ dgn_status dgn_mode_gram(dgn_ctx* ctx, const dgn_tensor* Y, int32_t n, double* G
  * block doubles, mode n's I_n x block column-major block after those of modes
  * < n.  A: N device pointers to I_n x R FP64 outputs.  sv (device, may be
  * NULL): N x R doubles, sv[n R + r] = r-th singular value of Y_(n).  Needs
- * R <= every I_n and a real tensor (DGN_EINVAL otherwise).  DGN_ESINGULAR if
+ * R <= every I_n (DGN_EINVAL otherwise).  Complex tensors (Section 5): omega
+ * and the factors are interleaved complex128, the vectors are fixed up to a
+ * unit complex factor, chosen so that each column's largest-magnitude entry is
+ * real and positive; R <= 32 and block <= 40, as the iteration runs on the real
+ * embedding [[Re G, -Im G], [Im G, Re G]] of the Hermitian Gram.  DGN_ESINGULAR if
  * the orthonormalisation breaks down (omega of deficient rank).  Workspace
  * from dgn_workspace_size_svd.  Synchronises the stream before returning. */
 dgn_status cp_svd_init(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, int32_t block, const double* omega,

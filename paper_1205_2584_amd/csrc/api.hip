@@ -821,46 +821,60 @@ struct SvdWork {
   double* part;
   double* sigma;
   int* bad;
+  // complex tensors: the problem in m is the real embedding (doubled sizes)
+  bool cplx = false;
+  double* Gp = nullptr;   // real Gram of the interleaved rows, (2 I_n)^2 for the largest mode
+  double* svr = nullptr;  // N x 2R singular values of the embedding
 };
 
-// Validates the tensor for the SVD calls (real dtypes, no rank check beyond
-// 1 <= R) and fills s / yt.
+// Validates the tensor for the SVD calls (no rank check beyond 1 <= R) and
+// fills s / yt.
 dgn_status check_svd_tensor(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, Shape* s, YType* yt) {
-  const int32_t rr = (R >= 1 && R <= DGN_MAX_RANK) ? R : 1;
-  dgn_status st = check_shape(ctx, Y, rr, s, yt);
-  if (st != DGN_OK) return st;
-  if (is_complex(*yt)) return set_err(ctx, DGN_EINVAL, "the mode Gram and the SVD initialisation take real tensors");
-  return DGN_OK;
+  const int32_t rr = (R >= 1 && R <= kMaxRankC) ? R : 1;
+  return check_shape(ctx, Y, rr, s, yt);
 }
 
-void carve_svd(Arena& ar, const Shape& s, int R, int b, SvdWork& w) {
+// Complex tensors run the real pipeline on the embeddings [[G_re, -G_im],
+// [G_im, G_re]] of their Hermitian Grams: sizes, block and rank doubled.
+void carve_svd(Arena& ar, const Shape& s, int R, int b, bool cplx, SvdWork& w) {
+  const int f = cplx ? 2 : 1;
   SvdModes& m = w.m;
+  w.cplx = cplx;
   m.N = s.N;
-  m.b = b;
-  m.bp = (b + 15) / 16 * 16;
-  m.R = R;
+  m.b = f * b;
+  m.bp = (m.b + 15) / 16 * 16;
+  m.R = f * R;
   m.blk0[0] = 0;
+  size_t gp = 0;
   for (int n = 0; n < s.N; ++n) {
-    m.I[n] = s.I[n];
-    m.Ip[n] = (s.I[n] + 63) / 64 * 64;
+    m.I[n] = f * s.I[n];
+    m.Ip[n] = (m.I[n] + 63) / 64 * 64;
     m.G[n] = ar.take<double>((size_t)m.Ip[n] * m.Ip[n]);
     m.Q[n] = ar.take<double>((size_t)m.Ip[n] * m.bp);
     m.Z[n] = ar.take<double>((size_t)m.Ip[n] * m.bp);
-    m.A[n] = nullptr;
+    m.A[n] = cplx ? ar.take<double>((size_t)m.I[n] * m.R) : nullptr;
     m.blk0[n + 1] = m.blk0[n] + (m.Ip[n] / 64) * (m.bp / 16);
+    const size_t g2 = (size_t)m.I[n] * m.I[n];
+    if (g2 > gp) gp = g2;
   }
-  w.part = ar.take<double>(gram_part_doubles(s));
+  w.part = ar.take<double>(cplx ? gram_part_doubles_c(s) : gram_part_doubles(s));
   w.sigma = ar.take<double>(kMaxOrder);
   w.bad = ar.take<int>(64);
+  if (cplx) {
+    w.Gp = ar.take<double>(gp);
+    w.svr = ar.take<double>((size_t)s.N * m.R);
+  }
 }
 
-dgn_status check_svd_args(dgn_ctx* ctx, const Shape& s, int32_t R, int32_t block, int32_t iters) {
+dgn_status check_svd_args(dgn_ctx* ctx, const Shape& s, bool cplx, int32_t R, int32_t block, int32_t iters) {
   int mn = s.I[0];
   for (int n = 1; n < s.N; ++n) mn = s.I[n] < mn ? s.I[n] : mn;
-  if (R < 1 || R > DGN_MAX_RANK) return set_err(ctx, DGN_EINVAL, "rank must be in [1, 64]");
+  const int rmax = cplx ? kMaxRankC : DGN_MAX_RANK;
+  const int bmax = cplx ? kMaxSvdBlock / 2 : kMaxSvdBlock;
+  if (R < 1 || R > rmax) return set_err(ctx, DGN_EINVAL, cplx ? "complex tensors need rank in [1, 32]" : "rank must be in [1, 64]");
   if (R > mn) return set_err(ctx, DGN_EINVAL, "the SVD initialisation needs R <= every I_n");
-  if (block < R || block > mn || block > kMaxSvdBlock)
-    return set_err(ctx, DGN_EINVAL, "block must satisfy R <= block <= min(min_n I_n, 80)");
+  if (block < R || block > mn || block > bmax)
+    return set_err(ctx, DGN_EINVAL, "block must satisfy R <= block <= min(min_n I_n, 80; 40 for complex tensors)");
   if (iters < 0) return set_err(ctx, DGN_EINVAL, "iters must be >= 0");
   return DGN_OK;
 }
@@ -873,10 +887,10 @@ dgn_status dgn_workspace_size_svd(const dgn_tensor* Y, int32_t R, int32_t block,
   YType yt;
   dgn_status st = check_svd_tensor(nullptr, Y, R, &s, &yt);
   if (st != DGN_OK) return st;
-  if ((st = check_svd_args(nullptr, s, R, block, 0)) != DGN_OK) return st;
+  if ((st = check_svd_args(nullptr, s, is_complex(yt), R, block, 0)) != DGN_OK) return st;
   Arena ar{nullptr, (size_t)-1};
   SvdWork w{};
-  carve_svd(ar, s, R, block, w);
+  carve_svd(ar, s, R, block, is_complex(yt), w);
   *bytes = ar.used;
   return DGN_OK;
 }
@@ -889,13 +903,18 @@ dgn_status dgn_mode_gram(dgn_ctx* ctx, const dgn_tensor* Y, int32_t n, double* G
   if (st != DGN_OK) return st;
   if (n < 0 || n >= s.N) return set_err(ctx, DGN_EINVAL, "mode index out of range");
   if (!G) return set_err(ctx, DGN_EINVAL, "output pointer is NULL");
+  const bool cplx = is_complex(yt);
   Arena ar{ctx->ws, ctx->ws_size};
-  double* part = ar.take<double>(gram_part_doubles(s));
+  double* part = ar.take<double>(cplx ? gram_part_doubles_c(s) : gram_part_doubles(s));
+  double* Gp = cplx ? ar.take<double>((size_t)4 * s.I[n] * s.I[n]) : nullptr;
   if (ar.fail)
     return set_err(ctx, DGN_ENOMEM, "workspace budget too small: need " + std::to_string(ar.used) + " bytes");
   hipStream_t hs = (hipStream_t)stream;
   HIPCHK(hipSetDevice(ctx->device), "hipSetDevice");
-  HIPCHK(launch_mode_gram(s, n, Y->data, yt, part, G, s.I[n], s.I[n], hs), "mode gram");
+  if (cplx)
+    HIPCHK(launch_mode_gram_c(s, n, Y->data, yt, part, Gp, nullptr, 0, G, hs), "mode gram");
+  else
+    HIPCHK(launch_mode_gram(s, n, Y->data, yt, part, G, s.I[n], s.I[n], hs), "mode gram");
   return DGN_OK;
 }
 
@@ -906,21 +925,29 @@ dgn_status cp_svd_init(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, int32_t blo
   YType yt;
   dgn_status st = check_svd_tensor(ctx, Y, R, &s, &yt);
   if (st != DGN_OK) return st;
-  if ((st = check_svd_args(ctx, s, R, block, iters)) != DGN_OK) return st;
+  const bool cplx = is_complex(yt);
+  if ((st = check_svd_args(ctx, s, cplx, R, block, iters)) != DGN_OK) return st;
   if (!omega) return set_err(ctx, DGN_EINVAL, "start block pointer is NULL");
   if (!A) return set_err(ctx, DGN_EINVAL, "factor pointer array is NULL");
   for (int n = 0; n < s.N; ++n)
     if (!A[n]) return set_err(ctx, DGN_EINVAL, "NULL factor pointer");
   Arena ar{ctx->ws, ctx->ws_size};
   SvdWork w{};
-  carve_svd(ar, s, R, block, w);
+  carve_svd(ar, s, R, block, cplx, w);
   if (ar.fail)
     return set_err(ctx, DGN_ENOMEM, "workspace budget too small: need " + std::to_string(ar.used) + " bytes");
-  for (int n = 0; n < s.N; ++n) w.m.A[n] = (double*)A[n];
   hipStream_t hs = (hipStream_t)stream;
   HIPCHK(hipSetDevice(ctx->device), "hipSetDevice");
   HIPCHK(hipMemsetAsync(w.bad, 0, sizeof(int), hs), "memset");
-  HIPCHK(launch_svd_init(s, Y->data, yt, w.m, omega, iters, w.part, w.sigma, sv, w.bad, hs), "svd init");
+  if (cplx) {
+    CxFactors out{};
+    for (int n = 0; n < s.N; ++n) out.A[n] = (double*)A[n];
+    HIPCHK(launch_svd_init_c(s, Y->data, yt, w.m, out, w.Gp, omega, iters, w.part, w.sigma, w.svr, sv, w.bad, hs),
+           "svd init");
+  } else {
+    for (int n = 0; n < s.N; ++n) w.m.A[n] = (double*)A[n];
+    HIPCHK(launch_svd_init(s, Y->data, yt, w.m, omega, iters, w.part, w.sigma, sv, w.bad, hs), "svd init");
+  }
   int bad = 0;
   HIPCHK(hipMemcpyAsync(&bad, w.bad, sizeof bad, hipMemcpyDeviceToHost, hs), "copy");
   HIPCHK(hipStreamSynchronize(hs), "sync");

@@ -226,6 +226,22 @@ struct SvdModes {
 // columns in [I_n, lim) get zeros); part holds gram_part_doubles(s) doubles.
 hipError_t launch_mode_gram(const Shape& s, int n, const void* Y, YType yt, double* part, double* G, long long ld,
                             int lim, hipStream_t st);
+// Complex tensors: the Hermitian Gram from the real Gram of the interleaved
+// rows (Gp: (2 I_n)^2 doubles), into its real embedding E (2 I_n x 2 I_n,
+// leading dimension lde) and/or the interleaved complex Gc (I_n x I_n).
+GramPlan plan_gram_c(const Shape& s, int n);
+size_t gram_part_doubles_c(const Shape& s);
+hipError_t launch_mode_gram_c(const Shape& s, int n, const void* Y, YType yt, double* part, double* Gp,
+                              double* E, long long lde, double* Gc, hipStream_t st);
+struct CxFactors {
+  double* A[kMaxOrder];  // interleaved complex I_n x R outputs
+};
+// Complex SVD initialisation on the real embeddings: m describes the doubled
+// problem (I = 2 I_n, b = 2 block, R = 2 R, A = real scratch 2 I_n x 2 R),
+// svr N x 2R scratch; the complex factors go to out, sv (N x R) when not NULL.
+hipError_t launch_svd_init_c(const Shape& s, const void* Y, YType yt, SvdModes m, CxFactors out, double* Gp,
+                             const double* omega, int iters, double* part, double* sigma, double* svr, double* sv,
+                             int* bad, hipStream_t st);
 // The whole SVD initialisation; sigma: N doubles, sv: N x R or NULL, *bad
 // raised on a Cholesky breakdown of the orthonormalisation.
 hipError_t launch_svd_init(const Shape& s, const void* Y, YType yt, SvdModes m, const double* omega, int iters,

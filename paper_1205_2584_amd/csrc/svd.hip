@@ -83,7 +83,7 @@ __device__ __forceinline__ void mma_chunk128(const double* Ti, const double* Tj,
 // logical blocks that share a split (and its row blocks of Y) sit on one XCD.
 // part[(split * ntile + tile) * GT^2 + c + GT r] = sum over the split's chunks
 // of Y(., GT ti + r, .) Y(., GT tj + c, .).  Diagonal tiles stage one operand.
-template <typename T, bool KR>
+template <typename T, bool KR, bool CX>
 __device__ __forceinline__ void gram_tile(const T* __restrict__ Y, const GramPlan& g, double* __restrict__ part,
                                           int tile, long long split, double* lds) {
   int ti, tj;
@@ -113,7 +113,7 @@ __device__ __forceinline__ void gram_tile(const T* __restrict__ Y, const GramPla
         vi[s] = (okq && i < g.I) ? yi[s * step] : T(0);
         if (!diag) vj[s] = (okq && j < g.I) ? yj[s * step] : T(0);
       }
-    } else {  // the chunk runs along p, contiguous for each row
+    } else if (!CX) {  // the chunk runs along p, contiguous for each row
       const long long q = c / cpq;
       const long long p0 = (c - q * cpq) * GK;
       const bool okp = p0 + k0 < g.P;
@@ -125,6 +125,18 @@ __device__ __forceinline__ void gram_tile(const T* __restrict__ Y, const GramPla
       for (int s = 0; s < NS; ++s) {
         vi[s] = (okp && i + 8 * s < g.I) ? yi[s * step] : T(0);
         if (!diag) vj[s] = (okp && j + 8 * s < g.I) ? yj[s * step] : T(0);
+      }
+    } else {  // complex, interleaved (re, im): row 2 i + c is part c of complex row i
+      const long long q = c / cpq;
+      const long long p0 = (c - q * cpq) * GK;
+      const bool okp = p0 + k0 < g.P;
+      const long long Ic = g.I >> 1;
+      const T* yq = Y + 2 * (p0 + k0 + g.P * Ic * q);
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const int ri = ti * GT + r0 + 8 * s, rj = tj * GT + r0 + 8 * s;
+        vi[s] = (okp && ri < g.I) ? yq[(ri & 1) + 2 * g.P * (long long)(ri >> 1)] : T(0);
+        if (!diag) vj[s] = (okp && rj < g.I) ? yq[(rj & 1) + 2 * g.P * (long long)(rj >> 1)] : T(0);
       }
     }
   };
@@ -160,13 +172,39 @@ __device__ __forceinline__ void gram_tile(const T* __restrict__ Y, const GramPla
       }
 }
 
-template <typename T, bool KR>
+template <typename T, bool KR, bool CX = false>
 __global__ __launch_bounds__(256, 2) void k_mode_gram(const T* __restrict__ Y, GramPlan g, double* __restrict__ part) {
   __shared__ double lds[2 * GOP];
   const long long per_xcd = gridDim.x / 8;
   const long long L = (long long)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
   if (L >= (long long)g.ntile * g.S) return;
-  gram_tile<T, KR>(Y, g, part, (int)(L % g.ntile), L / g.ntile, lds);
+  gram_tile<T, KR, CX>(Y, g, part, (int)(L % g.ntile), L / g.ntile, lds);
+}
+
+// The Hermitian G = Y_(n) Y_(n)^H from the real Gram G' of the interleaved rows
+// (row 2 i + c = part c of row i): G_re = G'[2i][2j] + G'[2i+1][2j+1],
+// G_im = G'[2i+1][2j] - G'[2i][2j+1].  E (leading dimension lde) receives the
+// real symmetric embedding [[G_re, -G_im], [G_im, G_re]] (2I x 2I), Gc (when
+// not NULL, leading dimension I) the interleaved complex G.
+__global__ __launch_bounds__(256) void k_hermitian(const double* __restrict__ Gp, long long ldg, int I,
+                                                   double* __restrict__ E, long long lde,
+                                                   double* __restrict__ Gc) {
+  const long long total = (long long)I * I;
+  for (long long e = blockIdx.x * 256LL + threadIdx.x; e < total; e += (long long)gridDim.x * 256) {
+    const int i = (int)(e % I), j = (int)(e / I);
+    const double gre = Gp[2 * i + ldg * (2 * j)] + Gp[2 * i + 1 + ldg * (2 * j + 1)];
+    const double gim = Gp[2 * i + 1 + ldg * (2 * j)] - Gp[2 * i + ldg * (2 * j + 1)];
+    if (E) {
+      E[i + lde * j] = gre;
+      E[i + lde * (I + j)] = -gim;
+      E[I + i + lde * j] = gim;
+      E[I + i + lde * (I + j)] = gre;
+    }
+    if (Gc) {
+      Gc[2 * (i + (long long)I * j)] = gre;
+      Gc[2 * (i + (long long)I * j) + 1] = gim;
+    }
+  }
 }
 
 // G[gr + ld gc] = G[gc + ld gr] = sum over splits (in order) of the partial
@@ -209,6 +247,74 @@ __global__ __launch_bounds__(256) void k_svd_load(SvdModes m, const double* __re
     const int i = (int)(e % Ip), c = (int)(e / Ip);
     m.Z[n][e] = (i < I && c < m.b) ? omega[off + i + (long long)I * c] : 0.0;
     m.Q[n][e] = 0.0;
+  }
+}
+
+// Complex tensors: Z_n = the real embedding [[W_re, -W_im], [W_im, W_re]] of the
+// complex start block W (I_c x b_c, interleaved, modes stacked) in the 2 I_c x
+// 2 b_c leading part of the Ip x bp block, zeros elsewhere; Q_n = 0.
+__global__ __launch_bounds__(256) void k_svd_load_c(SvdModes m, const double* __restrict__ omega) {
+  const int n = blockIdx.y;
+  const int Ip = m.Ip[n], Ic = m.I[n] / 2, bc = m.b / 2;
+  long long off = 0;
+  for (int k = 0; k < n; ++k) off += (long long)(m.I[k] / 2) * bc;
+  const long long total = (long long)Ip * m.bp;
+  for (long long e = blockIdx.x * 256LL + threadIdx.x; e < total; e += (long long)gridDim.x * 256) {
+    const int i = (int)(e % Ip), c = (int)(e / Ip);
+    double v = 0.0;
+    if (i < 2 * Ic && c < 2 * bc) {
+      const int ii = i % Ic, cc = c % bc, bi = i / Ic, bc2 = c / bc;
+      const double* w = omega + 2 * (off + ii + (long long)Ic * cc);
+      v = bi == bc2 ? w[0] : (bi == 1 ? w[1] : -w[1]);
+    }
+    m.Z[n][e] = v;
+    m.Q[n][e] = 0.0;
+  }
+}
+
+// Complex tensors: the real Ritz vectors of the embedding come in pairs (both
+// for one complex singular value); column 2r = [a; b] gives u_r = a + i b,
+// scaled by the unit factor that makes its largest-magnitude entry (the first
+// on ties) real and positive.  One block per mode, wave w takes r = w, w + 4, ...
+__global__ __launch_bounds__(256) void k_svd_complexify(SvdModes m, int R, CxFactors out,
+                                                        const double* __restrict__ svr, double* sv) {
+  const int n = blockIdx.x, Ic = m.I[n] / 2, I2 = m.I[n];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const double* V = m.A[n];
+  double* A = out.A[n];
+  for (int r = w; r < R; r += 4) {
+    const double* v = V + (long long)I2 * (2 * r);
+    double best = -1.0, bre = 0.0, bim = 0.0;
+    int bi = 0x7fffffff;
+    for (int i = lane; i < Ic; i += 64) {
+      const double re = v[i], im = v[Ic + i];
+      const double a = sqrt(re * re + im * im);
+      if (a > best) {
+        best = a;
+        bre = re;
+        bim = im;
+        bi = i;
+      }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ob = __shfl_xor(best, o, 64), ore = __shfl_xor(bre, o, 64), oim = __shfl_xor(bim, o, 64);
+      const int oi = __shfl_xor(bi, o, 64);
+      if (ob > best || (ob == best && oi < bi)) {
+        best = ob;
+        bre = ore;
+        bim = oim;
+        bi = oi;
+      }
+    }
+    // phase = conj(u_k) / |u_k|
+    const double pr = best > 0.0 ? bre / best : 1.0, pi = best > 0.0 ? -bim / best : 0.0;
+    for (int i = lane; i < Ic; i += 64) {
+      const double re = v[i], im = v[Ic + i];
+      A[2 * (i + (long long)Ic * r)] = re * pr - im * pi;
+      A[2 * (i + (long long)Ic * r) + 1] = re * pi + im * pr;
+    }
+    if (sv && lane == 0) sv[n * R + r] = svr[n * 2 * R + 2 * r];
   }
 }
 
@@ -613,13 +719,18 @@ hipError_t launch_mode_gram(const Shape& s, int n, const void* Y, YType yt, doub
   return hipGetLastError();
 }
 
-hipError_t launch_svd_init(const Shape& s, const void* Y, YType yt, SvdModes m, const double* omega, int iters,
-                           double* part, double* sigma, double* sv, int* bad, hipStream_t st) {
+namespace {
+
+// Shift, start block, orthonormalisation, iterations and Rayleigh-Ritz on the
+// Grams already in m.G (real, or the embeddings of complex ones).
+hipError_t svd_iterate(SvdModes m, bool cplx, const double* omega, int iters, double* sigma, double* sv, int* bad,
+                       hipStream_t st) {
   hipError_t e;
-  for (int n = 0; n < s.N; ++n)
-    if ((e = launch_mode_gram(s, n, Y, yt, part, m.G[n], m.Ip[n], m.Ip[n], st)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_svd_shift, dim3(m.N), dim3(256), 0, st, m, sigma);
-  hipLaunchKernelGGL(k_svd_load, dim3(64, m.N), dim3(256), 0, st, m, omega);
+  if (cplx)
+    hipLaunchKernelGGL(k_svd_load_c, dim3(64, m.N), dim3(256), 0, st, m, omega);
+  else
+    hipLaunchKernelGGL(k_svd_load, dim3(64, m.N), dim3(256), 0, st, m, omega);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if ((e = orth_or_rr(m, false, sigma, sv, bad, st)) != hipSuccess) return e;
   for (int it = 0; it < iters; ++it) {
@@ -630,6 +741,81 @@ hipError_t launch_svd_init(const Shape& s, const void* Y, YType yt, SvdModes m, 
   hipLaunchKernelGGL(k_gq, dim3(m.blk0[m.N]), dim3(256), 0, st, m, sigma);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   return orth_or_rr(m, true, sigma, sv, bad, st);
+}
+
+}  // namespace
+
+hipError_t launch_svd_init(const Shape& s, const void* Y, YType yt, SvdModes m, const double* omega, int iters,
+                           double* part, double* sigma, double* sv, int* bad, hipStream_t st) {
+  hipError_t e;
+  for (int n = 0; n < s.N; ++n)
+    if ((e = launch_mode_gram(s, n, Y, yt, part, m.G[n], m.Ip[n], m.Ip[n], st)) != hipSuccess) return e;
+  return svd_iterate(m, false, omega, iters, sigma, sv, bad, st);
+}
+
+GramPlan plan_gram_c(const Shape& s, int n) {
+  GramPlan g = plan_gram(s, n);  // P, Q, chunks in complex elements
+  g.I = 2 * s.I[n];              // rows: (re, im) parts of each complex row
+  const int nt = (g.I + GT - 1) / GT;
+  g.ntile = nt * (nt + 1) / 2;
+  long long S = 512 / g.ntile;
+  if (S > g.nchunk) S = g.nchunk;
+  if (S < 1) S = 1;
+  g.cps = (g.nchunk + S - 1) / S;
+  g.S = (int)((g.nchunk + g.cps - 1) / g.cps);
+  return g;
+}
+
+size_t gram_part_doubles_c(const Shape& s) {
+  size_t mx = 0;
+  for (int n = 0; n < s.N; ++n) {
+    const GramPlan g = plan_gram_c(s, n);
+    const size_t d = (size_t)g.S * g.ntile * GT * GT;
+    if (d > mx) mx = d;
+  }
+  return mx;
+}
+
+hipError_t launch_mode_gram_c(const Shape& s, int n, const void* Y, YType yt, double* part, double* Gp,
+                              double* E, long long lde, double* Gc, hipStream_t st) {
+  const GramPlan g = plan_gram_c(s, n);
+  const long long blocks = (long long)g.ntile * g.S;
+  const unsigned grid = (unsigned)((blocks + 7) / 8 * 8);
+  // mode 1: the interleaved rows of a chunk are contiguous, the real kernel applies
+  const bool kr = g.P == 1;
+  switch (yt) {
+    case YType::C128:
+      if (kr) hipLaunchKernelGGL((k_mode_gram<double, true>), dim3(grid), dim3(256), 0, st, (const double*)Y, g, part);
+      else hipLaunchKernelGGL((k_mode_gram<double, false, true>), dim3(grid), dim3(256), 0, st, (const double*)Y, g, part);
+      break;
+    case YType::C64:
+      if (kr) hipLaunchKernelGGL((k_mode_gram<float, true>), dim3(grid), dim3(256), 0, st, (const float*)Y, g, part);
+      else hipLaunchKernelGGL((k_mode_gram<float, false, true>), dim3(grid), dim3(256), 0, st, (const float*)Y, g, part);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_gram_reduce, dim3(g.ntile * (GT * GT / 256)), dim3(256), 0, st, part, g.S, g.ntile, Gp,
+                     (long long)g.I, g.I);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_hermitian, dim3(256), dim3(256), 0, st, Gp, (long long)g.I, s.I[n], E, lde, Gc);
+  return hipGetLastError();
+}
+
+hipError_t launch_svd_init_c(const Shape& s, const void* Y, YType yt, SvdModes m, CxFactors out, double* Gp,
+                             const double* omega, int iters, double* part, double* sigma, double* svr, double* sv,
+                             int* bad, hipStream_t st) {
+  hipError_t e;
+  for (int n = 0; n < s.N; ++n) {
+    // the embedding fills 2 I_n x 2 I_n; its padding to Ip must be zero
+    if ((e = hipMemsetAsync(m.G[n], 0, sizeof(double) * m.Ip[n] * m.Ip[n], st)) != hipSuccess) return e;
+    if ((e = launch_mode_gram_c(s, n, Y, yt, part, Gp, m.G[n], m.Ip[n], nullptr, st)) != hipSuccess) return e;
+  }
+  if ((e = svd_iterate(m, true, omega, iters, sigma, svr, bad, st)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_svd_complexify, dim3(m.N), dim3(256), 0, st, m, m.R / 2, out, svr, sv);
+  return hipGetLastError();
 }
 
 }  // namespace dgn

@@ -270,20 +270,23 @@ class Context:
         d = tensor_desc(y, dims)
         G = None
         if 0 <= int(n) < len(dims):
-            G = torch.empty((int(dims[n]), int(dims[n])), dtype=torch.float64, device=y.device)
+            gt = torch.complex128 if y.dtype.is_complex else torch.float64
+            G = torch.empty((int(dims[n]), int(dims[n])), dtype=gt, device=y.device)
         self._check(self.L.dgn_mode_gram(self.h, ctypes.byref(d), int(n),
                                          ctypes.c_void_p(G.data_ptr() if G is not None else 0), _stream()))
         return G
 
     def cp_svd_init(self, y, dims, R, block, omega, iters):
         """Leading R left singular vectors of every unfolding; returns (factors, sv):
-        factors[n] of shape (R, I_n) (column-major I_n x R), sv of shape (N, R).
-        omega: float64 device tensor of sum_n I_n * block random start entries."""
+        factors[n] of shape (R, I_n) (column-major I_n x R; complex128 for complex
+        tensors), sv of shape (N, R).  omega: device tensor of sum_n I_n * block
+        random start entries (float64, complex128 for complex tensors)."""
         d = tensor_desc(y, dims)
         need = sum(int(I) for I in dims) * int(block)
-        if omega.dtype != torch.float64 or not omega.is_cuda or not omega.is_contiguous() or omega.numel() != need:
-            raise ValueError(f"omega must be a contiguous float64 device tensor of {need} entries")
-        A = [torch.empty((int(R), int(I)), dtype=torch.float64, device=y.device) for I in dims]
+        ft = torch.complex128 if y.dtype.is_complex else torch.float64
+        if omega.dtype != ft or not omega.is_cuda or not omega.is_contiguous() or omega.numel() != need:
+            raise ValueError(f"omega must be a contiguous {ft} device tensor of {need} entries")
+        A = [torch.empty((int(R), int(I)), dtype=ft, device=y.device) for I in dims]
         sv = torch.empty((len(dims), int(R)), dtype=torch.float64, device=y.device)
         self._check(self.L.cp_svd_init(self.h, ctypes.byref(d), int(R), int(block),
                                        ctypes.c_void_p(omega.data_ptr()), int(iters), _ptrs(A),

@@ -231,9 +231,15 @@ def test_svd_init_rejects_bad_arguments():
         with pytest.raises(ValueError):
             ctx.cp_svd_init(y, dims, 3, 4, omega[:-1], 3)
         yc = torch.zeros(10 * 12 * 14, dtype=torch.complex128, device="cuda")
-        with pytest.raises(dgn.DgnError) as e:
+        omc = torch.zeros(sum(dims) * 4, dtype=torch.complex128, device="cuda")
+        with pytest.raises(ValueError):  # complex tensors take complex start blocks
             ctx.cp_svd_init(yc, dims, 3, 4, omega, 3)
+        with pytest.raises(dgn.DgnError) as e:  # complex: block <= 40 would be needed, rank <= 32
+            ctx.cp_svd_init(yc, dims, 33, 4, omc, 3)
         assert e.value.status == -1
+        with pytest.raises(dgn.DgnError) as e:  # a zero complex tensor breaks the orthonormalisation too
+            ctx.cp_svd_init(yc, dims, 3, 4, omc, 3)
+        assert e.value.status == -3
         with pytest.raises(dgn.DgnError) as e:
             ctx.mode_gram(y, dims, 3)
         assert e.value.status == -1
@@ -303,5 +309,94 @@ def test_svd_init_full_size_500cube():
                 row = Yn @ Yn[i]
                 d = np.sqrt(np.sum(Yn * Yn, axis=1))
                 assert np.all(np.abs(Gd[i] - row) <= 2 * g * d[i] * d + 1e-300), (n, i)
+    finally:
+        ctx.close()
+
+
+# ---- complex tensors (Section 5) ----------------------------------------------
+
+
+def _problem_c(seed, dims, R, snr_db=40.0, spread=1.5):
+    rng = np.random.default_rng(seed)
+    F = [rng.standard_normal((int(I), R)) + 1j * rng.standard_normal((int(I), R)) for I in dims]
+    lam = 10.0 ** (-spread * np.arange(R) / max(R, 1))
+    y = synth.cp_tensor(F, lam)
+    if snr_db is not None:
+        y, _ = synth.add_noise(rng, y, snr_db)
+    return y
+
+
+def _device_tensor_c(y, name):
+    t = torch.from_numpy(np.ascontiguousarray(y, dtype=np.complex128))
+    if name == "c64":
+        t = t.to(torch.complex64)
+    return t.cuda(), t.to(torch.complex128).numpy()
+
+
+@pytest.mark.parametrize("dims,dt", [((40, 30, 20), "c128"), ((3, 70, 40), "c128"), ((130, 9, 33), "c64"),
+                                     ((12, 10, 9, 7), "c128")])
+def test_mode_gram_complex_matches_oracle(dims, dt):
+    dgn = _dgn()
+    y = _problem_c(71 + len(dims), dims, 3)
+    yd, y64 = _device_tensor_c(y, dt)
+    Y = cp.as_tensor(y64, dims)
+    ctx = dgn.Context(0, 96 << 20)
+    try:
+        for n in range(len(dims)):
+            print(f"mode_gram complex dims={dims} dtype={dt} n={n}", flush=True)
+            G = ctx.mode_gram(yd, dims, n).cpu().numpy().T  # (I, I) row-major view of a column-major matrix
+            Yn = cp.unfold(Y, n)
+            W = Yn @ Yn.conj().T
+            # each real and imaginary part sums 2K real products
+            assert np.all(np.abs(G - W) <= 2 * _gram_tol(W.real, 2 * Yn.shape[1])), n
+            assert np.array_equal(G, G.conj().T)
+    finally:
+        ctx.close()
+
+
+SVD_CASES_C = [
+    ((40, 30, 20), 4, 10, 40, "c128"),
+    ((3, 70, 40), 3, 3, 20, "c128"),
+    ((50, 45, 30), 6, 16, 40, "c64"),
+    ((12, 10, 9, 8), 3, 8, 40, "c128"),
+]
+
+
+@pytest.mark.parametrize("dims,R,block,iters,dt", SVD_CASES_C)
+def test_svd_init_complex_matches_oracle(dims, R, block, iters, dt):
+    dgn = _dgn()
+    y = _problem_c(91 + R, dims, R)
+    yd, y64 = _device_tensor_c(y, dt)
+    Y = cp.as_tensor(y64, dims)
+    omega = torch.from_numpy(synth.svd_start_block_complex(np.random.default_rng(5 + R), dims, block)).cuda()
+    ctx = dgn.Context(0, dgn.workspace_size_svd(dims, R, block, torch.complex128))
+    try:
+        print(f"svd_init complex dims={dims} R={R} block={block} dtype={dt}", flush=True)
+        A, sv = ctx.cp_svd_init(yd, dims, R, block, omega, iters)
+        got = dgn.to_host_factors(A)
+        svh = sv.cpu().numpy()
+        want, S = cp.svd_init(Y, R)
+        for n, (a, u) in enumerate(zip(got, want)):
+            Yn = cp.unfold(Y, n)
+            lam_all = np.linalg.svd(Yn, compute_uv=False) ** 2
+            I, K = Yn.shape
+            g = 2 * K * U64 / (1 - 2 * K * U64)
+            tr = float(np.sum(lam_all))
+            noise = 2 * 2 * g * tr + 1e2 * (2 * block + 2 * I) * U64 * lam_all[0]
+            sig = 1e-7 * 2 * tr
+            assert np.linalg.norm(a.conj().T @ a - np.eye(R)) < 1e-12 * R
+            for r in range(R):
+                gaps = [lam_all[r] - lam_all[r + 1] if r + 1 < len(lam_all) else lam_all[r]]
+                if r > 0:
+                    gaps.append(lam_all[r - 1] - lam_all[r])
+                gap = max(min(gaps), 1e-300)
+                lam_next = lam_all[block] if block < len(lam_all) else 0.0
+                trunc = ((lam_next + sig) / (lam_all[r] + sig)) ** iters if block < I else 0.0
+                tol = np.sqrt(2) * noise / gap + 1e3 * trunc
+                assert tol < 1e-4, (n, r, tol)
+                assert np.linalg.norm(a[:, r] - u[:, r]) <= tol, (n, r, np.linalg.norm(a[:, r] - u[:, r]), tol)
+                assert abs(svh[n, r] ** 2 - S[n][r] ** 2) <= noise + 1e3 * lam_all[r] * trunc ** 2
+                k = int(np.argmax(np.abs(a[:, r])))
+                assert abs(a[k, r].imag) <= 1e-14 * abs(a[k, r]) and a[k, r].real > 0
     finally:
         ctx.close()
