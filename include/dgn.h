@@ -201,14 +201,17 @@ dgn_status dgn_step(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, const void* co
  * representation: the R x R inverses (Gamma^(n) + mu I)^-1 and the NR^2
  * system, never the RT x RT inverse), with J the Jacobian of the CP model at the
  * factors A (Lemma B.1) -- dgn_step is this call with V = the gradient.  order,
- * dims: the mode sizes; A: N device pointers to I_n x R FP64 factors; V, X: N
- * device pointers to I_n x R FP64 column-major blocks (the parameter vector in
- * blocks, as the factors are; X may not alias V).  Real factors only; mu > 0;
- * opts->solver selects the direct or the iterative NR^2 solve as for dgn_step.
+ * dims: the mode sizes; dtype: DGN_F64, or DGN_C128 for complex factors
+ * (Section 5: (J^H J + mu I)^-1, factors and blocks interleaved complex128);
+ * A: N device pointers to I_n x R factors; V, X: N device pointers to I_n x R
+ * column-major blocks (the parameter vector in blocks, as the factors are; X
+ * may not alias V).  mu > 0; opts->solver selects the direct or the iterative
+ * NR^2 solve as for dgn_step (real factors).
  * Workspace as dgn_workspace_size for an F64 tensor of these sizes.
  * Synchronises the stream before returning. */
-dgn_status dgn_hessian_solve(dgn_ctx* ctx, int32_t order, const int64_t* dims, int32_t R, const void* const* A,
-                             const void* const* V, void* const* X, double mu, const dgn_opts* opts, void* stream);
+dgn_status dgn_hessian_solve(dgn_ctx* ctx, int32_t order, const int64_t* dims, int32_t R, int32_t dtype,
+                             const void* const* A, const void* const* V, void* const* X, double mu,
+                             const dgn_opts* opts, void* stream);
 
 /* The plain damped Gauss-Newton step of Section 3 with the Hessian formed
  * explicitly: (J^T J + mu I) da = J^T vec(Y - Y_hat), J^T J of size RT x RT

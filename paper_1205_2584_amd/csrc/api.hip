@@ -286,7 +286,7 @@ hipError_t enqueue_step_c(Work& w, bool resid, double mu_host, FitState* state, 
   if ((e = mark(ev, 2, st)) != hipSuccess) return e;
   if ((e = launch_sys_factor_solve(s, w.sp, w.sb, w.sy, singular, stop, st)) != hipSuccess) return e;
   if ((e = mark(ev, 3, st)) != hipSuccess) return e;
-  return launch_small_post_c(s, w.A, w.Ac, w.sb, mu_host, state, stop, st);
+  return launch_small_post_c(s, w.A, w.Ac, w.sb, mu_host, state, stop, st, w.da_out);
 }
 
 hipError_t enqueue_step(Work& w, bool resid, double mu_host, FitState* state, int* singular,
@@ -531,8 +531,9 @@ dgn_status dgn_step(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, const void* co
   return DGN_OK;
 }
 
-dgn_status dgn_hessian_solve(dgn_ctx* ctx, int32_t order, const int64_t* dims, int32_t R, const void* const* A,
-                             const void* const* V, void* const* X, double mu, const dgn_opts* opts, void* stream) {
+dgn_status dgn_hessian_solve(dgn_ctx* ctx, int32_t order, const int64_t* dims, int32_t R, int32_t dtype,
+                             const void* const* A, const void* const* V, void* const* X, double mu,
+                             const dgn_opts* opts, void* stream) {
   if (!ctx) return DGN_EINVAL;
   if (!dims || !A || !V || !X) return set_err(ctx, DGN_EINVAL, "NULL dims or pointer array");
   if (!(mu > 0.0) || !isfinite(mu)) return set_err(ctx, DGN_EINVAL, "mu must be finite and > 0");
@@ -543,12 +544,13 @@ dgn_status dgn_hessian_solve(dgn_ctx* ctx, int32_t order, const int64_t* dims, i
   if (o.solver == DGN_SOLVER_AUTO && (o.cg_max_iters < 0 || !(o.cg_tol > 0.0)))
     return set_err(ctx, DGN_EINVAL, "need cg_max_iters >= 0 and cg_tol > 0");
   if (order < 3 || order > DGN_MAX_ORDER) return set_err(ctx, DGN_EINVAL, "order must be in [3, 8]");
-  // the system depends on the factors only: plan it as for an FP64 tensor of
-  // these sizes, whose data is never read
+  if (dtype != DGN_F64 && dtype != DGN_C128) return set_err(ctx, DGN_EINVAL, "dtype must be DGN_F64 or DGN_C128");
+  // the system depends on the factors only: plan it as for an FP64 (complex128)
+  // tensor of these sizes, whose data is never read
   dgn_tensor t{};
   t.order = order;
   for (int n = 0; n < order; ++n) t.dims[n] = dims[n];
-  t.dtype = DGN_F64;
+  t.dtype = dtype;
   t.data = &t;
   Work w{};
   dgn_status rc = prepare(ctx, &t, R, true, w);

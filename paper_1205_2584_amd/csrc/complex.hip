@@ -696,7 +696,7 @@ __global__ __launch_bounds__(256) void k_fq_c(Shape s, const cd* C, const cd* u,
 // sum Re(conj(da) (g + mu da)) and sum |da|^2.
 __global__ __launch_bounds__(256) void k_update_c(Shape s, const cd* A, const cd* P, const cd* G, const cd* Q,
                                                   double mu_host, const FitState* state, cd* Ac, double* part,
-                                                  int chunks, int stride, const int* stop) {
+                                                  int chunks, int stride, cd* da_out, const int* stop) {
   if (stopped(stop)) return;
   __shared__ cd As[64][LC];
   __shared__ cd Qs[kMaxRankC][LC];
@@ -729,6 +729,7 @@ __global__ __launch_bounds__(256) void k_update_c(Shape s, const cd* A, const cd
       const cd da = P[gi] - acc;
       v = As[ii][r] + da;
       Ac[gi] = v;
+      if (da_out) da_out[gi] = da;
       const cd gm = G[gi] + mu * da;
       den += da.x * gm.x + da.y * gm.y;  // Re(conj(da) (g + mu da))
       da2 += abs2(da);
@@ -920,7 +921,7 @@ hipError_t launch_subblock_c(const Shape& s, const SysPlan& p, const SmallBuffer
 }
 
 hipError_t launch_small_post_c(const Shape& s, const double* A, double* Ac, const SmallBuffers& b, double mu_host,
-                               const FitState* state, const int* stop, hipStream_t st) {
+                               const FitState* state, const int* stop, hipStream_t st, double* da_out) {
   const int ch = row_chunks(s), stride = part_stride_c(s);
   k_u_c<<<s.N, 256, 0, st>>>(s, reinterpret_cast<const cd*>(b.w), b.y, reinterpret_cast<const cd*>(b.X),
                               reinterpret_cast<const cd*>(b.Lc), reinterpret_cast<cd*>(b.u), stop);
@@ -929,7 +930,8 @@ hipError_t launch_small_post_c(const Shape& s, const double* A, double* Ac, cons
                                reinterpret_cast<cd*>(b.Q), stop);
   k_update_c<<<dim3(s.N, ch), 256, 0, st>>>(s, reinterpret_cast<const cd*>(A), reinterpret_cast<const cd*>(b.P),
                                              reinterpret_cast<const cd*>(b.G), reinterpret_cast<const cd*>(b.Q),
-                                             mu_host, state, reinterpret_cast<cd*>(Ac), b.rowpart, ch, stride, stop);
+                                             mu_host, state, reinterpret_cast<cd*>(Ac), b.rowpart, ch, stride,
+                                             reinterpret_cast<cd*>(da_out), stop);
   k_rows_reduce_c<<<s.N, 256, 0, st>>>(b.rowpart, ch, stride, 2 * s.R * s.R, b.Cc, stop);
   k_scalars_reduce_c<<<1, 64, 0, st>>>(b.rowpart, s.N, ch, stride, s.R * s.R, b.scal, stop);
   return hipGetLastError();

@@ -143,7 +143,7 @@ hipError_t launch_small_pre_c(const Shape& s, const double* A, const double* M, 
 hipError_t launch_subblock_c(const Shape& s, const SysPlan& p, const SmallBuffers& b, const SysBuffers& y,
                              const int* stop, hipStream_t st);
 hipError_t launch_small_post_c(const Shape& s, const double* A, double* Ac, const SmallBuffers& b,
-                               double mu_host, const FitState* state, const int* stop, hipStream_t st);
+                               double mu_host, const FitState* state, const int* stop, hipStream_t st, double* da_out = nullptr);
 // Gamma_n, the Cholesky of Gamma_n + mu I and Gt_n = (Gamma_n + mu I)^-1 for every mode (complex).
 hipError_t launch_gamma_c(const Shape& s, const double* C, double mu_host, const FitState* state,
                           const SmallBuffers& b, int* singular, const int* stop, hipStream_t st);

@@ -115,7 +115,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.cp_als.argtypes = [vp, ctypes.POINTER(dgn_tensor), i32, ctypes.POINTER(vp), i32,
                          ctypes.POINTER(dgn_opts), ctypes.POINTER(dbl), vp]
     L.dgn_mode_gram.argtypes = [vp, ctypes.POINTER(dgn_tensor), i32, vp, vp]
-    L.dgn_hessian_solve.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int64), i32, ctypes.POINTER(vp),
+    L.dgn_hessian_solve.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int64), i32, i32, ctypes.POINTER(vp),
                                     ctypes.POINTER(vp), ctypes.POINTER(vp), dbl, ctypes.POINTER(dgn_opts), vp]
     L.cp_svd_init.argtypes = [vp, ctypes.POINTER(dgn_tensor), i32, i32, vp, i32, ctypes.POINTER(vp), vp, vp]
     L.dgn_workspace_size_svd.argtypes = [ctypes.POINTER(dgn_tensor), i32, i32, ctypes.POINTER(ctypes.c_size_t)]
@@ -257,11 +257,12 @@ class Context:
         return err2.value
 
     def hessian_solve(self, dims, R, factors, V, mu, options: dgn_opts | None = None):
-        """X = (J^T J + mu I)^-1 vec(V) at the factors; V and the result are (R, I_n)
-        float64 device tensors (column-major I_n x R blocks)."""
+        """X = (J^H J + mu I)^-1 vec(V) at the factors; V and the result are (R, I_n)
+        float64 (complex128 for complex factors) device tensors (column-major I_n x R blocks)."""
         X = [torch.empty_like(v) for v in V]
         d = (ctypes.c_int64 * len(dims))(*[int(v) for v in dims])
-        self._check(self.L.dgn_hessian_solve(self.h, len(dims), d, int(R), _ptrs(factors), _ptrs(V), _ptrs(X),
+        dt = _DTYPE[torch.complex128] if factors[0].dtype.is_complex else _DTYPE[torch.float64]
+        self._check(self.L.dgn_hessian_solve(self.h, len(dims), d, int(R), dt, _ptrs(factors), _ptrs(V), _ptrs(X),
                                              float(mu), ctypes.byref(options) if options else None, _stream()))
         return X
 

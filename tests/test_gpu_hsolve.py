@@ -111,3 +111,24 @@ def test_hessian_solve_rejects_bad_arguments():
         assert e.value.status == -1
     finally:
         ctx.close()
+
+
+@pytest.mark.parametrize("dims,R,mu", [((9, 8, 7), 3, 1.0), ((7, 6, 5, 4), 2, 0.5)])
+def test_hessian_solve_complex_matches_explicit_solve(dims, R, mu):
+    # Section 5: (J^H J + mu I)^-1 v with the complex Jacobian of Lemma B.1
+    dgn = _dgn()
+    p = cpgen.small_problem(520 + R, dims, R, c=0.4, complex_=True)
+    A = p.init
+    rng = np.random.default_rng(19 + R)
+    V = [rng.standard_normal((I, R)) + 1j * rng.standard_normal((I, R)) for I in dims]
+    J = brute.jacobian(A)
+    H = J.conj().T @ J + mu * np.eye(J.shape[1])
+    want = np.linalg.solve(H, brute.param_vec(V))
+    ctx = dgn.Context(0, dgn.workspace_size(dims, R, torch.complex128) + (16 << 20))
+    try:
+        print(f"hessian_solve complex dims={dims} R={R} mu={mu}", flush=True)
+        X = ctx.hessian_solve(dims, R, dgn.to_device_factors(A), dgn.to_device_factors(V), mu)
+        got = brute.param_vec(dgn.to_host_factors(X))
+        assert _rel(got, want) < 1e-9, _rel(got, want)
+    finally:
+        ctx.close()
