@@ -92,3 +92,35 @@ def test_workspace_size_complex(lib):
     assert dgn.workspace_size((40, 30, 20), 32, torch.complex64) > 0
     with pytest.raises(dgn.DgnError):
         dgn.workspace_size((40, 30, 20), 33, torch.complex64)
+
+
+def test_opts_solver_defaults(lib):
+    from paper_1205_2584_amd import dgn
+    o = dgn.opts()
+    assert o.solver == 0 and o.cg_max_iters == 100 and o.cg_tol == 1e-10 and o.als_sweeps == 0
+
+
+@pytest.mark.parametrize("dims,R,block,dtype,ok", [
+    ((500, 500, 500), 30, 48, "f32", True),
+    ((10, 12, 14), 3, 10, "f64", True),
+    ((10, 12, 14), 3, 11, "f64", False),     # block > min I_n
+    ((100, 100, 100), 30, 81, "f64", False),  # block > 80
+    ((10, 12, 14), 11, 11, "f64", False),     # R > min I_n
+    ((10, 12, 14), 4, 3, "f64", False),       # block < R
+    ((60, 50, 40), 20, 40, "c128", True),
+    ((60, 50, 40), 20, 41, "c128", False),    # complex: block <= 40
+    ((60, 50, 40), 33, 40, "c64", False),     # complex: R <= 32
+])
+def test_workspace_size_svd_validates(lib, dims, R, block, dtype, ok):
+    from paper_1205_2584_amd import dgn
+    torch = dgn.torch
+    dt = {"f32": torch.float32, "f64": torch.float64, "c128": torch.complex128, "c64": torch.complex64}[dtype]
+    if ok:
+        n = dgn.workspace_size_svd(dims, R, block, dt)
+        # at least the per-mode Grams (complex: of the doubled embedding)
+        f = 2 if dtype.startswith("c") else 1
+        assert n >= sum(((f * I + 63) // 64 * 64) ** 2 for I in dims) * 8
+    else:
+        with pytest.raises(dgn.DgnError) as e:
+            dgn.workspace_size_svd(dims, R, block, dt)
+        assert e.value.status == -1
