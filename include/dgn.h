@@ -118,10 +118,11 @@ typedef struct dgn_opts {
   int32_t als_sweeps;   /* cp_fit and the server: ALS sweeps (as cp_als) on the starting factors
                            before the first trial; default 0.  cp_fit_batched rejects a nonzero
                            value with DGN_EINVAL */
-  /* dgn_step and cp_fit, real tensors with N <= 4 and R <= 32: DGN_SOLVER_AUTO
+  /* dgn_step and cp_fit, N <= 4 and R <= 32 (complex tensors: R <= 16): DGN_SOLVER_AUTO
    * first solves the NR^2 system by conjugate gradients on its structured SPD
    * form (Section 4.3: Kronecker and permuted-diagonal products, the matrix is
-   * never formed) and runs the direct tiled Cholesky only when CG has not
+   * never formed; Hermitian for complex tensors, Section 5) and runs the direct
+   * tiled Cholesky only when CG has not
    * reached ||r|| <= cg_tol ||z|| within cg_max_iters iterations; inside cp_fit
    * the first such failure leaves CG out for the rest of the fit.  The step
    * then differs from the direct one by the CG tolerance (amplified by the

@@ -280,11 +280,17 @@ hipError_t enqueue_step_c(Work& w, bool resid, double mu_host, FitState* state, 
   if ((e = mark(ev, 0, st)) != hipSuccess) return e;
   if ((e = launch_small_pre_c(s, w.A, w.M, resid, mu_host, state, w.sb, singular, stop, st)) != hipSuccess) return e;
   if ((e = mark(ev, 1, st)) != hipSuccess) return e;
-  if ((e = launch_sys_fill(w.sp, w.sy, stop, st)) != hipSuccess) return e;
-  if ((e = launch_subblock_c(s, w.sp, w.sb, w.sy, stop, st)) != hipSuccess) return e;
-  if ((e = launch_sys_rhs_syrk(w.sp, w.sb.z, w.sy, stop, st)) != hipSuccess) return e;
+  // DGN_SOLVER_AUTO: CG on the Hermitian system first, as in the real step
+  const int* solve_stop = stop;
+  if (w.solver == DGN_SOLVER_AUTO && cg_supported_c(s)) {
+    if ((e = launch_cg_c(s, w.sb, w.cg_tol, w.cg_max, state, mu_host, w.flags + 8, stop, st)) != hipSuccess) return e;
+    solve_stop = w.flags + 8;
+  }
+  if ((e = launch_sys_fill(w.sp, w.sy, solve_stop, st)) != hipSuccess) return e;
+  if ((e = launch_subblock_c(s, w.sp, w.sb, w.sy, solve_stop, st)) != hipSuccess) return e;
+  if ((e = launch_sys_rhs_syrk(w.sp, w.sb.z, w.sy, solve_stop, st)) != hipSuccess) return e;
   if ((e = mark(ev, 2, st)) != hipSuccess) return e;
-  if ((e = launch_sys_factor_solve(s, w.sp, w.sb, w.sy, singular, stop, st)) != hipSuccess) return e;
+  if ((e = launch_sys_factor_solve(s, w.sp, w.sb, w.sy, singular, solve_stop, st)) != hipSuccess) return e;
   if ((e = mark(ev, 3, st)) != hipSuccess) return e;
   return launch_small_post_c(s, w.A, w.Ac, w.sb, mu_host, state, stop, st, w.da_out);
 }
@@ -515,7 +521,7 @@ dgn_status dgn_step(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, const void* co
   HIPCHK(hipMemcpyAsync(sc, w.sb.scal, sizeof sc, hipMemcpyDeviceToHost, st), "copy");
   HIPCHK(hipMemcpyAsync(flags, w.flags, sizeof flags, hipMemcpyDeviceToHost, st), "copy");
   HIPCHK(hipStreamSynchronize(st), "sync");
-  const bool cg_ran = w.solver == DGN_SOLVER_AUTO && w.cs == 1 && cg_supported(w.s);
+  const bool cg_ran = w.solver == DGN_SOLVER_AUTO && (w.cs == 1 ? cg_supported(w.s) : cg_supported_c(w.s));
   if (info) {
     info->cg_iters = (cg_ran && flags[8]) ? flags[10] : -1;
     info->err2_old = host[0];

@@ -206,6 +206,170 @@ __global__ __launch_bounds__(1024) void k_cg(Shape s, const double* __restrict__
   }
 }
 
+// Complex tensors (Section 5): the Hermitian positive definite S = I + W^H K W
+// of the complex step, S_nm[a + bR, c + dR] = sum_{j,i} conj(X_n[j,b]) L_m[j,c]
+// Gamma_nm[j,i] conj(L_n[i,a]) X_m[i,d], applied as
+//   U_m = L_m Y_m X_m^T,  V_n = sum_{m != n} Gamma_nm .* U_m,
+//   (S y)_n = Y_n + L_n^H V_n^T conj(X_n).
+// Here R <= 16: thread t owns entry (t % 16, (t / 16) % 16) of mode t / 256, and
+// wave m < N computes mode m's 16 x 16 complex products (four real MFMA chains).
+// z and y use the embedded layout of the direct solve: [Re z_1, Im z_1, Re z_t, Im z_t].
+constexpr int QR = 16;
+constexpr int QS = QR + 1;
+
+template <class FA, class FB, class FO>
+__device__ __forceinline__ void cgemm16(int N, FA fa, FB fb, FO fo) {
+  const int lane = threadIdx.x & 63, m = threadIdx.x >> 6;
+  if (m >= N) return;
+  v4d ar = v4d{0.0, 0.0, 0.0, 0.0}, ai = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < QR; k += 4) {
+    const int kk = k + (lane >> 4);
+    double a_re, a_im, b_re, b_im;
+    fa(m, lane & 15, kk, a_re, a_im);
+    fb(m, kk, lane & 15, b_re, b_im);
+    ar = __builtin_amdgcn_mfma_f64_16x16x4f64(a_re, b_re, ar, 0, 0, 0);
+    ar = __builtin_amdgcn_mfma_f64_16x16x4f64(-a_im, b_im, ar, 0, 0, 0);
+    ai = __builtin_amdgcn_mfma_f64_16x16x4f64(a_re, b_im, ai, 0, 0, 0);
+    ai = __builtin_amdgcn_mfma_f64_16x16x4f64(a_im, b_re, ai, 0, 0, 0);
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) fo(m, (lane >> 4) + 4 * v, lane & 15, ar[v], ai[v]);
+}
+
+__device__ __forceinline__ long long emb_re(int n, int e, int R2, int N) {
+  return n == 0 ? e : 2LL * R2 + (long long)(n - 1) * R2 + e;
+}
+__device__ __forceinline__ long long emb_im(int n, int e, int R2, int N) {
+  return n == 0 ? (long long)R2 + e : 2LL * R2 + (long long)(N - 1) * R2 + (long long)(n - 1) * R2 + e;
+}
+
+__global__ __launch_bounds__(1024) void k_cg_c(Shape s, const double* __restrict__ C, const double* __restrict__ X,
+                                               const double* __restrict__ Lc, const double* __restrict__ z,
+                                               double* __restrict__ y, double tol, int maxit, FitState* state,
+                                               double mu_host, int* cgf, const int* stop) {
+  __shared__ double Lr[CN][QR][QS], Li[CN][QR][QS], Xr[CN][QR][QS], Xi[CN][QR][QS];
+  __shared__ double Pr[CN][QR][QS], Pi[CN][QR][QS], Tr[CN][QR][QS], Ti[CN][QR][QS];
+  __shared__ double red[16], red_a[16], red_b[16];
+  if (stopped(stop)) {
+    if (threadIdx.x == 0) cgf[0] = 1;
+    return;
+  }
+  const double mu = state ? state->mu : mu_host;
+  if (state && state->cg_mu_fail > 0.0) {
+    if (threadIdx.x == 0) cgf[0] = 0;
+    return;
+  }
+  const int N = s.N, R = s.R, R2 = R * R, t = threadIdx.x;
+  const int gn = t >> 8, gi = t & 15, gj = (t >> 4) & 15;
+  const bool act = gn < N && gi < R && gj < R;
+  const int e = gi + gj * R;
+  Lr[gn][gi][gj] = act ? Lc[2 * ((long long)gn * R2 + e)] : 0.0;
+  Li[gn][gi][gj] = act ? Lc[2 * ((long long)gn * R2 + e) + 1] : 0.0;
+  Xr[gn][gi][gj] = act ? X[2 * ((long long)gn * R2 + e)] : 0.0;
+  Xi[gn][gi][gj] = act ? X[2 * ((long long)gn * R2 + e) + 1] : 0.0;
+  // Gamma_{gn,m} at (gi, gj): complex product of C_k over k not in {gn, m}
+  double cre[CN], cim[CN];
+#pragma unroll
+  for (int k = 0; k < CN; ++k) {
+    const bool in = k < N && gi < R && gj < R;
+    cre[k] = in ? C[2 * ((long long)k * R2 + e)] : 0.0;
+    cim[k] = in ? C[2 * ((long long)k * R2 + e) + 1] : 0.0;
+  }
+  double gre[CN], gim[CN];
+#pragma unroll
+  for (int m = 0; m < CN; ++m) {
+    double pr = (act && m < N && m != gn) ? 1.0 : 0.0, pi = 0.0;
+#pragma unroll
+    for (int k = 0; k < CN; ++k)
+      if (k < N && k != gn && k != m) {
+        const double nr = pr * cre[k] - pi * cim[k];
+        pi = pr * cim[k] + pi * cre[k];
+        pr = nr;
+      }
+    gre[m] = pr;
+    gim[m] = pi;
+  }
+  double xr = 0.0, xi = 0.0;
+  double rr_ = act ? z[emb_re(gn, e, R2, N)] : 0.0, ri = act ? z[emb_im(gn, e, R2, N)] : 0.0;
+  double pr = rr_, pi = ri;
+  double rr = block_sum(rr_ * rr_ + ri * ri, red);
+  const double goal = tol * tol * rr;
+  bool conv = rr <= goal;
+  int it = 0;
+  while (!conv && it < maxit && isfinite(rr)) {
+    Pr[gn][gi][gj] = pr;
+    Pi[gn][gi][gj] = pi;
+    sync_block();
+    // T_m = L_m P_m
+    cgemm16(
+        N, [&](int m, int r, int k, double& a, double& b) { a = Lr[m][r][k]; b = Li[m][r][k]; },
+        [&](int m, int k, int c, double& a, double& b) { a = Pr[m][k][c]; b = Pi[m][k][c]; },
+        [&](int m, int r, int c, double a, double b) { Tr[m][r][c] = a; Ti[m][r][c] = b; });
+    sync_block();
+    // U_m = T_m X_m^T (into P)
+    cgemm16(
+        N, [&](int m, int r, int k, double& a, double& b) { a = Tr[m][r][k]; b = Ti[m][r][k]; },
+        [&](int m, int k, int c, double& a, double& b) { a = Xr[m][c][k]; b = Xi[m][c][k]; },
+        [&](int m, int r, int c, double a, double b) { Pr[m][r][c] = a; Pi[m][r][c] = b; });
+    sync_block();
+    // V_n = sum_{m != n} Gamma_nm .* U_m (into T)
+    {
+      double vr = 0.0, vi = 0.0;
+#pragma unroll
+      for (int m = 0; m < CN; ++m) {
+        const double ur = Pr[m][gi][gj], ui = Pi[m][gi][gj];
+        vr += gre[m] * ur - gim[m] * ui;
+        vi += gre[m] * ui + gim[m] * ur;
+      }
+      Tr[gn][gi][gj] = vr;
+      Ti[gn][gi][gj] = vi;
+    }
+    sync_block();
+    // W_n = V_n^T conj(X_n) (into P)
+    cgemm16(
+        N, [&](int m, int r, int k, double& a, double& b) { a = Tr[m][k][r]; b = Ti[m][k][r]; },
+        [&](int m, int k, int c, double& a, double& b) { a = Xr[m][k][c]; b = -Xi[m][k][c]; },
+        [&](int m, int r, int c, double a, double b) { Pr[m][r][c] = a; Pi[m][r][c] = b; });
+    sync_block();
+    // O_n = L_n^H W_n (into T); (S p)_n = P_n + O_n
+    cgemm16(
+        N, [&](int m, int r, int k, double& a, double& b) { a = Lr[m][k][r]; b = -Li[m][k][r]; },
+        [&](int m, int k, int c, double& a, double& b) { a = Pr[m][k][c]; b = Pi[m][k][c]; },
+        [&](int m, int r, int c, double a, double b) { Tr[m][r][c] = a; Ti[m][r][c] = b; });
+    sync_block();
+    const double apr = act ? pr + Tr[gn][gi][gj] : 0.0, api = act ? pi + Ti[gn][gi][gj] : 0.0;
+    const double pap = block_sum1(pr * apr + pi * api, red_a);  // Re(p^H S p)
+    if (!(pap > 0.0)) break;
+    const double alpha = rr / pap;
+    xr += alpha * pr;
+    xi += alpha * pi;
+    rr_ -= alpha * apr;
+    ri -= alpha * api;
+    const double rn = block_sum1(rr_ * rr_ + ri * ri, red_b);
+    ++it;
+    conv = rn <= goal;
+    const double beta = rn / rr;
+    rr = rn;
+    pr = rr_ + beta * pr;
+    pi = ri + beta * pi;
+  }
+  if (conv && act) {
+    y[emb_re(gn, e, R2, N)] = xr;
+    y[emb_im(gn, e, R2, N)] = xi;
+  }
+  if (t == 0) {
+    cgf[0] = conv ? 1 : 0;
+    cgf[2] = it;
+    if (conv) {
+      cgf[3] += 1;
+      cgf[4] += it;
+    } else if (state) {
+      state->cg_mu_fail = mu;
+    }
+  }
+}
+
 }  // namespace
 
 bool cg_supported(const Shape& s) { return s.N <= CN && s.R <= CR; }
@@ -215,6 +379,20 @@ hipError_t launch_cg(const Shape& s, const SmallBuffers& b, double tol, int maxi
   if (!cg_supported(s)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_cg, dim3(1), dim3(1024), 0, st, s, b.C, b.X, b.Lc, b.z, b.y, tol, maxit, state, mu_host, cgf,
                      stop);
+  return hipGetLastError();
+}
+
+}  // namespace dgn
+
+namespace dgn {
+
+bool cg_supported_c(const Shape& s) { return s.N <= CN && s.R <= QR; }
+
+hipError_t launch_cg_c(const Shape& s, const SmallBuffers& b, double tol, int maxit, FitState* state, double mu_host,
+                       int* cgf, const int* stop, hipStream_t st) {
+  if (!cg_supported_c(s)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_cg_c, dim3(1), dim3(1024), 0, st, s, b.C, b.X, b.Lc, b.z, b.y, tol, maxit, state, mu_host,
+                     cgf, stop);
   return hipGetLastError();
 }
 

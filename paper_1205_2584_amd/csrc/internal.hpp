@@ -197,6 +197,10 @@ bool cg_supported(const Shape& s);  // N <= 4, R <= 32
 // state when state != NULL, which also carries the retry rule of a fit.
 hipError_t launch_cg(const Shape& s, const SmallBuffers& b, double tol, int maxit, FitState* state, double mu_host,
                      int* cgf, const int* stop, hipStream_t st);
+// The same for the complex step (Hermitian S, embedded z and y), N <= 4, R <= 16.
+bool cg_supported_c(const Shape& s);
+hipError_t launch_cg_c(const Shape& s, const SmallBuffers& b, double tol, int maxit, FitState* state, double mu_host,
+                       int* cgf, const int* stop, hipStream_t st);
 
 // ---- mode-n singular vectors (SVD initialisation) ---------------------------
 // Y viewed for mode n as (P, I, Q): element (p, i, q) at p + P (i + I q).

@@ -185,3 +185,53 @@ def test_cg_step_full_size_500cube():
         assert _rel(dc, dd) <= 10 * kappa * 1e-12 + 1e-11, (_rel(dc, dd), kappa)
     finally:
         ctx.close()
+
+
+# ---- complex tensors (Section 5): CG on the Hermitian system ---------------------
+
+
+def cond_Phi(Y, A, mu):
+    """cond(S) of the complex step from the eigenvalues of Phi_1 = I + Psi K,
+    which has the spectrum of S = I + W^H K W (Psi = W W^H)."""
+    ev = np.linalg.eigvals(cp.fast_step(Y, A, mu).Phi)
+    ev = np.abs(ev)
+    return float(ev.max() / ev.min())
+
+
+@pytest.mark.parametrize("dims,R,mu", [((20, 18, 16), 4, 1.0), ((12, 10, 9, 8), 3, 1.0), ((36, 34, 32), 16, 10.0)])
+def test_cg_complex_step_matches_direct(dims, R, mu):
+    dgn = _dgn()
+    p = cpgen.small_problem(700 + R, dims, R, c=0.4, snr_db=30.0, complex_=True)
+    Y = cp.as_tensor(p.y, dims)
+    y = torch.from_numpy(p.y).cuda()
+    ctx = dgn.Context(0, dgn.workspace_size(dims, R, torch.complex128) + (16 << 20))
+    try:
+        print(f"cg complex step dims={dims} R={R} mu={mu}", flush=True)
+        A = dgn.to_device_factors(p.init)
+        out_d, info_d = ctx.dgn_step(y, dims, R, A, mu)
+        out_c, info_c = ctx.dgn_step(y, dims, R, A, mu, dgn.opts(solver=1, cg_max_iters=500, cg_tol=1e-12))
+        assert info_d["cg_iters"] == -1
+        assert 0 < info_c["cg_iters"] <= 500, info_c["cg_iters"]
+        kappa = cond_Phi(Y, p.init, mu)
+        dd = [o - a for o, a in zip(dgn.to_host_factors(out_d), p.init)]
+        dc = [o - a for o, a in zip(dgn.to_host_factors(out_c), p.init)]
+        assert _rel(dc, dd) <= 10 * kappa * 1e-12 + 1e-11, (_rel(dc, dd), kappa)
+    finally:
+        ctx.close()
+
+
+def test_cg_complex_fallback_and_unsupported_rank_are_the_direct_step():
+    dgn = _dgn()
+    for dims, R, kw in (((20, 18, 16), 4, {"cg_max_iters": 1}), ((24, 22, 20), 17, {})):
+        p = cpgen.small_problem(800 + R, dims, R, complex_=True)
+        y = torch.from_numpy(p.y).cuda()
+        ctx = dgn.Context(0, dgn.workspace_size(dims, R, torch.complex128) + (16 << 20))
+        try:
+            A = dgn.to_device_factors(p.init)
+            out_d, _ = ctx.dgn_step(y, dims, R, A, 1.0)
+            out_c, info = ctx.dgn_step(y, dims, R, A, 1.0, dgn.opts(solver=1, **kw))
+            assert info["cg_iters"] == -1
+            for a, b in zip(out_c, out_d):
+                assert torch.equal(a, b)
+        finally:
+            ctx.close()
