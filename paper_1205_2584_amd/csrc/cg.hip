@@ -47,6 +47,18 @@ __device__ __forceinline__ void gemm32(int N, FA fa, FB fb, FO fo) {
   }
 }
 
+// Early exit of a solve that will not converge within the cap: every 10
+// iterations from the 20th, the mean reduction of ||r||^2 per iteration so far
+// is extrapolated; when the goal lies beyond twice maxit the solve gives up (the
+// direct solve then runs), so a hopeless attempt costs about 20 iterations
+// rather than maxit.  Uniform across the workgroup (scalars from block sums).
+__device__ __forceinline__ bool give_up(int it, double rn, double rr0, double goal, int maxit) {
+  if (it < 20 || it % 10 != 0 || !(rn > 0.0) || !(rn < rr0)) return it >= 20 && it % 10 == 0 && !(rn < rr0);
+  const double per = log(rn / rr0) / it;  // < 0
+  const double need = log(goal / rn) / per;
+  return it + need > 2.0 * maxit;  // twice the cap: CG often speeds up once the outliers are resolved
+}
+
 // Sum over the workgroup with a single barrier: the callers alternate two
 // scratch arrays, and every reuse of one is separated from its previous reads
 // by the barriers of the product phases.
@@ -62,7 +74,8 @@ __device__ __forceinline__ double block_sum1(double v, double* scratch) {
 
 // cgf: [0] 1 when the direct solve is to be skipped (converged, or the fit has
 // stopped), [2] this solve's iterations, [3] solves that converged, [4] their
-// iterations summed.  Inside a fit (state != NULL) the first failed solve
+// iterations summed.  A solve that cannot reach the goal within maxit at its
+// rate so far gives up early (give_up).  Inside a fit (state != NULL) the first failed solve
 // records its damping in the state and CG is not tried again in that fit, so a
 // fit loses at most one capped attempt.
 __global__ __launch_bounds__(1024) void k_cg(Shape s, const double* __restrict__ C, const double* __restrict__ X,
@@ -122,6 +135,7 @@ __global__ __launch_bounds__(1024) void k_cg(Shape s, const double* __restrict__
     zz += zv * zv;
   }
   double rr = block_sum(zz, red);
+  const double rr0 = rr;
   const double goal = tol * tol * rr;  // stop at ||r|| <= tol ||z||
   bool conv = rr <= goal;
   int it = 0;
@@ -184,6 +198,7 @@ __global__ __launch_bounds__(1024) void k_cg(Shape s, const double* __restrict__
     rn = block_sum1(rn, red_b);
     ++it;
     conv = rn <= goal;
+    if (!conv && give_up(it, rn, rr0, goal, maxit)) break;
     const double beta = rn / rr;
     rr = rn;
 #pragma unroll
@@ -294,6 +309,7 @@ __global__ __launch_bounds__(1024) void k_cg_c(Shape s, const double* __restrict
   double rr_ = act ? z[emb_re(gn, e, R2, N)] : 0.0, ri = act ? z[emb_im(gn, e, R2, N)] : 0.0;
   double pr = rr_, pi = ri;
   double rr = block_sum(rr_ * rr_ + ri * ri, red);
+  const double rr0 = rr;
   const double goal = tol * tol * rr;
   bool conv = rr <= goal;
   int it = 0;
@@ -349,6 +365,7 @@ __global__ __launch_bounds__(1024) void k_cg_c(Shape s, const double* __restrict
     const double rn = block_sum1(rr_ * rr_ + ri * ri, red_b);
     ++it;
     conv = rn <= goal;
+    if (!conv && give_up(it, rn, rr0, goal, maxit)) break;
     const double beta = rn / rr;
     rr = rn;
     pr = rr_ + beta * pr;
