@@ -19,7 +19,10 @@ Pins (see tests/test_oracle_pins.py): every function here is checked against
 something other than itself -- the explicit-Jacobian solve, the closed-form
 inverse of K (Appendix E), the zero gradient at an exact rank-R tensor, exact
 recovery of noiseless data, the cross-mode MTTKRP invariant, the Euler
-identity J a = N vec(Y_hat), and the generator's closed forms.  The damping
+identity J a = N vec(Y_hat), the decrease of the linearised residual
+(the gain-ratio denominator), tau max diag(J^T J) (mu0), the model-preserving
+normalisations, the closed form of each damping rule over a run of rejected
+trials, and the generator's closed forms.  The damping
 loop's trajectory (fit) has no printed worked example in the paper: parity
 unpinned beyond those step-level pins and the recovery test.
 """

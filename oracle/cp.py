@@ -244,7 +244,10 @@ def fast_step(Y: np.ndarray, A, mu: float, variant: str = "a", w_form: str = "ap
     F = [unvec(f[n * R2:(n + 1) * R2], R, R) for n in range(N)]   # frontal slices of F
     # boxed update (equ_fast_low_LM1a): A_mu + A (I - (F_n + Gamma) Gamma~)
     A_new = [A_mu[n] + A[n] @ (I_R - (F[n] + Gam_fac[n]) @ Gt_fac[n]) for n in range(N)]
-    dA = [A_new[n] - A[n] for n in range(N)]
+    # the step da = H_mu^-1 g itself (Section 4.5 defines rho with it): the boxed
+    # update minus A, i.e. P_n - A_n F_n Gamma~_n; formed directly rather than as
+    # A_new - A, which cancels to zero once da is below the factors' rounding
+    dA = [P[n] - A[n] @ F[n] @ Gt_fac[n] for n in range(N)]
     return Step(A_new=A_new, dA=dA, g=G, M=M, C=C, Gam=Gam, Gt=Gt_psi, P=P, w=w, f=f, F=F,
                 K=K, Psi=Psi, Phi=Phi)
 
@@ -304,22 +307,28 @@ STOP_TOL, STOP_MAX_IT, STOP_MU, STOP_NONFINITE = 0, 1, 2, 3
 
 
 def fit(Y: np.ndarray, A0, mu0: float, tol: float, max_iters: int, normalize: str = "balanced",
-        tau: float = 1e-3, variant: str = "a", trace: bool = False):
+        tau: float = 1e-3, variant: str = "a", trace: bool = False, mu_rule: str = "paper"):
     """Algorithm 1 with the damping of Section 4.5.
 
     One iteration is one trial step.  A trial is accepted iff the residual
     decreases (equivalently rho > 0, the denominator being positive); then the
-    factors are normalised and mu <- mu max(1/3, 1 - (2 rho - 1)^3).  A
-    rejected trial doubles mu.  The fit stops on an accepted trial whose
-    relative-error change |eps_prev - eps| is below tol, after max_iters trials,
-    or when mu exceeds 1e30.
+    factors are normalised and mu <- mu max(1/3, 1 - (2 rho - 1)^3).  On a
+    rejected trial, mu_rule "paper" doubles mu (as Section 4.5 prints it);
+    "nielsen" is the rule of the damping paper Section 4.5 cites: mu <- mu nu
+    and nu <- 2 nu on a rejection, nu reset to 2 on an acceptance, so that
+    consecutive rejections grow mu ever faster.  The fit stops on an accepted
+    trial whose relative-error change |eps_prev - eps| is below tol, after
+    max_iters trials, or when mu exceeds 1e30.
     """
+    if mu_rule not in ("paper", "nielsen"):
+        raise ValueError(mu_rule)
     A = [np.array(a, dtype=np.result_type(a, np.float64), order="F") for a in A0]
     normf = {"balanced": normalize_balanced, "unit": normalize_unit_except_last,
              "none": lambda x: x}[normalize]
     if mu0 <= 0:
         mu0 = mu0_from_tau(A, tau)
     mu = mu0
+    nu = 2.0
     ynorm = float(np.sqrt(np.sum(np.abs(Y) ** 2)))
     err2 = residual_norm2(Y, A)
     eps = np.sqrt(err2) / ynorm
@@ -347,11 +356,15 @@ def fit(Y: np.ndarray, A0, mu0: float, tol: float, max_iters: int, normalize: st
             err2 = err2_new
             eps_prev, eps = eps, np.sqrt(err2) / ynorm
             mu = mu * max(1.0 / 3.0, 1.0 - (2.0 * rho - 1.0) ** 3)
+            nu = 2.0
             if abs(eps_prev - eps) < tol:
                 reason = STOP_TOL
                 break
-        else:
+        elif mu_rule == "paper":
             mu = 2.0 * mu
+        else:
+            mu = nu * mu
+            nu = 2.0 * nu
         if mu > 1e30:
             reason = STOP_MU
             break

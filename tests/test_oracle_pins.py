@@ -469,3 +469,166 @@ def test_svd_init_complex_matches_hermitian_gram_eigenvectors():
         for r in range(R):  # the canonical phase: largest entry real and positive
             k = int(np.argmax(np.abs(A[n][:, r])))
             assert abs(A[n][k, r].imag) < 1e-15 and A[n][k, r].real > 0
+
+
+# ---- gain ratio, mu0 and the normalisations (Section 4.5, eq. mu0, Section 2) ----
+
+
+def _linear_model_decrease(y_vec, A, dA):
+    """||e||^2 - ||e - J da||^2 with J formed explicitly: the decrease that the
+    linearised model predicts for the step da (e = y - y_hat)."""
+    J = brute.jacobian(A)
+    e = y_vec - brute.model_vec(A)
+    r = e - J @ brute.param_vec(dA)
+    return float(np.sum(np.abs(e) ** 2) - np.sum(np.abs(r) ** 2))
+
+
+@pytest.mark.parametrize("complex_", [False, True])
+@pytest.mark.parametrize("mu", [1e-2, 1.0, 30.0])
+def test_gain_denominator_is_the_linear_model_decrease(mu, complex_):
+    """The denominator of rho (Section 4.5) is the decrease of the linearised
+    residual: for da = (J^H J + mu I)^-1 J^H e,
+    ||e||^2 - ||e - J da||^2 = 2 Re(da^H g) - da^H H da = Re(da^H (g + mu da)).
+    The left side is computed from the explicit Jacobian only."""
+    dims, R = (4, 3, 5), 3
+    p, Y = _problem(31, dims, R, complex_)
+    st = cp.fast_step(Y, p.init, mu)
+    ref = _linear_model_decrease(p.y, p.init, st.dA)
+    got = cp.gain_denominator(st.dA, st.g, mu)
+    assert ref > 0
+    assert abs(got - ref) <= 1e-10 * ref
+
+
+def test_gain_denominator_planted_mistakes_fail():
+    """A sign slip on the mu term, or the mu term dropped, misses the linear-model decrease."""
+    dims, R, mu = (4, 3, 5), 3, 1.0
+    p, Y = _problem(32, dims, R)
+    st = cp.fast_step(Y, p.init, mu)
+    ref = _linear_model_decrease(p.y, p.init, st.dA)
+    assert abs(cp.gain_denominator(st.dA, st.g, -mu) - ref) > 1e-3 * ref
+    assert abs(cp.gain_denominator(st.dA, st.g, 0.0) - ref) > 1e-3 * ref
+
+
+@pytest.mark.parametrize("complex_", [False, True])
+def test_mu0_is_tau_times_max_diag_of_explicit_hessian(complex_):
+    """eq. mu0, first form: mu0 = tau max diag(J^H J), J formed explicitly."""
+    dims, R, tau = (4, 5, 3, 3), 3, 1e-3
+    p, _ = _problem(33, dims, R, complex_)
+    A = [a * s for a, s in zip(p.init, (0.5, 2.0, 3.0, 0.7))]   # modes of unequal scale
+    J = brute.jacobian(A)
+    ref = tau * float(np.max(np.real(np.sum(np.abs(J) ** 2, axis=0))))
+    assert abs(cp.mu0_from_tau(A, tau) - ref) <= 1e-13 * ref
+
+
+def test_mu0_last_form_holds_for_unit_modes():
+    """eq. mu0, last form: with unit-norm columns in modes 1..N-1 the rule is
+    tau max{1, diag C^(N)}."""
+    dims, R, tau = (5, 4, 6), 3, 1e-2
+    p, _ = _problem(34, dims, R)
+    A = cp.normalize_unit_except_last([a * 3.0 for a in p.init])
+    ref = tau * max(1.0, float(np.max(np.diag(A[-1].T @ A[-1]))))
+    assert abs(cp.mu0_from_tau(A, tau) - ref) <= 1e-13 * ref
+
+
+def test_mu0_planted_gram_instead_of_gamma_fails(monkeypatch):
+    """Planted mistake: the maximum over diag C^(n) instead of diag Gamma^(n)."""
+    dims, R, tau = (4, 5, 3), 3, 1e-3
+    p, _ = _problem(35, dims, R)
+    A = [a * s for a, s in zip(p.init, (0.5, 2.0, 3.0))]
+    ref = tau * float(np.max(np.sum(brute.jacobian(A) ** 2, axis=0)))
+    monkeypatch.setattr(cp, "gammas", lambda C: C)
+    assert abs(cp.mu0_from_tau(A, tau) - ref) > 1e-3 * ref
+
+
+@pytest.mark.parametrize("complex_", [False, True])
+def test_normalize_unit_except_last(complex_):
+    """Section 2 convention: Y_hat unchanged, unit columns in modes 1..N-1 and
+    the last mode's column norms equal to prod_n ||a^(n)_r||."""
+    dims, R = (4, 3, 5, 3), 3
+    p, _ = _problem(36, dims, R, complex_)
+    A = [a * s for a, s in zip(p.init, (0.5, 2.0, 3.0, 0.7))]
+    out = cp.normalize_unit_except_last(A)
+    assert _rel(brute.model_vec(out), brute.model_vec(A)) < 1e-14
+    for n in range(len(dims) - 1):
+        assert np.allclose(np.linalg.norm(out[n], axis=0), 1.0, rtol=1e-14, atol=0)
+    lam = np.prod([np.linalg.norm(a, axis=0) for a in A], axis=0)
+    assert np.allclose(np.linalg.norm(out[-1], axis=0), lam, rtol=1e-13, atol=0)
+
+
+def test_normalize_balanced_keeps_the_model():
+    """Algorithm 1 normalisation: Y_hat unchanged and every mode's column norm
+    equal to lambda_r^(1/N)."""
+    dims, R = (4, 3, 5), 3
+    p, _ = _problem(37, dims, R)
+    A = [a * s for a, s in zip(p.init, (0.5, 2.0, 3.0))]
+    out = cp.normalize_balanced(A)
+    assert _rel(brute.model_vec(out), brute.model_vec(A)) < 1e-14
+    lam = np.prod([np.linalg.norm(a, axis=0) for a in A], axis=0)
+    for a in out:
+        assert np.allclose(np.linalg.norm(a, axis=0), lam ** (1 / 3), rtol=1e-14, atol=0)
+
+
+def test_normalize_planted_missing_last_mode_scale_fails(monkeypatch):
+    """Planted mistake: modes 1..N-1 scaled to unit norm without moving the
+    magnitude into mode N changes the model."""
+    dims, R = (4, 3, 5), 3
+    p, _ = _problem(38, dims, R)
+    A = [a * s for a, s in zip(p.init, (0.5, 2.0, 3.0))]
+
+    def bad(A):
+        out = [a.copy() for a in A]
+        for n in range(len(A) - 1):
+            out[n] = out[n] / np.linalg.norm(out[n], axis=0)
+        return out
+
+    assert _rel(brute.model_vec(bad(A)), brute.model_vec(A)) > 1e-2
+
+
+# ---- damping rules on a run of rejected trials (Section 4.5) ------------------
+
+
+def _null_step_fit(mu_rule):
+    """At mu0 = 1e25 every step is far below half an ulp of the factors, so
+    A + da == A, the residual is unchanged and every trial is rejected."""
+    dims, R = (5, 4, 3), 2
+    p, Y = _problem(39, dims, R)
+    return cp.fit(Y, p.init, mu0=1e25, tol=0.0, max_iters=100, trace=True, mu_rule=mu_rule)
+
+
+def test_paper_rule_doubles_mu_per_rejection():
+    """Section 4.5 as printed: after k rejections mu = mu0 2^k; the first mu
+    above 1e30 stops the fit, here after k = 17 (2^17 > 1e5 > 2^16)."""
+    res = _null_step_fit("paper")
+    assert res["reason"] == cp.STOP_MU and res["accepted"] == 0
+    assert res["iters"] == 17
+    mus = [h["mu"] for h in res["hist"]]
+    assert mus == [1e25 * 2.0 ** k for k in range(17)]
+
+
+def test_nielsen_rule_closed_form_on_rejection_runs():
+    """Nielsen's rule: with nu = 2 after an acceptance (or at the start), j
+    consecutive rejections multiply mu by 2 * 4 * ... * 2^j = 2^(j(j+1)/2).
+    From 1e25 the fit passes 1e30 after j = 6 (2^21 > 1e5 > 2^15)."""
+    res = _null_step_fit("nielsen")
+    assert res["reason"] == cp.STOP_MU and res["accepted"] == 0
+    assert res["iters"] == 6
+    mus = [h["mu"] for h in res["hist"]]
+    assert mus == [1e25 * 2.0 ** (j * (j + 1) // 2) for j in range(6)]
+    assert res["mu"] == 1e25 * 2.0 ** 21
+
+
+def test_nielsen_rule_resets_nu_on_acceptance():
+    """On a real fit the two rules agree up to the first rejection; after an
+    acceptance the next rejection multiplies mu by 2 again."""
+    p = cpgen.cfg1()
+    Y = cp.as_tensor(p.y, p.dims)
+    a = cp.fit(Y, p.init, mu0=1e-3, tol=0.0, max_iters=30, trace=True, mu_rule="paper")["hist"]
+    b = cp.fit(Y, p.init, mu0=1e-3, tol=0.0, max_iters=30, trace=True, mu_rule="nielsen")["hist"]
+    first_rej = next(i for i, h in enumerate(a) if not h["accepted"])
+    for i in range(first_rej + 1):
+        assert a[i]["mu"] == b[i]["mu"]
+    run = 0
+    for h0, h1 in zip(b, b[1:]):
+        run = 0 if h0["accepted"] else run + 1
+        if not h0["accepted"]:
+            assert h1["mu"] == h0["mu"] * 2.0 ** run
