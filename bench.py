@@ -110,7 +110,17 @@ def cpu_baseline(p, gpu_check, seconds_cap=30.0):
             break
     dt = time.perf_counter() - t0
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     base = {"value": n / dt, "unit": "iters/s", "cores": threads, "kind": "oracle",
+            "nproc": len(os.sched_getaffinity(0)), "cpu_model": model,
             "sample": f"{n} trial step(s) (fast step + residual) of the same 500^3 R=30 fit, FP64 NumPy"}
     return base, gpu_check(first, mu)
 
@@ -357,13 +367,51 @@ def oracle_check(dgn, torch, p, ref, mu):
         got = np.concatenate([m.ravel(order="F") for m in dgn.to_host_factors(M)])
         out[f"mttkrp_rel_err_{name}"] = rel(got, Mref)
         del y
-    A_out, info = ctx.dgn_step(y64, p.dims, p.R, dgn.to_device_factors(p.init), mu)
-    da = np.concatenate([(g - a).ravel(order="F") for g, a in zip(dgn.to_host_factors(A_out), p.init)])
     dref = np.concatenate([d.ravel(order="F") for d in ref.dA])
-    out["step_rel_err_f64"] = rel(da, dref)
+    y32 = y64.float()
+    # the first step from each stored precision against the oracle's FP64 step:
+    # FP64 tensor; FP32 tensor with the plain pass and with the residual-corrected
+    # pass; the FP32 tensor with its BF16 copy for the plain pass
+    for name, y, o in (("f64", y64, None), ("f32", y32, None), ("f32_resid", y32, dgn.opts(resid_switch=-1.0)),
+                       ("bf16", y32, dgn.opts(y_bf16=y32.to(torch.bfloat16)))):
+        A_out, info = ctx.dgn_step(y, p.dims, p.R, dgn.to_device_factors(p.init), mu, o)
+        da = np.concatenate([(g - a).ravel(order="F") for g, a in zip(dgn.to_host_factors(A_out), p.init)])
+        out[f"step_rel_err_{name}"] = rel(da, dref)
     out["mu"] = mu
     ctx.close()
-    del y64
+    del y64, y32
+    torch.cuda.empty_cache()
+    return out
+
+
+def precision_oracle_sample(dgn, torch, dims=(150, 150, 150), R=10, trials=150, seed=33):
+    """Final eps of the FP64, FP32 and FP32+BF16 paths against the FP64 oracle's fit
+    on a sample of the same recipe small enough for the oracle (150^3, R = 10,
+    lambda over three decades, correlation 0.9 in mode 3, 25 dB; random start,
+    150 trials, no early stop: the oracle reaches the noise floor).  The mixed
+    paths are compared with the oracle run on the FP32-rounded tensor."""
+    import numpy as np
+    import cpgen
+    from oracle import cp
+    p = cpgen.cfg3(seed=seed, dims=dims, R=R)
+    y32h = p.y.astype(np.float32).astype(np.float64)
+    t0 = time.perf_counter()
+    ref = {"f64": cp.fit(cp.as_tensor(p.y, dims), p.init, mu0=-1.0, tol=0.0, max_iters=trials),
+           "f32": cp.fit(cp.as_tensor(y32h, dims), p.init, mu0=-1.0, tol=0.0, max_iters=trials)}
+    oracle_s = time.perf_counter() - t0
+    y64 = torch.from_numpy(p.y).cuda()
+    y32 = y64.float()
+    ctx = dgn.Context(0, dgn.workspace_size(dims, R, torch.float64) + (64 << 20))
+    out = {"sample": f"{'x'.join(map(str, dims))}, R={R}, {trials} trials from a random start",
+           "oracle_s": round(oracle_s, 1)}
+    for name, y, o, rk in (("f64", y64, dgn.opts(), "f64"), ("f32", y32, dgn.opts(), "f32"),
+                           ("bf16", y32, dgn.opts(y_bf16=y32.to(torch.bfloat16)), "f32")):
+        A = dgn.to_device_factors(p.init)
+        fi = ctx.cp_fit(y, dims, R, A, -1.0, 0.0, trials, o)
+        out[name] = {"eps": fi["eps"], "oracle_eps": ref[rk]["eps"], "eps_diff_vs_oracle": abs(fi["eps"] - ref[rk]["eps"]),
+                     "resid_iters": fi["resid_iters"], "accepted": fi["accepted"], "oracle_accepted": ref[rk]["accepted"]}
+    ctx.close()
+    del y64, y32
     torch.cuda.empty_cache()
     return out
 
@@ -374,7 +422,9 @@ def precision_report(dgn, torch, p):
     near convergence), so that each path reaches the accuracy it can resolve.
     Reports each final eps and its difference from the FP64 path's.  (With a
     stop test |delta eps| < 1e-8 the FP32 path's stopping point is set by the
-    noise of its FP32 residual, about 3e-10 ||Y||^2 in eps^2, and can come early.)"""
+    noise of its FP32 residual, about 3e-10 ||Y||^2 in eps^2, and can come early.)
+    The comparison with the oracle itself runs on a smaller sample of the recipe
+    (precision_oracle_sample)."""
     y64 = torch.from_numpy(p.y).cuda()
     y32 = y64.float()
     ybf = y32.to(torch.bfloat16)
@@ -390,6 +440,7 @@ def precision_report(dgn, torch, p):
         res[name]["eps_diff_vs_f64"] = abs(res[name]["eps"] - res["f64"]["eps"])
     del y64, y32, ybf
     torch.cuda.empty_cache()
+    res["vs_oracle"] = precision_oracle_sample(dgn, torch)
     return res
 
 

@@ -157,10 +157,10 @@ def cfg2(seed: int = 2, dims=(100, 100, 100, 100)) -> Problem:
                    meta={"name": "cfg2", "c": 0.95, "snr_db": 20.0, "lam": lam})
 
 
-def cfg3(seed: int = 3, dims=(500, 500, 500)) -> Problem:
-    """3-way 500^3, R=30, lambda_r = 10^(3(r-1)/(R-1)), correlation 0.9 in mode 3, 25 dB."""
+def cfg3(seed: int = 3, dims=(500, 500, 500), R: int = 30) -> Problem:
+    """3-way 500^3, R=30, lambda_r = 10^(3(r-1)/(R-1)), correlation 0.9 in mode 3, 25 dB
+    (smaller dims and R give samples of the same recipe)."""
     rng = np.random.default_rng(seed)
-    R = 30
     truth = [np.asfortranarray(rng.standard_normal((I, R))) for I in dims[:-1]]
     truth.append(collinear_factor(rng, dims[-1], R, 0.9))
     lam = 10.0 ** (3.0 * np.arange(R) / (R - 1))

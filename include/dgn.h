@@ -123,16 +123,28 @@ typedef struct dgn_opts {
    * form (Section 4.3: Kronecker and permuted-diagonal products, the matrix is
    * never formed; Hermitian for complex tensors, Section 5) and runs the direct
    * tiled Cholesky only when CG has not
-   * reached ||r|| <= cg_tol ||z|| within cg_max_iters iterations; inside cp_fit
+   * reached ||r|| <= cg_tol ||z|| within cg_max_iters iterations, or earlier
+   * when it cannot: every 10 iterations from the 20th the mean reduction of
+   * ||r||^2 per iteration so far is extrapolated, and an attempt whose goal
+   * lies beyond 2 cg_max_iters at that rate is abandoned (so a hopeless
+   * attempt costs about 20 iterations); inside cp_fit
    * the first such failure leaves CG out for the rest of the fit.  The step
    * then differs from the direct one by the CG tolerance (amplified by the
    * condition number of the system).  Default DGN_SOLVER_DIRECT. */
   int32_t solver;
   int32_t cg_max_iters; /* default 100 */
   double cg_tol;        /* default 1e-10 */
+  /* cp_fit, cp_fit_batched and the server: growth of mu on a rejected trial
+   * (Section 4.5).  DGN_MU_PAPER (default): mu <- 2 mu, as the section prints
+   * it.  DGN_MU_NIELSEN: the rule of the damping reference the section cites,
+   * mu <- mu nu and nu <- 2 nu on a rejection, nu reset to 2 on an acceptance,
+   * so that a run of rejections grows mu ever faster.  The decrease on an
+   * accepted trial is the same under both. */
+  int32_t mu_rule;
 } dgn_opts;
 
 typedef enum dgn_solver { DGN_SOLVER_DIRECT = 0, DGN_SOLVER_AUTO = 1 } dgn_solver;
+typedef enum dgn_mu_rule { DGN_MU_PAPER = 0, DGN_MU_NIELSEN = 1 } dgn_mu_rule;
 
 /* Result of one trial step (dgn_step). */
 typedef struct dgn_step_info {
@@ -144,6 +156,8 @@ typedef struct dgn_step_info {
   double mnorm;     /* ||[M_n]||, all-mode MTTKRP norm (plain form) or ||[M_n - A_n Gamma_n]|| is g */
   double danorm;    /* ||da|| */
   int32_t cg_iters; /* DGN_SOLVER_AUTO: CG iterations of a converged CG solve, -1 when the direct solve ran */
+  int32_t cg_attempt_iters; /* DGN_SOLVER_AUTO: iterations of the CG attempt, converged or abandoned
+                               (the direct solve then ran); -1 when CG was not tried */
 } dgn_step_info;
 
 /* Result of a fit (cp_fit). */
@@ -234,7 +248,8 @@ dgn_status dgn_workspace_size_explicit(const dgn_tensor* Y, int32_t R, size_t* b
  * starting factors, out the result (N device pointers, FP64 / C128).
  * mu0 > 0 is used as given, mu0 <= 0 takes tau * max diag Gamma^(n).
  * Each trial: step at mu; accept iff the residual decreases, then normalise
- * and mu <- mu max(1/3, 1 - (2 rho - 1)^3); else mu <- 2 mu.  Stops on an
+ * and mu <- mu max(1/3, 1 - (2 rho - 1)^3); else mu grows by opts->mu_rule
+ * (default mu <- 2 mu).  Stops on an
  * accepted trial with |eps_prev - eps| < tol, after max_iters trials, or at
  * mu > 1e30.  Synchronises the stream before returning. */
 dgn_status cp_fit(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, void* const* A, double mu0,

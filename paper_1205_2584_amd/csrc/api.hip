@@ -389,6 +389,7 @@ void dgn_opts_default(dgn_opts* o) {
   o->solver = DGN_SOLVER_DIRECT;
   o->cg_max_iters = 100;
   o->cg_tol = 1e-10;
+  o->mu_rule = DGN_MU_PAPER;
 }
 
 dgn_status dgn_create(dgn_ctx** out, int32_t device, size_t ws_budget_bytes) {
@@ -524,6 +525,7 @@ dgn_status dgn_step(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, const void* co
   const bool cg_ran = w.solver == DGN_SOLVER_AUTO && (w.cs == 1 ? cg_supported(w.s) : cg_supported_c(w.s));
   if (info) {
     info->cg_iters = (cg_ran && flags[8]) ? flags[10] : -1;
+    info->cg_attempt_iters = cg_ran ? flags[10] : -1;
     info->err2_old = host[0];
     info->err2_new = host[1];
     info->denom = sc[0];
@@ -641,6 +643,7 @@ dgn_status dgn_step_explicit(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, const
     info->gnorm = sqrt(sc[2]);
     info->mnorm = sqrt(sc[3]);
     info->cg_iters = -1;
+    info->cg_attempt_iters = -1;
   }
   if (flags[0]) return set_err(ctx, DGN_ESINGULAR, "non-positive pivot in J^T J + mu I");
   if (!isfinite(host[1]) || !isfinite(sc[0])) return set_err(ctx, DGN_ENONFINITE, "non-finite step");
@@ -659,6 +662,7 @@ dgn_status cp_fit(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, void* const* A, 
   if (opts) o = *opts;
   if (o.poll_every < 1) o.poll_every = 1;
   if (o.normalize < 0 || o.normalize > 2) return set_err(ctx, DGN_EINVAL, "bad normalize option");
+  if (o.mu_rule != DGN_MU_PAPER && o.mu_rule != DGN_MU_NIELSEN) return set_err(ctx, DGN_EINVAL, "bad mu_rule option");
   if (o.als_sweeps < 0) return set_err(ctx, DGN_EINVAL, "als_sweeps must be >= 0");
   if (o.solver != DGN_SOLVER_DIRECT && o.solver != DGN_SOLVER_AUTO) return set_err(ctx, DGN_EINVAL, "bad solver option");
   if (o.solver == DGN_SOLVER_AUTO && (o.cg_max_iters < 0 || !(o.cg_tol > 0.0)))
@@ -683,6 +687,7 @@ dgn_status cp_fit(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, void* const* A, 
   hs.tol = tol;
   hs.max_iters = max_iters;
   hs.normalize = o.normalize;
+  hs.mu_rule = o.mu_rule;
   hs.stop = 0;
   FitState* ds = w.state;
   double* e2 = w.scr + 1024;
@@ -976,6 +981,7 @@ dgn_status cp_fit_batched(dgn_ctx* ctx, int32_t B, const dgn_batch_fit* fits, do
   dgn_opts_default(&o);
   if (opts) o = *opts;
   if (o.poll_every < 1) o.poll_every = 1;
+  if (o.mu_rule != DGN_MU_PAPER && o.mu_rule != DGN_MU_NIELSEN) return set_err(ctx, DGN_EINVAL, "bad mu_rule option");
   // validate and size the workspace
   size_t need = 0;
   auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
@@ -1024,7 +1030,7 @@ dgn_status cp_fit_batched(dgn_ctx* ctx, int32_t B, const dgn_batch_fit* fits, do
     h.st = reinterpret_cast<FitState*>(take(sizeof(FitState)));
     states[b] = h.st;
   }
-  BatchCfg cfg{tol, o.tau, o.resid_switch, max_iters, o.normalize, nstopped};
+  BatchCfg cfg{tol, o.tau, o.resid_switch, max_iters, o.normalize, o.mu_rule, nstopped};
   // order the private stream after the caller's work
   hipEvent_t ev_in, ev_out;
   HIPCHK(hipEventCreateWithFlags(&ev_in, hipEventDisableTiming), "event");

@@ -308,6 +308,8 @@ __global__ __launch_bounds__(256) void k_binit(BFit* fits, int nfits, BatchCfg c
     st->resid = resid;
     st->resid_iters = 0;
     st->pad0 = 0;  // refresh pending
+    st->mu_rule = cfg.mu_rule;
+    st->nu = 2.0;
     if (st->stop) atomicAdd(cfg.nstopped, 1);
   }
 }
@@ -588,6 +590,7 @@ __global__ __launch_bounds__(256) void k_btrial(BFit* fits, int nfits, BatchCfg 
         double fct = 1.0 - t3 * t3 * t3;
         if (fct < 1.0 / 3.0) fct = 1.0 / 3.0;
         st->mu *= fct;
+        st->nu = 2.0;
         if (fabs(st->eps_prev - st->eps) < st->tol) {
           st->stop = 1;
           st->reason = 0;
@@ -595,6 +598,9 @@ __global__ __launch_bounds__(256) void k_btrial(BFit* fits, int nfits, BatchCfg 
           st->resid = 1;
           st->pad0 = 1;
         }
+      } else if (st->mu_rule == 1) {
+        st->mu *= st->nu;
+        st->nu *= 2.0;
       } else {
         st->mu *= 2.0;
       }

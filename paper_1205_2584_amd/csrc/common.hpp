@@ -29,8 +29,9 @@ struct FitState {
   double gnorm2, danorm2, mnorm2;
   int iters, accepted, stop, reason;
   int max_iters, commit_iter, singular, normalize;
-  int resid, resid_iters, pad0, pad1;
+  int resid, resid_iters, pad0, mu_rule;  // mu_rule: 0 double on a rejection, 1 Nielsen's nu rule
   double cg_mu_fail;   // damping of the trial whose CG solve did not converge (0: none yet)
+  double nu;           // growth factor of the next rejection under Nielsen's rule
   double scale[kMaxOrder * kMaxRank];  // column scales of the last normalisation
 };
 

@@ -5,7 +5,9 @@
 // the residual-corrected pass) or as ||Y||^2 - 2 <Y, Y_hat> + ||Y_hat||^2 with
 // <Y, Y_hat> = sum(A_1 * M_1) and ||Y_hat||^2 = sum_{r,s} prod_n C_n[r,s].
 // A trial is accepted iff the residual decreases; then mu <- mu max(1/3,
-// 1 - (2 rho - 1)^3), else mu <- 2 mu.  Accepted factors are normalised; the
+// 1 - (2 rho - 1)^3), else mu <- 2 mu (the rule as Section 4.5 prints it) or,
+// with Nielsen's rule (the damping reference of Section 4.5), mu <- mu nu and
+// nu <- 2 nu, nu returning to 2 on every acceptance.  Accepted factors are normalised; the
 // stored MTTKRP (or gradient) columns and Gram matrices are rescaled with the
 // same column scales, which leave Y_hat unchanged.
 #include "common.hpp"
@@ -72,6 +74,7 @@ __global__ __launch_bounds__(256) void k_fit_init(Shape s, const double* A, cons
     st->singular = 0;
     st->resid = resid;
     st->resid_iters = 0;
+    st->nu = 2.0;
   }
 }
 
@@ -136,11 +139,15 @@ __global__ __launch_bounds__(256) void k_control(Shape s, const double* Ac, cons
         double f = 1.0 - t3 * t3 * t3;
         if (f < 1.0 / 3.0) f = 1.0 / 3.0;
         st->mu *= f;
+        st->nu = 2.0;
         st->commit_iter = trial;
         if (fabs(st->eps_prev - st->eps) < st->tol) {
           st->stop = 1;
           st->reason = 0;
         }
+      } else if (st->mu_rule == 1) {
+        st->mu *= st->nu;
+        st->nu *= 2.0;
       } else {
         st->mu *= 2.0;
       }

@@ -180,7 +180,7 @@ struct BFit {
 
 struct BatchCfg {
   double tol, tau, resid_switch;
-  int max_iters, normalize;
+  int max_iters, normalize, mu_rule;
   int* nstopped;
 };
 

@@ -171,6 +171,7 @@ dgn_status dgn_server_create(dgn_server** out, int32_t device, size_t budget_byt
                              int32_t max_slots, const dgn_opts* opts) {
   if (!out || max_slots < 1 || max_slots > 64 || budget_bytes < 4096) return DGN_EINVAL;
   *out = nullptr;
+  if (opts && opts->mu_rule != DGN_MU_PAPER && opts->mu_rule != DGN_MU_NIELSEN) return DGN_EINVAL;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return DGN_EINVAL;
   if (hipSetDevice(device) != hipSuccess) return DGN_EHIP;

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libdgn.so")
 MAX_ORDER = 8
 F64, F32, BF16, C64, C128 = 0, 1, 2, 3, 4
 NORM_BALANCED, NORM_UNIT_EXCEPT_LAST, NORM_NONE = 0, 1, 2
+MU_PAPER, MU_NIELSEN = 0, 1
 STOP_TOL, STOP_MAX_IT, STOP_MU, STOP_NONFINITE = 0, 1, 2, 3
 STATUS = {0: "DGN_OK", -1: "DGN_EINVAL", -2: "DGN_ENOMEM", -3: "DGN_ESINGULAR",
           -4: "DGN_ENONFINITE", -5: "DGN_EHIP", -6: "DGN_EBUSY"}
@@ -43,12 +44,14 @@ class dgn_opts(ctypes.Structure):
                 ("resid_switch", ctypes.c_double), ("y_bf16", ctypes.c_void_p),
                 ("poll_every", ctypes.c_int32), ("timing", ctypes.c_int32),
                 ("graph", ctypes.c_int32), ("als_sweeps", ctypes.c_int32),
-                ("solver", ctypes.c_int32), ("cg_max_iters", ctypes.c_int32), ("cg_tol", ctypes.c_double)]
+                ("solver", ctypes.c_int32), ("cg_max_iters", ctypes.c_int32), ("cg_tol", ctypes.c_double),
+                ("mu_rule", ctypes.c_int32)]
 
 
 class dgn_step_info(ctypes.Structure):
     _fields_ = [(n, ctypes.c_double) for n in
-                ("err2_old", "err2_new", "rho", "denom", "gnorm", "mnorm", "danorm")] + [("cg_iters", ctypes.c_int32)]
+                ("err2_old", "err2_new", "rho", "denom", "gnorm", "mnorm", "danorm")] + [
+        ("cg_iters", ctypes.c_int32), ("cg_attempt_iters", ctypes.c_int32)]
 
 
 class dgn_fit_info(ctypes.Structure):
@@ -160,11 +163,15 @@ def tensor_desc(y: torch.Tensor, dims) -> dgn_tensor:
 
 
 def opts(**kw) -> dgn_opts:
+    """dgn_opts with the library defaults and the given fields.  A tensor passed
+    as y_bf16 is kept alive by the returned object (the struct holds only its
+    device address)."""
     o = dgn_opts()
     load().dgn_opts_default(ctypes.byref(o))
     for k, v in kw.items():
-        if k == "y_bf16":
-            v = v.data_ptr() if isinstance(v, torch.Tensor) else v
+        if k == "y_bf16" and isinstance(v, torch.Tensor):
+            o._y_bf16 = v
+            v = v.data_ptr()
         setattr(o, k, v)
     return o
 

@@ -124,3 +124,55 @@ def test_workspace_size_svd_validates(lib, dims, R, block, dtype, ok):
         with pytest.raises(dgn.DgnError) as e:
             dgn.workspace_size_svd(dims, R, block, dt)
         assert e.value.status == -1
+
+
+def test_opts_mu_rule_default(lib):
+    from paper_1205_2584_amd import dgn
+    assert dgn.opts().mu_rule == dgn.MU_PAPER == 0 and dgn.MU_NIELSEN == 1
+
+
+STRUCTS = {
+    "dgn_tensor": ["order", "dims", "dtype", "data"],
+    "dgn_opts": ["normalize", "tau", "resid_switch", "y_bf16", "poll_every", "timing", "graph",
+                 "als_sweeps", "solver", "cg_max_iters", "cg_tol", "mu_rule"],
+    "dgn_step_info": ["err2_old", "err2_new", "rho", "denom", "gnorm", "mnorm", "danorm", "cg_iters",
+                      "cg_attempt_iters"],
+    "dgn_fit_info": ["iters", "accepted", "reason", "resid_iters", "eps", "err2", "mu", "mu0",
+                     "cg_trials", "cg_iters"],
+    "dgn_batch_fit": ["Y", "R", "mu0", "A"],
+    "dgn_request": ["Y", "R", "mu0", "tol", "max_iters", "A", "tag"],
+    "dgn_result": ["id", "tag", "status", "info", "t_submit", "t_admit", "t_done"],
+}
+
+
+def test_binding_struct_layout_matches_header(tmp_path):
+    """Every struct of the header has the size and field offsets the ctypes binding
+    assumes (compiled against include/dgn.h with the host C compiler)."""
+    import shutil
+    import subprocess
+    from paper_1205_2584_amd import dgn
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "dgn.h"', "int main(void) {"]
+    for s, fields in STRUCTS.items():
+        lines.append(f'  printf("{s} size %zu\\n", sizeof({s}));')
+        for f in fields:
+            lines.append(f'  printf("{s} {f} %zu\\n", offsetof({s}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for ln in out:
+        if ln:
+            parts = ln.split()
+            got[tuple(parts[:-1])] = int(parts[-1])
+    for s, fields in STRUCTS.items():
+        cls = getattr(dgn, s)
+        assert got[(s, "size")] == ctypes.sizeof(cls), s
+        assert [n for n, _ in cls._fields_] == fields, s
+        for f in fields:
+            assert got[(s, f)] == getattr(cls, f).offset, (s, f)

@@ -4,7 +4,9 @@ Tolerances (derived from the arithmetic, stated per test):
 * FP64 tensor pass: normwise relative error <= 1e-12 (J-term sums in FP64).
 * FP32 pass: <= 2e-5 (FP32 products of FP32-rounded factors, FP32 partial
   sums over at most a few hundred slabs, FP64 final reduction).
-* BF16 tensor: <= 2e-2 (factors may be rounded to BF16 on the MFMA path).
+* BF16 tensor: <= 4e-5 against the MTTKRP of the BF16-rounded tensor (the
+  factors enter the BF16 matrix cores as hi + lo pairs, 2^-18 relative each;
+  FP32 products and partial sums).
 * FP64 step: relative update error <= 1e-9 on unconverged inputs
   (||g|| / ||M|| >= 1e-5), the bar of the stated target.
 """
@@ -47,7 +49,7 @@ def _quantize(y, dtype):
 
 
 @pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-12), (torch.float32, 2e-5),
-                                       (torch.bfloat16, 2e-2)])
+                                       (torch.bfloat16, 4e-5)])
 @pytest.mark.parametrize("shape", MTTKRP_SHAPES)
 def test_mttkrp_all_modes(ctx, shape, dtype, tol):
     dims, R = shape
