@@ -184,7 +184,8 @@ void dgn_opts_default(dgn_opts* opts);
  * DGN_ENOMEM; dgn_workspace_size() gives the requirement. */
 dgn_status dgn_create(dgn_ctx** out, int32_t device, size_t ws_budget_bytes);
 dgn_status dgn_destroy(dgn_ctx* ctx);
-/* Message of the last failure on this context ("" if none).  Owned by ctx. */
+/* Message of the last failure on this context ("" if none).  Owned by ctx.
+ * ctx == NULL: the last failure of dgn_step_noalloc on the calling thread. */
 const char* dgn_last_error(const dgn_ctx* ctx);
 
 /* Workspace bytes dgn_step / cp_fit / dgn_mttkrp need for this shape. */
@@ -210,6 +211,25 @@ dgn_status dgn_mttkrp(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, const void* 
 dgn_status dgn_step(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, const void* const* A_in,
                     void* const* A_out, double mu, const dgn_opts* opts, dgn_step_info* info,
                     void* stream);
+
+/* dgn_step for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same step, arguments, outputs and errors as dgn_step, but with no context.
+ * Its workspace is a fixed scratch array inside the library, one per GPU,
+ * of dgn_noalloc_scratch_bytes() bytes (64 MiB), held by every GPU the library
+ * runs on until the process ends; the call allocates nothing and frees
+ * nothing.  The device is the calling thread's current device.  A shape whose
+ * workspace (dgn_workspace_size) exceeds the array gives DGN_ENOMEM with a
+ * message from dgn_last_error(NULL), which also holds the message of any other
+ * failure of this call on this thread.  Every call on one GPU shares that
+ * GPU's array: calls that overlap on one GPU (other host threads, or streams
+ * that run concurrently) race and give wrong results; serialise them.  The
+ * call clears the parts of the array that must start at zero.  Synchronises
+ * the stream before returning. */
+dgn_status dgn_step_noalloc(const dgn_tensor* Y, int32_t R, const void* const* A_in, void* const* A_out,
+                            double mu, const dgn_opts* opts, dgn_step_info* info, void* stream);
+/* Size in bytes of the scratch array of dgn_step_noalloc. */
+size_t dgn_noalloc_scratch_bytes(void);
 
 /* The damped system with any right-hand side: X = (J^T J + mu I)^-1 V, the
  * inverse of H_mu applied in the block form of Section 4.1 (the memory-saving

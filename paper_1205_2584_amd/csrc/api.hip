@@ -3,6 +3,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -59,6 +60,9 @@ struct Arena {
 };
 
 constexpr int kNormParts = 1024;
+
+// Message of the last failing dgn_step_noalloc call on this thread (no context to hold it).
+thread_local std::string g_noalloc_err;
 
 struct Work {
   Shape s;
@@ -419,7 +423,7 @@ dgn_status dgn_destroy(dgn_ctx* ctx) {
   return DGN_OK;
 }
 
-const char* dgn_last_error(const dgn_ctx* ctx) { return ctx ? ctx->err.c_str() : ""; }
+const char* dgn_last_error(const dgn_ctx* ctx) { return ctx ? ctx->err.c_str() : g_noalloc_err.c_str(); }
 
 dgn_status dgn_last_phase_times(const dgn_ctx* ctx, double* ms_out, int32_t n, int32_t* trials) {
   if (!ctx || (!ms_out && n > 0) || n < 0 || n > DGN_NUM_PHASES) return DGN_EINVAL;
@@ -477,10 +481,21 @@ dgn_status dgn_mttkrp(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, const void* 
   return DGN_OK;
 }
 
-dgn_status dgn_step(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, const void* const* A_in,
-                    void* const* A_out, double mu, const dgn_opts* opts, dgn_step_info* info,
-                    void* stream) {
-  if (!ctx) return DGN_EINVAL;
+}  // extern "C"
+
+namespace {
+
+// Zero n ints on the stream with a kernel (no memset node, so the enqueue
+// sequence stays free of hipMemsetAsync).
+__global__ void k_zero_ints(int* p, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
+}
+
+// dgn_step on the workspace of ctx (a context's own arena, or the fixed
+// scratch array of dgn_step_noalloc).
+dgn_status step_impl(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, const void* const* A_in,
+                     void* const* A_out, double mu, const dgn_opts* opts, dgn_step_info* info,
+                     void* stream) {
   if (!A_in || !A_out) return set_err(ctx, DGN_EINVAL, "factor pointer array is NULL");
   if (!(mu > 0.0) || !isfinite(mu)) return set_err(ctx, DGN_EINVAL, "mu must be finite and > 0");
   dgn_opts o;
@@ -506,7 +521,8 @@ dgn_status dgn_step(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, const void* co
   double* e2a = w.scr + 1024;
   double* e2b = w.scr + 1025;
   double* out = w.scr + 1026;  // err2 old, new
-  HIPCHK(hipMemsetAsync(w.flags, 0, 64 * sizeof(int), st), "memset");
+  k_zero_ints<<<1, 64, 0, st>>>(w.flags, 64);
+  HIPCHK(hipGetLastError(), "zero flags");
   HIPCHK(copy_factors_in(w, A_in, w.A, st), "copy factors");
   HIPCHK(run_norm2(ps, J, w.scr, ynp, st), "norm");
   HIPCHK(run_gram(w, w.A, w.sb.C, nullptr, st), "gram");
@@ -537,6 +553,74 @@ dgn_status dgn_step(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, const void* co
   if (flags[0]) return set_err(ctx, DGN_ESINGULAR, "non-positive pivot in (Gamma + mu I) or the NR^2 system");
   if (!isfinite(host[1]) || !isfinite(sc[0])) return set_err(ctx, DGN_ENONFINITE, "non-finite step");
   return DGN_OK;
+}
+
+// The fixed scratch of dgn_step_noalloc: one array per GPU the library runs
+// on (each device holds its own copy at its own address), held until the
+// process ends.  Host code never passes the array's name to a kernel or a
+// copy: the name is a host-side stand-in; the device address comes from
+// hipGetSymbolAddress, once per device, with that device current.
+constexpr size_t kNoAllocBytes = size_t(64) << 20;
+constexpr int kNoAllocMaxDevices = 64;
+static __device__ __align__(256) char scratch[kNoAllocBytes];
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kNoAllocMaxDevices] = {};
+
+}  // namespace
+
+extern "C" {
+
+dgn_status dgn_step(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, const void* const* A_in,
+                    void* const* A_out, double mu, const dgn_opts* opts, dgn_step_info* info,
+                    void* stream) {
+  if (!ctx) return DGN_EINVAL;
+  return step_impl(ctx, Y, R, A_in, A_out, mu, opts, info, stream);
+}
+
+size_t dgn_noalloc_scratch_bytes(void) { return kNoAllocBytes; }
+
+dgn_status dgn_step_noalloc(const dgn_tensor* Y, int32_t R, const void* const* A_in, void* const* A_out,
+                            double mu, const dgn_opts* opts, dgn_step_info* info, void* stream) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kNoAllocMaxDevices) {
+    g_noalloc_err = "dgn_step_noalloc: no usable current device";
+    return DGN_EHIP;
+  }
+  char* base = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+      void* p = nullptr;
+      const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !p) {
+        g_noalloc_err = std::string("dgn_step_noalloc: hipGetSymbolAddress of the scratch array: ") +
+                        hipGetErrorString(e);
+        return DGN_EHIP;
+      }
+      g_scratch_ptr[dev] = static_cast<char*>(p);
+    }
+    base = g_scratch_ptr[dev];
+  }
+  size_t need = 0;
+  dgn_status rc = dgn_workspace_size(Y, R, opts, &need);
+  if (rc != DGN_OK) {
+    g_noalloc_err = "dgn_step_noalloc: bad tensor descriptor or rank";
+    return rc;
+  }
+  if (need > kNoAllocBytes) {
+    g_noalloc_err = "dgn_step_noalloc: this shape needs " + std::to_string(need) +
+                    " bytes of scratch, above the fixed maximum of " + std::to_string(kNoAllocBytes) +
+                    " bytes; use dgn_step with a context";
+    return DGN_ENOMEM;
+  }
+  dgn_ctx c;  // a context over the scratch array: nothing is allocated on the device
+  c.device = dev;
+  c.ws = base;
+  c.ws_size = kNoAllocBytes;
+  c.owns_ws = false;
+  rc = step_impl(&c, Y, R, A_in, A_out, mu, opts, info, stream);
+  g_noalloc_err = rc == DGN_OK ? std::string() : c.err;
+  return rc;
 }
 
 dgn_status dgn_hessian_solve(dgn_ctx* ctx, int32_t order, const int64_t* dims, int32_t R, int32_t dtype,

@@ -82,7 +82,8 @@ EXPORTS = ["dgn_opts_default", "dgn_create", "dgn_destroy", "dgn_last_error", "d
            "dgn_mttkrp", "dgn_step", "dgn_step_explicit", "dgn_workspace_size_explicit", "cp_fit", "cp_als",
            "dgn_mode_gram", "cp_svd_init", "dgn_workspace_size_svd", "dgn_hessian_solve", "dgn_last_phase_times", "cp_fit_batched",
            "dgn_server_create", "dgn_server_submit", "dgn_server_poll", "dgn_server_wait_idle",
-           "dgn_server_stats", "dgn_server_now", "dgn_server_destroy"]
+           "dgn_server_stats", "dgn_server_now", "dgn_server_destroy", "dgn_step_noalloc",
+           "dgn_noalloc_scratch_bytes"]
 NUM_PHASES = 6
 PHASES = ["pre", "assemble", "factor_solve", "update", "tensor_pass", "control"]
 
@@ -133,11 +134,16 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.dgn_server_now.argtypes = [vp]
     L.dgn_server_now.restype = dbl
     L.dgn_server_destroy.argtypes = [vp]
+    L.dgn_step_noalloc.argtypes = [ctypes.POINTER(dgn_tensor), i32, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                   dbl, ctypes.POINTER(dgn_opts), ctypes.POINTER(dgn_step_info), vp]
+    L.dgn_noalloc_scratch_bytes.argtypes = []
+    L.dgn_noalloc_scratch_bytes.restype = ctypes.c_size_t
     for name in ("dgn_create", "dgn_destroy", "dgn_workspace_size", "dgn_mttkrp", "dgn_step", "cp_fit", "cp_als",
                  "dgn_step_explicit", "dgn_workspace_size_explicit",
                  "dgn_mode_gram", "cp_svd_init", "dgn_workspace_size_svd", "dgn_hessian_solve",
                  "dgn_last_phase_times", "cp_fit_batched", "dgn_server_create", "dgn_server_submit",
-                 "dgn_server_poll", "dgn_server_wait_idle", "dgn_server_stats", "dgn_server_destroy"):
+                 "dgn_server_poll", "dgn_server_wait_idle", "dgn_server_stats", "dgn_server_destroy",
+                 "dgn_step_noalloc"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -325,6 +331,24 @@ class Context:
         n = ctypes.c_int32()
         self._check(self.L.dgn_last_phase_times(self.h, ms, NUM_PHASES, ctypes.byref(n)))
         return dict(zip(PHASES, list(ms))), n.value
+
+
+def dgn_step_noalloc(y, dims, R, factors, mu, options: dgn_opts | None = None, out=None):
+    """dgn_step without a context: the library's fixed per-GPU scratch array is the
+    workspace (nothing is allocated on the device).  Runs on the current device."""
+    L = load()
+    out = [torch.empty_like(a) for a in factors] if out is None else out
+    info = dgn_step_info()
+    d = tensor_desc(y, dims)
+    st = L.dgn_step_noalloc(ctypes.byref(d), int(R), _ptrs(factors), _ptrs(out), float(mu),
+                            ctypes.byref(options) if options else None, ctypes.byref(info), _stream())
+    if st != 0:
+        raise DgnError(st, L.dgn_last_error(None).decode())
+    return out, {k: getattr(info, k) for k, _ in dgn_step_info._fields_}
+
+
+def noalloc_scratch_bytes() -> int:
+    return int(load().dgn_noalloc_scratch_bytes())
 
 
 class Server:
