@@ -173,10 +173,17 @@ typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 constexpr int kQMax = 16;  // slabs per block of the MFMA kernels (t and c_q staged in LDS)
 // Slabs in flight ahead of the computed one (the ring of slab registers): the
 // FP32 slab takes about 2k MFMA cycles per wave, the BF16 slab a fraction of
-// that, and both must cover the HBM latency.  kQMax is a multiple of both.
-constexpr int kPrefetchF32 = 2;
-constexpr int kPrefetchBf16 = 4;
-static_assert(kQMax % kPrefetchF32 == 0 && kQMax % kPrefetchBf16 == 0, "sub-chunks align with the ring");
+// that, and both must cover the HBM latency (measured: a ring of two 16 KB
+// slabs per workgroup streams the tensor at 6.2 TB/s when nothing else runs).
+// The compiler waits for the whole ring once per revolution, so the ring is
+// deep enough that a revolution covers that latency; ranks above 32 keep the
+// shorter ring so that two workgroups still fit on a CU.  kQMax is a multiple
+// of every depth.
+template <int NB> constexpr int kPrefetchF32 = NB <= 2 ? 4 : 2;
+template <int NB> constexpr int kPrefetchBf16 = NB <= 2 ? 8 : 4;
+static_assert(kQMax % kPrefetchF32<1> == 0 && kQMax % kPrefetchBf16<1> == 0 && kQMax % kPrefetchF32<4> == 0 &&
+                  kQMax % kPrefetchBf16<4> == 0,
+              "sub-chunks align with the ring");
 
 __device__ __forceinline__ float fac(const PassArgs& a, int mode, int Im, int i, int r) {
   return (i < Im && r < a.R) ? (float)a.A[a.off[mode] + i + (long long)r * Im] : 0.0f;
@@ -230,7 +237,10 @@ __device__ __forceinline__ void write_m(const PassArgs& a, int ti, int tj, int i
   }
 }
 
-template <int NB, bool RESID>
+// VEC: I_1 is a multiple of 4, so every 4-element piece of a slab row is one
+// aligned 16-byte load (a separate instantiation keeps the load sequence free of
+// branches, which lets the compiler wait for each slab's loads alone).
+template <int NB, bool RESID, bool VEC>
 __global__ __launch_bounds__(256) void k_pass_f32(PassArgs a, const int* stop) {
   if (stopped(stop)) return;
   constexpr int LDY = 68;
@@ -251,7 +261,6 @@ __global__ __launch_bounds__(256) void k_pass_f32(PassArgs a, const int* stop) {
   const long long q0 = (long long)blockIdx.y * a.q_per;
   const long long q1 = (q0 + a.q_per < a.Q) ? q0 + a.q_per : a.Q;
   const float* Y = static_cast<const float*>(a.Y);
-  const bool vec_ok = (I0 % 4) == 0;
 
   float b1[16][NB], b0[16][NB], a0t[NB][4];
 #pragma unroll
@@ -278,32 +287,48 @@ __global__ __launch_bounds__(256) void k_pass_f32(PassArgs a, const int* stop) {
   for (int nb = 0; nb < NB; ++nb) { m0acc[nb] = v4f{0, 0, 0, 0}; m1acc[nb] = v4f{0, 0, 0, 0}; }
   double e2 = 0.0;
 
-  // slab loads run kPrefetchF32 slabs ahead of the slab being computed
-  v4f pf[kPrefetchF32][4];
+  // Slab loads run kPrefetchF32<NB> slabs ahead of the slab being computed.  Every
+  // load is unconditional (a piece outside the tensor reads the slab's first
+  // elements) and the piece is masked when it is stored to LDS: a load under a
+  // branch makes the compiler wait for all outstanding loads (vmcnt(0)) before
+  // the slab store, which serialised the ring.  pn: elements of the piece inside
+  // the tensor (0..4); poff: its offset within the slab.
+  long long poff[4];
+  int pn[4];
+#pragma unroll
+  for (int s2 = 0; s2 < 4; ++s2) {
+    const int e = t + 256 * s2, jj = e >> 4, ii = (e & 15) * 4;
+    const int gi = i0 + ii, gj = j0 + jj;
+    const int n = (gj < I1) ? (I0 - gi < 0 ? 0 : (I0 - gi > 4 ? 4 : I0 - gi)) : 0;
+    pn[s2] = n;
+    poff[s2] = n > 0 ? (long long)gj * I0 + gi : 0;
+  }
+  v4f pf[kPrefetchF32<NB>][4];
   auto load = [&](long long q, v4f (&dst)[4]) {
-    const long long base = (long long)I0 * I1 * q;
+    const float* base = Y + (long long)I0 * I1 * q;
+    if constexpr (VEC) {
 #pragma unroll
-    for (int s2 = 0; s2 < 4; ++s2) {
-      const int e = t + 256 * s2, jj = e >> 4, ii = (e & 15) * 4;
-      const int gi = i0 + ii, gj = j0 + jj;
-      v4f v = v4f{0, 0, 0, 0};
-      if (gj < I1) {
-        const float* src = Y + base + (long long)gj * I0 + gi;
-        if (vec_ok && gi + 3 < I0) {
-          v = *reinterpret_cast<const v4f*>(src);
-        } else {
+      for (int s2 = 0; s2 < 4; ++s2) dst[s2] = *reinterpret_cast<const v4f*>(base + poff[s2]);
+    } else {
 #pragma unroll
-          for (int k = 0; k < 4; ++k) v[k] = (gi + k < I0) ? src[k] : 0.0f;
-        }
-      }
-      dst[s2] = v;
+      for (int s2 = 0; s2 < 4; ++s2)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) dst[s2][k] = base[poff[s2] + (k < pn[s2] ? k : 0)];
     }
   };
-
+  auto masked = [&](const v4f& v, int s2) {
+    v4f m;
 #pragma unroll
-  for (int d = 0; d < kPrefetchF32; ++d)
-    if (q0 + d < q1) load(q0 + d, pf[d]);
-  for (long long qb = q0; qb < q1; qb += kPrefetchF32) {
+    for (int k = 0; k < 4; ++k) m[k] = k < pn[s2] ? v[k] : 0.0f;
+    return m;
+  };
+
+  // the ring is filled and refilled unconditionally (past the chunk's end the
+  // last slab is read again and never used), so every load of the loop sits
+  // on the straight-line path and each slab waits only for its own loads
+#pragma unroll
+  for (int d = 0; d < kPrefetchF32<NB>; ++d) load(q0 + d < q1 ? q0 + d : q1 - 1, pf[d]);
+  for (long long qb = q0; qb < q1; qb += kPrefetchF32<NB>) {
   if ((qb - q0) % kQMax == 0) {
     // new sub-chunk of at most kQMax slabs: t of the previous one flushed, c_q staged
     if (qb > q0) flush_t(a, tq_s, qb - kQMax, qb, tile);
@@ -314,19 +339,22 @@ __global__ __launch_bounds__(256) void k_pass_f32(PassArgs a, const int* stop) {
     }
   }
 #pragma unroll
-  for (int d = 0; d < kPrefetchF32; ++d) {
+  for (int d = 0; d < kPrefetchF32<NB>; ++d) {
     const long long q = qb + d;
-    if (q >= q1) break;
+    const bool live = q < q1;  // uniform over the workgroup
     const int ql = (int)((q - q0) % kQMax);
     float (*Ys)[LDY] = Ysb[(q - q0) & (NBUF - 1)];
-    if (NBUF == 1) sync_block();
+    if (live) {
+      if (NBUF == 1) sync_block();
 #pragma unroll
-    for (int s2 = 0; s2 < 4; ++s2) {
-      const int e = t + 256 * s2, jj = e >> 4, ii = (e & 15) * 4;
-      *reinterpret_cast<v4f*>(&Ys[jj][ii]) = pf[d][s2];
+      for (int s2 = 0; s2 < 4; ++s2) {
+        const int e = t + 256 * s2, jj = e >> 4, ii = (e & 15) * 4;
+        *reinterpret_cast<v4f*>(&Ys[jj][ii]) = masked(pf[d][s2], s2);
+      }
     }
+    load(q + kPrefetchF32<NB> < q1 ? q + kPrefetchF32<NB> : q1 - 1, pf[d]);
+    if (!live) continue;
     const float* cq_s = cq_all[ql];
-    if (q + kPrefetchF32 < q1) load(q + kPrefetchF32, pf[d]);
     sync_block();
     if (RESID) {
       constexpr int KS = NB * 4;  // R padded to 16, in steps of 4
@@ -397,7 +425,7 @@ __device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
 // BF16 tensor: 16x16x32 BF16 MFMA with FP32 accumulation.  Factors enter as
 // hi + lo BF16 pairs (two instructions), so only the tensor's own rounding
 // remains at the BF16 level.
-template <int NB>
+template <int NB, bool VEC>
 __global__ __launch_bounds__(256) void k_pass_bf16(PassArgs a, const int* stop) {
   if (stopped(stop)) return;
   constexpr int LDY = 72;
@@ -412,7 +440,6 @@ __global__ __launch_bounds__(256) void k_pass_bf16(PassArgs a, const int* stop) 
   const long long q0 = (long long)blockIdx.y * a.q_per;
   const long long q1 = (q0 + a.q_per < a.Q) ? q0 + a.q_per : a.Q;
   const __bf16* Y = static_cast<const __bf16*>(a.Y);
-  const bool vec_ok = (I0 % 4) == 0;
 
   v8bf b1h[2][NB], b1l[2][NB], b0h[2][NB], b0l[2][NB];
   float a0t[NB][4];
@@ -440,11 +467,13 @@ __global__ __launch_bounds__(256) void k_pass_bf16(PassArgs a, const int* stop) 
   for (int nb = 0; nb < NB; ++nb) { m0acc[nb] = v4f{0, 0, 0, 0}; m1acc[nb] = v4f{0, 0, 0, 0}; }
 
   typedef unsigned short us4 __attribute__((ext_vector_type(4)));
-  // slab loads run kPrefetchBf16 slabs ahead of the slab being computed
-  us4 pf[kPrefetchBf16][4];
+  // slab loads run kPrefetchBf16<NB> slabs ahead of the slab being computed
+  us4 pf[kPrefetchBf16<NB>][4];
   // this thread's four 4-element pieces of a slab: offset within the slab and
   // how many of the 4 elements lie inside the tensor (an out-of-range piece
-  // reads the slab's first element and is zeroed, so every load is unconditional)
+  // reads the slab's first element; every load is unconditional and the piece
+  // is masked only when it is stored to LDS, so that the compiler waits for
+  // each slab's own loads and not for the whole ring)
   long long poff[4];
   int pn[4];
 #pragma unroll
@@ -457,29 +486,28 @@ __global__ __launch_bounds__(256) void k_pass_bf16(PassArgs a, const int* stop) 
   }
   auto load = [&](long long q, us4 (&dst)[4]) {
     const unsigned short* base = reinterpret_cast<const unsigned short*>(Y) + (long long)I0 * I1 * q;
-    if (vec_ok) {
+    if constexpr (VEC) {
 #pragma unroll
-      for (int s2 = 0; s2 < 4; ++s2) {
-        const us4 v = *reinterpret_cast<const us4*>(base + poff[s2]);
-        dst[s2] = pn[s2] == 4 ? v : us4{0, 0, 0, 0};
-      }
+      for (int s2 = 0; s2 < 4; ++s2) dst[s2] = *reinterpret_cast<const us4*>(base + poff[s2]);
     } else {
 #pragma unroll
-      for (int s2 = 0; s2 < 4; ++s2) {
-        us4 v;
+      for (int s2 = 0; s2 < 4; ++s2)
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const unsigned short x = base[poff[s2] + (k < pn[s2] ? k : 0)];
-          v[k] = k < pn[s2] ? x : (unsigned short)0;
-        }
-        dst[s2] = v;
-      }
+        for (int k = 0; k < 4; ++k) dst[s2][k] = base[poff[s2] + (k < pn[s2] ? k : 0)];
     }
   };
+  auto masked = [&](const us4& v, int s2) {
+    us4 m;
 #pragma unroll
-  for (int d = 0; d < kPrefetchBf16; ++d)
-    if (q0 + d < q1) load(q0 + d, pf[d]);
-  for (long long qb = q0; qb < q1; qb += kPrefetchBf16) {
+    for (int k = 0; k < 4; ++k) m[k] = k < pn[s2] ? v[k] : (unsigned short)0;
+    return m;
+  };
+  // the ring is filled and refilled unconditionally (past the chunk's end the
+  // last slab is read again and never used), so every load of the loop sits
+  // on the straight-line path and each slab waits only for its own loads
+#pragma unroll
+  for (int d = 0; d < kPrefetchBf16<NB>; ++d) load(q0 + d < q1 ? q0 + d : q1 - 1, pf[d]);
+  for (long long qb = q0; qb < q1; qb += kPrefetchBf16<NB>) {
   if ((qb - q0) % kQMax == 0) {
     // new sub-chunk of at most kQMax slabs: t of the previous one flushed, c_q staged
     if (qb > q0) flush_t(a, tq_s, qb - kQMax, qb, tile);
@@ -490,18 +518,21 @@ __global__ __launch_bounds__(256) void k_pass_bf16(PassArgs a, const int* stop) 
     }
   }
 #pragma unroll
-  for (int d = 0; d < kPrefetchBf16; ++d) {
+  for (int d = 0; d < kPrefetchBf16<NB>; ++d) {
     const long long q = qb + d;
-    if (q >= q1) break;
+    const bool live = q < q1;  // uniform over the workgroup
     const int ql = (int)((q - q0) % kQMax);
     __bf16 (*Ys)[LDY] = Ysb[(q - q0) & 1];
+    if (live) {
 #pragma unroll
-    for (int s2 = 0; s2 < 4; ++s2) {
-      const int e = t + 256 * s2, jj = e >> 4, ii = (e & 15) * 4;
-      *reinterpret_cast<us4*>(&Ys[jj][ii]) = pf[d][s2];
+      for (int s2 = 0; s2 < 4; ++s2) {
+        const int e = t + 256 * s2, jj = e >> 4, ii = (e & 15) * 4;
+        *reinterpret_cast<us4*>(&Ys[jj][ii]) = masked(pf[d][s2], s2);
+      }
     }
+    load(q + kPrefetchBf16<NB> < q1 ? q + kPrefetchBf16<NB> : q1 - 1, pf[d]);
+    if (!live) continue;
     const float* cq_s = cq_all[ql];
-    if (q + kPrefetchBf16 < q1) load(q + kPrefetchBf16, pf[d]);
     sync_block();
     v4f zacc[NB], wacc[NB];
 #pragma unroll
@@ -690,22 +721,31 @@ hipError_t launch_tensor_pass(const Shape& s, YType yt, const void* Y, const dou
     if (resid) k_pass_fma<double, double, true><<<grid, 256, 0, st>>>(a, stop);
     else k_pass_fma<double, double, false><<<grid, 256, 0, st>>>(a, stop);
   } else if (yt == YType::F32) {
-#define F32_CASE(nb)                                                        \
-  case nb:                                                                  \
-    if (resid) k_pass_f32<nb, true><<<grid, 256, 0, st>>>(a, stop);         \
-    else k_pass_f32<nb, false><<<grid, 256, 0, st>>>(a, stop);              \
+    // 16-byte pieces need I_1 % 4 == 0 and a 16-byte aligned tensor
+    const bool vec = (s.I[0] % 4) == 0 && (reinterpret_cast<uintptr_t>(Y) % 16) == 0;
+#define F32_CASE(nb)                                                                     \
+  case nb:                                                                               \
+    if (vec) {                                                                           \
+      if (resid) k_pass_f32<nb, true, true><<<grid, 256, 0, st>>>(a, stop);              \
+      else k_pass_f32<nb, false, true><<<grid, 256, 0, st>>>(a, stop);                   \
+    } else {                                                                             \
+      if (resid) k_pass_f32<nb, true, false><<<grid, 256, 0, st>>>(a, stop);             \
+      else k_pass_f32<nb, false, false><<<grid, 256, 0, st>>>(a, stop);                  \
+    }                                                                                    \
     break;
     switch (NB) { F32_CASE(1) F32_CASE(2) F32_CASE(3) F32_CASE(4) default: return hipErrorInvalidValue; }
 #undef F32_CASE
   } else {
     if (resid) return hipErrorInvalidValue;  // the residual pass reads the FP32 tensor
-    switch (NB) {
-      case 1: k_pass_bf16<1><<<grid, 256, 0, st>>>(a, stop); break;
-      case 2: k_pass_bf16<2><<<grid, 256, 0, st>>>(a, stop); break;
-      case 3: k_pass_bf16<3><<<grid, 256, 0, st>>>(a, stop); break;
-      case 4: k_pass_bf16<4><<<grid, 256, 0, st>>>(a, stop); break;
-      default: return hipErrorInvalidValue;
-    }
+    // 8-byte pieces need I_1 % 4 == 0 and an 8-byte aligned tensor
+    const bool vec = (s.I[0] % 4) == 0 && (reinterpret_cast<uintptr_t>(Y) % 8) == 0;
+#define BF16_CASE(nb)                                                      \
+  case nb:                                                                 \
+    if (vec) k_pass_bf16<nb, true><<<grid, 256, 0, st>>>(a, stop);         \
+    else k_pass_bf16<nb, false><<<grid, 256, 0, st>>>(a, stop);            \
+    break;
+    switch (NB) { BF16_CASE(1) BF16_CASE(2) BF16_CASE(3) BF16_CASE(4) default: return hipErrorInvalidValue; }
+#undef BF16_CASE
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
