@@ -202,6 +202,46 @@ __device__ __forceinline__ float cq_of(const PassArgs& a, long long q, int r) {
   return (float)c;
 }
 
+// c_q of a sub-chunk of kQMax slabs starting at qs: thread t holds the entries
+// e = t + 256 k (slab qs + e / 64, rank e % 64).  For order 3 c_q is a row of
+// A^(3), read with unconditional loads (clamped indices, masked on use) one
+// sub-chunk ahead of its use, so that its wait never drains the slab ring;
+// higher orders form the products when the sub-chunk starts.
+struct CqFetch {
+  double v[4];
+};
+__device__ __forceinline__ void cq_prefetch(const PassArgs& a, long long qs, CqFetch& f) {
+  if (a.N != 3) return;
+  const int I3 = a.It[0];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int e = threadIdx.x + 256 * k, r = e & 63;
+    const long long q = qs + (e >> 6);
+    const long long qc = q < a.Q ? q : a.Q - 1;
+    const int rc = r < a.R ? r : a.R - 1;
+    f.v[k] = a.A[a.off[2] + qc + (long long)rc * I3];
+  }
+}
+__device__ __forceinline__ void cq_stage(const PassArgs& a, long long qs, long long q1, const CqFetch& f,
+                                         float (*cq_all)[64]) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int e = threadIdx.x + 256 * k, ql = e >> 6, r = e & 63;
+    const bool ok = qs + ql < q1 && r < a.R;
+    cq_all[ql][r] = ok ? (a.N == 3 ? (float)f.v[k] : cq_of(a, qs + ql, r)) : 0.0f;
+  }
+}
+
+// Sum over the four 16-lane rows of the wave (lane l gets the sum over the lanes
+// l mod 16 + 16 g): one swap of odd and even rows, then of the two halves, in
+// the order ((x0 + x1) + (x2 + x3)) for the lanes of row 0.
+__device__ __forceinline__ float sum_rows(float x) {
+  const auto p = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+  const float y = __uint_as_float(p[0]) + __uint_as_float(p[1]);
+  const auto q = __builtin_amdgcn_permlane32_swap(__float_as_uint(y), __float_as_uint(y), false, false);
+  return __uint_as_float(q[0]) + __uint_as_float(q[1]);
+}
+
 // t of the slabs [q0, q1) (at most kQMax, staged per wave in LDS) to the tile's partial.
 __device__ __forceinline__ void flush_t(const PassArgs& a, float (*tq_s)[kQMax][64], long long q0, long long q1,
                                         int tile) {
@@ -328,15 +368,15 @@ __global__ __launch_bounds__(256) void k_pass_f32(PassArgs a, const int* stop) {
   // on the straight-line path and each slab waits only for its own loads
 #pragma unroll
   for (int d = 0; d < kPrefetchF32<NB>; ++d) load(q0 + d < q1 ? q0 + d : q1 - 1, pf[d]);
+  CqFetch cqf;
+  cq_prefetch(a, q0, cqf);
   for (long long qb = q0; qb < q1; qb += kPrefetchF32<NB>) {
   if ((qb - q0) % kQMax == 0) {
-    // new sub-chunk of at most kQMax slabs: t of the previous one flushed, c_q staged
+    // new sub-chunk of at most kQMax slabs: t of the previous one flushed, c_q
+    // staged from the prefetched values, the next sub-chunk's c_q fetched
     if (qb > q0) flush_t(a, tq_s, qb - kQMax, qb, tile);
-    const long long sq1 = (qb + kQMax < q1) ? qb + kQMax : q1;
-    for (int e = t; e < kQMax * 64; e += 256) {
-      const int ql = e >> 6, r = e & 63;
-      cq_all[ql][r] = (qb + ql < sq1) ? cq_of(a, qb + ql, r) : 0.0f;
-    }
+    cq_stage(a, qb, q1, cqf, cq_all);
+    cq_prefetch(a, qb + kQMax, cqf);
   }
 #pragma unroll
   for (int d = 0; d < kPrefetchF32<NB>; ++d) {
@@ -401,10 +441,8 @@ __global__ __launch_bounds__(256) void k_pass_f32(PassArgs a, const int* stop) {
       const float c = cq_s[16 * nb + c16];
       m0acc[nb] += c * zacc[nb];
       m1acc[nb] += c * wacc[nb];
-      float tv = a0t[nb][0] * zacc[nb][0] + a0t[nb][1] * zacc[nb][1] + a0t[nb][2] * zacc[nb][2] +
-                 a0t[nb][3] * zacc[nb][3];
-      tv += __shfl_xor(tv, 16, 64);
-      tv += __shfl_xor(tv, 32, 64);
+      const float tv = sum_rows(a0t[nb][0] * zacc[nb][0] + a0t[nb][1] * zacc[nb][1] + a0t[nb][2] * zacc[nb][2] +
+                                a0t[nb][3] * zacc[nb][3]);
       if (g == 0) tq_s[w][ql][16 * nb + c16] = tv;
     }
   }
@@ -507,15 +545,15 @@ __global__ __launch_bounds__(256) void k_pass_bf16(PassArgs a, const int* stop) 
   // on the straight-line path and each slab waits only for its own loads
 #pragma unroll
   for (int d = 0; d < kPrefetchBf16<NB>; ++d) load(q0 + d < q1 ? q0 + d : q1 - 1, pf[d]);
+  CqFetch cqf;
+  cq_prefetch(a, q0, cqf);
   for (long long qb = q0; qb < q1; qb += kPrefetchBf16<NB>) {
   if ((qb - q0) % kQMax == 0) {
-    // new sub-chunk of at most kQMax slabs: t of the previous one flushed, c_q staged
+    // new sub-chunk of at most kQMax slabs: t of the previous one flushed, c_q
+    // staged from the prefetched values, the next sub-chunk's c_q fetched
     if (qb > q0) flush_t(a, tq_s, qb - kQMax, qb, tile);
-    const long long sq1 = (qb + kQMax < q1) ? qb + kQMax : q1;
-    for (int e = t; e < kQMax * 64; e += 256) {
-      const int ql = e >> 6, r = e & 63;
-      cq_all[ql][r] = (qb + ql < sq1) ? cq_of(a, qb + ql, r) : 0.0f;
-    }
+    cq_stage(a, qb, q1, cqf, cq_all);
+    cq_prefetch(a, qb + kQMax, cqf);
   }
 #pragma unroll
   for (int d = 0; d < kPrefetchBf16<NB>; ++d) {
@@ -559,10 +597,8 @@ __global__ __launch_bounds__(256) void k_pass_bf16(PassArgs a, const int* stop) 
       const float c = cq_s[16 * nb + c16];
       m0acc[nb] += c * zacc[nb];
       m1acc[nb] += c * wacc[nb];
-      float tv = a0t[nb][0] * zacc[nb][0] + a0t[nb][1] * zacc[nb][1] + a0t[nb][2] * zacc[nb][2] +
-                 a0t[nb][3] * zacc[nb][3];
-      tv += __shfl_xor(tv, 16, 64);
-      tv += __shfl_xor(tv, 32, 64);
+      const float tv = sum_rows(a0t[nb][0] * zacc[nb][0] + a0t[nb][1] * zacc[nb][1] + a0t[nb][2] * zacc[nb][2] +
+                                a0t[nb][3] * zacc[nb][3]);
       if (g == 0) tq_s[w][ql][16 * nb + c16] = tv;
     }
   }
