@@ -262,7 +262,7 @@ __device__ __forceinline__ void panel_trail_block(int b, int kb, int& bi, int& b
 // 16-blocks by forward substitution (wave w inverts block w, lane j a column),
 // then the blocks at distance d = 1..3 below the diagonal:
 //   X_ij = -X_ii sum_{k=j}^{i-1} L_ik X_kj.
-__device__ void invert_lower64(double (*T)[TR], double (*X)[TR], const double* rinv, double (*Z)[16][17]) {
+__device__ void invert_lower64(double (*T)[TR], double (*X)[TR], const double* rinv, double (*Z)[16][16]) {
   const int t = threadIdx.x, w = t >> 6, lane = t & 63, cl = lane & 15, kq = lane >> 4;
   {
     const int b0 = 16 * w, j = cl;
@@ -541,18 +541,187 @@ __device__ __forceinline__ void barrier3(int* ctr, int& epoch, int* bad) {
   wait_at_least(ctr, 3 * epoch, bad);
 }
 
+// ---- solution by Gauss-Jordan elimination on the factor --------------------------
+//
+// The backward substitution y_k = L_kk^-T (w_k - sum_{m > k} L_mk^T y_m) (w the
+// forward-substituted right-hand side, which rides along the factorisation) is
+// carried along the phases instead of after them.  Step s (tile column s
+// factored) writes a_s = L_ss^-T w_s and G_sm = L_ss^-T L_ms^T (m > s), so that
+// y_s = a_s - sum_{m > s} G_sm y_m; step s then eliminates y_s from every
+// earlier relation: a_k -= G_ks a_s and G_km -= G_ks G_sm (k < s < m).  After
+// the last step y_k = a_k.  G_km lives in the upper tile (k, m) of St, which the
+// factorisation never touches, and a in yt.  The launch of phase ph writes step
+// ph - 1 and eliminates with step ph - 2, so every operand comes from an earlier
+// launch; these blocks run beside the panel of phase ph and are off its critical
+// path.  Two launches after the last phase finish the elimination.
+__host__ __device__ inline int phase_panels(const SysPlan& p, int ph) { return ph < p.Tt ? p.Tt - ph + 1 : 0; }
+__host__ __device__ inline long long phase_trailing(const SysPlan& p, int ph) {
+  if (ph <= 0 || ph >= p.Tt) return 0;
+  long long n = 0;
+  for (int j = ph + 1; j < p.Tt; ++j) n += p.Tt - j + 1;
+  return n;
+}
+// Tiles of a row per block (measured at 500^3, R = 30: one tile per block keeps
+// the phases shortest; three per block made them 0.4 us longer on average).
+constexpr int kGjGroup = 1;
+__host__ __device__ inline int gj_groups(const SysPlan& p, int s) { return (p.Tt - 1 - s + kGjGroup - 1) / kGjGroup; }
+// write blocks of step s: groups of the tiles G_sm, m in (s, Tt - 1], then the vector a_s
+__host__ __device__ inline long long gj_writes(const SysPlan& p, int s) { return (s >= 0 && s < p.Tt) ? gj_groups(p, s) + 1 : 0; }
+// elimination blocks of step s: groups of the tiles (k, m), k < s < m < Tt, then the vectors a_k, k < s
+__host__ __device__ inline long long gj_elims(const SysPlan& p, int s) {
+  return (s >= 0 && s < p.Tt) ? (long long)s * gj_groups(p, s) + s : 0;
+}
+__host__ inline long long phase_blocks(const SysPlan& p, int ph) {
+  return phase_panels(p, ph) + phase_trailing(p, ph) + gj_writes(p, ph - 1) + gj_elims(p, ph - 2);
+}
+
+// X = L_ss^-1 (rows 64..127 of T) from the factored diagonal tile Ld[s].
+__device__ void gj_inverse(const SysPlan& p, const double* Ld, int s, double (*T)[TR], double* rinv,
+                           double (*Z)[16][16]) {
+  stage_panel(T, Ld + (long long)s * 64 * 64, 64);
+  // invert_lower64 writes the lower blocks of X only: the blocks above the
+  // diagonal start at zero, since the products below sum over whole rows
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) T[64 + (e >> 6)][e & 63] = 0.0;
+  sync_block();
+  if (threadIdx.x < 64) rinv[threadIdx.x] = 1.0 / T[threadIdx.x][threadIdx.x];
+  sync_block();
+  invert_lower64(T, T + 64, rinv, Z);
+  sync_block();
+}
+
+// The blocks reuse the phase kernel's LDS: T (128 x TR), rinv (64) and the
+// 4 x 16 x 16 panel array Lk (the inversion's scratch); the partial sums of the
+// vector blocks go to the first 256 doubles of T once T's first rows are free.
+__device__ void gj_block(const SysPlan& p, int ph, double* St, const double* Ld, double* yt, long long id,
+                         double (*T)[TR], double* rinv, double (*Z)[16][16]) {
+  double* vec = rinv;
+  double (*part)[64] = reinterpret_cast<double (*)[64]>(&T[0][0]);
+  const long long lds = p.lds;
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63, cl = lane & 15, kq = lane >> 4;
+  const int sw = ph - 1, se = ph - 2;
+  const long long nw = gj_writes(p, sw);
+  if (id < nw) {
+    // step sw: G_sw,m = (L(m, sw) X)^T, or the vector a_sw = X^T w_sw
+    gj_inverse(p, Ld, sw, T, rinv, Z);
+    const double (*X)[TR] = T + 64;
+    if (id == nw - 1) {
+      if (t < 64) vec[t] = St[p.ntp + (long long)(64 * sw + t) * lds];
+      sync_block();
+      // a[c] = sum_r X[r][c] w[r]; wave g sums r = g, g + 4, ...
+      double acc = 0.0;
+#pragma unroll
+      for (int s2 = 0; s2 < 16; ++s2) {
+        const int r = w + 4 * s2;
+        acc += X[r][lane] * vec[r];
+      }
+      part[w][lane] = acc;
+      sync_block();
+      if (t < 64) yt[64 * sw + t] = (part[0][t] + part[1][t]) + (part[2][t] + part[3][t]);
+      return;
+    }
+    const int m0 = sw + 1 + kGjGroup * (int)id;
+    const int m1 = m0 + kGjGroup < p.Tt ? m0 + kGjGroup : p.Tt;
+    for (int m = m0; m < m1; ++m) {
+      const double* A = St + 64 * m + (long long)(64 * sw) * lds;  // L(m, sw), column-major
+      // P = A X: wave w forms rows 16w.. of P; lane: A[16w + cl][k0 + kq], X[k0 + kq][16 blk + cl]
+      double av[16];
+#pragma unroll
+      for (int s2 = 0; s2 < 16; ++s2) av[s2] = A[(16 * w + cl) + (long long)(4 * s2 + kq) * lds];
+      v4d acc[4];
+      zero_acc(acc);
+#pragma unroll
+      for (int s2 = 0; s2 < 16; ++s2)
+#pragma unroll
+        for (int blk = 0; blk < 4; ++blk)
+          acc[blk] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s2], X[4 * s2 + kq][16 * blk + cl], acc[blk], 0, 0, 0);
+      // acc[blk][v] = P[16w + kq + 4v][16blk + cl] = G[16blk + cl][16w + kq + 4v]
+      double* G = St + 64 * sw + (long long)(64 * m) * lds;
+#pragma unroll
+      for (int blk = 0; blk < 4; ++blk)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) G[(16 * blk + cl) + (long long)(16 * w + kq + 4 * v) * lds] = acc[blk][v];
+    }
+    return;
+  }
+  id -= nw;
+  // elimination with step se (its G_se,m and a_se were written by the previous launch)
+  const int ngrp = gj_groups(p, se);
+  const long long ntile = (long long)se * ngrp;
+  if (id < ntile) {
+    const int k = (int)(id / ngrp), m0 = se + 1 + kGjGroup * (int)(id % ngrp);
+    const int m1 = m0 + kGjGroup < p.Tt ? m0 + kGjGroup : p.Tt;
+    // C = G_ks G_sm computed as C^T: A-operand G_sm^T[c][j] = TB[j][c], B-operand G_ks^T[j][r] = TA[j][r];
+    // G_ks is staged once for the group
+    const double* Gks = St + 64 * k + (long long)(64 * se) * lds;  // column-major
+    double (*TA)[TR] = T;       // TA[j][r] = G_ks(r, j)
+    double (*TB)[TR] = T + 64;  // TB[j][c] = G_sm(j, c)
+    for (int m = m0; m < m1; ++m) {
+      const double* Gsm = St + 64 * se + (long long)(64 * m) * lds;
+      double* Gkm = St + 64 * k + (long long)(64 * m) * lds;
+      double va[16], vb[16];
+#pragma unroll
+      for (int s2 = 0; s2 < 16; ++s2) {
+        const int e = t + 256 * s2, r = e & 63, c = e >> 6;
+        if (m == m0) va[s2] = Gks[r + (long long)c * lds];
+        vb[s2] = Gsm[r + (long long)c * lds];
+      }
+      if (m > m0) sync_block();  // the previous tile's products have read TB
+#pragma unroll
+      for (int s2 = 0; s2 < 16; ++s2) {
+        const int e = t + 256 * s2, r = e & 63, c = e >> 6;
+        if (m == m0) TA[c][r] = va[s2];
+        TB[r][c] = vb[s2];
+      }
+      sync_block();
+      v4d acc[4];
+      zero_acc(acc);
+#pragma unroll
+      for (int s2 = 0; s2 < 16; ++s2) {
+        const double a = TB[4 * s2 + kq][16 * w + cl];
+#pragma unroll
+        for (int blk = 0; blk < 4; ++blk)
+          acc[blk] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, TA[4 * s2 + kq][16 * blk + cl], acc[blk], 0, 0, 0);
+      }
+      // acc[blk][v] = C^T[16w + kq + 4v][16blk + cl] = C[16blk + cl][16w + kq + 4v]
+#pragma unroll
+      for (int blk = 0; blk < 4; ++blk)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Gkm[(16 * blk + cl) + (long long)(16 * w + kq + 4 * v) * lds] -= acc[blk][v];
+    }
+    return;
+  }
+  id -= ntile;
+  // a_k -= G_k,se a_se
+  const int k = (int)id;
+  const double* Gks = St + 64 * k + (long long)(64 * se) * lds;
+  if (t < 64) vec[t] = yt[64 * se + t];
+  double g[16];
+#pragma unroll
+  for (int s2 = 0; s2 < 16; ++s2) g[s2] = Gks[lane + (long long)(w + 4 * s2) * lds];
+  sync_block();
+  double acc = 0.0;
+#pragma unroll
+  for (int s2 = 0; s2 < 16; ++s2) acc += g[s2] * vec[w + 4 * s2];
+  part[w][lane] = acc;
+  sync_block();
+  if (t < 64) yt[64 * k + t] -= (part[0][t] + part[1][t]) + (part[2][t] + part[3][t]);
+}
+
 __global__ __launch_bounds__(256, 2) void k_chol_phase(SysPlan p, int ph, double* St, double* Ld,
-                                                       double* Li, int* bad, const int* stop) {
+                                                       double* yt, int* bad, const int* stop) {
   if (stopped(stop)) return;
   __shared__ double T[128][TR];
   __shared__ __align__(16) double Lk[4][16][16];  // L_kk of each column step
   __shared__ double rinv[64];
   __shared__ int step_done, b_count, d_done;
-  const int npanel = p.Tt - ph + 1;
+  const int npanel = phase_panels(p, ph);
   const long long lds = p.lds;
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
   const int cl = lane & 15, kq = lane >> 4;
   if ((int)blockIdx.x < npanel) {
+    // the panel is the critical path of the phase: its waves win instruction
+    // issue over the trailing and Gauss-Jordan blocks that share their CU
+    __builtin_amdgcn_s_setprio(3);
     const int i = ph + blockIdx.x;
     const bool hb = (i != ph);
     const double* Dg = St + ph * 64 + (long long)ph * 64 * lds;
@@ -672,8 +841,12 @@ __global__ __launch_bounds__(256, 2) void k_chol_phase(SysPlan p, int ph, double
     }
     return;
   }
-  if (ph == 0) return;
   long long id = (long long)blockIdx.x - npanel;
+  const long long nupd = phase_trailing(p, ph);
+  if (id >= nupd) {
+    gj_block(p, ph, St, Ld, yt, id - nupd, T, rinv, Lk);
+    return;
+  }
   int j = ph + 1;
   while (id >= (long long)(p.Tt - j + 1)) {
     id -= (p.Tt - j + 1);
@@ -706,169 +879,6 @@ __global__ __launch_bounds__(256, 2) void k_chol_phase(SysPlan p, int ph, double
   for (int blk = 0; blk < 4; ++blk)
 #pragma unroll
     for (int v = 0; v < 4; ++v) C[(16 * blk + cl) + (long long)(16 * w + kq + 4 * v) * lds] -= acc[blk][v];
-}
-
-// L_kk^-1 of every diagonal tile (row-major, into Li), one workgroup per tile,
-// after the factorisation: the inverses only serve the backward substitution.
-__global__ __launch_bounds__(256) void k_inv_diag(SysPlan p, const double* Ld, double* Li, const int* stop) {
-  if (stopped(stop)) return;
-  __shared__ double T[64][TR];
-  __shared__ double X[64][TR];
-  __shared__ double rinv[64];
-  __shared__ double Z[4][16][17];
-  const int k = blockIdx.x, t = threadIdx.x;
-  stage_panel(T, Ld + (long long)k * 64 * 64, 64);
-  sync_block();
-  if (t < 64) rinv[t] = 1.0 / T[t][t];
-  sync_block();
-  invert_lower64(T, X, rinv, Z);
-  double* Xg = Li + (long long)k * 64 * 64;
-  for (int e = t; e < 64 * 64; e += 256) {
-    const int r = e >> 6, c = e & 63;
-    Xg[c + r * 64] = (c <= r) ? X[r][c] : 0.0;
-  }
-}
-
-// Backward substitution, phase k (descending).  Every block forms
-// y_k = L_kk^-T u_k from the inverse tile (u_k is the right-hand-side row of
-// tile column k); block k stores y_k and block j < k updates u_j -= L_kj^T y_k.
-__global__ __launch_bounds__(256) void k_bsolve(SysPlan p, int k, double* St, const double* Li, double* yt,
-                                                const int* stop) {
-  if (stopped(stop)) return;
-  __shared__ double Lt[64][TL];  // staged L(k, j), [col][row]
-  __shared__ double u[64];
-  __shared__ double ys[64];
-  __shared__ double part[4][64];
-  const long long lds = p.lds;
-  const int t = threadIdx.x, j = blockIdx.x, c = t & 63, g = t >> 6;
-  if (t < 64) u[t] = St[p.ntp + (long long)(k * 64 + t) * lds];
-  if (j != k) stage(Lt, St + k * 64 + (long long)j * 64 * lds, lds);
-  sync_block();
-  // y_k[c] = sum_r X[r][c] u[r], X = L_kk^-1 stored row-major
-  const double* X = Li + (long long)k * 64 * 64;
-  double acc = 0.0;
-#pragma unroll
-  for (int s2 = 0; s2 < 16; ++s2) {
-    const int r = g + 4 * s2;
-    acc += X[r * 64 + c] * u[r];
-  }
-  part[g][c] = acc;
-  sync_block();
-  if (t < 64) ys[t] = part[0][t] + part[1][t] + part[2][t] + part[3][t];
-  sync_block();
-  if (j == k) {
-    if (t < 64) yt[k * 64 + t] = ys[t];
-    return;
-  }
-  // u_j[c] -= sum_r L(k, j)[r][c] y_k[r]
-  acc = 0.0;
-#pragma unroll
-  for (int s2 = 0; s2 < 16; ++s2) {
-    const int r = g + 4 * s2;
-    acc += Lt[c][r] * ys[r];
-  }
-  part[g][c] = acc;
-  sync_block();
-  if (t < 64) {
-    const double v = part[0][t] + part[1][t] + part[2][t] + part[3][t];
-    St[p.ntp + (long long)(j * 64 + t) * lds] -= v;
-  }
-}
-
-// Backward substitution for the tile pair (k, k-1), k >= 1 (descending).  Every
-// block forms y_k = L_kk^-T u_k, u'_{k-1} = u_{k-1} - L(k, k-1)^T y_k and
-// y_{k-1} = L_{k-1,k-1}^-T u'_{k-1} from the inverse tiles; blocks k and k-1
-// store them, block j < k-1 updates u_j -= L(k, j)^T y_k + L(k-1, j)^T y_{k-1}.
-// All loads of a thread are issued before the first product.
-__global__ __launch_bounds__(256) void k_bsolve2(SysPlan p, int k, double* St, const double* Li, double* yt,
-                                                 const int* stop) {
-  if (stopped(stop)) return;
-  __shared__ double Lt[3][64][TL];  // L(k, k-1), L(k, j), L(k-1, j), each [col][row]
-  __shared__ double u[2][64];
-  __shared__ double ys[2][64];
-  __shared__ double part[4][64];
-  const long long lds = p.lds;
-  const int t = threadIdx.x, j = blockIdx.x, c = t & 63, g = t >> 6;
-  const bool upd = j < k - 1;
-  const double* src[3] = {St + k * 64 + (long long)(k - 1) * 64 * lds, upd ? St + k * 64 + (long long)j * 64 * lds : nullptr,
-                          upd ? St + (k - 1) * 64 + (long long)j * 64 * lds : nullptr};
-  const double* Xk = Li + (long long)k * 64 * 64;          // L_kk^-1, row-major
-  const double* Xk1 = Li + (long long)(k - 1) * 64 * 64;
-  double v[3][16], xk[16], xk1[16], u0 = 0.0, u1 = 0.0;
-  if (t < 64) {
-    u0 = St[p.ntp + (long long)(k * 64 + t) * lds];
-    u1 = St[p.ntp + (long long)((k - 1) * 64 + t) * lds];
-  }
-#pragma unroll
-  for (int s2 = 0; s2 < 16; ++s2) {
-    const int r = g + 4 * s2;
-    xk[s2] = Xk[r * 64 + c];
-    xk1[s2] = Xk1[r * 64 + c];
-  }
-#pragma unroll
-  for (int m = 0; m < 3; ++m)
-#pragma unroll
-    for (int s2 = 0; s2 < 16; ++s2) {
-      const int e = t + 256 * s2, rr = e & 63, cc = e >> 6;
-      v[m][s2] = src[m] ? src[m][rr + (long long)cc * lds] : 0.0;
-    }
-  if (t < 64) {
-    u[0][t] = u0;
-    u[1][t] = u1;
-  }
-#pragma unroll
-  for (int m = 0; m < 3; ++m)
-    if (src[m])
-#pragma unroll
-      for (int s2 = 0; s2 < 16; ++s2) {
-        const int e = t + 256 * s2, rr = e & 63, cc = e >> 6;
-        Lt[m][cc][rr] = v[m][s2];
-      }
-  sync_block();
-  // y_k[c] = sum_r X_k[r][c] u_k[r]
-  double acc = 0.0;
-#pragma unroll
-  for (int s2 = 0; s2 < 16; ++s2) acc += xk[s2] * u[0][g + 4 * s2];
-  part[g][c] = acc;
-  sync_block();
-  if (t < 64) ys[0][t] = part[0][t] + part[1][t] + part[2][t] + part[3][t];
-  sync_block();
-  // u_{k-1}[c] -= sum_r L(k, k-1)[r][c] y_k[r]
-  acc = 0.0;
-#pragma unroll
-  for (int s2 = 0; s2 < 16; ++s2) {
-    const int r = g + 4 * s2;
-    acc += Lt[0][c][r] * ys[0][r];
-  }
-  part[g][c] = acc;
-  sync_block();
-  if (t < 64) u[1][t] -= part[0][t] + part[1][t] + part[2][t] + part[3][t];
-  sync_block();
-  // y_{k-1}[c] = sum_r X_{k-1}[r][c] u'_{k-1}[r]
-  acc = 0.0;
-#pragma unroll
-  for (int s2 = 0; s2 < 16; ++s2) acc += xk1[s2] * u[1][g + 4 * s2];
-  part[g][c] = acc;
-  sync_block();
-  if (t < 64) ys[1][t] = part[0][t] + part[1][t] + part[2][t] + part[3][t];
-  sync_block();
-  if (j >= k - 1) {
-    if (t < 64) yt[(long long)j * 64 + t] = ys[j == k ? 0 : 1][t];
-    return;
-  }
-  // u_j[c] -= sum_r L(k, j)[r][c] y_k[r] + L(k-1, j)[r][c] y_{k-1}[r]
-  acc = 0.0;
-#pragma unroll
-  for (int s2 = 0; s2 < 16; ++s2) {
-    const int r = g + 4 * s2;
-    acc += Lt[1][c][r] * ys[0][r] + Lt[2][c][r] * ys[1][r];
-  }
-  part[g][c] = acc;
-  sync_block();
-  if (t < 64) {
-    const double d = part[0][t] + part[1][t] + part[2][t] + part[3][t];
-    St[p.ntp + (long long)(j * 64 + t) * lds] -= d;
-  }
 }
 
 // y_1 = z_1 - B^T y_t (one wave per entry) and y[R^2 + q] = y_t[q].
@@ -953,17 +963,12 @@ SysPlan plan_sys_c(const Shape& s) {
 
 hipError_t launch_sys_factor_solve_core(const SysPlan& p, const SysBuffers& y, int* singular, const int* stop,
                                         hipStream_t st) {
-  for (int ph = 0; ph < p.Tt; ++ph) {
-    const int npanel = p.Tt - ph + 1;
-    long long nupd = 0;
-    if (ph > 0)
-      for (int j = ph + 1; j < p.Tt; ++j) nupd += p.Tt - j + 1;
-    k_chol_phase<<<(unsigned)(npanel + nupd), 256, 0, st>>>(p, ph, y.St, y.Ld, y.Li, singular, stop);
+  // Tt factorisation phases (each also writing and eliminating the solution's
+  // Gauss-Jordan steps), then two launches that finish the elimination
+  for (int ph = 0; ph < p.Tt + 2; ++ph) {
+    const long long nb = phase_blocks(p, ph);
+    if (nb > 0) k_chol_phase<<<(unsigned)nb, 256, 0, st>>>(p, ph, y.St, y.Ld, y.yt, singular, stop);
   }
-  k_inv_diag<<<p.Tt, 256, 0, st>>>(p, y.Ld, y.Li, stop);
-  int k = p.Tt - 1;
-  for (; k >= 1; k -= 2) k_bsolve2<<<k + 1, 256, 0, st>>>(p, k, y.St, y.Li, y.yt, stop);
-  if (k == 0) k_bsolve<<<1, 256, 0, st>>>(p, 0, y.St, y.Li, y.yt, stop);
   return hipGetLastError();
 }
 

@@ -96,7 +96,6 @@ struct SysBuffers {
   double* Ld;   // Tt tiles of 64 x 64 (column-major, leading dimension 64): the factored
                 // diagonal tiles L(k, k). They live apart from St so that, while phase k
                 // runs, every workgroup still reads the unfactored tile (k, k) from St.
-  double* Li;   // Tt tiles of 64 x 64, row-major: L(k, k)^-1, used by the backward substitution
 };
 
 hipError_t launch_sys_assemble(const Shape& s, const SysPlan& p, const SmallBuffers& b,
@@ -105,8 +104,9 @@ hipError_t launch_sys_factor_solve(const Shape& s, const SysPlan& p, const Small
                                    const SysBuffers& y, int* singular, const int* stop,
                                    hipStream_t st);
 // The tiled Cholesky of the lower tiles of y.St with the right-hand-side row
-// (forward substitution inside), the inverse diagonal tiles and the backward
-// substitution into y.yt; any system size with the SysPlan layout.
+// (forward substitution inside) and the backward substitution, carried along
+// the phases as Gauss-Jordan elimination (upper tiles of y.St), into y.yt; any
+// system size with the SysPlan layout.
 hipError_t launch_sys_factor_solve_core(const SysPlan& p, const SysBuffers& y, int* singular, const int* stop,
                                         hipStream_t st);
 
