@@ -125,42 +125,56 @@ def cpu_baseline(p, gpu_check, seconds_cap=30.0):
     return base, gpu_check(first, mu)
 
 
-def bench_batched(dgn, torch, count=1024, max_iters=200, tol=1e-8, seq_sample=8):
-    """1024 independent 3-way fits (I_n ~ U{8..64}, R ~ U{2..8}), FP32 tensors,
-    one cp_fit_batched call vs the same fits one cp_fit at a time (a sample)."""
+def bench_batched(dgn, torch, count=1024, max_iters=200, tol=1e-8, seq_sample=128):
+    """1024 independent 3-way fits (I_n ~ U{8..64}, R ~ U{2..8}), FP32 tensors, in
+    one cp_fit_batched call: the launch shape the library's tuner picks (AUTO), and
+    each shape forced; per-fit latency inside the batch from the device clock; the
+    same fits one cp_fit at a time on a sample of `seq_sample` fits."""
     import numpy as np
     import cpgen
     ps = cpgen.cfg4(count=count, max_iters=max_iters, tol=tol)
     ys = [torch.from_numpy(p.y.astype(np.float32)).cuda() for p in ps]
     ctx = dgn.Context(0, 2 << 30)
-    probs = [(ys[b], p.dims, p.R, dgn.to_device_factors(p.init), -1.0) for b, p in enumerate(ps)]
-    torch.cuda.synchronize()
-    ctx.cp_fit_batched(probs[:64], tol, 2)  # warm-up (module load, graph path)
-    probs = [(ys[b], p.dims, p.R, dgn.to_device_factors(p.init), -1.0) for b, p in enumerate(ps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    infos = ctx.cp_fit_batched(probs, tol, max_iters)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+
+    def run(launch):
+        probs = [(ys[b], p.dims, p.R, dgn.to_device_factors(p.init), -1.0) for b, p in enumerate(ps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        infos = ctx.cp_fit_batched(probs, tol, max_iters, dgn.opts(batched_launch=launch))
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, infos, ctx.batched_last_launch()
+
+    names = {1: "graph", 2: "persistent"}
+    run(0)  # warm-up; the first AUTO call also times both shapes and records the choice
+    dt, infos, used = run(0)
+    shapes = {}
+    for launch in (1, 2):
+        d, _, _ = run(launch)
+        shapes[names[launch]] = round(count / d, 1)
     trials = sum(i["iters"] for i in infos)
+    lat = np.array([i["t_done"] for i in infos]) * 1e3
     # sequential baseline on a sample
     t1 = time.perf_counter()
-    seq_trials = 0
     for b in range(seq_sample):
         A = dgn.to_device_factors(ps[b].init)
-        fi = ctx.cp_fit(ys[b], ps[b].dims, ps[b].R, A, -1.0, tol, max_iters)
-        seq_trials += fi["iters"]
+        ctx.cp_fit(ys[b], ps[b].dims, ps[b].R, A, -1.0, tol, max_iters)
     torch.cuda.synchronize()
     dseq = time.perf_counter() - t1
     ctx.close()
     seq_rate = seq_sample / dseq
+    imax = max(max(p.dims) for p in ps)
+    rmax = max(p.R for p in ps)
+    table = [e for e in dgn.batched_tuning() if e["imax_bucket"] == 16 * ((imax + 15) // 16) and e["rmax"] == rmax]
     return {"fits": count, "fits_per_s": round(count / dt, 1), "wall_s": round(dt, 3),
+            "launch": names.get(used, used), "fits_per_s_by_launch": shapes,
+            "tuner_entry": table[0] if table else None,
             "trials_total": trials, "mean_trials": round(trials / count, 1),
             "sequential_cp_fit_fits_per_s": round(seq_rate, 2),
             "sequential_sample": f"first {seq_sample} fits, one cp_fit call each",
             "speedup_vs_sequential": round((count / dt) / seq_rate, 1),
-            "p50_latency_ms": round(dt * 1e3, 1), "p99_latency_ms": round(dt * 1e3, 1),
-            "latency_note": "all fits of the batch complete with the call"}
+            "p50_latency_ms": round(float(np.percentile(lat, 50)), 2),
+            "p99_latency_ms": round(float(np.percentile(lat, 99)), 2),
+            "latency_note": "per-fit time from the batch's first initial state to the fit's stop (device clock)"}
 
 
 def bench_serving(dgn, torch, n_req=256, rate=2000.0, pool=32, slots=4, seed=5):

@@ -141,10 +141,21 @@ typedef struct dgn_opts {
    * so that a run of rejections grows mu ever faster.  The decrease on an
    * accepted trial is the same under both. */
   int32_t mu_rule;
+  /* cp_fit_batched: how the trials are launched.  DGN_BATCH_GRAPH: one block per
+   * fit per trial, trials replayed from a captured hipGraph (or launched one by
+   * one with graph = 0).  DGN_BATCH_PERSISTENT: one block per CU, each taking the
+   * next fit from a queue (largest first) and running it to its stop.
+   * DGN_BATCH_AUTO (default): the shape the library's tuner measured faster for
+   * batches of this largest mode size (buckets of 16) and largest rank; the first
+   * call with a new key times both shapes on up to 256 of its fits for a few
+   * trials (dgn_batched_tuning lists the table).  Every shape gives each fit the
+   * same result. */
+  int32_t batched_launch;
 } dgn_opts;
 
 typedef enum dgn_solver { DGN_SOLVER_DIRECT = 0, DGN_SOLVER_AUTO = 1 } dgn_solver;
 typedef enum dgn_mu_rule { DGN_MU_PAPER = 0, DGN_MU_NIELSEN = 1 } dgn_mu_rule;
+typedef enum dgn_batch_launch { DGN_BATCH_AUTO = 0, DGN_BATCH_GRAPH = 1, DGN_BATCH_PERSISTENT = 2 } dgn_batch_launch;
 
 /* Result of one trial step (dgn_step). */
 typedef struct dgn_step_info {
@@ -172,6 +183,8 @@ typedef struct dgn_fit_info {
   double mu0;           /* initial damping actually used */
   int32_t cg_trials;    /* DGN_SOLVER_AUTO: trials whose NR^2 system CG solved (else 0) */
   int32_t cg_iters;     /* their CG iterations, summed */
+  double t_done;        /* cp_fit_batched: seconds from the first fit's initial state to this fit's
+                           stop (device clock), the fit's latency inside the batch; 0 elsewhere */
 } dgn_fit_info;
 
 typedef struct dgn_ctx dgn_ctx;
@@ -344,8 +357,8 @@ typedef struct dgn_batch_fit {
 
 /* B independent fits, each run exactly as cp_fit runs it (Algorithm 1 with
  * the damping of Section 4.5, same stop rules, tol and max_iters shared),
- * all advanced together: every trial of every unfinished fit is one block of
- * one kernel launch; the launches are replayed from a captured hipGraph.
+ * all advanced together, launched as opts->batched_launch selects (one block
+ * per fit per trial from a replayed hipGraph, or a persistent queue of fits).
  * Fits stop independently.  infos (host, B entries, may be NULL) receives
  * each fit's result.  The tensor pass reads FP32 data and accumulates in
  * FP64.  Returns DGN_EINVAL if a fit is outside the supported shapes (order
@@ -353,6 +366,22 @@ typedef struct dgn_batch_fit {
 dgn_status cp_fit_batched(dgn_ctx* ctx, int32_t B, const dgn_batch_fit* fits, double tol,
                           int32_t max_iters, const dgn_opts* opts, dgn_fit_info* infos,
                           void* stream);
+
+/* One entry of the batched tuner's table: batches whose largest mode size is at
+ * most imax_bucket (a multiple of 16) and whose largest rank is rmax run with
+ * `launch` (dgn_batch_launch); the measured microseconds per fit-trial of each
+ * shape on the sample (sample_fits fits, sample_trials trials from their starts). */
+typedef struct dgn_batch_tune_entry {
+  int32_t imax_bucket, rmax, launch;
+  double us_per_trial_graph, us_per_trial_persistent;
+  int32_t sample_fits, sample_trials;
+} dgn_batch_tune_entry;
+
+/* Copy up to max entries of the process-wide tuning table into out; *n receives
+ * the count. */
+dgn_status dgn_batched_tuning(dgn_batch_tune_entry* out, int32_t max, int32_t* n);
+/* The launch shape (dgn_batch_launch) the last cp_fit_batched call on ctx used; -1 for NULL. */
+int32_t dgn_batched_last_launch(const dgn_ctx* ctx);
 
 /* ---- Serving: a request loop over cp_fit ------------------------------------
  * A server owns one device arena of budget_bytes.  Requests are admitted in

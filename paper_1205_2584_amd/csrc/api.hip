@@ -3,6 +3,8 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -20,6 +22,7 @@ struct dgn_ctx {
   hipStream_t own = nullptr;        // private stream for graph capture (default priority)
   double phase_ms[DGN_NUM_PHASES] = {0, 0, 0, 0, 0, 0};
   int phase_trials = 0;
+  int batch_launch = 0;             // launch shape of the last cp_fit_batched call
 };
 
 namespace dgn {
@@ -63,6 +66,16 @@ constexpr int kNormParts = 1024;
 
 // Message of the last failing dgn_step_noalloc call on this thread (no context to hold it).
 thread_local std::string g_noalloc_err;
+
+// Launch shapes of cp_fit_batched chosen by its tuner, keyed by the batch's
+// largest mode size (in buckets of 16) and largest rank; process-wide.
+struct BatchTune {
+  int launch;              // DGN_BATCH_GRAPH or DGN_BATCH_PERSISTENT
+  double us_graph, us_persistent;
+  int sample_fits, sample_trials;
+};
+std::mutex g_tune_mu;
+std::map<std::pair<int, int>, BatchTune> g_tune;
 
 struct Work {
   Shape s;
@@ -392,6 +405,7 @@ void dgn_opts_default(dgn_opts* o) {
   o->cg_max_iters = 100;
   o->cg_tol = 1e-10;
   o->mu_rule = DGN_MU_PAPER;
+  o->batched_launch = DGN_BATCH_AUTO;
 }
 
 dgn_status dgn_create(dgn_ctx** out, int32_t device, size_t ws_budget_bytes) {
@@ -850,6 +864,7 @@ dgn_status cp_fit(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, void* const* A, 
     info->mu0 = hs.mu0;
     info->cg_trials = fl[11];
     info->cg_iters = fl[12];
+    info->t_done = 0.0;
   }
   if (hs.singular) return set_err(ctx, DGN_ESINGULAR, "non-positive pivot in (Gamma + mu I) or the NR^2 system");
   if (hs.reason == DGN_STOP_NONFINITE) return set_err(ctx, DGN_ENONFINITE, "non-finite error or step");
@@ -1077,7 +1092,9 @@ dgn_status cp_fit_batched(dgn_ctx* ctx, int32_t B, const dgn_batch_fit* fits, do
     int I[3] = {(int)f.Y.dims[0], (int)f.Y.dims[1], (int)f.Y.dims[2]};
     need += al(batched_fit_doubles(I, f.R) * sizeof(double)) + al(sizeof(FitState));
   }
-  need += al(sizeof(BFit) * (size_t)B) + al(sizeof(int) * 64);
+  need += al(sizeof(BFit) * (size_t)B) + al(sizeof(int) * 64) + al(sizeof(int) * (size_t)B);
+  if (o.batched_launch < DGN_BATCH_AUTO || o.batched_launch > DGN_BATCH_PERSISTENT)
+    return set_err(ctx, DGN_EINVAL, "bad batched_launch option");
   if (need > ctx->ws_size)
     return set_err(ctx, DGN_ENOMEM, "workspace budget too small for the batch: need " + std::to_string(need));
   hipStream_t cs = (hipStream_t)stream;
@@ -1088,7 +1105,8 @@ dgn_status cp_fit_batched(dgn_ctx* ctx, int32_t B, const dgn_batch_fit* fits, do
   size_t used = 0;
   auto take = [&](size_t bytes) { char* p = base + used; used += al(bytes); return p; };
   BFit* dfits = reinterpret_cast<BFit*>(take(sizeof(BFit) * (size_t)B));
-  int* nstopped = reinterpret_cast<int*>(take(sizeof(int) * 64));
+  int* nstopped = reinterpret_cast<int*>(take(sizeof(int) * 64));  // [0] stopped fits, [1] persistent queue
+  int* dorder = reinterpret_cast<int*>(take(sizeof(int) * (size_t)B));
   std::vector<FitState*> states(B);
   for (int b = 0; b < B; ++b) {
     const dgn_batch_fit& f = fits[b];
@@ -1121,6 +1139,85 @@ dgn_status cp_fit_batched(dgn_ctx* ctx, int32_t B, const dgn_batch_fit* fits, do
   HIPCHK(hipStreamWaitEvent(st, ev_in, 0), "event");
   HIPCHK(hipMemcpyAsync(dfits, hf.data(), sizeof(BFit) * (size_t)B, hipMemcpyHostToDevice, st), "copy fits");
   HIPCHK(hipMemsetAsync(nstopped, 0, sizeof(int), st), "memset");
+  // Fits in decreasing order of their per-trial tensor work (largest first), the
+  // queue order of the persistent launch.
+  std::vector<int> order(B);
+  for (int b = 0; b < B; ++b) order[b] = b;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    const double wx = (double)hf[x].I[0] * hf[x].I[1] * hf[x].I[2] * hf[x].R;
+    const double wy = (double)hf[y].I[0] * hf[y].I[1] * hf[y].I[2] * hf[y].R;
+    return wx > wy;
+  });
+  HIPCHK(hipMemcpyAsync(dorder, order.data(), sizeof(int) * (size_t)B, hipMemcpyHostToDevice, st), "copy order");
+  int ncu = 0;
+  HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, ctx->device), "device attribute");
+  const int pblocks = ncu > 0 ? ncu : 256;  // the trial kernel's LDS allows one block per CU
+  int launch = o.batched_launch;
+  if (launch == DGN_BATCH_AUTO) launch = DGN_BATCH_GRAPH;
+  if (o.batched_launch == DGN_BATCH_AUTO && max_iters > 0) {
+    int imax = 1, rmax = 1;
+    for (int b = 0; b < B; ++b) {
+      rmax = std::max(rmax, hf[b].R);
+      for (int n = 0; n < 3; ++n) imax = std::max(imax, hf[b].I[n]);
+    }
+    const std::pair<int, int> key((imax + 15) / 16, rmax);
+    bool have = false;
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      auto it = g_tune.find(key);
+      if (it != g_tune.end()) {
+        launch = it->second.launch;
+        have = true;
+      }
+    }
+    if (!have) {
+      // Time both shapes on (up to) 256 fits spread over the batch's order, from
+      // their initial states through a few trials; the caller's factors are not
+      // touched, and every state is initialised again by the run below.
+      const int ns = std::min(B, 256), nt = std::min(max_iters, 4);
+      std::vector<BFit> sample(ns);
+      for (int k = 0; k < ns; ++k) sample[k] = hf[order[(long long)k * B / ns]];
+      std::vector<int> sorder(ns);
+      for (int k = 0; k < ns; ++k) sorder[k] = k;
+      HIPCHK(hipMemcpyAsync(dfits, sample.data(), sizeof(BFit) * (size_t)ns, hipMemcpyHostToDevice, st), "copy sample");
+      HIPCHK(hipMemcpyAsync(dorder, sorder.data(), sizeof(int) * (size_t)ns, hipMemcpyHostToDevice, st), "copy order");
+      hipEvent_t t0, t1, t2;
+      HIPCHK(hipEventCreate(&t0), "event");
+      HIPCHK(hipEventCreate(&t1), "event");
+      HIPCHK(hipEventCreate(&t2), "event");
+      HIPCHK(hipEventRecord(t0, st), "event");
+      HIPCHK(launch_batched_init(dfits, ns, cfg, st), "tune init");
+      for (int k = 0; k < nt; ++k) HIPCHK(launch_batched_trial(dfits, ns, cfg, st), "tune trial");
+      HIPCHK(hipEventRecord(t1, st), "event");
+      HIPCHK(launch_batched_persistent(dfits, ns, dorder, nstopped + 1, cfg, pblocks, nt, false, st), "tune persistent");
+      HIPCHK(hipEventRecord(t2, st), "event");
+      HIPCHK(hipEventSynchronize(t2), "sync");
+      float ms_g = 0.f, ms_p = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms_g, t0, t1), "elapsed");
+      HIPCHK(hipEventElapsedTime(&ms_p, t1, t2), "elapsed");
+      hipEventDestroy(t0);
+      hipEventDestroy(t1);
+      hipEventDestroy(t2);
+      BatchTune bt;
+      bt.launch = ms_p < ms_g ? DGN_BATCH_PERSISTENT : DGN_BATCH_GRAPH;
+      bt.us_graph = 1e3 * ms_g / ((double)ns * nt);
+      bt.us_persistent = 1e3 * ms_p / ((double)ns * nt);
+      bt.sample_fits = ns;
+      bt.sample_trials = nt;
+      {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[key] = bt;
+      }
+      launch = bt.launch;
+      HIPCHK(hipMemcpyAsync(dfits, hf.data(), sizeof(BFit) * (size_t)B, hipMemcpyHostToDevice, st), "copy fits");
+      HIPCHK(hipMemcpyAsync(dorder, order.data(), sizeof(int) * (size_t)B, hipMemcpyHostToDevice, st), "copy order");
+      HIPCHK(hipMemsetAsync(nstopped, 0, sizeof(int), st), "memset");
+    }
+  }
+  ctx->batch_launch = launch;
+  if (launch == DGN_BATCH_PERSISTENT) {
+    HIPCHK(launch_batched_persistent(dfits, B, dorder, nstopped + 1, cfg, pblocks, max_iters, true, st), "persistent");
+  } else {
   HIPCHK(launch_batched_init(dfits, B, cfg, st), "batched init");
   const int per = o.poll_every < max_iters ? o.poll_every : (max_iters > 0 ? max_iters : 1);
   hipGraph_t graph = nullptr;
@@ -1146,6 +1243,7 @@ dgn_status cp_fit_batched(dgn_ctx* ctx, int32_t B, const dgn_batch_fit* fits, do
   if (exec) hipGraphExecDestroy(exec);
   if (graph) hipGraphDestroy(graph);
   HIPCHK(launch_batched_final(dfits, B, st), "batched final");
+  }
   std::vector<FitState> hs(B);
   for (int b = 0; b < B; ++b)
     HIPCHK(hipMemcpyAsync(&hs[b], states[b], sizeof(FitState), hipMemcpyDeviceToHost, st), "state");
@@ -1155,8 +1253,13 @@ dgn_status cp_fit_batched(dgn_ctx* ctx, int32_t B, const dgn_batch_fit* fits, do
   hipEventDestroy(ev_in);
   hipEventDestroy(ev_out);
   int nonfinite = 0;
+  int clk_khz = 0;
+  if (hipDeviceGetAttribute(&clk_khz, hipDeviceAttributeWallClockRate, ctx->device) != hipSuccess) clk_khz = 0;
+  long long tstart = hs.empty() ? 0 : hs[0].t0_ticks;
+  for (int b = 0; b < B; ++b) tstart = std::min(tstart, hs[b].t0_ticks);
   for (int b = 0; b < B; ++b) {
     if (infos) {
+      infos[b].t_done = clk_khz > 0 ? (double)(hs[b].t1_ticks - tstart) / (1e3 * clk_khz) : 0.0;
       infos[b].iters = hs[b].iters;
       infos[b].accepted = hs[b].accepted;
       infos[b].reason = hs[b].reason;
@@ -1173,5 +1276,26 @@ dgn_status cp_fit_batched(dgn_ctx* ctx, int32_t B, const dgn_batch_fit* fits, do
   if (nonfinite) return set_err(ctx, DGN_ENONFINITE, std::to_string(nonfinite) + " fit(s) stopped on a non-finite or singular step");
   return DGN_OK;
 }
+
+dgn_status dgn_batched_tuning(dgn_batch_tune_entry* out, int32_t max, int32_t* n) {
+  if (!n || max < 0 || (max > 0 && !out)) return DGN_EINVAL;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  int k = 0;
+  for (const auto& kv : g_tune) {
+    if (k >= max) break;
+    out[k].imax_bucket = kv.first.first * 16;
+    out[k].rmax = kv.first.second;
+    out[k].launch = kv.second.launch;
+    out[k].us_per_trial_graph = kv.second.us_graph;
+    out[k].us_per_trial_persistent = kv.second.us_persistent;
+    out[k].sample_fits = kv.second.sample_fits;
+    out[k].sample_trials = kv.second.sample_trials;
+    ++k;
+  }
+  *n = k;
+  return DGN_OK;
+}
+
+int32_t dgn_batched_last_launch(const dgn_ctx* ctx) { return ctx ? ctx->batch_launch : -1; }
 
 }  // extern "C"

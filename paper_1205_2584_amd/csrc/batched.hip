@@ -253,11 +253,7 @@ __device__ void rr_mode(const BFit& f, int n, double mu, Smem& S) {
 }
 
 // Per-fit initial state: ||Y||^2, Grams, first tensor pass, err2, mu0.
-__global__ __launch_bounds__(256) void k_binit(BFit* fits, int nfits, BatchCfg cfg) {
-  __shared__ Smem S;
-  const int fi = blockIdx.x;
-  if (fi >= nfits) return;
-  const BFit f = fits[fi];
+__device__ void binit_body(const BFit& f, const BatchCfg& cfg, Smem& S) {
   const int t = threadIdx.x, R = f.R;
   FitState* st = f.st;
   // stacked copy of the caller's factors
@@ -310,16 +306,21 @@ __global__ __launch_bounds__(256) void k_binit(BFit* fits, int nfits, BatchCfg c
     st->pad0 = 0;  // refresh pending
     st->mu_rule = cfg.mu_rule;
     st->nu = 2.0;
+    st->t0_ticks = (long long)wall_clock64();
+    st->t1_ticks = st->t0_ticks;
     if (st->stop) atomicAdd(cfg.nstopped, 1);
   }
 }
 
-// One trial for every unfinished fit.
-__global__ __launch_bounds__(256) void k_btrial(BFit* fits, int nfits, BatchCfg cfg) {
+__global__ __launch_bounds__(256) void k_binit(BFit* fits, int nfits, BatchCfg cfg) {
   __shared__ Smem S;
   const int fi = blockIdx.x;
   if (fi >= nfits) return;
-  const BFit f = fits[fi];
+  binit_body(fits[fi], cfg, S);
+}
+
+// One trial of an unfinished fit (returns at once for a stopped one).
+__device__ void btrial_body(const BFit& f, const BatchCfg& cfg, Smem& S) {
   FitState* st = f.st;
   if (st->stop) return;
   const int t = threadIdx.x, lane = t & 63, R = f.R, R2 = R * R, N = 3;
@@ -613,7 +614,10 @@ __global__ __launch_bounds__(256) void k_btrial(BFit* fits, int nfits, BatchCfg 
         st->reason = 1;
       }
     }
-    if (st->stop) atomicAdd(cfg.nstopped, 1);
+    if (st->stop) {
+      st->t1_ticks = (long long)wall_clock64();
+      atomicAdd(cfg.nstopped, 1);
+    }
     accept_s = accept;
   }
   sync_block();
@@ -660,15 +664,60 @@ __global__ __launch_bounds__(256) void k_btrial(BFit* fits, int nfits, BatchCfg 
   }
 }
 
-// Copy the result factors back to the caller's buffers.
-__global__ __launch_bounds__(256) void k_bfinal(BFit* fits, int nfits) {
+// One trial for every unfinished fit, one block per fit.
+__global__ __launch_bounds__(256) void k_btrial(BFit* fits, int nfits, BatchCfg cfg) {
+  __shared__ Smem S;
   const int fi = blockIdx.x;
   if (fi >= nfits) return;
-  const BFit f = fits[fi];
+  btrial_body(fits[fi], cfg, S);
+}
+
+// Copy the result factors back to the caller's buffers.
+__device__ void bfinal_body(const BFit& f) {
   for (int n = 0; n < 3; ++n) {
     const long long o = aoff(f, n);
     for (int e = threadIdx.x; e < f.I[n] * f.R; e += 256) f.Ain[n][e] = f.A[o + e];
   }
+}
+
+__global__ __launch_bounds__(256) void k_bfinal(BFit* fits, int nfits) {
+  const int fi = blockIdx.x;
+  if (fi >= nfits) return;
+  bfinal_body(fits[fi]);
+}
+
+// Persistent launch: each block takes the next fit from a queue (in the order
+// given, largest first) and runs it from its initial state to its stop, then
+// takes the next, so uneven fits share the CUs without a launch or a grid-wide
+// step per trial.  Every block leaves once the queue is past the last fit;
+// every fit runs at most max_iters trials.  copy_out = 0 leaves the caller's
+// factors untouched (timing runs of the tuner).
+__global__ __launch_bounds__(256) void k_bpersist(BFit* fits, int nfits, const int* order, int* queue,
+                                                  BatchCfg cfg, int ntrials, int copy_out) {
+  __shared__ Smem S;
+  __shared__ int slot_s, stop_s;
+  for (;;) {
+    sync_block();
+    if (threadIdx.x == 0) slot_s = atomicAdd(queue, 1);
+    sync_block();
+    const int slot = slot_s;
+    if (slot >= nfits) return;
+    const BFit f = fits[order[slot]];
+    binit_body(f, cfg, S);
+    for (int it = 0; it < ntrials; ++it) {
+      sync_block();
+      if (threadIdx.x == 0) stop_s = __hip_atomic_load(&f.st->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      sync_block();
+      if (stop_s) break;
+      btrial_body(f, cfg, S);
+    }
+    sync_block();
+    if (copy_out) bfinal_body(f);
+  }
+}
+
+__global__ void k_bqueue_reset(int* queue) {
+  if (threadIdx.x == 0) *queue = 0;
 }
 
 }  // namespace
@@ -697,6 +746,13 @@ hipError_t launch_batched_trial(BFit* fits, int nfits, const BatchCfg& cfg, hipS
 
 hipError_t launch_batched_final(BFit* fits, int nfits, hipStream_t st) {
   k_bfinal<<<nfits, 256, 0, st>>>(fits, nfits);
+  return hipGetLastError();
+}
+
+hipError_t launch_batched_persistent(BFit* fits, int nfits, const int* order, int* queue, const BatchCfg& cfg,
+                                     int blocks, int ntrials, bool copy_out, hipStream_t st) {
+  k_bqueue_reset<<<1, 64, 0, st>>>(queue);
+  k_bpersist<<<blocks, 256, 0, st>>>(fits, nfits, order, queue, cfg, ntrials, copy_out ? 1 : 0);
   return hipGetLastError();
 }
 

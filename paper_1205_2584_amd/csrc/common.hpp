@@ -32,6 +32,7 @@ struct FitState {
   int resid, resid_iters, pad0, mu_rule;  // mu_rule: 0 double on a rejection, 1 Nielsen's nu rule
   double cg_mu_fail;   // damping of the trial whose CG solve did not converge (0: none yet)
   double nu;           // growth factor of the next rejection under Nielsen's rule
+  long long t0_ticks, t1_ticks;  // batched fits: device clock at the initial state and at the stop
   double scale[kMaxOrder * kMaxRank];  // column scales of the last normalisation
 };
 

@@ -189,6 +189,12 @@ size_t batched_fit_doubles(const int* I, int R);
 hipError_t launch_batched_init(BFit* fits, int nfits, const BatchCfg& cfg, hipStream_t st);
 hipError_t launch_batched_trial(BFit* fits, int nfits, const BatchCfg& cfg, hipStream_t st);
 hipError_t launch_batched_final(BFit* fits, int nfits, hipStream_t st);
+// Persistent form: `blocks` blocks drain a queue of the fits (queue: one int of
+// device memory, reset on the stream first), each running a fit from its
+// initial state through at most `ntrials` trials; copy_out writes the result
+// factors to the caller's buffers.
+hipError_t launch_batched_persistent(BFit* fits, int nfits, const int* order, int* queue, const BatchCfg& cfg,
+                                     int blocks, int ntrials, bool copy_out, hipStream_t st);
 
 // ---- iterative NR^2 solve (conjugate gradients on the structured SPD form) ----
 bool cg_supported(const Shape& s);  // N <= 4, R <= 32

@@ -20,6 +20,7 @@ MAX_ORDER = 8
 F64, F32, BF16, C64, C128 = 0, 1, 2, 3, 4
 NORM_BALANCED, NORM_UNIT_EXCEPT_LAST, NORM_NONE = 0, 1, 2
 MU_PAPER, MU_NIELSEN = 0, 1
+BATCH_AUTO, BATCH_GRAPH, BATCH_PERSISTENT = 0, 1, 2
 STOP_TOL, STOP_MAX_IT, STOP_MU, STOP_NONFINITE = 0, 1, 2, 3
 STATUS = {0: "DGN_OK", -1: "DGN_EINVAL", -2: "DGN_ENOMEM", -3: "DGN_ESINGULAR",
           -4: "DGN_ENONFINITE", -5: "DGN_EHIP", -6: "DGN_EBUSY"}
@@ -45,7 +46,7 @@ class dgn_opts(ctypes.Structure):
                 ("poll_every", ctypes.c_int32), ("timing", ctypes.c_int32),
                 ("graph", ctypes.c_int32), ("als_sweeps", ctypes.c_int32),
                 ("solver", ctypes.c_int32), ("cg_max_iters", ctypes.c_int32), ("cg_tol", ctypes.c_double),
-                ("mu_rule", ctypes.c_int32)]
+                ("mu_rule", ctypes.c_int32), ("batched_launch", ctypes.c_int32)]
 
 
 class dgn_step_info(ctypes.Structure):
@@ -58,7 +59,13 @@ class dgn_fit_info(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("accepted", ctypes.c_int32), ("reason", ctypes.c_int32),
                 ("resid_iters", ctypes.c_int32), ("eps", ctypes.c_double), ("err2", ctypes.c_double),
                 ("mu", ctypes.c_double), ("mu0", ctypes.c_double),
-                ("cg_trials", ctypes.c_int32), ("cg_iters", ctypes.c_int32)]
+                ("cg_trials", ctypes.c_int32), ("cg_iters", ctypes.c_int32), ("t_done", ctypes.c_double)]
+
+
+class dgn_batch_tune_entry(ctypes.Structure):
+    _fields_ = [("imax_bucket", ctypes.c_int32), ("rmax", ctypes.c_int32), ("launch", ctypes.c_int32),
+                ("us_per_trial_graph", ctypes.c_double), ("us_per_trial_persistent", ctypes.c_double),
+                ("sample_fits", ctypes.c_int32), ("sample_trials", ctypes.c_int32)]
 
 
 class dgn_batch_fit(ctypes.Structure):
@@ -83,7 +90,7 @@ EXPORTS = ["dgn_opts_default", "dgn_create", "dgn_destroy", "dgn_last_error", "d
            "dgn_mode_gram", "cp_svd_init", "dgn_workspace_size_svd", "dgn_hessian_solve", "dgn_last_phase_times", "cp_fit_batched",
            "dgn_server_create", "dgn_server_submit", "dgn_server_poll", "dgn_server_wait_idle",
            "dgn_server_stats", "dgn_server_now", "dgn_server_destroy", "dgn_step_noalloc",
-           "dgn_noalloc_scratch_bytes"]
+           "dgn_noalloc_scratch_bytes", "dgn_batched_tuning", "dgn_batched_last_launch"]
 NUM_PHASES = 6
 PHASES = ["pre", "assemble", "factor_solve", "update", "tensor_pass", "control"]
 
@@ -136,6 +143,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.dgn_server_destroy.argtypes = [vp]
     L.dgn_step_noalloc.argtypes = [ctypes.POINTER(dgn_tensor), i32, ctypes.POINTER(vp), ctypes.POINTER(vp),
                                    dbl, ctypes.POINTER(dgn_opts), ctypes.POINTER(dgn_step_info), vp]
+    L.dgn_batched_tuning.argtypes = [ctypes.POINTER(dgn_batch_tune_entry), i32, ctypes.POINTER(i32)]
+    L.dgn_batched_tuning.restype = ctypes.c_int
+    L.dgn_batched_last_launch.argtypes = [vp]
+    L.dgn_batched_last_launch.restype = i32
     L.dgn_noalloc_scratch_bytes.argtypes = []
     L.dgn_noalloc_scratch_bytes.restype = ctypes.c_size_t
     for name in ("dgn_create", "dgn_destroy", "dgn_workspace_size", "dgn_mttkrp", "dgn_step", "cp_fit", "cp_als",
@@ -325,6 +336,10 @@ class Context:
                                           _stream()))
         return [{k: getattr(infos[b], k) for k, _ in dgn_fit_info._fields_} for b in range(B)]
 
+    def batched_last_launch(self):
+        """Launch shape (BATCH_GRAPH / BATCH_PERSISTENT) of the last cp_fit_batched call."""
+        return int(self.L.dgn_batched_last_launch(self.h))
+
     def dgn_last_phase_times(self):
         """Per-phase total milliseconds of the last timed cp_fit and the trial count."""
         ms = (ctypes.c_double * NUM_PHASES)()
@@ -345,6 +360,16 @@ def dgn_step_noalloc(y, dims, R, factors, mu, options: dgn_opts | None = None, o
     if st != 0:
         raise DgnError(st, L.dgn_last_error(None).decode())
     return out, {k: getattr(info, k) for k, _ in dgn_step_info._fields_}
+
+
+def batched_tuning():
+    """The batched tuner's table: one dict per (largest mode size bucket, largest rank) key."""
+    out = (dgn_batch_tune_entry * 64)()
+    n = ctypes.c_int32()
+    st = load().dgn_batched_tuning(out, 64, ctypes.byref(n))
+    if st != 0:
+        raise DgnError(st, "dgn_batched_tuning failed")
+    return [{f: getattr(out[k], f) for f, _ in dgn_batch_tune_entry._fields_} for k in range(n.value)]
 
 
 def noalloc_scratch_bytes() -> int:
