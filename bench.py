@@ -326,7 +326,7 @@ def bench_svd_init(dgn, torch, y, dims, R, dev, block=48, iters=30, reps=3, samp
             "oracle_threads": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count()))}
 
 
-def bench_dgn_vs_flm(dgn, torch, ranks=(5, 10, 20, 30, 40, 50, 60), reps=3, mu=10.0):
+def bench_dgn_vs_flm(dgn, torch, ranks=(5, 10, 20, 30, 40, 50, 60, 64), reps=3, mu=10.0):
     """Time per step and workspace of the fast step (dgn_step) against the plain
     dGN step with J^T J formed explicitly (dgn_step_explicit) on 100 x 100 x 100
     tensors with random entries, as in the paper's complexity study (Section 6),
@@ -360,6 +360,119 @@ def bench_dgn_vs_flm(dgn, torch, ranks=(5, 10, 20, 30, 40, 50, 60), reps=3, mu=1
         del y, A
         torch.cuda.empty_cache()
     return {"tensor": "100x100x100 FP64, random entries", "mu": mu, "steps": out}
+
+
+def dgn_fit_explicit(ctx, y, dims, R, A0, mu0, tol, max_iters, ynorm2):
+    """The plain dGN fit the paper compares with: the damping loop of Section 4.5
+    (accept iff the residual decreases, mu <- mu max(1/3, 1 - (2 rho - 1)^3),
+    mu <- 2 mu on a rejection, stop on |eps_prev - eps| < tol) driven from the
+    host around dgn_step_explicit, whose J^T J is formed and factorised
+    explicitly.  A trial whose J^T J + mu I meets a non-positive pivot is
+    rejected, as in cp_fit.  No normalisation between trials (the angles of the
+    factors do not depend on it)."""
+    import math
+    import torch
+    from paper_1205_2584_amd import dgn
+    A = [a.clone() for a in A0]
+    B = [torch.empty_like(a) for a in A0]
+    mu, eps, it, acc = mu0, None, 0, 0
+    while it < max_iters:
+        it += 1
+        try:
+            _, info = ctx.dgn_step_explicit(y, dims, R, A, mu, out=B)
+        except dgn.DgnError as e:
+            if e.status != -3:
+                raise
+            # J^T J + mu I not positive definite in FP64: rejected, as cp_fit does
+            mu *= 2.0
+            continue
+        e_old, e_new = info["err2_old"], info["err2_new"]
+        if eps is None:
+            eps = math.sqrt(e_old / ynorm2)
+        if not math.isfinite(e_new):
+            break
+        if e_new < e_old:
+            acc += 1
+            rho = (e_old - e_new) / info["denom"]
+            A, B = B, A
+            eps_prev, eps = eps, math.sqrt(e_new / ynorm2)
+            mu *= max(1.0 / 3.0, 1.0 - (2.0 * rho - 1.0) ** 3)
+            if abs(eps_prev - eps) < tol:
+                break
+        else:
+            mu *= 2.0
+        if mu > 1e30:
+            break
+    return A, {"iters": it, "accepted": acc, "eps": eps}
+
+
+def bench_medsae(dgn, torch, ranks=(5, 10, 20, 30, 40, 60), tensors=2, noisy=2, nu=0.5, snr_db=30.0,
+                 tol=1e-8, max_iters=1000, seed=61):
+    """Recovery of collinear components by the fast fit (cp_fit) and the plain
+    dGN fit (dgn_fit_explicit) on the Section 6.1 data: 100 x 100 x 100 tensors
+    of the nu-collinear generator (nu = 0.5: 27 and 37 degrees between
+    components) at 30 dB, both fits started from the same mode-n singular
+    vectors (cp_svd_init) and the same mu0 (the tau rule), stopped on
+    |eps_prev - eps| < 1e-8 or after 1000 trials.  MedSAE (eq. (equ_MedSAE))
+    over tensors x noisy runs per rank (the paper: 10 x 20), with the averages
+    it plots: first components, and components r >= 2."""
+    import numpy as np
+    from cpgen import synth
+    from paper_1205_2584_amd import metrics
+    dims = (100, 100, 100)
+    rng = np.random.default_rng(seed)
+    out = []
+    for R in ranks:
+        a2 = {"flm": [], "dgn": []}
+        row = {"R": R, "runs": tensors * noisy, "flm": {"iters": [], "eps": [], "s": []},
+               "dgn": {"iters": [], "eps": [], "s": []}}
+        block = min(80, R + 20)
+        ws = max(dgn.workspace_size(dims, R), dgn.workspace_size_explicit(dims, R),
+                 dgn.workspace_size_svd(dims, R, block))
+        ctx = dgn.Context(0, ws + (16 << 20))
+        try:
+            for t in range(tensors):
+                truth, _ = synth.nu_collinear_factors(rng, dims, R, nu)
+                y0 = synth.cp_tensor(truth)
+                for k in range(noisy):
+                    yn, _ = synth.add_noise(rng, y0, snr_db)
+                    y = torch.from_numpy(yn).cuda()
+                    ynorm2 = float(np.sum(yn * yn))
+                    omega = torch.from_numpy(synth.svd_start_block(rng, dims, block)).cuda()
+                    A0, _ = ctx.cp_svd_init(y, dims, R, block, omega, 30)
+                    A = [a.clone() for a in A0]
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    fi = ctx.cp_fit(y, dims, R, A, -1.0, tol, max_iters)
+                    torch.cuda.synchronize()
+                    row["flm"]["s"].append(time.perf_counter() - t0)
+                    row["flm"]["iters"].append(fi["iters"])
+                    row["flm"]["eps"].append(fi["eps"])
+                    a2["flm"].append(metrics.squared_angular_errors(truth, dgn.to_host_factors(A)))
+                    t0 = time.perf_counter()
+                    B, di = dgn_fit_explicit(ctx, y, dims, R, A0, fi["mu0"], tol, max_iters, ynorm2)
+                    torch.cuda.synchronize()
+                    row["dgn"]["s"].append(time.perf_counter() - t0)
+                    row["dgn"]["iters"].append(di["iters"])
+                    row["dgn"]["eps"].append(di["eps"])
+                    a2["dgn"].append(metrics.squared_angular_errors(truth, dgn.to_host_factors(B)))
+                    print(f"medsae R={R} run={t * noisy + k} flm iters={fi['iters']} eps={fi['eps']:.4e} "
+                          f"dgn iters={di['iters']} eps={di['eps']:.4e}", file=sys.stderr, flush=True)
+                    del y, A, A0, B
+        finally:
+            ctx.close()
+        for m in ("flm", "dgn"):
+            r = row[m]
+            r.update(metrics.medsae_summary(a2[m]))
+            r["median_iters"] = int(np.median(r.pop("iters")))
+            r["median_eps"] = float(np.median(r.pop("eps")))
+            s = r.pop("s")
+            r["s_per_fit"] = round(float(np.mean(s)), 3)
+            r["ms_per_trial"] = round(1e3 * float(np.sum(s)) / max(1, r["median_iters"] * len(s)), 3)
+        out.append(row)
+        torch.cuda.empty_cache()
+    return {"tensor": "100x100x100 FP64, nu-collinear factors (nu = %.2g), %g dB" % (nu, snr_db),
+            "init": "mode-n singular vectors", "tol": tol, "max_iters": max_iters, "ranks": out}
 
 
 def rel(a, b):
@@ -485,6 +598,8 @@ def main():
     ap.add_argument("--no-svd", action="store_true")
     ap.add_argument("--no-cg", action="store_true")
     ap.add_argument("--no-hsolve", action="store_true")
+    ap.add_argument("--medsae", default="1x1",
+                    help="collinear-recovery leg: TENSORSxNOISY runs per rank (0 to skip)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run a plain copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
@@ -625,6 +740,9 @@ def main():
         line["precision"] = precision_report(dgn, torch, p)
     if not args.no_dgn_sweep:
         line["dgn_vs_flm"] = bench_dgn_vs_flm(dgn, torch)
+    if args.medsae != "0":
+        nt, nn = (int(v) for v in args.medsae.split("x"))
+        line["medsae"] = bench_medsae(dgn, torch, tensors=nt, noisy=nn)
     if not args.no_batched:
         line["batched"] = bench_batched(dgn, torch)
     if not args.no_serving:

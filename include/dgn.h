@@ -282,7 +282,10 @@ dgn_status dgn_workspace_size_explicit(const dgn_tensor* Y, int32_t R, size_t* b
  * mu0 > 0 is used as given, mu0 <= 0 takes tau * max diag Gamma^(n).
  * Each trial: step at mu; accept iff the residual decreases, then normalise
  * and mu <- mu max(1/3, 1 - (2 rho - 1)^3); else mu grows by opts->mu_rule
- * (default mu <- 2 mu).  Stops on an
+ * (default mu <- 2 mu).  A trial whose (Gamma^(n) + mu I) or NR^2 system
+ * meets a non-positive pivot in FP64 is rejected the same way (the damping is
+ * too small for the system to be positive definite in working precision), so
+ * cp_fit does not return DGN_ESINGULAR for the trials themselves.  Stops on an
  * accepted trial with |eps_prev - eps| < tol, after max_iters trials, or at
  * mu > 1e30.  Synchronises the stream before returning. */
 dgn_status cp_fit(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, void* const* A, double mu0,

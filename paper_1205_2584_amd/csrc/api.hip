@@ -866,7 +866,6 @@ dgn_status cp_fit(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, void* const* A, 
     info->cg_iters = fl[12];
     info->t_done = 0.0;
   }
-  if (hs.singular) return set_err(ctx, DGN_ESINGULAR, "non-positive pivot in (Gamma + mu I) or the NR^2 system");
   if (hs.reason == DGN_STOP_NONFINITE) return set_err(ctx, DGN_ENONFINITE, "non-finite error or step");
   return DGN_OK;
 }
@@ -1273,7 +1272,7 @@ dgn_status cp_fit_batched(dgn_ctx* ctx, int32_t B, const dgn_batch_fit* fits, do
     }
     nonfinite += hs[b].reason == DGN_STOP_NONFINITE;
   }
-  if (nonfinite) return set_err(ctx, DGN_ENONFINITE, std::to_string(nonfinite) + " fit(s) stopped on a non-finite or singular step");
+  if (nonfinite) return set_err(ctx, DGN_ENONFINITE, std::to_string(nonfinite) + " fit(s) stopped on a non-finite step");
   return DGN_OK;
 }
 

@@ -576,12 +576,13 @@ __device__ void btrial_body(const BFit& f, const BatchCfg& cfg, Smem& S) {
     st->err2_cand = err2c;
     st->iters += 1;
     if (resid) st->resid_iters += 1;
-    if (S.flags[0]) st->singular = 1;
-    if (st->singular || !isfinite(err2c) || !isfinite(den)) {
+    // a non-positive pivot rejects the trial (mu grows), as in the single fit
+    const int sing = S.flags[0] != 0;
+    if (!sing && (!isfinite(err2c) || !isfinite(den))) {
       st->stop = 1;
       st->reason = 3;
     } else {
-      if (err2c < st->err2) {
+      if (!sing && err2c < st->err2) {
         accept = 1;
         st->accepted += 1;
         st->eps_prev = st->eps;

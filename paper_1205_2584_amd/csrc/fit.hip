@@ -125,11 +125,16 @@ __global__ __launch_bounds__(256) void k_control(Shape s, const double* Ac, cons
     st->iters += 1;
     if (resid) st->resid_iters += 1;
     st->commit_iter = -1;
-    if (st->singular || !isfinite(err2c) || !isfinite(denom)) {
+    // A non-positive pivot of (Gamma^(n) + mu I) or of the NR^2 system means the
+    // damping is too small for the system to be positive definite in FP64: the
+    // trial is rejected and mu grows as after a rise of the residual.
+    const int sing = st->singular;
+    st->singular = 0;
+    if (!sing && (!isfinite(err2c) || !isfinite(denom))) {
       st->stop = 1;
       st->reason = 3;
     } else {
-      if (err2c < st->err2) {
+      if (!sing && err2c < st->err2) {
         accept = 1;
         st->accepted += 1;
         st->eps_prev = st->eps;

@@ -5,7 +5,7 @@ attempt counters, through the C ABI.
   from dgn_step and cp_fit (and a failing server request is retired with that
   status while the others finish with the results they have alone).
 * A damped Gram (Gamma^(n) + mu I) that is singular to working precision:
-  DGN_ESINGULAR.  Built exactly: two equal columns in every factor with
+  DGN_ESINGULAR from dgn_step; inside a fit the trial is rejected instead.  Built exactly: two equal columns in every factor with
   squared norm 2 make Gamma^(n) = 4 * ones(2, 2); mu = 1e-300 vanishes in
   4 + mu, and the second Cholesky pivot is 4 - 2 * 2 = 0 in floating point.
 * A zero column: H + mu I stays positive definite, so the step is defined and
@@ -100,6 +100,27 @@ def test_zero_column_step_defined_als_singular(ctx):
     with pytest.raises(dgn.DgnError) as e:
         ctx.cp_als(y, p.dims, p.R, dgn.to_device_factors(A0), 1)
     assert e.value.status == -3
+
+
+@pytest.mark.parametrize("batched", [False, True])
+def test_singular_trials_rejected_in_fit(ctx, batched):
+    """In a fit, a trial whose damped Gram is singular in FP64 is rejected and mu
+    doubles; the fit goes on and returns no error.  The equal-column factors of
+    the step test with mu0 = 1e-17: 4 + mu rounds to 4 for mu = 1e-17, 2e-17 and
+    4e-17 (half an ulp of 4 is 4.4e-16), so all three trials are singular."""
+    dgn = _dgn()
+    dims = (4, 3, 5)
+    A = _equal_column_factors(dims)
+    y = torch.from_numpy(np.random.default_rng(3).standard_normal(int(np.prod(dims)))).cuda()
+    Ad = dgn.to_device_factors(A)
+    if batched:
+        fi = ctx.cp_fit_batched([(y, dims, 2, Ad, 1e-17)], 0.0, 3)[0]
+    else:
+        fi = ctx.cp_fit(y, dims, 2, Ad, 1e-17, 0.0, 3)
+    assert fi["iters"] == 3 and fi["accepted"] == 0 and fi["reason"] == dgn.STOP_MAX_IT
+    assert fi["mu"] == 8e-17
+    got = dgn.to_host_factors(Ad)
+    assert all(np.array_equal(g, a) for g, a in zip(got, A))
 
 
 @pytest.mark.parametrize("rule,trials", [(0, 4), (1, 3)])
