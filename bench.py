@@ -177,53 +177,67 @@ def bench_batched(dgn, torch, count=1024, max_iters=200, tol=1e-8, seq_sample=12
             "latency_note": "per-fit time from the batch's first initial state to the fit's stop (device clock)"}
 
 
-def bench_serving(dgn, torch, n_req=256, rate=2000.0, pool=32, slots=4, seed=5):
-    """Poisson arrival trace (mean `rate` req/s) of real fits drawn from a
-    seeded pool generated on the GPU: N in {3,4}, I_n log-uniform in [16,256],
-    R ~ U{2..20}, correlation U[0,0.95], 20 dB, 20 % complex64 requests, tensors
-    capped at 2^27 entries (larger draws are redrawn); stop at |delta eps| < 1e-8
-    or 200 trials.  The same trace runs through `slots` concurrent slots and
-    through one slot (FIFO one-at-a-time)."""
+def bench_serving(dgn, torch, n_req=2000, rate=2000.0, slots=4, seed=5):
+    """Poisson arrival trace (mean `rate` req/s) of `n_req` distinct seeded fit
+    requests, each generated on the GPU before the replay: N in {3,4}, I_n
+    log-uniform in [16,256], R ~ U{2..20}, correlation U[0,0.95], 20 dB, 20 %
+    complex64 requests, tensors capped at 2^27 entries (larger draws are
+    redrawn); stop at |delta eps| < 1e-8 or 200 trials.  The trace runs through
+    the server with `slots` concurrent slots plus the batch lane, and through
+    one slot without the lane (FIFO one at a time) at the same arrival times."""
     import numpy as np
     from cpgen import device as cdev
     rng = np.random.default_rng(seed)
-    probs = cdev.make_pool(torch, seed * 1000, pool, max_elems=1 << 27)
-    ys = [p.y for p in probs]
-    picks = rng.integers(0, pool, size=n_req)
-    gaps = rng.exponential(1.0 / rate, size=n_req)
+    t_gen = time.perf_counter()
+    probs = cdev.make_pool(torch, seed * 1000, n_req, max_elems=1 << 27)
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t_gen
+    tensor_bytes = sum(p.y.numel() * p.y.element_size() for p in probs)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n_req))
     budget = 8 << 30
 
-    def run(nslots):
-        srv = dgn.Server(0, budget_bytes=budget, max_slots=nslots)
-        facs = [dgn.to_device_factors(probs[k].init) for k in picks]
+    def run(nslots, lane):
+        srv = dgn.Server(0, budget_bytes=budget, max_slots=nslots, options=dgn.opts(serve_batch=int(lane)))
+        facs = [dgn.to_device_factors(p.init) for p in probs]
         torch.cuda.synchronize()
-        t0 = srv.now()
         t_wall = time.perf_counter()
-        for j, k in enumerate(picks):
-            target = t_wall + float(np.sum(gaps[:j + 1]))
+        for j, p in enumerate(probs):
+            target = t_wall + float(arrivals[j])
             while time.perf_counter() < target:
                 pass
-            p = probs[k]
-            srv.submit(ys[k], p.dims, p.R, facs[j], -1.0, 1e-8, 200, tag=j)
+            srv.submit(p.y, p.dims, p.R, facs[j], -1.0, 1e-8, 200, tag=j)
         srv.wait_idle()
         res = srv.poll(max_results=n_req)
         srv.close()
+        del facs
         lat = np.array([r["t_done"] - r["t_submit"] for r in res])
+        lane_mask = np.array([r["lane"] == 1 for r in res])
         span = max(r["t_done"] for r in res) - min(r["t_submit"] for r in res)
         ok = sum(r["status"] == 0 for r in res)
-        return {"completed": len(res), "ok": int(ok), "fits_per_s": round(len(res) / span, 2),
-                "p50_latency_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
-                "p99_latency_ms": round(float(np.percentile(lat, 99)) * 1e3, 2),
-                "span_s": round(span, 3)}
+        out = {"completed": len(res), "ok": int(ok), "fits_per_s": round(len(res) / span, 2),
+               "p50_latency_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
+               "p99_latency_ms": round(float(np.percentile(lat, 99)) * 1e3, 2),
+               "span_s": round(span, 3), "trials_total": int(sum(r["info"]["iters"] for r in res))}
+        if lane_mask.any():
+            sizes = [r["batch_size"] for r in res if r["lane"] == 1]
+            out["lane_requests"] = int(lane_mask.sum())
+            out["lane_mean_batch"] = round(float(np.mean(sizes)), 1)
+            out["lane_p50_latency_ms"] = round(float(np.percentile(lat[lane_mask], 50)) * 1e3, 2)
+            out["slot_p50_latency_ms"] = round(float(np.percentile(lat[~lane_mask], 50)) * 1e3, 2)
+        return out
 
-    multi = run(slots)
-    single = run(1)
-    ncomplex = int(sum(probs[k].complex_ for k in picks))
-    return {"requests": n_req, "complex_requests": ncomplex, "offered_rate_per_s": rate, "slots": slots,
-            "served": multi, "fifo_one_slot": single,
+    multi = run(slots, True)
+    single = run(1, False)
+    ncomplex = int(sum(p.complex_ for p in probs))
+    del probs
+    torch.cuda.empty_cache()
+    return {"requests": n_req, "distinct": n_req, "complex_requests": ncomplex, "offered_rate_per_s": rate,
+            "slots": slots, "served": multi, "fifo_one_slot": single,
             "speedup_vs_fifo": round(multi["fits_per_s"] / single["fits_per_s"], 2),
-            "trace": "Poisson arrivals; pool of 32 seeded fits generated on the GPU, N in {3,4}, "
-                     "I_n log-uniform [16,256] (tensors <= 2^27 entries), R in [2,20], 20% complex64"}
+            "generation_s": round(gen_s, 1), "tensor_GB": round(tensor_bytes / 1e9, 1),
+            "trace": f"Poisson arrivals at {rate:g}/s of {n_req} distinct seeded fits generated on the GPU, "
+                     "N in {3,4}, I_n log-uniform [16,256] (tensors <= 2^27 entries), R in [2,20], 20% complex64; "
+                     "served = slots + batch lane, fifo = one slot, no lane"}
 
 
 def bench_als(dgn, torch, ctx, y, dims, R, p, dev, sweeps=5):

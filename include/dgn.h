@@ -151,6 +151,12 @@ typedef struct dgn_opts {
    * trials (dgn_batched_tuning lists the table).  Every shape gives each fit the
    * same result. */
   int32_t batched_launch;
+  /* dgn_server: route requests within the batched shapes (order 3, F32/F64
+   * data, I_n <= 64, R <= 8) to a batch lane that runs every such request
+   * pending at the time, grouped by (tol, max_iters), in one cp_fit_batched
+   * call with the persistent launch; the next group forms while it runs.
+   * Default 1; 0 runs every request in a slot as cp_fit. */
+  int32_t serve_batch;
 } dgn_opts;
 
 typedef enum dgn_solver { DGN_SOLVER_DIRECT = 0, DGN_SOLVER_AUTO = 1 } dgn_solver;
@@ -390,7 +396,14 @@ int32_t dgn_batched_last_launch(const dgn_ctx* ctx);
  * A server owns one device arena of budget_bytes.  Requests are admitted in
  * arrival order when a slot is free and their workspace (dgn_workspace_size)
  * fits in the free part of the arena; admitted requests run concurrently,
- * each on its own stream, so their kernels overlap on the device.  The
+ * each on its own stream, so their kernels overlap on the device.  Requests
+ * within the batched shapes go to the batch lane instead (opts->serve_batch):
+ * whatever of them is pending when the lane is free runs as one batched
+ * launch on the lane's own stream, beside the slots, and requests arriving
+ * meanwhile form the next batch.  A fit's result is the same whichever batch
+ * it joins (each fit is computed on its own); a batch-lane result differs
+ * from the same fit run by cp_fit within the batched path's tolerance (its
+ * tensor pass accumulates in FP64 without matrix cores).  The
  * caller keeps ownership of each request's tensor and factors until its
  * result has been polled.  Results do not depend on what else is running. */
 typedef struct dgn_server dgn_server;
@@ -411,6 +424,8 @@ typedef struct dgn_result {
   int32_t status;      /* dgn_status of the fit */
   dgn_fit_info info;
   double t_submit, t_admit, t_done; /* seconds on the server's monotonic clock */
+  int32_t lane;        /* 0: ran in a slot (cp_fit); 1: ran in the batch lane (cp_fit_batched) */
+  int32_t batch_size;  /* fits in the batched launch that ran it (1 for a slot) */
 } dgn_result;
 
 /* max_slots concurrent fits (1..64); opts as for cp_fit (may be NULL). */

@@ -28,6 +28,19 @@ struct dgn_ctx {
 namespace dgn {
 hipError_t launch_inner(const Shape& s, const double* A, const double* M, double* out, hipStream_t st);
 
+// Workspace of cp_fit_batched: a part per fit (its arrays and state) and a
+// part per call (the fit table, counters and the launch order); the server's
+// batch lane sizes its arena region with these.
+size_t batched_ws_fit(const int64_t* dims, int R) {
+  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+  const int I[3] = {(int)dims[0], (int)dims[1], (int)dims[2]};
+  return al(batched_fit_doubles(I, R) * sizeof(double)) + al(sizeof(FitState));
+}
+size_t batched_ws_call(int B) {
+  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+  return al(sizeof(BFit) * (size_t)B) + al(sizeof(int) * 64) + al(sizeof(int) * (size_t)B);
+}
+
 // A context over a caller-provided device region (used by the server's slots).
 dgn_ctx* ctx_over(int device, char* ws, size_t size) {
   dgn_ctx* c = new dgn_ctx();
@@ -406,6 +419,7 @@ void dgn_opts_default(dgn_opts* o) {
   o->cg_tol = 1e-10;
   o->mu_rule = DGN_MU_PAPER;
   o->batched_launch = DGN_BATCH_AUTO;
+  o->serve_batch = 1;
 }
 
 dgn_status dgn_create(dgn_ctx** out, int32_t device, size_t ws_budget_bytes) {
@@ -1088,10 +1102,9 @@ dgn_status cp_fit_batched(dgn_ctx* ctx, int32_t B, const dgn_batch_fit* fits, do
         !batched_supported(f.Y.order, f.Y.dims, f.R) || !f.A[0] || !f.A[1] || !f.A[2] || !isfinite(f.mu0))
       return set_err(ctx, DGN_EINVAL, "batch fit " + std::to_string(b) +
                                           ": need order 3, F32/F64 data, I_n <= 64, 1 <= R <= 8, non-NULL factors");
-    int I[3] = {(int)f.Y.dims[0], (int)f.Y.dims[1], (int)f.Y.dims[2]};
-    need += al(batched_fit_doubles(I, f.R) * sizeof(double)) + al(sizeof(FitState));
+    need += batched_ws_fit(f.Y.dims, f.R);
   }
-  need += al(sizeof(BFit) * (size_t)B) + al(sizeof(int) * 64) + al(sizeof(int) * (size_t)B);
+  need += batched_ws_call(B);
   if (o.batched_launch < DGN_BATCH_AUTO || o.batched_launch > DGN_BATCH_PERSISTENT)
     return set_err(ctx, DGN_EINVAL, "bad batched_launch option");
   if (need > ctx->ws_size)

@@ -46,7 +46,8 @@ class dgn_opts(ctypes.Structure):
                 ("poll_every", ctypes.c_int32), ("timing", ctypes.c_int32),
                 ("graph", ctypes.c_int32), ("als_sweeps", ctypes.c_int32),
                 ("solver", ctypes.c_int32), ("cg_max_iters", ctypes.c_int32), ("cg_tol", ctypes.c_double),
-                ("mu_rule", ctypes.c_int32), ("batched_launch", ctypes.c_int32)]
+                ("mu_rule", ctypes.c_int32), ("batched_launch", ctypes.c_int32),
+                ("serve_batch", ctypes.c_int32)]
 
 
 class dgn_step_info(ctypes.Structure):
@@ -82,7 +83,7 @@ class dgn_request(ctypes.Structure):
 class dgn_result(ctypes.Structure):
     _fields_ = [("id", ctypes.c_uint64), ("tag", ctypes.c_uint64), ("status", ctypes.c_int32),
                 ("info", dgn_fit_info), ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
-                ("t_done", ctypes.c_double)]
+                ("t_done", ctypes.c_double), ("lane", ctypes.c_int32), ("batch_size", ctypes.c_int32)]
 
 
 EXPORTS = ["dgn_opts_default", "dgn_create", "dgn_destroy", "dgn_last_error", "dgn_workspace_size",
@@ -377,7 +378,8 @@ def noalloc_scratch_bytes() -> int:
 
 
 class Server:
-    """dgn_server: FIFO admission by device-memory budget, concurrent slots."""
+    """dgn_server: FIFO admission by device-memory budget, concurrent slots, and
+    a batch lane for requests within the batched shapes."""
 
     def __init__(self, device=0, budget_bytes=1 << 30, max_slots=4, options: dgn_opts | None = None):
         self.L = load()
@@ -415,7 +417,8 @@ class Server:
             self._keep.pop(o.id, None)
             res.append(dict(id=o.id, tag=o.tag, status=o.status,
                             info={f: getattr(o.info, f) for f, _ in dgn_fit_info._fields_},
-                            t_submit=o.t_submit, t_admit=o.t_admit, t_done=o.t_done))
+                            t_submit=o.t_submit, t_admit=o.t_admit, t_done=o.t_done,
+                            lane=o.lane, batch_size=o.batch_size))
         return res
 
     def wait_idle(self):

@@ -131,17 +131,22 @@ def test_opts_mu_rule_default(lib):
     assert dgn.opts().mu_rule == dgn.MU_PAPER == 0 and dgn.MU_NIELSEN == 1
 
 
+def test_opts_serve_batch_default(lib):
+    from paper_1205_2584_amd import dgn
+    assert dgn.opts().serve_batch == 1
+
+
 STRUCTS = {
     "dgn_tensor": ["order", "dims", "dtype", "data"],
     "dgn_opts": ["normalize", "tau", "resid_switch", "y_bf16", "poll_every", "timing", "graph",
-                 "als_sweeps", "solver", "cg_max_iters", "cg_tol", "mu_rule", "batched_launch"],
+                 "als_sweeps", "solver", "cg_max_iters", "cg_tol", "mu_rule", "batched_launch", "serve_batch"],
     "dgn_step_info": ["err2_old", "err2_new", "rho", "denom", "gnorm", "mnorm", "danorm", "cg_iters",
                       "cg_attempt_iters"],
     "dgn_fit_info": ["iters", "accepted", "reason", "resid_iters", "eps", "err2", "mu", "mu0",
                      "cg_trials", "cg_iters", "t_done"],
     "dgn_batch_fit": ["Y", "R", "mu0", "A"],
     "dgn_request": ["Y", "R", "mu0", "tol", "max_iters", "A", "tag"],
-    "dgn_result": ["id", "tag", "status", "info", "t_submit", "t_admit", "t_done"],
+    "dgn_result": ["id", "tag", "status", "info", "t_submit", "t_admit", "t_done", "lane", "batch_size"],
     "dgn_batch_tune_entry": ["imax_bucket", "rmax", "launch", "us_per_trial_graph", "us_per_trial_persistent",
                              "sample_fits", "sample_trials"],
 }
