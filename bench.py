@@ -61,8 +61,9 @@ def syrk_flops(N, R):
 # either changes the figure no longer describes the kernel and is reported as
 # null.
 TRAFFIC = {
-    "factor_solve": ("paper_1205_2584_amd/csrc/chol.hip", "f9e7e750e062b9f4", 465931056),
-    "tensor_pass_f32": ("paper_1205_2584_amd/csrc/tensor_pass.hip", "88f57e8363b93a88", 548414654),
+    "factor_solve": ("paper_1205_2584_amd/csrc/chol.hip", "5c323964c16d94d6", 835960386),
+    "tensor_pass_f32": ("paper_1205_2584_amd/csrc/tensor_pass.hip", "4340cf06d86734ac", 517661481),
+    "tensor_pass_bf16": ("paper_1205_2584_amd/csrc/tensor_pass.hip", "4340cf06d86734ac", 268081857),
 }
 
 
@@ -153,6 +154,12 @@ def bench_batched(dgn, torch, count=1024, max_iters=200, tol=1e-8, seq_sample=12
         shapes[names[launch]] = round(count / d, 1)
     trials = sum(i["iters"] for i in infos)
     lat = np.array([i["t_done"] for i in infos]) * 1e3
+    # algorithmic work of the run: each trial of fit b takes one pass over its
+    # FP32 tensor (J_b entries) with 4 J_b R_b FP64 flops (all-mode MTTKRP)
+    Js = [int(np.prod(p.dims)) for p in ps]
+    flops = sum(4.0 * J * p.R * i["iters"] for J, p, i in zip(Js, ps, infos))
+    tbytes = sum(4.0 * J * i["iters"] for J, i in zip(Js, infos))
+    tf = flops / dt / 1e12
     # sequential baseline on a sample
     t1 = time.perf_counter()
     for b in range(seq_sample):
@@ -174,7 +181,13 @@ def bench_batched(dgn, torch, count=1024, max_iters=200, tol=1e-8, seq_sample=12
             "speedup_vs_sequential": round((count / dt) / seq_rate, 1),
             "p50_latency_ms": round(float(np.percentile(lat, 50)), 2),
             "p99_latency_ms": round(float(np.percentile(lat, 99)), 2),
-            "latency_note": "per-fit time from the batch's first initial state to the fit's stop (device clock)"}
+            "latency_note": "per-fit time from the batch's first initial state to the fit's stop (device clock)",
+            "roofline_batched": {"bound": "alu", "achieved": round(tf, 3), "peak": PEAK_FP64_TFLOPS,
+                                 "unit": "TFLOP/s", "frac": round(tf / PEAK_FP64_TFLOPS, 4), "traffic": None,
+                                 "algorithmic_flops": flops, "tensor_GBs": round(tbytes / dt / 1e9, 1),
+                                 "tensor_MB_total": round(sum(4.0 * J for J in Js) / 1e6, 1),
+                                 "note": "FP64 FMA tensor pass (4 J R flops per trial) over the whole call's wall "
+                                         "time; the 1024 tensors together fit in the 256 MB Infinity Cache"}}
 
 
 def bench_serving(dgn, torch, n_req=2000, rate=2000.0, slots=4, seed=5):
@@ -614,6 +627,8 @@ def main():
     ap.add_argument("--no-hsolve", action="store_true")
     ap.add_argument("--medsae", default="1x1",
                     help="collinear-recovery leg: TENSORSxNOISY runs per rank (0 to skip)")
+    ap.add_argument("--only", choices=["batched", "serving", "medsae", "dgn-sweep"], default=None,
+                    help="run this leg alone and print its JSON (profiling)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run a plain copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
@@ -631,6 +646,18 @@ def main():
     torch.cuda.set_device(dev)
     if args.copy_probe_mib > 0:
         copy_probe(torch, args.copy_probe_mib)
+    if args.only is not None:
+        if args.only == "batched":
+            leg = bench_batched(dgn, torch)
+        elif args.only == "serving":
+            leg = bench_serving(dgn, torch)
+        elif args.only == "dgn-sweep":
+            leg = bench_dgn_vs_flm(dgn, torch)
+        else:
+            nt, nn = (int(v) for v in (args.medsae if args.medsae != "0" else "1x1").split("x"))
+            leg = bench_medsae(dgn, torch, tensors=nt, noisy=nn)
+        print(json.dumps({args.only: leg}), flush=True)
+        return
     t_gen = time.perf_counter()
     p = workload(args.workload)
     y32 = torch.from_numpy(p.y.astype(np.float32)).to(dev)
@@ -721,7 +748,11 @@ def main():
         "roofline_solve": roof_sys,
         "phase_ms": {k: round(v, 4) for k, v in per.items()},
         "bf16_pass": {"iters_per_s": round(infob["iters"] / dtb, 3), "tensor_pass_ms": round(perb["tensor_pass"], 4),
-                      "tensor_pass_GBs": round(passb_gbs, 1)},
+                      "tensor_pass_GBs": round(passb_gbs, 1),
+                      "roofline": {"bound": "hbm", "achieved": round(passb_gbs, 1), "peak": PEAK_HBM_GBS,
+                                   "unit": "GB/s", "frac": round(passb_gbs / PEAK_HBM_GBS, 4),
+                                   "traffic": traffic("tensor_pass_bf16", args.workload),
+                                   "algorithmic_bytes": J * 2}},
         "fit": {"eps": info["eps"], "accepted": info["accepted"], "mu": info["mu"],
                 "resid_iters": info["resid_iters"]},
         "gen_s": round(gen_s, 1),
