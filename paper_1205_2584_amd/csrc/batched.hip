@@ -18,6 +18,7 @@ namespace dgn {
 
 namespace {
 
+typedef double v4d __attribute__((ext_vector_type(4)));
 constexpr int BR = 8;          // max rank
 constexpr int BR2 = BR * BR;   // 64
 constexpr int BI = 64;         // max mode size
@@ -38,7 +39,6 @@ struct Smem {
       double Sp[kPacked];
       double Bm[BNT][BR2];
       double Tb[BR * BR * BR];
-      double lk[BNT + 2];
     } sys;
     struct {
       double Ys[BI][BI + 1];  // Ys[j][i]
@@ -87,21 +87,38 @@ __device__ double bpass(const BFit& f, const double* Ain, double* Mout, int resi
   }
   double m0[2] = {0.0, 0.0}, m1[2] = {0.0, 0.0};
   double e2 = 0.0;
+  // slice q of Y (and row q of A^(3)) is loaded into registers while slice
+  // q - 1 is processed, every load of a slice issued before the first is used
+  TY yv[16];
+  double cv = 0.0;
+  auto load_slice = [&](int q) {
+    const long long base = (long long)I0 * I1 * q;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int e = t + 256 * k, ii = e & 63, jj = e >> 6;
+      yv[k] = (ii < I0 && jj < I1) ? Y[base + ii + (long long)I0 * jj] : TY(0);
+    }
+    cv = (t < R) ? A2[q + (long long)t * I2] : 0.0;
+  };
+  if (I2 > 0) load_slice(0);
   for (int q = 0; q < I2; ++q) {
     sync_block();
-    const long long base = (long long)I0 * I1 * q;
-    for (int e = t; e < BI * BI; e += 256) {
-      const int ii = e & 63, jj = e >> 6;
-      P.Ys[jj][ii] = (ii < I0 && jj < I1) ? to_f64(Y[base + ii + (long long)I0 * jj]) : 0.0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int e = t + 256 * k, ii = e & 63, jj = e >> 6;
+      P.Ys[jj][ii] = to_f64(yv[k]);
     }
-    if (t < BR) P.cq[t] = (t < R) ? A2[q + (long long)t * I2] : 0.0;
+    if (t < BR) P.cq[t] = cv;
     sync_block();
+    if (q + 1 < I2) load_slice(q + 1);
     if (resid) {
       for (int e = t; e < BI * BI; e += 256) {
         const int ii = e & 63, jj = e >> 6;
         if (ii < I0 && jj < I1) {
           double yh = 0.0;
-          for (int r = 0; r < R; ++r) yh += P.A0s[ii][r] * (P.A1s[jj][r] * P.cq[r]);
+#pragma unroll
+          for (int r = 0; r < BR; ++r)
+            if (r < R) yh += P.A0s[ii][r] * (P.A1s[jj][r] * P.cq[r]);
           const double ev = P.Ys[jj][ii] - yh;
           e2 += ev * ev;
           P.Ys[jj][ii] = ev;
@@ -110,11 +127,14 @@ __device__ double bpass(const BFit& f, const double* Ain, double* Mout, int resi
       sync_block();
     }
     double zp[2] = {0.0, 0.0}, wp[2] = {0.0, 0.0};
+    // unrolled so that the LDS reads of several rows are in flight together
+#pragma unroll 8
     for (int jj = 0; jj < I1; ++jj) {
       const double yv = P.Ys[jj][lane];
       zp[0] += yv * P.A1s[jj][rg];
       zp[1] += yv * P.A1s[jj][rg + 4];
     }
+#pragma unroll 8
     for (int ii = 0; ii < I0; ++ii) {
       const double yv = P.Ys[lane][ii];
       wp[0] += yv * P.A0s[ii][rg];
@@ -193,63 +213,63 @@ __device__ double gamma_of(const double (*Cs)[BR2], int skip1, int skip2, int e)
 
 // Serial R x R work of one mode (R <= 8) by one thread: Gamma_n, Cholesky of
 // Gamma_n + mu I, X_n = L^-T, Gt_n = X_n X_n^T, semidefinite-safe L of C_n.
+// R x R work of mode n by one wave, lane (r, q) = (lane & 7, lane >> 3) holding
+// entry (r, q): Gamma_n, the Cholesky factor L of Gamma_n + mu I (a
+// non-positive pivot raises the singular flag), X_n = L^-T, Gt_n = X_n X_n^T,
+// and the semidefinite-safe Cholesky factor L_n of C_n.  The factorisations
+// are right-looking on the full symmetric matrix; the column and pivot of a
+// step are broadcast with lane shuffles.
 __device__ void rr_mode(const BFit& f, int n, double mu, Smem& S) {
-  const int R = f.R;
-  double H[BR][BR], Li[BR][BR];
-  for (int r = 0; r < R; ++r)
-    for (int q = 0; q < R; ++q) {
-      const double g = gamma_of(S.Cs, n, -1, r + q * R);
-      S.Gm[n][r + q * R] = g;
-      H[r][q] = g + (r == q ? mu : 0.0);
-    }
+  const int R = f.R, lane = threadIdx.x & 63, r = lane & 7, q = lane >> 3;
+  const bool act = r < R && q < R;
+  const int e = r + q * R;
+  double g = 0.0;
+  if (act) {
+    g = gamma_of(S.Cs, n, -1, e);
+    S.Gm[n][e] = g;
+  }
+  double h = g + ((r == q) ? mu : 0.0);
   for (int k = 0; k < R; ++k) {
-    double d = H[k][k];
-    for (int j = 0; j < k; ++j) d -= H[k][j] * H[k][j];
-    if (!(d > 0.0)) {
-      S.flags[0] = 1;
-      d = 1.0;
-    }
-    d = sqrt(d);
-    H[k][k] = d;
-    for (int i = k + 1; i < R; ++i) {
-      double s = H[i][k];
-      for (int j = 0; j < k; ++j) s -= H[i][j] * H[k][j];
-      H[i][k] = s / d;
-    }
+    const double piv = __shfl(h, 9 * k);
+    const double lrk = __shfl(h, r + 8 * k), lqk = __shfl(h, q + 8 * k);
+    double d = 1.0;
+    if (piv > 0.0) d = sqrt(piv);
+    else if (lane == 0) S.flags[0] = 1;
+    if (r > k && q > k) h -= (lrk / d) * (lqk / d);
+    else if (q == k && r > k) h = lrk / d;
+    else if (q == k && r == k) h = d;
   }
-  for (int j = 0; j < R; ++j) {
-    for (int i = 0; i < R; ++i) Li[i][j] = 0.0;
-    Li[j][j] = 1.0 / H[j][j];
-    for (int i = j + 1; i < R; ++i) {
-      double acc = 0.0;
-      for (int k = j; k < i; ++k) acc += H[i][k] * Li[k][j];
-      Li[i][j] = -acc / H[i][i];
-    }
-  }
-  for (int r = 0; r < R; ++r)
-    for (int q = 0; q < R; ++q) {
-      S.Xs[n][r + q * R] = Li[q][r];
-      double acc = 0.0;
-      for (int k = (r > q ? r : q); k < R; ++k) acc += Li[k][r] * Li[k][q];
-      S.Gt[n][r + q * R] = acc;
-    }
-  // L L^T = C_n
-  for (int r = 0; r < R; ++r)
-    for (int q = 0; q < R; ++q) H[r][q] = S.Cs[n][r + q * R];
+  // column q of L^-1 by forward substitution, one step per column of L
+  double x = (r == q) ? 1.0 : 0.0;
   for (int k = 0; k < R; ++k) {
-    double d = H[k][k];
-    for (int j = 0; j < k; ++j) d -= H[k][j] * H[k][j];
-    const bool zero = !(d > 64.0 * 2.220446049250313e-16 * S.Cs[n][k + k * R]);
-    d = zero ? 0.0 : sqrt(d);
-    H[k][k] = d;
-    for (int i = k + 1; i < R; ++i) {
-      double s = H[i][k];
-      for (int j = 0; j < k; ++j) s -= H[i][j] * H[k][j];
-      H[i][k] = zero ? 0.0 : s / d;
-    }
+    const double lkk = __shfl(h, 9 * k);
+    const double xkq = __shfl(x, k + 8 * q) / lkk;
+    const double lrk = __shfl(h, r + 8 * k);
+    if (r == k) x = xkq;
+    else if (r > k) x -= lrk * xkq;
   }
-  for (int r = 0; r < R; ++r)
-    for (int q = 0; q < R; ++q) S.Ls[n][r + q * R] = (q <= r) ? H[r][q] : 0.0;
+  const double xt = __shfl(x, q + 8 * r);  // Li[q][r]
+  double gt = 0.0;
+  for (int k = 0; k < R; ++k) {
+    const double a = __shfl(x, k + 8 * r), b = __shfl(x, k + 8 * q);
+    if (k >= r && k >= q) gt += a * b;
+  }
+  if (act) {
+    S.Xs[n][e] = xt;
+    S.Gt[n][e] = gt;
+  }
+  // L L^T = C_n, a pivot below 64 u times its diagonal zeroing the column
+  double c = act ? S.Cs[n][e] : 0.0;
+  for (int k = 0; k < R; ++k) {
+    const double piv = __shfl(c, 9 * k);
+    const double lrk = __shfl(c, r + 8 * k), lqk = __shfl(c, q + 8 * k);
+    const bool zero = !(piv > 64.0 * 2.220446049250313e-16 * S.Cs[n][k + k * R]);
+    const double d = zero ? 0.0 : sqrt(piv);
+    if (r > k && q > k) c -= zero ? 0.0 : (lrk / d) * (lqk / d);
+    else if (q == k && r > k) c = zero ? 0.0 : lrk / d;
+    else if (q == k && r == k) c = d;
+  }
+  if (act) S.Ls[n][e] = (q <= r) ? c : 0.0;
 }
 
 // Per-fit initial state: ||Y||^2, Grams, first tensor pass, err2, mu0.
@@ -343,7 +363,7 @@ __device__ void btrial_body(const BFit& f, const BatchCfg& cfg, Smem& S) {
   for (int e = t; e < 3 * BR2; e += 256) S.Cs[e >> 6][e & 63] = f.C[e];
   sync_block();
   // S1: R x R work per mode
-  if (t == 0 || t == 64 || t == 128) rr_mode(f, t >> 6, mu, S);
+  if (t < 192) rr_mode(f, t >> 6, mu, S);
   sync_block();
   // S2: gradient rows G, P = G Gt
   if (t < T) {
@@ -351,22 +371,34 @@ __device__ void btrial_body(const BFit& f, const BatchCfg& cfg, Smem& S) {
     const int n = mode_of_row(f, t, &i);
     const int In = f.I[n];
     const long long o = aoff(f, n);
+    // the row in registers: loops over the rank are unrolled to BR with guards
     double g[BR], a[BR];
-    for (int r = 0; r < R; ++r) {
-      a[r] = f.A[o + i + (long long)r * In];
-      g[r] = f.M[o + i + (long long)r * In];
+#pragma unroll
+    for (int r = 0; r < BR; ++r) {
+      a[r] = (r < R) ? f.A[o + i + (long long)r * In] : 0.0;
+      g[r] = (r < R) ? f.M[o + i + (long long)r * In] : 0.0;
     }
     if (!resid)
-      for (int r = 0; r < R; ++r) {
-        double acc = 0.0;
-        for (int s2 = 0; s2 < R; ++s2) acc += a[s2] * S.Gm[n][s2 + r * R];
-        g[r] -= acc;
+#pragma unroll
+      for (int r = 0; r < BR; ++r) {
+        if (r < R) {
+          double acc = 0.0;
+#pragma unroll
+          for (int s2 = 0; s2 < BR; ++s2)
+            if (s2 < R) acc += a[s2] * S.Gm[n][s2 + r * R];
+          g[r] -= acc;
+        }
       }
-    for (int r = 0; r < R; ++r) {
-      double acc = 0.0;
-      for (int s2 = 0; s2 < R; ++s2) acc += g[s2] * S.Gt[n][s2 + r * R];
-      f.G[o + i + (long long)r * In] = g[r];
-      f.P[o + i + (long long)r * In] = acc;
+#pragma unroll
+    for (int r = 0; r < BR; ++r) {
+      if (r < R) {
+        double acc = 0.0;
+#pragma unroll
+        for (int s2 = 0; s2 < BR; ++s2)
+          if (s2 < R) acc += g[s2] * S.Gt[n][s2 + r * R];
+        f.G[o + i + (long long)r * In] = g[r];
+        f.P[o + i + (long long)r * In] = acc;
+      }
     }
   }
   sync_block();
@@ -439,31 +471,70 @@ __device__ void btrial_body(const BFit& f, const BatchCfg& cfg, Smem& S) {
     }
     sync_block();
   }
-  // Schur update with block 1 and the right-hand side row
-  for (int p = (t & 127); p < nt; p += 128)
-    for (int q = (t >> 7); q <= p; q += 2) {
-      double acc = 0.0;
-      for (int k = 0; k < R2; ++k) acc += Y.Bm[p][k] * Y.Bm[q][k];
-      Y.Sp[pidx(p, q)] -= acc;
+  // Schur update with block 1 (S_tt -= B B^T on the FP64 matrix cores, one
+  // 16 x 16 lower tile per wave at a time) and the right-hand side row.
+  // v_mfma_f64_16x16x4f64: lane l holds A[l%16][l/16] and B[l/16][l%16] of the
+  // step and the result D[l/16 + 4v][l%16]; rows of B beyond nt only reach
+  // outputs that are not stored, columns of B beyond R^2 are masked to zero.
+  {
+    const int w = t >> 6, li = lane & 15, lq = lane >> 4;
+    const int nT = (nt + 15) >> 4, ntile = nT * (nT + 1) / 2, K4 = (R2 + 3) & ~3;
+    for (int tile = w; tile < ntile; tile += 4) {
+      int P = 0;
+      while ((P + 1) * (P + 2) / 2 <= tile) ++P;
+      const int Q = tile - P * (P + 1) / 2;
+      v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+      for (int k0 = 0; k0 < K4; k0 += 4) {
+        const int k = k0 + lq;
+        const double a = (k < R2) ? Y.Bm[16 * P + li][k] : 0.0;
+        const double b = (k < R2) ? Y.Bm[16 * Q + li][k] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int pr = 16 * P + lq + 4 * v, qc = 16 * Q + li;
+        if (pr < nt && qc <= pr) Y.Sp[pidx(pr, qc)] -= acc[v];
+      }
     }
+  }
   for (int p = t; p < nt; p += 256) {
     double acc = 0.0;
     for (int k = 0; k < R2; ++k) acc += Y.Bm[p][k] * S.z[k];
     Y.Sp[pidx(nt, p)] = S.z[R2 + p] - acc;
   }
-  // S5: Cholesky of the trailing system; row nt becomes L^-1 z'
+  // S5: Cholesky of the trailing system; row nt becomes L^-1 z'.  One barrier
+  // per column: step k updates the columns right of k from the unscaled
+  // column k (every thread scales the entries it reads), and column k itself
+  // is scaled in step k + 1, when nothing reads it any more.
+  double dprev = 1.0;
   for (int k = 0; k < nt; ++k) {
     sync_block();
     const double dkk = Y.Sp[pidx(k, k)];
     double d = 1.0;
     if (dkk > 0.0) d = sqrt(dkk);
     else if (t == 0) S.flags[0] = 1;
-    for (int i = k + 1 + t; i <= nt; i += 256) Y.lk[i] = Y.Sp[pidx(i, k)] / d;
-    sync_block();
-    if (t == 0) Y.Sp[pidx(k, k)] = d;
-    for (int i = k + 1 + t; i <= nt; i += 256) Y.Sp[pidx(i, k)] = Y.lk[i];
-    for (int i = k + 1 + (t & 127); i <= nt; i += 128)
-      for (int j = k + 1 + (t >> 7); j <= i && j < nt; j += 2) Y.Sp[pidx(i, j)] -= Y.lk[i] * Y.lk[j];
+    const double inv = 1.0 / d;
+    if (k > 0) {
+      for (int i = k + t; i <= nt; i += 256) Y.Sp[pidx(i, k - 1)] *= 1.0 / dprev;
+      if (t == 0) Y.Sp[pidx(k - 1, k - 1)] = dprev;
+    }
+    // rows i in (k, nt], each row's columns j in (k, min(i, nt - 1)] split over
+    // `js` threads (js = 256 / rows, at most 8), so no thread runs a long chain
+    {
+      const int rows = nt - k;
+      const int js = rows >= 128 ? 2 : (rows >= 64 ? 4 : 8);
+      const int ri = t / js, part = t - ri * js;
+      for (int i = k + 1 + ri; i <= nt; i += 256 / js) {
+        const double li = Y.Sp[pidx(i, k)] * inv;
+        for (int j = k + 1 + part; j <= i && j < nt; j += js) Y.Sp[pidx(i, j)] -= li * (Y.Sp[pidx(j, k)] * inv);
+      }
+    }
+    dprev = d;
+  }
+  sync_block();
+  if (nt > 0) {
+    for (int i = nt + t; i <= nt; i += 256) Y.Sp[pidx(i, nt - 1)] *= 1.0 / dprev;
+    if (t == 0) Y.Sp[pidx(nt - 1, nt - 1)] = dprev;
   }
   sync_block();
   // backward substitution L^T y_t = v by wave 0 (rows lane and lane + 64)
@@ -538,14 +609,20 @@ __device__ void btrial_body(const BFit& f, const BatchCfg& cfg, Smem& S) {
     const int In = f.I[n];
     const long long o = aoff(f, n);
     double a[BR];
-    for (int r = 0; r < R; ++r) a[r] = f.A[o + i + (long long)r * In];
-    for (int r = 0; r < R; ++r) {
-      double acc = 0.0;
-      for (int s2 = 0; s2 < R; ++s2) acc += a[s2] * S.Qs[n][s2 + r * R];
-      const long long gi = o + i + (long long)r * In;
-      const double da = f.P[gi] - acc;
-      f.Ac[gi] = a[r] + da;
-      den += da * (f.G[gi] + mu * da);
+#pragma unroll
+    for (int r = 0; r < BR; ++r) a[r] = (r < R) ? f.A[o + i + (long long)r * In] : 0.0;
+#pragma unroll
+    for (int r = 0; r < BR; ++r) {
+      if (r < R) {
+        double acc = 0.0;
+#pragma unroll
+        for (int s2 = 0; s2 < BR; ++s2)
+          if (s2 < R) acc += a[s2] * S.Qs[n][s2 + r * R];
+        const long long gi = o + i + (long long)r * In;
+        const double da = f.P[gi] - acc;
+        f.Ac[gi] = a[r] + da;
+        den += da * (f.G[gi] + mu * da);
+      }
     }
   }
   den = block_sum(den, S.red);

@@ -200,7 +200,11 @@ def test_bad_mu_rule_rejected(ctx):
     assert e.value.status == -1
 
 
-def test_server_retires_failing_request():
+@pytest.mark.parametrize("serve_batch", [0, 1])
+def test_server_retires_failing_request(serve_batch):
+    """A request with a NaN entry is retired with DGN_ENONFINITE while the others
+    finish with the results they have alone (through the slots, or with the
+    batch lane on, the order-3 ones and the failing one through the lane)."""
     dgn = _dgn()
     specs = [((20, 18, 16), 3, 21), ((16, 14, 12, 6), 4, 22), ((24, 20, 10), 5, 23)]
     probs = [cpgen.small_problem(s, d, R, c=0.5, snr_db=25.0) for d, R, s in specs]
@@ -208,11 +212,17 @@ def test_server_retires_failing_request():
     alone = []
     for p in probs:
         A = dgn.to_device_factors(p.init)
-        info = ctx.cp_fit(torch.from_numpy(p.y).cuda(), p.dims, p.R, A, -1.0, 1e-8, 30)
+        y = torch.from_numpy(p.y).cuda()
+        if serve_batch and len(p.dims) == 3:
+            info = ctx.cp_fit_batched([(y, p.dims, p.R, A, -1.0)], 1e-8, 30,
+                                      dgn.opts(batched_launch=dgn.BATCH_PERSISTENT))[0]
+        else:
+            info = ctx.cp_fit(y, p.dims, p.R, A, -1.0, 1e-8, 30)
+        info.pop("t_done")
         alone.append((dgn.to_host_factors(A), info))
     ctx.close()
     bad, ybad = _nan_problem()
-    srv = dgn.Server(0, budget_bytes=64 << 20, max_slots=2)
+    srv = dgn.Server(0, budget_bytes=64 << 20, max_slots=2, options=dgn.opts(serve_batch=serve_batch))
     keep = {}
     for k, p in enumerate(probs):
         A = dgn.to_device_factors(p.init)
@@ -225,9 +235,13 @@ def test_server_retires_failing_request():
     srv.close()
     assert set(res) == {0, 1, 2, 99}
     assert res[99]["status"] == -4
+    assert res[99]["lane"] == serve_batch
     for k in range(3):
         assert res[k]["status"] == 0
-        assert res[k]["info"] == alone[k][1]
+        assert res[k]["lane"] == int(serve_batch and len(probs[k].dims) == 3)
+        info = dict(res[k]["info"])
+        info.pop("t_done")
+        assert info == alone[k][1]
         for a, b in zip(dgn.to_host_factors(keep[k]), alone[k][0]):
             assert np.array_equal(a, b)
 
