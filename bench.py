@@ -29,6 +29,10 @@ PEAK_HBM_GBS = 8000.0
 PEAK_FP64_TFLOPS = 78.6
 
 
+def progress(msg):
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def workload(name):
     import cpgen
     if name == "500cube_r30":
@@ -679,6 +683,7 @@ def main():
     # FP32 tensor pass (MTTKRP in FP32 with FP32 accumulation), FP64 solve; the
     # rate is taken without per-phase events, the phase times from a second run
     # of the same trials with them
+    progress("main fit")
     run(args.warmup, dgn.opts())
     dt, info = run(args.steps, dgn.opts())
     o32 = dgn.opts(timing=1)
@@ -759,6 +764,7 @@ def main():
     }
     if cg_leg is not None:
         line["cg_auto"] = cg_leg
+    progress("hessian_solve")
     if not args.no_hsolve:
         # (J^T J + mu I)^-1 V for a random V at the starting factors: the step
         # without its tensor passes (block-form inverse, direct NR^2 solve)
@@ -774,24 +780,32 @@ def main():
         torch.cuda.synchronize()
         line["hessian_solve"] = {"ms_per_solve": round((time.perf_counter() - t0) / 5 * 1e3, 4), "mu": mu_h,
                                  "note": "(J^T J + mu I)^-1 V, V random, J at the starting factors of the workload"}
+    progress("als")
     if not args.no_als:
         line["als"] = bench_als(dgn, torch, ctx, y32, dims, R, p, dev)
+    progress("svd_init")
     if not args.no_svd:
         line["svd_init"] = bench_svd_init(dgn, torch, y32, dims, R, dev)
     ctx.close()
     del y32, ybf
     torch.cuda.empty_cache()
+    progress("precision")
     if not args.no_precision:
         line["precision"] = precision_report(dgn, torch, p)
+    progress("dgn_vs_flm")
     if not args.no_dgn_sweep:
         line["dgn_vs_flm"] = bench_dgn_vs_flm(dgn, torch)
+    progress("medsae")
     if args.medsae != "0":
         nt, nn = (int(v) for v in args.medsae.split("x"))
         line["medsae"] = bench_medsae(dgn, torch, tensors=nt, noisy=nn)
+    progress("batched")
     if not args.no_batched:
         line["batched"] = bench_batched(dgn, torch)
+    progress("serving")
     if not args.no_serving:
         line["serving"] = bench_serving(dgn, torch)
+    progress("cpu_baseline")
     if not args.no_cpu_baseline:
         line["cpu_baseline"], line["oracle_check"] = cpu_baseline(p, lambda ref, mu: oracle_check(dgn, torch, p, ref, mu))
     print(json.dumps(line), flush=True)

@@ -219,6 +219,7 @@ void carve(Arena& ar, Work& w, bool with_system) {
     w.sy.B = ar.take<double>((size_t)q.ntp * r2p);
     w.sy.yt = ar.take<double>((size_t)q.ntp);
     w.sy.Ld = ar.take<double>((size_t)q.Tt * 64 * 64);
+    w.sy.Li = ar.take<double>((size_t)q.Tt * 64 * 64);
   } else {
     w.sy = SysBuffers{nullptr, nullptr, nullptr, nullptr};
   }
@@ -248,6 +249,7 @@ void carve_explicit(Arena& ar, Work& w) {
   w.ey.B = nullptr;
   w.ey.yt = ar.take<double>((size_t)q.ntp);
   w.ey.Ld = ar.take<double>((size_t)q.Tt * 64 * 64);
+  w.ey.Li = ar.take<double>((size_t)q.Tt * 64 * 64);
 }
 
 dgn_status prepare_explicit(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, Work& w) {

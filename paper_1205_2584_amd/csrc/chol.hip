@@ -564,12 +564,21 @@ __host__ __device__ inline long long phase_trailing(const SysPlan& p, int ph) {
 // Tiles of a row per block (measured at 500^3, R = 30: one tile per block keeps
 // the phases shortest; three per block made them 0.4 us longer on average).
 constexpr int kGjGroup = 1;
+// The elimination does about Tt^3 / 6 tile products, as many flops as the
+// factorisation itself; it pays while a phase's elimination blocks (up to
+// (Tt / 2)^2) fit beside the panel in one round of the CUs.  Larger systems
+// (the explicit dGN Hessian, R > 45) take the tile-by-tile backward
+// substitution after the factorisation instead.
+constexpr int kGjMaxTiles = 48;
+__host__ __device__ inline bool use_gj(const SysPlan& p) { return p.Tt <= kGjMaxTiles; }
 __host__ __device__ inline int gj_groups(const SysPlan& p, int s) { return (p.Tt - 1 - s + kGjGroup - 1) / kGjGroup; }
 // write blocks of step s: groups of the tiles G_sm, m in (s, Tt - 1], then the vector a_s
-__host__ __device__ inline long long gj_writes(const SysPlan& p, int s) { return (s >= 0 && s < p.Tt) ? gj_groups(p, s) + 1 : 0; }
+__host__ __device__ inline long long gj_writes(const SysPlan& p, int s) {
+  return (use_gj(p) && s >= 0 && s < p.Tt) ? gj_groups(p, s) + 1 : 0;
+}
 // elimination blocks of step s: groups of the tiles (k, m), k < s < m < Tt, then the vectors a_k, k < s
 __host__ __device__ inline long long gj_elims(const SysPlan& p, int s) {
-  return (s >= 0 && s < p.Tt) ? (long long)s * gj_groups(p, s) + s : 0;
+  return (use_gj(p) && s >= 0 && s < p.Tt) ? (long long)s * gj_groups(p, s) + s : 0;
 }
 __host__ inline long long phase_blocks(const SysPlan& p, int ph) {
   return phase_panels(p, ph) + phase_trailing(p, ph) + gj_writes(p, ph - 1) + gj_elims(p, ph - 2);
@@ -881,6 +890,169 @@ __global__ __launch_bounds__(256, 2) void k_chol_phase(SysPlan p, int ph, double
     for (int v = 0; v < 4; ++v) C[(16 * blk + cl) + (long long)(16 * w + kq + 4 * v) * lds] -= acc[blk][v];
 }
 
+// L_kk^-1 of every diagonal tile (row-major, into Li), one workgroup per tile,
+// after the factorisation: the inverses only serve the backward substitution.
+__global__ __launch_bounds__(256) void k_inv_diag(SysPlan p, const double* Ld, double* Li, const int* stop) {
+  if (stopped(stop)) return;
+  __shared__ double T[64][TR];
+  __shared__ double X[64][TR];
+  __shared__ double rinv[64];
+  __shared__ double Z[4][16][16];
+  const int k = blockIdx.x, t = threadIdx.x;
+  stage_panel(T, Ld + (long long)k * 64 * 64, 64);
+  sync_block();
+  if (t < 64) rinv[t] = 1.0 / T[t][t];
+  sync_block();
+  invert_lower64(T, X, rinv, Z);
+  double* Xg = Li + (long long)k * 64 * 64;
+  for (int e = t; e < 64 * 64; e += 256) {
+    const int r = e >> 6, c = e & 63;
+    Xg[c + r * 64] = (c <= r) ? X[r][c] : 0.0;
+  }
+}
+
+// Backward substitution, phase k (descending).  Every block forms
+// y_k = L_kk^-T u_k from the inverse tile (u_k is the right-hand-side row of
+// tile column k); block k stores y_k and block j < k updates u_j -= L_kj^T y_k.
+__global__ __launch_bounds__(256) void k_bsolve(SysPlan p, int k, double* St, const double* Li, double* yt,
+                                                const int* stop) {
+  if (stopped(stop)) return;
+  __shared__ double Lt[64][TL];  // staged L(k, j), [col][row]
+  __shared__ double u[64];
+  __shared__ double ys[64];
+  __shared__ double part[4][64];
+  const long long lds = p.lds;
+  const int t = threadIdx.x, j = blockIdx.x, c = t & 63, g = t >> 6;
+  if (t < 64) u[t] = St[p.ntp + (long long)(k * 64 + t) * lds];
+  if (j != k) stage(Lt, St + k * 64 + (long long)j * 64 * lds, lds);
+  sync_block();
+  // y_k[c] = sum_r X[r][c] u[r], X = L_kk^-1 stored row-major
+  const double* X = Li + (long long)k * 64 * 64;
+  double acc = 0.0;
+#pragma unroll
+  for (int s2 = 0; s2 < 16; ++s2) {
+    const int r = g + 4 * s2;
+    acc += X[r * 64 + c] * u[r];
+  }
+  part[g][c] = acc;
+  sync_block();
+  if (t < 64) ys[t] = part[0][t] + part[1][t] + part[2][t] + part[3][t];
+  sync_block();
+  if (j == k) {
+    if (t < 64) yt[k * 64 + t] = ys[t];
+    return;
+  }
+  // u_j[c] -= sum_r L(k, j)[r][c] y_k[r]
+  acc = 0.0;
+#pragma unroll
+  for (int s2 = 0; s2 < 16; ++s2) {
+    const int r = g + 4 * s2;
+    acc += Lt[c][r] * ys[r];
+  }
+  part[g][c] = acc;
+  sync_block();
+  if (t < 64) {
+    const double v = part[0][t] + part[1][t] + part[2][t] + part[3][t];
+    St[p.ntp + (long long)(j * 64 + t) * lds] -= v;
+  }
+}
+
+// Backward substitution for the tile pair (k, k-1), k >= 1 (descending).  Every
+// block forms y_k = L_kk^-T u_k, u'_{k-1} = u_{k-1} - L(k, k-1)^T y_k and
+// y_{k-1} = L_{k-1,k-1}^-T u'_{k-1} from the inverse tiles; blocks k and k-1
+// store them, block j < k-1 updates u_j -= L(k, j)^T y_k + L(k-1, j)^T y_{k-1}.
+// All loads of a thread are issued before the first product.
+__global__ __launch_bounds__(256) void k_bsolve2(SysPlan p, int k, double* St, const double* Li, double* yt,
+                                                 const int* stop) {
+  if (stopped(stop)) return;
+  __shared__ double Lt[3][64][TL];  // L(k, k-1), L(k, j), L(k-1, j), each [col][row]
+  __shared__ double u[2][64];
+  __shared__ double ys[2][64];
+  __shared__ double part[4][64];
+  const long long lds = p.lds;
+  const int t = threadIdx.x, j = blockIdx.x, c = t & 63, g = t >> 6;
+  const bool upd = j < k - 1;
+  const double* src[3] = {St + k * 64 + (long long)(k - 1) * 64 * lds, upd ? St + k * 64 + (long long)j * 64 * lds : nullptr,
+                          upd ? St + (k - 1) * 64 + (long long)j * 64 * lds : nullptr};
+  const double* Xk = Li + (long long)k * 64 * 64;          // L_kk^-1, row-major
+  const double* Xk1 = Li + (long long)(k - 1) * 64 * 64;
+  double v[3][16], xk[16], xk1[16], u0 = 0.0, u1 = 0.0;
+  if (t < 64) {
+    u0 = St[p.ntp + (long long)(k * 64 + t) * lds];
+    u1 = St[p.ntp + (long long)((k - 1) * 64 + t) * lds];
+  }
+#pragma unroll
+  for (int s2 = 0; s2 < 16; ++s2) {
+    const int r = g + 4 * s2;
+    xk[s2] = Xk[r * 64 + c];
+    xk1[s2] = Xk1[r * 64 + c];
+  }
+#pragma unroll
+  for (int m = 0; m < 3; ++m)
+#pragma unroll
+    for (int s2 = 0; s2 < 16; ++s2) {
+      const int e = t + 256 * s2, rr = e & 63, cc = e >> 6;
+      v[m][s2] = src[m] ? src[m][rr + (long long)cc * lds] : 0.0;
+    }
+  if (t < 64) {
+    u[0][t] = u0;
+    u[1][t] = u1;
+  }
+#pragma unroll
+  for (int m = 0; m < 3; ++m)
+    if (src[m])
+#pragma unroll
+      for (int s2 = 0; s2 < 16; ++s2) {
+        const int e = t + 256 * s2, rr = e & 63, cc = e >> 6;
+        Lt[m][cc][rr] = v[m][s2];
+      }
+  sync_block();
+  // y_k[c] = sum_r X_k[r][c] u_k[r]
+  double acc = 0.0;
+#pragma unroll
+  for (int s2 = 0; s2 < 16; ++s2) acc += xk[s2] * u[0][g + 4 * s2];
+  part[g][c] = acc;
+  sync_block();
+  if (t < 64) ys[0][t] = part[0][t] + part[1][t] + part[2][t] + part[3][t];
+  sync_block();
+  // u_{k-1}[c] -= sum_r L(k, k-1)[r][c] y_k[r]
+  acc = 0.0;
+#pragma unroll
+  for (int s2 = 0; s2 < 16; ++s2) {
+    const int r = g + 4 * s2;
+    acc += Lt[0][c][r] * ys[0][r];
+  }
+  part[g][c] = acc;
+  sync_block();
+  if (t < 64) u[1][t] -= part[0][t] + part[1][t] + part[2][t] + part[3][t];
+  sync_block();
+  // y_{k-1}[c] = sum_r X_{k-1}[r][c] u'_{k-1}[r]
+  acc = 0.0;
+#pragma unroll
+  for (int s2 = 0; s2 < 16; ++s2) acc += xk1[s2] * u[1][g + 4 * s2];
+  part[g][c] = acc;
+  sync_block();
+  if (t < 64) ys[1][t] = part[0][t] + part[1][t] + part[2][t] + part[3][t];
+  sync_block();
+  if (j >= k - 1) {
+    if (t < 64) yt[(long long)j * 64 + t] = ys[j == k ? 0 : 1][t];
+    return;
+  }
+  // u_j[c] -= sum_r L(k, j)[r][c] y_k[r] + L(k-1, j)[r][c] y_{k-1}[r]
+  acc = 0.0;
+#pragma unroll
+  for (int s2 = 0; s2 < 16; ++s2) {
+    const int r = g + 4 * s2;
+    acc += Lt[1][c][r] * ys[0][r] + Lt[2][c][r] * ys[1][r];
+  }
+  part[g][c] = acc;
+  sync_block();
+  if (t < 64) {
+    const double d = part[0][t] + part[1][t] + part[2][t] + part[3][t];
+    St[p.ntp + (long long)(j * 64 + t) * lds] -= d;
+  }
+}
+
 // y_1 = z_1 - B^T y_t (one wave per entry) and y[R^2 + q] = y_t[q].
 __global__ __launch_bounds__(256) void k_y0(SysPlan p, const double* B, const double* z,
                                             const double* yt, double* y, const int* stop) {
@@ -963,12 +1135,23 @@ SysPlan plan_sys_c(const Shape& s) {
 
 hipError_t launch_sys_factor_solve_core(const SysPlan& p, const SysBuffers& y, int* singular, const int* stop,
                                         hipStream_t st) {
-  // Tt factorisation phases (each also writing and eliminating the solution's
-  // Gauss-Jordan steps), then two launches that finish the elimination
-  for (int ph = 0; ph < p.Tt + 2; ++ph) {
-    const long long nb = phase_blocks(p, ph);
-    if (nb > 0) k_chol_phase<<<(unsigned)nb, 256, 0, st>>>(p, ph, y.St, y.Ld, y.yt, singular, stop);
+  if (use_gj(p)) {
+    // Tt factorisation phases (each also writing and eliminating the solution's
+    // Gauss-Jordan steps), then two launches that finish the elimination
+    for (int ph = 0; ph < p.Tt + 2; ++ph) {
+      const long long nb = phase_blocks(p, ph);
+      if (nb > 0) k_chol_phase<<<(unsigned)nb, 256, 0, st>>>(p, ph, y.St, y.Ld, y.yt, singular, stop);
+    }
+    return hipGetLastError();
   }
+  // large systems: the factorisation, every L_kk^-1, then the backward
+  // substitution two tiles per launch
+  for (int ph = 0; ph < p.Tt; ++ph)
+    k_chol_phase<<<(unsigned)phase_blocks(p, ph), 256, 0, st>>>(p, ph, y.St, y.Ld, y.yt, singular, stop);
+  k_inv_diag<<<p.Tt, 256, 0, st>>>(p, y.Ld, y.Li, stop);
+  int k = p.Tt - 1;
+  for (; k >= 1; k -= 2) k_bsolve2<<<k + 1, 256, 0, st>>>(p, k, y.St, y.Li, y.yt, stop);
+  if (k == 0) k_bsolve<<<1, 256, 0, st>>>(p, 0, y.St, y.Li, y.yt, stop);
   return hipGetLastError();
 }
 

@@ -96,6 +96,8 @@ struct SysBuffers {
   double* Ld;   // Tt tiles of 64 x 64 (column-major, leading dimension 64): the factored
                 // diagonal tiles L(k, k). They live apart from St so that, while phase k
                 // runs, every workgroup still reads the unfactored tile (k, k) from St.
+  double* Li;   // Tt tiles of 64 x 64 (row-major): L(k, k)^-1, for the backward
+                // substitution of systems too large for the Gauss-Jordan elimination
 };
 
 hipError_t launch_sys_assemble(const Shape& s, const SysPlan& p, const SmallBuffers& b,
