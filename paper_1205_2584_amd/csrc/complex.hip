@@ -31,6 +31,8 @@ namespace dgn {
 
 namespace {
 
+typedef double v4d __attribute__((ext_vector_type(4)));
+
 struct cd {
   double x, y;
 };
@@ -107,18 +109,24 @@ __device__ cd cq_conj(const PassArgsC& a, long long q, int r) {
   return c;
 }
 
-// Slab tile 32 x 32 of Y_q; thread (lane32, rg) owns row lane32 and the
-// columns r = rg + 8k of Z_q = Y_q conj(A^(2)) and W_q = Y_q^T conj(A^(1)).
+// Slab tile 32 x 32 of Y_q on the FP64 matrix cores.  Per slice the three complex products
+// of a 32 x 32 tile (Y_hat for the residual, Z_q = Y_q conj(A^(2)) and
+// W_q = Y_q^T conj(A^(1))) run as 16 x 16 MFMA tiles, each complex product as
+// four real ones (re += a.re b.re - a.im b.im, im += a.re b.im + a.im b.re).
+// v_mfma_f64_16x16x4f64: lane l holds A[l%16][l/16] and B[l/16][l%16] of the
+// step and the result D[l/16 + 4v][l%16].  Wave w takes row block w >> 1 and
+// column block w & 1 (ranks 16 (w & 1).. of Z and W; columns j of Y_hat).
 template <typename TY, bool RESID>
-__global__ __launch_bounds__(256) void k_pass_c(PassArgsC a, const int* stop) {
+__global__ __launch_bounds__(256) void k_pass_cm(PassArgsC a, const int* stop) {
   if (stopped(stop)) return;
-  __shared__ cd Ys[TC][TC + 1];  // Ys[jj][ii] = Y[i0 + ii, j0 + jj, q] (or E)
-  __shared__ cd A0s[TC][LC];     // conj(A^(1)) rows of the tile
-  __shared__ cd A1s[TC][LC];     // conj(A^(2)) rows of the tile
-  __shared__ cd A1c[RESID ? TC : 1][LC];  // conj(A^(2)) diag(conj c_q)
+  __shared__ cd Ys[TC][TC + 1];            // Ys[jj][ii] = Y[i0 + ii, j0 + jj, q] (or E)
+  __shared__ cd A0s[TC][LC];               // conj(A^(1)) rows of the tile, zero beyond R
+  __shared__ cd A1s[TC][LC];               // conj(A^(2)) rows of the tile, zero beyond R
+  __shared__ cd A1c[RESID ? TC : 1][LC];   // conj(A^(2)) diag(conj c_q)
   __shared__ cd cq[kMaxRankC];
+  __shared__ cd tl[2][kMaxRankC];          // t_q partial of each row block
   __shared__ double red[16];
-  const int t = threadIdx.x, l32 = t & 31, rg = t >> 5;
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63, li = lane & 15, lk = lane >> 4;
   const int R = a.R, I0 = a.I0, I1 = a.I1;
   const int tile = blockIdx.x, tj = tile % a.tiles_j, ti = tile / a.tiles_j;
   const int i0 = ti * TC, j0 = tj * TC;
@@ -132,82 +140,108 @@ __global__ __launch_bounds__(256) void k_pass_c(PassArgsC a, const int* stop) {
     A0s[ii][r] = (r < R && gi < I0) ? conjc(a.A[a.off[0] + gi + (long long)r * I0]) : czero();
     A1s[ii][r] = (r < R && gj < I1) ? conjc(a.A[a.off[1] + gj + (long long)r * I1]) : czero();
   }
-  const int KR = (R + 7) / 8;
+  const int xb = w >> 1, rb = w & 1;
+  const bool zw_on = rb * 16 < R;
+  const int rr = 16 * rb + li;  // rank of this lane's Z and W columns
   cd m0[4], m1[4];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    m0[k] = czero();
-    m1[k] = czero();
+  for (int v = 0; v < 4; ++v) {
+    m0[v] = czero();
+    m1[v] = czero();
   }
   double e2 = 0.0;
+  cd* tp = a.tpart + (long long)tile * R * a.Q;
+  const int KR4 = (R + 3) / 4;
   for (long long q = q0; q < q1; ++q) {
     sync_block();
+    if (q > q0 && t < R) tp[(long long)t * a.Q + q - 1] = tl[0][t] + tl[1][t];
     const long long base = (long long)I0 * I1 * q;
-    for (int e = t; e < TC * TC; e += 256) {
-      const int ii = e % TC, jj = e / TC;
+    cd yv[TC * TC / 256];
+#pragma unroll
+    for (int k = 0; k < TC * TC / 256; ++k) {
+      const int e = t + 256 * k, ii = e % TC, jj = e / TC;
       const int gi = i0 + ii, gj = j0 + jj;
-      Ys[jj][ii] = (gi < I0 && gj < I1) ? load_c<TY>(Y, base + gi + (long long)I0 * gj) : czero();
+      yv[k] = (gi < I0 && gj < I1) ? load_c<TY>(Y, base + gi + (long long)I0 * gj) : czero();
     }
-    if (t < R) cq[t] = cq_conj(a, q, t);
+    if (t < kMaxRankC) cq[t] = (t < R) ? cq_conj(a, q, t) : czero();
+#pragma unroll
+    for (int k = 0; k < TC * TC / 256; ++k) {
+      const int e = t + 256 * k, ii = e % TC, jj = e / TC;
+      Ys[jj][ii] = yv[k];
+    }
     sync_block();
     if (RESID) {
       for (int e = t; e < TC * kMaxRankC; e += 256) {
         const int jj = e % TC, r = e / TC;
-        A1c[jj][r] = r < R ? A1s[jj][r] * cq[r] : czero();
+        A1c[jj][r] = A1s[jj][r] * cq[r];
       }
       sync_block();
-      // E = Y - Y_hat, Y_hat = conj(sum_r conj(A1) conj(A2) conj(c_q))
-      for (int e = t; e < TC * TC; e += 256) {
-        const int ii = e % TC, jj = e / TC;
-        cd yc = czero();
-        for (int r = 0; r < R; ++r) yc += A0s[ii][r] * A1c[jj][r];
-        const cd ev = Ys[jj][ii] - conjc(yc);  // zero outside the tensor
+      // conj(Y_hat)[i][j] = sum_r A0s[i][r] A1c[j][r]: rows i = 16 xb.., columns j = 16 rb..
+      v4d hre = v4d{0.0, 0.0, 0.0, 0.0}, him = v4d{0.0, 0.0, 0.0, 0.0};
+      for (int k4 = 0; k4 < KR4; ++k4) {
+        const int kk = 4 * k4 + lk;
+        const cd av = A0s[16 * xb + li][kk];
+        const cd bv = A1c[16 * rb + li][kk];
+        hre = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, bv.x, hre, 0, 0, 0);
+        hre = __builtin_amdgcn_mfma_f64_16x16x4f64(-av.y, bv.y, hre, 0, 0, 0);
+        him = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, bv.y, him, 0, 0, 0);
+        him = __builtin_amdgcn_mfma_f64_16x16x4f64(av.y, bv.x, him, 0, 0, 0);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int ii = 16 * xb + lk + 4 * v, jj = 16 * rb + li;
+        const cd ev = Ys[jj][ii] - cd{hre[v], -him[v]};  // zero outside the tensor
         e2 += abs2(ev);
         Ys[jj][ii] = ev;
       }
       sync_block();
     }
-    cd zp[4], wp[4];
+    if (zw_on) {
+      v4d zre = v4d{0.0, 0.0, 0.0, 0.0}, zim = v4d{0.0, 0.0, 0.0, 0.0};
+      v4d wre = v4d{0.0, 0.0, 0.0, 0.0}, wim = v4d{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      zp[k] = czero();
-      wp[k] = czero();
-    }
-    for (int jj = 0; jj < TC; ++jj) {
-      const cd yv = Ys[jj][l32];
-#pragma unroll
-      for (int k = 0; k < 4; ++k)
-        if (k < KR) zp[k] += yv * A1s[jj][rg + 8 * k];
-    }
-    for (int ii = 0; ii < TC; ++ii) {
-      const cd yv = Ys[l32][ii];
-#pragma unroll
-      for (int k = 0; k < 4; ++k)
-        if (k < KR) wp[k] += yv * A0s[ii][rg + 8 * k];
-    }
-    cd* tp = a.tpart + (long long)tile * R * a.Q;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      if (k < KR) {
-        const int r = rg + 8 * k;
-        const cd c = (r < R) ? cq[r] : czero();
-        m0[k] += c * zp[k];
-        m1[k] += c * wp[k];
-        cd tv = A0s[l32][r] * zp[k];
-#pragma unroll
-        for (int o = 16; o > 0; o >>= 1) tv += shfl_xor_cd(tv, o);  // within the 32-lane half
-        if (l32 == 0 && r < R) tp[(long long)r * a.Q + q] = tv;
+      for (int k4 = 0; k4 < TC / 4; ++k4) {
+        const int kk = 4 * k4 + lk;
+        // Z: A[i][j] = Y(i, j), i = 16 xb + li, j = kk; B[j][r] = A1s[j][r]
+        const cd ya = Ys[kk][16 * xb + li];
+        const cd b1 = A1s[kk][rr];
+        zre = __builtin_amdgcn_mfma_f64_16x16x4f64(ya.x, b1.x, zre, 0, 0, 0);
+        zre = __builtin_amdgcn_mfma_f64_16x16x4f64(-ya.y, b1.y, zre, 0, 0, 0);
+        zim = __builtin_amdgcn_mfma_f64_16x16x4f64(ya.x, b1.y, zim, 0, 0, 0);
+        zim = __builtin_amdgcn_mfma_f64_16x16x4f64(ya.y, b1.x, zim, 0, 0, 0);
+        // W: A[j][i] = Y(i, j), j = 16 xb + li, i = kk; B[i][r] = A0s[i][r]
+        const cd yw = Ys[16 * xb + li][kk];
+        const cd b0 = A0s[kk][rr];
+        wre = __builtin_amdgcn_mfma_f64_16x16x4f64(yw.x, b0.x, wre, 0, 0, 0);
+        wre = __builtin_amdgcn_mfma_f64_16x16x4f64(-yw.y, b0.y, wre, 0, 0, 0);
+        wim = __builtin_amdgcn_mfma_f64_16x16x4f64(yw.x, b0.y, wim, 0, 0, 0);
+        wim = __builtin_amdgcn_mfma_f64_16x16x4f64(yw.y, b0.x, wim, 0, 0, 0);
       }
+      const cd c = cq[rr];
+      cd tv = czero();
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const cd z = cd{zre[v], zim[v]}, wv = cd{wre[v], wim[v]};
+        m0[v] += c * z;
+        m1[v] += c * wv;
+        tv += A0s[16 * xb + lk + 4 * v][rr] * z;
+      }
+      // sum over the four row groups of the 16 rows (lanes li + 16 lk)
+      tv += shfl_xor_cd(tv, 16);
+      tv += shfl_xor_cd(tv, 32);
+      if (lk == 0 && rr < R) tl[xb][rr] = tv;
     }
   }
+  sync_block();
+  if (q1 > q0 && t < R) tp[(long long)t * a.Q + q1 - 1] = tl[0][t] + tl[1][t];
   cd* m0p = a.m0part + ((long long)blockIdx.y * a.tiles_j + tj) * R * I0;
   cd* m1p = a.m1part + ((long long)blockIdx.y * a.tiles_i + ti) * R * I1;
+  if (zw_on && rr < R) {
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const int r = rg + 8 * k;
-    if (k < KR && r < R) {
-      if (i0 + l32 < I0) m0p[(long long)r * I0 + i0 + l32] = m0[k];
-      if (j0 + l32 < I1) m1p[(long long)r * I1 + j0 + l32] = m1[k];
+    for (int v = 0; v < 4; ++v) {
+      const int ro = 16 * xb + lk + 4 * v;
+      if (i0 + ro < I0) m0p[(long long)rr * I0 + i0 + ro] = m0[v];
+      if (j0 + ro < I1) m1p[(long long)rr * I1 + j0 + ro] = m1[v];
     }
   }
   if (RESID) {
@@ -846,11 +880,11 @@ hipError_t launch_tensor_pass_c(const Shape& s, bool y64, const void* Y, const d
   a.e2part = b.e2part;
   const dim3 grid((unsigned)(p.tiles_i * p.tiles_j), (unsigned)p.n_qc);
   if (y64) {
-    if (resid) k_pass_c<double2, true><<<grid, 256, 0, st>>>(a, stop);
-    else k_pass_c<double2, false><<<grid, 256, 0, st>>>(a, stop);
+    if (resid) k_pass_cm<double2, true><<<grid, 256, 0, st>>>(a, stop);
+    else k_pass_cm<double2, false><<<grid, 256, 0, st>>>(a, stop);
   } else {
-    if (resid) k_pass_c<float2, true><<<grid, 256, 0, st>>>(a, stop);
-    else k_pass_c<float2, false><<<grid, 256, 0, st>>>(a, stop);
+    if (resid) k_pass_cm<float2, true><<<grid, 256, 0, st>>>(a, stop);
+    else k_pass_cm<float2, false><<<grid, 256, 0, st>>>(a, stop);
   }
   cd* M = reinterpret_cast<cd*>(Md);
   const int R = s.R;
