@@ -194,7 +194,7 @@ def bench_batched(dgn, torch, count=1024, max_iters=200, tol=1e-8, seq_sample=12
                                          "time; the 1024 tensors together fit in the 256 MB Infinity Cache"}}
 
 
-def bench_serving(dgn, torch, n_req=2000, rate=2000.0, slots=4, seed=5):
+def bench_serving(dgn, torch, n_req=2000, rate=2000.0, slots=8, seed=5):
     """Poisson arrival trace (mean `rate` req/s) of `n_req` distinct seeded fit
     requests, each generated on the GPU before the replay: N in {3,4}, I_n
     log-uniform in [16,256], R ~ U{2..20}, correlation U[0,0.95], 20 dB, 20 %
