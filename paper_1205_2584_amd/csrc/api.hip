@@ -332,9 +332,8 @@ hipError_t enqueue_step(Work& w, bool resid, double mu_host, FitState* state, in
   hipError_t e;
   if ((e = mark(ev, 0, st)) != hipSuccess) return e;
   if ((e = launch_gamma(s, w.sb.C, mu_host, state, w.sb, singular, stop, st)) != hipSuccess) return e;
-  if ((e = launch_pw(s, w.A, w.M, resid, w.sb, stop, st)) != hipSuccess) return e;
+  if ((e = launch_pw(s, w.A, w.M, resid, w.sb, true, stop, st)) != hipSuccess) return e;
   if ((e = launch_wz(s, w.sb, stop, st)) != hipSuccess) return e;
-  if ((e = launch_tnm(s, w.sb, stop, st)) != hipSuccess) return e;
   if ((e = mark(ev, 1, st)) != hipSuccess) return e;
   // DGN_SOLVER_AUTO: CG first; the direct assembly and solve then skip
   // themselves (flags[8] set) when CG converged or the fit has stopped
@@ -730,7 +729,7 @@ dgn_status dgn_step_explicit(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, const
   HIPCHK(launch_err2(s, w.A, w.M, w.sb.C, resid, e2a, ynp, out, st), "err2");
   // gradient blocks G (and ||G||^2, ||M||^2) through the fast step's own kernels
   HIPCHK(launch_gamma(s, w.sb.C, mu, nullptr, w.sb, w.flags, nullptr, st), "gamma");
-  HIPCHK(launch_pw(s, w.A, w.M, resid, w.sb, nullptr, st), "pw");
+  HIPCHK(launch_pw(s, w.A, w.M, resid, w.sb, false, nullptr, st), "pw");
   HIPCHK(launch_wz(s, w.sb, nullptr, st), "wz");
   // (J^T J + mu I) da = g, J^T J formed explicitly
   HIPCHK(launch_explicit_system(s, w.ep, w.A, w.sb.C, w.sb.G, mu, w.ey.St, st), "hessian");

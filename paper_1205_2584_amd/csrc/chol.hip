@@ -16,12 +16,12 @@
 // backward substitution runs tile by tile afterwards.
 #include "common.hpp"
 #include "internal.hpp"
+#include "panel.hpp"
 
 namespace dgn {
 
 namespace {
 
-typedef double v4d __attribute__((ext_vector_type(4)));
 constexpr int LD = kMaxRank + 1;
 constexpr int TL = 65;  // padded leading dimension of 64 x 64 LDS tiles
 
@@ -85,14 +85,6 @@ __device__ __forceinline__ void stage_rowmajor(double (*T)[TL], const double* g,
   }
 }
 
-// 1/sqrt(x) to FP64 accuracy: hardware estimate refined by two Newton steps.
-__device__ __forceinline__ double rsqrt_f64(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-  y = y * (1.5 - 0.5 * x * y * y);
-  y = y * (1.5 - 0.5 * x * y * y);
-  return y;
-}
-
 // acc[blk] += A * B^T from LDS tiles stored [col][row]; wave w owns rows
 // 16w.. of A; the result element (v, blk) is (A B^T)[acc_row(v)][acc_col(blk)].
 __device__ __forceinline__ void mma_lds(const double (*A)[TL], const double (*B)[TL], v4d acc[4]) {
@@ -114,104 +106,6 @@ __device__ __forceinline__ void mma_lds(const double (*A)[TL], const double (*B)
 // factored in four 16-column steps: a 16 x 16 Cholesky of the diagonal block by
 // one wave, a row-parallel triangular solve for every row below it, and an MFMA
 // update of the columns to its right.
-
-constexpr int TR = 66;  // row stride of the panel: T[row][k] MFMA operand reads are bank-conflict free
-
-// Broadcast lane SRC of each 16-lane row of v to that whole row (DPP row_newbcast).
-template <int SRC>
-__device__ __forceinline__ double row_bcast(double v) {
-  return __builtin_amdgcn_update_dpp(0.0, v, 0x150 + SRC, 0xf, 0xf, true);
-}
-
-// 1/x to FP64 accuracy: hardware estimate y = (1 - e)/x refined by one cubic
-// step, y (1 + e + e^2) = (1 - e^3)/x.
-__device__ __forceinline__ double rcp_f64(double x) {
-  const double y = __builtin_amdgcn_rcp(x);
-  const double e = __builtin_fma(-x, y, 1.0);
-  return __builtin_fma(__builtin_fma(e, e, e), y, y);
-}
-
-// Column C of the in-register 16 x 16 factorisation in L D L^T form: lane `row`
-// holds row `row` in r.  With a = A[row][C] (unscaled) and d_C = A[C][C], the
-// rows below the pivot are updated by A[row][J] -= (a / d_C) A[J][C]; the
-// broadcasts of column C do not wait for the reciprocal of the pivot.  r[C]
-// keeps a (so lane C keeps d_C).
-template <int J>
-__device__ __forceinline__ void ldl_update(double (&r)[16], double l, double a) {
-  if constexpr (J < 16) {
-    r[J] -= l * row_bcast<J>(a);
-    ldl_update<J + 1>(r, l, a);
-  }
-}
-
-template <int C>
-__device__ __forceinline__ void ldl_column(double (&r)[16], int row, bool& ok) {
-  if constexpr (C < 16) {
-    const double a = r[C];
-    const double am = (row > C) ? a : 0.0;
-    const double piv = row_bcast<C>(a);
-    ok = ok && (piv > 0.0);
-    ldl_update<C + 1>(r, am * rcp_f64(piv), a);
-    ldl_column<C + 1>(r, row, ok);
-  }
-}
-
-// Rescale the L D L^T result of one lane to the Cholesky factor:
-// L[row][c] = A^(c)[row][c] / sqrt(d_c).
-template <int C>
-__device__ __forceinline__ void ldl_scale(double (&r)[16], int row, double myd, double myrsq) {
-  if constexpr (C < 16) {
-    const double rs = row_bcast<C>(myrsq);
-    r[C] = (row > C) ? r[C] * rs : (row == C ? myd * myrsq : 0.0);
-    ldl_scale<C + 1>(r, row, myd, myrsq);
-  }
-}
-
-// Cholesky of the 16 x 16 block T[k0.., k0..] by one wave (each 16-lane row of
-// the wave computes the same rows).  L goes back into T (zeros above), a
-// compact copy into Lkk, and 1/L_cc into rinv[k0 + c].  A non-positive pivot
-// sets *bad.
-__device__ void chol16(double (*T)[TR], int k0, int* bad, double (*Lkk)[16], double* rinv) {
-  const int lane = threadIdx.x & 63;
-  const int row = lane & 15;
-  double r[16];
-#pragma unroll
-  for (int j = 0; j < 16; ++j) r[j] = T[k0 + row][k0 + j];
-  bool ok = true;
-  ldl_column<0>(r, row, ok);
-  double myd = 0.0;
-#pragma unroll
-  for (int j = 0; j < 16; ++j)
-    if (row == j) myd = r[j];
-  const double myrsq = rsqrt_f64(myd > 0.0 ? myd : 1.0);
-  ldl_scale<0>(r, row, myd, myrsq);
-  if (lane < 16) {
-#pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      T[k0 + row][k0 + j] = r[j];
-      Lkk[row][j] = r[j];
-    }
-    rinv[k0 + row] = myrsq;
-  }
-  if (!ok && lane == 0) *bad = 1;
-}
-
-// Row r of the 16-column block k0: T[r][k0..] <- T[r][k0..] L_kk^-T.
-__device__ __forceinline__ void trsm16_row(double (*T)[TR], int r, int k0, const double (*Lkk)[16],
-                                           const double* rinv) {
-  double x[16];
-#pragma unroll
-  for (int c = 0; c < 16; ++c) x[c] = T[r][k0 + c];
-#pragma unroll
-  for (int c = 0; c < 16; ++c) {
-    double v = x[c];
-#pragma unroll
-    for (int d = 0; d < c; ++d) v -= x[d] * Lkk[c][d];
-    x[c] = v * rinv[k0 + c];
-  }
-#pragma unroll
-  for (int c = 0; c < 16; ++c) T[r][k0 + c] = x[c];
-}
 
 // Stage a 64 x 64 column-major global tile into LDS rows T[r][c] (row stride TR).
 __device__ __forceinline__ void stage_panel(double (*T)[TR], const double* g, long long ld) {
@@ -254,54 +148,6 @@ __device__ __forceinline__ void panel_trail_block(int b, int kb, int& bi, int& b
   } else {
     bi = 4 + (b - ndb) / m;
     bj = kb + 1 + (b - ndb) % m;
-  }
-}
-
-// X = L^-1 for the lower 64 x 64 factor in T rows 0..63, written to X (rows
-// 64..127 of the panel array, unused by the diagonal workgroup).  Diagonal
-// 16-blocks by forward substitution (wave w inverts block w, lane j a column),
-// then the blocks at distance d = 1..3 below the diagonal:
-//   X_ij = -X_ii sum_{k=j}^{i-1} L_ik X_kj.
-__device__ void invert_lower64(double (*T)[TR], double (*X)[TR], const double* rinv, double (*Z)[16][16]) {
-  const int t = threadIdx.x, w = t >> 6, lane = t & 63, cl = lane & 15, kq = lane >> 4;
-  {
-    const int b0 = 16 * w, j = cl;
-    double x[16];
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      double v = (i == j) ? 1.0 : 0.0;
-#pragma unroll
-      for (int k = 0; k < i; ++k) v -= T[b0 + i][b0 + k] * x[k];
-      x[i] = v * rinv[b0 + i];
-    }
-    if (lane < 16) {
-#pragma unroll
-      for (int i = 0; i < 16; ++i) X[b0 + i][b0 + j] = x[i];
-    }
-  }
-  sync_block();
-  for (int d = 1; d < 4; ++d) {
-    const int j = w, i = w + d;
-    if (i < 4) {
-      v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
-      for (int k = j; k < i; ++k)
-#pragma unroll
-        for (int s2 = 0; s2 < 16; s2 += 4)
-          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(T[16 * i + cl][16 * k + s2 + kq], X[16 * k + s2 + kq][16 * j + cl],
-                                                     acc, 0, 0, 0);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) Z[w][kq + 4 * v][cl] = acc[v];
-      // Z is written and read by the same wave only
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-      __builtin_amdgcn_wave_barrier();
-      acc = v4d{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int s2 = 0; s2 < 16; s2 += 4)
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(X[16 * i + cl][16 * i + s2 + kq], Z[w][s2 + kq][cl], acc, 0, 0, 0);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) X[16 * i + kq + 4 * v][16 * j + cl] = -acc[v];
-    }
-    sync_block();
   }
 }
 
@@ -783,15 +629,7 @@ __global__ __launch_bounds__(256, 2) void k_chol_phase(SysPlan p, int ph, double
     if (hb) stage_panel(T + 64, Bg, lds);
     sync_block();
     // in-panel update of the 16 x 16 block (bi, bj) with column step k0
-    auto trail_block = [&](int bi, int bj, int k0) {
-      v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int k = 0; k < 16; k += 4)
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(T[16 * bi + cl][k0 + k + kq], T[16 * bj + cl][k0 + k + kq], acc,
-                                                   0, 0, 0);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) T[16 * bi + kq + 4 * v][16 * bj + cl] -= acc[v];
-    };
+    auto trail_block = [&](int bi, int bj, int k0) { trail16(T, bi, bj, k0); };
     if (ph > 0) update_rows(dri, dri + 1, La, av0, bv0);
     if (lane == 0) __hip_atomic_fetch_add(&d_done, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
     if (w == 0) {

@@ -61,10 +61,12 @@ hipError_t launch_gram(const Shape& s, const double* A, const SmallBuffers& b, d
                        const int* stop, hipStream_t st);
 hipError_t launch_gamma(const Shape& s, const double* C, double mu_host, const FitState* state,
                         const SmallBuffers& b, int* singular, const int* stop, hipStream_t st);
+// G, P and the row-chunk partials of w (and, with with_tnm, the T_nm of the
+// NR^2 assembly in the same launch).
 hipError_t launch_pw(const Shape& s, const double* A, const double* M, bool resid,
-                     const SmallBuffers& b, const int* stop, hipStream_t st);
+                     const SmallBuffers& b, bool with_tnm, const int* stop, hipStream_t st);
+// w, ||G||^2, ||M||^2 from the partials, and z = W^T K w.
 hipError_t launch_wz(const Shape& s, const SmallBuffers& b, const int* stop, hipStream_t st);
-hipError_t launch_tnm(const Shape& s, const SmallBuffers& b, const int* stop, hipStream_t st);
 hipError_t launch_u(const Shape& s, const SmallBuffers& b, const int* stop, hipStream_t st);
 hipError_t launch_fq(const Shape& s, const SmallBuffers& b, const int* stop, hipStream_t st);
 // A_c = A + P - A Q_n; partial Grams of A_c and the gain-ratio denominator.

@@ -12,6 +12,7 @@
 // u = w - W y, f = K u, Q_n = F_n Gt_n and the update A_n + P_n - A_n Q_n.
 #include "common.hpp"
 #include "internal.hpp"
+#include "panel.hpp"
 
 namespace dgn {
 
@@ -27,6 +28,43 @@ __device__ __forceinline__ int rr_shift_of(int R) { return R <= 16 ? 4 : (R <= 3
 #define FOR_RR(r, q)                                                              \
   for (int q = (int)(threadIdx.x >> rr_sh); q < R; q += (int)(blockDim.x >> rr_sh)) \
     for (int r = (int)(threadIdx.x & ((1 << rr_sh) - 1)); r < R; r += (1 << rr_sh))
+
+// Products of small LDS matrices on the FP64 matrix cores.  Each 16 x 16
+// result block (ti, tj), ti < mt, tj < nt, is formed by one wave (the waves
+// take the blocks in turn) as out(i, j, sum_{k < K} a(i, k) b(k, j)), K a
+// multiple of 4; the operands must be zero wherever i, j or k lies beyond the
+// true sizes.  v_mfma_f64_16x16x4f64: lane l supplies a(16 ti + l%16, k + l/16)
+// and b(k + l/16, 16 tj + l%16) and receives the result rows 16 ti + l/16 + 4v
+// of column 16 tj + l%16.  Call from wave-uniform control flow.
+template <typename FA, typename FB, typename FO>
+__device__ __forceinline__ void mm16(int mt, int nt, int K, FA a, FB b, FO out) {
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, cl = lane & 15, kq = lane >> 4;
+  for (int tile = w; tile < mt * nt; tile += (int)(blockDim.x >> 6)) {
+    const int ti = tile % mt, tj = tile / mt;
+    v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+    for (int k = 0; k < K; k += 4)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a(16 * ti + cl, k + kq), b(k + kq, 16 * tj + cl), acc, 0, 0, 0);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) out(16 * ti + kq + 4 * v, 16 * tj + cl, acc[v]);
+  }
+}
+
+// R rounded up to a multiple of 16 (the MFMA block edge).
+__device__ __forceinline__ int round16(int R) { return (R + 15) & ~15; }
+
+// Zero S[i][j], i < 64, R <= j < Rp (the padding columns of a 64-row block).
+__device__ __forceinline__ void pad_cols(double (*S)[LD], int R, int Rp) {
+  for (int e = threadIdx.x; e < 64 * (Rp - R); e += blockDim.x) S[e & 63][R + (e >> 6)] = 0.0;
+}
+
+// Zero S[i][j], i, j < Rp, outside the leading R x R block.
+__device__ __forceinline__ void pad_rr(double (*S)[LD], int R, int Rp) {
+  for (int e = threadIdx.x; e < 64 * Rp; e += blockDim.x) {
+    const int i = e & 63, j = e >> 6;
+    if (i < Rp && (i >= R || j >= R)) S[i][j] = 0.0;
+  }
+}
 
 // FOR_RR for staging: the values of up to four q-steps of the thread are
 // produced first (their loads in flight together), then put stores them.
@@ -92,48 +130,6 @@ __device__ __forceinline__ void stage_rows(double (*S)[LD], const double* src, i
   if (sq) *sq += acc;
 }
 
-// Cholesky of the R x R matrix H (lower, in place) with 256 threads.
-// mode 0: a non-positive pivot sets *bad.  mode 1 (semidefinite): a pivot
-// below 64 u times the original diagonal zeroes the column.
-__device__ void chol_lds(double (*H)[LD], int R, int mode, int* bad, double* lk) {
-  const int t = threadIdx.x;
-  for (int k = 0; k < R; ++k) {
-    sync_block();
-    const double dkk = H[k][k];
-    double d = 1.0, inv = 1.0;
-    bool zero = false;
-    if (mode == 0) {
-      if (!(dkk > 0.0)) {
-        if (t == 0) *bad = 1;
-      } else {
-        d = sqrt(dkk);
-        inv = 1.0 / d;
-      }
-    } else {
-      const double ref = lk[64 + k];
-      if (!(dkk > 64.0 * 2.220446049250313e-16 * ref)) {
-        zero = true;
-      } else {
-        d = sqrt(dkk);
-        inv = 1.0 / d;
-      }
-    }
-    for (int i = k + t; i < R; i += blockDim.x) lk[i] = zero ? 0.0 : ((i == k) ? d : H[i][k] * inv);
-    sync_block();
-    for (int j = k + 1 + (int)(t >> 6); j < R; j += (int)(blockDim.x >> 6)) {
-      const int i = t & 63;
-      if (i >= j && i < R) H[i][j] -= lk[i] * lk[j];
-    }
-    for (int i = k + t; i < R; i += blockDim.x) H[i][k] = lk[i];
-  }
-  sync_block();
-  RR_SHIFT;
-  FOR_RR(i, j) {
-    if (j > i) H[i][j] = 0.0;
-  }
-  sync_block();
-}
-
 // Gram partials of 64-row chunks: part[(n * chunks + c) * stride + (r + s R)].
 __global__ __launch_bounds__(256) void k_gram_part(Shape s, const double* A, double* part,
                                                    int chunks, int stride, const int* stop) {
@@ -177,82 +173,99 @@ __global__ void k_rows_reduce(const double* part, int N, int chunks, int stride,
   }
 }
 
-// Per mode n: Gamma_n, Cholesky of Gamma_n + mu I, its inverse factor
-// X_n = L^-T, Gt_n = X_n X_n^T, and the (semidefinite-safe) Cholesky L_n of C_n.
+// Factor an Rp x Rp block (Rp = 16 nkb) held in T rows 0..Rp-1 in place by the
+// first wave: per 16-column step the L D L^T of the diagonal block, the
+// triangular solve of the rows below it and the MFMA update of the blocks to
+// its right.  PSD: semidefinite-safe, with the original diagonal in dref.
+template <bool PSD>
+__device__ void chol_chain(double (*T)[TR], int nkb, int* bad, double (*Lk)[16][16], double* rinv,
+                           const double* dref) {
+  const int lane = threadIdx.x & 63, Rp = 16 * nkb;
+  for (int kb = 0; kb < nkb; ++kb) {
+    const int k0 = 16 * kb;
+    chol16<PSD>(T, k0, bad, Lk[kb], rinv, dref);
+    if (lane < Rp - k0 - 16) trsm16_row(T, k0 + 16 + lane, k0, Lk[kb], rinv);
+    for (int bi = kb + 1; bi < nkb; ++bi)
+      for (int bj = kb + 1; bj <= bi; ++bj) trail16(T, bi, bj, k0);
+  }
+}
+
+// Per mode n (blockIdx.y = 0): Gamma_n, the Cholesky factor L of Gamma_n + mu I,
+// X_n = L^-T and Gt_n = X_n X_n^T = (Gamma_n + mu I)^-1; a non-positive pivot
+// sets *bad.  blockIdx.y = 1: the semidefinite-safe Cholesky factor L_n of C_n
+// (a pivot below 64 u times its original diagonal drops its column).  The R x R
+// matrix is the leading block of a 64 x 64 LDS tile completed with the
+// identity; the first wave factors it and the workgroup inverts the factor.
 __global__ __launch_bounds__(256) void k_gamma(Shape s, const double* C, double mu_host,
                                                const FitState* state, double* Gam, double* Gt,
                                                double* X, double* Lc, int* bad, const int* stop) {
   if (stopped(stop)) return;
-  __shared__ double H[64][LD];
-  __shared__ double Li[64][LD];
-  __shared__ double lk[128];
+  __shared__ double T[128][TR];                   // rows 0..63: H, then L; rows 64..127: L^-1
+  __shared__ __align__(16) double Lk[4][16][16];  // L_kk of each column step, then scratch
+  __shared__ double rinv[64];                     // 1 / L_kk
   const int n = blockIdx.x, R = s.R, R2 = R * R, N = s.N, t = threadIdx.x;
+  const int nkb = (R + 15) >> 4, Rp = 16 * nkb;
+  const bool chol_c = blockIdx.y == 1;
   RR_SHIFT;
-  if (blockIdx.y == 1) {
-    // the (semidefinite-safe) Cholesky L_n of C_n, in parallel with the damped inverse
+  const double mu = state ? state->mu : mu_host;
+  double* dref = &T[64][0];  // original diagonal of C_n (the semidefinite factor only)
+  if (chol_c) {
     for_rr_staged(
         R, rr_sh, [&](int r, int q) { return C[(long long)n * R2 + r + q * R]; },
-        [&](int r, int q, double v) { H[r][q] = v; });
-    for (int r = t; r < R; r += 256) lk[64 + r] = C[(long long)n * R2 + r + r * R];
-    chol_lds(H, R, 1, bad, lk);
-    FOR_RR(r, q) {
-      const int e = r + q * R;
-      Lc[(long long)n * R2 + e] = H[r][q];
-    }
+        [&](int r, int q, double v) { T[r][q] = v; });
+    for (int r = t; r < 64; r += 256) dref[r] = r < R ? C[(long long)n * R2 + r + r * R] : 1.0;
+  } else {
+    for_rr_staged(
+        R, rr_sh,
+        [&](int r, int q) {
+          double cv[kMaxOrder];
+          load_c(C, N, R2, r + q * R, cv);
+          return prod_except(cv, n, -1);
+        },
+        [&](int r, int q, double g) {
+          Gam[(long long)n * R2 + r + q * R] = g;
+          T[r][q] = g + (r == q ? mu : 0.0);
+        });
+  }
+  for (int e = t; e < 64 * 64; e += 256) {
+    const int r = e >> 6, c = e & 63;
+    if (r >= R || c >= R) T[r][c] = (r == c) ? 1.0 : 0.0;
+    if (!chol_c) T[64 + r][c] = 0.0;  // the inverse writes its lower blocks only
+  }
+  sync_block();
+  if (t < 64) {
+    if (chol_c)
+      chol_chain<true>(T, nkb, bad, Lk, rinv, dref);
+    else
+      chol_chain<false>(T, nkb, bad, Lk, rinv, nullptr);
+    if (t >= Rp) rinv[t] = 1.0;
+  }
+  sync_block();
+  if (chol_c) {
+    // the blocks above the diagonal still hold C
+    FOR_RR(r, q) Lc[(long long)n * R2 + r + q * R] = (r >= q) ? T[r][q] : 0.0;
     return;
   }
-  const double mu = state ? state->mu : mu_host;
-  for_rr_staged(
-      R, rr_sh,
-      [&](int r, int q) {
-        double cv[kMaxOrder];
-        load_c(C, N, R2, r + q * R, cv);
-        return prod_except(cv, n, -1);
-      },
-      [&](int r, int q, double g) {
-        Gam[(long long)n * R2 + r + q * R] = g;
-        H[r][q] = g + (r == q ? mu : 0.0);
-      });
-  chol_lds(H, R, 0, bad, lk);
-  // Li = L^-1, one column per thread (forward substitution on the identity)
-  if (t < R) lk[t] = 1.0 / H[t][t];
-  sync_block();
-  for (int j = t; j < 64; j += 256) {
-    if (j < R) {
-      Li[j][j] = lk[j];
-      for (int i = j + 1; i < R; ++i) {
-        double acc = 0.0;
-        for (int k = j; k < i; ++k) acc += H[i][k] * Li[k][j];
-        Li[i][j] = -acc * lk[i];
-      }
-      for (int i = 0; i < j; ++i) Li[i][j] = 0.0;
-    }
-  }
-  sync_block();
+  invert_lower64(T, T + 64, rinv, Lk);
   FOR_RR(r, q) {
     const int e = r + q * R;
-    // X = Li^T (upper triangular), Gt = Li^T Li
-    X[(long long)n * R2 + e] = Li[q][r];
+    // X = L^-T (upper triangular), Gt = L^-T L^-1
+    X[(long long)n * R2 + e] = T[64 + q][r];
     const int k0 = r > q ? r : q;
     double acc = 0.0;
-    for (int k = k0; k < R; ++k) acc += Li[k][r] * Li[k][q];
+    for (int k = k0; k < R; ++k) acc += T[64 + k][r] * T[64 + k][q];
     Gt[(long long)n * R2 + e] = acc;
   }
 }
 
 // Rows of mode n, chunk c: G = M - A Gamma (or M itself when it already is the
-// gradient), P = G Gt, partial w = A^T P, partial ||G||^2 and ||M||^2.
-__global__ __launch_bounds__(256) void k_pw(Shape s, const double* A, const double* M, int resid,
-                                            const double* Gam, const double* Gt, double* Gout,
-                                            double* Pout, double* part, int chunks, int stride,
-                                            const int* stop) {
-  if (stopped(stop)) return;
-  __shared__ double As[64][LD];
-  __shared__ double Gs[64][LD];
-  __shared__ double Ps[64][LD];
-  __shared__ double Gm[64][LD];
-  __shared__ double red[16];
-  const int n = blockIdx.x, c = blockIdx.y, R = s.R, R2 = R * R, In = s.I[n], t = threadIdx.x;
+// gradient), P = G Gt, partial w = A^T P, partial ||G||^2 and ||M||^2.  The
+// three products run on the matrix cores with R padded to Rp = 16 ceil(R/16).
+__device__ void pw_block(const Shape& s, int n, int c, const double* A, const double* M, int resid,
+                         const double* Gam, const double* Gt, double* Gout, double* Pout, double* part,
+                         int chunks, int stride, double (*As)[LD], double (*Gs)[LD], double (*Ps)[LD],
+                         double (*Gm)[LD], double* red) {
+  const int R = s.R, R2 = R * R, In = s.I[n], t = threadIdx.x, nt = (R + 15) >> 4, Rp = 16 * nt;
   RR_SHIFT;
   const int r0 = c * 64;
   double* out = part + ((long long)n * chunks + c) * stride;
@@ -267,46 +280,46 @@ __global__ __launch_bounds__(256) void k_pw(Shape s, const double* A, const doub
   double m2 = 0.0;
   stage_rows(As, A + base, In, r0, R);
   stage_rows(Gs, M + base, In, r0, R, &m2);
+  pad_cols(As, R, Rp);
+  pad_cols(Gs, R, Rp);
+  pad_rr(Gm, R, Rp);
   sync_block();
+  double (*Gp)[LD] = Gs;  // gradient rows
+  double (*Pp)[LD] = Ps;  // rows of P
   if (!resid) {
-    // G = M - A Gamma
-    for (int e = t; e < 64 * R; e += 256) {
-      const int ii = e & 63, r = e >> 6;
-      double acc = 0.0;
-      for (int k = 0; k < R; ++k) acc += As[ii][k] * Gm[k][r];
-      Ps[ii][r] = Gs[ii][r] - acc;
-    }
-    sync_block();
-    for (int e = t; e < 64 * R; e += 256) {
-      const int ii = e & 63, r = e >> 6;
-      Gs[ii][r] = Ps[ii][r];
-    }
+    // G = M - A Gamma, into Ps
+    mm16(
+        4, nt, Rp, [&](int i, int k) { return As[i][k]; }, [&](int k, int j) { return Gm[k][j]; },
+        [&](int i, int j, double v) { Ps[i][j] = Gs[i][j] - v; });
     sync_block();
     for_rr_staged(
         R, rr_sh, [&](int r, int q) { return Gt[(long long)n * R2 + r + q * R]; },
         [&](int r, int q, double v) { Gm[r][q] = v; });
     sync_block();
+    Gp = Ps;
+    Pp = Gs;
   }
+  mm16(
+      4, nt, Rp, [&](int i, int k) { return Gp[i][k]; }, [&](int k, int j) { return Gm[k][j]; },
+      [&](int i, int j, double v) { Pp[i][j] = v; });
+  sync_block();
   double g2 = 0.0;
   for (int e = t; e < 64 * R; e += 256) {
     const int ii = e & 63, r = e >> 6;
-    double acc = 0.0;
-    for (int k = 0; k < R; ++k) acc += Gs[ii][k] * Gm[k][r];
-    Ps[ii][r] = acc;
     if (r0 + ii < In) {
       const long long gi = base + r0 + ii + (long long)r * In;
-      Gout[gi] = Gs[ii][r];
-      Pout[gi] = acc;
-      g2 += Gs[ii][r] * Gs[ii][r];
+      const double g = Gp[ii][r];
+      Gout[gi] = g;
+      Pout[gi] = Pp[ii][r];
+      g2 += g * g;
     }
   }
-  sync_block();
-  FOR_RR(a, b) {
-    const int e = a + b * R;
-    double acc = 0.0;
-    for (int i = 0; i < 64; ++i) acc += As[i][a] * Ps[i][b];
-    out[e] = acc;
-  }
+  // partial w = A^T P over the chunk's rows (rows beyond I_n are zero in both)
+  mm16(
+      nt, nt, 64, [&](int a, int k) { return As[k][a]; }, [&](int k, int b) { return Pp[k][b]; },
+      [&](int a, int b, double v) {
+        if (a < R && b < R) out[a + b * R] = v;
+      });
   g2 = block_sum(g2, red);
   m2 = block_sum(m2, red);
   if (t == 0) {
@@ -317,54 +330,107 @@ __global__ __launch_bounds__(256) void k_pw(Shape s, const double* A, const doub
   }
 }
 
-// w_n = sum over row chunks of the partial A_n^T P_n; block 0 also reduces
-// ||G||^2 and ||M||^2 into scal[2], scal[3].
-__global__ __launch_bounds__(256) void k_wred(Shape s, const double* part, int chunks, int stride,
-                                              double* w, double* scal, const int* stop) {
+// T_nm[(a + d R) * R + i] = sum_j Gamma_nm[i, j] L_n[j, a] X_m[j, d] for n != m
+// and one d.
+__device__ void tnm_block(const Shape& s, int pair, int d, const double* C, const double* X,
+                          const double* Lc, double* Tnm, double (*Gs)[LD], double (*Ls)[LD]) {
+  const int R = s.R, R2 = R * R, N = s.N, nt = (R + 15) >> 4, Rp = 16 * nt;
+  RR_SHIFT;
+  const int n = pair / N, m = pair % N;
+  const double* xd = X + (long long)m * R2 + d * R;  // X_m[:, d]
+  // Ls[j][a] = L_n[j, a] X_m[j, d]
+  for_rr_staged(
+      R, rr_sh,
+      [&](int i, int j) {
+        const int e = i + j * R;
+        double cv[kMaxOrder];
+        load_c(C, N, R2, e, cv);
+        return d3{prod_except(cv, n, m), Lc[(long long)n * R2 + e], xd[i]};
+      },
+      [&](int i, int j, d3 v) {
+        Gs[i][j] = v.x;
+        Ls[i][j] = v.y * v.z;
+      });
+  pad_rr(Gs, R, Rp);
+  pad_rr(Ls, R, Rp);
+  sync_block();
+  double* out = Tnm + (long long)pair * R * R2;
+  mm16(
+      nt, nt, Rp, [&](int i, int j) { return Gs[i][j]; }, [&](int j, int a) { return Ls[j][a]; },
+      [&](int i, int a, double v) {
+        if (i < R && a < R) out[((long long)a + (long long)d * R) * R + i] = v;
+      });
+}
+
+// Blocks 0 .. N chunks - 1: the rows of the fast step's gradient (pw_block).
+// With tnm, the N (N - 1) R blocks after them form the T_nm of the NR^2
+// assembly (they need only C, X and L from k_gamma).
+__global__ __launch_bounds__(256) void k_pw(Shape s, const double* A, const double* M, int resid,
+                                            const double* Gam, const double* Gt, double* Gout,
+                                            double* Pout, double* part, int chunks, int stride,
+                                            const double* C, const double* X, const double* Lc,
+                                            double* Tnm, const int* stop) {
   if (stopped(stop)) return;
-  const int n = blockIdx.x, R = s.R, R2 = R * R, N = s.N, t = threadIdx.x;
-  for (int e = t; e < R2; e += 256) {
-    const double* p0 = part + (long long)n * chunks * stride + e;
-    double a0 = 0.0, a1 = 0.0;
-    int c = 0;
-    for (; c + 1 < chunks; c += 2) {
-      a0 += p0[(long long)c * stride];
-      a1 += p0[(long long)(c + 1) * stride];
-    }
-    if (c < chunks) a0 += p0[(long long)c * stride];
-    w[(long long)n * R2 + e] = a0 + a1;
+  __shared__ double As[64][LD];
+  __shared__ double Gs[64][LD];
+  __shared__ double Ps[64][LD];
+  __shared__ double Gm[64][LD];
+  __shared__ double red[16];
+  const int id = blockIdx.x, npw = s.N * chunks;
+  if (id < npw) {
+    pw_block(s, id / chunks, id % chunks, A, M, resid, Gam, Gt, Gout, Pout, part, chunks, stride, As, Gs, Ps,
+             Gm, red);
+    return;
   }
+  // T_nm blocks: pairs n != m in order, then d
+  const int R = s.R, k = id - npw, p = k / R, d = k % R;
+  const int n = p / (s.N - 1), mo = p % (s.N - 1), m = mo < n ? mo : mo + 1;
+  tnm_block(s, n * s.N + m, d, C, X, Lc, Tnm, As, Gs);
+}
+
+// w_m[e] = sum over the row chunks of the partials A_m^T P_m (fixed order, so
+// every block that needs w_m[e] gets the same value).
+__device__ __forceinline__ double w_sum(const double* part, int m, int chunks, int stride, int e) {
+  const double* p0 = part + (long long)m * chunks * stride + e;
+  double a0 = 0.0, a1 = 0.0;
+  int c = 0;
+  for (; c + 1 < chunks; c += 2) {
+    a0 += p0[(long long)c * stride];
+    a1 += p0[(long long)(c + 1) * stride];
+  }
+  if (c < chunks) a0 += p0[(long long)c * stride];
+  return a0 + a1;
+}
+
+// Per mode n: w_n from the row-chunk partials, V = sum_{m != n} Gamma_nm * W_m^T
+// and z_n = vec(L_n^T V X_n) (= (W^T K w)_n); block 0 also reduces ||G||^2 and
+// ||M||^2 into scal[2], scal[3].
+__global__ __launch_bounds__(256) void k_z(Shape s, const double* C, const double* part, int chunks,
+                                           int stride, const double* X, const double* Lc, double* w,
+                                           double* scal, double* z, const int* stop) {
+  if (stopped(stop)) return;
+  __shared__ double V[64][LD];
+  __shared__ double Ls[64][LD];
+  __shared__ double Xs[64][LD];
+  __shared__ double Tm[64][LD];
+  const int n = blockIdx.x, R = s.R, R2 = R * R, N = s.N, t = threadIdx.x, nt = (R + 15) >> 4, Rp = 16 * nt;
+  RR_SHIFT;
   if (n == 0 && t < 2) {
     double acc = 0.0;
     for (int m = 0; m < N; ++m)
       for (int c = 0; c < chunks; ++c) acc += part[((long long)m * chunks + c) * stride + R2 + t];
     scal[2 + t] = acc;
   }
-}
-
-// Per mode n: V = sum_{m != n} Gamma_nm * W_m^T and z_n = vec(L_n^T V X_n) (= (W^T K w)_n).
-__global__ __launch_bounds__(256) void k_z(Shape s, const double* C, const double* w,
-                                           const double* X, const double* Lc, double* z,
-                                           const int* stop) {
-  if (stopped(stop)) return;
-  __shared__ double V[64][LD];
-  __shared__ double Ls[64][LD];
-  __shared__ double Xs[64][LD];
-  __shared__ double Tm[64][LD];
-  const int n = blockIdx.x, R = s.R, R2 = R * R, N = s.N;
-  RR_SHIFT;
+  FOR_RR(a, b) w[(long long)n * R2 + a + b * R] = w_sum(part, n, chunks, stride, a + b * R);
   for_rr_staged(
       R, rr_sh,
       [&](int a, int b) {
         const int e = a + b * R;
-        double cv[kMaxOrder], wv[kMaxOrder];
+        double cv[kMaxOrder];
         load_c(C, N, R2, e, cv);
-#pragma unroll
-        for (int m = 0; m < kMaxOrder; ++m) wv[m] = (m < N && m != n) ? w[(long long)m * R2 + b + a * R] : 0.0;
         double v = 0.0;
-#pragma unroll
-        for (int m = 0; m < kMaxOrder; ++m)
-          if (m < N && m != n) v += prod_except(cv, n, m) * wv[m];
+        for (int m = 0; m < N; ++m)
+          if (m != n) v += prod_except(cv, n, m) * w_sum(part, m, chunks, stride, b + a * R);
         return d3{v, Lc[(long long)n * R2 + e], X[(long long)n * R2 + e]};
       },
       [&](int a, int b, d3 v) {
@@ -372,53 +438,20 @@ __global__ __launch_bounds__(256) void k_z(Shape s, const double* C, const doubl
         Ls[a][b] = v.y;
         Xs[a][b] = v.z;
       });
+  pad_rr(V, R, Rp);
+  pad_rr(Ls, R, Rp);
+  pad_rr(Xs, R, Rp);
   sync_block();
-  FOR_RR(a, b) {
-    double acc = 0.0;
-    for (int k = 0; k < R; ++k) acc += Ls[k][a] * V[k][b];
-    Tm[a][b] = acc;
-  }
+  // Tm = L_n^T V
+  mm16(
+      nt, nt, Rp, [&](int a, int k) { return Ls[k][a]; }, [&](int k, int b) { return V[k][b]; },
+      [&](int a, int b, double v) { Tm[a][b] = v; });
   sync_block();
-  FOR_RR(a, b) {
-    double acc = 0.0;
-    for (int k = 0; k < R; ++k) acc += Tm[a][k] * Xs[k][b];
-    z[(long long)n * R2 + a + b * R] = acc;
-  }
-}
-
-// T_nm[(a + d R) * R + i] = sum_j Gamma_nm[i, j] L_n[j, a] X_m[j, d] for n != m.
-// Grid: (N * N pairs, R values of d).
-__global__ __launch_bounds__(256) void k_tnm(Shape s, const double* C, const double* X,
-                                             const double* Lc, double* Tnm, const int* stop) {
-  if (stopped(stop)) return;
-  __shared__ double Gs[64][LD];
-  __shared__ double Ls[64][LD];
-  __shared__ double xd[64];
-  const int pair = blockIdx.x, d = blockIdx.y, R = s.R, R2 = R * R, N = s.N, t = threadIdx.x;
-  RR_SHIFT;
-  const int n = pair / N, m = pair % N;
-  if (n == m) return;
-  for_rr_staged(
-      R, rr_sh,
-      [&](int i, int j) {
-        const int e = i + j * R;
-        double cv[kMaxOrder];
-        load_c(C, N, R2, e, cv);
-        return d2{prod_except(cv, n, m), Lc[(long long)n * R2 + e]};
-      },
-      [&](int i, int j, d2 v) {
-        Gs[i][j] = v.x;
-        Ls[i][j] = v.y;
+  mm16(
+      nt, nt, Rp, [&](int a, int k) { return Tm[a][k]; }, [&](int k, int b) { return Xs[k][b]; },
+      [&](int a, int b, double v) {
+        if (a < R && b < R) z[(long long)n * R2 + a + b * R] = v;
       });
-  for (int j = t; j < R; j += 256) xd[j] = X[(long long)m * R2 + j + d * R];
-  sync_block();
-  double* out = Tnm + (long long)pair * R * R2;
-  FOR_RR(i, a) {
-    const int e = i + a * R;
-    double acc = 0.0;
-    for (int j = 0; j < R; ++j) acc += Gs[i][j] * Ls[j][a] * xd[j];
-    out[((long long)a + (long long)d * R) * R + i] = acc;
-  }
 }
 
 // u_n = w_n - vec(L_n Y_n X_n^T), Y_n = unvec(y_n).
@@ -430,7 +463,7 @@ __global__ __launch_bounds__(256) void k_u(Shape s, const double* w, const doubl
   __shared__ double Tm[64][LD];
   __shared__ double Ls[64][LD];
   __shared__ double Xs[64][LD];
-  const int n = blockIdx.x, R = s.R, R2 = R * R;
+  const int n = blockIdx.x, R = s.R, R2 = R * R, nt = (R + 15) >> 4, Rp = 16 * nt;
   RR_SHIFT;
   for_rr_staged(
       R, rr_sh,
@@ -443,19 +476,22 @@ __global__ __launch_bounds__(256) void k_u(Shape s, const double* w, const doubl
         Ls[r][q] = v.y;
         Xs[r][q] = v.z;
       });
+  pad_rr(Ys, R, Rp);
+  pad_rr(Ls, R, Rp);
+  pad_rr(Xs, R, Rp);
   sync_block();
-  FOR_RR(a, b) {
-    double acc = 0.0;
-    for (int k = 0; k < R; ++k) acc += Ls[a][k] * Ys[k][b];
-    Tm[a][b] = acc;
-  }
+  mm16(
+      nt, nt, Rp, [&](int a, int k) { return Ls[a][k]; }, [&](int k, int b) { return Ys[k][b]; },
+      [&](int a, int b, double v) { Tm[a][b] = v; });
   sync_block();
-  FOR_RR(a, b) {
-    const int e = a + b * R;
-    double acc = 0.0;
-    for (int k = 0; k < R; ++k) acc += Tm[a][k] * Xs[b][k];
-    u[(long long)n * R2 + e] = w[(long long)n * R2 + e] - acc;
-  }
+  mm16(
+      nt, nt, Rp, [&](int a, int k) { return Tm[a][k]; }, [&](int k, int b) { return Xs[b][k]; },
+      [&](int a, int b, double v) {
+        if (a < R && b < R) {
+          const long long e = (long long)n * R2 + a + b * R;
+          u[e] = w[e] - v;
+        }
+      });
 }
 
 // f_n = vec(sum_{m != n} Gamma_nm * U_m^T) (= (K u)_n), Q_n = F_n Gt_n.
@@ -465,7 +501,7 @@ __global__ __launch_bounds__(256) void k_fq(Shape s, const double* C, const doub
   if (stopped(stop)) return;
   __shared__ double Fs[64][LD];
   __shared__ double Gs[64][LD];
-  const int n = blockIdx.x, R = s.R, R2 = R * R, N = s.N;
+  const int n = blockIdx.x, R = s.R, R2 = R * R, N = s.N, nt = (R + 15) >> 4, Rp = 16 * nt;
   RR_SHIFT;
   for_rr_staged(
       R, rr_sh,
@@ -486,13 +522,14 @@ __global__ __launch_bounds__(256) void k_fq(Shape s, const double* C, const doub
         f[(long long)n * R2 + a + b * R] = v.y;
         Fs[a][b] = v.y;
       });
+  pad_rr(Fs, R, Rp);
+  pad_rr(Gs, R, Rp);
   sync_block();
-  FOR_RR(a, b) {
-    const int e = a + b * R;
-    double acc = 0.0;
-    for (int k = 0; k < R; ++k) acc += Fs[a][k] * Gs[k][b];
-    Q[(long long)n * R2 + e] = acc;
-  }
+  mm16(
+      nt, nt, Rp, [&](int a, int k) { return Fs[a][k]; }, [&](int k, int b) { return Gs[k][b]; },
+      [&](int a, int b, double v) {
+        if (a < R && b < R) Q[(long long)n * R2 + a + b * R] = v;
+      });
 }
 
 // A_c = A + P - A Q_n on the rows of (mode n, chunk c).  Partials: Gram of A_c,
@@ -507,6 +544,7 @@ __global__ __launch_bounds__(256) void k_update(Shape s, const double* A, const 
   __shared__ double Cs[64][LD];
   __shared__ double red[16];
   const int n = blockIdx.x, c = blockIdx.y, R = s.R, R2 = R * R, In = s.I[n], t = threadIdx.x;
+  const int nt = (R + 15) >> 4, Rp = 16 * nt;
   RR_SHIFT;
   const int r0 = c * 64;
   double* out = part + ((long long)n * chunks + c) * stride;
@@ -520,6 +558,13 @@ __global__ __launch_bounds__(256) void k_update(Shape s, const double* A, const 
       R, rr_sh, [&](int r, int q) { return Q[(long long)n * R2 + r + q * R]; },
       [&](int r, int q, double v) { Qs[r][q] = v; });
   stage_rows(As, A + base, In, r0, R);
+  pad_cols(As, R, Rp);
+  pad_rr(Qs, R, Rp);
+  sync_block();
+  // Cs = A Q_n (padding columns come out zero)
+  mm16(
+      4, nt, Rp, [&](int i, int k) { return As[i][k]; }, [&](int k, int j) { return Qs[k][j]; },
+      [&](int i, int j, double v) { Cs[i][j] = v; });
   sync_block();
   double den = 0.0, da2 = 0.0;
   for (int e = t; e < 64 * R; e += 256) {
@@ -527,9 +572,7 @@ __global__ __launch_bounds__(256) void k_update(Shape s, const double* A, const 
     double v = 0.0;
     if (r0 + ii < In) {
       const long long gi = base + r0 + ii + (long long)r * In;
-      double acc = 0.0;
-      for (int k = 0; k < R; ++k) acc += As[ii][k] * Qs[k][r];
-      const double da = P[gi] - acc;
+      const double da = P[gi] - Cs[ii][r];
       v = As[ii][r] + da;
       Ac[gi] = v;
       if (da_out) da_out[gi] = da;
@@ -539,12 +582,11 @@ __global__ __launch_bounds__(256) void k_update(Shape s, const double* A, const 
     Cs[ii][r] = v;
   }
   sync_block();
-  FOR_RR(r, q) {
-    const int e = r + q * R;
-    double acc = 0.0;
-    for (int i = 0; i < 64; ++i) acc += Cs[i][r] * Cs[i][q];
-    out[e] = acc;
-  }
+  mm16(
+      nt, nt, 64, [&](int a, int k) { return Cs[k][a]; }, [&](int k, int b) { return Cs[k][b]; },
+      [&](int a, int b, double v) {
+        if (a < R && b < R) out[a + b * R] = v;
+      });
   den = block_sum(den, red);
   da2 = block_sum(da2, red);
   if (t == 0) {
@@ -594,22 +636,17 @@ hipError_t launch_gamma(const Shape& s, const double* C, double mu_host, const F
 }
 
 hipError_t launch_pw(const Shape& s, const double* A, const double* M, bool resid,
-                     const SmallBuffers& b, const int* stop, hipStream_t st) {
+                     const SmallBuffers& b, bool with_tnm, const int* stop, hipStream_t st) {
   const int ch = row_chunks(s), stride = part_stride(s);
-  k_pw<<<dim3(s.N, ch), 256, 0, st>>>(s, A, M, resid ? 1 : 0, b.Gam, b.Gt, b.G, b.P, b.wpart, ch,
-                                       stride, stop);
+  const int nblk = s.N * ch + (with_tnm ? s.N * (s.N - 1) * s.R : 0);
+  k_pw<<<nblk, 256, 0, st>>>(s, A, M, resid ? 1 : 0, b.Gam, b.Gt, b.G, b.P, b.wpart, ch, stride, b.C, b.X, b.Lc,
+                             b.Tnm, stop);
   return hipGetLastError();
 }
 
 hipError_t launch_wz(const Shape& s, const SmallBuffers& b, const int* stop, hipStream_t st) {
   const int ch = row_chunks(s), stride = part_stride(s);
-  k_wred<<<s.N, 256, 0, st>>>(s, b.wpart, ch, stride, b.w, b.scal, stop);
-  k_z<<<s.N, 256, 0, st>>>(s, b.C, b.w, b.X, b.Lc, b.z, stop);
-  return hipGetLastError();
-}
-
-hipError_t launch_tnm(const Shape& s, const SmallBuffers& b, const int* stop, hipStream_t st) {
-  k_tnm<<<dim3(s.N * s.N, s.R), 256, 0, st>>>(s, b.C, b.X, b.Lc, b.Tnm, stop);
+  k_z<<<s.N, 256, 0, st>>>(s, b.C, b.wpart, ch, stride, b.X, b.Lc, b.w, b.scal, b.z, stop);
   return hipGetLastError();
 }
 
