@@ -198,6 +198,7 @@ void carve(Arena& ar, Work& w, bool with_system) {
   b.wpart = ar.take<double>((size_t)s.N * ch * stride);
   b.rowpart = ar.take<double>((size_t)s.N * ch * stride);
   b.scal = ar.take<double>(8);
+  b.ipart = ar.take<double>(((size_t)s.maxI * s.R + 63) / 64);
   b.w = ar.take<double>(NR2);
   b.z = ar.take<double>(NR2);
   b.y = ar.take<double>(NR2);
@@ -325,8 +326,10 @@ hipError_t enqueue_step_c(Work& w, bool resid, double mu_host, FitState* state, 
   return launch_small_post_c(s, w.A, w.Ac, w.sb, mu_host, state, stop, st, w.da_out);
 }
 
+// fold_reduce: leave the sums of the update's Gram partials to the tensor pass
+// that follows (PassFold); real tensors only.
 hipError_t enqueue_step(Work& w, bool resid, double mu_host, FitState* state, int* singular,
-                        const int* stop, hipStream_t st, hipEvent_t* ev = nullptr) {
+                        const int* stop, hipStream_t st, hipEvent_t* ev = nullptr, bool fold_reduce = false) {
   if (w.cs == 2) return enqueue_step_c(w, resid, mu_host, state, singular, stop, st, ev);
   const Shape& s = w.s;
   hipError_t e;
@@ -349,6 +352,7 @@ hipError_t enqueue_step(Work& w, bool resid, double mu_host, FitState* state, in
   if ((e = launch_u(s, w.sb, stop, st)) != hipSuccess) return e;
   if ((e = launch_fq(s, w.sb, stop, st)) != hipSuccess) return e;
   if ((e = launch_update(s, w.A, w.Ac, w.sb, mu_host, state, stop, st, w.da_out)) != hipSuccess) return e;
+  if (fold_reduce) return hipSuccess;
   return launch_update_reduce(s, w.sb, w.sb.scal, stop, st);
 }
 
@@ -363,10 +367,10 @@ PassSel pass_tensor(const Work& w, const dgn_tensor* Y, const dgn_opts& o, bool 
 }
 
 hipError_t run_pass(const Work& w, const PassSel& ps, const double* A, bool resid, double* M, double* e2,
-                    const int* stop, hipStream_t st) {
+                    const int* stop, hipStream_t st, const PassFold* fold = nullptr) {
   if (w.cs == 2)
     return launch_tensor_pass_c(w.s, ps.yt == YType::C128, ps.data, A, resid, w.pp, w.pb, M, e2, stop, st);
-  return launch_tensor_pass(w.s, ps.yt, ps.data, A, resid, w.pp, w.pb, M, e2, stop, st);
+  return launch_tensor_pass(w.s, ps.yt, ps.data, A, resid, w.pp, w.pb, M, e2, stop, st, fold);
 }
 
 // sum |y|^2; a complex tensor is summed as 2J real values.
@@ -829,11 +833,25 @@ dgn_status cp_fit(dgn_ctx* ctx, const dgn_tensor* Y, int32_t R, void* const* A, 
   int enq = 0;
   for (int t = 0; t < max_iters; ++t) {
     hipEvent_t* ev = o.timing ? &ctx->events[(size_t)EV * t] : nullptr;
-    HIPCHK(enqueue_step(w, resid, 0.0, ds, &ds->singular, stop, st, ev), "step");
+    // real tensors: the Gram sums of the update and the pieces of <A_1, M_1>
+    // ride in the pass's reduction launch
+    const bool fold = w.cs != 2;
+    PassFold pf;
+    if (fold) {
+      pf.ipart = resid ? nullptr : w.sb.ipart;
+      pf.rowpart = w.sb.rowpart;
+      pf.chunks = row_chunks(w.s);
+      pf.stride = w.s.R * w.s.R + 4;
+      pf.gout = w.sb.Cc;
+      pf.gscal = w.sb.scal;
+    }
+    HIPCHK(enqueue_step(w, resid, 0.0, ds, &ds->singular, stop, st, ev, fold), "step");
     HIPCHK(mark(ev, 4, st), "event");
-    HIPCHK(run_pass(w, ps, w.Ac, resid, w.Mc, e2c, stop, st), "pass");
+    HIPCHK(run_pass(w, ps, w.Ac, resid, w.Mc, e2c, stop, st, fold ? &pf : nullptr), "pass");
     HIPCHK(mark(ev, 5, st), "event");
-    HIPCHK(launch_control(w.s, w.Ac, w.Mc, w.sb.Cc, resid, e2c, w.sb.scal, ds, t, st, w.cs), "control");
+    HIPCHK(launch_control(w.s, w.Ac, w.Mc, w.sb.Cc, resid, e2c, w.sb.scal, ds, t, st, w.cs, pf.ipart,
+                          (int)(((long long)w.s.I[0] * w.s.R + 63) / 64)),
+           "control");
     HIPCHK(launch_commit(w.s, w.A, w.Ac, w.M, w.Mc, w.sb.C, w.sb.Cc, ds, t, st, w.cs), "commit");
     HIPCHK(mark(ev, 6, st), "event");
     enq = t + 1;

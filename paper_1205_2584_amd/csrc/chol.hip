@@ -151,13 +151,14 @@ __device__ __forceinline__ void panel_trail_block(int b, int kb, int& bi, int& b
   }
 }
 
-// Fill the lower tiles of St and all of B with identity / zeros (the
-// off-diagonal blocks are overwritten by k_subblock afterwards).
-__global__ __launch_bounds__(256) void k_fill(SysPlan p, double* St, double* B, int R2p,
-                                              const int* stop) {
-  if (stopped(stop)) return;
+// id < ntri: lower tile id (ti, tj) of St (identity / zeros), or a tile of the
+// right-hand-side row (zeros); id >= ntri: one of the nbz blocks that zero B.
+// skip_sub: leave out the positions k_subblock writes (the off-diagonal mode
+// blocks of St and the first R^2 columns of B's first nt rows), so that both
+// can run in one launch.
+__device__ void fill_body(const SysPlan& p, double* St, double* B, int R2p, long long id, long long nbz,
+                          int skip_sub) {
   const long long ntri = (long long)p.Tt * (p.Tt + 1) / 2 + p.Tt;  // lower tiles + RHS row tiles
-  const long long id = blockIdx.x;
   if (id < ntri) {
     int ti, tj;
     if (id < (long long)p.Tt * (p.Tt + 1) / 2) {
@@ -172,30 +173,51 @@ __global__ __launch_bounds__(256) void k_fill(SysPlan p, double* St, double* B, 
     for (int e = threadIdx.x; e < 64 * 64; e += 256) {
       const int ii = e & 63, jj = e >> 6;
       const int r = ti * 64 + ii, c = tj * 64 + jj;
+      if (skip_sub && ti < p.Tt && r < p.nt && c < p.nt && r / p.R2 > c / p.R2) continue;
       double v = 0.0;
       if (ti < p.Tt && r == c) v = 1.0;
       St[r + (long long)c * p.lds] = v;
     }
   } else {
     const long long nb = (long long)p.ntp * R2p;
-    for (long long e = (id - ntri) * 256 + threadIdx.x; e < nb; e += (long long)(gridDim.x - ntri) * 256)
+    for (long long e = (id - ntri) * 256 + threadIdx.x; e < nb; e += nbz * 256) {
+      if (skip_sub && e % p.ntp < p.nt && e / p.ntp < p.R2) continue;
       B[e] = 0.0;
+    }
   }
+}
+
+// Fill the lower tiles of St and all of B with identity / zeros (the
+// off-diagonal blocks are overwritten by the sub-block kernel afterwards).
+__global__ __launch_bounds__(256) void k_fill(SysPlan p, double* St, double* B, int R2p,
+                                              const int* stop) {
+  if (stopped(stop)) return;
+  const long long ntri = (long long)p.Tt * (p.Tt + 1) / 2 + p.Tt;
+  fill_body(p, St, B, R2p, blockIdx.x, (long long)gridDim.x - ntri, 0);
 }
 
 // R x R sub-block (b, d) of S_nm for n > m: rows n R^2 + a + b R, columns m R^2 + c + d R.
 // RM: the rank bound the LDS tiles are sized for (32 or 64), so that ranks up to
 // 32 keep several blocks per CU.
+// One launch: blocks [0, npairs R^2) form the sub-blocks ((pair, b) fastest,
+// then d); the blocks after them run fill_body with the positions written here
+// left out (nbz of them zero B).
 template <int RM>
 __global__ __launch_bounds__(256) void k_subblock(Shape s, SysPlan p, const double* Tnm,
                                                   const double* X, const double* Lc, double* St,
-                                                  double* B, const int* stop) {
+                                                  double* B, int R2p, long long nbz, const int* stop) {
   if (stopped(stop)) return;
   __shared__ double Td[RM][RM + 1];  // Td[i][a] = T_nm[i, a + dR]
   __shared__ double Lm[RM][RM + 1];
   const int N = s.N, R = s.R, R2 = R * R;
+  const long long nx = (long long)(N * (N - 1) / 2) * R, nsub = nx * R;
+  if ((long long)blockIdx.x >= nsub) {
+    fill_body(p, St, B, R2p, (long long)blockIdx.x - nsub, nbz, 1);
+    return;
+  }
+  const int bx = (int)(blockIdx.x % nx), by = (int)(blockIdx.x / nx);
   // decode the strictly lower pair (n, m), n > m
-  int pr = blockIdx.x / R, b = blockIdx.x % R, d = blockIdx.y;
+  int pr = bx / R, b = bx % R, d = by;
   int n = 1, m = 0;
   while (pr >= n) { pr -= n; ++n; }
   m = pr;
@@ -934,13 +956,13 @@ hipError_t launch_sys_assemble(const Shape& s, const SysPlan& p, const SmallBuff
   const int R2p = r2pad(p.R2);
   const long long ntri = (long long)p.Tt * (p.Tt + 1) / 2 + p.Tt;
   const long long nbblocks = ((long long)p.ntp * R2p + 255) / 256;
-  long long extra = nbblocks < 1024 ? nbblocks : 1024;
-  k_fill<<<(unsigned)(ntri + extra), 256, 0, st>>>(p, y.St, y.B, R2p, stop);
-  const int npairs = s.N * (s.N - 1) / 2;
+  const long long extra = nbblocks < 1024 ? nbblocks : 1024;
+  const long long nsub = (long long)(s.N * (s.N - 1) / 2) * s.R * s.R;
+  const unsigned nblk = (unsigned)(nsub + ntri + extra);
   if (s.R <= 32)
-    k_subblock<32><<<dim3(npairs * s.R, s.R), 256, 0, st>>>(s, p, b.Tnm, b.X, b.Lc, y.St, y.B, stop);
+    k_subblock<32><<<nblk, 256, 0, st>>>(s, p, b.Tnm, b.X, b.Lc, y.St, y.B, R2p, extra, stop);
   else
-    k_subblock<64><<<dim3(npairs * s.R, s.R), 256, 0, st>>>(s, p, b.Tnm, b.X, b.Lc, y.St, y.B, stop);
+    k_subblock<64><<<nblk, 256, 0, st>>>(s, p, b.Tnm, b.X, b.Lc, y.St, y.B, R2p, extra, stop);
   k_syrk<<<(unsigned)(p.ntp / 64 + (long long)p.Tt * (p.Tt + 1) / 2), 256, 0, st>>>(p, y.B, b.z, R2p, y.St, stop);
   return hipGetLastError();
 }

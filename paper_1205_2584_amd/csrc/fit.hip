@@ -17,19 +17,28 @@ namespace dgn {
 
 namespace {
 
-// err2 of factors A with pass output M (mode 1 block) and Grams C.
+// err2 of factors A with pass output M (mode 1 block) and Grams C.  With
+// ipart, <A_1, M_1> is the sum of its nip pieces.
 __device__ double err2_of(const Shape& s, const double* A, const double* M, const double* C,
-                          int resid, const double* e2, double ynorm2_pass, double* red) {
+                          int resid, const double* e2, double ynorm2_pass, double* red,
+                          const double* ipart = nullptr, int nip = 0) {
   if (resid) return e2[0];
   const int R = s.R, R2 = R * R, I0 = s.I[0];
   // 16 independent loads per thread in flight: the operands are a few hundred KB
-  const int n = I0 * R, bd = blockDim.x;
+  const int n = ipart ? nip : I0 * R, bd = blockDim.x;
   double part[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   int e = threadIdx.x;
-  for (; e + 7 * bd < n; e += 8 * bd)
+  if (ipart) {
+    for (; e + 7 * bd < n; e += 8 * bd)
 #pragma unroll
-    for (int q = 0; q < 8; ++q) part[q] += A[e + q * bd] * M[e + q * bd];
-  for (; e < n; e += bd) part[0] += A[e] * M[e];
+      for (int q = 0; q < 8; ++q) part[q] += ipart[e + q * bd];
+    for (; e < n; e += bd) part[0] += ipart[e];
+  } else {
+    for (; e + 7 * bd < n; e += 8 * bd)
+#pragma unroll
+      for (int q = 0; q < 8; ++q) part[q] += A[e + q * bd] * M[e + q * bd];
+    for (; e < n; e += bd) part[0] += A[e] * M[e];
+  }
   double inner = ((part[0] + part[1]) + (part[2] + part[3])) + ((part[4] + part[5]) + (part[6] + part[7]));
   inner = block_sum(inner, red);
   double yh = 0.0;
@@ -106,11 +115,12 @@ __global__ __launch_bounds__(256) void k_inner(Shape s, const double* A, const d
 
 __global__ __launch_bounds__(256) void k_control(Shape s, const double* Ac, const double* Mc,
                                                  const double* Cc, int resid, const double* e2,
-                                                 const double* scal, FitState* st, int trial, int cs) {
+                                                 const double* scal, FitState* st, int trial, int cs,
+                                                 const double* ipart, int nip) {
   __shared__ double red[16];
   __shared__ int accept_s;
   if (st->stop) return;
-  const double err2c = err2_of(s, Ac, Mc, Cc, resid, e2, st->ynorm2_pass, red);
+  const double err2c = err2_of(s, Ac, Mc, Cc, resid, e2, st->ynorm2_pass, red, ipart, nip);
   const int N = s.N, R = s.R, R2 = R * R;
   if (threadIdx.x == 0) {
     int accept = 0;
@@ -258,8 +268,8 @@ hipError_t launch_inner(const Shape& s, const double* A, const double* M, double
 
 hipError_t launch_control(const Shape& s, const double* Ac, const double* Mc, const double* Cc,
                           bool resid, const double* e2, const double* scal, FitState* state,
-                          int trial, hipStream_t st, int cs) {
-  k_control<<<1, 256, 0, st>>>(s, Ac, Mc, Cc, resid ? 1 : 0, e2, scal, state, trial, cs);
+                          int trial, hipStream_t st, int cs, const double* ipart, int nip) {
+  k_control<<<1, 256, 0, st>>>(s, Ac, Mc, Cc, resid ? 1 : 0, e2, scal, state, trial, cs, ipart, nip);
   return hipGetLastError();
 }
 

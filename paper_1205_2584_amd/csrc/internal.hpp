@@ -35,9 +35,21 @@ struct PassBuffers {
 // M (stacked FP64, I_n x R per mode) = MTTKRP of Y (resid = false) or of
 // E = Y - Y_hat (resid = true) at the stacked FP64 factors A.  With resid,
 // e2out[0] receives sum(E^2).  Returns hipSuccess or the launch error.
+// Work folded into the pass's final reduction launch (fits only):
+// ipart receives ceil(I_1 R / 64) partial sums of <A_1, M_1> (the error of
+// the candidate is ||Y||^2 - 2 <A_1, M_1> + ||Y_hat||^2); with rowpart, the
+// row-chunk Gram partials of the update are summed into gout (N R^2) and its
+// two per-row scalars into gscal (what launch_update_reduce does).
+struct PassFold {
+  double* ipart = nullptr;
+  const double* rowpart = nullptr;
+  int chunks = 0, stride = 0;
+  double* gout = nullptr;
+  double* gscal = nullptr;
+};
 hipError_t launch_tensor_pass(const Shape& s, YType yt, const void* Y, const double* A, bool resid,
                               const PassPlan& p, const PassBuffers& b, double* M, double* e2out,
-                              const int* stop, hipStream_t st);
+                              const int* stop, hipStream_t st, const PassFold* fold = nullptr);
 
 // sum(y^2) over n elements of Y in FP64.
 hipError_t launch_norm2(YType yt, const void* Y, long long n, double* part, int nparts, double* out,
@@ -53,6 +65,7 @@ struct SmallBuffers {
   double *Tnm;           // N x N x R x R^2 (T_nm[i, a + d R])
   double *rowpart;       // N x chunks x (R^2 + 4) partial Grams and scalars
   double *scal;          // per-trial scalars: denom, ||da||^2, ||g||^2, ||M||^2
+  double *ipart;         // pieces of <A_1, M_1> from the pass's reduction, ceil(I_max R / 64)
 };
 
 int row_chunks(const Shape& s);  // 64-row chunks per mode
@@ -163,9 +176,12 @@ hipError_t launch_fit_init(const Shape& s, const double* A, const double* M, con
 hipError_t launch_refresh(const Shape& s, const double* e2, FitState* state, hipStream_t st);
 hipError_t launch_err2(const Shape& s, const double* A, const double* M, const double* C, bool resid,
                        const double* e2, const double* ynorm2_pass, double* out, hipStream_t st);
+// ipart (nip values): <A_1, M_1> in pieces from the pass (PassFold); null:
+// the inner product is formed here from Ac and Mc.
 hipError_t launch_control(const Shape& s, const double* Ac, const double* Mc, const double* Cc,
                           bool resid, const double* e2, const double* scal, FitState* state,
-                          int trial, hipStream_t st, int cs = 1);
+                          int trial, hipStream_t st, int cs = 1, const double* ipart = nullptr,
+                          int nip = 0);
 hipError_t launch_commit(const Shape& s, double* A, const double* Ac, double* M, const double* Mc,
                          double* C, const double* Cc, const FitState* state, int trial,
                          hipStream_t st, int cs = 1);

@@ -388,24 +388,27 @@ __global__ __launch_bounds__(256) void k_pw(Shape s, const double* A, const doub
   tnm_block(s, n * s.N + m, d, C, X, Lc, Tnm, As, Gs);
 }
 
-// w_m[e] = sum over the row chunks of the partials A_m^T P_m (fixed order, so
-// every block that needs w_m[e] gets the same value).
+// w_m[e] = sum over the row chunks of the partials A_m^T P_m, eight loads in
+// flight at a time (fixed order, so every block that needs w_m[e] gets the
+// same value).
 __device__ __forceinline__ double w_sum(const double* part, int m, int chunks, int stride, int e) {
   const double* p0 = part + (long long)m * chunks * stride + e;
-  double a0 = 0.0, a1 = 0.0;
+  double acc = 0.0;
   int c = 0;
-  for (; c + 1 < chunks; c += 2) {
-    a0 += p0[(long long)c * stride];
-    a1 += p0[(long long)(c + 1) * stride];
+  for (; c + 8 <= chunks; c += 8) {
+    double v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = p0[(long long)(c + k) * stride];
+    acc += ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
   }
-  if (c < chunks) a0 += p0[(long long)c * stride];
-  return a0 + a1;
+  for (; c < chunks; ++c) acc += p0[(long long)c * stride];
+  return acc;
 }
 
 // Per mode n: w_n from the row-chunk partials, V = sum_{m != n} Gamma_nm * W_m^T
 // and z_n = vec(L_n^T V X_n) (= (W^T K w)_n); block 0 also reduces ||G||^2 and
 // ||M||^2 into scal[2], scal[3].
-__global__ __launch_bounds__(256) void k_z(Shape s, const double* C, const double* part, int chunks,
+__global__ __launch_bounds__(1024) void k_z(Shape s, const double* C, const double* part, int chunks,
                                            int stride, const double* X, const double* Lc, double* w,
                                            double* scal, double* z, const int* stop) {
   if (stopped(stop)) return;
@@ -429,8 +432,9 @@ __global__ __launch_bounds__(256) void k_z(Shape s, const double* C, const doubl
         double cv[kMaxOrder];
         load_c(C, N, R2, e, cv);
         double v = 0.0;
-        for (int m = 0; m < N; ++m)
-          if (m != n) v += prod_except(cv, n, m) * w_sum(part, m, chunks, stride, b + a * R);
+#pragma unroll
+        for (int m = 0; m < kMaxOrder; ++m)
+          if (m < N && m != n) v += prod_except(cv, n, m) * w_sum(part, m, chunks, stride, b + a * R);
         return d3{v, Lc[(long long)n * R2 + e], X[(long long)n * R2 + e]};
       },
       [&](int a, int b, d3 v) {
@@ -646,7 +650,7 @@ hipError_t launch_pw(const Shape& s, const double* A, const double* M, bool resi
 
 hipError_t launch_wz(const Shape& s, const SmallBuffers& b, const int* stop, hipStream_t st) {
   const int ch = row_chunks(s), stride = part_stride(s);
-  k_z<<<s.N, 256, 0, st>>>(s, b.C, b.wpart, ch, stride, b.X, b.Lc, b.w, b.scal, b.z, stop);
+  k_z<<<s.N, 1024, 0, st>>>(s, b.C, b.wpart, ch, stride, b.X, b.Lc, b.w, b.scal, b.z, stop);
   return hipGetLastError();
 }
 

@@ -609,13 +609,61 @@ __global__ __launch_bounds__(256) void k_pass_bf16(PassArgs a, const int* stop) 
 
 // out[x] = sum_s part[s * len + x], accumulated in FP64.  A block covers 64
 // consecutive x; its 16 waves split the slots.
+struct SlotSeg {
+  const void* part;  // nslots partial arrays of len values each
+  int nslots;
+  long long len;
+  double* out;
+};
+
+// The slot sums of one pass in one launch: blocks [0, nb[0]) sum mode 1's
+// partials, the next nb[1] mode 2's, the next nb[2] the t vectors, 64 outputs
+// per block.  Optional folds: ipart[b] = sum of A_1[x] M_1[x] over the 64
+// outputs of mode-1 block b (the <A_1, M_1> of the error formula in pieces);
+// and N + 1 blocks after the slots that sum the row-chunk Gram partials of the
+// candidate factors into gout (N R^2) and the two per-row scalars into gscal.
+struct ReduceArgs {
+  SlotSeg seg[3];
+  int nb[3];
+  const double* A1;
+  double* ipart;
+  const double* rowpart;
+  int N, chunks, stride, R2;
+  double* gout;
+  double* gscal;
+};
+
 template <typename TC>
-__global__ __launch_bounds__(1024) void k_reduce_slots(const TC* part, int nslots, long long len,
-                                                       double* out, const int* stop) {
+__global__ __launch_bounds__(1024) void k_reduce_slots(ReduceArgs ra, const int* stop) {
   if (stopped(stop)) return;
   __shared__ double red[16][65];
   const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
-  const long long x = blockIdx.x * 64LL + lane;
+  int b = blockIdx.x, sg = 0;
+  while (sg < 3 && b >= ra.nb[sg]) b -= ra.nb[sg++];
+  if (sg == 3) {
+    // Gram partials: block b < N sums mode b, block N the two scalars
+    const int t = threadIdx.x;
+    if (b == ra.N) {
+      if (t < 2) {
+        double acc = 0.0;
+        for (int m = 0; m < ra.N; ++m)
+          for (int c = 0; c < ra.chunks; ++c) acc += ra.rowpart[((long long)m * ra.chunks + c) * ra.stride + ra.R2 + t];
+        ra.gscal[t] = acc;
+      }
+      return;
+    }
+    for (int x = t; x < ra.R2; x += blockDim.x) {
+      double acc = 0.0;
+      for (int c = 0; c < ra.chunks; ++c) acc += ra.rowpart[((long long)b * ra.chunks + c) * ra.stride + x];
+      ra.gout[(long long)b * ra.R2 + x] = acc;
+    }
+    return;
+  }
+  const SlotSeg sd = ra.seg[sg];
+  const TC* part = static_cast<const TC*>(sd.part);
+  const int nslots = sd.nslots;
+  const long long len = sd.len;
+  const long long x = b * 64LL + lane;
   double s = 0.0;
   if (x < len) {
     int k = g;
@@ -630,11 +678,15 @@ __global__ __launch_bounds__(1024) void k_reduce_slots(const TC* part, int nslot
   }
   red[g][lane] = s;
   sync_block();
-  if (g == 0 && x < len) {
+  if (g == 0) {
     double v = 0.0;
 #pragma unroll
     for (int i = 0; i < 16; ++i) v += red[i][lane];
-    out[x] = v;
+    if (x < len) sd.out[x] = v;
+    if (sg == 0 && ra.ipart) {
+      const double p = wave_sum(x < len ? ra.A1[x] * v : 0.0);
+      if (lane == 0) ra.ipart[b] = p;
+    }
   }
 }
 
@@ -733,7 +785,7 @@ PassPlan plan_pass(const Shape& s, YType yt) {
 
 hipError_t launch_tensor_pass(const Shape& s, YType yt, const void* Y, const double* A, bool resid,
                               const PassPlan& p, const PassBuffers& b, double* M, double* e2out,
-                              const int* stop, hipStream_t st) {
+                              const int* stop, hipStream_t st, const PassFold* fold) {
   PassArgs a{};
   a.Y = Y;
   a.I0 = s.I[0];
@@ -790,19 +842,29 @@ hipError_t launch_tensor_pass(const Shape& s, YType yt, const void* Y, const dou
   const long long len0 = (long long)s.R * s.I[0], len1 = (long long)s.R * s.I[1];
   const long long lent = (long long)s.R * p.Q;
   double* tdst = (s.N == 3) ? M + (long long)s.off[2] * s.R : b.tbuf;
-  if (p.tc_bytes == 8) {
-    k_reduce_slots<double><<<(unsigned)((len0 + 63) / 64), 1024, 0, st>>>((const double*)b.m0part, nslot0, len0,
-                                                       M + (long long)s.off[0] * s.R, stop);
-    k_reduce_slots<double><<<(unsigned)((len1 + 63) / 64), 1024, 0, st>>>((const double*)b.m1part, nslot1, len1,
-                                                       M + (long long)s.off[1] * s.R, stop);
-    k_reduce_slots<double><<<(unsigned)((lent + 63) / 64), 1024, 0, st>>>((const double*)b.tpart, ntile, lent, tdst, stop);
-  } else {
-    k_reduce_slots<float><<<(unsigned)((len0 + 63) / 64), 1024, 0, st>>>((const float*)b.m0part, nslot0, len0,
-                                                      M + (long long)s.off[0] * s.R, stop);
-    k_reduce_slots<float><<<(unsigned)((len1 + 63) / 64), 1024, 0, st>>>((const float*)b.m1part, nslot1, len1,
-                                                      M + (long long)s.off[1] * s.R, stop);
-    k_reduce_slots<float><<<(unsigned)((lent + 63) / 64), 1024, 0, st>>>((const float*)b.tpart, ntile, lent, tdst, stop);
+  ReduceArgs ra{};
+  ra.seg[0] = SlotSeg{b.m0part, nslot0, len0, M + (long long)s.off[0] * s.R};
+  ra.seg[1] = SlotSeg{b.m1part, nslot1, len1, M + (long long)s.off[1] * s.R};
+  ra.seg[2] = SlotSeg{b.tpart, ntile, lent, tdst};
+  for (int k = 0; k < 3; ++k) ra.nb[k] = (int)((ra.seg[k].len + 63) / 64);
+  ra.A1 = A + (long long)s.off[0] * s.R;
+  ra.N = s.N;
+  ra.R2 = s.R * s.R;
+  int nextra = 0;
+  if (fold) {
+    ra.ipart = fold->ipart;
+    if (fold->rowpart) {
+      ra.rowpart = fold->rowpart;
+      ra.chunks = fold->chunks;
+      ra.stride = fold->stride;
+      ra.gout = fold->gout;
+      ra.gscal = fold->gscal;
+      nextra = s.N + 1;
+    }
   }
+  const unsigned nblk = (unsigned)(ra.nb[0] + ra.nb[1] + ra.nb[2] + nextra);
+  if (p.tc_bytes == 8) k_reduce_slots<double><<<nblk, 1024, 0, st>>>(ra, stop);
+  else k_reduce_slots<float><<<nblk, 1024, 0, st>>>(ra, stop);
   if (s.N >= 4) k_modes_from_t<<<256, 256, 0, st>>>(a, b.tbuf, M, stop);
   if (resid && e2out) k_sum<<<1, 256, 0, st>>>(b.e2part, (int)p.e2_elems, e2out, stop);
   return hipGetLastError();
