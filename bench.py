@@ -65,27 +65,28 @@ def syrk_flops(N, R):
 # either changes the figure no longer describes the kernel and is reported as
 # null.
 TRAFFIC = {
-    "factor_solve": ("paper_1205_2584_amd/csrc/chol.hip", "5c323964c16d94d6", 835960386),
-    "tensor_pass_f32": ("paper_1205_2584_amd/csrc/tensor_pass.hip", "4340cf06d86734ac", 517661481),
-    "tensor_pass_bf16": ("paper_1205_2584_amd/csrc/tensor_pass.hip", "4340cf06d86734ac", 268081857),
+    "factor_solve": (("paper_1205_2584_amd/csrc/chol.hip", "paper_1205_2584_amd/csrc/panel.hpp"),
+                     "0aa69a8a8e551a13", 837922863),
+    "tensor_pass_f32": (("paper_1205_2584_amd/csrc/tensor_pass.hip",), "cec26df43e38f726", 517664165),
+    "tensor_pass_bf16": (("paper_1205_2584_amd/csrc/tensor_pass.hip",), "cec26df43e38f726", 268074243),
 }
 
 
 def traffic(key, workload_name):
-    import hashlib
     if workload_name != "500cube_r30":
         return None
-    path, sha, nbytes = TRAFFIC[key]
-    return nbytes if kernel_sha(path) == sha else None
+    paths, sha, nbytes = TRAFFIC[key]
+    return nbytes if kernel_sha(paths) == sha else None
 
 
-def kernel_sha(path):
-    """SHA-256 prefix of a kernel source together with the library's compiler flags."""
+def kernel_sha(paths):
+    """SHA-256 prefix of a kernel's sources together with the library's compiler flags."""
     import hashlib
     from paper_1205_2584_amd import build
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, path), "rb") as f:
-        h.update(f.read())
+    for path in paths:
+        with open(os.path.join(ROOT, path), "rb") as f:
+            h.update(f.read())
     flags = [f for i, f in enumerate(build.FLAGS) if f != "-I" and not (i and build.FLAGS[i - 1] == "-I")]
     h.update(" ".join(flags).encode())  # include paths differ between machines
     return h.hexdigest()[:16]
