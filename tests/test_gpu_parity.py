@@ -96,6 +96,30 @@ def test_step_fp64_matches_oracle(ctx, shape, mu):
         assert _rel(cp.flat(da), cp.flat(bda)) < 1e-9
 
 
+# ranks at the edges of the 16-column blocks of the R x R factorisations (R
+# padded to 16 ceil(R / 16) with the identity: one block with and without
+# padding, two blocks with 15 and with 0 padding rows)
+EDGE_RANKS = [((17, 16, 15), 15), ((18, 17, 16), 16), ((19, 18, 17), 17), ((16, 15, 14), 31),
+              ((15, 14, 13), 32)]
+
+
+@pytest.mark.parametrize("mu", [1e-2, 30.0])
+@pytest.mark.parametrize("shape", EDGE_RANKS)
+def test_step_block_edge_ranks_match_oracle(ctx, shape, mu):
+    dims, R = shape
+    print(f"edge-rank step dims={dims} R={R} mu={mu}", flush=True)
+    p = cpgen.small_problem(5 * R + 1, dims, R, c=0.5, snr_db=25.0)
+    dgn = _dgn()
+    out, info = ctx.dgn_step(torch.from_numpy(p.y).cuda(), dims, R, dgn.to_device_factors(p.init), mu)
+    got = dgn.to_host_factors(out)
+    ref = cp.fast_step(cp.as_tensor(p.y, dims), p.init, mu)
+    da = [g - a for g, a in zip(got, p.init)]
+    err = _rel(cp.flat(da), cp.flat(ref.dA))
+    print(f"  rel err vs oracle {err:.2e}", flush=True)
+    assert err < 1e-9
+    assert abs(info["denom"] - cp.gain_denominator(ref.dA, ref.g, mu)) <= 1e-9 * abs(info["denom"])
+
+
 def test_step_zero_gradient_exact_rank(ctx):
     dims, R = (9, 8, 7), 3
     p = cpgen.small_problem(3, dims, R, c=0.4, snr_db=None)

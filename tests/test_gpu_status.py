@@ -102,6 +102,31 @@ def test_zero_column_step_defined_als_singular(ctx):
     assert e.value.status == -3
 
 
+@pytest.mark.parametrize("case", ["zero_first_block", "zero_second_block", "equal_columns"])
+def test_semidefinite_gram_step(ctx, case):
+    """C_n singular at R = 20 (two 16-column blocks in the factorisation of C_n):
+    a zero column in either block, or two equal columns of one factor (the
+    pivot falls to rounding level in the second block).  H + mu I stays
+    positive definite, and the step equals the explicit-Jacobian solve."""
+    dgn = _dgn()
+    p = cpgen.small_problem(9, (14, 13, 12), 20, c=0.3, snr_db=30.0)
+    A0 = [a.copy() for a in p.init]
+    if case == "zero_first_block":
+        A0[1][:, 2] = 0.0
+    elif case == "zero_second_block":
+        A0[0][:, 18] = 0.0
+    else:
+        A0[2][:, 17] = A0[2][:, 5]
+    print(f"semidefinite C_n step case={case}", flush=True)
+    y = torch.from_numpy(p.y).cuda()
+    out, info = ctx.dgn_step(y, p.dims, p.R, dgn.to_device_factors(A0), 0.5)
+    bda, _, _ = brute.plain_step(p.y, A0, 0.5)
+    da = [g - a for g, a in zip(dgn.to_host_factors(out), A0)]
+    err = _rel(cp.flat(da), cp.flat(bda))
+    print(f"  rel err vs explicit solve {err:.2e}", flush=True)
+    assert err < 1e-9
+
+
 @pytest.mark.parametrize("batched", [False, True])
 def test_singular_trials_rejected_in_fit(ctx, batched):
     """In a fit, a trial whose damped Gram is singular in FP64 is rejected and mu
