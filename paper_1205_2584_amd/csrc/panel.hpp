@@ -158,9 +158,11 @@ __device__ __forceinline__ void trail16(double (*T)[TR], int bi, int bj, int k0)
 // 16-blocks by forward substitution (wave w inverts block w, lane j a column),
 // then the blocks at distance d = 1..3 below the diagonal:
 //   X_ij = -X_ii sum_{k=j}^{i-1} L_ik X_kj.
-__device__ void invert_lower64(double (*T)[TR], double (*X)[TR], const double* rinv, double (*Z)[16][16]) {
+// Only the leading nb 16-blocks (nb <= 4) are inverted when nb < 4.
+__device__ void invert_lower64(double (*T)[TR], double (*X)[TR], const double* rinv, double (*Z)[16][16],
+                               int nb = 4) {
   const int t = threadIdx.x, w = t >> 6, lane = t & 63, cl = lane & 15, kq = lane >> 4;
-  {
+  if (w < nb) {
     const int b0 = 16 * w, j = cl;
     double x[16];
 #pragma unroll
@@ -176,9 +178,9 @@ __device__ void invert_lower64(double (*T)[TR], double (*X)[TR], const double* r
     }
   }
   sync_block();
-  for (int d = 1; d < 4; ++d) {
+  for (int d = 1; d < nb; ++d) {
     const int j = w, i = w + d;
-    if (i < 4) {
+    if (i < nb) {
       v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
       for (int k = j; k < i; ++k)
 #pragma unroll

@@ -246,16 +246,15 @@ __global__ __launch_bounds__(256) void k_gamma(Shape s, const double* C, double 
     FOR_RR(r, q) Lc[(long long)n * R2 + r + q * R] = (r >= q) ? T[r][q] : 0.0;
     return;
   }
-  invert_lower64(T, T + 64, rinv, Lk);
-  FOR_RR(r, q) {
-    const int e = r + q * R;
-    // X = L^-T (upper triangular), Gt = L^-T L^-1
-    X[(long long)n * R2 + e] = T[64 + q][r];
-    const int k0 = r > q ? r : q;
-    double acc = 0.0;
-    for (int k = k0; k < R; ++k) acc += T[64 + k][r] * T[64 + k][q];
-    Gt[(long long)n * R2 + e] = acc;
-  }
+  invert_lower64(T, T + 64, rinv, Lk, nkb);
+  // X = L^-T (upper triangular), Gt = L^-T L^-1 (the padding rows of L^-1 are
+  // zero in the first R columns, so the sum may run to Rp)
+  FOR_RR(r, q) X[(long long)n * R2 + r + q * R] = T[64 + q][r];
+  mm16(
+      nkb, nkb, Rp, [&](int r, int k) { return T[64 + k][r]; }, [&](int k, int q) { return T[64 + k][q]; },
+      [&](int r, int q, double v) {
+        if (r < R && q < R) Gt[(long long)n * R2 + r + q * R] = v;
+      });
 }
 
 // Rows of mode n, chunk c: G = M - A Gamma (or M itself when it already is the
@@ -389,8 +388,7 @@ __global__ __launch_bounds__(256) void k_pw(Shape s, const double* A, const doub
 }
 
 // w_m[e] = sum over the row chunks of the partials A_m^T P_m, eight loads in
-// flight at a time (fixed order, so every block that needs w_m[e] gets the
-// same value).
+// flight at a time.
 __device__ __forceinline__ double w_sum(const double* part, int m, int chunks, int stride, int e) {
   const double* p0 = part + (long long)m * chunks * stride + e;
   double acc = 0.0;
@@ -405,36 +403,48 @@ __device__ __forceinline__ double w_sum(const double* part, int m, int chunks, i
   return acc;
 }
 
-// Per mode n: w_n from the row-chunk partials, V = sum_{m != n} Gamma_nm * W_m^T
-// and z_n = vec(L_n^T V X_n) (= (W^T K w)_n); block 0 also reduces ||G||^2 and
-// ||M||^2 into scal[2], scal[3].
-__global__ __launch_bounds__(1024) void k_z(Shape s, const double* C, const double* part, int chunks,
-                                           int stride, const double* X, const double* Lc, double* w,
-                                           double* scal, double* z, const int* stop) {
+// w = the sums of the row-chunk partials A_n^T P_n, one entry per thread over
+// all modes; the last block reduces ||G||^2 and ||M||^2 into scal[2], scal[3].
+__global__ __launch_bounds__(256) void k_wred(Shape s, const double* part, int chunks, int stride, double* w,
+                                              double* scal, const int* stop) {
+  if (stopped(stop)) return;
+  const int R2 = s.R * s.R, N = s.N, t = threadIdx.x;
+  if ((int)blockIdx.x == (int)gridDim.x - 1) {
+    if (t < 2) {
+      double acc = 0.0;
+      for (int m = 0; m < N; ++m)
+        for (int c = 0; c < chunks; ++c) acc += part[((long long)m * chunks + c) * stride + R2 + t];
+      scal[2 + t] = acc;
+    }
+    return;
+  }
+  const int x = blockIdx.x * 256 + t;
+  if (x < N * R2) w[x] = w_sum(part, x / R2, chunks, stride, x % R2);
+}
+
+// Per mode n: V = sum_{m != n} Gamma_nm * W_m^T and z_n = vec(L_n^T V X_n)
+// (= (W^T K w)_n).
+__global__ __launch_bounds__(256) void k_z(Shape s, const double* C, const double* w, const double* X,
+                                           const double* Lc, double* z, const int* stop) {
   if (stopped(stop)) return;
   __shared__ double V[64][LD];
   __shared__ double Ls[64][LD];
   __shared__ double Xs[64][LD];
   __shared__ double Tm[64][LD];
-  const int n = blockIdx.x, R = s.R, R2 = R * R, N = s.N, t = threadIdx.x, nt = (R + 15) >> 4, Rp = 16 * nt;
+  const int n = blockIdx.x, R = s.R, R2 = R * R, N = s.N, nt = (R + 15) >> 4, Rp = 16 * nt;
   RR_SHIFT;
-  if (n == 0 && t < 2) {
-    double acc = 0.0;
-    for (int m = 0; m < N; ++m)
-      for (int c = 0; c < chunks; ++c) acc += part[((long long)m * chunks + c) * stride + R2 + t];
-    scal[2 + t] = acc;
-  }
-  FOR_RR(a, b) w[(long long)n * R2 + a + b * R] = w_sum(part, n, chunks, stride, a + b * R);
   for_rr_staged(
       R, rr_sh,
       [&](int a, int b) {
         const int e = a + b * R;
-        double cv[kMaxOrder];
+        double cv[kMaxOrder], wv[kMaxOrder];
         load_c(C, N, R2, e, cv);
+#pragma unroll
+        for (int m = 0; m < kMaxOrder; ++m) wv[m] = (m < N && m != n) ? w[(long long)m * R2 + b + a * R] : 0.0;
         double v = 0.0;
 #pragma unroll
         for (int m = 0; m < kMaxOrder; ++m)
-          if (m < N && m != n) v += prod_except(cv, n, m) * w_sum(part, m, chunks, stride, b + a * R);
+          if (m < N && m != n) v += prod_except(cv, n, m) * wv[m];
         return d3{v, Lc[(long long)n * R2 + e], X[(long long)n * R2 + e]};
       },
       [&](int a, int b, d3 v) {
@@ -650,7 +660,9 @@ hipError_t launch_pw(const Shape& s, const double* A, const double* M, bool resi
 
 hipError_t launch_wz(const Shape& s, const SmallBuffers& b, const int* stop, hipStream_t st) {
   const int ch = row_chunks(s), stride = part_stride(s);
-  k_z<<<s.N, 1024, 0, st>>>(s, b.C, b.wpart, ch, stride, b.X, b.Lc, b.w, b.scal, b.z, stop);
+  const int nw = (s.N * s.R * s.R + 255) / 256;
+  k_wred<<<nw + 1, 256, 0, st>>>(s, b.wpart, ch, stride, b.w, b.scal, stop);
+  k_z<<<s.N, 256, 0, st>>>(s, b.C, b.w, b.X, b.Lc, b.z, stop);
   return hipGetLastError();
 }
 
