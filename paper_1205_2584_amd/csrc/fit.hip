@@ -18,7 +18,8 @@ namespace dgn {
 namespace {
 
 // err2 of factors A with pass output M (mode 1 block) and Grams C.  With
-// ipart, <A_1, M_1> is the sum of its nip pieces.
+// ipart, <A_1, M_1> is the sum of its nip pieces.  red: 32 doubles of shared
+// memory; the two sums share one block reduction.
 __device__ double err2_of(const Shape& s, const double* A, const double* M, const double* C,
                           int resid, const double* e2, double ynorm2_pass, double* red,
                           const double* ipart = nullptr, int nip = 0) {
@@ -40,21 +41,47 @@ __device__ double err2_of(const Shape& s, const double* A, const double* M, cons
     for (; e < n; e += bd) part[0] += A[e] * M[e];
   }
   double inner = ((part[0] + part[1]) + (part[2] + part[3])) + ((part[4] + part[5]) + (part[6] + part[7]));
-  inner = block_sum(inner, red);
+  // ||Y_hat||^2 = sum over (r, s) of prod_n C_n[r, s]; the loads of four entries in flight
   double yh = 0.0;
-  for (int e = threadIdx.x; e < R2; e += blockDim.x) {
-    double g = 1.0;
-    for (int k = 0; k < s.N; ++k) g *= C[(long long)k * R2 + e];
-    yh += g;
+  for (int e0 = threadIdx.x; e0 < R2; e0 += 4 * bd) {
+    double cv[4][kMaxOrder];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int k = 0; k < kMaxOrder; ++k) {
+        const int x = e0 + u * bd;
+        cv[u][k] = (k < s.N && x < R2) ? C[(long long)k * R2 + x] : 1.0;
+      }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      double g = 1.0;
+#pragma unroll
+      for (int k = 0; k < kMaxOrder; ++k) g *= cv[u][k];
+      if (e0 + u * bd < R2) yh += g;
+    }
   }
-  yh = block_sum(yh, red);
-  return ynorm2_pass - 2.0 * inner + yh;
+  inner = wave_sum(inner);
+  yh = wave_sum(yh);
+  const int w = threadIdx.x / kWave, nw = bd / kWave;
+  sync_block();
+  if (threadIdx.x % kWave == 0) {
+    red[w] = inner;
+    red[16 + w] = yh;
+  }
+  sync_block();
+  double si = 0.0, sy = 0.0;
+  for (int i = 0; i < nw; ++i) {
+    si += red[i];
+    sy += red[16 + i];
+  }
+  sync_block();
+  return ynorm2_pass - 2.0 * si + sy;
 }
 
 __global__ __launch_bounds__(256) void k_fit_init(Shape s, const double* A, const double* M,
                                                   const double* C, int resid, const double* e2,
                                                   double mu0, double tau, FitState* st, int cs) {
-  __shared__ double red[16];
+  __shared__ double red[32];
   const double err2 = err2_of(s, A, M, C, resid, e2, st->ynorm2_pass, red);
   if (threadIdx.x == 0) {
     const int R = s.R, R2 = R * R;
@@ -99,14 +126,14 @@ __global__ __launch_bounds__(256) void k_refresh(Shape s, const double* e2, FitS
 __global__ __launch_bounds__(256) void k_err2(Shape s, const double* A, const double* M,
                                               const double* C, int resid, const double* e2,
                                               const double* ynorm2_pass, double* out) {
-  __shared__ double red[16];
+  __shared__ double red[32];
   const double v = err2_of(s, A, M, C, resid, e2, ynorm2_pass[0], red);
   if (threadIdx.x == 0) out[0] = v;
 }
 
 __global__ __launch_bounds__(256) void k_inner(Shape s, const double* A, const double* M,
                                                double* out) {
-  __shared__ double red[16];
+  __shared__ double red[32];
   double v = 0.0;
   for (int e = threadIdx.x; e < s.I[0] * s.R; e += blockDim.x) v += A[e] * M[e];
   v = block_sum(v, red);
@@ -117,7 +144,7 @@ __global__ __launch_bounds__(256) void k_control(Shape s, const double* Ac, cons
                                                  const double* Cc, int resid, const double* e2,
                                                  const double* scal, FitState* st, int trial, int cs,
                                                  const double* ipart, int nip) {
-  __shared__ double red[16];
+  __shared__ double red[32];
   __shared__ int accept_s;
   if (st->stop) return;
   const double err2c = err2_of(s, Ac, Mc, Cc, resid, e2, st->ynorm2_pass, red, ipart, nip);
@@ -218,17 +245,43 @@ __global__ __launch_bounds__(256) void k_commit(Shape s, double* A, const double
   const int n = blockIdx.x, c = blockIdx.y, R = s.R, R2 = R * R, In = s.I[n], N = s.N;
   const double* sc = st->scale;
   const long long base = (long long)s.off[n] * R;
-  for (int e = threadIdx.x; e < 64 * R; e += 256) {
-    const int ii = e & 63, r = e >> 6;
-    const int i = c * 64 + ii;
-    if (i >= In) continue;
-    const long long gi = base + i + (long long)r * In;
-    double other = 1.0;
-    for (int k = 0; k < N; ++k)
-      if (k != n) other *= sc[k * kMaxRank + r];
-    for (int h = 0; h < cs; ++h) {
-      A[cs * gi + h] = Ac[cs * gi + h] * sc[n * kMaxRank + r];
-      M[cs * gi + h] = Mc[cs * gi + h] * other;
+  if (cs == 1) {
+    // every load of the thread issued before the stores
+    constexpr int NE = 64 * kMaxRank / 256;
+    double av[NE], mv[NE];
+#pragma unroll
+    for (int k = 0; k < NE; ++k) {
+      const int e = threadIdx.x + 256 * k, ii = e & 63, r = e >> 6, i = c * 64 + ii;
+      const bool ok = e < 64 * R && i < In;
+      const long long gi = base + i + (long long)r * In;
+      av[k] = ok ? Ac[gi] : 0.0;
+      mv[k] = ok ? Mc[gi] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < NE; ++k) {
+      const int e = threadIdx.x + 256 * k, ii = e & 63, r = e >> 6, i = c * 64 + ii;
+      if (e < 64 * R && i < In) {
+        const long long gi = base + i + (long long)r * In;
+        double other = 1.0;
+        for (int m = 0; m < N; ++m)
+          if (m != n) other *= sc[m * kMaxRank + r];
+        A[gi] = av[k] * sc[n * kMaxRank + r];
+        M[gi] = mv[k] * other;
+      }
+    }
+  } else {
+    for (int e = threadIdx.x; e < 64 * R; e += 256) {
+      const int ii = e & 63, r = e >> 6;
+      const int i = c * 64 + ii;
+      if (i >= In) continue;
+      const long long gi = base + i + (long long)r * In;
+      double other = 1.0;
+      for (int k = 0; k < N; ++k)
+        if (k != n) other *= sc[k * kMaxRank + r];
+      for (int h = 0; h < cs; ++h) {
+        A[cs * gi + h] = Ac[cs * gi + h] * sc[n * kMaxRank + r];
+        M[cs * gi + h] = Mc[cs * gi + h] * other;
+      }
     }
   }
   if (c == 0) {

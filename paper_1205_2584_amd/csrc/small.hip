@@ -109,25 +109,35 @@ __device__ __forceinline__ double prod_except(const double (&cv)[kMaxOrder], int
   return g;
 }
 
-// Stage rows r0..r0+63 of the column-major In x R block src into S[ii][r]
-// (zero outside), with every load of the thread issued before the LDS stores.
-// Returns nothing; optional square-sum of the staged values through *sq.
-__device__ __forceinline__ void stage_rows(double (*S)[LD], const double* src, int In, int r0, int R,
-                                           double* sq = nullptr) {
+// Rows r0..r0+63 of the column-major In x R block src, as the thread's share
+// of S[ii][r] (zero outside): load_rows issues the loads, store_rows puts them
+// into LDS (optionally adding the square-sum of the values to *sq), so that
+// other loads can be issued in between.
+struct RowVals {
   double v[16];
+};
+__device__ __forceinline__ void load_rows(RowVals& rv, const double* src, int In, int r0, int R) {
 #pragma unroll
   for (int s2 = 0; s2 < 16; ++s2) {
     const int e = threadIdx.x + 256 * s2, ii = e & 63, r = e >> 6;
-    v[s2] = (r < R && r0 + ii < In) ? src[r0 + ii + (long long)r * In] : 0.0;
+    rv.v[s2] = (r < R && r0 + ii < In) ? src[r0 + ii + (long long)r * In] : 0.0;
   }
+}
+__device__ __forceinline__ void store_rows(double (*S)[LD], const RowVals& rv, int R, double* sq = nullptr) {
   double acc = 0.0;
 #pragma unroll
   for (int s2 = 0; s2 < 16; ++s2) {
     const int e = threadIdx.x + 256 * s2, ii = e & 63, r = e >> 6;
-    if (r < R) S[ii][r] = v[s2];
-    acc += v[s2] * v[s2];
+    if (r < R) S[ii][r] = rv.v[s2];
+    acc += rv.v[s2] * rv.v[s2];
   }
   if (sq) *sq += acc;
+}
+__device__ __forceinline__ void stage_rows(double (*S)[LD], const double* src, int In, int r0, int R,
+                                           double* sq = nullptr) {
+  RowVals rv;
+  load_rows(rv, src, In, r0, R);
+  store_rows(S, rv, R, sq);
 }
 
 // Gram partials of 64-row chunks: part[(n * chunks + c) * stride + (r + s R)].
@@ -274,11 +284,15 @@ __device__ void pw_block(const Shape& s, int n, int c, const double* A, const do
   }
   const long long base = (long long)s.off[n] * R;
   const double* G0 = (resid ? Gt : Gam) + (long long)n * R2;
+  // the row loads of A and M in flight while Gamma (or Gt) is staged
+  RowVals ra, rm;
+  load_rows(ra, A + base, In, r0, R);
+  load_rows(rm, M + base, In, r0, R);
   for_rr_staged(
       R, rr_sh, [&](int r, int q) { return G0[r + q * R]; }, [&](int r, int q, double v) { Gm[r][q] = v; });
   double m2 = 0.0;
-  stage_rows(As, A + base, In, r0, R);
-  stage_rows(Gs, M + base, In, r0, R, &m2);
+  store_rows(As, ra, R);
+  store_rows(Gs, rm, R, &m2);
   pad_cols(As, R, Rp);
   pad_cols(Gs, R, Rp);
   pad_rr(Gm, R, Rp);
@@ -568,10 +582,23 @@ __global__ __launch_bounds__(256) void k_update(Shape s, const double* A, const 
   }
   const double mu = state ? state->mu : mu_host;
   const long long base = (long long)s.off[n] * R;
+  // this thread's entries of P and G, in flight while A and Q_n are staged
+  constexpr int NE = 64 * kMaxRank / 256;
+  double pv[NE], gv[NE];
+#pragma unroll
+  for (int k = 0; k < NE; ++k) {
+    const int e = t + 256 * k, ii = e & 63, r = e >> 6;
+    const bool ok = e < 64 * R && r0 + ii < In;
+    const long long gi = base + r0 + ii + (long long)r * In;
+    pv[k] = ok ? P[gi] : 0.0;
+    gv[k] = ok ? G[gi] : 0.0;
+  }
+  RowVals ra;
+  load_rows(ra, A + base, In, r0, R);
   for_rr_staged(
       R, rr_sh, [&](int r, int q) { return Q[(long long)n * R2 + r + q * R]; },
       [&](int r, int q, double v) { Qs[r][q] = v; });
-  stage_rows(As, A + base, In, r0, R);
+  store_rows(As, ra, R);
   pad_cols(As, R, Rp);
   pad_rr(Qs, R, Rp);
   sync_block();
@@ -581,19 +608,22 @@ __global__ __launch_bounds__(256) void k_update(Shape s, const double* A, const 
       [&](int i, int j, double v) { Cs[i][j] = v; });
   sync_block();
   double den = 0.0, da2 = 0.0;
-  for (int e = t; e < 64 * R; e += 256) {
-    const int ii = e & 63, r = e >> 6;
-    double v = 0.0;
-    if (r0 + ii < In) {
-      const long long gi = base + r0 + ii + (long long)r * In;
-      const double da = P[gi] - Cs[ii][r];
-      v = As[ii][r] + da;
-      Ac[gi] = v;
-      if (da_out) da_out[gi] = da;
-      den += da * (G[gi] + mu * da);
-      da2 += da * da;
+#pragma unroll
+  for (int k = 0; k < NE; ++k) {
+    const int e = t + 256 * k, ii = e & 63, r = e >> 6;
+    if (e < 64 * R) {
+      double v = 0.0;
+      if (r0 + ii < In) {
+        const long long gi = base + r0 + ii + (long long)r * In;
+        const double da = pv[k] - Cs[ii][r];
+        v = As[ii][r] + da;
+        Ac[gi] = v;
+        if (da_out) da_out[gi] = da;
+        den += da * (gv[k] + mu * da);
+        da2 += da * da;
+      }
+      Cs[ii][r] = v;
     }
-    Cs[ii][r] = v;
   }
   sync_block();
   mm16(
