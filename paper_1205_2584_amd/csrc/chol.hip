@@ -386,8 +386,9 @@ __global__ __launch_bounds__(256) void k_syrk(SysPlan p, const double* B, const 
 // factors [D; B] in LDS.  Block 0 (i = ph, no B) writes L(ph, ph) to Ld.  Every diagonal-tile copy is read from St,
 // which this launch never writes.  The remaining blocks are the trailing tiles
 // (i, j), ph < j <= i <= Tt, j < Tt, which receive the update of column ph-1.
-// Their MFMA operands load straight from global memory into registers, so the
-// launch needs about 79 KB of LDS and two workgroups fit on a CU.
+// Their MFMA operands load straight from global memory into registers.  The
+// launches reserve LDS so that each workgroup has its CU alone
+// (phase_lds_reserve).
 // Bounded wait until the workgroup-shared counter reaches `target`; on
 // exhaustion (never expected: the waves waited on make progress on their own)
 // the singular flag is raised and the wait ends.
@@ -596,8 +597,7 @@ __global__ __launch_bounds__(256, 2) void k_chol_phase(SysPlan p, int ph, double
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
   const int cl = lane & 15, kq = lane >> 4;
   if ((int)blockIdx.x < npanel) {
-    // the panel is the critical path of the phase: its waves win instruction
-    // issue over the trailing and Gauss-Jordan blocks that share their CU
+    // the panel is the critical path of the phase
     __builtin_amdgcn_s_setprio(3);
     const int i = ph + blockIdx.x;
     const bool hb = (i != ph);
@@ -993,6 +993,23 @@ SysPlan plan_sys_c(const Shape& s) {
   return p;
 }
 
+// Dynamic LDS reserved by every phase launch on top of the kernel's own, so
+// that a workgroup takes more than half of a CU's 160 KB and has its CU alone:
+// measured at 500^3, R = 30, two workgroups per CU let the trailing and
+// elimination blocks' FP64 MFMA slow the panel's FP64 VALU chain (0.710 ms of
+// phases per trial against 0.665 ms with one per CU).  The kernel keeps the
+// register budget of two workgroups per CU (its launch bounds), which
+// scheduled faster than the budget of one (0.670 ms).
+static unsigned phase_lds_reserve() {
+  static const unsigned v = [] {
+    hipFuncAttributes a{};
+    if (hipFuncGetAttributes(&a, reinterpret_cast<const void*>(k_chol_phase)) != hipSuccess) return 8192u;
+    const size_t half = 160 * 1024 / 2;
+    return a.sharedSizeBytes > half ? 0u : (unsigned)(half - a.sharedSizeBytes + 1024);
+  }();
+  return v;
+}
+
 hipError_t launch_sys_factor_solve_core(const SysPlan& p, const SysBuffers& y, int* singular, const int* stop,
                                         hipStream_t st) {
   if (use_gj(p)) {
@@ -1000,14 +1017,14 @@ hipError_t launch_sys_factor_solve_core(const SysPlan& p, const SysBuffers& y, i
     // Gauss-Jordan steps), then two launches that finish the elimination
     for (int ph = 0; ph < p.Tt + 2; ++ph) {
       const long long nb = phase_blocks(p, ph);
-      if (nb > 0) k_chol_phase<<<(unsigned)nb, 256, 0, st>>>(p, ph, y.St, y.Ld, y.yt, singular, stop);
+      if (nb > 0) k_chol_phase<<<(unsigned)nb, 256, phase_lds_reserve(), st>>>(p, ph, y.St, y.Ld, y.yt, singular, stop);
     }
     return hipGetLastError();
   }
   // large systems: the factorisation, every L_kk^-1, then the backward
   // substitution two tiles per launch
   for (int ph = 0; ph < p.Tt; ++ph)
-    k_chol_phase<<<(unsigned)phase_blocks(p, ph), 256, 0, st>>>(p, ph, y.St, y.Ld, y.yt, singular, stop);
+    k_chol_phase<<<(unsigned)phase_blocks(p, ph), 256, phase_lds_reserve(), st>>>(p, ph, y.St, y.Ld, y.yt, singular, stop);
   k_inv_diag<<<p.Tt, 256, 0, st>>>(p, y.Ld, y.Li, stop);
   int k = p.Tt - 1;
   for (; k >= 1; k -= 2) k_bsolve2<<<k + 1, 256, 0, st>>>(p, k, y.St, y.Li, y.yt, stop);
