@@ -55,18 +55,20 @@ __device__ __forceinline__ void ldl_update(double (&r)[16], double l, double a) 
 // multipliers are zero, and so is the column of the scaled factor.
 constexpr double kPsdTol = 64.0 * 2.220446049250313e-16;
 
+// Lanes at or above the pivot row (row <= C) run the same update on their
+// entries right of the diagonal; those entries feed no entry on or below it
+// (the broadcasts read column C of rows J > C) and ldl_scale clears them.
 template <int C, bool PSD>
 __device__ __forceinline__ void ldl_column(double (&r)[16], int row, bool& ok, double ref) {
   if constexpr (C < 16) {
     const double a = r[C];
-    const double am = (row > C) ? a : 0.0;
     const double piv = row_bcast<C>(a);
     double l;
     if constexpr (PSD) {
-      l = (piv > kPsdTol * row_bcast<C>(ref)) ? am * rcp_f64(piv) : 0.0;
+      l = (piv > kPsdTol * row_bcast<C>(ref)) ? a * rcp_f64(piv) : 0.0;
     } else {
       ok = ok && (piv > 0.0);
-      l = am * rcp_f64(piv);
+      l = a * rcp_f64(piv);
     }
     ldl_update<C + 1>(r, l, a);
     ldl_column<C + 1, PSD>(r, row, ok, ref);
@@ -74,13 +76,14 @@ __device__ __forceinline__ void ldl_column(double (&r)[16], int row, bool& ok, d
 }
 
 // Rescale the L D L^T result of one lane to the Cholesky factor:
-// L[row][c] = A^(c)[row][c] / sqrt(d_c).
+// L[row][c] = A^(c)[row][c] / sqrt(d_c) (on the diagonal r[c] = d_c, so the
+// same product gives sqrt(d_c)), zero right of the diagonal.
 template <int C>
-__device__ __forceinline__ void ldl_scale(double (&r)[16], int row, double myd, double myrsq) {
+__device__ __forceinline__ void ldl_scale(double (&r)[16], int row, double myrsq) {
   if constexpr (C < 16) {
     const double rs = row_bcast<C>(myrsq);
-    r[C] = (row > C) ? r[C] * rs : (row == C ? myd * myrsq : 0.0);
-    ldl_scale<C + 1>(r, row, myd, myrsq);
+    r[C] = (row >= C) ? r[C] * rs : 0.0;
+    ldl_scale<C + 1>(r, row, myrsq);
   }
 }
 
@@ -110,7 +113,7 @@ __device__ void chol16(double (*T)[TR], int k0, int* bad, double (*Lkk)[16], dou
     myrsq = (myd > kPsdTol * ref) ? rsqrt_f64(myd) : 0.0;
   else
     myrsq = rsqrt_f64(myd > 0.0 ? myd : 1.0);
-  ldl_scale<0>(r, row, myd, myrsq);
+  ldl_scale<0>(r, row, myrsq);
   if (lane < 16) {
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
