@@ -993,21 +993,26 @@ SysPlan plan_sys_c(const Shape& s) {
   return p;
 }
 
-// Dynamic LDS reserved by every phase launch on top of the kernel's own, so
-// that a workgroup takes more than half of a CU's 160 KB and has its CU alone:
-// measured at 500^3, R = 30, two workgroups per CU let the trailing and
-// elimination blocks' FP64 MFMA slow the panel's FP64 VALU chain (0.710 ms of
-// phases per trial against 0.665 ms with one per CU).  The kernel keeps the
+// Dynamic LDS reserved by a phase launch on top of the kernel's own, so that a
+// workgroup takes more than half of a CU's 160 KB and has its CU alone.  It
+// pays where the phase is latency-bound, its blocks fitting in about two
+// rounds of the CUs: measured at 500^3, R = 30 (at most 463 blocks a phase),
+// two workgroups per CU let the trailing and elimination blocks' FP64 MFMA
+// slow the panel's FP64 VALU chain (0.710 ms of phases per trial against 0.665
+// ms with one per CU).  Phases with more blocks are bound by the trailing
+// update and keep two per CU (with every phase exclusive, the explicit dGN
+// step at R = 30, 141 tiles, went from 16.2 to 25.4 ms).  The kernel keeps the
 // register budget of two workgroups per CU (its launch bounds), which
 // scheduled faster than the budget of one (0.670 ms).
-static unsigned phase_lds_reserve() {
+constexpr long long kExclusiveMaxBlocks = 512;
+static unsigned phase_lds_reserve(long long nblocks) {
   static const unsigned v = [] {
     hipFuncAttributes a{};
     if (hipFuncGetAttributes(&a, reinterpret_cast<const void*>(k_chol_phase)) != hipSuccess) return 8192u;
     const size_t half = 160 * 1024 / 2;
     return a.sharedSizeBytes > half ? 0u : (unsigned)(half - a.sharedSizeBytes + 1024);
   }();
-  return v;
+  return nblocks <= kExclusiveMaxBlocks ? v : 0u;
 }
 
 hipError_t launch_sys_factor_solve_core(const SysPlan& p, const SysBuffers& y, int* singular, const int* stop,
@@ -1017,14 +1022,16 @@ hipError_t launch_sys_factor_solve_core(const SysPlan& p, const SysBuffers& y, i
     // Gauss-Jordan steps), then two launches that finish the elimination
     for (int ph = 0; ph < p.Tt + 2; ++ph) {
       const long long nb = phase_blocks(p, ph);
-      if (nb > 0) k_chol_phase<<<(unsigned)nb, 256, phase_lds_reserve(), st>>>(p, ph, y.St, y.Ld, y.yt, singular, stop);
+      if (nb > 0) k_chol_phase<<<(unsigned)nb, 256, phase_lds_reserve(nb), st>>>(p, ph, y.St, y.Ld, y.yt, singular, stop);
     }
     return hipGetLastError();
   }
   // large systems: the factorisation, every L_kk^-1, then the backward
   // substitution two tiles per launch
-  for (int ph = 0; ph < p.Tt; ++ph)
-    k_chol_phase<<<(unsigned)phase_blocks(p, ph), 256, phase_lds_reserve(), st>>>(p, ph, y.St, y.Ld, y.yt, singular, stop);
+  for (int ph = 0; ph < p.Tt; ++ph) {
+    const long long nb = phase_blocks(p, ph);
+    k_chol_phase<<<(unsigned)nb, 256, phase_lds_reserve(nb), st>>>(p, ph, y.St, y.Ld, y.yt, singular, stop);
+  }
   k_inv_diag<<<p.Tt, 256, 0, st>>>(p, y.Ld, y.Li, stop);
   int k = p.Tt - 1;
   for (; k >= 1; k -= 2) k_bsolve2<<<k + 1, 256, 0, st>>>(p, k, y.St, y.Li, y.yt, stop);
