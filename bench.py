@@ -66,9 +66,9 @@ def syrk_flops(N, R):
 # null.
 TRAFFIC = {
     "factor_solve": (("paper_1205_2584_amd/csrc/chol.hip", "paper_1205_2584_amd/csrc/panel.hpp"),
-                     "0aa69a8a8e551a13", 837922863),
-    "tensor_pass_f32": (("paper_1205_2584_amd/csrc/tensor_pass.hip",), "cec26df43e38f726", 517664165),
-    "tensor_pass_bf16": (("paper_1205_2584_amd/csrc/tensor_pass.hip",), "cec26df43e38f726", 268074243),
+                     "92c3d5dea91c1b07", 837638188),
+    "tensor_pass_f32": (("paper_1205_2584_amd/csrc/tensor_pass.hip",), "cec26df43e38f726", 517789678),
+    "tensor_pass_bf16": (("paper_1205_2584_amd/csrc/tensor_pass.hip",), "cec26df43e38f726", 268071419),
 }
 
 
