@@ -380,6 +380,131 @@ __global__ __launch_bounds__(256) void k_syrk(SysPlan p, const double* B, const 
     for (int v = 0; v < 4; ++v) C[acc_col(blk) + (long long)acc_row(v) * p.lds] -= acc[blk][v];
 }
 
+// ---- the Schur update from the structure of B (R <= 32) ----------------------
+//
+// The eliminated block column is B = [S_21; S_31; ...] with
+//   S_n1[a + bR, c + dR] = sum_i X_n[i,b] L_1[i,c] T_n1[i, a + dR].
+// Summing over c (C' = L_1 L_1^T) and d first, its Gram blocks are
+//   (S_n1 S_q1^T)[a + bR, a' + b'R]
+//     = sum_{i,i'} X_n[i,b] X_q[i',b'] C'[i,i'] sum_d T_n1[i, a + dR] T_q1[i', a' + dR],
+// that is X_n^T (C' o (T_a T_a'^T)) X_q for each (a, a'), with T_a[i][d] =
+// T_n1[i, a + dR]: 3 R^5 multiply-adds per block pair against the R^6 of the
+// dense product B B^T.  One workgroup takes a block pair (n, q), q <= n, one a'
+// and kBbtAG values of a; each R x R product runs as 16 x 16 FP64 MFMA tiles (R
+// padded to 16 or 32, one output tile per wave).  Within a diagonal block pair
+// only the entries in tiles on or below the diagonal are updated, as by the
+// dense product.  The first ntp / 64 blocks form the right-hand-side row.
+constexpr int kBbtAG = 4;
+constexpr int BL = 33;  // leading dimension of the 32 x 32 LDS operands
+
+__global__ __launch_bounds__(256, 2) void k_bbt(Shape s, SysPlan p, const double* B, const double* z,
+                                                const double* Tnm, const double* X, const double* Lc,
+                                                double* St, const int* stop) {
+  if (stopped(stop)) return;
+  const int nrhs = p.ntp / 64;
+  if ((int)blockIdx.x < nrhs) {
+    rhs_block(p, B, z, St, blockIdx.x);
+    return;
+  }
+  __shared__ double Tq[32][BL];  // T_q1[i', a' + dR] as [i'][d]
+  __shared__ double Xn[32][BL];
+  __shared__ double Xq[32][BL];
+  __shared__ double TW[32][BL];  // T_a, then W = X_n^T V
+  __shared__ double UV[32][BL];  // L_1 (for C'), then V = C' o U
+  __shared__ double Out[kBbtAG][32][32];
+  const int R = s.R, R2 = R * R, N = s.N, t = threadIdx.x, w = t >> 6, lane = t & 63;
+  const int cl = lane & 15, kq = lane >> 4;
+  const int nt = (R + 15) >> 4, K = 16 * nt;
+  const int ng = (R + kBbtAG - 1) / kBbtAG;
+  long long id = (long long)blockIdx.x - nrhs;
+  const int grp = (int)(id % ng);
+  id /= ng;
+  const int ap = (int)(id % R);
+  int pr = (int)(id / R);
+  int n = 1;
+  while (pr >= n) {
+    pr -= n;
+    ++n;
+  }
+  const int q = pr + 1;
+  const double* Tn = Tnm + (long long)(n * N) * R * R2;  // T_n1: pair (n, mode 1)
+  const double* Tqg = Tnm + (long long)(q * N) * R * R2;
+  // wave w < nt^2 owns output tile (ti, tj) of every product
+  const bool tw = w < nt * nt;
+  const int ti = w % nt, tj = w / nt;
+  for (int e = t; e < 32 * 32; e += 256) {
+    const int r = e & 31, c2 = e >> 5;
+    const bool ok = r < R && c2 < R;
+    Tq[r][c2] = ok ? Tqg[(long long)(ap + c2 * R) * R + r] : 0.0;
+    Xn[r][c2] = ok ? X[(long long)n * R2 + r + c2 * R] : 0.0;
+    Xq[r][c2] = ok ? X[(long long)q * R2 + r + c2 * R] : 0.0;
+    UV[r][c2] = ok ? Lc[r + c2 * R] : 0.0;  // L_1
+  }
+  const int a0 = grp * kBbtAG, na = (R - a0 < kBbtAG) ? R - a0 : kBbtAG;
+  double tv[4];
+  auto load_ta = [&](int a) {
+#pragma unroll
+    for (int s2 = 0; s2 < 4; ++s2) {
+      const int e = t + 256 * s2, r = e & 31, c2 = e >> 5;
+      tv[s2] = (r < R && c2 < R) ? Tn[(long long)(a + c2 * R) * R + r] : 0.0;
+    }
+  };
+  load_ta(a0);
+  sync_block();
+  // C' = L_1 L_1^T on this wave's tile, kept in registers
+  v4d c1 = v4d{0.0, 0.0, 0.0, 0.0};
+  if (tw)
+    for (int k = 0; k < K; k += 4)
+      c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(UV[16 * ti + cl][k + kq], UV[16 * tj + cl][k + kq], c1, 0, 0, 0);
+  sync_block();
+  for (int al = 0; al < na; ++al) {
+#pragma unroll
+    for (int s2 = 0; s2 < 4; ++s2) {
+      const int e = t + 256 * s2, r = e & 31, c2 = e >> 5;
+      TW[r][c2] = tv[s2];
+    }
+    if (al + 1 < na) load_ta(a0 + al + 1);  // the next T_a in flight
+    sync_block();
+    if (tw) {
+      // U = T_a T_q^T, V = C' o U
+      v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+      for (int k = 0; k < K; k += 4)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(TW[16 * ti + cl][k + kq], Tq[16 * tj + cl][k + kq], acc, 0, 0, 0);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) UV[16 * ti + kq + 4 * v][16 * tj + cl] = c1[v] * acc[v];
+    }
+    sync_block();
+    if (tw) {
+      // W = X_n^T V
+      v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+      for (int k = 0; k < K; k += 4)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Xn[k + kq][16 * ti + cl], UV[k + kq][16 * tj + cl], acc, 0, 0, 0);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) TW[16 * ti + kq + 4 * v][16 * tj + cl] = acc[v];
+    }
+    sync_block();
+    if (tw) {
+      // X_n^T V X_q
+      v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+      for (int k = 0; k < K; k += 4)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(TW[16 * ti + cl][k + kq], Xq[k + kq][16 * tj + cl], acc, 0, 0, 0);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Out[al][16 * ti + kq + 4 * v][16 * tj + cl] = acc[v];
+    }
+    sync_block();
+  }
+  // St[(n-1) R^2 + a + bR, (q-1) R^2 + a' + b'R] -= Out[a - a0][b][b'], the values
+  // of a of the group adjacent in memory
+  const long long rb = (long long)(n - 1) * R2 + a0, cb = (long long)(q - 1) * R2 + ap;
+  for (int e = t; e < kBbtAG * R2; e += 256) {
+    const int al = e % kBbtAG, rest = e / kBbtAG, b = rest % R, bq = rest / R;
+    if (al >= na) continue;
+    const long long r = rb + al + (long long)b * R, c2 = cb + (long long)bq * R;
+    if (n == q && (r >> 6) < (c2 >> 6)) continue;
+    St[r + c2 * p.lds] -= Out[al][b][bq];
+  }
+}
+
 // Phase ph of the tiled Cholesky.  Blocks [0, Tt - ph + 1) are the panel row
 // tiles i = ph + blk (the last one is the right-hand-side row).  Each applies
 // the update of column ph-1 to the diagonal tile D and to its tile B, then
@@ -963,7 +1088,14 @@ hipError_t launch_sys_assemble(const Shape& s, const SysPlan& p, const SmallBuff
     k_subblock<32><<<nblk, 256, 0, st>>>(s, p, b.Tnm, b.X, b.Lc, y.St, y.B, R2p, extra, stop);
   else
     k_subblock<64><<<nblk, 256, 0, st>>>(s, p, b.Tnm, b.X, b.Lc, y.St, y.B, R2p, extra, stop);
-  k_syrk<<<(unsigned)(p.ntp / 64 + (long long)p.Tt * (p.Tt + 1) / 2), 256, 0, st>>>(p, y.B, b.z, R2p, y.St, stop);
+  if (s.R <= 32) {
+    // B B^T from the structure of B (3 R^5 per block pair instead of the dense (N-1)^2 R^6)
+    const long long npairs_t = (long long)(s.N - 1) * s.N / 2;
+    const long long ntask = npairs_t * s.R * ((s.R + kBbtAG - 1) / kBbtAG);
+    k_bbt<<<(unsigned)(p.ntp / 64 + ntask), 256, 0, st>>>(s, p, y.B, b.z, b.Tnm, b.X, b.Lc, y.St, stop);
+  } else {
+    k_syrk<<<(unsigned)(p.ntp / 64 + (long long)p.Tt * (p.Tt + 1) / 2), 256, 0, st>>>(p, y.B, b.z, R2p, y.St, stop);
+  }
   return hipGetLastError();
 }
 
