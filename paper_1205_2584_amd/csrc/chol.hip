@@ -393,34 +393,117 @@ __global__ __launch_bounds__(256) void k_syrk(SysPlan p, const double* B, const 
 // and kBbtAG values of a; each R x R product runs as 16 x 16 FP64 MFMA tiles (R
 // padded to 16 or 32, one output tile per wave).  Within a diagonal block pair
 // only the entries in tiles on or below the diagonal are updated, as by the
-// dense product.  The first ntp / 64 blocks form the right-hand-side row.
+// dense product.  The last N blocks form the right-hand-side row.
 constexpr int kBbtAG = 4;
 constexpr int BL = 33;  // leading dimension of the 32 x 32 LDS operands
+
+// One 16 x 16 MFMA tile of an R x R product with K (16 or 32) a compile-time
+// constant: every LDS operand of the chain is read before the first MFMA.
+// a(k) / b(k): this lane's A / B operand for the k-step starting at k.
+template <int KK, typename FA, typename FB>
+__device__ __forceinline__ v4d mfma_chain(FA a, FB b) {
+  double av[KK / 4], bv[KK / 4];
+#pragma unroll
+  for (int s2 = 0; s2 < KK / 4; ++s2) {
+    av[s2] = a(4 * s2);
+    bv[s2] = b(4 * s2);
+  }
+  v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int s2 = 0; s2 < KK / 4; ++s2) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s2], bv[s2], acc, 0, 0, 0);
+  return acc;
+}
+template <typename FA, typename FB>
+__device__ __forceinline__ v4d mfma_chain_k(int K, FA a, FB b) {
+  return K == 32 ? mfma_chain<32>(a, b) : mfma_chain<16>(a, b);
+}
 
 __global__ __launch_bounds__(256, 2) void k_bbt(Shape s, SysPlan p, const double* B, const double* z,
                                                 const double* Tnm, const double* X, const double* Lc,
                                                 double* St, const int* stop) {
   if (stopped(stop)) return;
-  const int nrhs = p.ntp / 64;
-  if ((int)blockIdx.x < nrhs) {
-    rhs_block(p, B, z, St, blockIdx.x);
-    return;
-  }
+  const int R = s.R, R2 = R * R, N = s.N, t = threadIdx.x, w = t >> 6, lane = t & 63;
+  const int ng = (R + kBbtAG - 1) / kBbtAG;
+  // Workgroups go to the 8 XCDs in turn: block b = 8 k + x runs on XCD x.  All
+  // a-groups of one column group (block pair, a') share an XCD, so that the
+  // 128-byte lines of St they update together, and T_q, meet in one L2.
+  const long long ncg = (long long)(N - 1) * N / 2 * R, ntb = 8 * ((ncg + 7) / 8) * ng;
   __shared__ double Tq[32][BL];  // T_q1[i', a' + dR] as [i'][d]
   __shared__ double Xn[32][BL];
   __shared__ double Xq[32][BL];
   __shared__ double TW[32][BL];  // T_a, then W = X_n^T V
   __shared__ double UV[32][BL];  // L_1 (for C'), then V = C' o U
   __shared__ double Out[kBbtAG][32][32];
-  const int R = s.R, R2 = R * R, N = s.N, t = threadIdx.x, w = t >> 6, lane = t & 63;
   const int cl = lane & 15, kq = lane >> 4;
   const int nt = (R + 15) >> 4, K = 16 * nt;
-  const int ng = (R + kBbtAG - 1) / kBbtAG;
-  long long id = (long long)blockIdx.x - nrhs;
-  const int grp = (int)(id % ng);
-  id /= ng;
-  const int ap = (int)(id % R);
-  int pr = (int)(id / R);
+  if ((long long)blockIdx.x >= ntb) {
+    // the right-hand-side row z_t - B z_1, block n - 1 for mode n (the last block
+    // zeroes the padding), from the same structure:
+    //   (S_n1 z_1)[a + bR] = sum_i X_n[i,b] sum_d T_n1[i, a + dR] P[i,d],  P = L_1 Z_1
+    const int n = (int)((long long)blockIdx.x - ntb) + 1;
+    if (n == N) {
+      for (int x = p.nt + t; x < p.ntp; x += 256) St[p.ntp + (long long)x * p.lds] = 0.0;
+      return;
+    }
+    const double* Tn = Tnm + (long long)(n * N) * R * R2;
+    double (*Zs)[BL] = Tq;
+    double (*Ls)[BL] = Xq;
+    double (*Ps)[BL] = TW;
+    double (*Qs)[BL] = UV;
+    {
+      double vz[4], vl[4], vx[4];
+#pragma unroll
+      for (int s2 = 0; s2 < 4; ++s2) {
+        const int e = t + 256 * s2, r = e & 31, c2 = e >> 5;
+        const bool ok = r < R && c2 < R;
+        vz[s2] = ok ? z[r + c2 * R] : 0.0;  // Z_1[c][d] = z_1[c + dR]
+        vl[s2] = ok ? Lc[r + c2 * R] : 0.0;
+        vx[s2] = ok ? X[(long long)n * R2 + r + c2 * R] : 0.0;
+      }
+#pragma unroll
+      for (int s2 = 0; s2 < 4; ++s2) {
+        const int e = t + 256 * s2, r = e & 31, c2 = e >> 5;
+        Zs[r][c2] = vz[s2];
+        Ls[r][c2] = vl[s2];
+        Xn[r][c2] = vx[s2];
+      }
+    }
+    sync_block();
+    if (w < nt * nt) {  // P = L_1 Z_1
+      const int ti = w % nt, tj = w / nt;
+      const v4d acc = mfma_chain_k(
+          K, [&](int k) { return Ls[16 * ti + cl][k + kq]; }, [&](int k) { return Zs[k + kq][16 * tj + cl]; });
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Ps[16 * ti + kq + 4 * v][16 * tj + cl] = acc[v];
+    }
+    sync_block();
+    // Q[i][a] = sum_d T_n1[i, a + dR] P[i][d], one (i, a) per thread at a time
+    for (int e = t; e < R2; e += 256) {
+      const int i = e % R, a = e / R;
+      double tv[32];
+#pragma unroll
+      for (int d = 0; d < 32; ++d) tv[d] = d < R ? Tn[(long long)(a + d * R) * R + i] : 0.0;
+      double acc = 0.0;
+#pragma unroll
+      for (int d = 0; d < 32; ++d)
+        if (d < R) acc += tv[d] * Ps[i][d];  // (P holds only the K columns it computed)
+      Qs[i][a] = acc;
+    }
+    sync_block();
+    // rows (n-1) R^2 + a + bR: z_n[a + bR] - sum_i X_n[i,b] Q[i][a]
+    for (int e = t; e < R2; e += 256) {
+      const int a = e % R, b = e / R;
+      double acc = 0.0;
+      for (int i = 0; i < R; ++i) acc += Xn[i][b] * Qs[i][a];
+      St[p.ntp + ((long long)(n - 1) * R2 + e) * p.lds] = z[(long long)n * R2 + e] - acc;
+    }
+    return;
+  }
+  const long long kx = (long long)blockIdx.x / 8, cgi = (kx / ng) * 8 + blockIdx.x % 8;
+  if (cgi >= ncg) return;
+  const int grp = (int)(kx % ng);
+  const int ap = (int)(cgi % R);
+  int pr = (int)(cgi / R);
   int n = 1;
   while (pr >= n) {
     pr -= n;
@@ -432,13 +515,26 @@ __global__ __launch_bounds__(256, 2) void k_bbt(Shape s, SysPlan p, const double
   // wave w < nt^2 owns output tile (ti, tj) of every product
   const bool tw = w < nt * nt;
   const int ti = w % nt, tj = w / nt;
-  for (int e = t; e < 32 * 32; e += 256) {
-    const int r = e & 31, c2 = e >> 5;
-    const bool ok = r < R && c2 < R;
-    Tq[r][c2] = ok ? Tqg[(long long)(ap + c2 * R) * R + r] : 0.0;
-    Xn[r][c2] = ok ? X[(long long)n * R2 + r + c2 * R] : 0.0;
-    Xq[r][c2] = ok ? X[(long long)q * R2 + r + c2 * R] : 0.0;
-    UV[r][c2] = ok ? Lc[r + c2 * R] : 0.0;  // L_1
+  {
+    // every load of the thread issued before the LDS stores
+    double vq[4], vn[4], vx[4], vl[4];
+#pragma unroll
+    for (int s2 = 0; s2 < 4; ++s2) {
+      const int e = t + 256 * s2, r = e & 31, c2 = e >> 5;
+      const bool ok = r < R && c2 < R;
+      vq[s2] = ok ? Tqg[(long long)(ap + c2 * R) * R + r] : 0.0;
+      vn[s2] = ok ? X[(long long)n * R2 + r + c2 * R] : 0.0;
+      vx[s2] = ok ? X[(long long)q * R2 + r + c2 * R] : 0.0;
+      vl[s2] = ok ? Lc[r + c2 * R] : 0.0;  // L_1
+    }
+#pragma unroll
+    for (int s2 = 0; s2 < 4; ++s2) {
+      const int e = t + 256 * s2, r = e & 31, c2 = e >> 5;
+      Tq[r][c2] = vq[s2];
+      Xn[r][c2] = vn[s2];
+      Xq[r][c2] = vx[s2];
+      UV[r][c2] = vl[s2];
+    }
   }
   const int a0 = grp * kBbtAG, na = (R - a0 < kBbtAG) ? R - a0 : kBbtAG;
   double tv[4];
@@ -454,8 +550,8 @@ __global__ __launch_bounds__(256, 2) void k_bbt(Shape s, SysPlan p, const double
   // C' = L_1 L_1^T on this wave's tile, kept in registers
   v4d c1 = v4d{0.0, 0.0, 0.0, 0.0};
   if (tw)
-    for (int k = 0; k < K; k += 4)
-      c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(UV[16 * ti + cl][k + kq], UV[16 * tj + cl][k + kq], c1, 0, 0, 0);
+    c1 = mfma_chain_k(
+        K, [&](int k) { return UV[16 * ti + cl][k + kq]; }, [&](int k) { return UV[16 * tj + cl][k + kq]; });
   sync_block();
   for (int al = 0; al < na; ++al) {
 #pragma unroll
@@ -467,27 +563,24 @@ __global__ __launch_bounds__(256, 2) void k_bbt(Shape s, SysPlan p, const double
     sync_block();
     if (tw) {
       // U = T_a T_q^T, V = C' o U
-      v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
-      for (int k = 0; k < K; k += 4)
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(TW[16 * ti + cl][k + kq], Tq[16 * tj + cl][k + kq], acc, 0, 0, 0);
+      const v4d acc = mfma_chain_k(
+          K, [&](int k) { return TW[16 * ti + cl][k + kq]; }, [&](int k) { return Tq[16 * tj + cl][k + kq]; });
 #pragma unroll
       for (int v = 0; v < 4; ++v) UV[16 * ti + kq + 4 * v][16 * tj + cl] = c1[v] * acc[v];
     }
     sync_block();
     if (tw) {
       // W = X_n^T V
-      v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
-      for (int k = 0; k < K; k += 4)
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Xn[k + kq][16 * ti + cl], UV[k + kq][16 * tj + cl], acc, 0, 0, 0);
+      const v4d acc = mfma_chain_k(
+          K, [&](int k) { return Xn[k + kq][16 * ti + cl]; }, [&](int k) { return UV[k + kq][16 * tj + cl]; });
 #pragma unroll
       for (int v = 0; v < 4; ++v) TW[16 * ti + kq + 4 * v][16 * tj + cl] = acc[v];
     }
     sync_block();
     if (tw) {
       // X_n^T V X_q
-      v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
-      for (int k = 0; k < K; k += 4)
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(TW[16 * ti + cl][k + kq], Xq[k + kq][16 * tj + cl], acc, 0, 0, 0);
+      const v4d acc = mfma_chain_k(
+          K, [&](int k) { return TW[16 * ti + cl][k + kq]; }, [&](int k) { return Xq[k + kq][16 * tj + cl]; });
 #pragma unroll
       for (int v = 0; v < 4; ++v) Out[al][16 * ti + kq + 4 * v][16 * tj + cl] = acc[v];
     }
@@ -495,13 +588,23 @@ __global__ __launch_bounds__(256, 2) void k_bbt(Shape s, SysPlan p, const double
   }
   // St[(n-1) R^2 + a + bR, (q-1) R^2 + a' + b'R] -= Out[a - a0][b][b'], the values
   // of a of the group adjacent in memory
+  // (all the thread's reads of St in flight before its writes)
   const long long rb = (long long)(n - 1) * R2 + a0, cb = (long long)(q - 1) * R2 + ap;
-  for (int e = t; e < kBbtAG * R2; e += 256) {
-    const int al = e % kBbtAG, rest = e / kBbtAG, b = rest % R, bq = rest / R;
-    if (al >= na) continue;
+  constexpr int NW = (kBbtAG * 32 * 32 + 255) / 256;
+  long long gi[NW];
+  double old[NW];
+#pragma unroll
+  for (int s2 = 0; s2 < NW; ++s2) {
+    const int e = t + 256 * s2, al = e % kBbtAG, rest = e / kBbtAG, b = rest % R, bq = rest / R;
     const long long r = rb + al + (long long)b * R, c2 = cb + (long long)bq * R;
-    if (n == q && (r >> 6) < (c2 >> 6)) continue;
-    St[r + c2 * p.lds] -= Out[al][b][bq];
+    const bool ok = e < kBbtAG * R2 && al < na && !(n == q && (r >> 6) < (c2 >> 6));
+    gi[s2] = ok ? r + c2 * p.lds : -1;
+    old[s2] = ok ? St[gi[s2]] : 0.0;
+  }
+#pragma unroll
+  for (int s2 = 0; s2 < NW; ++s2) {
+    const int e = t + 256 * s2, al = e % kBbtAG, rest = e / kBbtAG, b = rest % R, bq = rest / R;
+    if (gi[s2] >= 0) St[gi[s2]] = old[s2] - Out[al][b][bq];
   }
 }
 
@@ -1090,9 +1193,9 @@ hipError_t launch_sys_assemble(const Shape& s, const SysPlan& p, const SmallBuff
     k_subblock<64><<<nblk, 256, 0, st>>>(s, p, b.Tnm, b.X, b.Lc, y.St, y.B, R2p, extra, stop);
   if (s.R <= 32) {
     // B B^T from the structure of B (3 R^5 per block pair instead of the dense (N-1)^2 R^6)
-    const long long npairs_t = (long long)(s.N - 1) * s.N / 2;
-    const long long ntask = npairs_t * s.R * ((s.R + kBbtAG - 1) / kBbtAG);
-    k_bbt<<<(unsigned)(p.ntp / 64 + ntask), 256, 0, st>>>(s, p, y.B, b.z, b.Tnm, b.X, b.Lc, y.St, stop);
+    const long long ncg = (long long)(s.N - 1) * s.N / 2 * s.R;
+    const long long ntb = 8 * ((ncg + 7) / 8) * ((s.R + kBbtAG - 1) / kBbtAG);
+    k_bbt<<<(unsigned)(ntb + s.N), 256, 0, st>>>(s, p, y.B, b.z, b.Tnm, b.X, b.Lc, y.St, stop);
   } else {
     k_syrk<<<(unsigned)(p.ntp / 64 + (long long)p.Tt * (p.Tt + 1) / 2), 256, 0, st>>>(p, y.B, b.z, R2p, y.St, stop);
   }
