@@ -393,7 +393,7 @@ __global__ __launch_bounds__(256) void k_syrk(SysPlan p, const double* B, const 
 // and kBbtAG values of a; each R x R product runs as 16 x 16 FP64 MFMA tiles (R
 // padded to 16 or 32, one output tile per wave).  Within a diagonal block pair
 // only the entries in tiles on or below the diagonal are updated, as by the
-// dense product.  The last N blocks form the right-hand-side row.
+// dense product.  The last (N - 1) R + 1 blocks form the right-hand-side row.
 constexpr int kBbtAG = 4;
 constexpr int BL = 33;  // leading dimension of the 32 x 32 LDS operands
 
@@ -433,25 +433,32 @@ __global__ __launch_bounds__(256, 2) void k_bbt(Shape s, SysPlan p, const double
   __shared__ double Xq[32][BL];
   __shared__ double TW[32][BL];  // T_a, then W = X_n^T V
   __shared__ double UV[32][BL];  // L_1 (for C'), then V = C' o U
-  __shared__ double Out[kBbtAG][32][32];
+  // X_n^T V X_q of the group's values of a: rows padded to BL and the slices
+  // staggered by 8 doubles, so that neither the MFMA stores nor the column reads
+  // of the write-out meet in one LDS bank
+  constexpr int OS = 32 * BL + 8;
+  __shared__ double Out[kBbtAG * OS];
   const int cl = lane & 15, kq = lane >> 4;
   const int nt = (R + 15) >> 4, K = 16 * nt;
   if ((long long)blockIdx.x >= ntb) {
-    // the right-hand-side row z_t - B z_1, block n - 1 for mode n (the last block
-    // zeroes the padding), from the same structure:
-    //   (S_n1 z_1)[a + bR] = sum_i X_n[i,b] sum_d T_n1[i, a + dR] P[i,d],  P = L_1 Z_1
-    const int n = (int)((long long)blockIdx.x - ntb) + 1;
-    if (n == N) {
+    // the right-hand-side row z_t - B z_1 from the same structure:
+    //   (S_n1 z_1)[a + bR] = sum_i X_n[i,b] Q[i,a],  Q[i,a] = sum_d T_n1[i, a + dR] P[i,d],
+    // P = L_1 Z_1.  Block (n, a) forms Q[:, a] and the R rows a + bR of mode n; the
+    // last block zeroes the padding.
+    const long long rid = (long long)blockIdx.x - ntb;
+    if (rid == (long long)(N - 1) * R) {
       for (int x = p.nt + t; x < p.ntp; x += 256) St[p.ntp + (long long)x * p.lds] = 0.0;
       return;
     }
+    const int n = (int)(rid / R) + 1, a = (int)(rid % R);
     const double* Tn = Tnm + (long long)(n * N) * R * R2;
     double (*Zs)[BL] = Tq;
     double (*Ls)[BL] = Xq;
     double (*Ps)[BL] = TW;
-    double (*Qs)[BL] = UV;
+    double (*Ts)[BL] = UV;  // Ts[i][d] = T_n1[i, a + dR]
+    double* Qv = &Out[0];
     {
-      double vz[4], vl[4], vx[4];
+      double vz[4], vl[4], vx[4], vt[4];
 #pragma unroll
       for (int s2 = 0; s2 < 4; ++s2) {
         const int e = t + 256 * s2, r = e & 31, c2 = e >> 5;
@@ -459,6 +466,7 @@ __global__ __launch_bounds__(256, 2) void k_bbt(Shape s, SysPlan p, const double
         vz[s2] = ok ? z[r + c2 * R] : 0.0;  // Z_1[c][d] = z_1[c + dR]
         vl[s2] = ok ? Lc[r + c2 * R] : 0.0;
         vx[s2] = ok ? X[(long long)n * R2 + r + c2 * R] : 0.0;
+        vt[s2] = ok ? Tn[(long long)(a + c2 * R) * R + r] : 0.0;
       }
 #pragma unroll
       for (int s2 = 0; s2 < 4; ++s2) {
@@ -466,10 +474,11 @@ __global__ __launch_bounds__(256, 2) void k_bbt(Shape s, SysPlan p, const double
         Zs[r][c2] = vz[s2];
         Ls[r][c2] = vl[s2];
         Xn[r][c2] = vx[s2];
+        Ts[r][c2] = vt[s2];
       }
     }
     sync_block();
-    if (w < nt * nt) {  // P = L_1 Z_1
+    if (w < nt * nt) {  // P = L_1 Z_1 (all K columns, zero beyond R)
       const int ti = w % nt, tj = w / nt;
       const v4d acc = mfma_chain_k(
           K, [&](int k) { return Ls[16 * ti + cl][k + kq]; }, [&](int k) { return Zs[k + kq][16 * tj + cl]; });
@@ -477,24 +486,16 @@ __global__ __launch_bounds__(256, 2) void k_bbt(Shape s, SysPlan p, const double
       for (int v = 0; v < 4; ++v) Ps[16 * ti + kq + 4 * v][16 * tj + cl] = acc[v];
     }
     sync_block();
-    // Q[i][a] = sum_d T_n1[i, a + dR] P[i][d], one (i, a) per thread at a time
-    for (int e = t; e < R2; e += 256) {
-      const int i = e % R, a = e / R;
-      double tv[32];
-#pragma unroll
-      for (int d = 0; d < 32; ++d) tv[d] = d < R ? Tn[(long long)(a + d * R) * R + i] : 0.0;
+    if (t < R) {  // Q[i][a] = sum_d Ts[i][d] P[i][d]
       double acc = 0.0;
-#pragma unroll
-      for (int d = 0; d < 32; ++d)
-        if (d < R) acc += tv[d] * Ps[i][d];  // (P holds only the K columns it computed)
-      Qs[i][a] = acc;
+      for (int d = 0; d < R; ++d) acc += Ts[t][d] * Ps[t][d];
+      Qv[t] = acc;
     }
     sync_block();
-    // rows (n-1) R^2 + a + bR: z_n[a + bR] - sum_i X_n[i,b] Q[i][a]
-    for (int e = t; e < R2; e += 256) {
-      const int a = e % R, b = e / R;
+    if (t < R) {  // row a + tR: z_n[a + tR] - sum_i X_n[i][t] Q[i]
       double acc = 0.0;
-      for (int i = 0; i < R; ++i) acc += Xn[i][b] * Qs[i][a];
+      for (int i = 0; i < R; ++i) acc += Xn[i][t] * Qv[i];
+      const int e = a + t * R;
       St[p.ntp + ((long long)(n - 1) * R2 + e) * p.lds] = z[(long long)n * R2 + e] - acc;
     }
     return;
@@ -515,37 +516,44 @@ __global__ __launch_bounds__(256, 2) void k_bbt(Shape s, SysPlan p, const double
   // wave w < nt^2 owns output tile (ti, tj) of every product
   const bool tw = w < nt * nt;
   const int ti = w % nt, tj = w / nt;
-  {
-    // every load of the thread issued before the LDS stores
-    double vq[4], vn[4], vx[4], vl[4];
-#pragma unroll
-    for (int s2 = 0; s2 < 4; ++s2) {
-      const int e = t + 256 * s2, r = e & 31, c2 = e >> 5;
-      const bool ok = r < R && c2 < R;
-      vq[s2] = ok ? Tqg[(long long)(ap + c2 * R) * R + r] : 0.0;
-      vn[s2] = ok ? X[(long long)n * R2 + r + c2 * R] : 0.0;
-      vx[s2] = ok ? X[(long long)q * R2 + r + c2 * R] : 0.0;
-      vl[s2] = ok ? Lc[r + c2 * R] : 0.0;  // L_1
-    }
-#pragma unroll
-    for (int s2 = 0; s2 < 4; ++s2) {
-      const int e = t + 256 * s2, r = e & 31, c2 = e >> 5;
-      Tq[r][c2] = vq[s2];
-      Xn[r][c2] = vn[s2];
-      Xq[r][c2] = vx[s2];
-      UV[r][c2] = vl[s2];
-    }
-  }
   const int a0 = grp * kBbtAG, na = (R - a0 < kBbtAG) ? R - a0 : kBbtAG;
-  double tv[4];
-  auto load_ta = [&](int a) {
+  // Every global load of the block at once: the operands, the kBbtAG slices
+  // T_a and the St entries it updates (no other block writes them).  St[(n-1)
+  // R^2 + a + bR, (q-1) R^2 + a' + b'R]: wave w takes the columns b' = w, w + 4,
+  // ..., its lanes the rows (a, b) with the group's values of a adjacent.
+  const long long rb = (long long)(n - 1) * R2 + a0, cb = (long long)(q - 1) * R2 + ap;
+  constexpr int NW = 16;  // 8 columns x 2 row halves per lane
+  long long gi[NW];
+  double old[NW];
+  double vq[4], vn[4], vx[4], vl[4], tv[kBbtAG][4];
 #pragma unroll
-    for (int s2 = 0; s2 < 4; ++s2) {
-      const int e = t + 256 * s2, r = e & 31, c2 = e >> 5;
-      tv[s2] = (r < R && c2 < R) ? Tn[(long long)(a + c2 * R) * R + r] : 0.0;
-    }
-  };
-  load_ta(a0);
+  for (int s2 = 0; s2 < 4; ++s2) {
+    const int e = t + 256 * s2, r = e & 31, c2 = e >> 5;
+    const bool ok = r < R && c2 < R;
+    vq[s2] = ok ? Tqg[(long long)(ap + c2 * R) * R + r] : 0.0;
+    vn[s2] = ok ? X[(long long)n * R2 + r + c2 * R] : 0.0;
+    vx[s2] = ok ? X[(long long)q * R2 + r + c2 * R] : 0.0;
+    vl[s2] = ok ? Lc[r + c2 * R] : 0.0;  // L_1
+#pragma unroll
+    for (int al = 0; al < kBbtAG; ++al)
+      tv[al][s2] = (ok && al < na) ? Tn[(long long)(a0 + al + c2 * R) * R + r] : 0.0;
+  }
+#pragma unroll
+  for (int s2 = 0; s2 < NW; ++s2) {
+    const int bq = w + 4 * (s2 >> 1), idx = lane + 64 * (s2 & 1), al = idx & (kBbtAG - 1), b = idx / kBbtAG;
+    const long long r = rb + al + (long long)b * R, c2 = cb + (long long)bq * R;
+    const bool ok = bq < R && b < R && al < na && !(n == q && (r >> 6) < (c2 >> 6));
+    gi[s2] = ok ? r + c2 * p.lds : -1;
+    old[s2] = ok ? St[gi[s2]] : 0.0;
+  }
+#pragma unroll
+  for (int s2 = 0; s2 < 4; ++s2) {
+    const int e = t + 256 * s2, r = e & 31, c2 = e >> 5;
+    Tq[r][c2] = vq[s2];
+    Xn[r][c2] = vn[s2];
+    Xq[r][c2] = vx[s2];
+    UV[r][c2] = vl[s2];
+  }
   sync_block();
   // C' = L_1 L_1^T on this wave's tile, kept in registers
   v4d c1 = v4d{0.0, 0.0, 0.0, 0.0};
@@ -553,13 +561,14 @@ __global__ __launch_bounds__(256, 2) void k_bbt(Shape s, SysPlan p, const double
     c1 = mfma_chain_k(
         K, [&](int k) { return UV[16 * ti + cl][k + kq]; }, [&](int k) { return UV[16 * tj + cl][k + kq]; });
   sync_block();
-  for (int al = 0; al < na; ++al) {
+#pragma unroll
+  for (int al = 0; al < kBbtAG; ++al) {
+    if (al >= na) break;
 #pragma unroll
     for (int s2 = 0; s2 < 4; ++s2) {
       const int e = t + 256 * s2, r = e & 31, c2 = e >> 5;
-      TW[r][c2] = tv[s2];
+      TW[r][c2] = tv[al][s2];
     }
-    if (al + 1 < na) load_ta(a0 + al + 1);  // the next T_a in flight
     sync_block();
     if (tw) {
       // U = T_a T_q^T, V = C' o U
@@ -582,29 +591,14 @@ __global__ __launch_bounds__(256, 2) void k_bbt(Shape s, SysPlan p, const double
       const v4d acc = mfma_chain_k(
           K, [&](int k) { return TW[16 * ti + cl][k + kq]; }, [&](int k) { return Xq[k + kq][16 * tj + cl]; });
 #pragma unroll
-      for (int v = 0; v < 4; ++v) Out[al][16 * ti + kq + 4 * v][16 * tj + cl] = acc[v];
+      for (int v = 0; v < 4; ++v) Out[al * OS + (16 * ti + kq + 4 * v) * BL + 16 * tj + cl] = acc[v];
     }
     sync_block();
   }
-  // St[(n-1) R^2 + a + bR, (q-1) R^2 + a' + b'R] -= Out[a - a0][b][b'], the values
-  // of a of the group adjacent in memory
-  // (all the thread's reads of St in flight before its writes)
-  const long long rb = (long long)(n - 1) * R2 + a0, cb = (long long)(q - 1) * R2 + ap;
-  constexpr int NW = (kBbtAG * 32 * 32 + 255) / 256;
-  long long gi[NW];
-  double old[NW];
 #pragma unroll
   for (int s2 = 0; s2 < NW; ++s2) {
-    const int e = t + 256 * s2, al = e % kBbtAG, rest = e / kBbtAG, b = rest % R, bq = rest / R;
-    const long long r = rb + al + (long long)b * R, c2 = cb + (long long)bq * R;
-    const bool ok = e < kBbtAG * R2 && al < na && !(n == q && (r >> 6) < (c2 >> 6));
-    gi[s2] = ok ? r + c2 * p.lds : -1;
-    old[s2] = ok ? St[gi[s2]] : 0.0;
-  }
-#pragma unroll
-  for (int s2 = 0; s2 < NW; ++s2) {
-    const int e = t + 256 * s2, al = e % kBbtAG, rest = e / kBbtAG, b = rest % R, bq = rest / R;
-    if (gi[s2] >= 0) St[gi[s2]] = old[s2] - Out[al][b][bq];
+    const int bq = w + 4 * (s2 >> 1), idx = lane + 64 * (s2 & 1), al = idx & (kBbtAG - 1), b = idx / kBbtAG;
+    if (gi[s2] >= 0) St[gi[s2]] = old[s2] - Out[al * OS + b * BL + bq];
   }
 }
 
@@ -1195,7 +1189,8 @@ hipError_t launch_sys_assemble(const Shape& s, const SysPlan& p, const SmallBuff
     // B B^T from the structure of B (3 R^5 per block pair instead of the dense (N-1)^2 R^6)
     const long long ncg = (long long)(s.N - 1) * s.N / 2 * s.R;
     const long long ntb = 8 * ((ncg + 7) / 8) * ((s.R + kBbtAG - 1) / kBbtAG);
-    k_bbt<<<(unsigned)(ntb + s.N), 256, 0, st>>>(s, p, y.B, b.z, b.Tnm, b.X, b.Lc, y.St, stop);
+    k_bbt<<<(unsigned)(ntb + (long long)(s.N - 1) * s.R + 1), 256, 0, st>>>(s, p, y.B, b.z, b.Tnm, b.X, b.Lc,
+                                                                                 y.St, stop);
   } else {
     k_syrk<<<(unsigned)(p.ntp / 64 + (long long)p.Tt * (p.Tt + 1) / 2), 256, 0, st>>>(p, y.B, b.z, R2p, y.St, stop);
   }
