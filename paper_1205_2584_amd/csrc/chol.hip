@@ -418,9 +418,8 @@ __device__ __forceinline__ v4d mfma_chain_k(int K, FA a, FB b) {
   return K == 32 ? mfma_chain<32>(a, b) : mfma_chain<16>(a, b);
 }
 
-__global__ __launch_bounds__(256, 2) void k_bbt(Shape s, SysPlan p, const double* B, const double* z,
-                                                const double* Tnm, const double* X, const double* Lc,
-                                                double* St, const int* stop) {
+__global__ __launch_bounds__(256, 2) void k_bbt(Shape s, SysPlan p, const double* z, const double* Tnm,
+                                                const double* X, const double* Lc, double* St, const int* stop) {
   if (stopped(stop)) return;
   const int R = s.R, R2 = R * R, N = s.N, t = threadIdx.x, w = t >> 6, lane = t & 63;
   const int ng = (R + kBbtAG - 1) / kBbtAG;
@@ -1189,8 +1188,8 @@ hipError_t launch_sys_assemble(const Shape& s, const SysPlan& p, const SmallBuff
     // B B^T from the structure of B (3 R^5 per block pair instead of the dense (N-1)^2 R^6)
     const long long ncg = (long long)(s.N - 1) * s.N / 2 * s.R;
     const long long ntb = 8 * ((ncg + 7) / 8) * ((s.R + kBbtAG - 1) / kBbtAG);
-    k_bbt<<<(unsigned)(ntb + (long long)(s.N - 1) * s.R + 1), 256, 0, st>>>(s, p, y.B, b.z, b.Tnm, b.X, b.Lc,
-                                                                                 y.St, stop);
+    k_bbt<<<(unsigned)(ntb + (long long)(s.N - 1) * s.R + 1), 256, 0, st>>>(s, p, b.z, b.Tnm, b.X, b.Lc, y.St,
+                                                                                 stop);
   } else {
     k_syrk<<<(unsigned)(p.ntp / 64 + (long long)p.Tt * (p.Tt + 1) / 2), 256, 0, st>>>(p, y.B, b.z, R2p, y.St, stop);
   }
