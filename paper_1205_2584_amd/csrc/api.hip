@@ -347,7 +347,8 @@ hipError_t enqueue_step(Work& w, bool resid, double mu_host, FitState* state, in
   }
   if ((e = launch_sys_assemble(s, w.sp, w.sb, w.sy, solve_stop, st)) != hipSuccess) return e;
   if ((e = mark(ev, 2, st)) != hipSuccess) return e;
-  if ((e = launch_sys_factor_solve(s, w.sp, w.sb, w.sy, singular, solve_stop, st)) != hipSuccess) return e;
+  if ((e = launch_sys_factor_solve(s, w.sp, w.sb, w.sy, singular, solve_stop, st, s.R <= 32)) != hipSuccess)
+    return e;
   if ((e = mark(ev, 3, st)) != hipSuccess) return e;
   if ((e = launch_u(s, w.sb, stop, st)) != hipSuccess) return e;
   if ((e = launch_fq(s, w.sb, stop, st)) != hipSuccess) return e;

@@ -205,7 +205,8 @@ __global__ __launch_bounds__(256) void k_fill(SysPlan p, double* St, double* B, 
 template <int RM>
 __global__ __launch_bounds__(256) void k_subblock(Shape s, SysPlan p, const double* Tnm,
                                                   const double* X, const double* Lc, double* St,
-                                                  double* B, int R2p, long long nbz, const int* stop) {
+                                                  double* B, int R2p, long long nbz, int write_b,
+                                                  const int* stop) {
   if (stopped(stop)) return;
   __shared__ double Td[RM][RM + 1];  // Td[i][a] = T_nm[i, a + dR]
   __shared__ double Lm[RM][RM + 1];
@@ -221,7 +222,8 @@ __global__ __launch_bounds__(256) void k_subblock(Shape s, SysPlan p, const doub
   int n = 1, m = 0;
   while (pr >= n) { pr -= n; ++n; }
   m = pr;
-  (void)N;
+  // the block column B (m = 0) only where a dense product still reads it
+  if (m == 0 && !write_b) return;
   const int pair = n * N + m;
   const double* T = Tnm + (long long)pair * R * R2;
   {
@@ -599,6 +601,76 @@ __global__ __launch_bounds__(256, 2) void k_bbt(Shape s, SysPlan p, const double
     const int bq = w + 4 * (s2 >> 1), idx = lane + 64 * (s2 & 1), al = idx & (kBbtAG - 1), b = idx / kBbtAG;
     if (gi[s2] >= 0) St[gi[s2]] = old[s2] - Out[al * OS + b * BL + bq];
   }
+}
+
+// y_1 = z_1 - B^T y_t from the structure of B (R <= 32):
+//   (B^T y_t)[c + dR] = sum_i L_1[i,c] H[i,d],
+//   H[i,d] = sum_{n >= 2} sum_a T_n1[i, a + dR] G_n[i,a],  G_n = X_n Y_n^T, Y_n[a][b] = y_n[a + bR].
+// Block d forms H[:, d] and the entries c + dR (each block also copies part of
+// y_t into y).
+__global__ __launch_bounds__(256) void k_y0s(Shape s, SysPlan p, const double* z, const double* yt,
+                                             const double* Tnm, const double* X, const double* Lc, double* y,
+                                             const int* stop) {
+  if (stopped(stop)) return;
+  __shared__ double Xs[32][BL];
+  __shared__ double Ys[32][BL];
+  __shared__ double Gs[32][BL];
+  __shared__ double Hp[8][32];
+  __shared__ double Hv[32];
+  const int R = s.R, R2 = R * R, N = s.N, t = threadIdx.x, w = t >> 6, lane = t & 63;
+  const int cl = lane & 15, kq = lane >> 4, nt = (R + 15) >> 4, K = 16 * nt;
+  const int d = blockIdx.x;
+  const int i = t & 31, ac = t >> 5;  // H: row i, values of a ac, ac + 8, ...
+  double h = 0.0;
+  for (int n = 1; n < N; ++n) {
+    const double* Tn = Tnm + (long long)(n * N) * R * R2;
+    double vx[4], vy[4], tv[4];
+#pragma unroll
+    for (int s2 = 0; s2 < 4; ++s2) {
+      const int e = t + 256 * s2, r = e & 31, c2 = e >> 5;
+      const bool ok = r < R && c2 < R;
+      vx[s2] = ok ? X[(long long)n * R2 + r + c2 * R] : 0.0;
+      vy[s2] = ok ? yt[(long long)(n - 1) * R2 + r + c2 * R] : 0.0;  // Y_n[r][c2]
+      const int a = ac + 8 * s2;
+      tv[s2] = (i < R && a < R) ? Tn[(long long)(a + d * R) * R + i] : 0.0;
+    }
+    sync_block();  // the previous mode's G is no longer read
+#pragma unroll
+    for (int s2 = 0; s2 < 4; ++s2) {
+      const int e = t + 256 * s2, r = e & 31, c2 = e >> 5;
+      Xs[r][c2] = vx[s2];
+      Ys[r][c2] = vy[s2];
+    }
+    sync_block();
+    if (w < nt * nt) {  // G = X_n Y_n^T
+      const int ti = w % nt, tj = w / nt;
+      const v4d acc = mfma_chain_k(
+          K, [&](int k) { return Xs[16 * ti + cl][k + kq]; }, [&](int k) { return Ys[16 * tj + cl][k + kq]; });
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Gs[16 * ti + kq + 4 * v][16 * tj + cl] = acc[v];
+    }
+    sync_block();
+#pragma unroll
+    for (int s2 = 0; s2 < 4; ++s2) {
+      const int a = ac + 8 * s2;
+      if (i < R && a < R) h += tv[s2] * Gs[i][a];
+    }
+  }
+  Hp[ac][i] = h;
+  sync_block();
+  if (t < 32) {
+    double acc = 0.0;
+#pragma unroll
+    for (int g = 0; g < 8; ++g) acc += Hp[g][t];
+    Hv[t] = acc;
+  }
+  sync_block();
+  if (t < R) {  // entry c = t: z_1[c + dR] - sum_i L_1[i][c] H[i]
+    double acc = 0.0;
+    for (int i2 = 0; i2 < R; ++i2) acc += Lc[i2 + t * R] * Hv[i2];
+    y[t + d * R] = z[t + d * R] - acc;
+  }
+  for (int q = blockIdx.x * 256 + t; q < p.nt; q += gridDim.x * 256) y[p.R2 + q] = yt[q];
 }
 
 // Phase ph of the tiled Cholesky.  Blocks [0, Tt - ph + 1) are the panel row
@@ -1177,13 +1249,16 @@ hipError_t launch_sys_assemble(const Shape& s, const SysPlan& p, const SmallBuff
   const int R2p = r2pad(p.R2);
   const long long ntri = (long long)p.Tt * (p.Tt + 1) / 2 + p.Tt;
   const long long nbblocks = ((long long)p.ntp * R2p + 255) / 256;
-  const long long extra = nbblocks < 1024 ? nbblocks : 1024;
   const long long nsub = (long long)(s.N * (s.N - 1) / 2) * s.R * s.R;
+  // R <= 32: the Schur update, the right-hand side and y_1 come from the structure
+  // of B, which is then neither written nor cleared
+  const bool dense_b = s.R > 32;
+  const long long extra = dense_b ? (nbblocks < 1024 ? nbblocks : 1024) : 0;
   const unsigned nblk = (unsigned)(nsub + ntri + extra);
   if (s.R <= 32)
-    k_subblock<32><<<nblk, 256, 0, st>>>(s, p, b.Tnm, b.X, b.Lc, y.St, y.B, R2p, extra, stop);
+    k_subblock<32><<<nblk, 256, 0, st>>>(s, p, b.Tnm, b.X, b.Lc, y.St, y.B, R2p, extra, dense_b ? 1 : 0, stop);
   else
-    k_subblock<64><<<nblk, 256, 0, st>>>(s, p, b.Tnm, b.X, b.Lc, y.St, y.B, R2p, extra, stop);
+    k_subblock<64><<<nblk, 256, 0, st>>>(s, p, b.Tnm, b.X, b.Lc, y.St, y.B, R2p, extra, 1, stop);
   if (s.R <= 32) {
     // B B^T from the structure of B (3 R^5 per block pair instead of the dense (N-1)^2 R^6)
     const long long ncg = (long long)(s.N - 1) * s.N / 2 * s.R;
@@ -1270,11 +1345,13 @@ hipError_t launch_sys_factor_solve_core(const SysPlan& p, const SysBuffers& y, i
 
 hipError_t launch_sys_factor_solve(const Shape& s, const SysPlan& p, const SmallBuffers& b,
                                    const SysBuffers& y, int* singular, const int* stop,
-                                   hipStream_t st) {
-  (void)s;
+                                   hipStream_t st, bool structured_b) {
   hipError_t e = launch_sys_factor_solve_core(p, y, singular, stop, st);
   if (e != hipSuccess) return e;
-  k_y0<<<(p.R2 + 3) / 4, 256, 0, st>>>(p, y.B, b.z, y.yt, b.y, stop);
+  if (structured_b)
+    k_y0s<<<s.R, 256, 0, st>>>(s, p, b.z, y.yt, b.Tnm, b.X, b.Lc, b.y, stop);
+  else
+    k_y0<<<(p.R2 + 3) / 4, 256, 0, st>>>(p, y.B, b.z, y.yt, b.y, stop);
   return hipGetLastError();
 }
 

@@ -117,9 +117,11 @@ struct SysBuffers {
 
 hipError_t launch_sys_assemble(const Shape& s, const SysPlan& p, const SmallBuffers& b,
                                const SysBuffers& y, const int* stop, hipStream_t st);
+// structured_b: y_1 = z_1 - B^T y_t from the structure of B (real systems, R <= 32,
+// assembled without B); otherwise from B itself.
 hipError_t launch_sys_factor_solve(const Shape& s, const SysPlan& p, const SmallBuffers& b,
                                    const SysBuffers& y, int* singular, const int* stop,
-                                   hipStream_t st);
+                                   hipStream_t st, bool structured_b = false);
 // The tiled Cholesky of the lower tiles of y.St with the right-hand-side row
 // (forward substitution inside) and the backward substitution, carried along
 // the phases as Gauss-Jordan elimination (upper tiles of y.St), into y.yt; any
