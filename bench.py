@@ -69,9 +69,9 @@ def schur_update_flops(N, R):
 # null.
 TRAFFIC = {
     "factor_solve": (("paper_1205_2584_amd/csrc/chol.hip", "paper_1205_2584_amd/csrc/panel.hpp"),
-                     "92c3d5dea91c1b07", 837638188),
-    "tensor_pass_f32": (("paper_1205_2584_amd/csrc/tensor_pass.hip",), "cec26df43e38f726", 517789678),
-    "tensor_pass_bf16": (("paper_1205_2584_amd/csrc/tensor_pass.hip",), "cec26df43e38f726", 268071419),
+                     "95b335ef34f2a89a", 825483331),
+    "tensor_pass_f32": (("paper_1205_2584_amd/csrc/tensor_pass.hip",), "cec26df43e38f726", 517666929),
+    "tensor_pass_bf16": (("paper_1205_2584_amd/csrc/tensor_pass.hip",), "cec26df43e38f726", 268064024),
 }
 
 
