@@ -69,7 +69,7 @@ def schur_update_flops(N, R):
 # null.
 TRAFFIC = {
     "factor_solve": (("paper_1205_2584_amd/csrc/chol.hip", "paper_1205_2584_amd/csrc/panel.hpp"),
-                     "95b335ef34f2a89a", 825483331),
+                     "73a3b3f640735299", 825483331),
     "tensor_pass_f32": (("paper_1205_2584_amd/csrc/tensor_pass.hip",), "cec26df43e38f726", 517666929),
     "tensor_pass_bf16": (("paper_1205_2584_amd/csrc/tensor_pass.hip",), "cec26df43e38f726", 268064024),
 }
@@ -510,6 +510,38 @@ def bench_medsae(dgn, torch, ranks=(5, 10, 20, 30, 40, 60), tensors=2, noisy=2, 
             "init": "mode-n singular vectors", "tol": tol, "max_iters": max_iters, "ranks": out}
 
 
+def bench_chol_yardstick(torch, sizes, reps=10, seed=21):
+    """Library yardstick for factor_solve: torch.linalg.cholesky_ex and
+    torch.cholesky_solve (ROCm's dense solver underneath) on seeded SPD FP64
+    matrices of the sizes the step factors, timed with events on torch's stream."""
+    out = {}
+    g = torch.Generator(device="cuda").manual_seed(seed)
+    for n in sizes:
+        a = torch.randn(n, n, generator=g, device="cuda", dtype=torch.float64)
+        s = a @ a.T / n + torch.eye(n, device="cuda", dtype=torch.float64)
+        b = torch.randn(n, 1, generator=g, device="cuda", dtype=torch.float64)
+
+        def once():
+            L, info = torch.linalg.cholesky_ex(s)
+            return torch.cholesky_solve(b, L), info
+
+        for _ in range(3):
+            once()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            x, info = once()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[str(n)] = {"ms": round(ms, 4), "TFLOPs": round(n ** 3 / 3 / (ms * 1e-3) / 1e12, 3),
+                       "rel_residual": float(torch.linalg.norm(s @ x - b) / torch.linalg.norm(b)),
+                       "info": int(info)}
+        del a, s, b, x
+    return out
+
+
 def rel(a, b):
     import numpy as np
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
@@ -735,6 +767,12 @@ def main():
                 "avg_ms": round(fs_ms, 4), "algorithmic_flops": chol_flops(N, R),
                 "assemble_update_TFLOPs": round(upd_tf, 2),
                 "dense_lu_equivalent_TFLOPs": round((2.0 / 3.0) * nr2 ** 3 / ((fs_ms + per["assemble"]) * 1e-3) / 1e12, 2)}
+    progress("factor_solve yardstick")
+    roof_sys["library_yardstick"] = {
+        "what": "torch.linalg.cholesky_ex + torch.cholesky_solve on a seeded SPD FP64 matrix of the trailing "
+                "system's size (N-1)R^2 and of the whole system's NR^2",
+        "ours_ms": round(fs_ms, 4),
+        "torch": bench_chol_yardstick(torch, ((N - 1) * R * R, nr2))}
     dominant = roof_sys if fs_ms > pass_ms else roof_pass
     line = {
         "metric": "dGN iters/s at 500^3 R=30 (HBM GB/s); batched CP fits/s + p50/p99 latency",

@@ -13,7 +13,9 @@
 // which is factored by a tiled right-looking Cholesky (64 x 64 FP64 tiles,
 // MFMA trailing updates).  The right-hand side rides along as an extra tile
 // row, so the forward substitution happens inside the factorisation; the
-// backward substitution runs tile by tile afterwards.
+// backward substitution is carried along the phases as Gauss-Jordan
+// elimination on the factor (systems of up to 48 tiles) or runs tile by tile
+// afterwards (larger systems).
 #include "common.hpp"
 #include "internal.hpp"
 #include "panel.hpp"
