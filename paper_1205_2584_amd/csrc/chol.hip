@@ -124,20 +124,6 @@ __device__ __forceinline__ void stage_panel(double (*T)[TR], const double* g, lo
   }
 }
 
-// 16 x 16 blocks of the update with column ph-1 inside a panel: 0..9 are the
-// lower blocks of D (row block bi, column block bj <= bi), 10..25 the blocks of B.
-__device__ __forceinline__ void panel_update_block(int b, int& bi, int& bj, bool& of_b) {
-  if (b < 10) {
-    bi = (b >= 1) + (b >= 3) + (b >= 6);
-    bj = b - bi * (bi + 1) / 2;
-    of_b = false;
-  } else {
-    bi = 4 + ((b - 10) >> 2);
-    bj = (b - 10) & 3;
-    of_b = true;
-  }
-}
-
 // Blocks of the in-panel update after column step kb: the lower blocks of D to
 // the right of it, then the blocks of B in those columns.
 __device__ __forceinline__ void panel_trail_block(int b, int kb, int& bi, int& bj) {
@@ -151,6 +137,30 @@ __device__ __forceinline__ void panel_trail_block(int b, int kb, int& bi, int& b
     bi = 4 + (b - ndb) / m;
     bj = kb + 1 + (b - ndb) % m;
   }
+}
+
+// The lower blocks of D right of column step KB, by the chain wave in one batch.
+template <int KB>
+__device__ __forceinline__ void trail_diag(double (*T)[TR]) {
+  constexpr int m = 3 - KB, NB = m * (m + 1) / 2;
+  int bi[NB], bj[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) panel_trail_block(b, KB, bi[b], bj[b]);
+  trail16_batch<NB>(T, bi, bj, 16 * KB);
+}
+
+// The blocks of B right of column step KB in the row blocks rb0..rb0+NRB-1
+// that one B wave owns, in one batch.
+template <int KB, int NRB>
+__device__ __forceinline__ void trail_rows(double (*T)[TR], int rb0) {
+  constexpr int m = 3 - KB, NB = NRB * m;
+  int bi[NB], bj[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    bi[b] = rb0 + b / m;
+    bj[b] = KB + 1 + b % m;
+  }
+  trail16_batch<NB>(T, bi, bj, 16 * KB);
 }
 
 // id < ntri: lower tile id (ti, tj) of St (identity / zeros), or a tile of the
@@ -945,8 +955,6 @@ __global__ __launch_bounds__(256, 2) void k_chol_phase(SysPlan p, int ph, double
     stage_panel(T, Dg, lds);
     if (hb) stage_panel(T + 64, Bg, lds);
     sync_block();
-    // in-panel update of the 16 x 16 block (bi, bj) with column step k0
-    auto trail_block = [&](int bi, int bj, int k0) { trail16(T, bi, bj, k0); };
     if (ph > 0) update_rows(dri, dri + 1, La, av0, bv0);
     if (lane == 0) __hip_atomic_fetch_add(&d_done, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
     if (w == 0) {
@@ -960,12 +968,12 @@ __global__ __launch_bounds__(256, 2) void k_chol_phase(SysPlan p, int ph, double
         if (kb == 0) wait_at_least(&d_done, 4, bad);
         if (lane < 48 - k0) trsm16_row(T, k0 + 16 + lane, k0, Lk[kb], rinv);
         if (lane == 0) __hip_atomic_store(&step_done, kb + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
-        const int m = 3 - kb, ndb = m * (m + 1) / 2;
-        for (int b = 0; b < ndb; ++b) {
-          int bi, bj;
-          panel_trail_block(b, kb, bi, bj);
-          trail_block(bi, bj, k0);
-        }
+        if (kb == 0)
+          trail_diag<0>(T);
+        else if (kb == 1)
+          trail_diag<1>(T);
+        else if (kb == 2)
+          trail_diag<2>(T);
       }
     } else if (hb) {
       // Waves 1..3: the rows of B.  Update with column ph-1, then follow the chain.
@@ -979,15 +987,34 @@ __global__ __launch_bounds__(256, 2) void k_chol_phase(SysPlan p, int ph, double
         }
       }
       barrier3(&b_count, epoch, bad);
-      const int r0 = (w - 1) * 22, r1 = (w == 3) ? 64 : r0 + 22;  // rows of B solved by this wave
+      // From here on each B wave owns whole row blocks (wave 1 row blocks 4 and
+      // 5, waves 2 and 3 row blocks 6 and 7): its solves and its updates touch
+      // only its own rows, so the steps wait for the chain's progress only.
+      // Between them, the fence orders the LDS hand-off among the wave's lanes.
+      const int rb0 = (w == 1) ? 4 : w + 4, nrows = (w == 1) ? 32 : 16;
       for (int kb = 0; kb < 4; ++kb) {
         const int k0 = 16 * kb;
         wait_at_least(&step_done, kb + 1, bad);
-        if (lane < r1 - r0) trsm16_row(T, 64 + r0 + lane, k0, Lk[kb], rinv);
-        barrier3(&b_count, epoch, bad);
-        const int m = 3 - kb;
-        for (int b = w - 1; b < 4 * m; b += 3) trail_block(4 + b / m, kb + 1 + b % m, k0);
-        barrier3(&b_count, epoch, bad);
+        if (lane < nrows) trsm16_row(T, 16 * rb0 + lane, k0, Lk[kb], rinv);
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        if (w == 1) {
+          if (kb == 0)
+            trail_rows<0, 2>(T, 4);
+          else if (kb == 1)
+            trail_rows<1, 2>(T, 4);
+          else if (kb == 2)
+            trail_rows<2, 2>(T, 4);
+        } else {
+          if (kb == 0)
+            trail_rows<0, 1>(T, rb0);
+          else if (kb == 1)
+            trail_rows<1, 1>(T, rb0);
+          else if (kb == 2)
+            trail_rows<2, 1>(T, rb0);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+        __builtin_amdgcn_wave_barrier();
       }
     }
     sync_block();

@@ -156,6 +156,35 @@ __device__ __forceinline__ void trail16(double (*T)[TR], int bi, int bj, int k0)
   for (int v = 0; v < 4; ++v) T[16 * bi + kq + 4 * v][16 * bj + cl] -= acc[v];
 }
 
+// trail16 on NB blocks (bi[n], bj[n]) at once: every operand read is issued
+// first and the blocks' MFMAs interleave, so the wave waits for the LDS and the
+// matrix pipeline once instead of once per block.  Each block sums its four
+// k-steps in trail16's order (same result bit for bit).  The operands (columns
+// k0..k0+15) must lie outside the blocks written (columns right of them).
+template <int NB>
+__device__ __forceinline__ void trail16_batch(double (*T)[TR], const int (&bi)[NB], const int (&bj)[NB], int k0) {
+  const int lane = threadIdx.x & 63, cl = lane & 15, kq = lane >> 4;
+  double a[NB][4], b[NB][4];
+#pragma unroll
+  for (int n = 0; n < NB; ++n)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      a[n][k] = T[16 * bi[n] + cl][k0 + 4 * k + kq];
+      b[n][k] = T[16 * bj[n] + cl][k0 + 4 * k + kq];
+    }
+  v4d acc[NB];
+#pragma unroll
+  for (int n = 0; n < NB; ++n) acc[n] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int n = 0; n < NB; ++n) acc[n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[n][k], b[n][k], acc[n], 0, 0, 0);
+#pragma unroll
+  for (int n = 0; n < NB; ++n)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) T[16 * bi[n] + kq + 4 * v][16 * bj[n] + cl] -= acc[n][v];
+}
+
 // X = L^-1 for the lower 64 x 64 factor in T rows 0..63, written to X (rows
 // 64..127 of the panel array, unused by the diagonal workgroup).  Diagonal
 // 16-blocks by forward substitution (wave w inverts block w, lane j a column),
