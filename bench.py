@@ -69,7 +69,7 @@ def schur_update_flops(N, R):
 # null.
 TRAFFIC = {
     "factor_solve": (("paper_1205_2584_amd/csrc/chol.hip", "paper_1205_2584_amd/csrc/panel.hpp"),
-                     "73a3b3f640735299", 825483331),
+                     "2f62f32b09a52b6d", 827900571),
     "tensor_pass_f32": (("paper_1205_2584_amd/csrc/tensor_pass.hip",), "cec26df43e38f726", 517666929),
     "tensor_pass_bf16": (("paper_1205_2584_amd/csrc/tensor_pass.hip",), "cec26df43e38f726", 268064024),
 }
